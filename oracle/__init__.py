@@ -1,0 +1,296 @@
+"""FP64 CPU oracle for the explicit APIC-MPM step (arXiv 1603.06188).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` import this package.  The product path (the
+HIP library under ``paper_1603_06188_amd/``) never imports, links or calls it,
+and the two share no code.
+
+The arithmetic lives in ``apic_oracle.c`` (plain C, binary64, no FMA
+contraction); this module only marshals NumPy arrays to it.  Every function
+cites the passage of the paper it follows:
+
+* ``bspline`` / ``weights``             -- interpolation weights, Sec. 3.5
+* ``neo_hookean_psi`` / ``neo_hookean_P`` -- energy density and first
+  Piola-Kirchhoff stress of Sec. 3.1 (the neo-Hookean form is a reading: the
+  paper names the model in Sec. 6 without writing it)
+* ``p2g``                              -- transfer to grid, Sec. 3.2, plus the
+  force of Sec. 3.3 at F^{n+lambda} = F^n (lambda = 0)
+* ``grid_update``                      -- grid evolution of Sec. 3.3, lambda = 0
+* ``g2p``                              -- transfer to particles, Sec. 3.4
+* ``particle_totals`` / ``grid_totals`` -- momenta of Sec. 3.1 with the
+  particle angular momentum of Sec. 5.3 (B term included)
+* ``cfl_dt``                           -- CFL rule of Sec. 4.3
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "apic_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OR_OK = 0
+OR_E_ARG = -1
+OR_E_DOMAIN = -2
+OR_E_SINGULAR = -3
+OR_E_INVERTED = -4
+
+_ERRORS = {
+    OR_E_ARG: "invalid argument",
+    OR_E_DOMAIN: "particle kernel support leaves the grid",
+    OR_E_SINGULAR: "singular matrix",
+    OR_E_INVERTED: "inverted element (det F <= 0)",
+}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (binary64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        G = ctypes.POINTER(_Grid)
+        lib.oracle_bspline.restype = ctypes.c_double
+        lib.oracle_bspline.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.oracle_bspline_deriv.restype = ctypes.c_double
+        lib.oracle_bspline_deriv.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.oracle_weights.restype = ctypes.c_int
+        lib.oracle_weights.argtypes = [G, _dp, _lp, _dp, _dp]
+        lib.oracle_neo_hookean_psi.restype = ctypes.c_int
+        lib.oracle_neo_hookean_psi.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        lib.oracle_neo_hookean_P.restype = ctypes.c_int
+        lib.oracle_neo_hookean_P.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        lib.oracle_p2g.restype = ctypes.c_int
+        lib.oracle_p2g.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp]
+        lib.oracle_grid_update.restype = ctypes.c_int
+        lib.oracle_grid_update.argtypes = [G, _dp, _dp, _dp, ctypes.c_double, _dp, _ip, _dp, _dp, _dp]
+        lib.oracle_g2p.restype = ctypes.c_int
+        lib.oracle_g2p.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.oracle_particle_totals.restype = None
+        lib.oracle_particle_totals.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp]
+        lib.oracle_grid_totals.restype = None
+        lib.oracle_grid_totals.argtypes = [G, _dp, _dp, _dp, _dp]
+        lib.oracle_potential.restype = ctypes.c_int
+        lib.oracle_potential.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, ctypes.c_double,
+                                         ctypes.c_double, _dp]
+        lib.oracle_cfl_dt.restype = ctypes.c_double
+        lib.oracle_cfl_dt.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                      _dp, _dp]
+        lib.oracle_node_count.restype = ctypes.c_int64
+        lib.oracle_node_count.argtypes = [G]
+        lib.oracle_matrix_det.restype = ctypes.c_double
+        lib.oracle_matrix_det.argtypes = [ctypes.c_int, _dp]
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != OR_OK:
+        raise OracleError(_ERRORS.get(rc, f"oracle error {rc}"))
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class Grid:
+    """Uniform grid with ``cells[a]`` cells (``cells[a] + 1`` nodes) per axis,
+    spacing ``dx``, origin 0 (Sec. 3.3: fixed Cartesian grid)."""
+
+    def __init__(self, dim: int, degree: int, cells, dx: float):
+        self.dim = int(dim)
+        self.degree = int(degree)
+        c = list(cells) + [0] * (3 - len(cells))
+        self.cells = tuple(int(v) for v in c[: self.dim])
+        self.dx = float(dx)
+        self._s = _Grid(self.dim, self.degree, (ctypes.c_int32 * 3)(*[int(v) for v in c[:3]]), self.dx)
+
+    @property
+    def nodes(self):
+        return tuple(c + 1 for c in self.cells)
+
+    @property
+    def node_count(self) -> int:
+        return int(np.prod(self.nodes))
+
+    def node_positions(self) -> np.ndarray:
+        """Node positions x_i, node-major in the oracle's linear order."""
+        axes = [np.arange(n, dtype=np.float64) * self.dx for n in self.nodes]
+        mesh = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+        return np.stack([m.reshape(-1) for m in mesh], axis=1)
+
+    def ref(self):
+        return ctypes.byref(self._s)
+
+
+def bspline(degree: int, t: float) -> float:
+    return _load().oracle_bspline(int(degree), float(t))
+
+
+def bspline_deriv(degree: int, t: float) -> float:
+    return _load().oracle_bspline_deriv(int(degree), float(t))
+
+
+def weights(grid: Grid, xp):
+    """Support of one particle: (node indices, w_ip, grad w_ip)."""
+    xp = _d(xp)
+    nodes = np.zeros(125, dtype=np.int64)
+    w = np.zeros(125)
+    gw = np.zeros(125 * grid.dim)
+    m = _load().oracle_weights(grid.ref(), _ptr(xp), nodes.ctypes.data_as(_lp), _ptr(w), _ptr(gw))
+    if m < 0:
+        _check(m)
+    return nodes[:m].copy(), w[:m].copy(), gw[: m * grid.dim].reshape(m, grid.dim).copy()
+
+
+def neo_hookean_psi(F, mu: float, lam: float) -> float:
+    F = _d(F)
+    d = F.shape[0]
+    out = ctypes.c_double()
+    _check(_load().oracle_neo_hookean_psi(d, _ptr(F), mu, lam, ctypes.byref(out)))
+    return out.value
+
+
+def neo_hookean_P(F, mu: float, lam: float) -> np.ndarray:
+    F = _d(F)
+    d = F.shape[0]
+    P = np.zeros((d, d))
+    _check(_load().oracle_neo_hookean_P(d, _ptr(F), mu, lam, _ptr(P)))
+    return P
+
+
+def det(A) -> float:
+    A = _d(A)
+    return _load().oracle_matrix_det(A.shape[0], _ptr(A))
+
+
+def p2g(grid: Grid, x, v, B, F, m, V, model: int = 0, mu: float = 0.0, lam: float = 0.0,
+        want_D: bool = False):
+    """Transfer to grid (Sec. 3.2) plus the force f_i of Sec. 3.3 (model 1).
+
+    Returns dict with node-major ``m`` (nodes), ``mv`` (nodes, d), ``f``
+    (nodes, d) and optionally ``D`` (np, d, d)."""
+    d = grid.dim
+    x, v, B, F, m, V = (_d(a) for a in (x, v, B, F, m, V))
+    npart = x.shape[0]
+    nn = grid.node_count
+    gm = np.zeros(nn)
+    gmv = np.zeros((nn, d))
+    gf = np.zeros((nn, d))
+    D = np.zeros((max(npart, 1), d, d)) if want_D else None
+    _check(_load().oracle_p2g(grid.ref(), npart, _ptr(x), _ptr(v), _ptr(B), _ptr(F), _ptr(m), _ptr(V),
+                              int(model), float(mu), float(lam), _ptr(gm), _ptr(gmv), _ptr(gf),
+                              _ptr(D) if want_D else None))
+    out = {"m": gm, "mv": gmv, "f": gf}
+    if want_D:
+        out["D"] = D[:npart]
+    return out
+
+
+def grid_update(grid: Grid, gm, gmv, gf, dt: float, gravity=None, band=None):
+    """Grid evolution of Sec. 3.3 at lambda = 0; returns v, vt, xt (nodes, d)."""
+    d = grid.dim
+    gm, gmv = _d(gm), _d(gmv)
+    keep = _d(gf) if gf is not None else None
+    gfp = _ptr(keep) if keep is not None else None
+    g = _d(np.zeros(3) if gravity is None else list(gravity) + [0.0] * (3 - len(gravity)))
+    bd = None
+    if band is not None:
+        bd = np.ascontiguousarray(list(band) + [0] * (6 - len(band)), dtype=np.int32)
+    nn = grid.node_count
+    gv, gvt, gxt = np.zeros((nn, d)), np.zeros((nn, d)), np.zeros((nn, d))
+    _check(_load().oracle_grid_update(grid.ref(), _ptr(gm), _ptr(gmv), gfp, float(dt), _ptr(g),
+                                      bd.ctypes.data_as(_ip) if bd is not None else None,
+                                      _ptr(gv), _ptr(gvt), _ptr(gxt)))
+    return {"v": gv, "vt": gvt, "xt": gxt}
+
+
+def g2p(grid: Grid, x, F, gvt, gxt):
+    """Transfer to particles (Sec. 3.4) with the weights of time n."""
+    d = grid.dim
+    x, F, gvt, gxt = (_d(a) for a in (x, F, gvt, gxt))
+    npart = x.shape[0]
+    xo, vo = np.zeros((npart, d)), np.zeros((npart, d))
+    Bo, Fo = np.zeros((npart, d, d)), np.zeros((npart, d, d))
+    _check(_load().oracle_g2p(grid.ref(), npart, _ptr(x), _ptr(F), _ptr(gvt), _ptr(gxt),
+                              _ptr(xo), _ptr(vo), _ptr(Bo), _ptr(Fo)))
+    return {"x": xo, "v": vo, "B": Bo, "F": Fo}
+
+
+def step(grid: Grid, x, v, B, F, m, V, model=0, mu=0.0, lam=0.0, dt=0.0, gravity=None, band=None):
+    """One explicit step: P2G, grid update, G2P.  Returns the grid stage
+    arrays and the new particle state."""
+    g = p2g(grid, x, v, B, F, m, V, model, mu, lam)
+    u = grid_update(grid, g["m"], g["mv"], g["f"] if model == 1 else None, dt, gravity, band)
+    p = g2p(grid, x, F, u["vt"], u["xt"])
+    out = dict(g)
+    out.update(u)
+    out.update({"x_new": p["x"], "v_new": p["v"], "B_new": p["B"], "F_new": p["F"]})
+    return out
+
+
+def particle_totals(x, v, B, m):
+    """[p (3), l (3), kinetic energy, mass]; l includes m_p B_p^T : eps (Sec. 5.3)."""
+    x, v, m = _d(x), _d(v), _d(m)
+    d = x.shape[1]
+    keep = _d(B) if B is not None else None
+    Bp = _ptr(keep) if keep is not None else None
+    out = np.zeros(8)
+    _load().oracle_particle_totals(d, x.shape[0], _ptr(x), _ptr(v), Bp, _ptr(m), _ptr(out))
+    return out
+
+
+def grid_totals(grid: Grid, gm, gvel, gpos=None):
+    """[p (3), l (3), kinetic energy, mass] of grid velocities at gpos (x_i if None)."""
+    gm, gvel = _d(gm), _d(gvel)
+    keep = _d(gpos) if gpos is not None else None
+    out = np.zeros(8)
+    _load().oracle_grid_totals(grid.ref(), _ptr(gm), _ptr(gvel), _ptr(keep) if keep is not None else None,
+                               _ptr(out))
+    return out
+
+
+def potential(F, V, mu: float, lam: float) -> float:
+    F, V = _d(F), _d(V)
+    out = ctypes.c_double()
+    _check(_load().oracle_potential(F.shape[1], F.shape[0], _ptr(F), _ptr(V), mu, lam, ctypes.byref(out)))
+    return out.value
+
+
+def cfl_dt(dx: float, v, B, nu: float = 1.0) -> float:
+    """Largest dt admitted by the CFL rule of Sec. 4.3."""
+    v, B = _d(v), _d(B)
+    return _load().oracle_cfl_dt(v.shape[1], float(dx), float(nu), v.shape[0], _ptr(v), _ptr(B))
