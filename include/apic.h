@@ -1,0 +1,235 @@
+/*
+ * apic.h -- C ABI of libapic, an MI355X (gfx950) implementation of the
+ * explicit Affine-Particle-In-Cell / MPM step of Jiang, Schroeder and Teran,
+ * "An angular momentum conserving Affine-Particle-In-Cell method"
+ * (arXiv 1603.06188).
+ *
+ * One step is
+ *   apic_sort         (optional, every k steps)  bin particles by cell
+ *   apic_p2g          Sec. 3.2 transfer to grid + fused force of Sec. 3.3
+ *   apic_grid_update  Sec. 3.3 grid evolution at lambda = 0 (symplectic Euler)
+ *   apic_g2p          Sec. 3.4 transfer to particles (lambda = 0 forms of Sec. 5.7)
+ * and apic_step runs whole steps for one or many scenes.
+ *
+ * Conventions shared by every call
+ *   - Every pointer inside the structs below is a DEVICE pointer owned by the
+ *     caller; the library borrows it for the duration of the call (and of the
+ *     work that call enqueues).  The library never allocates device memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Every call is asynchronous on that stream except apic_diagnostics and
+ *     apic_get_flags, which synchronize it.
+ *   - Errors: a call returns APIC_OK or a negative apic_status.  Argument
+ *     errors are detected on the host before anything is enqueued and leave
+ *     all buffers untouched; apic_last_error() then returns a message (per
+ *     host thread).  Problems found on the device (a particle whose kernel
+ *     support leaves the grid, a non-finite value, an inverted element) never
+ *     abort: they set sticky bits in the scene's flag word (apic_get_flags)
+ *     and the offending particle is skipped by the transfer that found it.
+ *   - Floating point planes hold binary32 (APIC_F32) or binary64 (APIC_F64)
+ *     values as selected by apic_grid_desc.precision.
+ *
+ * Grid: n[a] cells and n[a]+1 nodes per axis, node i at x_i = i*dx, origin 0
+ * (a fixed Cartesian grid, Sec. 3.3).  A particle must keep its whole kernel
+ * support inside the grid: quadratic needs 0.5 <= x/dx < n-0.5, cubic needs
+ * 1 <= x/dx < n-1 on every axis.
+ *
+ * Particles: structure of arrays.  A "plane" is one scalar field for all n
+ * particles; consecutive planes of one field are `stride` elements apart.
+ * Position = packed cell index + offset inside the cell in cell units:
+ *   3D: cell = cx | cy << 10 | cz << 20   (cells per axis <= 1024)
+ *   2D: cell = cx | cy << 16              (cells per axis <= 65535)
+ *   x_p[a] = (c_a + off[a]) * dx, 0 <= off[a] < 1.
+ */
+#ifndef APIC_H
+#define APIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t apic_status;
+enum {
+    APIC_OK = 0,
+    APIC_E_INVAL = -1,        /* bad argument (message in apic_last_error)    */
+    APIC_E_UNSUPPORTED = -2,  /* valid but not implemented combination        */
+    APIC_E_HIP = -3,          /* a HIP runtime call failed                    */
+    APIC_E_WORKSPACE = -4     /* workspace missing, misaligned or too small   */
+};
+
+enum { APIC_QUADRATIC = 2, APIC_CUBIC = 3 };      /* B-spline degree (Sec. 3.5) */
+enum { APIC_F32 = 0, APIC_F64 = 1 };              /* element type of planes    */
+enum { APIC_MODEL_NONE = 0, APIC_MODEL_NEO_HOOKEAN = 1 };
+
+/* apic_grid_desc.options bits */
+enum {
+    APIC_OPT_COMPENSATED = 1  /* accumulate grid mass/momentum with an error
+                                 term per node (two-sum), folded in by
+                                 apic_grid_update                            */
+};
+
+/* Sticky device flag bits (apic_get_flags). */
+enum {
+    APIC_FLAG_OUT_OF_DOMAIN = 1, /* a kernel support left the grid: skipped   */
+    APIC_FLAG_NONFINITE = 2,     /* NaN/Inf in a particle's state: skipped    */
+    APIC_FLAG_INVERTED = 4,      /* det F <= 0: the particle's force skipped  */
+    APIC_FLAG_CFL = 8            /* a particle moved more than one cell       */
+};
+
+typedef struct {
+    int32_t dim;        /* 2 or 3                                        */
+    int32_t degree;     /* APIC_QUADRATIC or APIC_CUBIC                  */
+    int32_t precision;  /* APIC_F32 or APIC_F64                          */
+    int32_t options;    /* APIC_OPT_* bits                               */
+    int32_t cells[3];   /* cells per axis; cells[2] ignored in 2D        */
+    double dx;          /* grid spacing (> 0)                            */
+} apic_grid_desc;
+
+typedef struct {
+    int64_t n;          /* particle count (>= 0)                            */
+    int64_t stride;     /* elements between planes of one field (>= n)     */
+    uint32_t *cell;     /* 1 plane, packed cell index                       */
+    void *off;          /* dim planes: offset in the cell, cell units       */
+    void *v;            /* dim planes: velocity v_p                         */
+    void *B;            /* dim*dim planes, row-major: plane r*dim+c = B_rc  */
+    void *F;            /* dim*dim planes, row-major: deformation gradient  */
+    void *mass;         /* 1 plane: m_p                                     */
+    int32_t *id;        /* optional (NULL): carried along by apic_sort      */
+} apic_particles;
+
+typedef struct {
+    double dt;          /* time step (>= 0); dt = 0 gives pure transfers    */
+    double gravity[3];  /* added to the velocity of nodes with mass         */
+    int32_t model;      /* APIC_MODEL_*                                     */
+    int32_t band[6];    /* sticky band width in nodes: -x,+x,-y,+y,-z,+z    */
+    double mu;          /* Lame mu of the neo-Hookean model                 */
+    double lambda;      /* Lame lambda of the neo-Hookean model             */
+    double rho0;        /* rest density: particle volume V_p = m_p / rho0   */
+} apic_params;
+
+typedef struct {
+    apic_grid_desc grid;
+    apic_particles p;
+    apic_params prm;
+    void *workspace;          /* device, 256-byte aligned, caller-owned     */
+    size_t workspace_bytes;   /* >= apic_workspace_bytes(grid, p.n)         */
+} apic_scene;
+
+/* Grid fields for apic_grid_export. */
+enum {
+    APIC_GRID_MASS = 0,       /* m_i                                 (1)     */
+    APIC_GRID_MOMENTUM = 1,   /* (m v)_i + dt f_i after apic_p2g    (dim)   */
+    APIC_GRID_VELOCITY = 2    /* vt_i after apic_grid_update        (dim)   */
+};
+
+/* Totals for apic_diagnostics. */
+enum {
+    APIC_DIAG_PARTICLES = 0,  /* p, l (with the B term of Sec. 5.3), KE, M    */
+    APIC_DIAG_GRID = 1,       /* p, l, KE, M of (m v)_i + dt f_i at x_i       */
+    APIC_DIAG_GRID_NEW = 2    /* p, l, KE, M of m_i vt_i at x_i + dt vt_i     */
+};
+
+/*
+ * Device workspace needed for a grid and up to max_particles particles.
+ * *bytes receives the size.  The workspace holds the grid (mass, momentum,
+ * velocity and their error terms), sort buffers, a shadow copy of the
+ * particle state used when reordering, flags and reduction partials.  The
+ * library keeps state across calls in it (e.g. the grid from apic_p2g is
+ * what apic_grid_update reads): one workspace per scene.
+ */
+apic_status apic_workspace_bytes(const apic_grid_desc *grid, int64_t max_particles, size_t *bytes);
+
+/*
+ * Clears the scene's workspace (grid, flags, counters).  Call once after
+ * allocating a workspace.
+ */
+apic_status apic_reset(apic_scene *scene, void *stream);
+
+/*
+ * Reorders the particles in place, stably, by the tile-major index of each
+ * particle's base grid node (the lowest node of its kernel support; tiles of
+ * 4x4x4 nodes in 3D, 8x8 in 2D).  Every plane, and p.id when non-NULL, is
+ * permuted.  The grid is fixed (Sec. 3.3) and particles move less than a cell
+ * per step (Sec. 4.3), so sorting every few steps keeps particles binned.
+ */
+apic_status apic_sort(apic_scene *scene, void *stream);
+
+/*
+ * Transfer to grid, Sec. 3.2, with D_p = (dx^2/4) I (quadratic) or (dx^2/3) I
+ * (cubic) (Sec. 5.6):
+ *   m_i       = sum_p w_ip m_p
+ *   (m v)_i   = sum_p w_ip m_p (v_p + B_p D_p^{-1} (x_i - x_p)) + dt f_i
+ * where f_i = -sum_p V_p P(F_p) F_p^T grad w_ip is the force of Sec. 3.3 at
+ * F^{n+lambda} = F^n (lambda = 0), fused into the momentum (model 1 only;
+ * P is neo-Hookean).  Clears and overwrites the workspace grid.
+ */
+apic_status apic_p2g(apic_scene *scene, void *stream);
+
+/*
+ * Grid update, Sec. 3.3 at lambda = 0: for m_i > 0,
+ *   vt_i = ((m v)_i + dt f_i) / m_i + dt g, zero inside sticky bands;
+ * vt_i = 0 where m_i = 0.  (The grid position x~_i = x_i + dt vt_i stays
+ * implicit: the grid is fixed.)
+ */
+apic_status apic_grid_update(apic_scene *scene, void *stream);
+
+/*
+ * Transfer to particles, Sec. 3.4, in its lambda = 0 form (Sec. 5.7), with the
+ * weights of time n:
+ *   v_p = sum_i w_ip vt_i
+ *   B_p = sum_i w_ip vt_i (x_i - x_p)^T
+ *   F_p = (I + dt sum_i vt_i grad w_ip^T) F_p
+ *   x_p = x_p + dt v_p   (cell index and offset updated together)
+ * Overwrites cell, off, v, B, F in place.
+ */
+apic_status apic_g2p(apic_scene *scene, void *stream);
+
+/*
+ * Runs n_steps whole steps (P2G, grid update, G2P) for each of n_scenes
+ * independent scenes (host array of scenes, each with its own workspace and
+ * particles), re-sorting each scene's particles every sort_every steps
+ * (0 = never).  Equivalent to the per-call sequence above.
+ */
+apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int32_t sort_every,
+                      void *stream);
+
+/*
+ * Copies one grid field (APIC_GRID_*) into `out`, a device buffer of
+ * node_count * components elements of the scene precision, component-major
+ * (component c of node i at out[c*node_count + i]), nodes in the order
+ * ix + N0*(iy + N1*iz), N_a = cells[a]+1.  Error terms are folded in.
+ */
+apic_status apic_grid_export(const apic_scene *scene, int32_t field, void *out, void *stream);
+
+/*
+ * Binary64 totals (Sec. 3.1 momenta; Sec. 5.3 particle angular momentum):
+ * out[0..2] linear momentum, out[3..5] angular momentum about the origin (in
+ * 2D the scalar is out[5]), out[6] kinetic energy 1/2 sum m |v|^2, out[7]
+ * mass.  `out` is a HOST array of 8 doubles.  Synchronizes `stream`.
+ */
+apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out, void *stream);
+
+/* Reads (host *flags) / clears the sticky flag word.  get synchronizes. */
+apic_status apic_get_flags(const apic_scene *scene, uint32_t *flags, void *stream);
+apic_status apic_clear_flags(apic_scene *scene, void *stream);
+
+/*
+ * Converts absolute binary64 positions (device, dim planes of p.stride
+ * elements) into p.cell / p.off, and back.
+ */
+apic_status apic_positions_from_absolute(apic_scene *scene, const double *x, void *stream);
+apic_status apic_positions_to_absolute(const apic_scene *scene, double *x, void *stream);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *apic_last_error(void);
+
+/* Library version string. */
+const char *apic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APIC_H */

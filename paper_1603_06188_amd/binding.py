@@ -1,0 +1,336 @@
+"""ctypes binding of libapic (C ABI in include/apic.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libapic.so``.  PyTorch provides device memory and the stream.  Importing
+this module fails loudly when the library has not been built; there is no
+CPU fallback.
+
+The functions ``apic_*`` mirror the C entry points one to one and take a
+ctypes ``ApicScene``.  ``DeviceScene`` owns the torch tensors behind one
+scene and is a convenience for tests, the benchmark and users.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # first: the library must bind to the HIP runtime torch loaded
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapic.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+APIC_OK = 0
+APIC_QUADRATIC, APIC_CUBIC = 2, 3
+APIC_F32, APIC_F64 = 0, 1
+APIC_MODEL_NONE, APIC_MODEL_NEO_HOOKEAN = 0, 1
+APIC_OPT_COMPENSATED = 1
+APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
+APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
+APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
+
+EXPORTED = [
+    "apic_workspace_bytes", "apic_reset", "apic_sort", "apic_p2g", "apic_grid_update", "apic_g2p", "apic_step",
+    "apic_grid_export", "apic_diagnostics", "apic_get_flags", "apic_clear_flags",
+    "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_last_error", "apic_version",
+]
+
+
+class ApicGridDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("options", ctypes.c_int32), ("cells", ctypes.c_int32 * 3), ("dx", ctypes.c_double)]
+
+
+class ApicParticles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("stride", ctypes.c_int64), ("cell", ctypes.c_void_p),
+                ("off", ctypes.c_void_p), ("v", ctypes.c_void_p), ("B", ctypes.c_void_p), ("F", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p), ("id", ctypes.c_void_p)]
+
+
+class ApicParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("model", ctypes.c_int32),
+                ("band", ctypes.c_int32 * 6), ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("rho0", ctypes.c_double)]
+
+
+class ApicScene(ctypes.Structure):
+    _fields_ = [("grid", ApicGridDesc), ("p", ApicParticles), ("prm", ApicParams),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+_S = ctypes.POINTER(ApicScene)
+_V = ctypes.c_void_p
+_sigs = {
+    "apic_workspace_bytes": [ctypes.POINTER(ApicGridDesc), ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+    "apic_reset": [_S, _V],
+    "apic_sort": [_S, _V],
+    "apic_p2g": [_S, _V],
+    "apic_grid_update": [_S, _V],
+    "apic_g2p": [_S, _V],
+    "apic_step": [_S, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V],
+    "apic_grid_export": [_S, ctypes.c_int32, _V, _V],
+    "apic_diagnostics": [_S, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _V],
+    "apic_get_flags": [_S, ctypes.POINTER(ctypes.c_uint32), _V],
+    "apic_clear_flags": [_S, _V],
+    "apic_positions_from_absolute": [_S, _V, _V],
+    "apic_positions_to_absolute": [_S, _V, _V],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int32
+_lib.apic_last_error.restype = ctypes.c_char_p
+_lib.apic_last_error.argtypes = []
+_lib.apic_version.restype = ctypes.c_char_p
+_lib.apic_version.argtypes = []
+
+
+class ApicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"apic error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> None:
+    if rc != APIC_OK:
+        raise ApicError(rc, _lib.apic_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# --- one-to-one wrappers of the C entry points -------------------------------
+
+def apic_workspace_bytes(grid: ApicGridDesc, max_particles: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.apic_workspace_bytes(ctypes.byref(grid), int(max_particles), ctypes.byref(out)))
+    return out.value
+
+
+def apic_reset(scene: ApicScene, stream=None) -> None:
+    _check(_lib.apic_reset(ctypes.byref(scene), _stream(stream)))
+
+
+def apic_sort(scene: ApicScene, stream=None) -> None:
+    _check(_lib.apic_sort(ctypes.byref(scene), _stream(stream)))
+
+
+def apic_p2g(scene: ApicScene, stream=None) -> None:
+    _check(_lib.apic_p2g(ctypes.byref(scene), _stream(stream)))
+
+
+def apic_grid_update(scene: ApicScene, stream=None) -> None:
+    _check(_lib.apic_grid_update(ctypes.byref(scene), _stream(stream)))
+
+
+def apic_g2p(scene: ApicScene, stream=None) -> None:
+    _check(_lib.apic_g2p(ctypes.byref(scene), _stream(stream)))
+
+
+def apic_step(scenes, n_steps: int, sort_every: int = 0, stream=None) -> None:
+    arr = (ApicScene * len(scenes))(*scenes)
+    _check(_lib.apic_step(arr, len(scenes), int(n_steps), int(sort_every), _stream(stream)))
+    # the C side does not modify the structs; nothing to copy back
+
+
+def apic_grid_export(scene: ApicScene, field: int, out_ptr: int, stream=None) -> None:
+    _check(_lib.apic_grid_export(ctypes.byref(scene), int(field), ctypes.c_void_p(out_ptr), _stream(stream)))
+
+
+def apic_diagnostics(scene: ApicScene, which: int, stream=None) -> np.ndarray:
+    out = (ctypes.c_double * 8)()
+    _check(_lib.apic_diagnostics(ctypes.byref(scene), int(which), out, _stream(stream)))
+    return np.array(out[:], dtype=np.float64)
+
+
+def apic_get_flags(scene: ApicScene, stream=None) -> int:
+    out = ctypes.c_uint32()
+    _check(_lib.apic_get_flags(ctypes.byref(scene), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def apic_clear_flags(scene: ApicScene, stream=None) -> None:
+    _check(_lib.apic_clear_flags(ctypes.byref(scene), _stream(stream)))
+
+
+def apic_positions_from_absolute(scene: ApicScene, x_ptr: int, stream=None) -> None:
+    _check(_lib.apic_positions_from_absolute(ctypes.byref(scene), ctypes.c_void_p(x_ptr), _stream(stream)))
+
+
+def apic_positions_to_absolute(scene: ApicScene, x_ptr: int, stream=None) -> None:
+    _check(_lib.apic_positions_to_absolute(ctypes.byref(scene), ctypes.c_void_p(x_ptr), _stream(stream)))
+
+
+def apic_last_error() -> str:
+    return _lib.apic_last_error().decode()
+
+
+def apic_version() -> str:
+    return _lib.apic_version().decode()
+
+
+# --- device-resident scene ----------------------------------------------------
+
+def pack_cells(cell: np.ndarray) -> np.ndarray:
+    """Per-axis int cell indices [n, dim] -> packed uint32 (layout of apic.h)."""
+    c = cell.astype(np.uint64)
+    if cell.shape[1] == 3:
+        packed = c[:, 0] | (c[:, 1] << np.uint64(10)) | (c[:, 2] << np.uint64(20))
+    else:
+        packed = c[:, 0] | (c[:, 1] << np.uint64(16))
+    return packed.astype(np.uint32)
+
+
+def unpack_cells(packed: np.ndarray, dim: int) -> np.ndarray:
+    p = packed.astype(np.uint64)
+    if dim == 3:
+        return np.stack([p & 1023, (p >> 10) & 1023, p >> 20], axis=1).astype(np.int64)
+    return np.stack([p & 0xFFFF, p >> 16], axis=1).astype(np.int64)
+
+
+class DeviceScene:
+    """Device copy of a ``scenes.Scene`` plus its workspace.
+
+    Particle planes live in one tensor ``f`` of shape [planes, stride]:
+    off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
+
+    def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True):
+        self.host = scene
+        self.dim = scene.dim
+        self.precision = precision or scene.precision
+        self.dtype = torch.float32 if self.precision == "fp32" else torch.float64
+        self.n = scene.n
+        self.capacity = max(int(capacity or self.n), 1)
+        d = self.dim
+        self.nplanes = 2 * d + 2 * d * d + 1
+        cap = self.capacity
+        self.f = torch.zeros((self.nplanes, cap), dtype=self.dtype, device=device)
+        self.cell = torch.zeros(cap, dtype=torch.int32, device=device)
+        self.id = torch.arange(cap, dtype=torch.int32, device=device) if with_id else None
+        self.upload(scene)
+        g = ApicGridDesc()
+        g.dim = d
+        g.degree = scene.degree
+        g.precision = APIC_F32 if self.precision == "fp32" else APIC_F64
+        g.options = APIC_OPT_COMPENSATED if compensated else 0
+        for a in range(3):
+            g.cells[a] = scene.cells[a] if a < d else 0
+        g.dx = scene.dx
+        self.wbytes = apic_workspace_bytes(g, cap)
+        self.ws = torch.empty(self.wbytes + 256, dtype=torch.uint8, device=device)
+        s = ApicScene()
+        s.grid = g
+        s.workspace = (self.ws.data_ptr() + 255) // 256 * 256
+        s.workspace_bytes = self.wbytes
+        prm = s.prm
+        prm.dt = scene.dt
+        for a in range(3):
+            prm.gravity[a] = scene.gravity[a] if a < len(scene.gravity) else 0.0
+        prm.model = scene.model
+        for k in range(6):
+            prm.band[k] = scene.band[k]
+        prm.mu = scene.mu
+        prm.lambda_ = scene.lam
+        prm.rho0 = scene.rho0
+        self.s = s
+        self._bind()
+        apic_reset(self.s)
+
+    def _plane(self, k):
+        return self.f[k].data_ptr()
+
+    def _bind(self):
+        d = self.dim
+        p = self.s.p
+        p.n = self.n
+        p.stride = self.capacity
+        p.cell = self.cell.data_ptr()
+        p.off = self._plane(0)
+        p.v = self._plane(d)
+        p.B = self._plane(2 * d)
+        p.F = self._plane(2 * d + d * d)
+        p.mass = self._plane(2 * d + 2 * d * d)
+        p.id = self.id.data_ptr() if self.id is not None else None
+
+    def upload(self, scene):
+        d = self.dim
+        n = scene.n
+        if n > self.capacity:
+            raise ValueError("scene larger than capacity")
+        self.n = n
+        planes = np.concatenate([scene.off.T, scene.v.T, scene.B.reshape(n, d * d).T, scene.F.reshape(n, d * d).T,
+                                 scene.m[None, :]], axis=0)
+        host = torch.from_numpy(np.ascontiguousarray(planes)).to(self.dtype)
+        self.f[:, :n].copy_(host)
+        self.cell[:n].copy_(torch.from_numpy(pack_cells(scene.cell).view(np.int32)))
+        if self.id is not None:
+            self.id[:n].copy_(torch.arange(n, dtype=torch.int32))
+        if hasattr(self, "s"):
+            self._bind()
+
+    # --- the path -----------------------------------------------------------
+    def sort(self):
+        apic_sort(self.s)
+
+    def p2g(self):
+        apic_p2g(self.s)
+
+    def grid_update(self):
+        apic_grid_update(self.s)
+
+    def g2p(self):
+        apic_g2p(self.s)
+
+    def step(self, n_steps=1, sort_every=0):
+        apic_step([self.s], n_steps, sort_every)
+
+    # --- observation (copies to host) ---------------------------------------
+    @property
+    def node_shape(self):
+        return tuple(c + 1 for c in self.host.cells)
+
+    def export(self, field):
+        """Grid field as a host array [nodes, comps] in the oracle's node order."""
+        nodes = int(np.prod(self.node_shape))
+        comps = 1 if field == APIC_GRID_MASS else self.dim
+        out = torch.empty(comps * nodes, dtype=self.dtype, device=self.f.device)
+        apic_grid_export(self.s, field, out.data_ptr())
+        a = out.cpu().numpy().astype(np.float64).reshape(comps, nodes).T
+        return a[:, 0] if comps == 1 else a
+
+    def diagnostics(self, which=APIC_DIAG_PARTICLES):
+        return apic_diagnostics(self.s, which)
+
+    def flags(self):
+        return apic_get_flags(self.s)
+
+    def clear_flags(self):
+        apic_clear_flags(self.s)
+
+    def state(self):
+        """Particle state on the host: cell [n,dim], off, x (float64 absolute),
+        v, B [n,d,d], F [n,d,d], m, id."""
+        d, n = self.dim, self.n
+        f = self.f[:, :n].cpu().numpy().astype(np.float64)
+        cell = unpack_cells(self.cell[:n].cpu().numpy().view(np.uint32), d)
+        off = f[0:d].T.copy()
+        out = {
+            "cell": cell,
+            "off": off,
+            "x": (cell.astype(np.float64) + off) * self.host.dx,
+            "v": f[d:2 * d].T.copy(),
+            "B": f[2 * d:2 * d + d * d].T.reshape(n, d, d).copy(),
+            "F": f[2 * d + d * d:2 * d + 2 * d * d].T.reshape(n, d, d).copy(),
+            "m": f[2 * d + 2 * d * d].copy(),
+        }
+        if self.id is not None:
+            out["id"] = self.id[:n].cpu().numpy().copy()
+        return out
