@@ -1,0 +1,198 @@
+"""Benchmark: explicit APIC-MPM step on one MI355X.
+
+Workload: the elastic cube of the benchmark spec's metric -- 3D, 128^3 cells on the
+unit cube, quadratic B-spline, cube [0.25, 0.75]^3 at 8 particles per cell
+(2,097,152 particles), neo-Hookean E = 1e4, nu = 0.3, rho = 1000, gravity
+-9.8 along z, sticky floor, dt = 1e-4, binary32 cell + offset positions with
+compensated grid accumulation.  Inputs are seeded and synthetic and resident
+in HBM before the timed region.
+
+One step = (re-sort every --sort-every steps) + P2G + grid update + G2P,
+each through the C ABI on torch's current stream.  HIP events bracket every
+phase inside the timed region; the dominant phase's average duration gives
+the roofline figure.  The FP64 CPU oracle is timed on a bounded sample of
+the same workload as the CPU baseline.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "APIC particle-updates/s (P2G+grid+G2P), 3D 2M ptcl; served p50/p99 latency"
+
+# Algorithmic bytes (binary32, 3D) -- what the method itself must move:
+#   particle read by P2G: cell 4 + off 12 + v 12 + B 36 + F 36 + m 4 = 104 B
+#   particle read by G2P: cell 4 + off 12 + F 36 = 52 B; written: cell, off, v, B, F = 100 B
+#   grid node: P2G writes m + mv (16 B; +16 B error terms when compensated),
+#   the grid update reads them and writes vt (12 B), G2P reads vt (12 B).
+P2G_PARTICLE_B = 104
+G2P_PARTICLE_B = 52 + 100
+NODE_MMV_B = 16
+NODE_VT_B = 12
+
+
+def _ensure_built():
+    lib = os.path.join(ROOT, "paper_1603_06188_amd", "libapic.so")
+    if not os.path.exists(lib):
+        from paper_1603_06188_amd.build import build_library
+        build_library()
+
+
+def cpu_baseline(scene, budget_s: float = 12.0, max_steps: int = 3):
+    """Time the FP64 oracle (single thread, as written) on the full particle
+    set of the workload for as many steps as fit in about budget_s."""
+    import oracle
+
+    g = oracle.Grid(scene.dim, scene.degree, scene.cells, scene.dx)
+    x, v, B, F = scene.x, scene.v, scene.B, scene.F
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        r = oracle.step(g, x, v, B, F, scene.m, scene.V, scene.model, scene.mu, scene.lam, scene.dt,
+                        scene.gravity, scene.band)
+        x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {
+        "value": scene.n * steps / el,
+        "unit": "particle-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"full {scene.n}-particle cube, {steps} step(s), {el:.1f} s, single-threaded FP64 C oracle",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--cells", type=int, default=128)
+    ap.add_argument("--plain", action="store_true", help="uncompensated binary32 accumulation")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the explicit APIC step of one scene is not "
+              "sharded across GPUs); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    _ensure_built()
+    import numpy as np
+    import torch
+
+    from paper_1603_06188_amd import binding as b
+    from paper_1603_06188_amd import scenes
+
+    torch.cuda.set_device(0)
+    scene = scenes.cube3d(cells=args.cells)
+    compensated = not args.plain
+    ds = b.DeviceScene(scene, compensated=compensated)
+    st = torch.cuda.current_stream()
+
+    # active grid nodes of the initial state (for the byte accounting)
+    ds.p2g()
+    active = int(np.count_nonzero(ds.export(b.APIC_GRID_MASS)))
+
+    def one_step(k, ev=None):
+        if args.sort_every > 0 and k % args.sort_every == 0:
+            if ev: ev["sort"][0].record(st)
+            ds.sort()
+            if ev: ev["sort"][1].record(st)
+        for name, fn in (("p2g", ds.p2g), ("grid_update", ds.grid_update), ("g2p", ds.g2p)):
+            if ev: ev[name][0].record(st)
+            fn()
+            if ev: ev[name][1].record(st)
+
+    for k in range(args.warmup):
+        one_step(k)
+    torch.cuda.synchronize()
+    ds.upload(scene)  # timed steps start from the initial state of the workload
+    ds.clear_flags()
+    torch.cuda.synchronize()
+
+    phases = ["sort", "p2g", "grid_update", "g2p"]
+    events = {p: [] for p in phases}
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev = {p: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for p in phases}
+        one_step(k, ev)
+        for p in phases:
+            events[p].append(ev[p])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    flags = ds.flags()
+
+    dur = {}
+    for p in phases:
+        ts = []
+        for s, e in events[p]:
+            try:
+                ts.append(s.elapsed_time(e))
+            except (RuntimeError, ValueError):
+                pass  # phase not run in this step (sort)
+        dur[p] = (sum(ts) / len(ts)) if ts else 0.0
+
+    n = scene.n
+    comp_b = 16 if compensated else 0
+    alg_bytes = {
+        "p2g": n * P2G_PARTICLE_B + active * (NODE_MMV_B + comp_b),
+        "grid_update": active * (NODE_MMV_B + comp_b + NODE_VT_B),
+        "g2p": n * G2P_PARTICLE_B + active * NODE_VT_B,
+    }
+    dom = max(("p2g", "grid_update", "g2p"), key=lambda p: dur[p])
+    achieved = alg_bytes[dom] / (dur[dom] * 1e-3) / 1e9
+    value = n * args.steps / el
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"elastic cube, {args.cells}^3 grid, quadratic B-spline, {n} particles, neo-Hookean, "
+                        f"gravity, dt=1e-4, {'compensated' if compensated else 'plain'} f32 cell+offset",
+            "particles": n,
+            "grid_cells": args.cells,
+            "active_nodes": active,
+            "sort_every": args.sort_every,
+        },
+        "phase_ms": {p: round(dur[p], 5) for p in phases},
+        "flags": flags,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

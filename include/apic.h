@@ -75,7 +75,10 @@ enum {
     APIC_FLAG_OUT_OF_DOMAIN = 1, /* a kernel support left the grid: skipped   */
     APIC_FLAG_NONFINITE = 2,     /* NaN/Inf in a particle's state: skipped    */
     APIC_FLAG_INVERTED = 4,      /* det F <= 0: the particle's force skipped  */
-    APIC_FLAG_CFL = 8            /* a particle moved more than one cell       */
+    APIC_FLAG_CFL = 8,           /* a particle moved more than one cell       */
+    APIC_FLAG_UNSORTED = 16      /* a particle was not where the binning put
+                                    it (particle data changed without
+                                    apic_sort): skipped by apic_p2g           */
 };
 
 typedef struct {
@@ -142,17 +145,24 @@ enum {
 apic_status apic_workspace_bytes(const apic_grid_desc *grid, int64_t max_particles, size_t *bytes);
 
 /*
- * Clears the scene's workspace (grid, flags, counters).  Call once after
- * allocating a workspace.
+ * Clears the scene's workspace (grid, flags, counters, binning state).  Call
+ * once after allocating a workspace (the first call on an unknown workspace
+ * also does it).
  */
 apic_status apic_reset(apic_scene *scene, void *stream);
 
 /*
- * Reorders the particles in place, stably, by the tile-major index of each
- * particle's base grid node (the lowest node of its kernel support; tiles of
- * 4x4x4 nodes in 3D, 8x8 in 2D).  Every plane, and p.id when non-NULL, is
- * permuted.  The grid is fixed (Sec. 3.3) and particles move less than a cell
- * per step (Sec. 4.3), so sorting every few steps keeps particles binned.
+ * Bins the particles in place by base grid node (the lowest node of a
+ * particle's kernel support).  Base nodes are grouped in tiles of 64 (4x4x4
+ * in 3D, 8x8 in 2D); the particles of a tile become contiguous and are stored
+ * level by level (level j holds the j-th particle of every base node of the
+ * tile with more than j particles, in node order).  Particles whose support
+ * leaves the grid, or whose position is not finite, are moved after all
+ * tiles and skipped by the transfers.  Every plane, and p.id when non-NULL,
+ * is permuted; the order of particles sharing a base node is unspecified.
+ * apic_g2p keeps the particles binned, so apic_sort is needed only after the
+ * caller changes particle data or count (apic_p2g bins unbinned particles
+ * itself).
  */
 apic_status apic_sort(apic_scene *scene, void *stream);
 
@@ -163,7 +173,8 @@ apic_status apic_sort(apic_scene *scene, void *stream);
  *   (m v)_i   = sum_p w_ip m_p (v_p + B_p D_p^{-1} (x_i - x_p)) + dt f_i
  * where f_i = -sum_p V_p P(F_p) F_p^T grad w_ip is the force of Sec. 3.3 at
  * F^{n+lambda} = F^n (lambda = 0), fused into the momentum (model 1 only;
- * P is neo-Hookean).  Clears and overwrites the workspace grid.
+ * P is neo-Hookean).  Overwrites the workspace grid; no float atomics, and
+ * the grid values do not depend on the order of the tiles.
  */
 apic_status apic_p2g(apic_scene *scene, void *stream);
 
@@ -182,15 +193,20 @@ apic_status apic_grid_update(apic_scene *scene, void *stream);
  *   B_p = sum_i w_ip vt_i (x_i - x_p)^T
  *   F_p = (I + dt sum_i vt_i grad w_ip^T) F_p
  *   x_p = x_p + dt v_p   (cell index and offset updated together)
- * Overwrites cell, off, v, B, F in place.
+ * Overwrites cell, off, v, B, F and re-bins the particles for the next
+ * apic_p2g (particles are permuted as by apic_sort; p.id follows them).
+ * Requires apic_p2g and apic_grid_update on the same particles before it.
  */
 apic_status apic_g2p(apic_scene *scene, void *stream);
 
 /*
  * Runs n_steps whole steps (P2G, grid update, G2P) for each of n_scenes
  * independent scenes (host array of scenes, each with its own workspace and
- * particles), re-sorting each scene's particles every sort_every steps
- * (0 = never).  Equivalent to the per-call sequence above.
+ * particles).  Equivalent to the per-call sequence above, but the particle
+ * state alternates between the caller's planes and the workspace instead of
+ * being copied back after every step; it ends in the caller's planes.
+ * sort_every > 0 additionally re-bins from scratch every sort_every steps
+ * (never needed for correctness).
  */
 apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int32_t sort_every,
                       void *stream);

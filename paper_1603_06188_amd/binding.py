@@ -31,6 +31,7 @@ APIC_F32, APIC_F64 = 0, 1
 APIC_MODEL_NONE, APIC_MODEL_NEO_HOOKEAN = 0, 1
 APIC_OPT_COMPENSATED = 1
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
+APIC_FLAG_UNSORTED = 16
 APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
 APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
 
@@ -275,6 +276,7 @@ class DeviceScene:
             self.id[:n].copy_(torch.arange(n, dtype=torch.int32))
         if hasattr(self, "s"):
             self._bind()
+            apic_sort(self.s)  # particle data changed outside the library: re-bin
 
     # --- the path -----------------------------------------------------------
     def sort(self):
@@ -315,12 +317,20 @@ class DeviceScene:
     def clear_flags(self):
         apic_clear_flags(self.s)
 
-    def state(self):
+    def state(self, raw=False):
         """Particle state on the host: cell [n,dim], off, x (float64 absolute),
-        v, B [n,d,d], F [n,d,d], m, id."""
+        v, B [n,d,d], F [n,d,d], m, id.  The library keeps particles binned
+        (it reorders them); unless `raw`, rows are returned in id order, i.e.
+        in the order the scene was uploaded."""
         d, n = self.dim, self.n
         f = self.f[:, :n].cpu().numpy().astype(np.float64)
         cell = unpack_cells(self.cell[:n].cpu().numpy().view(np.uint32), d)
+        if not raw and self.id is not None:
+            ids = self.id[:n].cpu().numpy()
+            order = np.empty(n, dtype=np.int64)
+            order[ids] = np.arange(n)
+            f = f[:, order]
+            cell = cell[order]
         off = f[0:d].T.copy()
         out = {
             "cell": cell,
@@ -332,5 +342,6 @@ class DeviceScene:
             "m": f[2 * d + 2 * d * d].copy(),
         }
         if self.id is not None:
-            out["id"] = self.id[:n].cpu().numpy().copy()
+            ids = self.id[:n].cpu().numpy().copy()
+            out["id"] = np.sort(ids) if not raw else ids
         return out

@@ -1,11 +1,13 @@
 // C ABI of libapic (declared in include/apic.h): host-side validation,
-// workspace layout and dispatch to the gfx950 kernels.
+// workspace layout, binning state and dispatch to the gfx950 kernels.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <unordered_map>
 
 #include "apic.h"
 #include "apic_kernels.h"
@@ -30,29 +32,43 @@ apic_status fail(apic_status code, const char *fmt, ...) {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Workspace layout.  The fixed part (grid planes, flags, reduction buffers)
-// persists between calls; the transient part (sort buffers, shadow particle
-// state) is sized by the particle count of the call and reused freely.
+int slab_nodes(int dim, int degree) {
+    const int re = (dim == 3 ? 4 : 8) + degree;
+    return dim == 3 ? re * re * re : re * re;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout for a grid and a particle capacity `cap`.
+// ---------------------------------------------------------------------------
+struct MetaOff {
+    size_t count, tile, base, maxc, kcount, kprefix, map;
+};
+
 struct Layout {
     GridDims d;
     size_t elem;
     bool comp;
-    size_t o_m, o_mv, o_vt, o_cm, o_cmv, o_flags, o_diag_out, o_diag_part, fixed_end;
-    size_t o_keys, o_perm, o_counts, o_cursor, o_sums, o_sh_cell, o_sh_id, o_sh_f, total;
-    int64_t n;
+    int64_t cap, rc;  // particle capacity, record capacity
+    int64_t slab_stride;
+    size_t o_vt, o_flags, o_diag_out, o_diag_part, o_key_count, o_tile_flag, o_node_flag, o_node_list,
+        o_node_count, o_sums, o_slabs;
+    MetaOff meta[2];
+    size_t fixed_end;
+    size_t o_pkey, o_prank, o_perm, o_sh_cell, o_sh_id, o_sh_f;
+    size_t total;
 };
 
-Layout make_layout(const apic_grid_desc *g, int64_t n) {
+Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     Layout L{};
     L.d.dim = g->dim;
     L.d.deg = g->degree;
-    const int tile_edge = g->dim == 3 ? 4 : 8;
+    const int te = g->dim == 3 ? 4 : 8;
     L.d.tiles = 1;
     for (int a = 0; a < 3; ++a) {
         if (a < g->dim) {
             L.d.n[a] = g->cells[a];
             L.d.N[a] = g->cells[a] + 1;
-            L.d.TN[a] = (L.d.N[a] + tile_edge - 1) / tile_edge;
+            L.d.TN[a] = (L.d.N[a] + te - 1) / te;
             L.d.tiles *= L.d.TN[a];
         } else {
             L.d.n[a] = 0;
@@ -63,48 +79,69 @@ Layout make_layout(const apic_grid_desc *g, int64_t n) {
     L.d.G = L.d.tiles * 64;
     L.elem = g->precision == APIC_F64 ? 8 : 4;
     L.comp = (g->options & APIC_OPT_COMPENSATED) != 0;
-    L.n = n;
-    const size_t G = (size_t)L.d.G, dim = (size_t)g->dim, e = L.elem;
+    L.cap = cap < 1 ? 1 : cap;
+    L.rc = L.d.tiles < L.cap ? L.d.tiles : L.cap;
+    const size_t TT = (size_t)L.d.tiles, G = (size_t)L.d.G, dim = (size_t)g->dim, e = L.elem;
+    const size_t RC = (size_t)L.rc, cp = (size_t)L.cap;
+    L.slab_stride = (int64_t)((1 + dim) * slab_nodes(g->dim, g->degree) * (L.comp ? 2 : 1));
     size_t o = 0;
-    L.o_m = o;
-    o = align_up(o + G * e);
-    L.o_mv = o;
-    o = align_up(o + dim * G * e);
-    L.o_vt = o;
-    o = align_up(o + dim * G * e);
-    L.o_cm = o;
-    o = align_up(o + (L.comp ? G * e : 0));
-    L.o_cmv = o;
-    o = align_up(o + (L.comp ? dim * G * e : 0));
-    L.o_flags = o;
-    o = align_up(o + 64);
-    L.o_diag_out = o;
-    o = align_up(o + 8 * sizeof(double));
-    L.o_diag_part = o;
-    o = align_up(o + (size_t)kDiagBlocks * 8 * sizeof(double));
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.o_vt = take(dim * G * e);
+    L.o_flags = take(64);
+    L.o_diag_out = take(8 * sizeof(double));
+    L.o_diag_part = take((size_t)kDiagBlocks * 8 * sizeof(double));
+    L.o_key_count = take(G * 4);
+    L.o_tile_flag = take(TT * 4);
+    L.o_node_flag = take(TT * 4);
+    L.o_node_list = take(TT * 4);
+    L.o_node_count = take(16);
+    for (int k = 0; k < 2; ++k) {
+        L.meta[k].count = take(16);
+        L.meta[k].tile = take(RC * 4);
+        L.meta[k].base = take((RC + 1) * 4);
+        L.meta[k].maxc = take(RC * 4);
+        L.meta[k].kcount = take(RC * 64 * 4);
+        L.meta[k].kprefix = take(RC * 64 * 4);
+        L.meta[k].map = take(TT * 4);
+    }
+    L.o_sums = take(((RC + 2 + 1023) / 1024 + 2) * 4);
+    L.o_slabs = take(RC * (size_t)L.slab_stride * e);
     L.fixed_end = o;
-    const size_t nn = (size_t)(n > 0 ? n : 0);
-    const size_t nkeys = G + 2;
-    L.o_keys = o;
-    o = align_up(o + nn * 4);
-    L.o_perm = o;
-    o = align_up(o + nn * 4);
-    L.o_counts = o;
-    o = align_up(o + nkeys * 4);
-    L.o_cursor = o;
-    o = align_up(o + nkeys * 4);
-    L.o_sums = o;
-    o = align_up(o + ((nkeys + 1023) / 1024 + 1) * 4);
-    L.o_sh_cell = o;
-    o = align_up(o + nn * 4);
-    L.o_sh_id = o;
-    o = align_up(o + nn * 4);
-    L.o_sh_f = o;
-    o = align_up(o + (size_t)(2 + 2 * dim + 2 * dim * dim) * nn * e);
+    L.o_pkey = take(cp * 4);
+    L.o_prank = take(cp * 4);
+    L.o_perm = take(cp * 4);
+    L.o_sh_cell = take(cp * 4);
+    L.o_sh_id = take(cp * 4);
+    L.o_sh_f = take((2 * dim + 2 * dim * dim + 1) * cp * e);
     L.total = o;
     return L;
 }
 
+// Largest particle capacity whose layout fits in `bytes` (0 if none).
+int64_t capacity_for(const apic_grid_desc *g, size_t bytes) {
+    if (make_layout(g, 1).total > bytes) return 0;
+    int64_t lo = 1, hi = 2;
+    while (hi < ((int64_t)1 << 31) && make_layout(g, hi).total <= bytes) {
+        lo = hi;
+        hi *= 2;
+    }
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(g, mid).total <= bytes)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
 apic_status check_grid(const apic_grid_desc *g) {
     if (!g) return fail(APIC_E_INVAL, "grid descriptor is NULL");
     if (g->dim != 2 && g->dim != 3) return fail(APIC_E_INVAL, "dim must be 2 or 3 (got %d)", g->dim);
@@ -118,12 +155,12 @@ apic_status check_grid(const apic_grid_desc *g) {
         if (g->cells[a] < g->degree + 1 || g->cells[a] > maxc)
             return fail(APIC_E_INVAL, "cells[%d] = %d outside [%d, %d]", a, g->cells[a], g->degree + 1, maxc);
     if (!(g->dx > 0.0) || !isfinite(g->dx)) return fail(APIC_E_INVAL, "dx must be positive and finite");
-    const Layout L = make_layout(g, 0);
-    if (L.d.G + 2 > (int64_t)0xFFFFFFFFu) return fail(APIC_E_INVAL, "grid too large");
+    const Layout L = make_layout(g, 1);
+    if (L.d.G >= (int64_t)0xFFFFFFFFu) return fail(APIC_E_INVAL, "grid too large");
     return APIC_OK;
 }
 
-apic_status check_scene(const apic_scene *s) {
+apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
     if (!s) return fail(APIC_E_INVAL, "scene is NULL");
     apic_status rc = check_grid(&s->grid);
     if (rc != APIC_OK) return rc;
@@ -150,124 +187,245 @@ apic_status check_scene(const apic_scene *s) {
         if (q.band[k] < 0) return fail(APIC_E_INVAL, "band widths must be >= 0");
     if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)s->workspace) % kAlign) return fail(APIC_E_WORKSPACE, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(&s->grid, p.n);
-    if (s->workspace_bytes < L.total)
-        return fail(APIC_E_WORKSPACE, "workspace has %zu bytes, %zu needed", s->workspace_bytes, L.total);
+    const int64_t cap = capacity_for(&s->grid, s->workspace_bytes);
+    if (cap < p.n || cap < 1)
+        return fail(APIC_E_WORKSPACE, "workspace of %zu bytes holds %lld particles, %lld given (need %zu bytes)",
+                    s->workspace_bytes, (long long)cap, (long long)p.n,
+                    make_layout(&s->grid, p.n > 0 ? p.n : 1).total);
+    *cap_out = cap;
     return APIC_OK;
 }
 
-template <typename T>
-Parts<T> parts_of(const apic_scene *s) {
-    Parts<T> P;
-    P.cell = s->p.cell;
-    P.off = (T *)s->p.off;
-    P.v = (T *)s->p.v;
-    P.B = (T *)s->p.B;
-    P.F = (T *)s->p.F;
-    P.m = (T *)s->p.mass;
-    P.id = s->p.id;
-    P.n = s->p.n;
-    P.s = s->p.stride;
-    return P;
+// ---------------------------------------------------------------------------
+// Host-side binning state per workspace.
+// ---------------------------------------------------------------------------
+struct SceneState {
+    apic_grid_desc grid;
+    size_t wbytes = 0;
+    bool binned = false;     // the user's particle buffers follow meta[cur]
+    int cur = 0;             // layout of the particles
+    int grid_meta = -1;      // layout the slabs (last apic_p2g) belong to
+    int node_meta = -1;      // layout the node list was built for
+    bool vt_valid = false;   // grid velocities from meta[grid_meta] are current
+    int64_t n = -1;
+    void *cell = nullptr;
+    int64_t stride = 0;
+};
+
+std::mutex g_mu;
+std::unordered_map<void *, SceneState> g_states;
+
+bool same_grid(const apic_grid_desc &a, const apic_grid_desc &b) { return memcmp(&a, &b, sizeof a) == 0; }
+
+apic_status hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(APIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    return APIC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Typed views of one scene
+// ---------------------------------------------------------------------------
 template <typename T>
-Parts<T> shadow_of(const apic_scene *s, const Layout &L) {
+struct View {
+    Layout L;
+    Parts<T> user, shadow;
+    BinMeta meta[2];
+    BinScratch sc;
+    Slabs<T> slabs;
+    GridState<T> g;
+    StepParams<T> prm;
+    Bounds b;
+    double *diag_part, *diag_out;
+};
+
+template <typename T>
+View<T> make_view(const apic_scene *s, int64_t cap) {
+    View<T> v;
+    v.L = make_layout(&s->grid, cap);
+    const Layout &L = v.L;
     char *w = (char *)s->workspace;
-    const int64_t n = L.n, dim = L.d.dim;
-    Parts<T> P;
-    P.cell = (uint32_t *)(w + L.o_sh_cell);
-    P.id = (int32_t *)(w + L.o_sh_id);
+    v.user.cell = s->p.cell;
+    v.user.off = (T *)s->p.off;
+    v.user.v = (T *)s->p.v;
+    v.user.B = (T *)s->p.B;
+    v.user.F = (T *)s->p.F;
+    v.user.m = (T *)s->p.mass;
+    v.user.id = s->p.id;
+    v.user.n = s->p.n;
+    v.user.s = s->p.stride;
+    const int64_t dim = L.d.dim, cp = L.cap;
+    v.shadow.cell = (uint32_t *)(w + L.o_sh_cell);
+    v.shadow.id = s->p.id ? (int32_t *)(w + L.o_sh_id) : nullptr;
     T *f = (T *)(w + L.o_sh_f);
-    P.off = f;
-    P.v = f + dim * n;
-    P.B = f + 2 * dim * n;
-    P.F = f + (2 * dim + dim * dim) * n;
-    P.m = f + (2 * dim + 2 * dim * dim) * n;
-    P.n = n;
-    P.s = n;
-    return P;
+    v.shadow.off = f;
+    v.shadow.v = f + dim * cp;
+    v.shadow.B = f + 2 * dim * cp;
+    v.shadow.F = f + (2 * dim + dim * dim) * cp;
+    v.shadow.m = f + (2 * dim + 2 * dim * dim) * cp;
+    v.shadow.n = s->p.n;
+    v.shadow.s = cp;
+    for (int k = 0; k < 2; ++k) {
+        const MetaOff &o = L.meta[k];
+        v.meta[k].count = (uint32_t *)(w + o.count);
+        v.meta[k].tile = (uint32_t *)(w + o.tile);
+        v.meta[k].base = (uint32_t *)(w + o.base);
+        v.meta[k].maxc = (uint32_t *)(w + o.maxc);
+        v.meta[k].kcount = (uint32_t *)(w + o.kcount);
+        v.meta[k].kprefix = (uint32_t *)(w + o.kprefix);
+        v.meta[k].map = (int32_t *)(w + o.map);
+    }
+    v.sc.key_count = (uint32_t *)(w + L.o_key_count);
+    v.sc.tile_flag = (uint32_t *)(w + L.o_tile_flag);
+    v.sc.node_flag = (uint32_t *)(w + L.o_node_flag);
+    v.sc.node_list = (uint32_t *)(w + L.o_node_list);
+    v.sc.node_count = (uint32_t *)(w + L.o_node_count);
+    v.sc.pkey = (uint32_t *)(w + L.o_pkey);
+    v.sc.prank = (uint32_t *)(w + L.o_prank);
+    v.sc.perm = (uint32_t *)(w + L.o_perm);
+    v.sc.sums = (uint32_t *)(w + L.o_sums);
+    v.slabs.v = (T *)(w + L.o_slabs);
+    v.slabs.stride = L.slab_stride;
+    v.g.vt = (T *)(w + L.o_vt);
+    v.g.flags = (uint32_t *)(w + L.o_flags);
+    v.g.d = L.d;
+    v.g.dx = (T)s->grid.dx;
+    v.g.inv_dx = (T)(1.0 / s->grid.dx);
+    v.prm.dt = (T)s->prm.dt;
+    for (int a = 0; a < 3; ++a) v.prm.g[a] = (T)s->prm.gravity[a];
+    v.prm.model = s->prm.model;
+    for (int k = 0; k < 6; ++k) v.prm.band[k] = s->prm.band[k];
+    v.prm.mu = (T)s->prm.mu;
+    v.prm.lam = (T)s->prm.lambda;
+    v.prm.inv_rho0 = s->prm.rho0 > 0.0 ? (T)(1.0 / s->prm.rho0) : T(0);
+    v.b.max_records = L.rc;
+    v.b.tiles = L.d.tiles;
+    v.diag_part = (double *)(w + L.o_diag_part);
+    v.diag_out = (double *)(w + L.o_diag_out);
+    return v;
 }
 
-template <typename T>
-GridPlanes<T> planes_of(const apic_scene *s, const Layout &L) {
-    char *w = (char *)s->workspace;
-    GridPlanes<T> g;
-    g.m = (T *)(w + L.o_m);
-    g.mv = (T *)(w + L.o_mv);
-    g.vt = (T *)(w + L.o_vt);
-    g.cm = (T *)(w + L.o_cm);
-    g.cmv = (T *)(w + L.o_cmv);
-    g.flags = (uint32_t *)(w + L.o_flags);
-    g.d = L.d;
-    g.dx = (T)s->grid.dx;
-    g.inv_dx = (T)(1.0 / s->grid.dx);
-    return g;
+// Device part of a reset: zero the fixed region, then mark every tile map
+// entry unlisted.
+void device_reset(const apic_scene *s, int64_t cap, hipStream_t st) {
+    const Layout L = make_layout(&s->grid, cap);
+    launch_fill<uint32_t>((uint32_t *)s->workspace, (int64_t)(L.fixed_end / 4), 0u, st);
+    for (int k = 0; k < 2; ++k)
+        launch_fill<int32_t>((int32_t *)((char *)s->workspace + L.meta[k].map), L.d.tiles, -1, st);
 }
 
-template <typename T>
-StepParams<T> params_of(const apic_scene *s) {
-    StepParams<T> q;
-    q.dt = (T)s->prm.dt;
-    for (int a = 0; a < 3; ++a) q.g[a] = (T)s->prm.gravity[a];
-    q.model = s->prm.model;
-    for (int k = 0; k < 6; ++k) q.band[k] = s->prm.band[k];
-    q.mu = (T)s->prm.mu;
-    q.lam = (T)s->prm.lambda;
-    q.inv_rho0 = s->prm.rho0 > 0.0 ? (T)(1.0 / s->prm.rho0) : T(0);
-    return q;
+// Registry entry of the scene, created (and the workspace reset) on first
+// use or when the grid or workspace size changed; `binned` is dropped when
+// the particle buffers are not the ones last binned.
+SceneState &state_of(const apic_scene *s, int64_t cap, hipStream_t st) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_states.find(s->workspace);
+    if (it == g_states.end() || !same_grid(it->second.grid, s->grid) || it->second.wbytes != s->workspace_bytes) {
+        SceneState fresh;
+        fresh.grid = s->grid;
+        fresh.wbytes = s->workspace_bytes;
+        g_states[s->workspace] = fresh;
+        device_reset(s, cap, st);
+        it = g_states.find(s->workspace);
+    }
+    SceneState &ss = it->second;
+    if (ss.n != s->p.n || ss.cell != (void *)s->p.cell || ss.stride != s->p.stride) {
+        ss.binned = false;
+        ss.n = s->p.n;
+        ss.cell = (void *)s->p.cell;
+        ss.stride = s->p.stride;
+    }
+    return ss;
 }
 
+// ---------------------------------------------------------------------------
+// Typed operations
+// ---------------------------------------------------------------------------
 enum class Op { Sort, P2G, GridUpdate, G2P, Export, DiagParticles, DiagGrid, Pack, Unpack };
 
 struct OpArgs {
-    void *ptr;    // export destination / positions / diag host out
-    int which;    // export field / diag kind
+    void *ptr;
+    int which;
 };
 
+// Bins the particles of `src` (at their current positions) into meta[nxt]
+// and writes them, in the new order, to `dst`.
+template <typename T, int DIM, int DEG>
+void bin_static(View<T> &v, const Parts<T> &src, const Parts<T> &dst, int nxt, hipStream_t st) {
+    launch_bin_begin(v.meta[nxt], v.sc, v.b, st);
+    launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.meta[nxt], v.sc, v.g.flags, st);
+    launch_bin_finish<DIM>(v.L.d, v.meta[nxt], v.sc, v.b, st);
+    launch_bin_scatter_copy<T, DIM>(src, dst, v.meta[nxt], v.sc, st);
+}
+
+// One G2P from `src` (layout meta[cur]) into `dst` (layout meta[1-cur]).
+template <typename T, int DIM, int DEG>
+void g2p_rebin(View<T> &v, const Parts<T> &src, const Parts<T> &dst, int cur, hipStream_t st) {
+    const int nxt = 1 - cur;
+    launch_bin_begin(v.meta[nxt], v.sc, v.b, st);
+    launch_bin_keys_moved<T, DIM, DEG>(src, v.meta[cur], v.g, v.prm, v.meta[nxt], v.sc, st);
+    launch_bin_finish<DIM>(v.L.d, v.meta[nxt], v.sc, v.b, st);
+    launch_g2p<T, DIM, DEG>(src, dst, v.meta[cur], v.meta[nxt], v.sc, v.g, v.prm, st);
+}
+
 template <typename T, int DIM, int DEG, bool COMP>
-apic_status run(Op op, const apic_scene *s, hipStream_t st, const OpArgs &a) {
-    const Layout L = make_layout(&s->grid, s->p.n);
-    const Parts<T> P = parts_of<T>(s);
-    const GridPlanes<T> g = planes_of<T>(s, L);
-    const StepParams<T> q = params_of<T>(s);
-    char *w = (char *)s->workspace;
+apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
+    View<T> v = make_view<T>(s, cap);
+    SceneState &ss = state_of(s, cap, st);
     switch (op) {
         case Op::Sort: {
-            SortBuffers sb;
-            sb.keys = (uint32_t *)(w + L.o_keys);
-            sb.perm = (uint32_t *)(w + L.o_perm);
-            sb.counts = (uint32_t *)(w + L.o_counts);
-            sb.cursor = (uint32_t *)(w + L.o_cursor);
-            sb.sums = (uint32_t *)(w + L.o_sums);
-            launch_sort<T, DIM, DEG>(P, shadow_of<T>(s, L), L.d, sb, st);
+            const int nxt = 1 - ss.cur;
+            bin_static<T, DIM, DEG>(v, v.user, v.shadow, nxt, st);
+            launch_copy_state<T, DIM>(v.shadow, v.user, st);
+            ss.cur = nxt;
+            ss.binned = true;
+            ss.node_meta = nxt;
+            if (ss.grid_meta == nxt) ss.grid_meta = -1;
+            ss.vt_valid = false;
             break;
         }
-        case Op::P2G:
-            launch_p2g<T, DIM, DEG, COMP>(P, g, q, st);
+        case Op::P2G: {
+            if (!ss.binned) {
+                apic_status rc = run<T, DIM, DEG, COMP>(Op::Sort, s, cap, st, a);
+                if (rc != APIC_OK) return rc;
+            }
+            launch_p2g<T, DIM, DEG, COMP>(v.user, v.meta[ss.cur], v.slabs, v.g, v.prm, v.b, st);
+            ss.grid_meta = ss.cur;
+            ss.vt_valid = false;
             break;
+        }
         case Op::GridUpdate:
-            launch_grid_update<T, DIM, COMP>(g, q, st);
+            if (ss.grid_meta < 0 || ss.node_meta != ss.grid_meta)
+                return fail(APIC_E_INVAL, "apic_grid_update needs a preceding apic_p2g on the current particles");
+            launch_grid_update<T, DIM, DEG, COMP>(v.meta[ss.grid_meta], v.sc, v.slabs, v.g, v.prm, v.b, st);
+            ss.vt_valid = true;
             break;
         case Op::G2P:
-            launch_g2p<T, DIM, DEG>(P, g, q, st);
+            if (!ss.vt_valid || !ss.binned || ss.grid_meta != ss.cur)
+                return fail(APIC_E_INVAL, "apic_g2p needs apic_p2g and apic_grid_update on the current particles");
+            g2p_rebin<T, DIM, DEG>(v, v.user, v.shadow, ss.cur, st);
+            launch_copy_state<T, DIM>(v.shadow, v.user, st);
+            ss.cur = 1 - ss.cur;
+            ss.node_meta = ss.cur;
+            ss.vt_valid = false;
             break;
         case Op::Export:
-            launch_grid_export<T, DIM, COMP>(g, a.which, (T *)a.ptr, st);
+            if (ss.grid_meta < 0) return fail(APIC_E_INVAL, "no grid yet: call apic_p2g first");
+            launch_grid_export<T, DIM, DEG, COMP>(v.meta[ss.grid_meta], v.slabs, v.g, a.which, (T *)a.ptr, st);
             break;
         case Op::DiagParticles:
-            launch_diag_particles<T, DIM>(P, s->grid.dx, (double *)(w + L.o_diag_part), (double *)(w + L.o_diag_out),
-                                          st);
+            launch_diag_particles<T, DIM>(v.user, s->grid.dx, v.diag_part, v.diag_out, st);
             break;
         case Op::DiagGrid:
-            launch_diag_grid<T, DIM, COMP>(g, a.which, s->prm.dt, (double *)(w + L.o_diag_part),
-                                           (double *)(w + L.o_diag_out), st);
+            if (ss.grid_meta < 0) return fail(APIC_E_INVAL, "no grid yet: call apic_p2g first");
+            launch_diag_grid<T, DIM, DEG, COMP>(v.meta[ss.grid_meta], v.slabs, v.g, a.which, s->prm.dt, v.diag_part,
+                                                v.diag_out, st);
             break;
         case Op::Pack:
-            launch_pack_positions<T, DIM>(P, (const double *)a.ptr, s->grid.dx, st);
+            launch_pack_positions<T, DIM>(v.user, (const double *)a.ptr, s->grid.dx, st);
+            ss.binned = false;
             break;
         case Op::Unpack:
-            launch_unpack_positions<T, DIM>(P, (double *)a.ptr, s->grid.dx, st);
+            launch_unpack_positions<T, DIM>(v.user, (double *)a.ptr, s->grid.dx, st);
             break;
     }
     hipError_t e = hipGetLastError();
@@ -275,35 +433,80 @@ apic_status run(Op op, const apic_scene *s, hipStream_t st, const OpArgs &a) {
     return APIC_OK;
 }
 
+// Whole steps for one scene with the particle state alternating between the
+// caller's buffers and the workspace shadow; ends in the caller's buffers.
+template <typename T, int DIM, int DEG, bool COMP>
+apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_every, hipStream_t st) {
+    View<T> v = make_view<T>(s, cap);
+    SceneState &ss = state_of(s, cap, st);
+    Parts<T> bufs[2] = {v.user, v.shadow};
+    int where = 0;
+    if (!ss.binned) {
+        bin_static<T, DIM, DEG>(v, v.user, v.shadow, 1 - ss.cur, st);
+        ss.cur = 1 - ss.cur;
+        where = 1;
+    }
+    for (int32_t k = 0; k < n_steps; ++k) {
+        if (sort_every > 0 && k > 0 && k % sort_every == 0) {
+            bin_static<T, DIM, DEG>(v, bufs[where], bufs[1 - where], 1 - ss.cur, st);
+            ss.cur = 1 - ss.cur;
+            where = 1 - where;
+        }
+        launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.meta[ss.cur], v.slabs, v.g, v.prm, v.b, st);
+        launch_grid_update<T, DIM, DEG, COMP>(v.meta[ss.cur], v.sc, v.slabs, v.g, v.prm, v.b, st);
+        ss.grid_meta = ss.cur;
+        g2p_rebin<T, DIM, DEG>(v, bufs[where], bufs[1 - where], ss.cur, st);
+        ss.cur = 1 - ss.cur;
+        where = 1 - where;
+    }
+    if (where == 1) launch_copy_state<T, DIM>(v.shadow, v.user, st);
+    ss.binned = true;
+    ss.node_meta = ss.cur;
+    ss.vt_valid = false;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(APIC_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return APIC_OK;
+}
+
 template <typename T, int DIM, int DEG>
-apic_status run_c(Op op, const apic_scene *s, hipStream_t st, const OpArgs &a) {
-    if (s->grid.options & APIC_OPT_COMPENSATED) return run<T, DIM, DEG, true>(op, s, st, a);
-    return run<T, DIM, DEG, false>(op, s, st, a);
+apic_status run_c(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
+    if (s->grid.options & APIC_OPT_COMPENSATED) return run<T, DIM, DEG, true>(op, s, cap, st, a);
+    return run<T, DIM, DEG, false>(op, s, cap, st, a);
 }
-
 template <typename T, int DIM>
-apic_status run_k(Op op, const apic_scene *s, hipStream_t st, const OpArgs &a) {
-    if (s->grid.degree == APIC_CUBIC) return run_c<T, DIM, 3>(op, s, st, a);
-    return run_c<T, DIM, 2>(op, s, st, a);
+apic_status run_k(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
+    if (s->grid.degree == APIC_CUBIC) return run_c<T, DIM, 3>(op, s, cap, st, a);
+    return run_c<T, DIM, 2>(op, s, cap, st, a);
 }
-
 template <typename T>
-apic_status run_d(Op op, const apic_scene *s, hipStream_t st, const OpArgs &a) {
-    if (s->grid.dim == 3) return run_k<T, 3>(op, s, st, a);
-    return run_k<T, 2>(op, s, st, a);
+apic_status run_d(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
+    if (s->grid.dim == 3) return run_k<T, 3>(op, s, cap, st, a);
+    return run_k<T, 2>(op, s, cap, st, a);
 }
 
 apic_status dispatch(Op op, const apic_scene *s, void *stream, const OpArgs &a = OpArgs{nullptr, 0}) {
-    apic_status rc = check_scene(s);
+    int64_t cap = 0;
+    apic_status rc = check_scene(s, &cap);
     if (rc != APIC_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (s->grid.precision == APIC_F64) return run_d<double>(op, s, st, a);
-    return run_d<float>(op, s, st, a);
+    if (s->grid.precision == APIC_F64) return run_d<double>(op, s, cap, st, a);
+    return run_d<float>(op, s, cap, st, a);
 }
 
-apic_status hip_check(hipError_t e, const char *what) {
-    if (e != hipSuccess) return fail(APIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
-    return APIC_OK;
+template <typename T, int DIM, int DEG>
+apic_status steps_c(apic_scene *s, int64_t cap, int32_t n, int32_t k, hipStream_t st) {
+    if (s->grid.options & APIC_OPT_COMPENSATED) return run_steps<T, DIM, DEG, true>(s, cap, n, k, st);
+    return run_steps<T, DIM, DEG, false>(s, cap, n, k, st);
+}
+
+apic_status dispatch_steps(apic_scene *s, int64_t cap, int32_t n, int32_t k, hipStream_t st) {
+    const bool f64 = s->grid.precision == APIC_F64, d3 = s->grid.dim == 3, cub = s->grid.degree == APIC_CUBIC;
+    if (f64) {
+        if (d3) return cub ? steps_c<double, 3, 3>(s, cap, n, k, st) : steps_c<double, 3, 2>(s, cap, n, k, st);
+        return cub ? steps_c<double, 2, 3>(s, cap, n, k, st) : steps_c<double, 2, 2>(s, cap, n, k, st);
+    }
+    if (d3) return cub ? steps_c<float, 3, 3>(s, cap, n, k, st) : steps_c<float, 3, 2>(s, cap, n, k, st);
+    return cub ? steps_c<float, 2, 3>(s, cap, n, k, st) : steps_c<float, 2, 2>(s, cap, n, k, st);
 }
 
 }  // namespace
@@ -315,15 +518,19 @@ apic_status apic_workspace_bytes(const apic_grid_desc *grid, int64_t max_particl
     if (rc != APIC_OK) return rc;
     if (!bytes) return fail(APIC_E_INVAL, "bytes is NULL");
     if (max_particles < 0) return fail(APIC_E_INVAL, "max_particles is negative");
-    *bytes = make_layout(grid, max_particles).total;
+    *bytes = make_layout(grid, max_particles > 0 ? max_particles : 1).total;
     return APIC_OK;
 }
 
 apic_status apic_reset(apic_scene *scene, void *stream) {
-    apic_status rc = check_scene(scene);
+    int64_t cap = 0;
+    apic_status rc = check_scene(scene, &cap);
     if (rc != APIC_OK) return rc;
-    const Layout L = make_layout(&scene->grid, scene->p.n);
-    launch_fill<uint32_t>((uint32_t *)scene->workspace, (int64_t)(L.fixed_end / 4), 0u, (hipStream_t)stream);
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_states.erase(scene->workspace);
+    }
+    (void)state_of(scene, cap, (hipStream_t)stream);  // fresh entry, device reset
     return hip_check(hipGetLastError(), "apic_reset");
 }
 
@@ -339,19 +546,19 @@ apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int
     if (n_scenes < 0 || n_steps < 0 || sort_every < 0)
         return fail(APIC_E_INVAL, "n_scenes, n_steps and sort_every must be >= 0");
     if (n_scenes > 0 && !scenes) return fail(APIC_E_INVAL, "scenes is NULL");
+    int64_t caps[1];
     for (int32_t k = 0; k < n_scenes; ++k) {
-        apic_status rc = check_scene(&scenes[k]);
+        apic_status rc = check_scene(&scenes[k], caps);
         if (rc != APIC_OK) return rc;
+        for (int32_t j = 0; j < k; ++j)
+            if (scenes[j].workspace == scenes[k].workspace)
+                return fail(APIC_E_INVAL, "scenes %d and %d share a workspace", j, k);
     }
-    for (int32_t step = 0; step < n_steps; ++step) {
-        for (int32_t k = 0; k < n_scenes; ++k) {
-            apic_status rc = APIC_OK;
-            if (sort_every > 0 && step % sort_every == 0) rc = dispatch(Op::Sort, &scenes[k], stream);
-            if (rc == APIC_OK) rc = dispatch(Op::P2G, &scenes[k], stream);
-            if (rc == APIC_OK) rc = dispatch(Op::GridUpdate, &scenes[k], stream);
-            if (rc == APIC_OK) rc = dispatch(Op::G2P, &scenes[k], stream);
-            if (rc != APIC_OK) return rc;
-        }
+    for (int32_t k = 0; k < n_scenes; ++k) {
+        int64_t cap = 0;
+        (void)check_scene(&scenes[k], &cap);
+        apic_status rc = dispatch_steps(&scenes[k], cap, n_steps, sort_every, (hipStream_t)stream);
+        if (rc != APIC_OK) return rc;
     }
     return APIC_OK;
 }
@@ -373,7 +580,9 @@ apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out
     else
         return fail(APIC_E_INVAL, "unknown diagnostics kind %d", which);
     if (rc != APIC_OK) return rc;
-    const Layout L = make_layout(&scene->grid, scene->p.n);
+    int64_t cap = 0;
+    (void)check_scene(scene, &cap);
+    const Layout L = make_layout(&scene->grid, cap);
     hipStream_t st = (hipStream_t)stream;
     rc = hip_check(hipMemcpyAsync(out, (char *)scene->workspace + L.o_diag_out, 8 * sizeof(double),
                                   hipMemcpyDeviceToHost, st),
@@ -384,9 +593,11 @@ apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out
 
 apic_status apic_get_flags(const apic_scene *scene, uint32_t *flags, void *stream) {
     if (!flags) return fail(APIC_E_INVAL, "flags is NULL");
-    apic_status rc = check_scene(scene);
+    int64_t cap = 0;
+    apic_status rc = check_scene(scene, &cap);
     if (rc != APIC_OK) return rc;
-    const Layout L = make_layout(&scene->grid, scene->p.n);
+    (void)state_of(scene, cap, (hipStream_t)stream);
+    const Layout L = make_layout(&scene->grid, cap);
     hipStream_t st = (hipStream_t)stream;
     rc = hip_check(hipMemcpyAsync(flags, (char *)scene->workspace + L.o_flags, sizeof(uint32_t),
                                   hipMemcpyDeviceToHost, st),
@@ -396,9 +607,11 @@ apic_status apic_get_flags(const apic_scene *scene, uint32_t *flags, void *strea
 }
 
 apic_status apic_clear_flags(apic_scene *scene, void *stream) {
-    apic_status rc = check_scene(scene);
+    int64_t cap = 0;
+    apic_status rc = check_scene(scene, &cap);
     if (rc != APIC_OK) return rc;
-    const Layout L = make_layout(&scene->grid, scene->p.n);
+    (void)state_of(scene, cap, (hipStream_t)stream);
+    const Layout L = make_layout(&scene->grid, cap);
     launch_fill<uint32_t>((uint32_t *)((char *)scene->workspace + L.o_flags), 16, 0u, (hipStream_t)stream);
     return hip_check(hipGetLastError(), "apic_clear_flags");
 }
@@ -415,6 +628,6 @@ apic_status apic_positions_to_absolute(const apic_scene *scene, double *x, void 
 
 const char *apic_last_error(void) { return g_last_error.c_str(); }
 
-const char *apic_version(void) { return "libapic 0.1 (gfx950)"; }
+const char *apic_version(void) { return "libapic 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -1,8 +1,25 @@
-// Shared device/host definitions of libapic (gfx950).
+// Shared device/host definitions of libapic (gfx950, wave64).
 //
 // Method: Jiang, Schroeder, Teran, "An angular momentum conserving
 // Affine-Particle-In-Cell method" (arXiv 1603.06188), explicit step at
 // lambda = 0 (Sec. 3.2-3.5, lambda = 0 forms of Sec. 5.7).
+//
+// Data layout
+//   Keys.  A particle's key is its base grid node: the lowest node of its
+//   kernel support (quadratic: the node below x/dx - 1/2; cubic: cell - 1).
+//   Keys and nodes are grouped in tiles of 64 (4x4x4 in 3D, 8x8 in 2D); a
+//   tile is handled by one wavefront, one lane per key / node.
+//   Grid.  Node values (velocity planes) are stored tile-major: node
+//   (x, y, z) at tile(x/4, y/4, z/4) * 64 + (x%4) + 4 (y%4) + 16 (z%4).
+//   Particles.  Structure of arrays.  After binning, the particles of every
+//   listed tile are contiguous and stored level by level: level j holds the
+//   j-th particle of every key of the tile that has more than j particles, in
+//   key order, so the wavefront that owns the tile reads each level with
+//   one coalesced load per field.  Particles that cannot be binned (support
+//   outside the grid, non-finite state) follow all tiles ("dead" region).
+//   Slabs.  P2G writes, per listed tile, the mass and momentum of the
+//   (4+K-1)^3 nodes its keys touch (K = kernel support width); the grid update
+//   sums the at most 8 slabs that cover a node.  No float atomics anywhere.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,13 +27,6 @@
 
 namespace apic {
 
-// ---------------------------------------------------------------------------
-// Workspace / grid description shared by host and device
-// ---------------------------------------------------------------------------
-
-// Grid nodes are stored tile-major: 4x4x4-node tiles in 3D, 8x8 in 2D, 64
-// nodes per tile, tiles in x-fastest order.  Planes are `G` nodes long
-// (node count padded to whole tiles).
 struct GridDims {
     int dim, deg;
     int n[3];      // cells per axis
@@ -34,13 +44,39 @@ struct Parts {
     int64_t n, s;  // count, plane stride
 };
 
+// One binned layout of the particles (double-buffered in the workspace).
+struct BinMeta {
+    uint32_t *count;    // [1] listed tiles;  count[1] = dead particles
+    uint32_t *tile;     // [cap] tile id of each record
+    uint32_t *base;     // [cap + 1] first particle of each record; base[count] = first dead particle
+    uint32_t *maxc;     // [cap] largest per-key count of the record
+    uint32_t *kcount;   // [cap * 64] particles per key
+    uint32_t *kprefix;  // [cap * 64] exclusive prefix of kcount within the record
+    int32_t *map;       // [tiles] tile id -> record, -1 if not listed
+};
+
+// Scratch of the binning passes (single-buffered; invariants noted).
+struct BinScratch {
+    uint32_t *key_count;  // [G]      per-key counters, all zero between passes
+    uint32_t *tile_flag;  // [tiles]  all zero between passes
+    uint32_t *node_flag;  // [tiles]  all zero between passes
+    uint32_t *node_list;  // [tiles]  node tiles the next grid update visits
+    uint32_t *node_count; // [1]
+    uint32_t *pkey;       // [cap]    new key of each particle (0xFFFFFFFF: dead)
+    uint32_t *prank;      // [cap]    rank of the particle within its key
+    uint32_t *perm;       // [cap]    key-major position -> level-major position
+    uint32_t *sums;       // scan scratch
+};
+
 template <typename T>
-struct GridPlanes {
-    T *m;      // 1 plane
-    T *mv;     // dim planes: (m v)_i + dt f_i
-    T *vt;     // dim planes: updated velocity
-    T *cm;     // 1 plane error term of m  (compensated option)
-    T *cmv;    // dim planes error term of mv
+struct Slabs {
+    T *v;               // [cap][NC * RN] (+ error terms when compensated)
+    int64_t stride;     // elements per record
+};
+
+template <typename T>
+struct GridState {
+    T *vt;              // dim planes of G nodes: updated velocity
     uint32_t *flags;
     GridDims d;
     T dx, inv_dx;
@@ -60,14 +96,29 @@ enum : uint32_t {
     FLAG_NONFINITE = 2u,
     FLAG_INVERTED = 4u,
     FLAG_CFL = 8u,
+    FLAG_UNSORTED = 16u,
+};
+
+constexpr uint32_t kDeadKey = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Compile-time geometry per (DIM, DEG)
+// ---------------------------------------------------------------------------
+template <int DIM, int DEG>
+struct Geo {
+    static constexpr int TE = DIM == 3 ? 4 : 8;          // tile edge
+    static constexpr int K = DEG + 1;                     // support width
+    static constexpr int RE = TE + DEG;                   // slab edge (nodes)
+    static constexpr int RN = DIM == 3 ? RE * RE * RE : RE * RE;
+    static constexpr int NODES = DIM == 3 ? K * K * K : K * K;  // support nodes
+    static constexpr int NC = 1 + DIM;                    // m, mv
 };
 
 // ---------------------------------------------------------------------------
 // Packed cell index and tiled node index
 // ---------------------------------------------------------------------------
-
 template <int DIM>
-__device__ __forceinline__ void unpack_cell(uint32_t c, int *ci) {
+__host__ __device__ __forceinline__ void unpack_cell(uint32_t c, int *ci) {
     if constexpr (DIM == 3) {
         ci[0] = (int)(c & 1023u);
         ci[1] = (int)((c >> 10) & 1023u);
@@ -79,7 +130,7 @@ __device__ __forceinline__ void unpack_cell(uint32_t c, int *ci) {
 }
 
 template <int DIM>
-__device__ __forceinline__ uint32_t pack_cell(const int *ci) {
+__host__ __device__ __forceinline__ uint32_t pack_cell(const int *ci) {
     if constexpr (DIM == 3)
         return (uint32_t)ci[0] | ((uint32_t)ci[1] << 10) | ((uint32_t)ci[2] << 20);
     else
@@ -87,34 +138,50 @@ __device__ __forceinline__ uint32_t pack_cell(const int *ci) {
 }
 
 template <int DIM>
-__host__ __device__ __forceinline__ int64_t node_index(int ix, int iy, int iz, const int *TN) {
+__host__ __device__ __forceinline__ int64_t tile_of(const int *c, const int *TN) {
+    if constexpr (DIM == 3)
+        return (int64_t)(c[0] >> 2) + (int64_t)TN[0] * ((c[1] >> 2) + (int64_t)TN[1] * (c[2] >> 2));
+    else
+        return (int64_t)(c[0] >> 3) + (int64_t)TN[0] * (c[1] >> 3);
+}
+
+template <int DIM>
+__host__ __device__ __forceinline__ int local_of(const int *c) {
+    if constexpr (DIM == 3)
+        return (c[0] & 3) | ((c[1] & 3) << 2) | ((c[2] & 3) << 4);
+    else
+        return (c[0] & 7) | ((c[1] & 7) << 3);
+}
+
+template <int DIM>
+__host__ __device__ __forceinline__ int64_t node_index(const int *c, const int *TN) {
+    return tile_of<DIM>(c, TN) * 64 + local_of<DIM>(c);
+}
+
+// tile id -> coordinates of its first node / key
+template <int DIM>
+__host__ __device__ __forceinline__ void tile_origin(int64_t t, const int *TN, int *c) {
+    constexpr int TE = DIM == 3 ? 4 : 8;
+    c[0] = (int)(t % TN[0]) * TE;
     if constexpr (DIM == 3) {
-        int64_t t = (int64_t)(ix >> 2) + (int64_t)TN[0] * ((iy >> 2) + (int64_t)TN[1] * (iz >> 2));
-        return t * 64 + ((ix & 3) | ((iy & 3) << 2) | ((iz & 3) << 4));
+        int64_t r = t / TN[0];
+        c[1] = (int)(r % TN[1]) * TE;
+        c[2] = (int)(r / TN[1]) * TE;
     } else {
-        int64_t t = (int64_t)(ix >> 3) + (int64_t)TN[0] * (iy >> 3);
-        return t * 64 + ((ix & 7) | ((iy & 7) << 3));
+        c[1] = (int)(t / TN[0]) * TE;
     }
 }
 
-// Inverse of node_index: tiled index -> node coordinates.
+// local index 0..63 -> offset inside the tile
 template <int DIM>
-__host__ __device__ __forceinline__ void node_coords(int64_t i, const int *TN, int *c) {
-    int64_t t = i >> 6;
-    int l = (int)(i & 63);
+__host__ __device__ __forceinline__ void local_coords(int l, int *c) {
     if constexpr (DIM == 3) {
-        int tx = (int)(t % TN[0]);
-        int64_t r = t / TN[0];
-        int ty = (int)(r % TN[1]);
-        int tz = (int)(r / TN[1]);
-        c[0] = tx * 4 + (l & 3);
-        c[1] = ty * 4 + ((l >> 2) & 3);
-        c[2] = tz * 4 + (l >> 4);
+        c[0] = l & 3;
+        c[1] = (l >> 2) & 3;
+        c[2] = l >> 4;
     } else {
-        int tx = (int)(t % TN[0]);
-        int ty = (int)(t / TN[0]);
-        c[0] = tx * 8 + (l & 7);
-        c[1] = ty * 8 + (l >> 3);
+        c[0] = l & 7;
+        c[1] = l >> 3;
     }
 }
 
@@ -122,9 +189,9 @@ __host__ __device__ __forceinline__ void node_coords(int64_t i, const int *TN, i
 // Quadratic / cubic B-spline weights along one axis (Sec. 3.5), in cell
 // units, relative to the base node of the kernel support.
 //
-// Quadratic: base = the node nearest below x/dx - 1/2; with c = x/dx - base - 1
-// in [-1/2, 1/2), the three weights are 1/2 (1/2 - c)^2, 3/4 - c^2,
-// 1/2 (1/2 + c)^2.  Cubic: base = cell - 1, u = offset in [0, 1), q = 1 - u:
+// Quadratic: base = node below x/dx - 1/2; with c = x/dx - base - 1 in
+// [-1/2, 1/2) the weights are 1/2 (1/2 - c)^2, 3/4 - c^2, 1/2 (1/2 + c)^2.
+// Cubic: base = cell - 1, u = offset in [0, 1), q = 1 - u:
 // q^3/6, u^3/2 - u^2 + 2/3, q^3/2 - q^2 + 2/3, u^3/6.
 // w[k]: weight of node base+k; dw[k]: d w[k] / d x_p (cell units);
 // r[k]: (x_{base+k} - x_p) / dx.
@@ -134,6 +201,14 @@ struct Axis {
     int base;
     T w[DEG + 1], dw[DEG + 1], r[DEG + 1];
 };
+
+template <typename T, int DEG>
+__device__ __forceinline__ int base_of(int cell, T off) {
+    if constexpr (DEG == 2)
+        return off < T(0.5) ? cell - 1 : cell;
+    else
+        return cell - 1;
+}
 
 template <typename T, int DEG>
 __device__ __forceinline__ void axis_weights(int cell, T off, Axis<T, DEG> &a) {
@@ -195,5 +270,25 @@ template <>
 __device__ __forceinline__ float floor_t<float>(float x) { return floorf(x); }
 template <>
 __device__ __forceinline__ double floor_t<double>(double x) { return floor(x); }
+
+// wave64 helpers
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// Exact error of a + b (Knuth two-sum).
+template <typename T>
+__device__ __forceinline__ T two_sum_err(T a, T b, T s) {
+    T bp = s - a;
+    return (a - (s - bp)) + (b - bp);
+}
+
+// Compiler and LDS ordering point between dependent rounds of one wavefront.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 }  // namespace apic

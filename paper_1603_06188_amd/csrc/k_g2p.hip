@@ -1,0 +1,312 @@
+// Transfer to particles (Sec. 3.4) in its lambda = 0 form (Sec. 5.7), with
+// the weights of time n, fused with the re-binning of the particles:
+//   v_p = sum_i w_ip vt_i
+//   B_p = sum_i w_ip vt_i (x_i - x_p)^T
+//   F_p = (I + dt sum_i vt_i grad w_ip^T) F_p
+//   x_p = x_p + dt v_p          (cell index + offset)
+// Pass 1 (k_bin_keys_moved) computes every particle's new position to find
+// its new key and rank; pass 2 (k_g2p) computes the whole update and writes
+// the particle at its place in the new layout.  Both passes get the new
+// position from `advect`, whose operation sequence is fixed (no contraction
+// freedom), so the two agree bit for bit.
+#include "apic_bin_device.h"
+#include "apic_kernels.h"
+
+namespace apic {
+
+// Weights along one axis with a fixed operation sequence (see axis_weights).
+template <typename T, int DEG>
+__device__ __forceinline__ int axis_w_fixed(int cell, T off, T *w) {
+#pragma clang fp contract(off)
+    if constexpr (DEG == 2) {
+        const bool lower = off < T(0.5);
+        const T c = lower ? off : off - T(1);
+        const T l = T(0.5) - c, h = T(0.5) + c;
+        w[0] = T(0.5) * (l * l);
+        w[1] = T(0.75) - c * c;
+        w[2] = T(0.5) * (h * h);
+        return lower ? cell - 1 : cell;
+    } else {
+        const T u = off, q = T(1) - off;
+        const T u2 = u * u, q2 = q * q;
+        w[0] = (q2 * q) * T(1.0 / 6.0);
+        w[1] = (T(0.5) * (u2 * u) - u2) + T(2.0 / 3.0);
+        w[2] = (T(0.5) * (q2 * q) - q2) + T(2.0 / 3.0);
+        w[3] = (u2 * u) * T(1.0 / 6.0);
+        return cell - 1;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Support-node velocities of a particle: vt[node][k], node = a + K (b + K c).
+template <typename T, int DIM, int DEG>
+__device__ __forceinline__ void load_support(const int *base, const GridState<T> &g,
+                                             T (&vt)[Geo<DIM, DEG>::NODES][DIM]) {
+    constexpr int K = DEG + 1;
+    const int64_t G = g.d.G;
+#pragma unroll
+    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const int nc[3] = {base[0] + a, base[1] + b, DIM == 3 ? base[2] + c : 0};
+                const int64_t i = node_index<DIM>(nc, g.d.TN);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) vt[a + K * (b + K * c)][k] = g.vt[k * G + i];
+            }
+}
+
+// New velocity sum_i w vt_i and position x + dt v, fixed operation order.
+template <typename T, int DIM, int DEG>
+__device__ __forceinline__ void advect(const int *ci, const T *off, const T (&vt)[Geo<DIM, DEG>::NODES][DIM],
+                                       const T (&w)[DIM][DEG + 1], T dt_inv_dx, T *vn, int *cn, T *on,
+                                       bool &cfl) {
+#pragma clang fp contract(off)
+    constexpr int K = DEG + 1;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) vn[k] = T(0);
+#pragma unroll
+    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const T wyz = DIM == 3 ? w[1][b] * w[2][c] : w[1][b];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const T wn = w[0][a] * wyz;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) vn[k] = fma_t(wn, vt[a + K * (b + K * c)][k], vn[k]);
+            }
+        }
+    cfl = false;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T step = dt_inv_dx * vn[a];
+        cfl = cfl || !(step <= T(1) && step >= T(-1));
+        T o = off[a] + step;
+        const T fl = floor_t(o);
+        int cc = ci[a] + (int)fl;
+        o = o - fl;
+        if (o >= T(1)) {
+            o = o - T(1);
+            cc += 1;
+        }
+        cn[a] = cc;
+        on[a] = o;
+    }
+}
+
+// A particle index at or beyond the first dead particle of `cur` is dead.
+__device__ __forceinline__ bool is_dead(int64_t p, const BinMeta &cur) { return p >= (int64_t)cur.base[cur.count[0]]; }
+
+// --- pass 1: keys at the advected positions ---------------------------------------
+template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinMeta cur, GridState<T> g, StepParams<T> prm,
+                                                        BinMeta nxt, BinScratch sc) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    uint32_t key = kDeadKey;
+    if (!is_dead(p, cur)) {
+        int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
+        unpack_cell<DIM>(P.cell[p], ci);
+        T off[DIM], w[DIM][DEG + 1], on[DIM], vn[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            off[a] = P.off[a * P.s + p];
+            base[a] = axis_w_fixed<T, DEG>(ci[a], off[a], w[a]);
+        }
+        T vt[Geo<DIM, DEG>::NODES][DIM];
+        load_support<T, DIM, DEG>(base, g, vt);
+        bool cfl;
+        advect<T, DIM, DEG>(ci, off, vt, w, prm.dt * g.inv_dx, vn, cn, on, cfl);
+        bool finite;
+        key = key_of<T, DIM, DEG>(cn, on, g.d, finite);
+        if (key == kDeadKey) atomicOr(g.flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
+    }
+    const uint32_t rank = bin_take_slot(key, nxt, sc);
+    sc.pkey[p] = key;
+    sc.prank[p] = rank;
+}
+
+template <typename T, int DIM, int DEG>
+void launch_bin_keys_moved(const Parts<T> &P, const BinMeta &cur, const GridState<T> &g, const StepParams<T> &prm,
+                           const BinMeta &nxt, const BinScratch &sc, hipStream_t st) {
+    if (P.n == 0) return;
+    hipLaunchKernelGGL((k_bin_keys_moved<T, DIM, DEG>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P,
+                       cur, g, prm, nxt, sc);
+}
+
+// --- pass 2: the transfer, written to the new layout --------------------------------
+template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) void k_g2p(Parts<T> src, Parts<T> dst, BinMeta cur, BinMeta nxt, BinScratch sc,
+                                             GridState<T> g, StepParams<T> prm) {
+    constexpr int K = DEG + 1;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= src.n) return;
+    const int64_t q = bin_destination(sc.pkey[p], sc.prank[p], nxt, sc);
+    const int64_t ss = src.s, ds = dst.s;
+    dst.m[q] = src.m[p];
+    if (src.id) dst.id[q] = src.id[p];
+    if (is_dead(p, cur)) {
+        dst.cell[q] = src.cell[p];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            dst.off[a * ds + q] = src.off[a * ss + p];
+            dst.v[a * ds + q] = src.v[a * ss + p];
+        }
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) {
+            dst.B[k * ds + q] = src.B[k * ss + p];
+            dst.F[k * ds + q] = src.F[k * ss + p];
+        }
+        return;
+    }
+    int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
+    unpack_cell<DIM>(src.cell[p], ci);
+    T off[DIM], wf[DIM][K], on[DIM], vn[DIM], F[DIM * DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        off[a] = src.off[a * ss + p];
+        base[a] = axis_w_fixed<T, DEG>(ci[a], off[a], wf[a]);
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) F[k] = src.F[k * ss + p];
+    T vt[Geo<DIM, DEG>::NODES][DIM];
+    load_support<T, DIM, DEG>(base, g, vt);
+    bool cfl;
+    advect<T, DIM, DEG>(ci, off, vt, wf, prm.dt * g.inv_dx, vn, cn, on, cfl);
+    if (cfl) atomicOr(g.flags, FLAG_CFL);
+
+    // B (cell units) and grad v (1/cell) from the tensor-product weights
+    Axis<T, DEG> ax[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) axis_weights<T, DEG>(ci[a], off[a], ax[a]);
+    T Bc[DIM * DIM], Gc[DIM * DIM];
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) Bc[k] = Gc[k] = T(0);
+    if constexpr (DIM == 3) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            T P1[3] = {0, 0, 0}, P2[3] = {0, 0, 0}, P3[3] = {0, 0, 0}, P4[3] = {0, 0, 0}, P5[3] = {0, 0, 0};
+#pragma unroll
+            for (int b = 0; b < K; ++b) {
+                T S[3] = {0, 0, 0}, Tz[3] = {0, 0, 0}, U[3] = {0, 0, 0};
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    const T wz = ax[2].w[c], wrz = ax[2].w[c] * ax[2].r[c], dz = ax[2].dw[c];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const T x = vt[a + K * (b + K * c)][k];
+                        S[k] += wz * x;
+                        Tz[k] += wrz * x;
+                        U[k] += dz * x;
+                    }
+                }
+                const T wy = ax[1].w[b], wry = ax[1].w[b] * ax[1].r[b], dy = ax[1].dw[b];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    P1[k] += wy * S[k];
+                    P2[k] += wry * S[k];
+                    P3[k] += dy * S[k];
+                    P4[k] += wy * Tz[k];
+                    P5[k] += wy * U[k];
+                }
+            }
+            const T wx = ax[0].w[a], wrx = ax[0].w[a] * ax[0].r[a], dx = ax[0].dw[a];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Bc[k * 3 + 0] += wrx * P1[k];
+                Gc[k * 3 + 0] += dx * P1[k];
+                Bc[k * 3 + 1] += wx * P2[k];
+                Gc[k * 3 + 1] += wx * P3[k];
+                Bc[k * 3 + 2] += wx * P4[k];
+                Gc[k * 3 + 2] += wx * P5[k];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            T P1[2] = {0, 0}, P2[2] = {0, 0}, P3[2] = {0, 0};
+#pragma unroll
+            for (int b = 0; b < K; ++b) {
+                const T wy = ax[1].w[b], wry = ax[1].w[b] * ax[1].r[b], dy = ax[1].dw[b];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const T x = vt[a + K * b][k];
+                    P1[k] += wy * x;
+                    P2[k] += wry * x;
+                    P3[k] += dy * x;
+                }
+            }
+            const T wx = ax[0].w[a], wrx = ax[0].w[a] * ax[0].r[a], dx = ax[0].dw[a];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                Bc[k * 2 + 0] += wrx * P1[k];
+                Gc[k * 2 + 0] += dx * P1[k];
+                Bc[k * 2 + 1] += wx * P2[k];
+                Gc[k * 2 + 1] += wx * P3[k];
+            }
+        }
+    }
+    // F <- (I + dt grad v) F, grad v = Gc / dx
+    const T gs = prm.dt * g.inv_dx;
+    T Fn[DIM * DIM];
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) acc += Gc[r * DIM + k] * F[k * DIM + c];
+            Fn[r * DIM + c] = F[r * DIM + c] + gs * acc;
+        }
+    // keep the packed index representable; a particle that left the grid is
+    // in the dead region of the new layout and is not transferred again
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) cn[a] = cn[a] < 0 ? 0 : (cn[a] > g.d.n[a] - 1 ? g.d.n[a] - 1 : cn[a]);
+    dst.cell[q] = pack_cell<DIM>(cn);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        dst.off[a * ds + q] = on[a];
+        dst.v[a * ds + q] = vn[a];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        dst.B[k * ds + q] = Bc[k] * g.dx;
+        dst.F[k * ds + q] = Fn[k];
+    }
+}
+
+template <typename T, int DIM, int DEG>
+void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinMeta &cur, const BinMeta &nxt,
+                const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm, hipStream_t st) {
+    if (src.n == 0) return;
+    Parts<T> s2 = src, d2 = dst;
+    if (!src.id || !dst.id) s2.id = d2.id = nullptr;
+    hipLaunchKernelGGL((k_g2p<T, DIM, DEG>), dim3((unsigned)((src.n + 255) / 256)), dim3(256), 0, st, s2, d2, cur, nxt,
+                       sc, g, prm);
+}
+
+#define APIC_G2P_INST(T, DIM, DEG)                                                                               \
+    template void launch_bin_keys_moved<T, DIM, DEG>(const Parts<T> &, const BinMeta &, const GridState<T> &,    \
+                                                     const StepParams<T> &, const BinMeta &, const BinScratch &,  \
+                                                     hipStream_t);                                               \
+    template void launch_g2p<T, DIM, DEG>(const Parts<T> &, const Parts<T> &, const BinMeta &, const BinMeta &,  \
+                                          const BinScratch &, const GridState<T> &, const StepParams<T> &,       \
+                                          hipStream_t);
+APIC_G2P_INST(float, 2, 2)
+APIC_G2P_INST(float, 2, 3)
+APIC_G2P_INST(float, 3, 2)
+APIC_G2P_INST(float, 3, 3)
+APIC_G2P_INST(double, 2, 2)
+APIC_G2P_INST(double, 2, 3)
+APIC_G2P_INST(double, 3, 2)
+APIC_G2P_INST(double, 3, 3)
+
+}  // namespace apic

@@ -1,0 +1,175 @@
+// Fills, state copies, binary64 particle totals and position conversion.
+#include "apic_kernels.h"
+
+namespace apic {
+
+static inline int blocks_for(int64_t work, int threads, int cap) {
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t count, T val) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+template <typename T>
+void launch_fill(T *p, int64_t count, T val, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(count, 256, 8192)), dim3(256), 0, st, p, count, val);
+}
+template void launch_fill<float>(float *, int64_t, float, hipStream_t);
+template void launch_fill<double>(double *, int64_t, double, hipStream_t);
+template void launch_fill<uint32_t>(uint32_t *, int64_t, uint32_t, hipStream_t);
+template void launch_fill<int32_t>(int32_t *, int64_t, int32_t, hipStream_t);
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_copy_state(Parts<T> src, Parts<T> dst) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= src.n) return;
+    dst.cell[j] = src.cell[j];
+    dst.m[j] = src.m[j];
+    if (src.id) dst.id[j] = src.id[j];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        dst.off[a * dst.s + j] = src.off[a * src.s + j];
+        dst.v[a * dst.s + j] = src.v[a * src.s + j];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        dst.B[k * dst.s + j] = src.B[k * src.s + j];
+        dst.F[k * dst.s + j] = src.F[k * src.s + j];
+    }
+}
+
+template <typename T, int DIM>
+void launch_copy_state(const Parts<T> &src, const Parts<T> &dst, hipStream_t st) {
+    if (src.n == 0) return;
+    Parts<T> s2 = src, d2 = dst;
+    if (!src.id || !dst.id) s2.id = d2.id = nullptr;
+    hipLaunchKernelGGL((k_copy_state<T, DIM>), dim3((unsigned)((src.n + 255) / 256)), dim3(256), 0, st, s2, d2);
+}
+
+// --- binary64 particle totals (Sec. 3.1; B term of Sec. 5.3) -------------------
+__device__ __forceinline__ void block_reduce8p(double *acc, double *partials) {
+    __shared__ double sh[8][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        double x = acc[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if (lane == 0) sh[k][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[threadIdx.x][w];
+        partials[blockIdx.x * 8 + threadIdx.x] = t;
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_diag_particles(Parts<T> P, double dx, double *partials) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += (int64_t)gridDim.x * blockDim.x) {
+        int ci[3] = {0, 0, 0};
+        unpack_cell<DIM>(P.cell[p], ci);
+        double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, Bm[9];
+        const double m = (double)P.m[p];
+        for (int a = 0; a < DIM; ++a) {
+            x[a] = ((double)ci[a] + (double)P.off[a * P.s + p]) * dx;
+            v[a] = (double)P.v[a * P.s + p];
+        }
+        for (int k = 0; k < DIM * DIM; ++k) Bm[k] = (double)P.B[k * P.s + p];
+        const double mv[3] = {m * v[0], m * v[1], m * v[2]};
+        acc[0] += mv[0];
+        acc[1] += mv[1];
+        acc[2] += mv[2];
+        if constexpr (DIM == 3) {
+            // x x m v + m (B^T : eps): B_zy - B_yz, B_xz - B_zx, B_yx - B_xy
+            acc[3] += x[1] * mv[2] - x[2] * mv[1] + m * (Bm[7] - Bm[5]);
+            acc[4] += x[2] * mv[0] - x[0] * mv[2] + m * (Bm[2] - Bm[6]);
+            acc[5] += x[0] * mv[1] - x[1] * mv[0] + m * (Bm[3] - Bm[1]);
+        } else {
+            acc[5] += x[0] * mv[1] - x[1] * mv[0] + m * (Bm[2] - Bm[1]);
+        }
+        double v2 = 0.0;
+        for (int a = 0; a < DIM; ++a) v2 += v[a] * v[a];
+        acc[6] += 0.5 * m * v2;
+        acc[7] += m;
+    }
+    block_reduce8p(acc, partials);
+}
+
+__global__ void k_diag_final(const double *partials, int nb, double *out) {
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += partials[b * 8 + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+template <typename T, int DIM>
+void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st) {
+    const int nb = blocks_for(P.n, 256, kDiagBlocks);
+    hipLaunchKernelGGL((k_diag_particles<T, DIM>), dim3(nb), dim3(256), 0, st, P, dx, partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, nb, out);
+}
+
+// --- absolute positions <-> cell + offset ---------------------------------------
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_pack_positions(Parts<T> P, const double *x, double inv_dx) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    int ci[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a) {
+        const double sx = x[a * P.s + p] * inv_dx;
+        double c = floor(sx);
+        T o = (T)(sx - c);
+        if (o >= T(1)) {
+            o = T(0);
+            c += 1.0;
+        }
+        const int lim = DIM == 3 ? 1023 : 65535;
+        ci[a] = c < 0.0 ? 0 : (c > lim ? lim : (int)c);
+        P.off[a * P.s + p] = o;
+    }
+    P.cell[p] = pack_cell<DIM>(ci);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_unpack_positions(Parts<T> P, double *x, double dx) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    int ci[3] = {0, 0, 0};
+    unpack_cell<DIM>(P.cell[p], ci);
+    for (int a = 0; a < DIM; ++a) x[a * P.s + p] = ((double)ci[a] + (double)P.off[a * P.s + p]) * dx;
+}
+
+template <typename T, int DIM>
+void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStream_t st) {
+    if (P.n == 0) return;
+    hipLaunchKernelGGL((k_pack_positions<T, DIM>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, x,
+                       1.0 / dx);
+}
+
+template <typename T, int DIM>
+void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st) {
+    if (P.n == 0) return;
+    hipLaunchKernelGGL((k_unpack_positions<T, DIM>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, x, dx);
+}
+
+#define APIC_MISC_INST(T, DIM)                                                                                  \
+    template void launch_copy_state<T, DIM>(const Parts<T> &, const Parts<T> &, hipStream_t);                    \
+    template void launch_diag_particles<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);     \
+    template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t);         \
+    template void launch_unpack_positions<T, DIM>(const Parts<T> &, double *, double, hipStream_t);
+APIC_MISC_INST(float, 2)
+APIC_MISC_INST(float, 3)
+APIC_MISC_INST(double, 2)
+APIC_MISC_INST(double, 3)
+
+}  // namespace apic

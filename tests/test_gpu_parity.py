@@ -116,24 +116,51 @@ def test_disk2d_fp64_ten_round_trips():
         x, v, B, F = ref["x_new"], ref["v_new"], ref["B_new"], ref["F_new"]
 
 
-def test_sort_is_a_stable_permutation_by_base_node():
+def _base_keys(cell, off, cells, degree):
+    """Tile id and local index (0..63) of each particle's base node."""
+    base = np.where(off < 0.5, cell - 1, cell) if degree == 2 else cell - 1
+    TN = [(c + 1 + 3) // 4 for c in cells]
+    tile = (base[:, 0] >> 2) + TN[0] * ((base[:, 1] >> 2) + TN[1] * (base[:, 2] >> 2))
+    local = (base[:, 0] & 3) + 4 * (base[:, 1] & 3) + 16 * (base[:, 2] & 3)
+    return tile, local
+
+
+def check_binned_layout(tile, local):
+    """Particles of a tile are contiguous and level-major: every level lists
+    distinct base nodes in increasing order, and the nodes of level j+1 are
+    a subset of those of level j."""
+    starts = np.flatnonzero(np.r_[True, tile[1:] != tile[:-1]])
+    ends = np.r_[starts[1:], len(tile)]
+    assert len(np.unique(tile[starts])) == len(starts), "a tile appears in two runs"
+    for s0, e0 in zip(starts, ends):
+        seq = local[s0:e0]
+        cuts = np.flatnonzero(np.r_[True, seq[1:] <= seq[:-1]])
+        levels = [seq[a:b] for a, b in zip(cuts, np.r_[cuts[1:], len(seq)])]
+        for lo, hi in zip(levels, levels[1:]):
+            assert set(hi.tolist()) <= set(lo.tolist())
+
+
+def test_sort_bins_particles_level_major_by_base_node():
     b = _b()
     s = scenes.cube3d(cells=24, precision="fp32", steps=1)
     rng = np.random.default_rng(0)
     s = s.subset(rng.permutation(s.n))
     ds = b.DeviceScene(s)
-    before = ds.state()
     ds.sort()
-    after = ds.state()
-    # expected order: stable by tile-major index of the base node
-    base = np.where(s.off < 0.5, s.cell - 1, s.cell)
-    TN = [(c + 1 + 3) // 4 for c in s.cells]
-    tile = (base[:, 0] >> 2) + TN[0] * ((base[:, 1] >> 2) + TN[1] * (base[:, 2] >> 2))
-    key = tile * 64 + (base[:, 0] & 3) + 4 * (base[:, 1] & 3) + 16 * (base[:, 2] & 3)
-    order = np.argsort(key, kind="stable")
-    assert np.array_equal(after["id"], before["id"][order])
+    raw = ds.state(raw=True)
+    # a permutation of the input rows, each row intact
+    assert np.array_equal(np.sort(raw["id"]), np.arange(s.n))
     for k in ("cell", "off", "v", "B", "F", "m"):
-        assert np.array_equal(after[k], before[k][order]), k
+        ref = {"cell": s.cell, "off": s.off, "v": s.v, "B": s.B, "F": s.F, "m": s.m}[k]
+        assert np.array_equal(raw[k], ref[raw["id"]]), k
+    tile, local = _base_keys(raw["cell"], raw["off"], s.cells, s.degree)
+    check_binned_layout(tile, local)
+    # every step keeps the particles binned
+    ds.step(3)
+    raw = ds.state(raw=True)
+    tile, local = _base_keys(raw["cell"], raw["off"], s.cells, s.degree)
+    check_binned_layout(tile, local)
+    assert ds.flags() == 0
 
 
 def test_empty_scene():
