@@ -106,44 +106,26 @@ def main(argv=None):
     ds.p2g()
     active = int(np.count_nonzero(ds.export(b.APIC_GRID_MASS)))
 
-    def one_step(k, ev=None):
-        if args.sort_every > 0 and k % args.sort_every == 0:
-            if ev: ev["sort"][0].record(st)
-            ds.sort()
-            if ev: ev["sort"][1].record(st)
-        for name, fn in (("p2g", ds.p2g), ("grid_update", ds.grid_update), ("g2p", ds.g2p)):
-            if ev: ev[name][0].record(st)
-            fn()
-            if ev: ev[name][1].record(st)
-
-    for k in range(args.warmup):
-        one_step(k)
+    ds.step(args.warmup, args.sort_every)
     torch.cuda.synchronize()
     ds.upload(scene)  # timed steps start from the initial state of the workload
     ds.clear_flags()
     torch.cuda.synchronize()
 
-    phases = ["sort", "p2g", "grid_update", "g2p"]
-    events = {p: [] for p in phases}
+    # timed region: K whole steps in one apic_step call; the library brackets
+    # every phase with HIP events on this stream
+    b.apic_timing_enable(True)
+    b.apic_timing_read()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev = {p: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for p in phases}
-        one_step(k, ev)
-        for p in phases:
-            events[p].append(ev[p])
+    ds.step(args.steps, args.sort_every)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    timing = b.apic_timing_read()
+    b.apic_timing_enable(False)
     flags = ds.flags()
-
-    dur = {}
-    for p in phases:
-        ts = []
-        for s, e in events[p]:
-            try:
-                ts.append(s.elapsed_time(e))
-            except (RuntimeError, ValueError):
-                pass  # phase not run in this step (sort)
-        dur[p] = (sum(ts) / len(ts)) if ts else 0.0
+    phases = list(timing)
+    dur = {p: timing[p][1] for p in phases}
 
     n = scene.n
     comp_b = 16 if compensated else 0

@@ -238,6 +238,26 @@ apic_status apic_clear_flags(apic_scene *scene, void *stream);
 apic_status apic_positions_from_absolute(apic_scene *scene, const double *x, void *stream);
 apic_status apic_positions_to_absolute(const apic_scene *scene, double *x, void *stream);
 
+/*
+ * Kernel timing, for benchmarks.  While enabled, apic_step brackets each of
+ * its phases (per scene and step) with a pair of HIP events on the call's
+ * stream.  apic_timing_read waits for the recorded events, writes per phase
+ * (index APIC_PHASE_*) the number of recorded launches to counts[] and their
+ * mean duration in milliseconds to mean_ms[] (host arrays of
+ * APIC_PHASE_COUNT entries), and forgets the records.  Events are created by
+ * the library (no device memory is allocated).
+ */
+enum {
+    APIC_PHASE_P2G = 0,          /* transfer to grid                         */
+    APIC_PHASE_GRID_UPDATE = 1,  /* grid update                              */
+    APIC_PHASE_BIN = 2,          /* keys at the advected positions + binning */
+    APIC_PHASE_G2P = 3,          /* transfer to particles (re-binned write)  */
+    APIC_PHASE_SORT = 4,         /* full re-bin from positions               */
+    APIC_PHASE_COUNT = 5
+};
+apic_status apic_timing_enable(int32_t enable);
+apic_status apic_timing_read(int64_t *counts, double *mean_ms);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char *apic_last_error(void);
 

@@ -38,8 +38,10 @@ APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
 EXPORTED = [
     "apic_workspace_bytes", "apic_reset", "apic_sort", "apic_p2g", "apic_grid_update", "apic_g2p", "apic_step",
     "apic_grid_export", "apic_diagnostics", "apic_get_flags", "apic_clear_flags",
-    "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_last_error", "apic_version",
+    "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
+    "apic_last_error", "apic_version",
 ]
+APIC_PHASES = ["p2g", "grid_update", "bin", "g2p", "sort"]
 
 
 class ApicGridDesc(ctypes.Structure):
@@ -85,6 +87,10 @@ for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = ctypes.c_int32
+_lib.apic_timing_enable.argtypes = [ctypes.c_int32]
+_lib.apic_timing_enable.restype = ctypes.c_int32
+_lib.apic_timing_read.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+_lib.apic_timing_read.restype = ctypes.c_int32
 _lib.apic_last_error.restype = ctypes.c_char_p
 _lib.apic_last_error.argtypes = []
 _lib.apic_version.restype = ctypes.c_char_p
@@ -168,6 +174,19 @@ def apic_positions_from_absolute(scene: ApicScene, x_ptr: int, stream=None) -> N
 
 def apic_positions_to_absolute(scene: ApicScene, x_ptr: int, stream=None) -> None:
     _check(_lib.apic_positions_to_absolute(ctypes.byref(scene), ctypes.c_void_p(x_ptr), _stream(stream)))
+
+
+def apic_timing_enable(enable: bool = True) -> None:
+    _check(_lib.apic_timing_enable(1 if enable else 0))
+
+
+def apic_timing_read() -> dict:
+    """{phase: (launches, mean ms)} of the phases apic_step recorded."""
+    n = len(APIC_PHASES)
+    counts = (ctypes.c_int64 * n)()
+    mean = (ctypes.c_double * n)()
+    _check(_lib.apic_timing_read(counts, mean))
+    return {APIC_PHASES[k]: (int(counts[k]), float(mean[k])) for k in range(n)}
 
 
 def apic_last_error() -> str:

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "apic.h"
 #include "apic_kernels.h"
@@ -223,6 +224,52 @@ apic_status hip_check(hipError_t e, const char *what) {
 }
 
 // ---------------------------------------------------------------------------
+// Optional phase timing (apic_timing_enable / apic_timing_read)
+// ---------------------------------------------------------------------------
+struct Timing {
+    std::mutex mu;
+    bool enabled = false;
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+Timing g_timing;
+
+// Runs `launch` bracketed by timing events when timing is enabled.
+template <typename F>
+void timed(int phase, hipStream_t st, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        if (g_timing.enabled) {
+            a = g_timing.take();
+            b = g_timing.take();
+        }
+    }
+    if (a && b) (void)hipEventRecord(a, st);
+    launch();
+    if (a && b) {
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        g_timing.recs.push_back({phase, a, b});
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Typed views of one scene
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -361,10 +408,13 @@ void bin_static(View<T> &v, const Parts<T> &src, const Parts<T> &dst, int nxt, h
 template <typename T, int DIM, int DEG>
 void g2p_rebin(View<T> &v, const Parts<T> &src, const Parts<T> &dst, int cur, hipStream_t st) {
     const int nxt = 1 - cur;
-    launch_bin_begin(v.meta[nxt], v.sc, v.b, st);
-    launch_bin_keys_moved<T, DIM, DEG>(src, v.meta[cur], v.g, v.prm, v.meta[nxt], v.sc, st);
-    launch_bin_finish<DIM>(v.L.d, v.meta[nxt], v.sc, v.b, st);
-    launch_g2p<T, DIM, DEG>(src, dst, v.meta[cur], v.meta[nxt], v.sc, v.g, v.prm, st);
+    timed(APIC_PHASE_BIN, st, [&] {
+        launch_bin_begin(v.meta[nxt], v.sc, v.b, st);
+        launch_bin_keys_moved<T, DIM, DEG>(src, v.meta[cur], v.g, v.prm, v.meta[nxt], v.sc, st);
+        launch_bin_finish<DIM>(v.L.d, v.meta[nxt], v.sc, v.b, st);
+    });
+    timed(APIC_PHASE_G2P, st,
+          [&] { launch_g2p<T, DIM, DEG>(src, dst, v.meta[cur], v.meta[nxt], v.sc, v.g, v.prm, st); });
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
@@ -442,18 +492,23 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
     Parts<T> bufs[2] = {v.user, v.shadow};
     int where = 0;
     if (!ss.binned) {
-        bin_static<T, DIM, DEG>(v, v.user, v.shadow, 1 - ss.cur, st);
+        timed(APIC_PHASE_SORT, st, [&] { bin_static<T, DIM, DEG>(v, v.user, v.shadow, 1 - ss.cur, st); });
         ss.cur = 1 - ss.cur;
         where = 1;
     }
     for (int32_t k = 0; k < n_steps; ++k) {
         if (sort_every > 0 && k > 0 && k % sort_every == 0) {
-            bin_static<T, DIM, DEG>(v, bufs[where], bufs[1 - where], 1 - ss.cur, st);
+            timed(APIC_PHASE_SORT, st,
+                  [&] { bin_static<T, DIM, DEG>(v, bufs[where], bufs[1 - where], 1 - ss.cur, st); });
             ss.cur = 1 - ss.cur;
             where = 1 - where;
         }
-        launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.meta[ss.cur], v.slabs, v.g, v.prm, v.b, st);
-        launch_grid_update<T, DIM, DEG, COMP>(v.meta[ss.cur], v.sc, v.slabs, v.g, v.prm, v.b, st);
+        timed(APIC_PHASE_P2G, st, [&] {
+            launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.meta[ss.cur], v.slabs, v.g, v.prm, v.b, st);
+        });
+        timed(APIC_PHASE_GRID_UPDATE, st, [&] {
+            launch_grid_update<T, DIM, DEG, COMP>(v.meta[ss.cur], v.sc, v.slabs, v.g, v.prm, v.b, st);
+        });
         ss.grid_meta = ss.cur;
         g2p_rebin<T, DIM, DEG>(v, bufs[where], bufs[1 - where], ss.cur, st);
         ss.cur = 1 - ss.cur;
@@ -624,6 +679,45 @@ apic_status apic_positions_from_absolute(apic_scene *scene, const double *x, voi
 apic_status apic_positions_to_absolute(const apic_scene *scene, double *x, void *stream) {
     if (!x && scene && scene->p.n > 0) return fail(APIC_E_INVAL, "x is NULL");
     return dispatch(Op::Unpack, scene, stream, OpArgs{(void *)x, 0});
+}
+
+apic_status apic_timing_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    g_timing.enabled = enable != 0;
+    return APIC_OK;
+}
+
+apic_status apic_timing_read(int64_t *counts, double *mean_ms) {
+    if (!counts || !mean_ms) return fail(APIC_E_INVAL, "counts and mean_ms must not be NULL");
+    std::vector<Timing::Rec> recs;
+    {
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        recs.swap(g_timing.recs);
+    }
+    double sum[APIC_PHASE_COUNT] = {0};
+    int64_t cnt[APIC_PHASE_COUNT] = {0};
+    apic_status rc = APIC_OK;
+    for (const auto &r : recs) {
+        if (rc == APIC_OK) rc = hip_check(hipEventSynchronize(r.b), "apic_timing_read");
+        float ms = 0.f;
+        if (rc == APIC_OK) rc = hip_check(hipEventElapsedTime(&ms, r.a, r.b), "apic_timing_read");
+        if (rc == APIC_OK && r.phase >= 0 && r.phase < APIC_PHASE_COUNT) {
+            sum[r.phase] += ms;
+            cnt[r.phase] += 1;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        for (const auto &r : recs) {
+            g_timing.pool.push_back(r.a);
+            g_timing.pool.push_back(r.b);
+        }
+    }
+    for (int k = 0; k < APIC_PHASE_COUNT; ++k) {
+        counts[k] = cnt[k];
+        mean_ms[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    }
+    return rc;
 }
 
 const char *apic_last_error(void) { return g_last_error.c_str(); }

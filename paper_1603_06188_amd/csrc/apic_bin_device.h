@@ -5,15 +5,36 @@
 
 namespace apic {
 
+// True for exactly one lane among the active lanes holding each value of t.
+// Must be called by the whole wavefront.
+__device__ __forceinline__ bool first_lane_of_value(uint32_t t, bool active) {
+    const int lane = lane_id();
+    uint64_t pending = ballot(active);
+    bool leader = false;
+    while (pending) {
+        const int first = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t tf = __shfl(t, first, 64);
+        pending &= ~ballot(active && t == tf);
+        leader = leader || lane == first;
+    }
+    return leader;
+}
+
 // Appends the key's tile to the record list on first touch and takes a rank
-// within the key; dead particles take a rank in the dead region.
-__device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, const BinMeta &nxt, const BinScratch &sc) {
-    if (key == kDeadKey) return atomicAdd(nxt.count + 1, 1u);
+// within the key; dead particles take a rank in the dead region.  Must be
+// called by the whole wavefront (`active` false for lanes without a particle).
+__device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, const BinMeta &nxt,
+                                                  const BinScratch &sc) {
+    const bool live = active && key != kDeadKey;
     const uint32_t t = key >> 6;
-    if (atomicOr(sc.tile_flag + t, 1u) == 0u) {
+    // one lane per distinct tile of the wavefront; a plain read skips the
+    // atomic for tiles already listed (a stale 0 only costs the atomic)
+    if (first_lane_of_value(t, live) && sc.tile_flag[t] == 0u && atomicOr(sc.tile_flag + t, 1u) == 0u) {
         const uint32_t rec = atomicAdd(nxt.count, 1u);
         nxt.tile[rec] = t;
     }
+    if (!active) return 0u;
+    if (key == kDeadKey) return atomicAdd(nxt.count + 1, 1u);
     return atomicAdd(sc.key_count + key, 1u);
 }
 

@@ -42,16 +42,20 @@ template <typename T, int DIM, int DEG>
 __global__ __launch_bounds__(256) void k_bin_keys_static(Parts<T> P, GridDims d, BinMeta nxt, BinScratch sc,
                                                          uint32_t *flags) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
-    int ci[3] = {0, 0, 0};
-    unpack_cell<DIM>(P.cell[p], ci);
-    T off[DIM];
+    const bool active = p < P.n;
+    uint32_t key = kDeadKey;
+    if (active) {
+        int ci[3] = {0, 0, 0};
+        unpack_cell<DIM>(P.cell[p], ci);
+        T off[DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) off[a] = P.off[a * P.s + p];
-    bool finite;
-    const uint32_t key = key_of<T, DIM, DEG>(ci, off, d, finite);
-    if (key == kDeadKey) atomicOr(flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
-    const uint32_t rank = bin_take_slot(key, nxt, sc);
+        for (int a = 0; a < DIM; ++a) off[a] = P.off[a * P.s + p];
+        bool finite;
+        key = key_of<T, DIM, DEG>(ci, off, d, finite);
+        if (key == kDeadKey) atomicOr(flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
+    }
+    const uint32_t rank = bin_take_slot(key, active, nxt, sc);
+    if (!active) return;
     sc.pkey[p] = key;
     sc.prank[p] = rank;
 }

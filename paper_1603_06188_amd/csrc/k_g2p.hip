@@ -110,9 +110,9 @@ template <typename T, int DIM, int DEG>
 __global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinMeta cur, GridState<T> g, StepParams<T> prm,
                                                         BinMeta nxt, BinScratch sc) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
+    const bool active = p < P.n;
     uint32_t key = kDeadKey;
-    if (!is_dead(p, cur)) {
+    if (active && !is_dead(p, cur)) {
         int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
         unpack_cell<DIM>(P.cell[p], ci);
         T off[DIM], w[DIM][DEG + 1], on[DIM], vn[DIM];
@@ -129,7 +129,8 @@ __global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinMeta cur,
         key = key_of<T, DIM, DEG>(cn, on, g.d, finite);
         if (key == kDeadKey) atomicOr(g.flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
     }
-    const uint32_t rank = bin_take_slot(key, nxt, sc);
+    const uint32_t rank = bin_take_slot(key, active, nxt, sc);
+    if (!active) return;
     sc.pkey[p] = key;
     sc.prank[p] = rank;
 }
