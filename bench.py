@@ -78,7 +78,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--cells", type=int, default=128)
     ap.add_argument("--plain", action="store_true", help="uncompensated binary32 accumulation")
     ap.add_argument("--no-cpu-baseline", action="store_true")

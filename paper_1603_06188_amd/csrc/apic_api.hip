@@ -51,7 +51,7 @@ struct Layout {
     bool comp;
     int64_t cap, rc;  // particle capacity, record capacity
     int64_t slab_stride;
-    size_t o_vt, o_flags, o_diag_out, o_diag_part, o_key_count, o_tile_flag, o_node_flag, o_node_list,
+    size_t o_vt, o_flags, o_vmax, o_diag_out, o_diag_part, o_key_count, o_tile_flag, o_node_flag, o_node_list,
         o_node_count, o_sums, o_slabs;
     MetaOff meta[2];
     size_t fixed_end;
@@ -93,6 +93,7 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     };
     L.o_vt = take(dim * G * e);
     L.o_flags = take(64);
+    L.o_vmax = take(64);
     L.o_diag_out = take(8 * sizeof(double));
     L.o_diag_part = take((size_t)kDiagBlocks * 8 * sizeof(double));
     L.o_key_count = take(G * 4);
@@ -334,6 +335,7 @@ View<T> make_view(const apic_scene *s, int64_t cap) {
     v.slabs.stride = L.slab_stride;
     v.g.vt = (T *)(w + L.o_vt);
     v.g.flags = (uint32_t *)(w + L.o_flags);
+    v.g.vmax = (uint32_t *)(w + L.o_vmax);
     v.g.d = L.d;
     v.g.dx = (T)s->grid.dx;
     v.g.inv_dx = (T)(1.0 / s->grid.dx);

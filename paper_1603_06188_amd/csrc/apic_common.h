@@ -78,6 +78,7 @@ template <typename T>
 struct GridState {
     T *vt;              // dim planes of G nodes: updated velocity
     uint32_t *flags;
+    uint32_t *vmax;     // binary32 bits of an upper bound of max_i |vt_i| (any component)
     GridDims d;
     T dx, inv_dx;
 };

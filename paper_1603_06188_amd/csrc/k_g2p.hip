@@ -111,22 +111,38 @@ __global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinMeta cur,
                                                         BinMeta nxt, BinScratch sc) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < P.n;
+    // Largest displacement this step in cell units, with a margin for
+    // rounding: |v_p| <= max_i |vt_i| since the weights are a partition of
+    // unity.  A particle farther than that from every boundary where its
+    // base node changes (offset 1/2 for quadratic, offset 0 or 1 for cubic)
+    // keeps its key; only the others need the gather.
+    const float vbound = __uint_as_float(*g.vmax);
+    const T reach = (T)vbound * prm.dt * g.inv_dx * T(1.0001) + T(1e-6);
     uint32_t key = kDeadKey;
     if (active && !is_dead(p, cur)) {
         int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
         unpack_cell<DIM>(P.cell[p], ci);
         T off[DIM], w[DIM][DEG + 1], on[DIM], vn[DIM];
+        bool far = reach < T(0.5);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             off[a] = P.off[a * P.s + p];
-            base[a] = axis_w_fixed<T, DEG>(ci[a], off[a], w[a]);
+            const T dist = DEG == 2 ? (off[a] < T(0.5) ? T(0.5) - off[a] : off[a] - T(0.5))
+                                    : (off[a] < T(0.5) ? off[a] : T(1) - off[a]);
+            far = far && dist > reach;
         }
-        T vt[Geo<DIM, DEG>::NODES][DIM];
-        load_support<T, DIM, DEG>(base, g, vt);
-        bool cfl;
-        advect<T, DIM, DEG>(ci, off, vt, w, prm.dt * g.inv_dx, vn, cn, on, cfl);
         bool finite;
-        key = key_of<T, DIM, DEG>(cn, on, g.d, finite);
+        if (far) {
+            key = key_of<T, DIM, DEG>(ci, off, g.d, finite);
+        } else {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) base[a] = axis_w_fixed<T, DEG>(ci[a], off[a], w[a]);
+            T vt[Geo<DIM, DEG>::NODES][DIM];
+            load_support<T, DIM, DEG>(base, g, vt);
+            bool cfl;
+            advect<T, DIM, DEG>(ci, off, vt, w, prm.dt * g.inv_dx, vn, cn, on, cfl);
+            key = key_of<T, DIM, DEG>(cn, on, g.d, finite);
+        }
         if (key == kDeadKey) atomicOr(g.flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
     }
     const uint32_t rank = bin_take_slot(key, active, nxt, sc);

@@ -83,8 +83,25 @@ __global__ __launch_bounds__(256) void k_grid_update(BinMeta cur, BinScratch sc,
         const bool live = valid && mm[0] > T(0) && !sticky;
         const T inv_m = live ? T(1) / mm[0] : T(0);
         const int64_t node = (int64_t)tau * 64 + lane;
+        float vabs = 0.f;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) g.vt[a * G + node] = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : T(0);
+        for (int a = 0; a < DIM; ++a) {
+            const T vt = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : T(0);
+            g.vt[a * G + node] = vt;
+            // binary32 value not below |vt| (NaN propagates as the largest bits)
+            const T va = vt < T(0) ? -vt : vt;
+            float f = (float)va;
+            if ((T)f < va) f = __uint_as_float(__float_as_uint(f) + 1u);  // next binary32 up
+            vabs = (f > vabs || f != f) ? f : vabs;
+        }
+        // wave maximum of the bit patterns (non-negative floats order like integers)
+        uint32_t bits = __float_as_uint(vabs);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t other = __shfl_xor(bits, o, 64);
+            bits = other > bits ? other : bits;
+        }
+        if (lane == 0) atomicMax(g.vmax, bits);
     }
 }
 

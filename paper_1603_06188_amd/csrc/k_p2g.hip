@@ -248,6 +248,8 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinMeta cur, Slabs<T> s
     const int lane = lane_id();
     int lcoord[3] = {0, 0, 0};
     local_coords<DIM>(lane, lcoord);
+    // the grid update that follows raises this bound of max |vt|
+    if (blockIdx.x == 0 && threadIdx.x == 0) *g.vmax = 0u;
     const uint32_t nrec = cur.count[0];
     for (uint32_t rec = blockIdx.x * 4 + (threadIdx.x >> 6); rec < nrec; rec += gridDim.x * 4) {
         const uint32_t t = cur.tile[rec];
