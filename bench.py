@@ -82,6 +82,9 @@ def main(argv=None):
     ap.add_argument("--cells", type=int, default=128)
     ap.add_argument("--plain", action="store_true", help="uncompensated binary32 accumulation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy three times (known bytes, for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -97,6 +100,13 @@ def main(argv=None):
     from paper_1603_06188_amd import scenes
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     scene = scenes.cube3d(cells=args.cells)
     compensated = not args.plain
     ds = b.DeviceScene(scene, compensated=compensated)

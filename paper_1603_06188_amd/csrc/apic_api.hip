@@ -41,21 +41,23 @@ int slab_nodes(int dim, int degree) {
 // ---------------------------------------------------------------------------
 // Workspace layout for a grid and a particle capacity `cap`.
 // ---------------------------------------------------------------------------
-struct MetaOff {
-    size_t count, tile, base, maxc, kcount, kprefix, map;
+struct ListOff {
+    size_t tile_gen, slot, rec_count, rec_list, tot, dead, node_gen, node_count, node_list;
 };
 
 struct Layout {
     GridDims d;
     size_t elem;
     bool comp;
-    int64_t cap, rc;  // particle capacity, record capacity
+    int64_t cap;    // particle capacity
+    int64_t rc;     // record (slab) capacity: min(tiles, cap)
+    int64_t rcap;   // list capacity per bucket: ceil(tiles / kBuckets)
     int64_t slab_stride;
-    size_t o_vt, o_flags, o_vmax, o_diag_out, o_diag_part, o_key_count, o_tile_flag, o_node_flag, o_node_list,
-        o_node_count, o_sums, o_slabs;
-    MetaOff meta[2];
+    size_t o_vt, o_flags, o_vmax, o_diag_out, o_diag_part, o_key_count;
+    ListOff lists[2];
+    size_t o_kcount, o_kprefix, o_maxc, o_off, o_lvl_off, o_lvl_mask, o_slabs;
     size_t fixed_end;
-    size_t o_pkey, o_prank, o_perm, o_sh_cell, o_sh_id, o_sh_f;
+    size_t o_pkey, o_prank, o_sh_cell, o_sh_id, o_sh_f;
     size_t total;
 };
 
@@ -82,8 +84,9 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.comp = (g->options & APIC_OPT_COMPENSATED) != 0;
     L.cap = cap < 1 ? 1 : cap;
     L.rc = L.d.tiles < L.cap ? L.d.tiles : L.cap;
+    L.rcap = (L.d.tiles + kBuckets - 1) / kBuckets;
     const size_t TT = (size_t)L.d.tiles, G = (size_t)L.d.G, dim = (size_t)g->dim, e = L.elem;
-    const size_t RC = (size_t)L.rc, cp = (size_t)L.cap;
+    const size_t RC = (size_t)L.rc, cp = (size_t)L.cap, LB = (size_t)kBuckets * (size_t)L.rcap;
     L.slab_stride = (int64_t)((1 + dim) * slab_nodes(g->dim, g->degree) * (L.comp ? 2 : 1));
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -93,29 +96,32 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     };
     L.o_vt = take(dim * G * e);
     L.o_flags = take(64);
-    L.o_vmax = take(64);
+    L.o_vmax = take((size_t)kVmaxSlots * 4);
     L.o_diag_out = take(8 * sizeof(double));
     L.o_diag_part = take((size_t)kDiagBlocks * 8 * sizeof(double));
     L.o_key_count = take(G * 4);
-    L.o_tile_flag = take(TT * 4);
-    L.o_node_flag = take(TT * 4);
-    L.o_node_list = take(TT * 4);
-    L.o_node_count = take(16);
     for (int k = 0; k < 2; ++k) {
-        L.meta[k].count = take(16);
-        L.meta[k].tile = take(RC * 4);
-        L.meta[k].base = take((RC + 1) * 4);
-        L.meta[k].maxc = take(RC * 4);
-        L.meta[k].kcount = take(RC * 64 * 4);
-        L.meta[k].kprefix = take(RC * 64 * 4);
-        L.meta[k].map = take(TT * 4);
+        ListOff &l = L.lists[k];
+        l.tile_gen = take(TT * 4);
+        l.slot = take(TT * 4);
+        l.rec_count = take((size_t)kBuckets * 4);
+        l.rec_list = take(LB * 4);
+        l.tot = take((size_t)kBuckets * 4);
+        l.dead = take(4);
+        l.node_gen = take(TT * 4);
+        l.node_count = take((size_t)kBuckets * 4);
+        l.node_list = take(LB * 4);
     }
-    L.o_sums = take(((RC + 2 + 1023) / 1024 + 2) * 4);
+    L.o_kcount = take(TT * 64 * 4);
+    L.o_kprefix = take(TT * 64 * 4);
+    L.o_maxc = take(TT * 4);
+    L.o_off = take(TT * 4);
+    L.o_lvl_off = take(TT * (size_t)kMaxLevels * 4);
+    L.o_lvl_mask = take(TT * (size_t)kMaxLevels * 8);
     L.o_slabs = take(RC * (size_t)L.slab_stride * e);
     L.fixed_end = o;
     L.o_pkey = take(cp * 4);
     L.o_prank = take(cp * 4);
-    L.o_perm = take(cp * 4);
     L.o_sh_cell = take(cp * 4);
     L.o_sh_id = take(cp * 4);
     L.o_sh_f = take((2 * dim + 2 * dim * dim + 1) * cp * e);
@@ -204,11 +210,11 @@ apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
 struct SceneState {
     apic_grid_desc grid;
     size_t wbytes = 0;
-    bool binned = false;     // the user's particle buffers follow meta[cur]
-    int cur = 0;             // layout of the particles
+    bool binned = false;     // the user's particle buffers follow layout `cur`
+    int cur = 0;             // layout (list parity) of the particles
     int grid_meta = -1;      // layout the slabs (last apic_p2g) belong to
-    int node_meta = -1;      // layout the node list was built for
-    bool vt_valid = false;   // grid velocities from meta[grid_meta] are current
+    bool vt_valid = false;   // grid velocities of layout grid_meta are current
+    uint32_t gen[2] = {0u, 0u};  // generation of the last build per parity
     int64_t n = -1;
     void *cell = nullptr;
     int64_t stride = 0;
@@ -277,17 +283,17 @@ template <typename T>
 struct View {
     Layout L;
     Parts<T> user, shadow;
-    BinMeta meta[2];
+    BinLists lists[2];
+    TileTables tab;
     BinScratch sc;
     Slabs<T> slabs;
     GridState<T> g;
     StepParams<T> prm;
-    Bounds b;
     double *diag_part, *diag_out;
 };
 
 template <typename T>
-View<T> make_view(const apic_scene *s, int64_t cap) {
+View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     View<T> v;
     v.L = make_layout(&s->grid, cap);
     const Layout &L = v.L;
@@ -313,24 +319,29 @@ View<T> make_view(const apic_scene *s, int64_t cap) {
     v.shadow.n = s->p.n;
     v.shadow.s = cp;
     for (int k = 0; k < 2; ++k) {
-        const MetaOff &o = L.meta[k];
-        v.meta[k].count = (uint32_t *)(w + o.count);
-        v.meta[k].tile = (uint32_t *)(w + o.tile);
-        v.meta[k].base = (uint32_t *)(w + o.base);
-        v.meta[k].maxc = (uint32_t *)(w + o.maxc);
-        v.meta[k].kcount = (uint32_t *)(w + o.kcount);
-        v.meta[k].kprefix = (uint32_t *)(w + o.kprefix);
-        v.meta[k].map = (int32_t *)(w + o.map);
+        const ListOff &o = L.lists[k];
+        BinLists &b = v.lists[k];
+        b.gen = ss.gen[k];
+        b.tile_gen = (uint32_t *)(w + o.tile_gen);
+        b.slot = (uint32_t *)(w + o.slot);
+        b.rec_count = (uint32_t *)(w + o.rec_count);
+        b.rec_list = (uint32_t *)(w + o.rec_list);
+        b.tot = (uint32_t *)(w + o.tot);
+        b.dead = (uint32_t *)(w + o.dead);
+        b.node_gen = (uint32_t *)(w + o.node_gen);
+        b.node_count = (uint32_t *)(w + o.node_count);
+        b.node_list = (uint32_t *)(w + o.node_list);
+        b.rcap = L.rcap;
     }
+    v.tab.kcount = (uint32_t *)(w + L.o_kcount);
+    v.tab.kprefix = (uint32_t *)(w + L.o_kprefix);
+    v.tab.maxc = (uint32_t *)(w + L.o_maxc);
+    v.tab.off = (uint32_t *)(w + L.o_off);
+    v.tab.lvl_off = (uint32_t *)(w + L.o_lvl_off);
+    v.tab.lvl_mask = (uint64_t *)(w + L.o_lvl_mask);
     v.sc.key_count = (uint32_t *)(w + L.o_key_count);
-    v.sc.tile_flag = (uint32_t *)(w + L.o_tile_flag);
-    v.sc.node_flag = (uint32_t *)(w + L.o_node_flag);
-    v.sc.node_list = (uint32_t *)(w + L.o_node_list);
-    v.sc.node_count = (uint32_t *)(w + L.o_node_count);
     v.sc.pkey = (uint32_t *)(w + L.o_pkey);
     v.sc.prank = (uint32_t *)(w + L.o_prank);
-    v.sc.perm = (uint32_t *)(w + L.o_perm);
-    v.sc.sums = (uint32_t *)(w + L.o_sums);
     v.slabs.v = (T *)(w + L.o_slabs);
     v.slabs.stride = L.slab_stride;
     v.g.vt = (T *)(w + L.o_vt);
@@ -346,20 +357,28 @@ View<T> make_view(const apic_scene *s, int64_t cap) {
     v.prm.mu = (T)s->prm.mu;
     v.prm.lam = (T)s->prm.lambda;
     v.prm.inv_rho0 = s->prm.rho0 > 0.0 ? (T)(1.0 / s->prm.rho0) : T(0);
-    v.b.max_records = L.rc;
-    v.b.tiles = L.d.tiles;
     v.diag_part = (double *)(w + L.o_diag_part);
     v.diag_out = (double *)(w + L.o_diag_out);
     return v;
 }
 
-// Device part of a reset: zero the fixed region, then mark every tile map
-// entry unlisted.
+// Next generation of list parity `k` before a layout is built in it.  On
+// wrap-around the parity's tags are cleared so no stale tag can match.
+template <typename T>
+void begin_build(View<T> &v, SceneState &ss, int k, hipStream_t st) {
+    if (ss.gen[k] == 0xFFFFFFFFu) {
+        launch_fill<uint32_t>(v.lists[k].tile_gen, v.L.d.tiles, 0u, st);
+        launch_fill<uint32_t>(v.lists[k].node_gen, v.L.d.tiles, 0u, st);
+        ss.gen[k] = 0u;
+    }
+    ss.gen[k] += 1u;
+    v.lists[k].gen = ss.gen[k];
+}
+
+// Device part of a reset: zero the fixed region (counters, tags, tables).
 void device_reset(const apic_scene *s, int64_t cap, hipStream_t st) {
     const Layout L = make_layout(&s->grid, cap);
     launch_fill<uint32_t>((uint32_t *)s->workspace, (int64_t)(L.fixed_end / 4), 0u, st);
-    for (int k = 0; k < 2; ++k)
-        launch_fill<int32_t>((int32_t *)((char *)s->workspace + L.meta[k].map), L.d.tiles, -1, st);
 }
 
 // Registry entry of the scene, created (and the workspace reset) on first
@@ -396,41 +415,46 @@ struct OpArgs {
     int which;
 };
 
-// Bins the particles of `src` (at their current positions) into meta[nxt]
-// and writes them, in the new order, to `dst`.
+// Bins the particles of `src` (at their current positions) into list
+// parity `nxt` and writes them, in the new order, to `dst`.
 template <typename T, int DIM, int DEG>
-void bin_static(View<T> &v, const Parts<T> &src, const Parts<T> &dst, int nxt, hipStream_t st) {
-    launch_bin_begin(v.meta[nxt], v.sc, v.b, st);
-    launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.meta[nxt], v.sc, v.g.flags, st);
-    launch_bin_finish<DIM>(v.L.d, v.meta[nxt], v.sc, v.b, st);
-    launch_bin_scatter_copy<T, DIM>(src, dst, v.meta[nxt], v.sc, st);
+void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &dst, int nxt, hipStream_t st) {
+    begin_build(v, ss, nxt, st);
+    launch_bin_reset(v.lists[nxt], st);
+    launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, st);
+    launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab, v.sc, v.L.rc, st);
+    launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab, v.sc, st);
 }
 
-// One G2P from `src` (layout meta[cur]) into `dst` (layout meta[1-cur]).
+// One G2P from `src` (layout `cur`) into `dst` (layout 1 - cur).  The
+// counters of the new layout were zeroed by the preceding P2G; `reset`
+// zeroes them again (calls outside a whole step).
 template <typename T, int DIM, int DEG>
-void g2p_rebin(View<T> &v, const Parts<T> &src, const Parts<T> &dst, int cur, hipStream_t st) {
+void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &dst, int cur, bool reset,
+               hipStream_t st) {
     const int nxt = 1 - cur;
+    begin_build(v, ss, nxt, st);
     timed(APIC_PHASE_BIN, st, [&] {
-        launch_bin_begin(v.meta[nxt], v.sc, v.b, st);
-        launch_bin_keys_moved<T, DIM, DEG>(src, v.meta[cur], v.g, v.prm, v.meta[nxt], v.sc, st);
-        launch_bin_finish<DIM>(v.L.d, v.meta[nxt], v.sc, v.b, st);
+        if (reset) launch_bin_reset(v.lists[nxt], st);
+        launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.g, v.prm, v.lists[nxt], v.sc, st);
+        launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab, v.sc, v.L.rc, st);
     });
-    timed(APIC_PHASE_G2P, st,
-          [&] { launch_g2p<T, DIM, DEG>(src, dst, v.meta[cur], v.meta[nxt], v.sc, v.g, v.prm, st); });
+    timed(APIC_PHASE_G2P, st, [&] {
+        launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.lists[nxt], v.tab, v.sc, v.g, v.prm, st);
+    });
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
 apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
-    View<T> v = make_view<T>(s, cap);
     SceneState &ss = state_of(s, cap, st);
+    View<T> v = make_view<T>(s, cap, ss);
     switch (op) {
         case Op::Sort: {
             const int nxt = 1 - ss.cur;
-            bin_static<T, DIM, DEG>(v, v.user, v.shadow, nxt, st);
+            bin_static<T, DIM, DEG>(v, ss, v.user, v.shadow, nxt, st);
             launch_copy_state<T, DIM>(v.shadow, v.user, st);
             ss.cur = nxt;
             ss.binned = true;
-            ss.node_meta = nxt;
             if (ss.grid_meta == nxt) ss.grid_meta = -1;
             ss.vt_valid = false;
             break;
@@ -439,37 +463,38 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
             if (!ss.binned) {
                 apic_status rc = run<T, DIM, DEG, COMP>(Op::Sort, s, cap, st, a);
                 if (rc != APIC_OK) return rc;
+                v = make_view<T>(s, cap, ss);
             }
-            launch_p2g<T, DIM, DEG, COMP>(v.user, v.meta[ss.cur], v.slabs, v.g, v.prm, v.b, st);
+            launch_p2g<T, DIM, DEG, COMP>(v.user, v.lists[ss.cur], v.lists[1 - ss.cur], v.tab, v.slabs, v.g, v.prm,
+                                          v.L.rc, st);
             ss.grid_meta = ss.cur;
             ss.vt_valid = false;
             break;
         }
         case Op::GridUpdate:
-            if (ss.grid_meta < 0 || ss.node_meta != ss.grid_meta)
+            if (ss.grid_meta < 0 || ss.grid_meta != ss.cur || !ss.binned)
                 return fail(APIC_E_INVAL, "apic_grid_update needs a preceding apic_p2g on the current particles");
-            launch_grid_update<T, DIM, DEG, COMP>(v.meta[ss.grid_meta], v.sc, v.slabs, v.g, v.prm, v.b, st);
+            launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.grid_meta], v.slabs, v.g, v.prm, v.L.d.tiles, st);
             ss.vt_valid = true;
             break;
         case Op::G2P:
             if (!ss.vt_valid || !ss.binned || ss.grid_meta != ss.cur)
                 return fail(APIC_E_INVAL, "apic_g2p needs apic_p2g and apic_grid_update on the current particles");
-            g2p_rebin<T, DIM, DEG>(v, v.user, v.shadow, ss.cur, st);
+            g2p_rebin<T, DIM, DEG>(v, ss, v.user, v.shadow, ss.cur, true, st);
             launch_copy_state<T, DIM>(v.shadow, v.user, st);
             ss.cur = 1 - ss.cur;
-            ss.node_meta = ss.cur;
             ss.vt_valid = false;
             break;
         case Op::Export:
             if (ss.grid_meta < 0) return fail(APIC_E_INVAL, "no grid yet: call apic_p2g first");
-            launch_grid_export<T, DIM, DEG, COMP>(v.meta[ss.grid_meta], v.slabs, v.g, a.which, (T *)a.ptr, st);
+            launch_grid_export<T, DIM, DEG, COMP>(v.lists[ss.grid_meta], v.slabs, v.g, a.which, (T *)a.ptr, st);
             break;
         case Op::DiagParticles:
             launch_diag_particles<T, DIM>(v.user, s->grid.dx, v.diag_part, v.diag_out, st);
             break;
         case Op::DiagGrid:
             if (ss.grid_meta < 0) return fail(APIC_E_INVAL, "no grid yet: call apic_p2g first");
-            launch_diag_grid<T, DIM, DEG, COMP>(v.meta[ss.grid_meta], v.slabs, v.g, a.which, s->prm.dt, v.diag_part,
+            launch_diag_grid<T, DIM, DEG, COMP>(v.lists[ss.grid_meta], v.slabs, v.g, a.which, s->prm.dt, v.diag_part,
                                                 v.diag_out, st);
             break;
         case Op::Pack:
@@ -489,36 +514,36 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
 // caller's buffers and the workspace shadow; ends in the caller's buffers.
 template <typename T, int DIM, int DEG, bool COMP>
 apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_every, hipStream_t st) {
-    View<T> v = make_view<T>(s, cap);
     SceneState &ss = state_of(s, cap, st);
+    View<T> v = make_view<T>(s, cap, ss);
     Parts<T> bufs[2] = {v.user, v.shadow};
     int where = 0;
     if (!ss.binned) {
-        timed(APIC_PHASE_SORT, st, [&] { bin_static<T, DIM, DEG>(v, v.user, v.shadow, 1 - ss.cur, st); });
+        timed(APIC_PHASE_SORT, st, [&] { bin_static<T, DIM, DEG>(v, ss, v.user, v.shadow, 1 - ss.cur, st); });
         ss.cur = 1 - ss.cur;
         where = 1;
     }
     for (int32_t k = 0; k < n_steps; ++k) {
         if (sort_every > 0 && k > 0 && k % sort_every == 0) {
             timed(APIC_PHASE_SORT, st,
-                  [&] { bin_static<T, DIM, DEG>(v, bufs[where], bufs[1 - where], 1 - ss.cur, st); });
+                  [&] { bin_static<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], 1 - ss.cur, st); });
             ss.cur = 1 - ss.cur;
             where = 1 - where;
         }
         timed(APIC_PHASE_P2G, st, [&] {
-            launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.meta[ss.cur], v.slabs, v.g, v.prm, v.b, st);
+            launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab, v.slabs, v.g,
+                                          v.prm, v.L.rc, st);
         });
         timed(APIC_PHASE_GRID_UPDATE, st, [&] {
-            launch_grid_update<T, DIM, DEG, COMP>(v.meta[ss.cur], v.sc, v.slabs, v.g, v.prm, v.b, st);
+            launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.cur], v.slabs, v.g, v.prm, v.L.d.tiles, st);
         });
         ss.grid_meta = ss.cur;
-        g2p_rebin<T, DIM, DEG>(v, bufs[where], bufs[1 - where], ss.cur, st);
+        g2p_rebin<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], ss.cur, false, st);
         ss.cur = 1 - ss.cur;
         where = 1 - where;
     }
     if (where == 1) launch_copy_state<T, DIM>(v.shadow, v.user, st);
     ss.binned = true;
-    ss.node_meta = ss.cur;
     ss.vt_valid = false;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(APIC_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));

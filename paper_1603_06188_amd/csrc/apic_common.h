@@ -15,17 +15,30 @@
 //   listed tile are contiguous and stored level by level: level j holds the
 //   j-th particle of every key of the tile that has more than j particles, in
 //   key order, so the wavefront that owns the tile reads each level with
-//   one coalesced load per field.  Particles that cannot be binned (support
-//   outside the grid, non-finite state) follow all tiles ("dead" region).
+//   one coalesced load per field (a tile whose busiest key holds more than
+//   kMaxLevels particles is stored key by key instead).  Particles that
+//   cannot be binned (support outside the grid, non-finite state) follow all
+//   tiles ("dead" region).
+//   Lists.  Listed tiles and the node tiles the grid update visits are kept
+//   in kBuckets append lists (bucket = tile id mod kBuckets) so appends do
+//   not contend on one counter; membership is a generation tag per tile, so
+//   nothing needs clearing between steps.  A tile's particles start at
+//   bucket_base[bucket] + off[tile], bucket_base being the exclusive prefix
+//   of the per-bucket particle totals.
 //   Slabs.  P2G writes, per listed tile, the mass and momentum of the
-//   (4+K-1)^3 nodes its keys touch (K = kernel support width); the grid update
-//   sums the at most 8 slabs that cover a node.  No float atomics anywhere.
+//   (4+K-1)^3 nodes its keys touch (K = kernel support width) to the slab of
+//   the tile's record index; the grid update sums the at most 8 slabs that
+//   cover a node.  No float atomics anywhere.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace apic {
+
+constexpr int kBuckets = 64;
+constexpr int kMaxLevels = 32;
+constexpr int kVmaxSlots = 64;
 
 struct GridDims {
     int dim, deg;
@@ -44,33 +57,43 @@ struct Parts {
     int64_t n, s;  // count, plane stride
 };
 
-// One binned layout of the particles (double-buffered in the workspace).
-struct BinMeta {
-    uint32_t *count;    // [1] listed tiles;  count[1] = dead particles
-    uint32_t *tile;     // [cap] tile id of each record
-    uint32_t *base;     // [cap + 1] first particle of each record; base[count] = first dead particle
-    uint32_t *maxc;     // [cap] largest per-key count of the record
-    uint32_t *kcount;   // [cap * 64] particles per key
-    uint32_t *kprefix;  // [cap * 64] exclusive prefix of kcount within the record
-    int32_t *map;       // [tiles] tile id -> record, -1 if not listed
+// Lists of one binned layout (double-buffered: the layout being read and the
+// one being built).
+struct BinLists {
+    uint32_t gen;          // generation tag of this layout
+    uint32_t *tile_gen;    // [tiles] == gen: tile listed
+    uint32_t *slot;        // [tiles] record index of a listed tile (its slab)
+    uint32_t *rec_count;   // [kBuckets] listed tiles per bucket
+    uint32_t *rec_list;    // [kBuckets * rcap] tile ids, bucket b from b * rcap
+    uint32_t *tot;         // [kBuckets] particles per bucket
+    uint32_t *dead;        // [1] dead particles
+    uint32_t *node_gen;    // [tiles] == gen: node tile listed for the grid update
+    uint32_t *node_count;  // [kBuckets]
+    uint32_t *node_list;   // [kBuckets * rcap] node tile ids, bucket b from b * rcap
+    int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
 };
 
-// Scratch of the binning passes (single-buffered; invariants noted).
+// Per-tile tables of the most recently built layout (dense, indexed by tile
+// id; entries of tiles not listed are stale and never read).
+struct TileTables {
+    uint32_t *kcount;      // [tiles * 64] particles per key
+    uint32_t *kprefix;     // [tiles * 64] exclusive prefix of kcount in the tile
+    uint32_t *maxc;        // [tiles] largest per-key count
+    uint32_t *off;         // [tiles] first particle relative to the bucket base
+    uint32_t *lvl_off;     // [tiles * kMaxLevels] first particle of level j in the tile
+    uint64_t *lvl_mask;    // [tiles * kMaxLevels] keys present in level j
+};
+
+// Scratch of the binning passes.
 struct BinScratch {
-    uint32_t *key_count;  // [G]      per-key counters, all zero between passes
-    uint32_t *tile_flag;  // [tiles]  all zero between passes
-    uint32_t *node_flag;  // [tiles]  all zero between passes
-    uint32_t *node_list;  // [tiles]  node tiles the next grid update visits
-    uint32_t *node_count; // [1]
-    uint32_t *pkey;       // [cap]    new key of each particle (0xFFFFFFFF: dead)
-    uint32_t *prank;      // [cap]    rank of the particle within its key
-    uint32_t *perm;       // [cap]    key-major position -> level-major position
-    uint32_t *sums;       // scan scratch
+    uint32_t *key_count;  // [G]   per-key counters, zero between passes
+    uint32_t *pkey;       // [cap] new key of each particle (kDeadKey: dead)
+    uint32_t *prank;      // [cap] rank of the particle within its key
 };
 
 template <typename T>
 struct Slabs {
-    T *v;               // [cap][NC * RN] (+ error terms when compensated)
+    T *v;               // [records][NC * RN] (+ error terms when compensated)
     int64_t stride;     // elements per record
 };
 
@@ -78,7 +101,7 @@ template <typename T>
 struct GridState {
     T *vt;              // dim planes of G nodes: updated velocity
     uint32_t *flags;
-    uint32_t *vmax;     // binary32 bits of an upper bound of max_i |vt_i| (any component)
+    uint32_t *vmax;     // [kVmaxSlots] binary32 bits; their max bounds max_i |vt_i|
     GridDims d;
     T dx, inv_dx;
 };

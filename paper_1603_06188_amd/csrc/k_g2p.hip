@@ -102,24 +102,29 @@ __device__ __forceinline__ void advect(const int *ci, const T *off, const T (&vt
     }
 }
 
-// A particle index at or beyond the first dead particle of `cur` is dead.
-__device__ __forceinline__ bool is_dead(int64_t p, const BinMeta &cur) { return p >= (int64_t)cur.base[cur.count[0]]; }
+// Bound of max_i |vt_i| over the slots the grid update raised (wave-wide).
+__device__ __forceinline__ float wave_vmax(const uint32_t *slots) {
+    return __uint_as_float(wave_max_u32(slots[lane_id() & (kVmaxSlots - 1)]));
+}
 
-// --- pass 1: keys at the advected positions ---------------------------------------
+// --- pass 1: keys at the advected positions -----------------------------------------
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinMeta cur, GridState<T> g, StepParams<T> prm,
-                                                        BinMeta nxt, BinScratch sc) {
+__global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinLists cur, GridState<T> g, StepParams<T> prm,
+                                                        BinLists nxt, BinScratch sc) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < P.n;
+    // particles at or beyond the live total of the current layout are dead
+    uint32_t live_cur, unused;
+    (void)wave_bucket_prefix(cur.tot, live_cur, unused);
     // Largest displacement this step in cell units, with a margin for
     // rounding: |v_p| <= max_i |vt_i| since the weights are a partition of
     // unity.  A particle farther than that from every boundary where its
     // base node changes (offset 1/2 for quadratic, offset 0 or 1 for cubic)
     // keeps its key; only the others need the gather.
-    const float vbound = __uint_as_float(*g.vmax);
+    const float vbound = wave_vmax(g.vmax);
     const T reach = (T)vbound * prm.dt * g.inv_dx * T(1.0001) + T(1e-6);
     uint32_t key = kDeadKey;
-    if (active && !is_dead(p, cur)) {
+    if (active && p < (int64_t)live_cur) {
         int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
         unpack_cell<DIM>(P.cell[p], ci);
         T off[DIM], w[DIM][DEG + 1], on[DIM], vn[DIM];
@@ -146,31 +151,38 @@ __global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinMeta cur,
         if (key == kDeadKey) atomicOr(g.flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
     }
     const uint32_t rank = bin_take_slot(key, active, nxt, sc);
-    if (!active) return;
-    sc.pkey[p] = key;
-    sc.prank[p] = rank;
+    if (active) {
+        sc.pkey[p] = key;
+        sc.prank[p] = rank;
+    }
 }
 
 template <typename T, int DIM, int DEG>
-void launch_bin_keys_moved(const Parts<T> &P, const BinMeta &cur, const GridState<T> &g, const StepParams<T> &prm,
-                           const BinMeta &nxt, const BinScratch &sc, hipStream_t st) {
+void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const GridState<T> &g, const StepParams<T> &prm,
+                           const BinLists &nxt, const BinScratch &sc, hipStream_t st) {
     if (P.n == 0) return;
     hipLaunchKernelGGL((k_bin_keys_moved<T, DIM, DEG>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P,
                        cur, g, prm, nxt, sc);
 }
 
-// --- pass 2: the transfer, written to the new layout --------------------------------
+// --- pass 2: the transfer, written to the new layout ----------------------------------
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) void k_g2p(Parts<T> src, Parts<T> dst, BinMeta cur, BinMeta nxt, BinScratch sc,
-                                             GridState<T> g, StepParams<T> prm) {
+__global__ __launch_bounds__(256) void k_g2p(Parts<T> src, Parts<T> dst, BinLists cur, BinLists nxt, TileTables tab,
+                                             BinScratch sc, GridState<T> g, StepParams<T> prm) {
     constexpr int K = DEG + 1;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= src.n) return;
-    const int64_t q = bin_destination(sc.pkey[p], sc.prank[p], nxt, sc);
+    const bool active = p < src.n;
+    uint32_t live_cur, live_nxt, unused;
+    (void)wave_bucket_prefix(cur.tot, live_cur, unused);
+    const uint32_t bbase = wave_bucket_prefix(nxt.tot, live_nxt, unused);
+    const uint32_t key = active ? sc.pkey[p] : kDeadKey;
+    const uint32_t rank = active ? sc.prank[p] : 0u;
+    const int64_t q = bin_destination(key, rank, tab, bbase, live_nxt);
+    if (!active) return;
     const int64_t ss = src.s, ds = dst.s;
     dst.m[q] = src.m[p];
     if (src.id) dst.id[q] = src.id[p];
-    if (is_dead(p, cur)) {
+    if (p >= (int64_t)live_cur) {
         dst.cell[q] = src.cell[p];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -207,67 +219,77 @@ __global__ __launch_bounds__(256) void k_g2p(Parts<T> src, Parts<T> dst, BinMeta
     T Bc[DIM * DIM], Gc[DIM * DIM];
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) Bc[k] = Gc[k] = T(0);
+    // Axis-pair grouping: with Tx_k(a) = sum_{b,c} wy wz vt, Ty_k(b) =
+    // sum_{a,c} wx wz vt, Tz_k(c) = sum_{a,b} wx wy vt (three multiply-adds
+    // per node and component),
+    //   B_k0 = sum_a wx rx Tx_k(a),  grad v_k0 = sum_a dx Tx_k(a), and the
+    // same along y with Ty and along z with Tz.
     if constexpr (DIM == 3) {
+        T Pyz[K][K], Qxz[K][K], Rxy[K][K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            T P1[3] = {0, 0, 0}, P2[3] = {0, 0, 0}, P3[3] = {0, 0, 0}, P4[3] = {0, 0, 0}, P5[3] = {0, 0, 0};
+        for (int i = 0; i < K; ++i)
 #pragma unroll
-            for (int b = 0; b < K; ++b) {
-                T S[3] = {0, 0, 0}, Tz[3] = {0, 0, 0}, U[3] = {0, 0, 0};
+            for (int j = 0; j < K; ++j) {
+                Pyz[i][j] = ax[1].w[i] * ax[2].w[j];
+                Qxz[i][j] = ax[0].w[i] * ax[2].w[j];
+                Rxy[i][j] = ax[0].w[i] * ax[1].w[j];
+            }
+        T Tx[3][K], Ty[3][K], Tz[3][K];
 #pragma unroll
-                for (int c = 0; c < K; ++c) {
-                    const T wz = ax[2].w[c], wrz = ax[2].w[c] * ax[2].r[c], dz = ax[2].dw[c];
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < K; ++i) Tx[k][i] = Ty[k][i] = Tz[k][i] = T(0);
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+#pragma unroll
+            for (int b = 0; b < K; ++b)
+#pragma unroll
+                for (int a = 0; a < K; ++a)
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         const T x = vt[a + K * (b + K * c)][k];
-                        S[k] += wz * x;
-                        Tz[k] += wrz * x;
-                        U[k] += dz * x;
+                        Tx[k][a] += Pyz[b][c] * x;
+                        Ty[k][b] += Qxz[a][c] * x;
+                        Tz[k][c] += Rxy[a][b] * x;
                     }
-                }
-                const T wy = ax[1].w[b], wry = ax[1].w[b] * ax[1].r[b], dy = ax[1].dw[b];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    P1[k] += wy * S[k];
-                    P2[k] += wry * S[k];
-                    P3[k] += dy * S[k];
-                    P4[k] += wy * Tz[k];
-                    P5[k] += wy * U[k];
-                }
-            }
-            const T wx = ax[0].w[a], wrx = ax[0].w[a] * ax[0].r[a], dx = ax[0].dw[a];
+        for (int i = 0; i < K; ++i) {
+            const T wrx = ax[0].w[i] * ax[0].r[i], wry = ax[1].w[i] * ax[1].r[i], wrz = ax[2].w[i] * ax[2].r[i];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                Bc[k * 3 + 0] += wrx * P1[k];
-                Gc[k * 3 + 0] += dx * P1[k];
-                Bc[k * 3 + 1] += wx * P2[k];
-                Gc[k * 3 + 1] += wx * P3[k];
-                Bc[k * 3 + 2] += wx * P4[k];
-                Gc[k * 3 + 2] += wx * P5[k];
+                Bc[k * 3 + 0] += wrx * Tx[k][i];
+                Gc[k * 3 + 0] += ax[0].dw[i] * Tx[k][i];
+                Bc[k * 3 + 1] += wry * Ty[k][i];
+                Gc[k * 3 + 1] += ax[1].dw[i] * Ty[k][i];
+                Bc[k * 3 + 2] += wrz * Tz[k][i];
+                Gc[k * 3 + 2] += ax[2].dw[i] * Tz[k][i];
             }
         }
     } else {
+        T Tx[2][K], Ty[2][K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            T P1[2] = {0, 0}, P2[2] = {0, 0}, P3[2] = {0, 0};
+        for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int b = 0; b < K; ++b) {
-                const T wy = ax[1].w[b], wry = ax[1].w[b] * ax[1].r[b], dy = ax[1].dw[b];
+            for (int i = 0; i < K; ++i) Tx[k][i] = Ty[k][i] = T(0);
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+#pragma unroll
+            for (int a = 0; a < K; ++a)
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
                     const T x = vt[a + K * b][k];
-                    P1[k] += wy * x;
-                    P2[k] += wry * x;
-                    P3[k] += dy * x;
+                    Tx[k][a] += ax[1].w[b] * x;
+                    Ty[k][b] += ax[0].w[a] * x;
                 }
-            }
-            const T wx = ax[0].w[a], wrx = ax[0].w[a] * ax[0].r[a], dx = ax[0].dw[a];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const T wrx = ax[0].w[i] * ax[0].r[i], wry = ax[1].w[i] * ax[1].r[i];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                Bc[k * 2 + 0] += wrx * P1[k];
-                Gc[k * 2 + 0] += dx * P1[k];
-                Bc[k * 2 + 1] += wx * P2[k];
-                Gc[k * 2 + 1] += wx * P3[k];
+                Bc[k * 2 + 0] += wrx * Tx[k][i];
+                Gc[k * 2 + 0] += ax[0].dw[i] * Tx[k][i];
+                Bc[k * 2 + 1] += wry * Ty[k][i];
+                Gc[k * 2 + 1] += ax[1].dw[i] * Ty[k][i];
             }
         }
     }
@@ -301,22 +323,23 @@ __global__ __launch_bounds__(256) void k_g2p(Parts<T> src, Parts<T> dst, BinMeta
 }
 
 template <typename T, int DIM, int DEG>
-void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinMeta &cur, const BinMeta &nxt,
-                const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm, hipStream_t st) {
+void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const BinLists &nxt,
+                const TileTables &tab, const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm,
+                hipStream_t st) {
     if (src.n == 0) return;
     Parts<T> s2 = src, d2 = dst;
     if (!src.id || !dst.id) s2.id = d2.id = nullptr;
     hipLaunchKernelGGL((k_g2p<T, DIM, DEG>), dim3((unsigned)((src.n + 255) / 256)), dim3(256), 0, st, s2, d2, cur, nxt,
-                       sc, g, prm);
+                       tab, sc, g, prm);
 }
 
 #define APIC_G2P_INST(T, DIM, DEG)                                                                               \
-    template void launch_bin_keys_moved<T, DIM, DEG>(const Parts<T> &, const BinMeta &, const GridState<T> &,    \
-                                                     const StepParams<T> &, const BinMeta &, const BinScratch &,  \
+    template void launch_bin_keys_moved<T, DIM, DEG>(const Parts<T> &, const BinLists &, const GridState<T> &,   \
+                                                     const StepParams<T> &, const BinLists &, const BinScratch &, \
                                                      hipStream_t);                                               \
-    template void launch_g2p<T, DIM, DEG>(const Parts<T> &, const Parts<T> &, const BinMeta &, const BinMeta &,  \
-                                          const BinScratch &, const GridState<T> &, const StepParams<T> &,       \
-                                          hipStream_t);
+    template void launch_g2p<T, DIM, DEG>(const Parts<T> &, const Parts<T> &, const BinLists &, const BinLists &, \
+                                          const TileTables &, const BinScratch &, const GridState<T> &,          \
+                                          const StepParams<T> &, hipStream_t);
 APIC_G2P_INST(float, 2, 2)
 APIC_G2P_INST(float, 2, 3)
 APIC_G2P_INST(float, 3, 2)

@@ -2,6 +2,7 @@
 //
 // A node's mass and momentum are the sum of the slabs of the (at most
 // 2^DIM) listed key tiles whose slab covers it, visited in a fixed order.
+#include "apic_bin_device.h"
 #include "apic_kernels.h"
 
 namespace apic {
@@ -15,7 +16,7 @@ static inline int blocks_for(int64_t work, int threads, int cap) {
 
 // Mass and momentum of node `nc`: out[0] = m, out[1..DIM] = (m v) + dt f.
 template <typename T, int DIM, int DEG, bool COMP>
-__device__ __forceinline__ void gather_node(const int *nc, const BinMeta &gm, const Slabs<T> &slabs,
+__device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, const Slabs<T> &slabs,
                                             const GridDims &d, T *out) {
     using Gm = Geo<DIM, DEG>;
     constexpr int TE = Gm::TE, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC;
@@ -38,8 +39,9 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinMeta &gm, co
             t += (int64_t)d.TN[0] * (kt[1] + (int64_t)d.TN[1] * kt[2]);
         else
             t += (int64_t)d.TN[0] * kt[1];
-        const int32_t rec = gm.map[t];
-        if (rec < 0) continue;
+        // membership tag and record index are independent loads
+        const uint32_t tag = gm.tile_gen[t], rec = gm.slot[t];
+        if (tag != gm.gen) continue;
         const int idx = DIM == 3 ? loc[0] + RE * (loc[1] + RE * loc[2]) : loc[0] + RE * loc[1];
         const T *s = slabs.v + (int64_t)rec * slabs.stride;
 #pragma unroll
@@ -59,13 +61,18 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinMeta &gm, co
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_grid_update(BinMeta cur, BinScratch sc, Slabs<T> slabs, GridState<T> g,
+__global__ __launch_bounds__(256) void k_grid_update(BinLists cur, Slabs<T> slabs, GridState<T> g,
                                                      StepParams<T> prm) {
     const int lane = lane_id();
-    const uint32_t ntiles = sc.node_count[0];
     const int64_t G = g.d.G;
-    for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < ntiles; i += gridDim.x * 4) {
-        const uint32_t tau = sc.node_list[i];
+    uint32_t ntiles, ncnt;
+    const uint32_t npre = wave_bucket_prefix(cur.node_count, ntiles, ncnt);
+    uint32_t bits = 0u;  // wave maximum so far of the bounds below
+    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (uint32_t i = wave; i < ntiles; i += gridDim.x * 4) {
+        uint32_t b, j;
+        bucket_locate(i, npre, ncnt, b, j);
+        const uint32_t tau = cur.node_list[(int64_t)b * cur.rcap + j];
         int nc[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
         tile_origin<DIM>(tau, g.d.TN, nc);
         local_coords<DIM>(lane, lc);
@@ -94,27 +101,24 @@ __global__ __launch_bounds__(256) void k_grid_update(BinMeta cur, BinScratch sc,
             if ((T)f < va) f = __uint_as_float(__float_as_uint(f) + 1u);  // next binary32 up
             vabs = (f > vabs || f != f) ? f : vabs;
         }
-        // wave maximum of the bit patterns (non-negative floats order like integers)
-        uint32_t bits = __float_as_uint(vabs);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t other = __shfl_xor(bits, o, 64);
-            bits = other > bits ? other : bits;
-        }
-        if (lane == 0) atomicMax(g.vmax, bits);
+        // non-negative binary32 values order like their bit patterns
+        const uint32_t mine = __float_as_uint(vabs);
+        bits = mine > bits ? mine : bits;
     }
+    bits = wave_max_u32(bits);
+    if (lane == 0 && bits != 0u) atomicMax(g.vmax + (wave & (kVmaxSlots - 1)), bits);
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-void launch_grid_update(const BinMeta &cur, const BinScratch &sc, const Slabs<T> &slabs, const GridState<T> &g,
-                        const StepParams<T> &prm, const Bounds &b, hipStream_t st) {
-    const int blocks = blocks_for(b.tiles, 4, 8192);
-    hipLaunchKernelGGL((k_grid_update<T, DIM, DEG, COMP>), dim3(blocks), dim3(256), 0, st, cur, sc, slabs, g, prm);
+void launch_grid_update(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm,
+                        int64_t max_node_tiles, hipStream_t st) {
+    const int blocks = blocks_for(max_node_tiles, 4, 8192);
+    hipLaunchKernelGGL((k_grid_update<T, DIM, DEG, COMP>), dim3(blocks), dim3(256), 0, st, cur, slabs, g, prm);
 }
 
 // --- export: dense node-major copy of one field ------------------------------------
 template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_grid_export(BinMeta gm, Slabs<T> slabs, GridState<T> g, int field, T *out) {
+__global__ __launch_bounds__(256) void k_grid_export(BinLists gm, Slabs<T> slabs, GridState<T> g, int field, T *out) {
     int64_t count = 1;
     for (int a = 0; a < DIM; ++a) count *= g.d.N[a];
     const int64_t G = g.d.G;
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(256) void k_grid_export(BinMeta gm, Slabs<T> slabs,
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-void launch_grid_export(const BinMeta &gm, const Slabs<T> &slabs, const GridState<T> &g, int field, T *out,
+void launch_grid_export(const BinLists &gm, const Slabs<T> &slabs, const GridState<T> &g, int field, T *out,
                         hipStream_t st) {
     int64_t count = 1;
     for (int a = 0; a < DIM; ++a) count *= g.d.N[a];
@@ -166,7 +170,7 @@ __device__ __forceinline__ void block_reduce8(double *acc, double *partials) {
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_diag_grid(BinMeta gm, Slabs<T> slabs, GridState<T> g, int which, double dt,
+__global__ __launch_bounds__(256) void k_diag_grid(BinLists gm, Slabs<T> slabs, GridState<T> g, int which, double dt,
                                                    double *partials) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t count = 1;
@@ -221,7 +225,7 @@ __global__ void k_diag_final_grid(const double *partials, int nb, double *out) {
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-void launch_diag_grid(const BinMeta &gm, const Slabs<T> &slabs, const GridState<T> &g, int which, double dt,
+void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState<T> &g, int which, double dt,
                       double *partials, double *out, hipStream_t st) {
     int64_t count = 1;
     for (int a = 0; a < DIM; ++a) count *= g.d.N[a];
@@ -232,12 +236,11 @@ void launch_diag_grid(const BinMeta &gm, const Slabs<T> &slabs, const GridState<
 }
 
 #define APIC_GRID_INST(T, DIM, DEG, COMP)                                                                         \
-    template void launch_grid_update<T, DIM, DEG, COMP>(const BinMeta &, const BinScratch &, const Slabs<T> &,    \
-                                                        const GridState<T> &, const StepParams<T> &,             \
-                                                        const Bounds &, hipStream_t);                            \
-    template void launch_grid_export<T, DIM, DEG, COMP>(const BinMeta &, const Slabs<T> &, const GridState<T> &,  \
+    template void launch_grid_update<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &, \
+                                                        const StepParams<T> &, int64_t, hipStream_t);            \
+    template void launch_grid_export<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &, \
                                                         int, T *, hipStream_t);                                  \
-    template void launch_diag_grid<T, DIM, DEG, COMP>(const BinMeta &, const Slabs<T> &, const GridState<T> &,    \
+    template void launch_diag_grid<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &,   \
                                                       int, double, double *, double *, hipStream_t);
 #define APIC_GRID_INST2(T, DIM, DEG) APIC_GRID_INST(T, DIM, DEG, false) APIC_GRID_INST(T, DIM, DEG, true)
 APIC_GRID_INST2(float, 2, 2)
