@@ -91,7 +91,7 @@ typedef struct {
 } apic_grid_desc;
 
 typedef struct {
-    int64_t n;          /* particle count (>= 0)                            */
+    int64_t n;          /* particle count: 0 <= n, n * element size < 2^32  */
     int64_t stride;     /* elements between planes of one field (>= n)     */
     uint32_t *cell;     /* 1 plane, packed cell index                       */
     void *off;          /* dim planes: offset in the cell, cell units       */

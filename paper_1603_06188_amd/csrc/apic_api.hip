@@ -45,6 +45,10 @@ struct ListOff {
     size_t tile_gen, slot, rec_count, rec_list, tot, dead, node_gen, node_count, node_list;
 };
 
+struct TabOff {
+    size_t kcount, kmov, kprefix, maxc, tcount, off, lvl_off, lvl_mask;
+};
+
 struct Layout {
     GridDims d;
     size_t elem;
@@ -53,9 +57,10 @@ struct Layout {
     int64_t rc;     // record (slab) capacity: min(tiles, cap)
     int64_t rcap;   // list capacity per bucket: ceil(tiles / kBuckets)
     int64_t slab_stride;
-    size_t o_vt, o_flags, o_vmax, o_diag_out, o_diag_part, o_key_count;
+    size_t o_vt, o_flags, o_vmax, o_diag_out, o_diag_part, o_key_count, o_scount;
     ListOff lists[2];
-    size_t o_kcount, o_kprefix, o_maxc, o_off, o_lvl_off, o_lvl_mask, o_slabs;
+    TabOff tabs[2];
+    size_t o_slabs;
     size_t fixed_end;
     size_t o_pkey, o_prank, o_sh_cell, o_sh_id, o_sh_f;
     size_t total;
@@ -100,6 +105,7 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.o_diag_out = take(8 * sizeof(double));
     L.o_diag_part = take((size_t)kDiagBlocks * 8 * sizeof(double));
     L.o_key_count = take(G * 4);
+    L.o_scount = take(G * 4);
     for (int k = 0; k < 2; ++k) {
         ListOff &l = L.lists[k];
         l.tile_gen = take(TT * 4);
@@ -112,12 +118,17 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         l.node_count = take((size_t)kBuckets * 4);
         l.node_list = take(LB * 4);
     }
-    L.o_kcount = take(TT * 64 * 4);
-    L.o_kprefix = take(TT * 64 * 4);
-    L.o_maxc = take(TT * 4);
-    L.o_off = take(TT * 4);
-    L.o_lvl_off = take(TT * (size_t)kMaxLevels * 4);
-    L.o_lvl_mask = take(TT * (size_t)kMaxLevels * 8);
+    for (int k = 0; k < 2; ++k) {
+        TabOff &t = L.tabs[k];
+        t.kcount = take(TT * 64 * 4);
+        t.kmov = take(TT * 64 * 4);
+        t.kprefix = take(TT * 64 * 4);
+        t.maxc = take(TT * 4);
+        t.tcount = take(TT * 4);
+        t.off = take(TT * 4);
+        t.lvl_off = take(TT * (size_t)kMaxLevels * 4);
+        t.lvl_mask = take(TT * (size_t)kMaxLevels * 8);
+    }
     L.o_slabs = take(RC * (size_t)L.slab_stride * e);
     L.fixed_end = o;
     L.o_pkey = take(cp * 4);
@@ -174,7 +185,10 @@ apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
     if (rc != APIC_OK) return rc;
     const apic_particles &p = s->p;
     if (p.n < 0) return fail(APIC_E_INVAL, "particle count n = %lld is negative", (long long)p.n);
-    if (p.n > (int64_t)0x7FFFFFFF) return fail(APIC_E_INVAL, "particle count above 2^31 - 1");
+    const int64_t elem = s->grid.precision == APIC_F64 ? 8 : 4;
+    if (p.n * elem >= ((int64_t)1 << 32))
+        return fail(APIC_E_INVAL, "particle count %lld too large: n * element size must stay below 2^32 bytes",
+                    (long long)p.n);
     if (p.n > 0) {
         if (p.stride < p.n) return fail(APIC_E_INVAL, "stride %lld < n %lld", (long long)p.stride, (long long)p.n);
         if (!p.cell || !p.off || !p.v || !p.B || !p.F || !p.mass)
@@ -284,7 +298,7 @@ struct View {
     Layout L;
     Parts<T> user, shadow;
     BinLists lists[2];
-    TileTables tab;
+    TileTables tab[2];
     BinScratch sc;
     Slabs<T> slabs;
     GridState<T> g;
@@ -333,13 +347,20 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         b.node_list = (uint32_t *)(w + o.node_list);
         b.rcap = L.rcap;
     }
-    v.tab.kcount = (uint32_t *)(w + L.o_kcount);
-    v.tab.kprefix = (uint32_t *)(w + L.o_kprefix);
-    v.tab.maxc = (uint32_t *)(w + L.o_maxc);
-    v.tab.off = (uint32_t *)(w + L.o_off);
-    v.tab.lvl_off = (uint32_t *)(w + L.o_lvl_off);
-    v.tab.lvl_mask = (uint64_t *)(w + L.o_lvl_mask);
+    for (int k = 0; k < 2; ++k) {
+        const TabOff &o = L.tabs[k];
+        TileTables &t = v.tab[k];
+        t.kcount = (uint32_t *)(w + o.kcount);
+        t.kmov = (uint32_t *)(w + o.kmov);
+        t.kprefix = (uint32_t *)(w + o.kprefix);
+        t.maxc = (uint32_t *)(w + o.maxc);
+        t.tcount = (uint32_t *)(w + o.tcount);
+        t.off = (uint32_t *)(w + o.off);
+        t.lvl_off = (uint32_t *)(w + o.lvl_off);
+        t.lvl_mask = (uint64_t *)(w + o.lvl_mask);
+    }
     v.sc.key_count = (uint32_t *)(w + L.o_key_count);
+    v.sc.scount = (uint32_t *)(w + L.o_scount);
     v.sc.pkey = (uint32_t *)(w + L.o_pkey);
     v.sc.prank = (uint32_t *)(w + L.o_prank);
     v.slabs.v = (T *)(w + L.o_slabs);
@@ -422,8 +443,8 @@ void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> 
     begin_build(v, ss, nxt, st);
     launch_bin_reset(v.lists[nxt], st);
     launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, st);
-    launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab, v.sc, v.L.rc, st);
-    launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab, v.sc, st);
+    launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
+    launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab[nxt], v.sc, st);
 }
 
 // One G2P from `src` (layout `cur`) into `dst` (layout 1 - cur).  The
@@ -436,11 +457,13 @@ void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &
     begin_build(v, ss, nxt, st);
     timed(APIC_PHASE_BIN, st, [&] {
         if (reset) launch_bin_reset(v.lists[nxt], st);
-        launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.g, v.prm, v.lists[nxt], v.sc, st);
-        launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab, v.sc, v.L.rc, st);
+        launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
+                                           st);
+        launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
     });
     timed(APIC_PHASE_G2P, st, [&] {
-        launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.lists[nxt], v.tab, v.sc, v.g, v.prm, st);
+        launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
+                                v.L.rc, st);
     });
 }
 
@@ -465,8 +488,8 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
                 if (rc != APIC_OK) return rc;
                 v = make_view<T>(s, cap, ss);
             }
-            launch_p2g<T, DIM, DEG, COMP>(v.user, v.lists[ss.cur], v.lists[1 - ss.cur], v.tab, v.slabs, v.g, v.prm,
-                                          v.L.rc, st);
+            launch_p2g<T, DIM, DEG, COMP>(v.user, v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur], v.slabs, v.g,
+                                          v.prm, v.L.rc, st);
             ss.grid_meta = ss.cur;
             ss.vt_valid = false;
             break;
@@ -531,8 +554,8 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
             where = 1 - where;
         }
         timed(APIC_PHASE_P2G, st, [&] {
-            launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab, v.slabs, v.g,
-                                          v.prm, v.L.rc, st);
+            launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur], v.slabs,
+                                          v.g, v.prm, v.L.rc, st);
         });
         timed(APIC_PHASE_GRID_UPDATE, st, [&] {
             launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.cur], v.slabs, v.g, v.prm, v.L.d.tiles, st);

@@ -53,6 +53,87 @@ __device__ __forceinline__ bool first_lane_of_value(uint32_t t, bool active) {
     return leader;
 }
 
+// Base of the bucket of `key` from the per-bucket bases held by lane = bucket
+// (`bbase`).  Wave-wide: call with all lanes.
+__device__ __forceinline__ uint32_t bucket_base_of(uint32_t key, uint32_t bbase) {
+    return __shfl(bbase, (int)bucket_of(key == kDeadKey ? 0u : key >> 6), 64);
+}
+
+// Position of particle (key, rank) in the layout described by `tab`, given
+// the base of the key's bucket and the live total (dead particles follow it).
+__device__ __forceinline__ uint32_t bin_destination(uint32_t key, uint32_t rank, const TileTables &tab,
+                                                    uint32_t base, uint32_t live_total) {
+    if (key == kDeadKey) return live_total + rank;
+    const uint32_t t = key >> 6, l = key & 63;
+    const uint32_t start = base + tab.off[t];
+    if (tab.maxc[t] <= (uint32_t)kMaxLevels) {
+        const uint64_t mask = tab.lvl_mask[(int64_t)t * kMaxLevels + rank];
+        return start + tab.lvl_off[(int64_t)t * kMaxLevels + rank] + (uint32_t)popc64(mask & lanes_below((int)l));
+    }
+    return start + tab.kprefix[(int64_t)t * 64 + l] + rank;
+}
+
+// Lists tile t in `nxt` unless already listed in this generation.
+__device__ __forceinline__ void list_tile(uint32_t t, const BinLists &nxt) {
+    if (nxt.tile_gen[t] != nxt.gen && atomicExch(nxt.tile_gen + t, nxt.gen) != nxt.gen) {
+        const uint32_t b = bucket_of(t);
+        const uint32_t j = atomicAdd(nxt.rec_count + b, 1u);
+        nxt.rec_list[(int64_t)b * nxt.rcap + j] = t;
+    }
+}
+
+// Index of the jj-th particle of a lane's key within a listed tile: level-
+// major (start + offset of level jj + rank among the keys present in it,
+// given the running level offset and the level's key mask), or key-major
+// (kstart + jj) for tiles whose busiest key holds more than kMaxLevels.
+__device__ __forceinline__ int64_t particle_at(uint32_t start, uint32_t kstart, uint32_t level, uint64_t mask,
+                                               uint32_t jj, uint32_t maxc, int lane) {
+    return maxc > (uint32_t)kMaxLevels ? (int64_t)kstart + jj
+                                       : (int64_t)start + level + (uint32_t)popc64(mask & lanes_below(lane));
+}
+
+// Listed tiles of a layout, enumerated as records r = 0, 1, ... in bucket
+// order, and the bases of its particle buckets.  Wave-wide.
+struct TileWalk {
+    uint32_t rpre, rcnt, nrec;   // lane = bucket: record prefix and count; total records
+    uint32_t bbase, live;        // lane = bucket: particle base; live particles
+};
+
+__device__ __forceinline__ TileWalk tile_walk(const BinLists &lists) {
+    TileWalk w;
+    uint32_t mine;
+    w.rpre = wave_bucket_prefix(lists.rec_count, w.nrec, w.rcnt);
+    w.bbase = wave_bucket_prefix(lists.tot, w.live, mine);
+    return w;
+}
+
+// Record r of the walk: tile id, first particle and particle count.
+__device__ __forceinline__ uint32_t tile_range(const TileWalk &w, uint32_t r, const BinLists &lists,
+                                               const TileTables &tab, uint32_t &start, uint32_t &total) {
+    uint32_t b, j;
+    bucket_locate(r, w.rpre, w.rcnt, b, j);
+    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + j];
+    start = __shfl(w.bbase, (int)b, 64) + tab.off[t];
+    total = tab.tcount[t];
+    return t;
+}
+
+// Record r of the walk: tile id, first particle, this lane's key count,
+// busiest key count and (busy tiles) first particle of this lane's key.
+__device__ __forceinline__ uint32_t tile_of_record(const TileWalk &w, uint32_t r, const BinLists &lists,
+                                                   const TileTables &tab, uint32_t &start, uint32_t &cnt,
+                                                   uint32_t &maxc, uint32_t &kstart) {
+    const int lane = lane_id();
+    uint32_t b, j;
+    bucket_locate(r, w.rpre, w.rcnt, b, j);
+    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + j];
+    start = __shfl(w.bbase, (int)b, 64) + tab.off[t];
+    cnt = tab.kcount[(int64_t)t * 64 + lane];
+    maxc = tab.maxc[t];
+    kstart = maxc > (uint32_t)kMaxLevels ? start + tab.kprefix[(int64_t)t * 64 + lane] : 0u;
+    return t;
+}
+
 // Lists the key's tile in `nxt` on first touch (generation tag + bucketed
 // append) and takes a rank within the key; dead particles take a rank in
 // the dead region.  `active` false for lanes without a particle.
@@ -60,30 +141,10 @@ __device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, con
                                                   const BinScratch &sc) {
     const bool live = active && key != kDeadKey;
     const uint32_t t = key >> 6;
-    if (first_lane_of_value(t, live) && nxt.tile_gen[t] != nxt.gen && atomicExch(nxt.tile_gen + t, nxt.gen) != nxt.gen) {
-        const uint32_t b = bucket_of(t);
-        const uint32_t j = atomicAdd(nxt.rec_count + b, 1u);
-        nxt.rec_list[(int64_t)b * nxt.rcap + j] = t;
-    }
+    if (first_lane_of_value(t, live)) list_tile(t, nxt);
     if (!active) return 0u;
     if (key == kDeadKey) return atomicAdd(nxt.dead, 1u);
     return atomicAdd(sc.key_count + key, 1u);
-}
-
-// Position of particle (key, rank) in the layout described by `tab`, given
-// this lane's bucket base of bucket = lane (`bbase`) and the live total.
-__device__ __forceinline__ uint32_t bin_destination(uint32_t key, uint32_t rank, const TileTables &tab,
-                                                    uint32_t bbase, uint32_t live_total) {
-    const uint32_t t = key >> 6;
-    const uint32_t base = __shfl(bbase, (int)bucket_of(key == kDeadKey ? 0u : t), 64);
-    if (key == kDeadKey) return live_total + rank;
-    const uint32_t l = key & 63;
-    const uint32_t start = base + tab.off[t];
-    if (tab.maxc[t] <= (uint32_t)kMaxLevels) {
-        const uint64_t mask = tab.lvl_mask[(int64_t)t * kMaxLevels + rank];
-        return start + tab.lvl_off[(int64_t)t * kMaxLevels + rank] + (uint32_t)popc64(mask & lanes_below((int)l));
-    }
-    return start + tab.kprefix[(int64_t)t * 64 + l] + rank;
 }
 
 // Key (base node) of a particle at cell `ci`, offset `off`, or kDeadKey when

@@ -73,22 +73,27 @@ struct BinLists {
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
 };
 
-// Per-tile tables of the most recently built layout (dense, indexed by tile
-// id; entries of tiles not listed are stale and never read).
+// Per-tile tables of one layout (dense, indexed by tile id; entries of tiles
+// not listed are stale and never read).  Within a key, particles that came
+// from other keys (movers) take ranks [0, kmov) and particles that stayed
+// take ranks [kmov, kcount) in their old order.
 struct TileTables {
     uint32_t *kcount;      // [tiles * 64] particles per key
+    uint32_t *kmov;        // [tiles * 64] of which movers
     uint32_t *kprefix;     // [tiles * 64] exclusive prefix of kcount in the tile
     uint32_t *maxc;        // [tiles] largest per-key count
+    uint32_t *tcount;      // [tiles] particles in the tile
     uint32_t *off;         // [tiles] first particle relative to the bucket base
     uint32_t *lvl_off;     // [tiles * kMaxLevels] first particle of level j in the tile
     uint64_t *lvl_mask;    // [tiles * kMaxLevels] keys present in level j
 };
 
-// Scratch of the binning passes.
+// Scratch of the binning passes (counters are zero between passes).
 struct BinScratch {
-    uint32_t *key_count;  // [G]   per-key counters, zero between passes
-    uint32_t *pkey;       // [cap] new key of each particle (kDeadKey: dead)
-    uint32_t *prank;      // [cap] rank of the particle within its key
+    uint32_t *key_count;  // [G]   movers entering each key
+    uint32_t *scount;     // [G]   particles staying in each key
+    uint32_t *pkey;       // [cap] new key of a mover (kDeadKey: dead)
+    uint32_t *prank;      // [cap] rank of a mover within its key / among the dead
 };
 
 template <typename T>
@@ -300,6 +305,14 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// Element of a particle plane at byte offset `boff` (index * sizeof(T)); the
+// plane pointer is wave-uniform, so plane + 32-bit offset addressing keeps
+// one offset register per particle for all planes.
+template <typename T>
+__device__ __forceinline__ T &plane_at(T *plane, uint32_t boff) {
+    return *(T *)((char *)plane + boff);
+}
 
 // Exact error of a + b (Knuth two-sum).
 template <typename T>

@@ -47,16 +47,18 @@ template <typename T, int DIM, int DEG, bool COMP>
 void launch_grid_update(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm,
                         int64_t max_node_tiles, hipStream_t st);
 
-// Keys of particles at their positions after G2P (first pass of apic_g2p).
+// New keys of the particles of layout `cur` after G2P (first pass of
+// apic_g2p): stayer counts per key, movers' keys and ranks, dead ranks.
 template <typename T, int DIM, int DEG>
-void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const GridState<T> &g, const StepParams<T> &prm,
-                           const BinLists &nxt, const BinScratch &sc, hipStream_t st);
+void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTables &ctab, const GridState<T> &g,
+                           const StepParams<T> &prm, const BinLists &nxt, const BinScratch &sc, int64_t max_records,
+                           hipStream_t st);
 
-// G2P proper, writing each particle to its new binned position.
+// G2P proper, writing each particle to its place in layout `nxt`.
 template <typename T, int DIM, int DEG>
-void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const BinLists &nxt,
-                const TileTables &tab, const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm,
-                hipStream_t st);
+void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const TileTables &ctab,
+                const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const GridState<T> &g,
+                const StepParams<T> &prm, int64_t max_records, hipStream_t st);
 
 // --- observation ----------------------------------------------------------------
 template <typename T, int DIM>

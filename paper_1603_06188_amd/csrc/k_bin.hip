@@ -28,7 +28,8 @@ void launch_bin_reset(const BinLists &nxt, hipStream_t st) {
     hipLaunchKernelGGL(k_bin_reset, dim3(1), dim3(64), 0, st, nxt);
 }
 
-// --- keys of particles at their current position (apic_sort) ------------------------
+// --- keys of particles at their current position (apic_sort); every particle
+// counts as a mover, so ranks come from the per-key counters ---------------------
 template <typename T, int DIM, int DEG>
 __global__ __launch_bounds__(256) void k_bin_keys_static(Parts<T> P, GridDims d, BinLists nxt, BinScratch sc,
                                                          uint32_t *flags) {
@@ -83,15 +84,19 @@ __global__ __launch_bounds__(256) void k_bin_records(BinLists nxt, TileTables ta
         bucket_locate(r, pre, cnt, b, j);
         const uint32_t t = nxt.rec_list[(int64_t)b * nxt.rcap + j];
         const int64_t key = (int64_t)t * 64 + lane;
-        const uint32_t c = sc.key_count[key];
+        const uint32_t mov = sc.key_count[key];
+        const uint32_t c = mov + sc.scount[key];
         sc.key_count[key] = 0u;
+        sc.scount[key] = 0u;
         uint32_t total;
         const uint32_t kp = wave_excl_scan(c, total);
         const uint32_t mx = wave_max_u32(c);
         tab.kcount[key] = c;
+        tab.kmov[key] = mov;
         tab.kprefix[key] = kp;
         if (lane == 0) {
             tab.maxc[t] = mx;
+            tab.tcount[t] = total;
             tab.off[t] = atomicAdd(nxt.tot + b, total);
             nxt.slot[t] = r;
         }
@@ -157,7 +162,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter_copy(Parts<T> src, Parts<T>
     const uint32_t bbase = wave_bucket_prefix(nxt.tot, live, bmine);
     const uint32_t key = active ? sc.pkey[p] : kDeadKey;
     const uint32_t rank = active ? sc.prank[p] : 0u;
-    const int64_t q = bin_destination(key, rank, tab, bbase, live);
+    const uint32_t base = bucket_base_of(key, bbase);
+    const int64_t q = bin_destination(key, rank, tab, base, live);
     if (!active) return;
     dst.cell[q] = src.cell[p];
     dst.m[q] = src.m[p];

@@ -28,27 +28,51 @@ struct P2GParticle {
     T Ac[DIM * DIM];
 };
 
-// Loads particle `q`, checks it and forms its per-particle terms.  Returns
-// false (and sets a flag) when the particle must be skipped.
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ bool p2g_prepare(const Parts<T> &P, int64_t q, const int *key, const StepParams<T> &prm,
-                                            T inv_dx, uint32_t *flags, P2GParticle<T, DIM, DEG> &pp) {
+// Raw state of one particle as stored (loaded one level ahead of its use).
+template <typename T, int DIM>
+struct P2GRaw {
+    uint32_t cell;
+    T m, off[DIM], v[DIM], B[DIM * DIM], F[DIM * DIM];
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ void p2g_load(const Parts<T> &P, uint32_t q, P2GRaw<T, DIM> &r) {
     const int64_t s = P.s;
+    const uint32_t qb = q * (uint32_t)sizeof(T);
+    r.cell = P.cell[q];
+    r.m = plane_at(P.m, qb);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        r.off[a] = plane_at(P.off + a * s, qb);
+        r.v[a] = plane_at(P.v + a * s, qb);
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        r.B[k] = plane_at(P.B + k * s, qb);
+        r.F[k] = plane_at(P.F + k * s, qb);
+    }
+}
+
+// Checks a loaded particle and forms its per-particle terms.  Returns false
+// (and sets a flag) when the particle must be skipped.
+template <typename T, int DIM, int DEG>
+__device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *key, const StepParams<T> &prm,
+                                            T inv_dx, uint32_t *flags, P2GParticle<T, DIM, DEG> &pp) {
     int ci[3] = {0, 0, 0};
-    unpack_cell<DIM>(P.cell[q], ci);
+    unpack_cell<DIM>(r.cell, ci);
     T off[DIM], v[DIM], B[DIM * DIM], F[DIM * DIM];
-    const T m = P.m[q];
+    const T m = r.m;
     bool finite = is_finite(m);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        off[a] = P.off[a * s + q];
-        v[a] = P.v[a * s + q];
+        off[a] = r.off[a];
+        v[a] = r.v[a];
         finite = finite && is_finite(off[a]) && is_finite(v[a]);
     }
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) {
-        B[k] = P.B[k * s + q];
-        F[k] = P.F[k * s + q];
+        B[k] = r.B[k];
+        F[k] = r.F[k];
         finite = finite && is_finite(B[k]) && is_finite(F[k]);
     }
     if (!finite) {
@@ -116,8 +140,7 @@ __device__ __forceinline__ void p2g_accumulate3(const P2GParticle<T, 3, DEG> &pp
                                                 T (&acc_v)[3][CZ][DEG + 1][DEG + 1]) {
     constexpr int K = DEG + 1;
     const Axis<T, DEG> &X = pp.ax[0], &Y = pp.ax[1], &Z = pp.ax[2];
-    T X0[3][K], Yb[3][K], Zc[3][CZ], Mx[K];
-    T Pyz[K][CZ], Qxz[K][CZ], Rxy[K][K];
+    T X0[3][K], Yb[3][K], Mx[K], Rxy[K][K];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const T wrx = X.w[a] * X.r[a], wry = Y.w[a] * Y.r[a];
@@ -127,38 +150,45 @@ __device__ __forceinline__ void p2g_accumulate3(const P2GParticle<T, 3, DEG> &pp
             X0[k][a] = X.w[a] * pp.p[k] + wrx * pp.Qc[k * 3 + 0] + X.dw[a] * pp.Ac[k * 3 + 0];
             Yb[k][a] = wry * pp.Qc[k * 3 + 1] + Y.dw[a] * pp.Ac[k * 3 + 1];
         }
+#pragma unroll
+        for (int b = 0; b < K; ++b) Rxy[a][b] = X.w[a] * Y.w[b];
     }
+    // slice by slice: the slice's own factors, then its K*K nodes
 #pragma unroll
     for (int cc = 0; cc < CZ; ++cc) {
         const int c = C0 + cc;
         const T wrz = Z.w[c] * Z.r[c];
+        T Zc[3], Pyz[K], Qxz[K];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Zc[k][cc] = wrz * pp.Qc[k * 3 + 2] + Z.dw[c] * pp.Ac[k * 3 + 2];
+        for (int k = 0; k < 3; ++k) Zc[k] = wrz * pp.Qc[k * 3 + 2] + Z.dw[c] * pp.Ac[k * 3 + 2];
 #pragma unroll
         for (int b = 0; b < K; ++b) {
-            Pyz[b][cc] = Y.w[b] * Z.w[c];
-            Qxz[b][cc] = X.w[b] * Z.w[c];
+            Pyz[b] = Y.w[b] * Z.w[c];
+            Qxz[b] = X.w[b] * Z.w[c];
         }
-    }
-#pragma unroll
-    for (int a = 0; a < K; ++a)
-#pragma unroll
-        for (int b = 0; b < K; ++b) Rxy[a][b] = X.w[a] * Y.w[b];
-#pragma unroll
-    for (int cc = 0; cc < CZ; ++cc)
 #pragma unroll
         for (int b = 0; b < K; ++b)
 #pragma unroll
             for (int a = 0; a < K; ++a) {
-                acc_m[cc][b][a] += Mx[a] * Pyz[b][cc];
+                acc_m[cc][b][a] += Mx[a] * Pyz[b];
                 // separate multiply-adds into the accumulator (one FMA each)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    acc_v[k][cc][b][a] += X0[k][a] * Pyz[b][cc];
-                    acc_v[k][cc][b][a] += Yb[k][b] * Qxz[a][cc];
-                    acc_v[k][cc][b][a] += Zc[k][cc] * Rxy[a][b];
+                    acc_v[k][cc][b][a] += X0[k][a] * Pyz[b];
+                    acc_v[k][cc][b][a] += Yb[k][b] * Qxz[a];
+                    acc_v[k][cc][b][a] += Zc[k] * Rxy[a][b];
                 }
             }
+        // the slice is accumulated here, not deferred (bounds live factors)
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                asm volatile("" : "+v"(acc_m[cc][b][a]));
+#pragma unroll
+                for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(acc_v[k][cc][b][a]));
+            }
+    }
 }
 
 // 2D: contribution = X0_k(a) wy(b) + Yb_k(b) wx(a).
@@ -191,6 +221,23 @@ __device__ __forceinline__ void p2g_accumulate2(const P2GParticle<T, 2, DEG> &pp
         }
 }
 
+// Slab planes in LDS, padded so that the 64 lanes of one round (a 4x4x4 or
+// 8x8 block of distinct nodes) fall in distinct banks of each half-wave:
+// 3D x + 8 y + 68 z, 2D x + 40 y.  The slab in global memory is compact.
+template <int DIM, int DEG>
+struct SlabLds {
+    static constexpr int RE = Geo<DIM, DEG>::RE;
+    static constexpr int SY = DIM == 3 ? 8 : 40;
+    static constexpr int SZ = DIM == 3 ? 68 : 0;
+    static constexpr int PLANE = DIM == 3 ? SZ * RE : SY * RE;
+    __device__ static constexpr int at(int x, int y, int z) { return x + SY * y + SZ * z; }
+    // compact index (x + RE (y + RE z)) -> padded index
+    __device__ static int from_compact(int i) {
+        const int x = i % RE, y = (i / RE) % RE, z = i / (RE * RE);
+        return at(x, y, DIM == 3 ? z : 0);
+    }
+};
+
 // Slab (LDS) update of one node from this lane: plain, or two-sum with an
 // error plane when compensated.
 template <typename T, bool COMP, int RN, int NC>
@@ -214,21 +261,13 @@ constexpr int p2g_slices() {
     return DIM == 2 ? K : (per_slice * K <= 128 ? K : (per_slice * 2 <= 128 ? 2 : 1));
 }
 
-// Index of the jj-th particle of this lane's key: level-major layout
-// (start + offset of level jj + rank among the keys present in it), or
-// key-major (kstart + jj) for tiles busier than kMaxLevels.
-__device__ __forceinline__ int64_t particle_at(uint32_t start, uint32_t kstart, uint32_t level, uint64_t mask,
-                                               uint32_t jj, uint32_t maxc, int lane) {
-    return maxc > (uint32_t)kMaxLevels ? (int64_t)kstart + jj
-                                       : (int64_t)start + level + (uint32_t)popc64(mask & lanes_below(lane));
-}
-
 template <typename T, int DEG, bool COMP, int C0, int CZ>
 __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int lcoord[3], uint32_t start,
                                           uint32_t kstart, uint32_t cnt, uint32_t maxc, const StepParams<T> &prm,
                                           T inv_dx, uint32_t *flags, T *lds) {
     using Gm = Geo<3, DEG>;
-    constexpr int K = DEG + 1, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC;
+    using SL = SlabLds<3, DEG>;
+    constexpr int K = DEG + 1, NC = Gm::NC, LP = SL::PLANE;
     const int lane = lane_id();
     T acc_m[CZ][K][K], acc_v[3][CZ][K][K];
 #pragma unroll
@@ -240,16 +279,25 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
                 acc_m[c][b][a] = T(0);
                 acc_v[0][c][b][a] = acc_v[1][c][b][a] = acc_v[2][c][b][a] = T(0);
             }
+    // level j's particle is loaded while level j-1 is accumulated
     uint32_t level = 0;
+    uint64_t mask = ballot(cnt > 0);
+    P2GRaw<T, 3> raw;
+    if (cnt > 0) p2g_load<T, 3>(P, (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane), raw);
     for (uint32_t j = 0; j < maxc; ++j) {
-        const uint64_t mask = ballot(cnt > j);
+        const uint32_t level_n = level + (uint32_t)popc64(mask);
+        const uint64_t mask_n = ballot(cnt > j + 1);
+        P2GRaw<T, 3> raw_n;
+        if (cnt > j + 1)
+            p2g_load<T, 3>(P, (uint32_t)particle_at(start, kstart, level_n, mask_n, j + 1, maxc, lane), raw_n);
         if (cnt > j) {
-            const int64_t q = particle_at(start, kstart, level, mask, j, maxc, lane);
             P2GParticle<T, 3, DEG> pp;
-            if (p2g_prepare<T, 3, DEG>(P, q, key, prm, inv_dx, flags, pp))
+            if (p2g_prepare<T, 3, DEG>(raw, key, prm, inv_dx, flags, pp))
                 p2g_accumulate3<T, DEG, C0, CZ>(pp, acc_m, acc_v);
         }
-        level += (uint32_t)popc64(mask);
+        raw = raw_n;
+        level = level_n;
+        mask = mask_n;
     }
     // K*K*CZ rounds; lanes of one round touch distinct nodes
 #pragma unroll
@@ -258,11 +306,11 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
         for (int b = 0; b < K; ++b)
 #pragma unroll
             for (int a = 0; a < K; ++a) {
-                const int idx = (lcoord[0] + a) + RE * ((lcoord[1] + b) + RE * (lcoord[2] + C0 + c));
-                slab_add<T, COMP, RN, NC>(lds, 0, idx, acc_m[c][b][a]);
-                slab_add<T, COMP, RN, NC>(lds, 1, idx, acc_v[0][c][b][a]);
-                slab_add<T, COMP, RN, NC>(lds, 2, idx, acc_v[1][c][b][a]);
-                slab_add<T, COMP, RN, NC>(lds, 3, idx, acc_v[2][c][b][a]);
+                const int idx = SL::at(lcoord[0] + a, lcoord[1] + b, lcoord[2] + C0 + c);
+                slab_add<T, COMP, LP, NC>(lds, 0, idx, acc_m[c][b][a]);
+                slab_add<T, COMP, LP, NC>(lds, 1, idx, acc_v[0][c][b][a]);
+                slab_add<T, COMP, LP, NC>(lds, 2, idx, acc_v[1][c][b][a]);
+                slab_add<T, COMP, LP, NC>(lds, 3, idx, acc_v[2][c][b][a]);
                 wave_lds_sync();
             }
 }
@@ -271,10 +319,13 @@ template <typename T, int DIM, int DEG, bool COMP>
 __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs,
                                              GridState<T> g, StepParams<T> prm) {
     using Gm = Geo<DIM, DEG>;
-    constexpr int K = Gm::K, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC;
-    constexpr int SLAB = NC * RN * (COMP ? 2 : 1);
-    __shared__ T lds_all[4 * SLAB];
-    T *lds = lds_all + (threadIdx.x >> 6) * SLAB;
+    using SL = SlabLds<DIM, DEG>;
+    constexpr int K = Gm::K, RN = Gm::RN, NC = Gm::NC, LP = SL::PLANE;
+    constexpr int NPL = NC * (COMP ? 2 : 1);      // planes
+    constexpr int SLAB = NPL * RN;                // compact, in global memory
+    constexpr int LSLAB = NPL * LP;               // padded, in LDS
+    __shared__ T lds_all[4 * LSLAB];
+    T *lds = lds_all + (threadIdx.x >> 6) * LSLAB;
     const int lane = lane_id();
     int lcoord[3] = {0, 0, 0};
     local_coords<DIM>(lane, lcoord);
@@ -287,23 +338,15 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists 
         nxt.node_count[threadIdx.x] = 0u;
         if (threadIdx.x == 0) nxt.dead[0] = 0u;
     }
-    uint32_t total_recs, rcnt, live, bmine;
-    const uint32_t rpre = wave_bucket_prefix(cur.rec_count, total_recs, rcnt);
-    const uint32_t bbase = wave_bucket_prefix(cur.tot, live, bmine);
-    for (uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < total_recs; r += gridDim.x * 4) {
-        uint32_t b, j;
-        bucket_locate(r, rpre, rcnt, b, j);
-        const uint32_t t = cur.rec_list[(int64_t)b * cur.rcap + j];
+    const TileWalk walk = tile_walk(cur);
+    for (uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < walk.nrec; r += gridDim.x * 4) {
+        uint32_t start, cnt, maxc, kstart;
+        const uint32_t t = tile_of_record(walk, r, cur, tab, start, cnt, maxc, kstart);
         int key[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, key);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) key[a] += lcoord[a];
-        const uint32_t start = __shfl(bbase, (int)b, 64) + tab.off[t];
-        const uint32_t cnt = tab.kcount[(int64_t)t * 64 + lane];
-        const uint32_t maxc = tab.maxc[t];
-        // first particle of this lane's key in key-major order (busy tiles)
-        const uint32_t kstart = maxc > (uint32_t)kMaxLevels ? start + tab.kprefix[(int64_t)t * 64 + lane] : 0u;
-        for (int i = lane; i < SLAB; i += 64) lds[i] = T(0);
+        for (int i = lane; i < LSLAB; i += 64) lds[i] = T(0);
         wave_lds_sync();
         if constexpr (DIM == 3) {
             constexpr int CZ = p2g_slices<T, 3, DEG>();
@@ -325,8 +368,10 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists 
                 const uint64_t mask = ballot(cnt > jj);
                 if (cnt > jj) {
                     const int64_t q = particle_at(start, kstart, level, mask, jj, maxc, lane);
+                    P2GRaw<T, 2> raw;
+                    p2g_load<T, 2>(P, (uint32_t)q, raw);
                     P2GParticle<T, 2, DEG> pp;
-                    if (p2g_prepare<T, 2, DEG>(P, q, key, prm, g.inv_dx, g.flags, pp))
+                    if (p2g_prepare<T, 2, DEG>(raw, key, prm, g.inv_dx, g.flags, pp))
                         p2g_accumulate2<T, DEG>(pp, acc_m, acc_v);
                 }
                 level += (uint32_t)popc64(mask);
@@ -335,15 +380,15 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists 
             for (int bb = 0; bb < K; ++bb)
 #pragma unroll
                 for (int a = 0; a < K; ++a) {
-                    const int idx = (lcoord[0] + a) + RE * (lcoord[1] + bb);
-                    slab_add<T, COMP, RN, NC>(lds, 0, idx, acc_m[bb][a]);
-                    slab_add<T, COMP, RN, NC>(lds, 1, idx, acc_v[0][bb][a]);
-                    slab_add<T, COMP, RN, NC>(lds, 2, idx, acc_v[1][bb][a]);
+                    const int idx = SL::at(lcoord[0] + a, lcoord[1] + bb, 0);
+                    slab_add<T, COMP, LP, NC>(lds, 0, idx, acc_m[bb][a]);
+                    slab_add<T, COMP, LP, NC>(lds, 1, idx, acc_v[0][bb][a]);
+                    slab_add<T, COMP, LP, NC>(lds, 2, idx, acc_v[1][bb][a]);
                     wave_lds_sync();
                 }
         }
         T *out = slabs.v + (int64_t)r * slabs.stride;
-        for (int i = lane; i < SLAB; i += 64) out[i] = lds[i];
+        for (int i = lane; i < SLAB; i += 64) out[i] = lds[(i / RN) * LP + SL::from_compact(i % RN)];
         wave_lds_sync();
     }
 }

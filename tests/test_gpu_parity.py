@@ -121,6 +121,56 @@ def test_apic_step_matches_chained_oracle_steps(dim, degree):
         check_binned_layout(tile, local)
 
 
+@pytest.mark.parametrize("degree", [2, 3])
+def test_particles_leaving_the_grid_are_carried_and_the_rest_match(degree):
+    """A cluster moving 0.6 cells per step toward the -x face leaves the
+    grid during the second step: from then on it sits in the dead region,
+    carried unchanged (its state is the oracle's after the step that took it
+    out), OUT_OF_DOMAIN is raised, and every other particle matches the
+    oracle chained over the steps without the cluster once it is gone."""
+    import dataclasses
+    b = _b()
+    cells, dt = 16, 1e-2
+    dx = 1.0 / cells
+    bulk = scenes.random_particles(1500, dim=3, cells=cells, degree=degree, seed=41, margin=5.0,
+                                   vel_sigma=0.2, f_sigma=0.02, b_sigma=0.01, model=0)
+    rng = np.random.default_rng(42)
+    start = 1.55 if degree == 2 else 2.05      # first cell whose support is inside
+    xc = np.column_stack([(start + 0.1 * rng.random(40)) * dx,
+                          (6.0 + 4.0 * rng.random((40, 2))) * dx])
+    x = np.vstack([bulk.x, xc])
+    v = np.vstack([bulk.v, np.tile([-0.6 * dx / dt, 0.0, 0.0], (40, 1))])
+    B = np.concatenate([bulk.B, np.zeros((40, 3, 3))])
+    F = np.concatenate([bulk.F, np.tile(np.eye(3), (40, 1, 1))])
+    m = np.concatenate([bulk.m, np.ones(40)])
+    s = dataclasses.replace(bulk, m=m, v=v, B=B, F=F, dt=dt).with_state(x=x)
+    steps = 4
+    ds = b.DeviceScene(s)
+    ds.step(steps)
+    got = ds.state()
+    g = ogrid(s)
+    cluster = np.arange(bulk.n, s.n)
+    live = np.ones(s.n, bool)
+    X, V, Bm, Fm = s.x.copy(), s.v.copy(), s.B.copy(), s.F.copy()
+    left_at = None
+    for k in range(steps):
+        idx = np.flatnonzero(live)
+        r = oracle.step(g, X[idx], V[idx], Bm[idx], Fm[idx], s.m[idx], s.V[idx], s.model, s.mu, s.lam, s.dt,
+                        s.gravity, s.band)
+        X[idx], V[idx], Bm[idx], Fm[idx] = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
+        # supports that no longer fit: base node below 0 along x
+        base = np.floor(X[:, 0] / dx - (0.5 if degree == 2 else 1.0))
+        gone = live & (base < 0)
+        if gone.any() and left_at is None:
+            left_at = k
+        live &= ~gone
+    assert left_at is not None and 0 < left_at < steps - 1
+    assert not live[cluster].any() and live[:bulk.n].all()
+    assert ds.flags() & b.APIC_FLAG_OUT_OF_DOMAIN
+    for key, a, ref in (("x", got["x"], X), ("v", got["v"], V), ("B", got["B"], Bm), ("F", got["F"], Fm)):
+        assert rel(a, ref) <= 1e-11, (key, rel(a, ref))
+
+
 def test_disk2d_fp64_ten_round_trips():
     """The rotating-disk transfer test: 10 P2G -> normalize -> G2P round
     trips at dt = 0 in binary64; per-transfer momenta conserved."""
