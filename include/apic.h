@@ -212,6 +212,25 @@ apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int
                       void *stream);
 
 /*
+ * Batched steps: the same computation as apic_step for n_scenes independent
+ * scenes, but each phase of a step (P2G, grid update, keys, records, G2P)
+ * is ONE kernel launch covering every scene, so many small scenes fill the
+ * GPU and pay one launch per phase instead of one per scene.  All scenes
+ * must share dim, degree, precision and options (else APIC_E_INVAL) and
+ * have distinct workspaces.  `batch_ws` is a device buffer of at least
+ * apic_batch_workspace_bytes(n_scenes) bytes, 256-byte aligned, owned by the
+ * caller; it holds the scene table of the call, written on `stream`, so
+ * calls that share a batch_ws must be ordered (same stream).  Results
+ * are those of apic_step on each scene alone (same kernels; a scene never
+ * reads another scene's memory).  Ends with every scene's particles in the
+ * caller's planes.  Kernel timing (apic_timing_enable) records each batched
+ * launch once under its phase.
+ */
+apic_status apic_batch_workspace_bytes(int32_t n_scenes, size_t *bytes);
+apic_status apic_step_batch(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, void *batch_ws,
+                            size_t batch_ws_bytes, void *stream);
+
+/*
  * Copies one grid field (APIC_GRID_*) into `out`, a device buffer of
  * node_count * components elements of the scene precision, component-major
  * (component c of node i at out[c*node_count + i]), nodes in the order

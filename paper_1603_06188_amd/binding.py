@@ -37,7 +37,7 @@ APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
 
 EXPORTED = [
     "apic_workspace_bytes", "apic_reset", "apic_sort", "apic_p2g", "apic_grid_update", "apic_g2p", "apic_step",
-    "apic_grid_export", "apic_diagnostics", "apic_get_flags", "apic_clear_flags",
+    "apic_batch_workspace_bytes", "apic_step_batch", "apic_grid_export", "apic_diagnostics", "apic_get_flags", "apic_clear_flags",
     "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
     "apic_last_error", "apic_version",
 ]
@@ -76,6 +76,8 @@ _sigs = {
     "apic_grid_update": [_S, _V],
     "apic_g2p": [_S, _V],
     "apic_step": [_S, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V],
+    "apic_batch_workspace_bytes": [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "apic_step_batch": [_S, ctypes.c_int32, ctypes.c_int32, _V, ctypes.c_size_t, _V],
     "apic_grid_export": [_S, ctypes.c_int32, _V, _V],
     "apic_diagnostics": [_S, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _V],
     "apic_get_flags": [_S, ctypes.POINTER(ctypes.c_uint32), _V],
@@ -146,6 +148,18 @@ def apic_step(scenes, n_steps: int, sort_every: int = 0, stream=None) -> None:
     arr = (ApicScene * len(scenes))(*scenes)
     _check(_lib.apic_step(arr, len(scenes), int(n_steps), int(sort_every), _stream(stream)))
     # the C side does not modify the structs; nothing to copy back
+
+
+def apic_batch_workspace_bytes(n_scenes: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.apic_batch_workspace_bytes(int(n_scenes), ctypes.byref(out)))
+    return out.value
+
+
+def apic_step_batch(scenes, n_steps: int, batch_ws_ptr: int, batch_ws_bytes: int, stream=None) -> None:
+    arr = (ApicScene * len(scenes))(*scenes)
+    _check(_lib.apic_step_batch(arr, len(scenes), int(n_steps), ctypes.c_void_p(batch_ws_ptr),
+                                int(batch_ws_bytes), _stream(stream)))
 
 
 def apic_grid_export(scene: ApicScene, field: int, out_ptr: int, stream=None) -> None:
@@ -364,3 +378,22 @@ class DeviceScene:
             ids = self.id[:n].cpu().numpy().copy()
             out["id"] = np.sort(ids) if not raw else ids
         return out
+
+
+class SceneBatch:
+    """Device scenes advanced together by apic_step_batch (one launch per
+    phase for all of them).  Owns the batch workspace (the scene table)."""
+
+    def __init__(self, device_scenes, device="cuda"):
+        self.scenes = list(device_scenes)
+        self.bbytes = apic_batch_workspace_bytes(len(self.scenes))
+        self.bws = torch.empty(self.bbytes + 256, dtype=torch.uint8, device=device)
+        self.bptr = (self.bws.data_ptr() + 255) // 256 * 256
+
+    def step(self, n_steps=1, stream=None):
+        apic_step_batch([d.s for d in self.scenes], n_steps, self.bptr, self.bbytes, stream)
+
+    def step_each(self, n_steps=1, stream=None):
+        """The same steps as one apic_step call over the scenes (per-scene
+        kernel launches, one scene after the other)."""
+        apic_step([d.s for d in self.scenes], n_steps, 0, stream)

@@ -614,6 +614,169 @@ apic_status dispatch_steps(apic_scene *s, int64_t cap, int32_t n, int32_t k, hip
     return cub ? steps_c<float, 2, 3>(s, cap, n, k, st) : steps_c<float, 2, 2>(s, cap, n, k, st);
 }
 
+// ---------------------------------------------------------------------------
+// Batched steps (apic_step_batch)
+// ---------------------------------------------------------------------------
+constexpr size_t kDescBytes = (sizeof(SceneDesc<double>) + 15) / 16 * 16;
+
+size_t batch_bytes(int32_t n) {
+    return align_up((size_t)n * kDescBytes) + align_up((size_t)BK_COUNT * (size_t)(n + 1) * 4);
+}
+
+// Host staging of the scene table, per batch workspace; `done` guards reuse.
+struct BatchHost {
+    void *pinned = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+std::unordered_map<void *, BatchHost> g_batch;
+std::mutex g_batch_mu;
+
+// Blocks of one scene's share of a batched launch, by particle count (about
+// 256 particles per wavefront; the kernels stride over any remainder).
+int share_blocks(int64_t n, int cap) {
+    int64_t b = (n + 1023) / 1024;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
+apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws, hipStream_t st) {
+    std::vector<SceneDesc<T>> descs((size_t)n);
+    std::vector<int32_t> starts((size_t)BK_COUNT * (size_t)(n + 1));
+    std::vector<SceneState *> states((size_t)n);
+    int32_t total[BK_COUNT] = {0, 0, 0, 0, 0, 0};
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t cap = 0;
+        (void)check_scene(&scenes[i], &cap);
+        SceneState &ss = state_of(&scenes[i], cap, st);
+        // generations of both parities must not wrap within the call
+        for (int p = 0; p < 2; ++p)
+            if (ss.gen[p] > 0xFFFFFFFFu - (uint32_t)n_steps - 2u) {
+                View<T> v = make_view<T>(&scenes[i], cap, ss);
+                launch_fill<uint32_t>(v.lists[p].tile_gen, v.L.d.tiles, 0u, st);
+                launch_fill<uint32_t>(v.lists[p].node_gen, v.L.d.tiles, 0u, st);
+                ss.gen[p] = 0u;
+                if (p == ss.cur) ss.binned = false;   // its tags are gone: bin again
+                if (p == ss.grid_meta) ss.grid_meta = -1;
+            }
+        View<T> v = make_view<T>(&scenes[i], cap, ss);
+        int where = 0;
+        if (!ss.binned) {
+            timed(APIC_PHASE_SORT, st, [&] { bin_static<T, DIM, DEG>(v, ss, v.user, v.shadow, 1 - ss.cur, st); });
+            ss.cur = 1 - ss.cur;
+            ss.binned = true;
+            where = 1;
+        }
+        SceneDesc<T> &d = descs[(size_t)i];
+        d.bufs[0] = v.user;
+        d.bufs[1] = v.shadow;
+        if (!v.user.id || !v.shadow.id) d.bufs[0].id = d.bufs[1].id = nullptr;
+        for (int p = 0; p < 2; ++p) {
+            d.lists[p] = v.lists[p];
+            d.lists[p].gen = ss.gen[p];
+            d.tab[p] = v.tab[p];
+        }
+        d.sc = v.sc;
+        d.slabs = v.slabs;
+        d.g = v.g;
+        d.prm = v.prm;
+        d.rc = v.L.rc;
+        d.cur0 = ss.cur;
+        d.where0 = where;
+        states[(size_t)i] = &ss;
+        const int64_t np = scenes[i].p.n;
+        const int share[BK_COUNT] = {share_blocks(np, 4096), share_blocks(np, 8192), share_blocks(np, 2048),
+                                     share_blocks(np, 4096), share_blocks(np, 4096), share_blocks(np, 4096)};
+        for (int k = 0; k < BK_COUNT; ++k) {
+            starts[(size_t)k * (n + 1) + i] = total[k];
+            total[k] += share[k];
+        }
+    }
+    for (int k = 0; k < BK_COUNT; ++k) starts[(size_t)k * (n + 1) + n] = total[k];
+
+    // scene table: host staging (pinned, reused once its last copy is done)
+    BatchHost &bh = g_batch[bws];
+    const size_t need = batch_bytes(n);
+    if (bh.pending) {
+        apic_status rc = hip_check(hipEventSynchronize(bh.done), "apic_step_batch staging");
+        if (rc != APIC_OK) return rc;
+        bh.pending = false;
+    }
+    if (bh.bytes < need) {
+        if (bh.pinned) (void)hipHostFree(bh.pinned);
+        bh.pinned = nullptr;
+        bh.bytes = 0;
+        apic_status rc = hip_check(hipHostMalloc(&bh.pinned, need, hipHostMallocDefault), "apic_step_batch staging");
+        if (rc != APIC_OK) return rc;
+        bh.bytes = need;
+    }
+    if (!bh.done) {
+        apic_status rc = hip_check(hipEventCreateWithFlags(&bh.done, hipEventDisableTiming), "apic_step_batch event");
+        if (rc != APIC_OK) return rc;
+    }
+    char *host = (char *)bh.pinned;
+    memcpy(host, descs.data(), (size_t)n * sizeof(SceneDesc<T>));
+    const size_t o_start = align_up((size_t)n * kDescBytes);
+    memcpy(host + o_start, starts.data(), starts.size() * 4);
+    // descriptors are packed at sizeof(SceneDesc<T>) (<= kDescBytes per entry)
+    apic_status rc = hip_check(hipMemcpyAsync(bws, host, need, hipMemcpyHostToDevice, st), "apic_step_batch table");
+    if (rc != APIC_OK) return rc;
+    rc = hip_check(hipEventRecord(bh.done, st), "apic_step_batch event");
+    if (rc != APIC_OK) return rc;
+    bh.pending = true;
+
+    const SceneDesc<T> *dd = (const SceneDesc<T> *)bws;
+    const int32_t *ds = (const int32_t *)((const char *)bws + o_start);
+    auto start_of = [&](int k) { return ds + (size_t)k * (n + 1); };
+    for (int32_t k = 0; k < n_steps; ++k) {
+        timed(APIC_PHASE_P2G, st,
+              [&] { launch_p2g_batch<T, DIM, DEG, COMP>(dd, start_of(BK_P2G), n, k, total[BK_P2G], st); });
+        timed(APIC_PHASE_GRID_UPDATE, st, [&] {
+            launch_grid_update_batch<T, DIM, DEG, COMP>(dd, start_of(BK_GRID), n, k, total[BK_GRID], st);
+        });
+        timed(APIC_PHASE_BIN, st, [&] {
+            launch_bin_keys_moved_batch<T, DIM, DEG>(dd, start_of(BK_KEYS), n, k, total[BK_KEYS], st);
+            launch_bin_records_batch<T, DIM>(dd, start_of(BK_RECORDS), n, k, total[BK_RECORDS], st);
+        });
+        timed(APIC_PHASE_G2P, st,
+              [&] { launch_g2p_batch<T, DIM, DEG>(dd, start_of(BK_G2P), n, k, total[BK_G2P], st); });
+    }
+    launch_copy_back_batch<T, DIM>(dd, start_of(BK_COPY), n, n_steps, total[BK_COPY], st);
+    for (int32_t i = 0; i < n; ++i) {
+        SceneState &ss = *states[(size_t)i];
+        const int cur0 = ss.cur;
+        // builds of this call: step k builds parity (cur0 + 1 + k) & 1
+        ss.gen[(cur0 + 1) & 1] += (uint32_t)((n_steps + 1) / 2);
+        ss.gen[cur0] += (uint32_t)(n_steps / 2);
+        ss.cur = (cur0 + n_steps) & 1;
+        if (n_steps > 0) ss.grid_meta = (cur0 + n_steps - 1) & 1;
+        ss.binned = true;
+        ss.vt_valid = false;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(APIC_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return APIC_OK;
+}
+
+template <typename T, int DIM, int DEG>
+apic_status batch_c(apic_scene *s, int32_t n, int32_t k, void *bws, hipStream_t st) {
+    if (s[0].grid.options & APIC_OPT_COMPENSATED) return run_batch<T, DIM, DEG, true>(s, n, k, bws, st);
+    return run_batch<T, DIM, DEG, false>(s, n, k, bws, st);
+}
+
+apic_status dispatch_batch(apic_scene *s, int32_t n, int32_t k, void *bws, hipStream_t st) {
+    const bool f64 = s[0].grid.precision == APIC_F64, d3 = s[0].grid.dim == 3, cub = s[0].grid.degree == APIC_CUBIC;
+    if (f64) {
+        if (d3) return cub ? batch_c<double, 3, 3>(s, n, k, bws, st) : batch_c<double, 3, 2>(s, n, k, bws, st);
+        return cub ? batch_c<double, 2, 3>(s, n, k, bws, st) : batch_c<double, 2, 2>(s, n, k, bws, st);
+    }
+    if (d3) return cub ? batch_c<float, 3, 3>(s, n, k, bws, st) : batch_c<float, 3, 2>(s, n, k, bws, st);
+    return cub ? batch_c<float, 2, 3>(s, n, k, bws, st) : batch_c<float, 2, 2>(s, n, k, bws, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -666,6 +829,41 @@ apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int
         if (rc != APIC_OK) return rc;
     }
     return APIC_OK;
+}
+
+apic_status apic_batch_workspace_bytes(int32_t n_scenes, size_t *bytes) {
+    if (n_scenes < 0) return fail(APIC_E_INVAL, "n_scenes must be >= 0");
+    if (!bytes) return fail(APIC_E_INVAL, "bytes is NULL");
+    *bytes = batch_bytes(n_scenes);
+    return APIC_OK;
+}
+
+apic_status apic_step_batch(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, void *batch_ws,
+                            size_t batch_ws_bytes, void *stream) {
+    if (n_scenes < 0 || n_steps < 0) return fail(APIC_E_INVAL, "n_scenes and n_steps must be >= 0");
+    if (n_scenes == 0) return APIC_OK;
+    if (!scenes) return fail(APIC_E_INVAL, "scenes is NULL");
+    if (!batch_ws) return fail(APIC_E_WORKSPACE, "batch workspace is NULL");
+    if (((uintptr_t)batch_ws) % kAlign) return fail(APIC_E_WORKSPACE, "batch workspace must be 256-byte aligned");
+    if (batch_ws_bytes < batch_bytes(n_scenes))
+        return fail(APIC_E_WORKSPACE, "batch workspace of %zu bytes, %zu needed for %d scenes", batch_ws_bytes,
+                    batch_bytes(n_scenes), n_scenes);
+    for (int32_t k = 0; k < n_scenes; ++k) {
+        int64_t cap = 0;
+        apic_status rc = check_scene(&scenes[k], &cap);
+        if (rc != APIC_OK) return rc;
+        const apic_grid_desc &a = scenes[0].grid, &b = scenes[k].grid;
+        if (a.dim != b.dim || a.degree != b.degree || a.precision != b.precision || a.options != b.options)
+            return fail(APIC_E_INVAL, "scene %d differs from scene 0 in dim, degree, precision or options", k);
+    }
+    {
+        std::unordered_map<void *, int32_t> seen;
+        for (int32_t k = 0; k < n_scenes; ++k)
+            if (!seen.emplace(scenes[k].workspace, k).second)
+                return fail(APIC_E_INVAL, "scenes %d and %d share a workspace", seen[scenes[k].workspace], k);
+    }
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    return dispatch_batch(scenes, n_scenes, n_steps, batch_ws, (hipStream_t)stream);
 }
 
 apic_status apic_grid_export(const apic_scene *scene, int32_t field, void *out, void *stream) {

@@ -147,6 +147,32 @@ __device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, con
     return atomicAdd(sc.key_count + key, 1u);
 }
 
+// One scene's view of step k of a batched launch: its descriptor, the lists
+// being read and built (with their generations) and its share of blocks.
+template <typename T>
+struct BatchStep {
+    const SceneDesc<T> *d;
+    StepParity sp;
+    BinLists cur, nxt;
+    uint32_t blk, nblk;
+};
+
+template <typename T>
+__device__ __forceinline__ BatchStep<T> batch_step(const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
+    BatchStep<T> b;
+    const int s = scene_of_block(start, n, blockIdx.x);
+    b.d = descs + s;
+    const uint32_t gen0[2] = {b.d->lists[0].gen, b.d->lists[1].gen};
+    b.sp = step_parity(b.d->cur0, b.d->where0, gen0, k);
+    b.cur = b.d->lists[b.sp.cur];
+    b.cur.gen = b.sp.gen_cur;
+    b.nxt = b.d->lists[b.sp.nxt];
+    b.nxt.gen = b.sp.gen_nxt;
+    b.blk = blockIdx.x - (uint32_t)start[s];
+    b.nblk = (uint32_t)(start[s + 1] - start[s]);
+    return b;
+}
+
 // Key (base node) of a particle at cell `ci`, offset `off`, or kDeadKey when
 // its support leaves the grid or the offset is not finite.
 template <typename T, int DIM, int DEG>

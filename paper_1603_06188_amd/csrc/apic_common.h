@@ -120,6 +120,46 @@ struct StepParams {
     T mu, lam, inv_rho0;
 };
 
+// Everything the step kernels need for one scene of a batch (the caller's
+// particle planes and the workspace shadow, both list parities, tables,
+// slabs, grid and parameters), as of the start of a batched call: the
+// layout being read is lists[cur0] and the particles are in bufs[where0].
+template <typename T>
+struct SceneDesc {
+    Parts<T> bufs[2];
+    BinLists lists[2];     // gen: generation of the last build in each parity
+    TileTables tab[2];
+    BinScratch sc;
+    Slabs<T> slabs;
+    GridState<T> g;
+    StepParams<T> prm;
+    int64_t rc;            // record capacity
+    int32_t cur0, where0;
+};
+
+// Kernels of a batched step; per kind, scene s owns blocks
+// [start[s], start[s + 1]) of the launch.
+enum BatchKernel : int { BK_P2G = 0, BK_GRID = 1, BK_KEYS = 2, BK_RECORDS = 3, BK_G2P = 4, BK_COPY = 5,
+                         BK_COUNT = 6 };
+
+// Layout parities and generations at step k of a batched call: step k
+// reads parity (cur0 + k) & 1 and builds the other one; the j-th build of a
+// call into parity p gets generation gen0[p] + 1 + j.
+struct StepParity {
+    int cur, nxt, src;
+    uint32_t gen_cur, gen_nxt;
+};
+
+__host__ __device__ __forceinline__ StepParity step_parity(int cur0, int where0, const uint32_t *gen0, int k) {
+    StepParity sp;
+    sp.cur = (cur0 + k) & 1;
+    sp.nxt = sp.cur ^ 1;
+    sp.src = (where0 + k) & 1;
+    sp.gen_cur = k == 0 ? gen0[sp.cur] : gen0[sp.cur] + 1u + (uint32_t)((k - 1) / 2);
+    sp.gen_nxt = gen0[sp.nxt] + 1u + (uint32_t)(k / 2);
+    return sp;
+}
+
 enum : uint32_t {
     FLAG_OUT_OF_DOMAIN = 1u,
     FLAG_NONFINITE = 2u,
@@ -299,6 +339,19 @@ template <>
 __device__ __forceinline__ float floor_t<float>(float x) { return floorf(x); }
 template <>
 __device__ __forceinline__ double floor_t<double>(double x) { return floor(x); }
+
+// Scene of block b in a batched launch: the largest s with start[s] <= b.
+__device__ __forceinline__ int scene_of_block(const int32_t *start, int n, uint32_t b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
 // wave64 helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }

@@ -60,6 +60,27 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
                 const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const GridState<T> &g,
                 const StepParams<T> &prm, int64_t max_records, hipStream_t st);
 
+// --- batched steps: one launch per phase for every scene of a batch -------------
+// `start` holds, per scene, its first block of the launch (n + 1 entries);
+// `k` is the step index within the batched call.
+template <typename T, int DIM, int DEG, bool COMP>
+void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st);
+template <typename T, int DIM, int DEG, bool COMP>
+void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                              hipStream_t st);
+template <typename T, int DIM, int DEG>
+void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                                 hipStream_t st);
+template <typename T, int DIM>
+void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                              hipStream_t st);
+template <typename T, int DIM, int DEG>
+void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st);
+// after k steps: scenes whose particles are in the shadow copy them back
+template <typename T, int DIM>
+void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                            hipStream_t st);
+
 // --- observation ----------------------------------------------------------------
 template <typename T, int DIM>
 void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);

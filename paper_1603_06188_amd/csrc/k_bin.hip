@@ -75,11 +75,12 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) 
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_bin_records(BinLists nxt, TileTables tab, BinScratch sc, GridDims d) {
+__device__ __forceinline__ void records_body(const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
+                                             const GridDims &d, uint32_t blk, uint32_t nblk) {
     const int lane = lane_id();
     uint32_t total_recs, cnt;
     const uint32_t pre = wave_bucket_prefix(nxt.rec_count, total_recs, cnt);
-    for (uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < total_recs; r += gridDim.x * 4) {
+    for (uint32_t r = blk * 4 + (threadIdx.x >> 6); r < total_recs; r += nblk * 4) {
         uint32_t b, j;
         bucket_locate(r, pre, cnt, b, j);
         const uint32_t t = nxt.rec_list[(int64_t)b * nxt.rcap + j];
@@ -146,6 +147,56 @@ __global__ __launch_bounds__(256) void k_bin_records(BinLists nxt, TileTables ta
 }
 
 template <int DIM>
+__global__ __launch_bounds__(256) void k_bin_records(BinLists nxt, TileTables tab, BinScratch sc, GridDims d) {
+    records_body<DIM>(nxt, tab, sc, d, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
+                                                           int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const SceneDesc<T> &d = *b.d;
+    records_body<DIM>(b.nxt, d.tab[b.sp.nxt], d.sc, d.g.d, b.blk, b.nblk);
+}
+
+template <typename T, int DIM>
+void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_bin_records_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+}
+
+// copies the particles of every scene that ended in the workspace shadow
+// back to the caller's planes
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
+                                                         int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    if (b.sp.src != 1) return;
+    const Parts<T> &src = b.d->bufs[1], &dst = b.d->bufs[0];
+    for (int64_t j = (int64_t)b.blk * blockDim.x + threadIdx.x; j < src.n; j += (int64_t)b.nblk * blockDim.x) {
+        dst.cell[j] = src.cell[j];
+        dst.m[j] = src.m[j];
+        if (src.id && dst.id) dst.id[j] = src.id[j];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            dst.off[a * dst.s + j] = src.off[a * src.s + j];
+            dst.v[a * dst.s + j] = src.v[a * src.s + j];
+        }
+#pragma unroll
+        for (int q = 0; q < DIM * DIM; ++q) {
+            dst.B[q * dst.s + j] = src.B[q * src.s + j];
+            dst.F[q * dst.s + j] = src.F[q * src.s + j];
+        }
+    }
+}
+
+template <typename T, int DIM>
+void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                            hipStream_t st) {
+    hipLaunchKernelGGL((k_copy_back_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+}
+
+template <int DIM>
 void launch_bin_records(const GridDims &d, const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
                         int64_t max_records, hipStream_t st) {
     hipLaunchKernelGGL((k_bin_records<DIM>), dim3(blocks_for(max_records, 4, 4096)), dim3(256), 0, st, nxt, tab, sc,
@@ -197,6 +248,10 @@ template void launch_bin_records<3>(const GridDims &, const BinLists &, const Ti
                                     int64_t, hipStream_t);
 
 #define APIC_BIN_INST(T, DIM)                                                                                    \
+    template void launch_bin_records_batch<T, DIM>(const SceneDesc<T> *, const int32_t *, int, int, int,          \
+                                                   hipStream_t);                                                  \
+    template void launch_copy_back_batch<T, DIM>(const SceneDesc<T> *, const int32_t *, int, int, int,            \
+                                                 hipStream_t);                                                    \
     template void launch_bin_scatter_copy<T, DIM>(const Parts<T> &, const Parts<T> &, const BinLists &,           \
                                                   const TileTables &, const BinScratch &, hipStream_t);           \
     template void launch_bin_keys_static<T, DIM, 2>(const Parts<T> &, const GridDims &, const BinLists &,         \

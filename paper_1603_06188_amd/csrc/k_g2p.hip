@@ -219,8 +219,9 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
 }
 
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinLists cur, TileTables ctab, GridState<T> g,
-                                                        StepParams<T> prm, BinLists nxt, BinScratch sc) {
+__device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur, const TileTables &ctab,
+                                          const GridState<T> &g, const StepParams<T> &prm, const BinLists &nxt,
+                                          const BinScratch &sc, uint32_t blk, uint32_t nblk) {
     __shared__ uint32_t lds_stay[4][64];
     __shared__ uint32_t lds_queue[4][128];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinLists cur
     const TileWalk walk = tile_walk(cur);
     const T reach = step_reach<T>(wave_vmax(g.vmax), prm, g.inv_dx);
     const uint32_t items = walk.nrec + dead_chunks(P.n, walk.live);
-    for (uint32_t r = blockIdx.x * 4 + (uint32_t)wv; r < items; r += gridDim.x * 4) {
+    for (uint32_t r = blk * 4 + (uint32_t)wv; r < items; r += nblk * 4) {
         if (r >= walk.nrec) {
             // particles that could not be binned stay in the dead region
             const int64_t p = (int64_t)walk.live + (int64_t)(r - walk.nrec) * 64 + lane;
@@ -281,6 +282,27 @@ __global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinLists cur
         if (ballot(s > 0u) != 0ull && lane == 0) list_tile(t, nxt);
         wave_lds_sync();
     }
+}
+
+template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinLists cur, TileTables ctab, GridState<T> g,
+                                                        StepParams<T> prm, BinLists nxt, BinScratch sc) {
+    keys_body<T, DIM, DEG>(P, cur, ctab, g, prm, nxt, sc, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) void k_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
+                                                              int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const SceneDesc<T> &d = *b.d;
+    keys_body<T, DIM, DEG>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk, b.nblk);
+}
+
+template <typename T, int DIM, int DEG>
+void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL((k_bin_keys_moved_batch<T, DIM, DEG>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
+                       n, k);
 }
 
 template <typename T, int DIM, int DEG>
@@ -351,9 +373,10 @@ constexpr int g2p_min_waves() {
 // (every lane busy).  A stayer's rank in its key continues from the key's
 // mover count (LDS counter); a mover takes the key and rank of pass 1.
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p(
-    Parts<T> src, Parts<T> dst, BinLists cur, TileTables ctab, BinLists nxt, TileTables ntab, BinScratch sc,
-    GridState<T> g, StepParams<T> prm) {
+__device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur,
+                                         const TileTables &ctab, const BinLists &nxt, const TileTables &ntab,
+                                         const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm,
+                                         uint32_t blk, uint32_t nblk) {
     constexpr int K = DEG + 1;
     constexpr int TE = DIM == 3 ? 4 : 8;
     using R = VtRegion<DIM>;
@@ -370,7 +393,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_wav
     const T dt_inv_dx = prm.dt * g.inv_dx, gs = prm.dt * g.inv_dx;
     const uint32_t items = walk.nrec + dead_chunks(src.n, walk.live);
     const int64_t ss = src.s, ds = dst.s;
-    for (uint32_t r = blockIdx.x * 4 + (uint32_t)wv; r < items; r += gridDim.x * 4) {
+    for (uint32_t r = blk * 4 + (uint32_t)wv; r < items; r += nblk * 4) {
         if (r >= walk.nrec) {
             // dead particles are carried over unchanged
             const int64_t p = (int64_t)walk.live + (int64_t)(r - walk.nrec) * 64 + lane;
@@ -538,6 +561,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_wav
 }
 
 template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p(
+    Parts<T> src, Parts<T> dst, BinLists cur, TileTables ctab, BinLists nxt, TileTables ntab, BinScratch sc,
+    GridState<T> g, StepParams<T> prm) {
+    g2p_body<T, DIM, DEG>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p_batch(
+    const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const SceneDesc<T> &d = *b.d;
+    Parts<T> src = d.bufs[b.sp.src], dst = d.bufs[b.sp.src ^ 1];
+    if (!src.id || !dst.id) src.id = dst.id = nullptr;
+    g2p_body<T, DIM, DEG>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm, b.blk, b.nblk);
+}
+
+template <typename T, int DIM, int DEG>
+void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+}
+
+template <typename T, int DIM, int DEG>
 void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const TileTables &ctab,
                 const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const GridState<T> &g,
                 const StepParams<T> &prm, int64_t max_records, hipStream_t st) {
@@ -552,6 +597,10 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
 }
 
 #define APIC_G2P_INST(T, DIM, DEG)                                                                               \
+    template void launch_bin_keys_moved_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int,  \
+                                                           hipStream_t);                                          \
+    template void launch_g2p_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int,             \
+                                                hipStream_t);                                                     \
     template void launch_bin_keys_moved<T, DIM, DEG>(const Parts<T> &, const BinLists &, const TileTables &,     \
                                                      const GridState<T> &, const StepParams<T> &,                \
                                                      const BinLists &, const BinScratch &, int64_t, hipStream_t); \

@@ -61,15 +61,15 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, c
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_grid_update(BinLists cur, Slabs<T> slabs, GridState<T> g,
-                                                     StepParams<T> prm) {
+__device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g,
+                                                 const StepParams<T> &prm, uint32_t blk, uint32_t nblk) {
     const int lane = lane_id();
     const int64_t G = g.d.G;
     uint32_t ntiles, ncnt;
     const uint32_t npre = wave_bucket_prefix(cur.node_count, ntiles, ncnt);
     uint32_t bits = 0u;  // wave maximum so far of the bounds below
-    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (uint32_t i = wave; i < ntiles; i += gridDim.x * 4) {
+    const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
+    for (uint32_t i = wave; i < ntiles; i += nblk * 4) {
         uint32_t b, j;
         bucket_locate(i, npre, ncnt, b, j);
         const uint32_t tau = cur.node_list[(int64_t)b * cur.rcap + j];
@@ -107,6 +107,27 @@ __global__ __launch_bounds__(256) void k_grid_update(BinLists cur, Slabs<T> slab
     }
     bits = wave_max_u32(bits);
     if (lane == 0 && bits != 0u) atomicMax(g.vmax + (wave & (kVmaxSlots - 1)), bits);
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
+__global__ __launch_bounds__(256) void k_grid_update(BinLists cur, Slabs<T> slabs, GridState<T> g,
+                                                     StepParams<T> prm) {
+    grid_update_body<T, DIM, DEG, COMP>(cur, slabs, g, prm, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
+__global__ __launch_bounds__(256) void k_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
+                                                           int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const SceneDesc<T> &d = *b.d;
+    grid_update_body<T, DIM, DEG, COMP>(b.cur, d.slabs, d.g, d.prm, b.blk, b.nblk);
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
+void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_grid_update_batch<T, DIM, DEG, COMP>), dim3((unsigned)blocks), dim3(256), 0, st, descs,
+                       start, n, k);
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
@@ -236,6 +257,8 @@ void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState
 }
 
 #define APIC_GRID_INST(T, DIM, DEG, COMP)                                                                         \
+    template void launch_grid_update_batch<T, DIM, DEG, COMP>(const SceneDesc<T> *, const int32_t *, int, int, int, \
+                                                              hipStream_t);                                       \
     template void launch_grid_update<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &, \
                                                         const StepParams<T> &, int64_t, hipStream_t);            \
     template void launch_grid_export<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &, \

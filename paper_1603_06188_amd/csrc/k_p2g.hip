@@ -316,8 +316,9 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs,
-                                             GridState<T> g, StepParams<T> prm) {
+__device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur, const BinLists &nxt,
+                                         const TileTables &tab, const Slabs<T> &slabs, const GridState<T> &g,
+                                         const StepParams<T> &prm, uint32_t blk, uint32_t nblk) {
     using Gm = Geo<DIM, DEG>;
     using SL = SlabLds<DIM, DEG>;
     constexpr int K = Gm::K, RN = Gm::RN, NC = Gm::NC, LP = SL::PLANE;
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists 
     const int lane = lane_id();
     int lcoord[3] = {0, 0, 0};
     local_coords<DIM>(lane, lcoord);
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
+    if (blk == 0 && threadIdx.x < 64) {
         // the grid update that follows raises these bounds of max |vt|, and
         // the layout the following G2P builds starts from empty lists
         g.vmax[threadIdx.x] = 0u;
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists 
         if (threadIdx.x == 0) nxt.dead[0] = 0u;
     }
     const TileWalk walk = tile_walk(cur);
-    for (uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < walk.nrec; r += gridDim.x * 4) {
+    for (uint32_t r = blk * 4 + (threadIdx.x >> 6); r < walk.nrec; r += nblk * 4) {
         uint32_t start, cnt, maxc, kstart;
         const uint32_t t = tile_of_record(walk, r, cur, tab, start, cnt, maxc, kstart);
         int key[3] = {0, 0, 0};
@@ -394,6 +395,24 @@ __global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists 
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
+__global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs,
+                                             GridState<T> g, StepParams<T> prm) {
+    p2g_body<T, DIM, DEG, COMP>(P, cur, nxt, tab, slabs, g, prm, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
+__global__ __launch_bounds__(256) void k_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const SceneDesc<T> &d = *b.d;
+    p2g_body<T, DIM, DEG, COMP>(d.bufs[b.sp.src], b.cur, b.nxt, d.tab[b.sp.cur], d.slabs, d.g, d.prm, b.blk, b.nblk);
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
+void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_p2g_batch<T, DIM, DEG, COMP>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+}
+
+template <typename T, int DIM, int DEG, bool COMP>
 void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, const TileTables &tab,
                 const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm, int64_t max_records,
                 hipStream_t st) {
@@ -405,6 +424,10 @@ void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, con
 }
 
 #define APIC_P2G_INST(T, DIM, DEG)                                                                                \
+    template void launch_p2g_batch<T, DIM, DEG, false>(const SceneDesc<T> *, const int32_t *, int, int, int,        \
+                                                       hipStream_t);                                              \
+    template void launch_p2g_batch<T, DIM, DEG, true>(const SceneDesc<T> *, const int32_t *, int, int, int,         \
+                                                      hipStream_t);                                               \
     template void launch_p2g<T, DIM, DEG, false>(const Parts<T> &, const BinLists &, const BinLists &,           \
                                                  const TileTables &, const Slabs<T> &, const GridState<T> &,     \
                                                  const StepParams<T> &, int64_t, hipStream_t);                   \

@@ -206,6 +206,54 @@ def spheres3d(seed: int = 3, cells: int = 256, radius: float = 0.2,
                    mu=mu, lam=lam, dt=dt, steps=steps)
 
 
+def body3d(seed: int, n_target: Optional[int] = None, n_lo: float = 1e3, n_hi: float = 2e5,
+           precision: str = "fp32", degree: int = 2, dt: float = 1e-4, gravity: float = -9.8,
+           floor_band: int = 3) -> Scene:
+    """One small body of a batched workload: a box or a sphere at 8
+    particles per cell holding about n_target particles (default: drawn
+    log-uniformly in [n_lo, n_hi]), centred in the unit cube on a grid of
+    n = clamp(roundup_8(3 x body extent in cells), 32, 128) cells; neo-Hookean
+    with E log-uniform in [1e3, 1e5], nu = 0.3, rho = 1000; rigid velocity
+    v ~ N(0, 0.5^2) per component plus rotation omega ~ N(0, 2^2); gravity
+    along -z, sticky floor."""
+    rng = np.random.default_rng(seed)
+    if n_target is None:
+        n_target = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+    sphere = bool(rng.random() < 0.5)
+    body_cells = n_target / 8.0
+    if sphere:
+        extent = 2.0 * (3.0 * body_cells / (4.0 * np.pi)) ** (1.0 / 3.0)
+    else:
+        extent = body_cells ** (1.0 / 3.0)
+    cells = int(min(max(8 * int(np.ceil(3.0 * extent / 8.0)), 32), 128))
+    dx = 1.0 / cells
+    c = np.full(3, 0.5)
+    half = 0.5 * extent * dx
+    lo = np.floor((c - half) / dx).astype(int)
+    hi = np.ceil((c + half) / dx).astype(int)
+    x = _stratified(rng, lo, hi, 2, dx)
+    if sphere:
+        x = x[np.sum((x - c) ** 2, axis=1) < half ** 2]
+    else:
+        x = x[np.all(np.abs(x - c) < half, axis=1)]
+    n = x.shape[0]
+    w = rng.normal(0.0, 2.0, size=3)
+    v = rng.normal(0.0, 0.5, size=3)[None, :] + np.cross(np.broadcast_to(w, x.shape), x - c)
+    B = np.zeros((n, 3, 3))
+    F = np.tile(np.eye(3), (n, 1, 1))
+    m = np.full(n, 1000.0 * dx ** 3 / 8.0)
+    E = float(np.exp(rng.uniform(np.log(1e3), np.log(1e5))))
+    mu, lam = lame(E, 0.3)
+    return _finish("body3d", 3, degree, (cells,) * 3, dx, precision, x, v, B, F, m, rho0=1000.0, model=1,
+                   mu=mu, lam=lam, dt=dt, gravity=(0.0, 0.0, gravity), band=(0, 0, 0, 0, floor_band, 0),
+                   steps=50)
+
+
+def many_bodies(n_scenes: int = 512, seed: int = 4, **kw):
+    """The batched workload: body3d(seed + scene index) for every scene."""
+    return [body3d(seed + k, **kw) for k in range(n_scenes)]
+
+
 def random_particles(n: int, dim: int = 3, cells: int = 8, degree: int = 2, seed: int = 0,
                      precision: str = "fp64", margin: Optional[float] = None, model: int = 1,
                      E: float = 1e3, nu: float = 0.3, rho: float = 10.0, dt: float = 1e-3,
