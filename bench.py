@@ -18,6 +18,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -73,6 +74,50 @@ def cpu_baseline(scene, budget_s: float = 12.0, max_steps: int = 3):
     }
 
 
+def served(pool_size: int, duration: float, load: float, seed: int = 6):
+    """Config 5: Poisson arrivals at `load` x the saturated batched capacity,
+    replayed against the batch server and against sequential per-scene solves."""
+    from paper_1603_06188_amd import serve
+
+    pool = serve.Pool(serve.request_pool(pool_size, seed=5))
+    mean_n = sum(pool.particles(k) for k in range(len(pool))) / len(pool)
+    capacity = serve.saturated_rate(pool)                       # particle-updates/s
+    rate = load * capacity / (mean_n * 275.0)                   # requests/s (mean 275 steps)
+    trace = serve.poisson_trace(rate, duration, len(pool), seed=seed)
+    out = {"requests": len(trace), "rate_per_s": rate, "load": load, "capacity_updates_per_s": capacity,
+           "pool_bodies": len(pool), "mean_particles": mean_n, "trace_s": duration}
+    for name, server in (("batched", serve.BatchServer(pool)), ("sequential", serve.SequentialServer(pool))):
+        st = server.run([dataclasses.replace(r) for r in trace])
+        out[name] = {"p50_s": st.percentile(50), "p99_s": st.percentile(99), "mean_s": float(st.latencies.mean()),
+                     "throughput": st.throughput, "wall_s": st.wall}
+    return out
+
+
+def batched(n_scenes: int, steps: int):
+    """Config 4: n_scenes bodies stepped by apic_step_batch vs the per-scene loop."""
+    import torch
+
+    from paper_1603_06188_amd import binding as b
+    from paper_1603_06188_amd import scenes
+
+    hosts = scenes.many_bodies(n_scenes)
+    ds = [b.DeviceScene(h, compensated=True) for h in hosts]
+    batch = b.SceneBatch(ds)
+    batch.step(2)
+    batch.step_each(2)
+    torch.cuda.synchronize()
+    total = sum(h.n for h in hosts)
+    res = {"scenes": n_scenes, "particles": total, "steps": steps}
+    for name, fn in (("batched", batch.step), ("per_scene_loop", batch.step_each)):
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"value": total * steps / el, "ms_per_step": el / steps * 1e3}
+    res["speedup"] = res["batched"]["value"] / res["per_scene_loop"]["value"]
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +127,13 @@ def main(argv=None):
     ap.add_argument("--cells", type=int, default=128)
     ap.add_argument("--plain", action="store_true", help="uncompensated binary32 accumulation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["cube", "batch"], default="cube",
+                    help="cube: the 128^3 elastic cube (headline); batch: 512 bodies, batched vs per-scene loop")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-latency replay")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy three times (known bytes, for "
                          "scaling hardware byte counters)")
@@ -100,6 +152,18 @@ def main(argv=None):
     from paper_1603_06188_amd import scenes
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        res = batched(args.scenes, args.steps if args.steps != 100 else 20)
+        print(json.dumps({
+            "metric": "APIC particle-updates/s, many bodies, batched (one launch per phase) vs per-scene loop",
+            "value": res["batched"]["value"], "unit": "particle-updates/s", "n_gpus": 1, "steps": res["steps"],
+            "warmup": 2, "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{res['scenes']} bodies (box/sphere, 8 ppc, N log-uniform 1e3..2e5, grids "
+                                   f"32..128), quadratic, neo-Hookean, gravity, dt=1e-4, compensated f32",
+                       "particles": res["particles"]},
+            "per_scene_loop": res["per_scene_loop"], "speedup": res["speedup"]}), flush=True)
+        return 0
     if args.calibrate_copy:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -180,6 +244,10 @@ def main(argv=None):
             "traffic": None,
         },
     }
+    if not args.no_serve:
+        del ds
+        torch.cuda.empty_cache()
+        out["served"] = served(args.serve_pool, args.serve_seconds, args.serve_load)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out), flush=True)

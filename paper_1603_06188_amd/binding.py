@@ -236,7 +236,8 @@ class DeviceScene:
     Particle planes live in one tensor ``f`` of shape [planes, stride]:
     off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
 
-    def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True):
+    def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True,
+                 packed=None):
         self.host = scene
         self.dim = scene.dim
         self.precision = precision or scene.precision
@@ -249,7 +250,7 @@ class DeviceScene:
         self.f = torch.zeros((self.nplanes, cap), dtype=self.dtype, device=device)
         self.cell = torch.zeros(cap, dtype=torch.int32, device=device)
         self.id = torch.arange(cap, dtype=torch.int32, device=device) if with_id else None
-        self.upload(scene)
+        self.upload(scene, packed)
         g = ApicGridDesc()
         g.dim = d
         g.degree = scene.degree
@@ -294,17 +295,23 @@ class DeviceScene:
         p.mass = self._plane(2 * d + 2 * d * d)
         p.id = self.id.data_ptr() if self.id is not None else None
 
-    def upload(self, scene):
-        d = self.dim
+    @staticmethod
+    def pack(scene, dtype):
+        """Host tensors in the device layout: planes [2d+2d^2+1, n] and packed cells [n]."""
+        d, n = scene.dim, scene.n
+        planes = np.concatenate([scene.off.T, scene.v.T, scene.B.reshape(n, d * d).T, scene.F.reshape(n, d * d).T,
+                                 scene.m[None, :]], axis=0)
+        return (torch.from_numpy(np.ascontiguousarray(planes)).to(dtype),
+                torch.from_numpy(pack_cells(scene.cell).view(np.int32)))
+
+    def upload(self, scene, packed=None):
         n = scene.n
         if n > self.capacity:
             raise ValueError("scene larger than capacity")
         self.n = n
-        planes = np.concatenate([scene.off.T, scene.v.T, scene.B.reshape(n, d * d).T, scene.F.reshape(n, d * d).T,
-                                 scene.m[None, :]], axis=0)
-        host = torch.from_numpy(np.ascontiguousarray(planes)).to(self.dtype)
-        self.f[:, :n].copy_(host)
-        self.cell[:n].copy_(torch.from_numpy(pack_cells(scene.cell).view(np.int32)))
+        host, cells = packed if packed is not None else self.pack(scene, self.dtype)
+        self.f[:, :n].copy_(host, non_blocking=True)
+        self.cell[:n].copy_(cells, non_blocking=True)
         if self.id is not None:
             self.id[:n].copy_(torch.arange(n, dtype=torch.int32))
         if hasattr(self, "s"):
