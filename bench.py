@@ -48,6 +48,23 @@ def _ensure_built():
         build_library()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube128.txt")
+
+
+def measured_traffic(phase: str):
+    """HBM bytes per launch of the phase's kernel from the committed counter
+    summary, or None when there is none or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    from paper_1603_06188_amd import profile_traffic
+
+    summ = profile_traffic.read_summary(TRAFFIC_FILE)
+    if summ.get("source_sha256") != profile_traffic.source_hash():
+        return None
+    v = summ.get(f"k_{phase}_traffic_bytes")
+    return float(v) if v is not None else None
+
+
 def cpu_baseline(scene, budget_s: float = 12.0, max_steps: int = 3):
     """Time the FP64 oracle (single thread, as written) on the full particle
     set of the workload for as many steps as fit in about budget_s."""
@@ -289,7 +306,7 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom),
         },
     }
     if not args.no_serve:
