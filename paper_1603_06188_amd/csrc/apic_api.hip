@@ -42,7 +42,7 @@ int slab_nodes(int dim, int degree) {
 // Workspace layout for a grid and a particle capacity `cap`.
 // ---------------------------------------------------------------------------
 struct ListOff {
-    size_t tile_gen, slot, rec_count, rec_list, tot, dead, node_gen, node_count, node_list;
+    size_t tile_gen, slot, rec_count, rec_list, tot, dead;
 };
 
 struct TabOff {
@@ -114,9 +114,6 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         l.rec_list = take(LB * 4);
         l.tot = take((size_t)kBuckets * 4);
         l.dead = take(4);
-        l.node_gen = take(TT * 4);
-        l.node_count = take((size_t)kBuckets * 4);
-        l.node_list = take(LB * 4);
     }
     for (int k = 0; k < 2; ++k) {
         TabOff &t = L.tabs[k];
@@ -342,9 +339,6 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         b.rec_list = (uint32_t *)(w + o.rec_list);
         b.tot = (uint32_t *)(w + o.tot);
         b.dead = (uint32_t *)(w + o.dead);
-        b.node_gen = (uint32_t *)(w + o.node_gen);
-        b.node_count = (uint32_t *)(w + o.node_count);
-        b.node_list = (uint32_t *)(w + o.node_list);
         b.rcap = L.rcap;
     }
     for (int k = 0; k < 2; ++k) {
@@ -389,7 +383,6 @@ template <typename T>
 void begin_build(View<T> &v, SceneState &ss, int k, hipStream_t st) {
     if (ss.gen[k] == 0xFFFFFFFFu) {
         launch_fill<uint32_t>(v.lists[k].tile_gen, v.L.d.tiles, 0u, st);
-        launch_fill<uint32_t>(v.lists[k].node_gen, v.L.d.tiles, 0u, st);
         ss.gen[k] = 0u;
     }
     ss.gen[k] += 1u;
@@ -497,7 +490,7 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
         case Op::GridUpdate:
             if (ss.grid_meta < 0 || ss.grid_meta != ss.cur || !ss.binned)
                 return fail(APIC_E_INVAL, "apic_grid_update needs a preceding apic_p2g on the current particles");
-            launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.grid_meta], v.slabs, v.g, v.prm, v.L.d.tiles, st);
+            launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.grid_meta], v.slabs, v.g, v.prm, v.L.rc, st);
             ss.vt_valid = true;
             break;
         case Op::G2P:
@@ -558,7 +551,7 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
                                           v.g, v.prm, v.L.rc, st);
         });
         timed(APIC_PHASE_GRID_UPDATE, st, [&] {
-            launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.cur], v.slabs, v.g, v.prm, v.L.d.tiles, st);
+            launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.cur], v.slabs, v.g, v.prm, v.L.rc, st);
         });
         ss.grid_meta = ss.cur;
         g2p_rebin<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], ss.cur, false, st);
@@ -657,7 +650,6 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
             if (ss.gen[p] > 0xFFFFFFFFu - (uint32_t)n_steps - 2u) {
                 View<T> v = make_view<T>(&scenes[i], cap, ss);
                 launch_fill<uint32_t>(v.lists[p].tile_gen, v.L.d.tiles, 0u, st);
-                launch_fill<uint32_t>(v.lists[p].node_gen, v.L.d.tiles, 0u, st);
                 ss.gen[p] = 0u;
                 if (p == ss.cur) ss.binned = false;   // its tags are gone: bin again
                 if (p == ss.grid_meta) ss.grid_meta = -1;

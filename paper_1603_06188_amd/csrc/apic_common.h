@@ -19,8 +19,7 @@
 //   kMaxLevels particles is stored key by key instead).  Particles that
 //   cannot be binned (support outside the grid, non-finite state) follow all
 //   tiles ("dead" region).
-//   Lists.  Listed tiles and the node tiles the grid update visits are kept
-//   in kBuckets append lists (bucket = tile id mod kBuckets) so appends do
+//   Lists.  Listed tiles are kept in kBuckets append lists (bucket = tile id mod kBuckets) so appends do
 //   not contend on one counter; membership is a generation tag per tile, so
 //   nothing needs clearing between steps.  A tile's particles start at
 //   bucket_base[bucket] + off[tile], bucket_base being the exclusive prefix
@@ -67,9 +66,6 @@ struct BinLists {
     uint32_t *rec_list;    // [kBuckets * rcap] tile ids, bucket b from b * rcap
     uint32_t *tot;         // [kBuckets] particles per bucket
     uint32_t *dead;        // [1] dead particles
-    uint32_t *node_gen;    // [tiles] == gen: node tile listed for the grid update
-    uint32_t *node_count;  // [kBuckets]
-    uint32_t *node_list;   // [kBuckets * rcap] node tile ids, bucket b from b * rcap
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
 };
 

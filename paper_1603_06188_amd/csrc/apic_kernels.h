@@ -45,7 +45,7 @@ void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, con
 
 template <typename T, int DIM, int DEG, bool COMP>
 void launch_grid_update(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm,
-                        int64_t max_node_tiles, hipStream_t st);
+                        int64_t max_records, hipStream_t st);
 
 // New keys of the particles of layout `cur` after G2P (first pass of
 // apic_g2p): stayer counts per key, movers' keys and ranks, dead ranks.

@@ -19,7 +19,6 @@ __global__ void k_bin_reset(BinLists nxt) {
     if (t < kBuckets) {
         nxt.rec_count[t] = 0u;
         nxt.tot[t] = 0u;
-        nxt.node_count[t] = 0u;
     }
     if (t == 0) nxt.dead[0] = 0u;
 }
@@ -61,7 +60,7 @@ void launch_bin_keys_static(const Parts<T> &P, const GridDims &d, const BinLists
                        d, nxt, sc, flags);
 }
 
-// --- per listed tile: counts, prefix sums, level table, node tiles ------------------
+// --- per listed tile: counts, prefix sums, tile offset, level table ------------------
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const int lane = lane_id();
     uint32_t inc = x;
@@ -116,31 +115,6 @@ __device__ __forceinline__ void records_body(const BinLists &nxt, const TileTabl
             if ((uint32_t)lane < mx) {
                 tab.lvl_off[(int64_t)t * kMaxLevels + lane] = my_off;
                 tab.lvl_mask[(int64_t)t * kMaxLevels + lane] = my_mask;
-            }
-        }
-        // node tiles covered by this tile's slab: t + {0,1}^DIM
-        if (lane < (1 << DIM)) {
-            int tc[3] = {0, 0, 0};
-            tc[0] = (int)(t % (uint32_t)d.TN[0]);
-            if constexpr (DIM == 3) {
-                tc[1] = (int)((t / (uint32_t)d.TN[0]) % (uint32_t)d.TN[1]);
-                tc[2] = (int)(t / ((uint32_t)d.TN[0] * (uint32_t)d.TN[1]));
-            } else {
-                tc[1] = (int)(t / (uint32_t)d.TN[0]);
-            }
-            bool ok = true;
-            int64_t tau = 0, mul = 1;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                const int c2 = tc[a] + ((lane >> a) & 1);
-                ok = ok && c2 < d.TN[a];
-                tau += c2 * mul;
-                mul *= d.TN[a];
-            }
-            if (ok && nxt.node_gen[tau] != nxt.gen && atomicExch(nxt.node_gen + tau, nxt.gen) != nxt.gen) {
-                const uint32_t nb = bucket_of((uint32_t)tau);
-                const uint32_t idx = atomicAdd(nxt.node_count + nb, 1u);
-                nxt.node_list[(int64_t)nb * nxt.rcap + idx] = (uint32_t)tau;
             }
         }
     }

@@ -241,17 +241,29 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         stay[lane] = 0u;
         wave_lds_sync();
         uint32_t queued = 0, c0 = 0;
+        // cell and offset of the current chunk; the next chunk's are loaded
+        // while this one is classified
+        uint32_t cell = 0;
+        T off[DIM];
+        if ((uint32_t)lane < total) {
+            cell = P.cell[start + lane];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) off[a] = P.off[a * P.s + start + lane];
+        }
         for (;;) {
             if (c0 < total) {
                 const uint32_t i = c0 + (uint32_t)lane;
+                uint32_t cell_n = 0;
+                T off_n[DIM];
+                if (i + 64 < total) {
+                    cell_n = P.cell[start + i + 64];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) off_n[a] = P.off[a * P.s + start + i + 64];
+                }
                 bool near = false;
                 if (i < total) {
-                    const uint32_t q = start + i;
                     int ci[3] = {0, 0, 0};
-                    unpack_cell<DIM>(P.cell[q], ci);
-                    T off[DIM];
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) off[a] = P.off[a * P.s + q];
+                    unpack_cell<DIM>(cell, ci);
                     if (keeps_key<T, DIM, DEG>(off, reach))
                         atomicAdd(stay + local_key<T, DIM, DEG>(ci, off), 1u);
                     else
@@ -260,6 +272,9 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
                 const uint64_t nm = ballot(near);
                 if (near) queue[queued + (uint32_t)popc64(nm & lanes_below(lane))] = start + i;
                 queued += (uint32_t)popc64(nm);
+                cell = cell_n;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) off[a] = off_n[a];
             }
             c0 += 64;
             const bool read_all = c0 >= total;
@@ -369,6 +384,27 @@ constexpr int g2p_min_waves() {
     return (sizeof(T) == 4 && DEG == 2) ? 4 : 1;
 }
 
+// What G2P reads of a particle (loaded one chunk ahead of its use).
+template <typename T, int DIM>
+struct G2PRaw {
+    uint32_t cell;
+    int32_t id;
+    T m, off[DIM], F[DIM * DIM];
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ void g2p_load(const Parts<T> &src, uint32_t p, G2PRaw<T, DIM> &r) {
+    const int64_t ss = src.s;
+    const uint32_t pb = p * (uint32_t)sizeof(T);
+    r.cell = src.cell[p];
+    r.m = plane_at(src.m, pb);
+    r.id = src.id ? plane_at(src.id, p * 4u) : 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) r.off[a] = plane_at(src.off + a * ss, pb);
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) r.F[k] = plane_at(src.F + k * ss, pb);
+}
+
 // One wavefront per listed tile walks the tile's particles in chunks of 64
 // (every lane busy).  A stayer's rank in its key continues from the key's
 // mover count (LDS counter); a mover takes the key and rank of pass 1.
@@ -424,17 +460,21 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         rankc[lane] = ntab.kmov[t * 64 + (uint32_t)lane];
         const uint32_t tbase = bases[bucket_of(t)];
         wave_lds_sync();
+        G2PRaw<T, DIM> raw;
+        if ((uint32_t)lane < total) g2p_load<T, DIM>(src, start + (uint32_t)lane, raw);
         for (uint32_t c0 = 0; c0 < total; c0 += 64) {
             const uint32_t i = c0 + (uint32_t)lane;
+            // the next chunk is in flight while this one is computed
+            G2PRaw<T, DIM> raw_n;
+            if (i + 64 < total) g2p_load<T, DIM>(src, start + i + 64, raw_n);
             if (i < total) {
                 const uint32_t p = start + i;
-                const uint32_t pb = p * (uint32_t)sizeof(T);
                 int ci[3] = {0, 0, 0}, cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
-                unpack_cell<DIM>(src.cell[p], ci);
+                unpack_cell<DIM>(raw.cell, ci);
                 T off[DIM], wf[DIM][K], on[DIM], vn[DIM], Bc[DIM * DIM], Fn[DIM * DIM];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    off[a] = plane_at(src.off + a * ss, pb);
+                    off[a] = raw.off[a];
                     lk[a] = axis_w_fixed<T, DEG>(ci[a], off[a], wf[a]) - origin[a];
                 }
                 // One sweep over the support nodes (c, b, a) from LDS: the
@@ -505,7 +545,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 // F <- (I + dt grad v) F, grad v = Gc / dx
                 T F[DIM * DIM];
 #pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) F[k] = plane_at(src.F + k * ss, pb);
+                for (int k = 0; k < DIM * DIM; ++k) F[k] = raw.F[k];
 #pragma unroll
                 for (int rr = 0; rr < DIM; ++rr)
 #pragma unroll
@@ -541,8 +581,8 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 for (int a = 0; a < DIM; ++a) cn[a] = cn[a] < 0 ? 0 : (cn[a] > g.d.n[a] - 1 ? g.d.n[a] - 1 : cn[a]);
                 const uint32_t qb = q * (uint32_t)sizeof(T), q4 = q * 4u;
                 plane_at(dst.cell, q4) = pack_cell<DIM>(cn);
-                plane_at(dst.m, qb) = plane_at(src.m, pb);
-                if (src.id) plane_at(dst.id, q4) = plane_at(src.id, p * 4u);
+                plane_at(dst.m, qb) = raw.m;
+                if (src.id) plane_at(dst.id, q4) = raw.id;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
                     plane_at(dst.off + a * ds, qb) = on[a];
@@ -554,6 +594,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                     plane_at(dst.F + k * ds, qb) = Fn[k];
                 }
             }
+            raw = raw_n;
         }
         wave_lds_sync();
     }

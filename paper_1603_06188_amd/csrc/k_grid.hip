@@ -60,50 +60,128 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, c
     for (int k = 0; k < NC; ++k) out[k] = COMP ? hi[k] + lo[k] : hi[k];
 }
 
+// Node tile tau is updated by exactly one wavefront: the one of the first
+// listed key tile, in the order e = 0, 1, ..., 2^DIM - 1, among the key tiles
+// tau - e whose slabs cover it.  In the interior every tile owns itself.
+// One load of 64 lanes (lane = corner c * 2^DIM + e) fetches the membership
+// tags and slab records of all key tiles around all 2^DIM candidate node
+// tiles t + c; they decide ownership and feed the slab gathers.
 template <typename T, int DIM, int DEG, bool COMP>
 __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g,
                                                  const StepParams<T> &prm, uint32_t blk, uint32_t nblk) {
+    using Gm = Geo<DIM, DEG>;
+    constexpr int TE = Gm::TE, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC, NCOR = 1 << DIM;
     const int lane = lane_id();
     const int64_t G = g.d.G;
-    uint32_t ntiles, ncnt;
-    const uint32_t npre = wave_bucket_prefix(cur.node_count, ntiles, ncnt);
+    uint32_t nrec, rcnt;
+    const uint32_t rpre = wave_bucket_prefix(cur.rec_count, nrec, rcnt);
     uint32_t bits = 0u;  // wave maximum so far of the bounds below
     const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
-    for (uint32_t i = wave; i < ntiles; i += nblk * 4) {
+    int lc[3] = {0, 0, 0};
+    local_coords<DIM>(lane, lc);
+    const int my_c = lane / NCOR, my_e = lane % NCOR;
+    for (uint32_t r = wave; r < nrec; r += nblk * 4) {
         uint32_t b, j;
-        bucket_locate(i, npre, ncnt, b, j);
-        const uint32_t tau = cur.node_list[(int64_t)b * cur.rcap + j];
-        int nc[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
-        tile_origin<DIM>(tau, g.d.TN, nc);
-        local_coords<DIM>(lane, lc);
-        bool valid = true, sticky = false;
+        bucket_locate(r, rpre, rcnt, b, j);
+        const uint32_t t = cur.rec_list[(int64_t)b * cur.rcap + j];
+        int tc[3] = {0, 0, 0};
+        tc[0] = (int)(t % (uint32_t)g.d.TN[0]);
+        if constexpr (DIM == 3) {
+            tc[1] = (int)((t / (uint32_t)g.d.TN[0]) % (uint32_t)g.d.TN[1]);
+            tc[2] = (int)(t / ((uint32_t)g.d.TN[0] * (uint32_t)g.d.TN[1]));
+        } else {
+            tc[1] = (int)(t / (uint32_t)g.d.TN[0]);
+        }
+        // lane (c, e): key tile (t + c) - e
+        bool node_in = my_c < NCOR, key_in = my_c < NCOR;
+        int64_t k = 0, mul = 1;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            nc[a] += lc[a];
-            valid = valid && nc[a] < g.d.N[a];
-            sticky = sticky || nc[a] < prm.band[2 * a] || nc[a] > g.d.n[a] - prm.band[2 * a + 1];
+            const int nt = tc[a] + ((my_c >> a) & 1);
+            const int kt = nt - ((my_e >> a) & 1);
+            node_in = node_in && nt < g.d.TN[a];
+            key_in = key_in && nt < g.d.TN[a] && kt >= 0;
+            k += (int64_t)kt * mul;
+            mul *= g.d.TN[a];
         }
-        T mm[1 + DIM];
-#pragma unroll
-        for (int k = 0; k <= DIM; ++k) mm[k] = T(0);
-        if (valid) gather_node<T, DIM, DEG, COMP>(nc, cur, slabs, g.d, mm);
-        const bool live = valid && mm[0] > T(0) && !sticky;
-        const T inv_m = live ? T(1) / mm[0] : T(0);
-        const int64_t node = (int64_t)tau * 64 + lane;
-        float vabs = 0.f;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const T vt = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : T(0);
-            g.vt[a * G + node] = vt;
-            // binary32 value not below |vt| (NaN propagates as the largest bits)
-            const T va = vt < T(0) ? -vt : vt;
-            float f = (float)va;
-            if ((T)f < va) f = __uint_as_float(__float_as_uint(f) + 1u);  // next binary32 up
-            vabs = (f > vabs || f != f) ? f : vabs;
+        uint32_t rec = 0u;
+        bool listed = false;
+        if (key_in) {
+            listed = cur.tile_gen[k] == cur.gen;
+            rec = cur.slot[k];
         }
-        // non-negative binary32 values order like their bit patterns
-        const uint32_t mine = __float_as_uint(vabs);
-        bits = mine > bits ? mine : bits;
+        const uint64_t lmask = ballot(listed);
+        const uint64_t nmask = ballot(node_in && my_e == 0);
+        for (int c = 0; c < NCOR; ++c) {
+            const uint32_t lst = (uint32_t)(lmask >> (c * NCOR)) & ((1u << NCOR) - 1u);
+            // owned: node tile inside, and no listed key tile before e = c
+            if (!((nmask >> (c * NCOR)) & 1ull) || (lst & ((1u << c) - 1u)) != 0u) continue;
+            int nc[3] = {0, 0, 0};
+            int64_t tau = 0, tmul = 1;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const int ta = tc[a] + ((c >> a) & 1);
+                tau += (int64_t)ta * tmul;
+                tmul *= g.d.TN[a];
+                nc[a] = ta * TE + lc[a];
+            }
+            bool valid = true, sticky = false;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                valid = valid && nc[a] < g.d.N[a];
+                sticky = sticky || nc[a] < prm.band[2 * a] || nc[a] > g.d.n[a] - prm.band[2 * a + 1];
+            }
+            // sum of the covering slabs, e in increasing order
+            T hi[NC], lo[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) hi[q] = lo[q] = T(0);
+#pragma unroll
+            for (int e = 0; e < NCOR; ++e) {
+                const uint32_t srec = __shfl(rec, c * NCOR + e, 64);
+                if (!((lst >> e) & 1u)) continue;
+                int loc[3] = {0, 0, 0};
+                bool ok = valid;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    loc[a] = lc[a] + ((e >> a) & 1) * TE;
+                    ok = ok && loc[a] < RE;
+                }
+                if (!ok) continue;
+                const int idx = DIM == 3 ? loc[0] + RE * (loc[1] + RE * loc[2]) : loc[0] + RE * loc[1];
+                const T *sp = slabs.v + (int64_t)srec * slabs.stride;
+#pragma unroll
+                for (int q = 0; q < NC; ++q) {
+                    const T x = sp[q * RN + idx];
+                    if constexpr (COMP) {
+                        const T sum = hi[q] + x;
+                        lo[q] += two_sum_err(hi[q], x, sum) + sp[(NC + q) * RN + idx];
+                        hi[q] = sum;
+                    } else {
+                        hi[q] += x;
+                    }
+                }
+            }
+            T mm[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) mm[q] = COMP ? hi[q] + lo[q] : hi[q];
+            const bool live = valid && mm[0] > T(0) && !sticky;
+            const T inv_m = live ? T(1) / mm[0] : T(0);
+            const int64_t node = tau * 64 + lane;
+            float vabs = 0.f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const T vt = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : T(0);
+                g.vt[a * G + node] = vt;
+                // binary32 value not below |vt| (NaN propagates as the largest bits)
+                const T va = vt < T(0) ? -vt : vt;
+                float f = (float)va;
+                if ((T)f < va) f = __uint_as_float(__float_as_uint(f) + 1u);  // next binary32 up
+                vabs = (f > vabs || f != f) ? f : vabs;
+            }
+            // non-negative binary32 values order like their bit patterns
+            const uint32_t mine = __float_as_uint(vabs);
+            bits = mine > bits ? mine : bits;
+        }
     }
     bits = wave_max_u32(bits);
     if (lane == 0 && bits != 0u) atomicMax(g.vmax + (wave & (kVmaxSlots - 1)), bits);
@@ -132,8 +210,8 @@ void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, i
 
 template <typename T, int DIM, int DEG, bool COMP>
 void launch_grid_update(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm,
-                        int64_t max_node_tiles, hipStream_t st) {
-    const int blocks = blocks_for(max_node_tiles, 4, 8192);
+                        int64_t max_records, hipStream_t st) {
+    const int blocks = blocks_for(max_records, 4, 4096);
     hipLaunchKernelGGL((k_grid_update<T, DIM, DEG, COMP>), dim3(blocks), dim3(256), 0, st, cur, slabs, g, prm);
 }
 

@@ -336,7 +336,6 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
         g.vmax[threadIdx.x] = 0u;
         nxt.rec_count[threadIdx.x] = 0u;
         nxt.tot[threadIdx.x] = 0u;
-        nxt.node_count[threadIdx.x] = 0u;
         if (threadIdx.x == 0) nxt.dead[0] = 0u;
     }
     const TileWalk walk = tile_walk(cur);
