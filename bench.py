@@ -8,9 +8,10 @@ compensated grid accumulation.  Inputs are seeded and synthetic and resident
 in HBM before the timed region.
 
 One step = (re-sort every --sort-every steps) + P2G + grid update + G2P,
-each through the C ABI on torch's current stream.  HIP events bracket every
-phase inside the timed region; the dominant phase's average duration gives
-the roofline figure.  The FP64 CPU oracle is timed on a bounded sample of
+each through the C ABI on torch's current stream.  The timed region runs
+without instrumentation; the same steps are then repeated with HIP events
+bracketing every phase, and the dominant phase's average duration gives the
+roofline figure.  The FP64 CPU oracle is timed on a bounded sample of
 the same workload as the CPU baseline.
 
 Prints one JSON line.
@@ -251,18 +252,25 @@ def main(argv=None):
     ds.clear_flags()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps in one apic_step call; the library brackets
-    # every phase with HIP events on this stream
-    b.apic_timing_enable(True)
-    b.apic_timing_read()
+    # timed region: K whole steps in one apic_step call, no instrumentation
+    # (HIP events between phases add ~10 % to the wall time)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ds.step(args.steps, args.sort_every)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    flags = ds.flags()
+    # the same K steps again from the same state, the library bracketing every
+    # phase with HIP events on this stream: per-kernel durations for the roofline
+    ds.upload(scene)
+    ds.clear_flags()
+    torch.cuda.synchronize()
+    b.apic_timing_enable(True)
+    b.apic_timing_read()
+    ds.step(args.steps, args.sort_every)
+    torch.cuda.synchronize()
     timing = b.apic_timing_read()
     b.apic_timing_enable(False)
-    flags = ds.flags()
     phases = list(timing)
     dur = {p: timing[p][1] for p in phases}
 

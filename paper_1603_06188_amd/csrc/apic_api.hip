@@ -42,7 +42,7 @@ int slab_nodes(int dim, int degree) {
 // Workspace layout for a grid and a particle capacity `cap`.
 // ---------------------------------------------------------------------------
 struct ListOff {
-    size_t tile_gen, slot, rec_count, rec_list, tot, dead;
+    size_t tile_gen, slot, rec_count, rec_list, tot, rpre, bpre, dead;
 };
 
 struct TabOff {
@@ -113,6 +113,8 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         l.rec_count = take((size_t)kBuckets * 4);
         l.rec_list = take(LB * 4);
         l.tot = take((size_t)kBuckets * 4);
+        l.rpre = take((size_t)(kBuckets + 1) * 4);
+        l.bpre = take((size_t)(kBuckets + 1) * 4);
         l.dead = take(4);
     }
     for (int k = 0; k < 2; ++k) {
@@ -338,6 +340,8 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         b.rec_count = (uint32_t *)(w + o.rec_count);
         b.rec_list = (uint32_t *)(w + o.rec_list);
         b.tot = (uint32_t *)(w + o.tot);
+        b.rpre = (uint32_t *)(w + o.rpre);
+        b.bpre = (uint32_t *)(w + o.bpre);
         b.dead = (uint32_t *)(w + o.dead);
         b.rcap = L.rcap;
     }
@@ -437,6 +441,7 @@ void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> 
     launch_bin_reset(v.lists[nxt], st);
     launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, st);
     launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
+    launch_bin_finalize(v.lists[nxt], st);
     launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab[nxt], v.sc, st);
 }
 
@@ -453,6 +458,7 @@ void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &
         launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
                                            st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
+        launch_bin_finalize(v.lists[nxt], st);
     });
     timed(APIC_PHASE_G2P, st, [&] {
         launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
@@ -640,7 +646,7 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
     std::vector<SceneDesc<T>> descs((size_t)n);
     std::vector<int32_t> starts((size_t)BK_COUNT * (size_t)(n + 1));
     std::vector<SceneState *> states((size_t)n);
-    int32_t total[BK_COUNT] = {0, 0, 0, 0, 0, 0};
+    int32_t total[BK_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     for (int32_t i = 0; i < n; ++i) {
         int64_t cap = 0;
         (void)check_scene(&scenes[i], &cap);
@@ -681,7 +687,7 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         states[(size_t)i] = &ss;
         const int64_t np = scenes[i].p.n;
         const int share[BK_COUNT] = {share_blocks(np, 4096), share_blocks(np, 8192), share_blocks(np, 2048),
-                                     share_blocks(np, 4096), share_blocks(np, 4096), share_blocks(np, 4096)};
+                                     share_blocks(np, 1024), share_blocks(np, 4096), share_blocks(np, 4096), 1};
         for (int k = 0; k < BK_COUNT; ++k) {
             starts[(size_t)k * (n + 1) + i] = total[k];
             total[k] += share[k];
@@ -732,6 +738,7 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         timed(APIC_PHASE_BIN, st, [&] {
             launch_bin_keys_moved_batch<T, DIM, DEG>(dd, start_of(BK_KEYS), n, k, total[BK_KEYS], st);
             launch_bin_records_batch<T, DIM>(dd, start_of(BK_RECORDS), n, k, total[BK_RECORDS], st);
+            launch_bin_finalize_batch<T>(dd, start_of(BK_FINAL), n, k, total[BK_FINAL], st);
         });
         timed(APIC_PHASE_G2P, st,
               [&] { launch_g2p_batch<T, DIM, DEG>(dd, start_of(BK_G2P), n, k, total[BK_G2P], st); });

@@ -8,18 +8,43 @@ namespace apic {
 
 __device__ __forceinline__ uint32_t bucket_of(uint32_t tile) { return tile & (kBuckets - 1); }
 
-// Lane b receives the exclusive prefix of v[0..kBuckets) at b; `total` the sum.
-__device__ __forceinline__ uint32_t wave_bucket_prefix(const uint32_t *v, uint32_t &total, uint32_t &mine) {
-    const int lane = lane_id();
-    mine = v[lane];
-    uint32_t inc = mine;
+// Block-wide (every thread of a 256-thread block must call): exclusive
+// prefix sums of the per-bucket counts v[0..kBuckets) into the LDS table
+// pre[0..kBuckets); returns the total.  Thread i owns buckets [4i, 4i + 4);
+// `part` is LDS scratch of 4 words.
+__device__ __forceinline__ uint32_t block_bucket_prefix(const uint32_t *v, uint32_t *pre, uint32_t *part) {
+    static_assert(kBuckets == 4 * 256, "one uint4 of buckets per thread");
+    const int tid = (int)threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint4 q = ((const uint4 *)v)[tid];
+    const uint32_t own = q.x + q.y + q.z + q.w;
+    uint32_t inc = own;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(inc, o, 64);
         if (lane >= o) inc += y;
     }
-    total = __shfl(inc, 63, 64);
-    return inc - mine;
+    if (lane == 63) part[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) before += k < w ? part[k] : 0u;
+    const uint32_t total = part[0] + part[1] + part[2] + part[3];
+    const uint32_t e = before + inc - own;
+    pre[4 * tid + 0] = e;
+    pre[4 * tid + 1] = e + q.x;
+    pre[4 * tid + 2] = e + q.x + q.y;
+    pre[4 * tid + 3] = e + q.x + q.y + q.z;
+    __syncthreads();
+    return total;
+}
+
+// Bucket of list index r (r below the table's total): the last bucket whose
+// exclusive prefix is <= r (it holds r).  Wave-wide, r wave-uniform.
+__device__ __forceinline__ uint32_t bucket_find(const uint32_t *pre, uint32_t r) {
+    const int lane = lane_id();
+    const int grp = popc64(ballot(pre[16 * lane] <= r)) - 1;
+    const uint64_t m = ballot(lane < 16 && pre[16 * grp + lane] <= r);
+    return (uint32_t)(16 * grp + popc64(m) - 1);
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
@@ -29,14 +54,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
         x = x > y ? x : y;
     }
     return x;
-}
-
-// Index r in [0, total) of a bucketed list -> (bucket, position in bucket),
-// given every lane's exclusive prefix `pre` and count `cnt` of bucket = lane.
-__device__ __forceinline__ void bucket_locate(uint32_t r, uint32_t pre, uint32_t cnt, uint32_t &bucket,
-                                              uint32_t &j) {
-    bucket = (uint32_t)popc64(ballot(pre + cnt <= r));
-    j = r - __shfl(pre, (int)bucket, 64);
 }
 
 // True for exactly one lane among the active lanes holding each value of t.
@@ -53,10 +70,9 @@ __device__ __forceinline__ bool first_lane_of_value(uint32_t t, bool active) {
     return leader;
 }
 
-// Base of the bucket of `key` from the per-bucket bases held by lane = bucket
-// (`bbase`).  Wave-wide: call with all lanes.
-__device__ __forceinline__ uint32_t bucket_base_of(uint32_t key, uint32_t bbase) {
-    return __shfl(bbase, (int)bucket_of(key == kDeadKey ? 0u : key >> 6), 64);
+// Base of the bucket of `key` from a block table of bucket bases.
+__device__ __forceinline__ uint32_t bucket_base_of(uint32_t key, const uint32_t *bases) {
+    return key == kDeadKey ? 0u : bases[bucket_of(key >> 6)];
 }
 
 // Position of particle (key, rank) in the layout described by `tab`, given
@@ -92,28 +108,29 @@ __device__ __forceinline__ int64_t particle_at(uint32_t start, uint32_t kstart, 
                                        : (int64_t)start + level + (uint32_t)popc64(mask & lanes_below(lane));
 }
 
-// Listed tiles of a layout, enumerated as records r = 0, 1, ... in bucket
-// order, and the bases of its particle buckets.  Wave-wide.
+// Listed tiles of a finished layout, enumerated as records r = 0, 1, ... in
+// bucket order, with the bases of its particle buckets (prefix tables written
+// once per layout by the finalize pass).
 struct TileWalk {
-    uint32_t rpre, rcnt, nrec;   // lane = bucket: record prefix and count; total records
-    uint32_t bbase, live;        // lane = bucket: particle base; live particles
+    const uint32_t *rpre, *bbase;  // [kBuckets] record prefix, particle base per bucket
+    uint32_t nrec, live;           // records, live particles
 };
 
 __device__ __forceinline__ TileWalk tile_walk(const BinLists &lists) {
     TileWalk w;
-    uint32_t mine;
-    w.rpre = wave_bucket_prefix(lists.rec_count, w.nrec, w.rcnt);
-    w.bbase = wave_bucket_prefix(lists.tot, w.live, mine);
+    w.rpre = lists.rpre;
+    w.bbase = lists.bpre;
+    w.nrec = lists.rpre[kBuckets];
+    w.live = lists.bpre[kBuckets];
     return w;
 }
 
 // Record r of the walk: tile id, first particle and particle count.
 __device__ __forceinline__ uint32_t tile_range(const TileWalk &w, uint32_t r, const BinLists &lists,
                                                const TileTables &tab, uint32_t &start, uint32_t &total) {
-    uint32_t b, j;
-    bucket_locate(r, w.rpre, w.rcnt, b, j);
-    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + j];
-    start = __shfl(w.bbase, (int)b, 64) + tab.off[t];
+    const uint32_t b = bucket_find(w.rpre, r);
+    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + (r - w.rpre[b])];
+    start = w.bbase[b] + tab.off[t];
     total = tab.tcount[t];
     return t;
 }
@@ -124,10 +141,9 @@ __device__ __forceinline__ uint32_t tile_of_record(const TileWalk &w, uint32_t r
                                                    const TileTables &tab, uint32_t &start, uint32_t &cnt,
                                                    uint32_t &maxc, uint32_t &kstart) {
     const int lane = lane_id();
-    uint32_t b, j;
-    bucket_locate(r, w.rpre, w.rcnt, b, j);
-    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + j];
-    start = __shfl(w.bbase, (int)b, 64) + tab.off[t];
+    const uint32_t b = bucket_find(w.rpre, r);
+    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + (r - w.rpre[b])];
+    start = w.bbase[b] + tab.off[t];
     cnt = tab.kcount[(int64_t)t * 64 + lane];
     maxc = tab.maxc[t];
     kstart = maxc > (uint32_t)kMaxLevels ? start + tab.kprefix[(int64_t)t * 64 + lane] : 0u;

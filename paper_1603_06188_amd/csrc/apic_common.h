@@ -35,9 +35,9 @@
 
 namespace apic {
 
-constexpr int kBuckets = 64;
+constexpr int kBuckets = 1024;   // 4 per thread of a 256-thread block
 constexpr int kMaxLevels = 32;
-constexpr int kVmaxSlots = 64;
+constexpr int kVmaxSlots = 1024;
 
 struct GridDims {
     int dim, deg;
@@ -65,6 +65,8 @@ struct BinLists {
     uint32_t *rec_count;   // [kBuckets] listed tiles per bucket
     uint32_t *rec_list;    // [kBuckets * rcap] tile ids, bucket b from b * rcap
     uint32_t *tot;         // [kBuckets] particles per bucket
+    uint32_t *rpre;        // [kBuckets + 1] exclusive prefix of rec_count; [kBuckets] = records
+    uint32_t *bpre;        // [kBuckets + 1] exclusive prefix of tot; [kBuckets] = live particles
     uint32_t *dead;        // [1] dead particles
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
 };
@@ -136,7 +138,7 @@ struct SceneDesc {
 // Kernels of a batched step; per kind, scene s owns blocks
 // [start[s], start[s + 1]) of the launch.
 enum BatchKernel : int { BK_P2G = 0, BK_GRID = 1, BK_KEYS = 2, BK_RECORDS = 3, BK_G2P = 4, BK_COPY = 5,
-                         BK_COUNT = 6 };
+                         BK_FINAL = 6, BK_COUNT = 7 };
 
 // Layout parities and generations at step k of a batched call: step k
 // reads parity (cur0 + k) & 1 and builds the other one; the j-th build of a

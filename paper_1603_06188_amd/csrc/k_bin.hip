@@ -15,16 +15,15 @@ static inline int blocks_for(int64_t work, int threads, int cap) {
 
 // --- counters of a layout about to be built ---------------------------------------
 __global__ void k_bin_reset(BinLists nxt) {
-    const int t = threadIdx.x;
-    if (t < kBuckets) {
+    for (int t = (int)threadIdx.x; t < kBuckets; t += (int)blockDim.x) {
         nxt.rec_count[t] = 0u;
         nxt.tot[t] = 0u;
     }
-    if (t == 0) nxt.dead[0] = 0u;
+    if (threadIdx.x == 0) nxt.dead[0] = 0u;
 }
 
 void launch_bin_reset(const BinLists &nxt, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_reset, dim3(1), dim3(64), 0, st, nxt);
+    hipLaunchKernelGGL(k_bin_reset, dim3(1), dim3(256), 0, st, nxt);
 }
 
 // --- keys of particles at their current position (apic_sort); every particle
@@ -76,13 +75,12 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) 
 template <int DIM>
 __device__ __forceinline__ void records_body(const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
                                              const GridDims &d, uint32_t blk, uint32_t nblk) {
+    __shared__ uint32_t rpre[kBuckets + 4];
     const int lane = lane_id();
-    uint32_t total_recs, cnt;
-    const uint32_t pre = wave_bucket_prefix(nxt.rec_count, total_recs, cnt);
+    const uint32_t total_recs = block_bucket_prefix(nxt.rec_count, rpre, rpre + kBuckets);
     for (uint32_t r = blk * 4 + (threadIdx.x >> 6); r < total_recs; r += nblk * 4) {
-        uint32_t b, j;
-        bucket_locate(r, pre, cnt, b, j);
-        const uint32_t t = nxt.rec_list[(int64_t)b * nxt.rcap + j];
+        const uint32_t b = bucket_find(rpre, r);
+        const uint32_t t = nxt.rec_list[(int64_t)b * nxt.rcap + (r - rpre[b])];
         const int64_t key = (int64_t)t * 64 + lane;
         const uint32_t mov = sc.key_count[key];
         const uint32_t c = mov + sc.scount[key];
@@ -170,10 +168,46 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
     hipLaunchKernelGGL((k_copy_back_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
 }
 
+// --- prefix tables of a finished layout (one block) ----------------------------------
+__device__ __forceinline__ void finalize_body(const BinLists &nxt) {
+    __shared__ uint32_t tmp[kBuckets + 8];
+    const uint32_t nrec = block_bucket_prefix(nxt.rec_count, tmp, tmp + kBuckets);
+    for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) nxt.rpre[i] = tmp[i];
+    __syncthreads();
+    const uint32_t live = block_bucket_prefix(nxt.tot, tmp, tmp + kBuckets + 4);
+    for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) nxt.bpre[i] = tmp[i];
+    if (threadIdx.x == 0) {
+        nxt.rpre[kBuckets] = nrec;
+        nxt.bpre[kBuckets] = live;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt) { finalize_body(nxt); }
+
+void launch_bin_finalize(const BinLists &nxt, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, st, nxt);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
+                                                            int k) {
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    finalize_body(b.nxt);
+}
+
+template <typename T>
+void launch_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_finalize_batch<T>, dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+}
+template void launch_bin_finalize_batch<float>(const SceneDesc<float> *, const int32_t *, int, int, int, hipStream_t);
+template void launch_bin_finalize_batch<double>(const SceneDesc<double> *, const int32_t *, int, int, int,
+                                                hipStream_t);
+
 template <int DIM>
 void launch_bin_records(const GridDims &d, const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
                         int64_t max_records, hipStream_t st) {
-    hipLaunchKernelGGL((k_bin_records<DIM>), dim3(blocks_for(max_records, 4, 4096)), dim3(256), 0, st, nxt, tab, sc,
+    hipLaunchKernelGGL((k_bin_records<DIM>), dim3(blocks_for(max_records, 4, 1024)), dim3(256), 0, st, nxt, tab, sc,
                        d);
 }
 
@@ -182,14 +216,11 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_bin_scatter_copy(Parts<T> src, Parts<T> dst, BinLists nxt, TileTables tab,
                                                           BinScratch sc) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = p < src.n;
-    uint32_t live, bmine;
-    const uint32_t bbase = wave_bucket_prefix(nxt.tot, live, bmine);
-    const uint32_t key = active ? sc.pkey[p] : kDeadKey;
-    const uint32_t rank = active ? sc.prank[p] : 0u;
-    const uint32_t base = bucket_base_of(key, bbase);
-    const int64_t q = bin_destination(key, rank, tab, base, live);
-    if (!active) return;
+    if (p >= src.n) return;
+    const uint32_t live = nxt.bpre[kBuckets];
+    const uint32_t key = sc.pkey[p];
+    const uint32_t rank = sc.prank[p];
+    const int64_t q = bin_destination(key, rank, tab, bucket_base_of(key, nxt.bpre), live);
     dst.cell[q] = src.cell[p];
     dst.m[q] = src.m[p];
     if (src.id) dst.id[q] = src.id[p];

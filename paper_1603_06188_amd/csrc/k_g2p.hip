@@ -132,7 +132,17 @@ __device__ __forceinline__ void move_position(const int *ci, const T *off, const
 
 // Bound of max_i |vt_i| over the slots the grid update raised (wave-wide).
 __device__ __forceinline__ float wave_vmax(const uint32_t *slots) {
-    return __uint_as_float(wave_max_u32(slots[lane_id() & (kVmaxSlots - 1)]));
+    static_assert(kVmaxSlots == 16 * 64, "16 slots per lane");
+    const uint4 *q = (const uint4 *)(slots + 16 * lane_id());
+    uint32_t m = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 v = q[i];
+        const uint32_t a = v.x > v.y ? v.x : v.y, c = v.z > v.w ? v.z : v.w;
+        m = m > a ? m : a;
+        m = m > c ? m : c;
+    }
+    return __uint_as_float(wave_max_u32(m));
 }
 
 // Largest displacement this step in cell units, with a margin for rounding:
@@ -418,13 +428,12 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     using R = VtRegion<DIM>;
     __shared__ T lds_vt[4 * DIM * R::SIZE];
     __shared__ uint32_t lds_rank[4][64];
-    __shared__ uint32_t lds_base[4][64];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
     T *reg = lds_vt + wv * (DIM * R::SIZE);
-    uint32_t *rankc = lds_rank[wv], *bases = lds_base[wv];
+    uint32_t *rankc = lds_rank[wv];
     const TileWalk walk = tile_walk(cur);
-    uint32_t live_nxt, unused;
-    bases[lane] = wave_bucket_prefix(nxt.tot, live_nxt, unused);
+    const uint32_t *bases = nxt.bpre;
+    const uint32_t live_nxt = nxt.bpre[kBuckets];
     const T reach = step_reach<T>(wave_vmax(g.vmax), prm, g.inv_dx);
     const T dt_inv_dx = prm.dt * g.inv_dx, gs = prm.dt * g.inv_dx;
     const uint32_t items = walk.nrec + dead_chunks(src.n, walk.live);
@@ -572,7 +581,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 } else {
                     dkey = sc.pkey[p];
                     drank = sc.prank[p];
-                    base = dkey == kDeadKey ? 0u : bases[bucket_of(dkey >> 6)];
+                    base = bucket_base_of(dkey, bases);
                 }
                 const uint32_t q = bin_destination(dkey, drank, ntab, base, live_nxt);
                 // keep the packed index representable; a particle that left

@@ -73,17 +73,17 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
     constexpr int TE = Gm::TE, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC, NCOR = 1 << DIM;
     const int lane = lane_id();
     const int64_t G = g.d.G;
-    uint32_t nrec, rcnt;
-    const uint32_t rpre = wave_bucket_prefix(cur.rec_count, nrec, rcnt);
+    __shared__ uint32_t wave_bits[4];
+    const uint32_t *rpre = cur.rpre;
+    const uint32_t nrec = rpre[kBuckets];
     uint32_t bits = 0u;  // wave maximum so far of the bounds below
     const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
     int lc[3] = {0, 0, 0};
     local_coords<DIM>(lane, lc);
     const int my_c = lane / NCOR, my_e = lane % NCOR;
     for (uint32_t r = wave; r < nrec; r += nblk * 4) {
-        uint32_t b, j;
-        bucket_locate(r, rpre, rcnt, b, j);
-        const uint32_t t = cur.rec_list[(int64_t)b * cur.rcap + j];
+        const uint32_t b = bucket_find(rpre, r);
+        const uint32_t t = cur.rec_list[(int64_t)b * cur.rcap + (r - rpre[b])];
         int tc[3] = {0, 0, 0};
         tc[0] = (int)(t % (uint32_t)g.d.TN[0]);
         if constexpr (DIM == 3) {
@@ -183,8 +183,15 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
             bits = mine > bits ? mine : bits;
         }
     }
+    // one atomic per block, blocks spread over the slots
     bits = wave_max_u32(bits);
-    if (lane == 0 && bits != 0u) atomicMax(g.vmax + (wave & (kVmaxSlots - 1)), bits);
+    if (lane == 0) wave_bits[threadIdx.x >> 6] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = wave_bits[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = wave_bits[k] > m ? wave_bits[k] : m;
+        if (m != 0u) atomicMax(g.vmax + (blk % (uint32_t)kVmaxSlots), m);
+    }
 }
 
 template <typename T, int DIM, int DEG, bool COMP>

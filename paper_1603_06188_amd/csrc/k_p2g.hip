@@ -330,12 +330,14 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
     const int lane = lane_id();
     int lcoord[3] = {0, 0, 0};
     local_coords<DIM>(lane, lcoord);
-    if (blk == 0 && threadIdx.x < 64) {
+    if (blk == 0) {
         // the grid update that follows raises these bounds of max |vt|, and
         // the layout the following G2P builds starts from empty lists
-        g.vmax[threadIdx.x] = 0u;
-        nxt.rec_count[threadIdx.x] = 0u;
-        nxt.tot[threadIdx.x] = 0u;
+        for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) {
+            g.vmax[i] = 0u;
+            nxt.rec_count[i] = 0u;
+            nxt.tot[i] = 0u;
+        }
         if (threadIdx.x == 0) nxt.dead[0] = 0u;
     }
     const TileWalk walk = tile_walk(cur);
