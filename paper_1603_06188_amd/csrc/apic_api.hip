@@ -42,7 +42,7 @@ int slab_nodes(int dim, int degree) {
 // Workspace layout for a grid and a particle capacity `cap`.
 // ---------------------------------------------------------------------------
 struct ListOff {
-    size_t tile_gen, slot, rec_count, rec_list, tot, rpre, bpre, dead;
+    size_t tile_gen, slot, rec_count, rec_list, rec_tile, tot, rpre, bpre, dead;
 };
 
 struct TabOff {
@@ -112,6 +112,7 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         l.slot = take(TT * 4);
         l.rec_count = take((size_t)kBuckets * 4);
         l.rec_list = take(LB * 4);
+        l.rec_tile = take(RC * 4);
         l.tot = take((size_t)kBuckets * 4);
         l.rpre = take((size_t)(kBuckets + 1) * 4);
         l.bpre = take((size_t)(kBuckets + 1) * 4);
@@ -339,6 +340,7 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         b.slot = (uint32_t *)(w + o.slot);
         b.rec_count = (uint32_t *)(w + o.rec_count);
         b.rec_list = (uint32_t *)(w + o.rec_list);
+        b.rec_tile = (uint32_t *)(w + o.rec_tile);
         b.tot = (uint32_t *)(w + o.tot);
         b.rpre = (uint32_t *)(w + o.rpre);
         b.bpre = (uint32_t *)(w + o.bpre);

@@ -128,9 +128,8 @@ __device__ __forceinline__ TileWalk tile_walk(const BinLists &lists) {
 // Record r of the walk: tile id, first particle and particle count.
 __device__ __forceinline__ uint32_t tile_range(const TileWalk &w, uint32_t r, const BinLists &lists,
                                                const TileTables &tab, uint32_t &start, uint32_t &total) {
-    const uint32_t b = bucket_find(w.rpre, r);
-    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + (r - w.rpre[b])];
-    start = w.bbase[b] + tab.off[t];
+    const uint32_t t = lists.rec_tile[r];
+    start = w.bbase[bucket_of(t)] + tab.off[t];
     total = tab.tcount[t];
     return t;
 }
@@ -141,9 +140,8 @@ __device__ __forceinline__ uint32_t tile_of_record(const TileWalk &w, uint32_t r
                                                    const TileTables &tab, uint32_t &start, uint32_t &cnt,
                                                    uint32_t &maxc, uint32_t &kstart) {
     const int lane = lane_id();
-    const uint32_t b = bucket_find(w.rpre, r);
-    const uint32_t t = lists.rec_list[(int64_t)b * lists.rcap + (r - w.rpre[b])];
-    start = w.bbase[b] + tab.off[t];
+    const uint32_t t = lists.rec_tile[r];
+    start = w.bbase[bucket_of(t)] + tab.off[t];
     cnt = tab.kcount[(int64_t)t * 64 + lane];
     maxc = tab.maxc[t];
     kstart = maxc > (uint32_t)kMaxLevels ? start + tab.kprefix[(int64_t)t * 64 + lane] : 0u;

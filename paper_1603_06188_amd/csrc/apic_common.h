@@ -66,6 +66,7 @@ struct BinLists {
     uint32_t *rec_list;    // [kBuckets * rcap] tile ids, bucket b from b * rcap
     uint32_t *tot;         // [kBuckets] particles per bucket
     uint32_t *rpre;        // [kBuckets + 1] exclusive prefix of rec_count; [kBuckets] = records
+    uint32_t *rec_tile;    // [records] tile id of record r (bucket order)
     uint32_t *bpre;        // [kBuckets + 1] exclusive prefix of tot; [kBuckets] = live particles
     uint32_t *dead;        // [1] dead particles
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)

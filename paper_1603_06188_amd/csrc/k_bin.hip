@@ -97,6 +97,7 @@ __device__ __forceinline__ void records_body(const BinLists &nxt, const TileTabl
             tab.tcount[t] = total;
             tab.off[t] = atomicAdd(nxt.tot + b, total);
             nxt.slot[t] = r;
+            nxt.rec_tile[r] = t;
         }
         if (mx <= (uint32_t)kMaxLevels) {
             // level jj holds the jj-th particle of every key with more than jj

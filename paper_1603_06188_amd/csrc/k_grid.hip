@@ -74,16 +74,14 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
     const int lane = lane_id();
     const int64_t G = g.d.G;
     __shared__ uint32_t wave_bits[4];
-    const uint32_t *rpre = cur.rpre;
-    const uint32_t nrec = rpre[kBuckets];
+    const uint32_t nrec = cur.rpre[kBuckets];
     uint32_t bits = 0u;  // wave maximum so far of the bounds below
     const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
     int lc[3] = {0, 0, 0};
     local_coords<DIM>(lane, lc);
     const int my_c = lane / NCOR, my_e = lane % NCOR;
     for (uint32_t r = wave; r < nrec; r += nblk * 4) {
-        const uint32_t b = bucket_find(rpre, r);
-        const uint32_t t = cur.rec_list[(int64_t)b * cur.rcap + (r - rpre[b])];
+        const uint32_t t = cur.rec_tile[r];
         int tc[3] = {0, 0, 0};
         tc[0] = (int)(t % (uint32_t)g.d.TN[0]);
         if constexpr (DIM == 3) {
