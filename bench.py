@@ -179,6 +179,8 @@ def main(argv=None):
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--cells", type=int, default=128)
     ap.add_argument("--plain", action="store_true", help="uncompensated binary32 accumulation")
+    ap.add_argument("--fused", action="store_true",
+                    help="APIC_OPT_FUSED_TRANSFER: G2P fused with the next step's P2G")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["cube", "batch", "spheres"], default="cube",
                     help="cube: the 128^3 elastic cube (headline); batch: 512 bodies, batched vs per-scene loop; "
@@ -239,7 +241,7 @@ def main(argv=None):
         del src, dst
     scene = scenes.cube3d(cells=args.cells)
     compensated = not args.plain
-    ds = b.DeviceScene(scene, compensated=compensated)
+    ds = b.DeviceScene(scene, compensated=compensated, with_id=False, fused=args.fused)
     st = torch.cuda.current_stream()
 
     # active grid nodes of the initial state (for the byte accounting)
@@ -304,6 +306,7 @@ def main(argv=None):
             "grid_cells": args.cells,
             "active_nodes": active,
             "sort_every": args.sort_every,
+            **({"fused_transfer": True} if args.fused else {}),
         },
         "phase_ms": {p: round(dur[p], 5) for p in phases},
         "flags": flags,

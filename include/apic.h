@@ -65,9 +65,15 @@ enum { APIC_MODEL_NONE = 0, APIC_MODEL_NEO_HOOKEAN = 1 };
 
 /* apic_grid_desc.options bits */
 enum {
-    APIC_OPT_COMPENSATED = 1  /* accumulate grid mass/momentum with an error
+    APIC_OPT_COMPENSATED = 1, /* accumulate grid mass/momentum with an error
                                  term per node (two-sum), folded in by
                                  apic_grid_update                            */
+    APIC_OPT_FUSED_TRANSFER = 2 /* apic_step, binary32 quadratic 3D only:
+                                 the transfer to particles of each step but
+                                 the last of a call also forms the next
+                                 step's grid sums (Sec. 3.4 fused with
+                                 Sec. 3.2); same results up to the order of
+                                 the sums.  Ignored by other combinations. */
 };
 
 /* Sticky device flag bits (apic_get_flags). */

@@ -30,6 +30,7 @@ APIC_QUADRATIC, APIC_CUBIC = 2, 3
 APIC_F32, APIC_F64 = 0, 1
 APIC_MODEL_NONE, APIC_MODEL_NEO_HOOKEAN = 0, 1
 APIC_OPT_COMPENSATED = 1
+APIC_OPT_FUSED_TRANSFER = 2
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
 APIC_FLAG_UNSORTED = 16
 APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
@@ -237,7 +238,7 @@ class DeviceScene:
     off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
 
     def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True,
-                 packed=None):
+                 packed=None, fused=False):
         self.host = scene
         self.dim = scene.dim
         self.precision = precision or scene.precision
@@ -255,7 +256,7 @@ class DeviceScene:
         g.dim = d
         g.degree = scene.degree
         g.precision = APIC_F32 if self.precision == "fp32" else APIC_F64
-        g.options = APIC_OPT_COMPENSATED if compensated else 0
+        g.options = (APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
         for a in range(3):
             g.cells[a] = scene.cells[a] if a < d else 0
         g.dx = scene.dx

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <type_traits>
 #include <vector>
 
 #include "apic.h"
@@ -168,7 +169,8 @@ apic_status check_grid(const apic_grid_desc *g) {
         return fail(APIC_E_INVAL, "degree must be 2 (quadratic) or 3 (cubic) (got %d)", g->degree);
     if (g->precision != APIC_F32 && g->precision != APIC_F64)
         return fail(APIC_E_INVAL, "precision must be APIC_F32 or APIC_F64 (got %d)", g->precision);
-    if (g->options & ~APIC_OPT_COMPENSATED) return fail(APIC_E_INVAL, "unknown option bits 0x%x", g->options);
+    if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER))
+        return fail(APIC_E_INVAL, "unknown option bits 0x%x", g->options);
     const int maxc = g->dim == 3 ? 1024 : 65535;
     for (int a = 0; a < g->dim; ++a)
         if (g->cells[a] < g->degree + 1 || g->cells[a] > maxc)
@@ -468,6 +470,37 @@ void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &
     });
 }
 
+// G2P fused with the next step's P2G: binary32 quadratic 3D, where a lane
+// holds every node sum of its key in registers.
+template <typename T, int DIM, int DEG>
+constexpr bool fused_step() {
+    return std::is_same<T, float>::value && DIM == 3 && DEG == 2;
+}
+
+// As g2p_rebin, then the slabs of the new layout for the next step: the
+// particles that kept their key in the fused pass, the others after it.
+template <typename T, int DIM, int DEG, bool COMP>
+void g2p2g_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &dst, int cur, hipStream_t st) {
+    const int nxt = 1 - cur;
+    begin_build(v, ss, nxt, st);
+    timed(APIC_PHASE_BIN, st, [&] {
+        launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
+                                           st);
+        launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
+        launch_bin_finalize(v.lists[nxt], st);
+    });
+    if constexpr (fused_step<T, DIM, DEG>()) {
+        timed(APIC_PHASE_G2P, st, [&] {
+            launch_g2p2g<T, DEG, COMP>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.slabs,
+                                       v.g, v.prm, v.L.rc, st);
+        });
+        timed(APIC_PHASE_P2G, st, [&] {
+            launch_p2g_movers<T, DEG, COMP>(dst, v.lists[cur], v.lists[nxt], v.tab[nxt], v.slabs, v.g, v.prm,
+                                            v.L.rc, st);
+        });
+    }
+}
+
 template <typename T, int DIM, int DEG, bool COMP>
 apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
     SceneState &ss = state_of(s, cap, st);
@@ -547,22 +580,33 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         ss.cur = 1 - ss.cur;
         where = 1;
     }
+    bool slabs_ready = false;  // the slabs already hold this step's P2G
     for (int32_t k = 0; k < n_steps; ++k) {
         if (sort_every > 0 && k > 0 && k % sort_every == 0) {
             timed(APIC_PHASE_SORT, st,
                   [&] { bin_static<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], 1 - ss.cur, st); });
             ss.cur = 1 - ss.cur;
             where = 1 - where;
+            slabs_ready = false;
         }
-        timed(APIC_PHASE_P2G, st, [&] {
-            launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur], v.slabs,
-                                          v.g, v.prm, v.L.rc, st);
-        });
+        if (!slabs_ready) {
+            timed(APIC_PHASE_P2G, st, [&] {
+                launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur],
+                                              v.slabs, v.g, v.prm, v.L.rc, st);
+            });
+        }
         timed(APIC_PHASE_GRID_UPDATE, st, [&] {
             launch_grid_update<T, DIM, DEG, COMP>(v.lists[ss.cur], v.slabs, v.g, v.prm, v.L.rc, st);
         });
         ss.grid_meta = ss.cur;
-        g2p_rebin<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], ss.cur, false, st);
+        // the last step of the call leaves the slabs of the step it made
+        const bool fuse = fused_step<T, DIM, DEG>() && (s->grid.options & APIC_OPT_FUSED_TRANSFER) &&
+                          k + 1 < n_steps && !(sort_every > 0 && (k + 1) % sort_every == 0);
+        if (fuse)
+            g2p2g_rebin<T, DIM, DEG, COMP>(v, ss, bufs[where], bufs[1 - where], ss.cur, st);
+        else
+            g2p_rebin<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], ss.cur, false, st);
+        slabs_ready = fuse;
         ss.cur = 1 - ss.cur;
         where = 1 - where;
     }

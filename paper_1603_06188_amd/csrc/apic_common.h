@@ -358,6 +358,37 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
+// Workgroups go to the 8 XCDs round-robin (hardware block b on XCD b % 8),
+// and each XCD has an L2 of its own.  This renumbering gives the blocks of
+// one XCD one contiguous range of logical indices, so that neighbouring work
+// items (which read the same slabs and node tiles) meet in the same L2.  It
+// is a bijection of [0, nblk) for any nblk, and it only needs the blocks of a
+// range to be consecutive hardware blocks.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t blk, uint32_t nblk) {
+    const uint32_t c = blk % kXcds, q = nblk / kXcds, rem = nblk % kXcds;
+    return c * q + (c < rem ? c : rem) + blk / kXcds;
+}
+
+// A walk over `items` work items, one per wavefront of 256-thread blocks.
+// Launches are sized for the capacity, so only the first
+// min(nblk, ceil(items / 4)) blocks take part, renumbered by xcd_block among
+// themselves; `first` is this wave's first item (items when it has none).
+// When the items outnumber the waves the walk is strided and left in
+// hardware order, which spreads the extra items over all XCDs.
+struct WaveWalk {
+    uint32_t first, stride;
+};
+__device__ __forceinline__ WaveWalk wave_walk(uint32_t blk, uint32_t nblk, uint32_t items) {
+    const uint32_t need = (uint32_t)(((uint64_t)items + 3u) / 4u);
+    const uint32_t nb = need < nblk ? need : nblk;
+    WaveWalk w;
+    w.stride = nb * 4u;
+    const uint32_t lb = need <= nblk ? xcd_block(blk, nb) : blk;
+    w.first = blk < nb ? lb * 4u + (uint32_t)(threadIdx.x >> 6) : items;
+    return w;
+}
+
 // Element of a particle plane at byte offset `boff` (index * sizeof(T)); the
 // plane pointer is wave-uniform, so plane + 32-bit offset addressing keeps
 // one offset register per particle for all planes.
@@ -375,9 +406,9 @@ __device__ __forceinline__ T two_sum_err(T a, T b, T s) {
 
 // Compiler and LDS ordering point between dependent rounds of one wavefront.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 }  // namespace apic

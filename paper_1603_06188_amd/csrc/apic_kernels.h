@@ -66,6 +66,22 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
                 const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const GridState<T> &g,
                 const StepParams<T> &prm, int64_t max_records, hipStream_t st);
 
+// G2P fused with the next step's P2G (binary32 quadratic 3D): writes each
+// particle to its place in layout `nxt` and the slabs of `nxt` with the
+// contributions of the particles that kept their key.
+template <typename T, int DEG, bool COMP>
+void launch_g2p2g(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const TileTables &ctab,
+                  const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const Slabs<T> &slabs,
+                  const GridState<T> &g, const StepParams<T> &prm, int64_t max_records, hipStream_t st);
+
+// Adds the contributions of the particles that changed key into the slabs
+// of layout `nxt` (after launch_g2p2g); zeroes the bounds of max |vt| and
+// the counters of layout `cur`, which the next step builds.
+template <typename T, int DEG, bool COMP>
+void launch_p2g_movers(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, const TileTables &ntab,
+                       const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm, int64_t max_records,
+                       hipStream_t st);
+
 // --- batched steps: one launch per phase for every scene of a batch -------------
 // `start` holds, per scene, its first block of the launch (n + 1 entries);
 // `k` is the step index within the batched call.

@@ -14,163 +14,10 @@
 // (movers first within a key, then stayers in their old order).  Both passes
 // get the new position through the same fixed operation sequence (no
 // contraction freedom), so they agree bit for bit on every key.
-#include "apic_bin_device.h"
 #include "apic_kernels.h"
+#include "g2p_device.h"
 
 namespace apic {
-
-// Weights along one axis with a fixed operation sequence (see axis_weights).
-template <typename T, int DEG>
-__device__ __forceinline__ int axis_w_fixed(int cell, T off, T *w) {
-#pragma clang fp contract(off)
-    if constexpr (DEG == 2) {
-        const bool lower = off < T(0.5);
-        const T c = lower ? off : off - T(1);
-        const T l = T(0.5) - c, h = T(0.5) + c;
-        w[0] = T(0.5) * (l * l);
-        w[1] = T(0.75) - c * c;
-        w[2] = T(0.5) * (h * h);
-        return lower ? cell - 1 : cell;
-    } else {
-        const T u = off, q = T(1) - off;
-        const T u2 = u * u, q2 = q * q;
-        w[0] = (q2 * q) * T(1.0 / 6.0);
-        w[1] = (T(0.5) * (u2 * u) - u2) + T(2.0 / 3.0);
-        w[2] = (T(0.5) * (q2 * q) - q2) + T(2.0 / 3.0);
-        w[3] = (u2 * u) * T(1.0 / 6.0);
-        return cell - 1;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ T fma_t(T a, T b, T c);
-template <>
-__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <>
-__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// Support-node velocities of a particle: vt[node][k], node = a + K (b + K c).
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void load_support(const int *base, const GridState<T> &g,
-                                             T (&vt)[Geo<DIM, DEG>::NODES][DIM]) {
-    constexpr int K = DEG + 1;
-    const int64_t G = g.d.G;
-#pragma unroll
-    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                const int nc[3] = {base[0] + a, base[1] + b, DIM == 3 ? base[2] + c : 0};
-                const int64_t i = node_index<DIM>(nc, g.d.TN);
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) vt[a + K * (b + K * c)][k] = g.vt[k * G + i];
-            }
-}
-
-// New velocity v = sum_i w_i vt_i with a fixed operation sequence, shared
-// by both passes: first the x-axis sums Tx_k(a) = sum_{c,b} (wy(b) wz(c))
-// vt_k(a,b,c), nodes in (c, b) order, then v_k = sum_a wx(a) Tx_k(a).
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], const T (&w)[DIM][DEG + 1], T *vn) {
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        vn[k] = T(0);
-#pragma unroll
-        for (int a = 0; a < DEG + 1; ++a) vn[k] = fma_t(w[0][a], tx[k][a], vn[k]);
-    }
-}
-
-// Pass 1: x-axis sums from support-node velocities held in registers.
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void gather_velocity(const T (&vt)[Geo<DIM, DEG>::NODES][DIM], const T (&w)[DIM][DEG + 1],
-                                                T *vn) {
-#pragma clang fp contract(off)
-    constexpr int K = DEG + 1;
-    T tx[DIM][K];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int a = 0; a < K; ++a) tx[k][a] = T(0);
-#pragma unroll
-    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-            const T wyz = DIM == 3 ? w[1][b] * w[2][c] : w[1][b];
-#pragma unroll
-            for (int a = 0; a < K; ++a)
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) tx[k][a] = fma_t(wyz, vt[a + K * (b + K * c)][k], tx[k][a]);
-        }
-    velocity_from_tx<T, DIM, DEG>(tx, w, vn);
-}
-
-// Position x + dt v as cell index + offset in [0, 1), fixed operation order;
-// cfl is set when the step exceeds one cell.
-template <typename T, int DIM>
-__device__ __forceinline__ void move_position(const int *ci, const T *off, const T *vn, T dt_inv_dx, int *cn, T *on,
-                                              bool &cfl) {
-#pragma clang fp contract(off)
-    cfl = false;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const T step = dt_inv_dx * vn[a];
-        cfl = cfl || !(step <= T(1) && step >= T(-1));
-        T o = off[a] + step;
-        const T fl = floor_t(o);
-        int cc = ci[a] + (int)fl;
-        o = o - fl;
-        if (o >= T(1)) {
-            o = o - T(1);
-            cc += 1;
-        }
-        cn[a] = cc;
-        on[a] = o;
-    }
-}
-
-// Bound of max_i |vt_i| over the slots the grid update raised (wave-wide).
-__device__ __forceinline__ float wave_vmax(const uint32_t *slots) {
-    static_assert(kVmaxSlots == 16 * 64, "16 slots per lane");
-    const uint4 *q = (const uint4 *)(slots + 16 * lane_id());
-    uint32_t m = 0u;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint4 v = q[i];
-        const uint32_t a = v.x > v.y ? v.x : v.y, c = v.z > v.w ? v.z : v.w;
-        m = m > a ? m : a;
-        m = m > c ? m : c;
-    }
-    return __uint_as_float(wave_max_u32(m));
-}
-
-// Largest displacement this step in cell units, with a margin for rounding:
-// |v_p| <= max_i |vt_i| since the weights are a partition of unity.
-template <typename T>
-__device__ __forceinline__ T step_reach(float vbound, const StepParams<T> &prm, T inv_dx) {
-    return (T)vbound * prm.dt * inv_dx * T(1.0001) + T(1e-6);
-}
-
-// True when the particle is farther than `reach` from every offset where its
-// base node changes (1/2 for quadratic, 0 and 1 for cubic): it keeps its key.
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ bool keeps_key(const T *off, T reach) {
-    bool far = reach < T(0.5);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const T dist = DEG == 2 ? (off[a] < T(0.5) ? T(0.5) - off[a] : off[a] - T(0.5))
-                                : (off[a] < T(0.5) ? off[a] : T(1) - off[a]);
-        far = far && dist > reach;
-    }
-    return far;
-}
-
-// Dead particles of the current layout are walked in chunks of 64 after the
-// listed tiles.
-__device__ __forceinline__ uint32_t dead_chunks(int64_t n, uint32_t live) {
-    return (uint32_t)((n - (int64_t)live + 63) / 64);
-}
 
 // --- pass 1: new keys ---------------------------------------------------------------------
 // One wavefront per listed tile walks the tile's particles in chunks of 64.
@@ -342,79 +189,6 @@ void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTab
 }
 
 // --- pass 2: the transfer, written to the new layout ------------------------------------
-// Grid velocities of the 2^DIM node tiles from the key tile on, in LDS:
-// 3D 8x8x8 nodes at x + 8 y + 68 z (the z pad spreads a wavefront's 4x4x4
-// reads over the banks), 2D 16x16 nodes at x + 16 y; component-major.
-template <int DIM>
-struct VtRegion {
-    static constexpr int SY = DIM == 3 ? 8 : 16;
-    static constexpr int SZ = DIM == 3 ? 68 : 0;
-    static constexpr int SIZE = DIM == 3 ? 8 * 68 : 256;
-    __device__ static constexpr int at(int x, int y, int z) { return x + SY * y + SZ * z; }
-};
-
-template <typename T, int DIM>
-__device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> &g, T *reg) {
-    using R = VtRegion<DIM>;
-    constexpr int TE = DIM == 3 ? 4 : 8;
-    const int lane = lane_id();
-    const int64_t G = g.d.G;
-    int tc[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
-    tc[0] = (int)(t % (uint32_t)g.d.TN[0]);
-    if constexpr (DIM == 3) {
-        tc[1] = (int)((t / (uint32_t)g.d.TN[0]) % (uint32_t)g.d.TN[1]);
-        tc[2] = (int)(t / ((uint32_t)g.d.TN[0] * (uint32_t)g.d.TN[1]));
-    } else {
-        tc[1] = (int)(t / (uint32_t)g.d.TN[0]);
-    }
-    local_coords<DIM>(lane, lc);
-#pragma unroll
-    for (int corner = 0; corner < (1 << DIM); ++corner) {
-        bool ok = true;
-        int64_t tau = 0, mul = 1;
-        int rc[3] = {0, 0, 0};
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const int bit = (corner >> a) & 1;
-            ok = ok && tc[a] + bit < g.d.TN[a];
-            tau += (int64_t)(tc[a] + bit) * mul;
-            mul *= g.d.TN[a];
-            rc[a] = bit * TE + lc[a];
-        }
-        const int idx = R::at(rc[0], rc[1], rc[2]);
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) reg[k * R::SIZE + idx] = ok ? g.vt[k * G + tau * 64 + lane] : T(0);
-    }
-}
-
-// Occupancy target: binary32 quadratic 3D fits 128 registers (4 waves per
-// SIMD); other variants are left to the compiler.
-template <typename T, int DIM, int DEG>
-constexpr int g2p_min_waves() {
-    return (sizeof(T) == 4 && DEG == 2) ? 4 : 1;
-}
-
-// What G2P reads of a particle (loaded one chunk ahead of its use).
-template <typename T, int DIM>
-struct G2PRaw {
-    uint32_t cell;
-    int32_t id;
-    T m, off[DIM], F[DIM * DIM];
-};
-
-template <typename T, int DIM>
-__device__ __forceinline__ void g2p_load(const Parts<T> &src, uint32_t p, G2PRaw<T, DIM> &r) {
-    const int64_t ss = src.s;
-    const uint32_t pb = p * (uint32_t)sizeof(T);
-    r.cell = src.cell[p];
-    r.m = plane_at(src.m, pb);
-    r.id = src.id ? plane_at(src.id, p * 4u) : 0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) r.off[a] = plane_at(src.off + a * ss, pb);
-#pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) r.F[k] = plane_at(src.F + k * ss, pb);
-}
-
 // One wavefront per listed tile walks the tile's particles in chunks of 64
 // (every lane busy).  A stayer's rank in its key continues from the key's
 // mover count (LDS counter); a mover takes the key and rank of pass 1.
@@ -440,24 +214,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     const int64_t ss = src.s, ds = dst.s;
     for (uint32_t r = blk * 4 + (uint32_t)wv; r < items; r += nblk * 4) {
         if (r >= walk.nrec) {
-            // dead particles are carried over unchanged
-            const int64_t p = (int64_t)walk.live + (int64_t)(r - walk.nrec) * 64 + lane;
-            if (p < src.n) {
-                const int64_t q = (int64_t)live_nxt + sc.prank[p];
-                dst.cell[q] = src.cell[p];
-                dst.m[q] = src.m[p];
-                if (src.id) dst.id[q] = src.id[p];
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    dst.off[a * ds + q] = src.off[a * ss + p];
-                    dst.v[a * ds + q] = src.v[a * ss + p];
-                }
-#pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) {
-                    dst.B[k * ds + q] = src.B[k * ss + p];
-                    dst.F[k * ds + q] = src.F[k * ss + p];
-                }
-            }
+            carry_dead<T, DIM>(src, dst, sc, walk.live, live_nxt, r - walk.nrec);
             continue;
         }
         uint32_t start, total;
@@ -478,95 +235,10 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
             if (i + 64 < total) g2p_load<T, DIM>(src, start + i + 64, raw_n);
             if (i < total) {
                 const uint32_t p = start + i;
-                int ci[3] = {0, 0, 0}, cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
-                unpack_cell<DIM>(raw.cell, ci);
-                T off[DIM], wf[DIM][K], on[DIM], vn[DIM], Bc[DIM * DIM], Fn[DIM * DIM];
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    off[a] = raw.off[a];
-                    lk[a] = axis_w_fixed<T, DEG>(ci[a], off[a], wf[a]) - origin[a];
-                }
-                // One sweep over the support nodes (c, b, a) from LDS: the
-                // axis-pair sums Tx_k(a) = sum_{b,c} wy wz vt_k (in the
-                // sequence of pass 1), Ty_k(b) = sum_{a,c} wx wz vt_k and
-                // Tz_k(c) = sum_{a,b} wx wy vt_k, from which
-                //   v_k = sum_a wx Tx_k(a),
-                //   B_k0 = sum_a wx rx Tx_k(a), grad v_k0 = sum_a dwx Tx_k(a),
-                // and likewise along y and z.
-                T Tx[DIM][K], Ty[DIM][K], Tz[DIM][K];
-#pragma unroll
-                for (int k = 0; k < DIM; ++k)
-#pragma unroll
-                    for (int ii = 0; ii < K; ++ii) Tx[k][ii] = Ty[k][ii] = Tz[k][ii] = T(0);
-                {
-#pragma clang fp contract(off)
-#pragma unroll
-                    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
-#pragma unroll
-                        for (int b = 0; b < K; ++b) {
-                            const T wyz = DIM == 3 ? wf[1][b] * wf[2][c] : wf[1][b];
-#pragma unroll
-                            for (int a = 0; a < K; ++a) {
-                                const T wxz = DIM == 3 ? wf[0][a] * wf[2][c] : wf[0][a];
-                                const T wxy = DIM == 3 ? wf[0][a] * wf[1][b] : T(0);
-                                const int idx = R::at(lk[0] + a, lk[1] + b, DIM == 3 ? lk[2] + c : 0);
-#pragma unroll
-                                for (int k = 0; k < DIM; ++k) {
-                                    const T x = reg[k * R::SIZE + idx];
-                                    Tx[k][a] = fma_t(wyz, x, Tx[k][a]);
-                                    Ty[k][b] = fma_t(wxz, x, Ty[k][b]);
-                                    if constexpr (DIM == 3) Tz[k][c] = fma_t(wxy, x, Tz[k][c]);
-                                }
-                            }
-                            // the sums are formed here, row by row, not sunk to
-                            // their later use (which would keep every LDS value
-                            // of the sweep in registers)
-#pragma unroll
-                            for (int k = 0; k < DIM; ++k)
-#pragma unroll
-                                for (int ii = 0; ii < K; ++ii) {
-                                    asm volatile("" : "+v"(Ty[k][ii]));
-                                    if constexpr (DIM == 3) asm volatile("" : "+v"(Tz[k][ii]));
-                                }
-                        }
-                }
-                velocity_from_tx<T, DIM, DEG>(Tx, wf, vn);
-                // B and grad v (cell units) from the axis sums; weight
-                // derivatives and node offsets from the offsets
-                T Gc[DIM * DIM];
-#pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) Bc[k] = Gc[k] = T(0);
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    Axis<T, DEG> ax;
-                    axis_weights<T, DEG>(ci[a], off[a], ax);
-#pragma unroll
-                    for (int ii = 0; ii < K; ++ii) {
-                        const T wr = wf[a][ii] * ax.r[ii];
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) {
-                            const T tk = a == 0 ? Tx[k][ii] : (a == 1 ? Ty[k][ii] : Tz[k][ii]);
-                            Bc[k * DIM + a] += wr * tk;
-                            Gc[k * DIM + a] += ax.dw[ii] * tk;
-                        }
-                    }
-                }
-                // F <- (I + dt grad v) F, grad v = Gc / dx
-                T F[DIM * DIM];
-#pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) F[k] = raw.F[k];
-#pragma unroll
-                for (int rr = 0; rr < DIM; ++rr)
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) acc += Gc[rr * DIM + k] * F[k * DIM + c];
-                        Fn[rr * DIM + c] = F[rr * DIM + c] + gs * acc;
-                    }
-                bool cfl;
-                move_position<T, DIM>(ci, off, vn, dt_inv_dx, cn, on, cfl);
-                if (cfl) atomicOr(g.flags, FLAG_CFL);
+                int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
+                T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
+                g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn);
+                const T *off = raw.off;
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);
                 if (!stays) {
@@ -599,7 +271,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 }
 #pragma unroll
                 for (int k = 0; k < DIM * DIM; ++k) {
-                    plane_at(dst.B + k * ds, qb) = Bc[k] * g.dx;
+                    plane_at(dst.B + k * ds, qb) = Bs[k];
                     plane_at(dst.F + k * ds, qb) = Fn[k];
                 }
             }

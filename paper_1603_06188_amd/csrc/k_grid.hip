@@ -76,11 +76,11 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
     __shared__ uint32_t wave_bits[4];
     const uint32_t nrec = cur.rpre[kBuckets];
     uint32_t bits = 0u;  // wave maximum so far of the bounds below
-    const uint32_t wave = blk * 4 + (threadIdx.x >> 6);
+    const WaveWalk ww = wave_walk(blk, nblk, nrec);
     int lc[3] = {0, 0, 0};
     local_coords<DIM>(lane, lc);
     const int my_c = lane / NCOR, my_e = lane % NCOR;
-    for (uint32_t r = wave; r < nrec; r += nblk * 4) {
+    for (uint32_t r = ww.first; r < nrec; r += ww.stride) {
         const uint32_t t = cur.rec_tile[r];
         int tc[3] = {0, 0, 0};
         tc[0] = (int)(t % (uint32_t)g.d.TN[0]);

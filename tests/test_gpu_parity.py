@@ -121,19 +121,21 @@ def test_apic_step_matches_chained_oracle_steps(dim, degree):
         check_binned_layout(tile, local)
 
 
-@pytest.mark.parametrize("degree", [2, 3])
-def test_particles_leaving_the_grid_are_carried_and_the_rest_match(degree):
+@pytest.mark.parametrize("degree,precision", [(2, "fp64"), (3, "fp64"), (2, "fp32")])
+def test_particles_leaving_the_grid_are_carried_and_the_rest_match(degree, precision):
     """A cluster moving 0.6 cells per step toward the -x face leaves the
     grid during the second step: from then on it sits in the dead region,
     carried unchanged (its state is the oracle's after the step that took it
     out), OUT_OF_DOMAIN is raised, and every other particle matches the
-    oracle chained over the steps without the cluster once it is gone."""
+    oracle chained over the steps without the cluster once it is gone.
+    Binary32 (quadratic: the steps before the last are fused with the next
+    transfer to grid): bar 1e-5 per step, 4e-5 over the four steps."""
     import dataclasses
     b = _b()
     cells, dt = 16, 1e-2
     dx = 1.0 / cells
     bulk = scenes.random_particles(1500, dim=3, cells=cells, degree=degree, seed=41, margin=5.0,
-                                   vel_sigma=0.2, f_sigma=0.02, b_sigma=0.01, model=0)
+                                   vel_sigma=0.2, f_sigma=0.02, b_sigma=0.01, model=0, precision=precision)
     rng = np.random.default_rng(42)
     start = 1.55 if degree == 2 else 2.05      # first cell whose support is inside
     xc = np.column_stack([(start + 0.1 * rng.random(40)) * dx,
@@ -167,8 +169,9 @@ def test_particles_leaving_the_grid_are_carried_and_the_rest_match(degree):
     assert left_at is not None and 0 < left_at < steps - 1
     assert not live[cluster].any() and live[:bulk.n].all()
     assert ds.flags() & b.APIC_FLAG_OUT_OF_DOMAIN
+    tol = 1e-11 if precision == "fp64" else steps * 1e-5
     for key, a, ref in (("x", got["x"], X), ("v", got["v"], V), ("B", got["B"], Bm), ("F", got["F"], Fm)):
-        assert rel(a, ref) <= 1e-11, (key, rel(a, ref))
+        assert rel(a, ref) <= tol, (key, rel(a, ref))
 
 
 def test_disk2d_fp64_ten_round_trips():
