@@ -38,6 +38,7 @@ namespace apic {
 constexpr int kBuckets = 1024;   // 4 per thread of a 256-thread block
 constexpr int kMaxLevels = 32;
 constexpr int kVmaxSlots = 1024;
+constexpr int kKeyChunks = 8;     // key pass: chunks of 64 particles loaded together
 
 struct GridDims {
     int dim, deg;

@@ -37,25 +37,6 @@ __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { retur
 template <>
 __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Support-node velocities of a particle: vt[node][k], node = a + K (b + K c).
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void load_support(const int *base, const GridState<T> &g,
-                                             T (&vt)[Geo<DIM, DEG>::NODES][DIM]) {
-    constexpr int K = DEG + 1;
-    const int64_t G = g.d.G;
-#pragma unroll
-    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                const int nc[3] = {base[0] + a, base[1] + b, DIM == 3 ? base[2] + c : 0};
-                const int64_t i = node_index<DIM>(nc, g.d.TN);
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) vt[a + K * (b + K * c)][k] = g.vt[k * G + i];
-            }
-}
-
 // New velocity v = sum_i w_i vt_i with a fixed operation sequence, shared
 // by both passes: first the x-axis sums Tx_k(a) = sum_{c,b} (wy(b) wz(c))
 // vt_k(a,b,c), nodes in (c, b) order, then v_k = sum_a wx(a) Tx_k(a).
@@ -68,30 +49,6 @@ __device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], co
 #pragma unroll
         for (int a = 0; a < DEG + 1; ++a) vn[k] = fma_t(w[0][a], tx[k][a], vn[k]);
     }
-}
-
-// Pass 1: x-axis sums from support-node velocities held in registers.
-template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void gather_velocity(const T (&vt)[Geo<DIM, DEG>::NODES][DIM], const T (&w)[DIM][DEG + 1],
-                                                T *vn) {
-#pragma clang fp contract(off)
-    constexpr int K = DEG + 1;
-    T tx[DIM][K];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int a = 0; a < K; ++a) tx[k][a] = T(0);
-#pragma unroll
-    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-            const T wyz = DIM == 3 ? w[1][b] * w[2][c] : w[1][b];
-#pragma unroll
-            for (int a = 0; a < K; ++a)
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) tx[k][a] = fma_t(wyz, vt[a + K * (b + K * c)][k], tx[k][a]);
-        }
-    velocity_from_tx<T, DIM, DEG>(tx, w, vn);
 }
 
 // Position x + dt v as cell index + offset in [0, 1), fixed operation order;
@@ -358,6 +315,35 @@ __device__ __forceinline__ void carry_dead(const Parts<T> &src, const Parts<T> &
         dst.B[k * ds + q] = src.B[k * ss + p];
         dst.F[k * ds + q] = src.F[k * ss + p];
     }
+}
+
+// New velocity from the grid velocities staged in LDS (base node at lk
+// relative to the region): x-axis sums Tx_k(a) over the nodes in (c, b)
+// order, then velocity_from_tx -- the operation sequence of the G2P sweep,
+// so both give the same bits.
+template <typename T, int DIM, int DEG>
+__device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const T (&w)[DIM][DEG + 1], T *vn) {
+#pragma clang fp contract(off)
+    constexpr int K = DEG + 1;
+    using R = VtRegion<DIM>;
+    T tx[DIM][K];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int a = 0; a < K; ++a) tx[k][a] = T(0);
+#pragma unroll
+    for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const T wyz = DIM == 3 ? w[1][b] * w[2][c] : w[1][b];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const int idx = R::at(lk[0] + a, lk[1] + b, DIM == 3 ? lk[2] + c : 0);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) tx[k][a] = fma_t(wyz, reg[k * R::SIZE + idx], tx[k][a]);
+            }
+        }
+    velocity_from_tx<T, DIM, DEG>(tx, w, vn);
 }
 
 }  // namespace apic

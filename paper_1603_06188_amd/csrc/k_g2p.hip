@@ -20,11 +20,12 @@
 namespace apic {
 
 // --- pass 1: new keys ---------------------------------------------------------------------
-// One wavefront per listed tile walks the tile's particles in chunks of 64.
-// A particle farther from every key boundary than this step can move keeps
-// its key and only adds to its key's stayer count (LDS).  The others are
-// queued in LDS and resolved 64 at a time with the gather, so the gather
-// runs about once per tile instead of once per chunk.
+// One wavefront per listed tile loads the tile's particles in groups of
+// kKeyChunks chunks of 64 (all loads of a group in flight together).  A
+// particle farther from every key boundary than this step can move keeps its
+// key and only adds to its key's stayer count (LDS).  The others are queued
+// in LDS and resolved 64 at a time from the grid velocities around the tile,
+// staged in LDS when the tile first needs them.
 
 // Base-node key, local index within its tile, of a particle at (ci, off).
 template <typename T, int DIM, int DEG>
@@ -36,29 +37,31 @@ __device__ __forceinline__ int local_key(const int *ci, const T *off) {
 }
 
 // Resolves queued particles lane < count: stayers add to their key's count,
-// movers take a rank in their new key (or among the dead).  Wave-wide.
+// movers take a rank in their new key (or among the dead).  The grid
+// velocities around tile t (first node `origin`) are staged in `reg`.
+// Wave-wide.
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<T> &g, const StepParams<T> &prm,
                                              const BinLists &nxt, const BinScratch &sc, const uint32_t *queue,
-                                             uint32_t count, uint32_t t, uint32_t *stay) {
+                                             uint32_t count, uint32_t t, const int *origin, const T *reg,
+                                             uint32_t *stay) {
     const int lane = lane_id();
     const bool act = (uint32_t)lane < count;
     uint32_t nkey = kDeadKey, q = 0;
     bool mover = false;
     if (act) {
         q = queue[lane];
-        int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
+        int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, lk[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
         unpack_cell<DIM>(P.cell[q], ci);
         T off[DIM], w[DIM][DEG + 1], vn[DIM], on[DIM];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             off[a] = P.off[a * P.s + q];
             base[a] = axis_w_fixed<T, DEG>(ci[a], off[a], w[a]);
+            lk[a] = base[a] - origin[a];
         }
         const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(base);
-        T vt[Geo<DIM, DEG>::NODES][DIM];
-        load_support<T, DIM, DEG>(base, g, vt);
-        gather_velocity<T, DIM, DEG>(vt, w, vn);
+        velocity_lds<T, DIM, DEG>(reg, lk, w, vn);
         bool cfl, finite;
         move_position<T, DIM>(ci, off, vn, prm.dt * g.inv_dx, cn, on, cfl);
         nkey = key_of<T, DIM, DEG>(cn, on, g.d, finite);
@@ -79,10 +82,13 @@ template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur, const TileTables &ctab,
                                           const GridState<T> &g, const StepParams<T> &prm, const BinLists &nxt,
                                           const BinScratch &sc, uint32_t blk, uint32_t nblk) {
+    using R = VtRegion<DIM>;
     __shared__ uint32_t lds_stay[4][64];
-    __shared__ uint32_t lds_queue[4][128];
+    __shared__ uint32_t lds_queue[4][64 * kKeyChunks];
+    __shared__ T lds_vt[4 * DIM * R::SIZE];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
     uint32_t *stay = lds_stay[wv], *queue = lds_queue[wv];
+    T *reg = lds_vt + wv * (DIM * R::SIZE);
     const TileWalk walk = tile_walk(cur);
     const T reach = step_reach<T>(wave_vmax(g.vmax), prm, g.inv_dx);
     const uint32_t items = walk.nrec + dead_chunks(P.n, walk.live);
@@ -95,58 +101,56 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         }
         uint32_t start, total;
         const uint32_t t = tile_range(walk, r, cur, ctab, start, total);
+        int origin[3] = {0, 0, 0};
+        tile_origin<DIM>(t, g.d.TN, origin);
+        bool staged = false;  // grid velocities around the tile, on first use
         stay[lane] = 0u;
         wave_lds_sync();
-        uint32_t queued = 0, c0 = 0;
-        // cell and offset of the current chunk; the next chunk's are loaded
-        // while this one is classified
-        uint32_t cell = 0;
-        T off[DIM];
-        if ((uint32_t)lane < total) {
-            cell = P.cell[start + lane];
+        uint32_t queued = 0;
+        // groups of kKeyChunks chunks of 64: every load of a group is in
+        // flight at once, then its chunks are classified in order
+        for (uint32_t g0 = 0; g0 < total; g0 += 64u * kKeyChunks) {
+            uint32_t cell[kKeyChunks];
+            T off[kKeyChunks][DIM];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) off[a] = P.off[a * P.s + start + lane];
-        }
-        for (;;) {
-            if (c0 < total) {
-                const uint32_t i = c0 + (uint32_t)lane;
-                uint32_t cell_n = 0;
-                T off_n[DIM];
-                if (i + 64 < total) {
-                    cell_n = P.cell[start + i + 64];
+            for (int u = 0; u < kKeyChunks; ++u) {
+                const uint32_t i = g0 + 64u * u + (uint32_t)lane;
+                cell[u] = 0u;
+                if (i < total) {
+                    cell[u] = P.cell[start + i];
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) off_n[a] = P.off[a * P.s + start + i + 64];
+                    for (int a = 0; a < DIM; ++a) off[u][a] = P.off[a * P.s + start + i];
                 }
+            }
+#pragma unroll
+            for (int u = 0; u < kKeyChunks; ++u) {
+                const uint32_t i = g0 + 64u * u + (uint32_t)lane;
+                if (g0 + 64u * u >= total) break;
                 bool near = false;
                 if (i < total) {
                     int ci[3] = {0, 0, 0};
-                    unpack_cell<DIM>(cell, ci);
-                    if (keeps_key<T, DIM, DEG>(off, reach))
-                        atomicAdd(stay + local_key<T, DIM, DEG>(ci, off), 1u);
+                    unpack_cell<DIM>(cell[u], ci);
+                    if (keeps_key<T, DIM, DEG>(off[u], reach))
+                        atomicAdd(stay + local_key<T, DIM, DEG>(ci, off[u]), 1u);
                     else
                         near = true;
                 }
                 const uint64_t nm = ballot(near);
                 if (near) queue[queued + (uint32_t)popc64(nm & lanes_below(lane))] = start + i;
                 queued += (uint32_t)popc64(nm);
-                cell = cell_n;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) off[a] = off_n[a];
             }
-            c0 += 64;
-            const bool read_all = c0 >= total;
-            if (queued >= 64 || (read_all && queued > 0)) {
-                // resolve up to 64 queued particles, keep the rest queued
-                const uint32_t take = queued < 64 ? queued : 64u;
+            // the group's queued particles, 64 at a time
+            for (uint32_t q0 = 0; q0 < queued; q0 += 64u) {
+                if (!staged) {
+                    stage_velocities<T, DIM>(t, g, reg);
+                    staged = true;
+                }
                 wave_lds_sync();
-                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue, take, t, stay);
-                const uint32_t rest = queued - take;
-                const uint32_t moved = (uint32_t)lane < rest ? queue[64 + lane] : 0u;
-                wave_lds_sync();
-                if ((uint32_t)lane < rest) queue[lane] = moved;
-                queued = rest;
+                const uint32_t take = queued - q0 < 64u ? queued - q0 : 64u;
+                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue + q0, take, t, origin, reg, stay);
             }
-            if (read_all && queued == 0) break;
+            queued = 0;
+            wave_lds_sync();
         }
         wave_lds_sync();
         const uint32_t s = stay[lane];

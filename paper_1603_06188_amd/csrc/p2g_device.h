@@ -121,62 +121,54 @@ __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *
 // the momentum contribution to node (a,b,c), component k, is
 //   w p_k + w (Qc r)_k + (Ac grad w)_k
 //   = X0_k(a) (wy wz)(b,c) + Yb_k(b) (wx wz)(a,c) + Zc_k(c) (wx wy)(a,b)
+//   = wz(c) S_k(a,b) + Zc_k(c) Rxy(a,b)
 // with X0_k = wx p_k + wx rx Qc_k0 + dx Ac_k0, Yb_k = wy ry Qc_k1 + dy Ac_k1,
-// Zc_k = wz rz Qc_k2 + dz Ac_k2: three multiply-adds per node and component.
+// Zc_k = wz rz Qc_k2 + dz Ac_k2, S_k(a,b) = X0_k(a) wy(b) + Yb_k(b) wx(a)
+// (independent of the slice) and Rxy = wx wy: two multiply-adds per node
+// and component, one for the mass (m wx wy) wz.
 template <typename T, int DEG, int C0, int CZ>
 __device__ __forceinline__ void p2g_accumulate3(const P2GParticle<T, 3, DEG> &pp, T (&acc_m)[CZ][DEG + 1][DEG + 1],
                                                 T (&acc_v)[3][CZ][DEG + 1][DEG + 1]) {
     constexpr int K = DEG + 1;
     const Axis<T, DEG> &X = pp.ax[0], &Y = pp.ax[1], &Z = pp.ax[2];
-    T X0[3][K], Yb[3][K], Mx[K], Rxy[K][K];
+    T X0[3][K], Yb[3][K], Zc[3][CZ];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const T wrx = X.w[a] * X.r[a], wry = Y.w[a] * Y.r[a];
-        Mx[a] = pp.m * X.w[a];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             X0[k][a] = X.w[a] * pp.p[k] + wrx * pp.Qc[k * 3 + 0] + X.dw[a] * pp.Ac[k * 3 + 0];
             Yb[k][a] = wry * pp.Qc[k * 3 + 1] + Y.dw[a] * pp.Ac[k * 3 + 1];
         }
-#pragma unroll
-        for (int b = 0; b < K; ++b) Rxy[a][b] = X.w[a] * Y.w[b];
     }
-    // slice by slice: the slice's own factors, then its K*K nodes
 #pragma unroll
     for (int cc = 0; cc < CZ; ++cc) {
         const int c = C0 + cc;
         const T wrz = Z.w[c] * Z.r[c];
-        T Zc[3], Pyz[K], Qxz[K];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Zc[k] = wrz * pp.Qc[k * 3 + 2] + Z.dw[c] * pp.Ac[k * 3 + 2];
+        for (int k = 0; k < 3; ++k) Zc[k][cc] = wrz * pp.Qc[k * 3 + 2] + Z.dw[c] * pp.Ac[k * 3 + 2];
+    }
+    // column by column (a, b): its own factors, then its CZ nodes
 #pragma unroll
-        for (int b = 0; b < K; ++b) {
-            Pyz[b] = Y.w[b] * Z.w[c];
-            Qxz[b] = X.w[b] * Z.w[c];
-        }
+    for (int b = 0; b < K; ++b)
 #pragma unroll
-        for (int b = 0; b < K; ++b)
+        for (int a = 0; a < K; ++a) {
+            const T Rxy = X.w[a] * Y.w[b], Mxy = pp.m * Rxy;
+            T S[3];
 #pragma unroll
-            for (int a = 0; a < K; ++a) {
-                acc_m[cc][b][a] += Mx[a] * Pyz[b];
+            for (int k = 0; k < 3; ++k) S[k] = X0[k][a] * Y.w[b] + Yb[k][b] * X.w[a];
+#pragma unroll
+            for (int cc = 0; cc < CZ; ++cc) {
+                const T wz = Z.w[C0 + cc];
+                acc_m[cc][b][a] += Mxy * wz;
                 // separate multiply-adds into the accumulator (one FMA each)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    acc_v[k][cc][b][a] += X0[k][a] * Pyz[b];
-                    acc_v[k][cc][b][a] += Yb[k][b] * Qxz[a];
-                    acc_v[k][cc][b][a] += Zc[k] * Rxy[a][b];
+                    acc_v[k][cc][b][a] += wz * S[k];
+                    acc_v[k][cc][b][a] += Zc[k][cc] * Rxy;
                 }
             }
-        // the slice is accumulated here, not deferred (bounds live factors)
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                asm volatile("" : "+v"(acc_m[cc][b][a]));
-#pragma unroll
-                for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(acc_v[k][cc][b][a]));
-            }
-    }
+        }
 }
 
 // 2D: contribution = X0_k(a) wy(b) + Yb_k(b) wx(a).
