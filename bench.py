@@ -104,7 +104,9 @@ def served(pool_size: int, duration: float, load: float, seed: int = 6):
     trace = serve.poisson_trace(rate, duration, len(pool), seed=seed)
     out = {"requests": len(trace), "rate_per_s": rate, "load": load, "capacity_updates_per_s": capacity,
            "pool_bodies": len(pool), "mean_particles": mean_n, "trace_s": duration}
-    for name, server in (("batched", serve.BatchServer(pool)), ("sequential", serve.SequentialServer(pool))):
+    batch_server = serve.BatchServer(pool)
+    out["mem_budget_bytes"] = batch_server.mem_budget
+    for name, server in (("batched", batch_server), ("sequential", serve.SequentialServer(pool))):
         st = server.run([dataclasses.replace(r) for r in trace])
         out[name] = {"p50_s": st.percentile(50), "p99_s": st.percentile(99), "mean_s": float(st.latencies.mean()),
                      "throughput": st.throughput, "wall_s": st.wall}

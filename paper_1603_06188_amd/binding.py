@@ -231,6 +231,32 @@ def unpack_cells(packed: np.ndarray, dim: int) -> np.ndarray:
     return np.stack([p & 0xFFFF, p >> 16], axis=1).astype(np.int64)
 
 
+def grid_desc(scene, precision=None, compensated=False, fused=False) -> ApicGridDesc:
+    """The apic_grid_desc of a host scene."""
+    precision = precision or scene.precision
+    g = ApicGridDesc()
+    g.dim = scene.dim
+    g.degree = scene.degree
+    g.precision = APIC_F32 if precision == "fp32" else APIC_F64
+    g.options = (APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
+    for a in range(3):
+        g.cells[a] = scene.cells[a] if a < scene.dim else 0
+    g.dx = scene.dx
+    return g
+
+
+def scene_footprint_bytes(scene, precision=None, compensated=False, with_id=True, capacity=None) -> int:
+    """Device bytes a DeviceScene of `scene` holds: its particle planes, cell
+    (and id) arrays and its workspace."""
+    precision = precision or scene.precision
+    cap = max(int(capacity or scene.n), 1)
+    d = scene.dim
+    elem = 4 if precision == "fp32" else 8
+    planes = (2 * d + 2 * d * d + 1) * cap * elem
+    ints = cap * 4 * (2 if with_id else 1)
+    return planes + ints + apic_workspace_bytes(grid_desc(scene, precision, compensated), cap) + 256
+
+
 class DeviceScene:
     """Device copy of a ``scenes.Scene`` plus its workspace.
 
@@ -252,14 +278,7 @@ class DeviceScene:
         self.cell = torch.zeros(cap, dtype=torch.int32, device=device)
         self.id = torch.arange(cap, dtype=torch.int32, device=device) if with_id else None
         self.upload(scene, packed)
-        g = ApicGridDesc()
-        g.dim = d
-        g.degree = scene.degree
-        g.precision = APIC_F32 if self.precision == "fp32" else APIC_F64
-        g.options = (APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
-        for a in range(3):
-            g.cells[a] = scene.cells[a] if a < d else 0
-        g.dx = scene.dx
+        g = grid_desc(scene, self.precision, compensated, fused)
         self.wbytes = apic_workspace_bytes(g, cap)
         self.ws = torch.empty(self.wbytes + 256, dtype=torch.uint8, device=device)
         s = ApicScene()

@@ -8,6 +8,9 @@ arrival trace:
 * ``BatchServer`` keeps every admitted request resident and advances all of
   them together, ``quantum`` steps per ``apic_step_batch`` call (one kernel
   launch per phase for all of them); requests join and leave between quanta.
+  Arrived requests are admitted in arrival order while their device
+  footprint (particle planes + workspace) fits the memory budget next to the
+  requests already resident.
 * ``SequentialServer`` solves one request at a time to completion with
   ``apic_step`` on that scene alone, first come first served.
 
@@ -78,10 +81,12 @@ class Pool:
     def __init__(self, pool, compensated: bool = True, device: str = "cuda", with_id: bool = False):
         self.with_id = with_id
         self.templates = []
+        self.footprints = []
         for s in pool:
             dtype = torch.float32 if s.precision == "fp32" else torch.float64
             f, cell = b.DeviceScene.pack(s, dtype)
             self.templates.append((s, (f.pin_memory(), cell.pin_memory())))
+            self.footprints.append(b.scene_footprint_bytes(s, compensated=compensated, with_id=with_id))
         self.compensated = compensated
         self.device = device
 
@@ -95,6 +100,10 @@ class Pool:
 
     def particles(self, k: int) -> int:
         return self.templates[k][0].n
+
+    def footprint(self, k: int) -> int:
+        """Device bytes a request on pool entry k holds while resident."""
+        return self.footprints[k]
 
 
 @dataclasses.dataclass
@@ -117,12 +126,31 @@ def _wait_until(t0: float, t: float) -> None:
         time.sleep(dt)
 
 
+def admit(pending, now: float, n_active: int, used: int, footprint, max_active: int, budget: int):
+    """Admission of the batch server: pops from the head of `pending` (in
+    arrival order) the requests that have arrived by `now`, while the number
+    of resident requests stays within `max_active` and their footprints
+    (`footprint(pool_index)` bytes each) within `budget`.  The head is never
+    overtaken; a request larger than the whole budget is admitted alone when
+    nothing else is resident.  Returns (admitted requests, bytes in use)."""
+    out = []
+    while pending and pending[0].arrival <= now and n_active + len(out) < max_active:
+        fp = footprint(pending[0].pool_index)
+        if used + fp > budget and n_active + len(out) > 0:
+            break
+        out.append(pending.popleft())
+        used += fp
+    return out, used
+
+
 class BatchServer:
     def __init__(self, pool, quantum: int = 10, max_active: int = 256, compensated: bool = True,
-                 device: str = "cuda", keep_scenes: bool = False):
+                 device: str = "cuda", keep_scenes: bool = False, mem_budget: Optional[int] = None):
         self.pool = pool if isinstance(pool, Pool) else Pool(pool, compensated, device)
         self.quantum = int(quantum)
         self.max_active = int(max_active)
+        # device memory for resident requests: by default 80 % of what is free now
+        self.mem_budget = int(mem_budget if mem_budget is not None else 0.8 * torch.cuda.mem_get_info()[0])
         self.keep = keep_scenes
         self.bbytes = b.apic_batch_workspace_bytes(self.max_active)
         self.bws = torch.empty(self.bbytes + 256, dtype=torch.uint8, device=device)
@@ -133,12 +161,14 @@ class BatchServer:
         active: List[Request] = []
         done: List[Request] = []
         work = 0.0
+        used = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while pending or active:
             now = time.perf_counter() - t0
-            while pending and pending[0].arrival <= now and len(active) < self.max_active:
-                r = pending.popleft()
+            admitted, used = admit(pending, now, len(active), used, self.pool.footprint, self.max_active,
+                                   self.mem_budget)
+            for r in admitted:
                 r.scene = self.pool.instantiate(r.pool_index)
                 r.left = r.steps
                 r.start = now
@@ -156,6 +186,7 @@ class BatchServer:
                 work += r.scene.n * q
                 if r.left == 0:
                     r.finish = now
+                    used -= self.pool.footprint(r.pool_index)
                     if not self.keep:
                         r.scene = None
                     done.append(r)
