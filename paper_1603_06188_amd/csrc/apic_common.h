@@ -230,14 +230,16 @@ __host__ __device__ __forceinline__ int64_t node_index(const int *c, const int *
 // tile id -> coordinates of its first node / key
 template <int DIM>
 __host__ __device__ __forceinline__ void tile_origin(int64_t t, const int *TN, int *c) {
+    // tile ids fit 32 bits: the padded node count 64 x tiles is below 2^32 (checked on the host)
     constexpr int TE = DIM == 3 ? 4 : 8;
-    c[0] = (int)(t % TN[0]) * TE;
+    const uint32_t u = (uint32_t)t, n0 = (uint32_t)TN[0];
+    c[0] = (int)(u % n0) * TE;
     if constexpr (DIM == 3) {
-        int64_t r = t / TN[0];
-        c[1] = (int)(r % TN[1]) * TE;
-        c[2] = (int)(r / TN[1]) * TE;
+        const uint32_t r = u / n0, n1 = (uint32_t)TN[1];
+        c[1] = (int)(r % n1) * TE;
+        c[2] = (int)(r / n1) * TE;
     } else {
-        c[1] = (int)(t / TN[0]) * TE;
+        c[1] = (int)(u / n0) * TE;
     }
 }
 
