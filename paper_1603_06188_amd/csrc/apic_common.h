@@ -342,24 +342,30 @@ __device__ __forceinline__ float floor_t<float>(float x) { return floorf(x); }
 template <>
 __device__ __forceinline__ double floor_t<double>(double x) { return floor(x); }
 
-// Scene of block b in a batched launch: the largest s with start[s] <= b.
-__device__ __forceinline__ int scene_of_block(const int32_t *start, int n, uint32_t b) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((uint32_t)start[mid] <= b)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
 // wave64 helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// Scene of block b in a batched launch: the largest s < n with
+// start[s] <= b (start ascending, start[0] = 0).  Wave-wide: the 64 lanes
+// test 64 evenly spaced entries of the remaining range at once, so the
+// search takes ceil(log64 n) dependent loads (two up to 4096 scenes).
+__device__ __forceinline__ int scene_of_block(const int32_t *start, int n, uint32_t b) {
+    const int lane = lane_id();
+    int lo = 0, len = n;  // the answer lies in [lo, lo + len)
+    while (len > 1) {
+        const int step = (len + 63) / 64;
+        const int idx = lo + lane * step;
+        const uint64_t m = ballot(idx < lo + len && (uint32_t)start[idx] <= b);
+        const int k = 63 - __builtin_clzll(m);  // lane 0 holds start[lo] <= b
+        const int end = lo + len;
+        lo += k * step;
+        len = end - lo < step ? end - lo : step;
+    }
+    return lo;
+}
 
 // Workgroups go to the 8 XCDs round-robin (hardware block b on XCD b % 8),
 // and each XCD has an L2 of its own.  This renumbering gives the blocks of
