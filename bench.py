@@ -319,7 +319,7 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom),
+            "traffic": None if args.fused else measured_traffic(dom),  # counters cover the unfused kernels
         },
     }
     if not args.no_serve:
