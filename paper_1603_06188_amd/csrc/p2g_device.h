@@ -218,21 +218,6 @@ struct SlabLds {
     }
 };
 
-// Slab (LDS) update of one node from this lane: plain, or two-sum with an
-// error plane when compensated.
-template <typename T, bool COMP, int RN, int NC>
-__device__ __forceinline__ void slab_add(T *lds, int comp, int idx, T x) {
-    T *hi = lds + comp * RN + idx;
-    if constexpr (!COMP) {
-        *hi += x;
-    } else {
-        const T a = *hi;
-        const T s = a + x;
-        *hi = s;
-        lds[(NC + comp) * RN + idx] += two_sum_err(a, x, s);
-    }
-}
-
 // All NC planes of one node: every read first, then the sums and writes
 // (one wait for the LDS per node instead of one per plane).
 template <typename T, bool COMP, int LP, int NC>

@@ -146,7 +146,7 @@ def admit(pending, now: float, n_active: int, used: int, footprint, max_active: 
 class BatchServer:
     def __init__(self, pool, quantum: int = 10, max_active: int = 256, compensated: bool = True,
                  device: str = "cuda", keep_scenes: bool = False, mem_budget: Optional[int] = None):
-        self.pool = pool if isinstance(pool, Pool) else Pool(pool, compensated, device)
+        self.pool = pool if hasattr(pool, "instantiate") else Pool(pool, compensated, device)
         self.quantum = int(quantum)
         self.max_active = int(max_active)
         # device memory for resident requests: by default 80 % of what is free now
@@ -199,7 +199,7 @@ class BatchServer:
 
 class SequentialServer:
     def __init__(self, pool, compensated: bool = True, device: str = "cuda", keep_scenes: bool = False):
-        self.pool = pool if isinstance(pool, Pool) else Pool(pool, compensated, device)
+        self.pool = pool if hasattr(pool, "instantiate") else Pool(pool, compensated, device)
         self.keep = keep_scenes
 
     def run(self, trace: List[Request]) -> ServeStats:

@@ -1,4 +1,5 @@
-"""Arrival traces of the serving replay (host logic, no GPU)."""
+"""Host logic of the serving replay (arrival traces, admission, the server
+loops against a fake device): no GPU."""
 import numpy as np
 
 
@@ -38,3 +39,60 @@ def test_scene_footprint_covers_planes_and_workspace():
     fp = b.scene_footprint_bytes(s, compensated=True, with_id=False)
     ws = b.apic_workspace_bytes(b.grid_desc(s, compensated=True), s.n)
     assert fp >= ws + s.n * (25 * 4 + 4)
+
+
+class _FakeScene:
+    def __init__(self, n):
+        self.n = n
+        self.s = object()
+        self.steps = 0
+
+    def step(self, k):
+        self.steps += k
+
+
+class _FakePool:
+    """Pool interface of serve.Pool without device memory."""
+    sizes = [1000, 5000, 20000]
+
+    def __len__(self):
+        return len(self.sizes)
+
+    def footprint(self, k):
+        return self.sizes[k] * 200
+
+    def particles(self, k):
+        return self.sizes[k]
+
+    def instantiate(self, k):
+        return _FakeScene(self.sizes[k])
+
+
+def test_server_loops_on_a_fake_device(monkeypatch):
+    """Every request is admitted, advanced by exactly its steps and retired;
+    the batch loop never holds more than max_active scenes or steps past a
+    request's remaining count."""
+    import torch
+    from paper_1603_06188_amd import serve
+    calls = []
+    resident = {}
+
+    def fake_step_batch(scenes, n_steps, ptr, nbytes, stream=None):
+        calls.append((len(scenes), n_steps))
+        for sc in scenes:
+            resident[id(sc)] = resident.get(id(sc), 0) + n_steps
+
+    monkeypatch.setattr(serve.b, "apic_step_batch", fake_step_batch)
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a: None)
+    trace = serve.poisson_trace(rate=2000.0, duration=0.02, pool_size=3, seed=3, steps_lo=20, steps_hi=45)
+    assert len(trace) > 10
+    pool = _FakePool()
+    srv = serve.BatchServer(pool, quantum=10, max_active=4, device="cpu", mem_budget=6_000_000, keep_scenes=True)
+    st = srv.run(trace)
+    assert len(st.latencies) == len(trace) and (st.latencies >= 0).all()
+    assert st.particle_updates == sum(pool.sizes[r.pool_index] * r.steps for r in trace)
+    assert all(1 <= n <= 4 and 1 <= q <= 10 for n, q in calls)
+    assert sorted(resident.values()) == sorted(r.steps for r in trace)
+    seq = serve.SequentialServer(pool, keep_scenes=True).run(
+        [serve.Request(rid=r.rid, arrival=r.arrival, pool_index=r.pool_index, steps=r.steps) for r in trace])
+    assert len(seq.latencies) == len(trace) and seq.particle_updates == st.particle_updates
