@@ -39,15 +39,23 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 
 // New velocity v = sum_i w_i vt_i with a fixed operation sequence, shared
 // by both passes: first the x-axis sums Tx_k(a) = sum_{c,b} (wy(b) wz(c))
-// vt_k(a,b,c), nodes in (c, b) order, then v_k = sum_a wx(a) Tx_k(a).
+// (vt_k(a,b,c) - c_k), nodes in (c, b) order, then
+// v_k = c_k + sum_a wx(a) Tx_k(a).  The reference velocity c (the grid
+// velocity at the particle's base node) is taken out of every node value
+// before the sums: with sum_i w_i = 1, sum_i w_i (x_i - x_p) = 0 and
+// sum_i grad w_i = 0 (Sec. 3.5) it changes none of v, B or grad v, but a
+// large common velocity no longer costs binary32 digits in B and grad v,
+// which are differences of such sums.
 template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], const T (&w)[DIM][DEG + 1], T *vn) {
+__device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], const T (&w)[DIM][DEG + 1],
+                                                 const T *cref, T *vn) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        vn[k] = T(0);
+        T s = T(0);
 #pragma unroll
-        for (int a = 0; a < DEG + 1; ++a) vn[k] = fma_t(w[0][a], tx[k][a], vn[k]);
+        for (int a = 0; a < DEG + 1; ++a) s = fma_t(w[0][a], tx[k][a], s);
+        vn[k] = cref[k] + s;
     }
 }
 
@@ -215,11 +223,13 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
     //   v_k = sum_a wx Tx_k(a),
     //   B_k0 = sum_a wx rx Tx_k(a), grad v_k0 = sum_a dwx Tx_k(a),
     // and likewise along y and z.
-    T Tx[DIM][K], Ty[DIM][K], Tz[DIM][K];
+    T Tx[DIM][K], Ty[DIM][K], Tz[DIM][K], cref[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k)
+    for (int k = 0; k < DIM; ++k) {
+        cref[k] = reg[k * R::SIZE + R::at(lk[0], lk[1], DIM == 3 ? lk[2] : 0)];
 #pragma unroll
         for (int ii = 0; ii < K; ++ii) Tx[k][ii] = Ty[k][ii] = Tz[k][ii] = T(0);
+    }
     {
 #pragma clang fp contract(off)
 #pragma unroll
@@ -234,7 +244,7 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
                     const int idx = R::at(lk[0] + a, lk[1] + b, DIM == 3 ? lk[2] + c : 0);
 #pragma unroll
                     for (int k = 0; k < DIM; ++k) {
-                        const T x = reg[k * R::SIZE + idx];
+                        const T x = reg[k * R::SIZE + idx] - cref[k];
                         Tx[k][a] = fma_t(wyz, x, Tx[k][a]);
                         Ty[k][b] = fma_t(wxz, x, Ty[k][b]);
                         if constexpr (DIM == 3) Tz[k][c] = fma_t(wxy, x, Tz[k][c]);
@@ -252,7 +262,7 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
                     }
             }
     }
-    velocity_from_tx<T, DIM, DEG>(Tx, wf, vn);
+    velocity_from_tx<T, DIM, DEG>(Tx, wf, cref, vn);
     // B and grad v (cell units) from the axis sums; weight
     // derivatives and node offsets from the offsets
     T Gc[DIM * DIM];
@@ -326,11 +336,13 @@ __device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const 
 #pragma clang fp contract(off)
     constexpr int K = DEG + 1;
     using R = VtRegion<DIM>;
-    T tx[DIM][K];
+    T tx[DIM][K], cref[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k)
+    for (int k = 0; k < DIM; ++k) {
+        cref[k] = reg[k * R::SIZE + R::at(lk[0], lk[1], DIM == 3 ? lk[2] : 0)];
 #pragma unroll
         for (int a = 0; a < K; ++a) tx[k][a] = T(0);
+    }
 #pragma unroll
     for (int c = 0; c < (DIM == 3 ? K : 1); ++c)
 #pragma unroll
@@ -340,10 +352,11 @@ __device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const 
             for (int a = 0; a < K; ++a) {
                 const int idx = R::at(lk[0] + a, lk[1] + b, DIM == 3 ? lk[2] + c : 0);
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) tx[k][a] = fma_t(wyz, reg[k * R::SIZE + idx], tx[k][a]);
+                for (int k = 0; k < DIM; ++k)
+                    tx[k][a] = fma_t(wyz, reg[k * R::SIZE + idx] - cref[k], tx[k][a]);
             }
         }
-    velocity_from_tx<T, DIM, DEG>(tx, w, vn);
+    velocity_from_tx<T, DIM, DEG>(tx, w, cref, vn);
 }
 
 }  // namespace apic
