@@ -264,6 +264,10 @@ def main(argv=None):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     flags = ds.flags()
+    # the CFL rule of Sec. 4.3 on the state the timed steps produced (outside the timed region)
+    t1 = time.perf_counter()
+    cfl_dt = ds.cfl_dt()
+    cfl_ms = (time.perf_counter() - t1) * 1e3
     # the same K steps again from the same state, the library bracketing every
     # phase with HIP events on this stream: per-kernel durations for the roofline
     ds.upload(scene)
@@ -311,6 +315,7 @@ def main(argv=None):
             **({"fused_transfer": True} if args.fused else {}),
         },
         "phase_ms": {p: round(dur[p], 5) for p in phases},
+        "cfl": {"dt_max": cfl_dt, "call_ms": round(cfl_ms, 4)},
         "flags": flags,
         "roofline": {
             "bound": "hbm",

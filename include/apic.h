@@ -16,8 +16,8 @@
  *     caller; the library borrows it for the duration of the call (and of the
  *     work that call enqueues).  The library never allocates device memory.
  *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
- *     Every call is asynchronous on that stream except apic_diagnostics and
- *     apic_get_flags, which synchronize it.
+ *     Every call is asynchronous on that stream except apic_diagnostics,
+ *     apic_cfl_dt and apic_get_flags, which synchronize it.
  *   - Errors: a call returns APIC_OK or a negative apic_status.  Argument
  *     errors are detected on the host before anything is enqueued and leave
  *     all buffers untouched; apic_last_error() then returns a message (per
@@ -251,6 +251,17 @@ apic_status apic_grid_export(const apic_scene *scene, int32_t field, void *out, 
  * mass.  `out` is a HOST array of 8 doubles.  Synchronizes `stream`.
  */
 apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out, void *stream);
+
+/*
+ * Largest time step the CFL rule of Sec. 4.3 admits for the scene's current
+ * particle state:
+ *   *dt_out = nu * dx / max_p (|v_p| + (6 sqrt(d) / dx) |B_p|_F)
+ * (the paper bounds every grid velocity the next transfer can produce by
+ * that maximum; kappa dx / k = 6 sqrt(d) / dx for both kernels), evaluated
+ * in binary64 over all n particles.  *dt_out is +inf when every particle is
+ * at rest.  nu must be positive and finite.  Synchronizes `stream`.
+ */
+apic_status apic_cfl_dt(const apic_scene *scene, double nu, double *dt_out, void *stream);
 
 /* Reads (host *flags) / clears the sticky flag word.  get synchronizes. */
 apic_status apic_get_flags(const apic_scene *scene, uint32_t *flags, void *stream);

@@ -39,7 +39,7 @@ APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
 
 EXPORTED = [
     "apic_workspace_bytes", "apic_reset", "apic_sort", "apic_p2g", "apic_grid_update", "apic_g2p", "apic_step",
-    "apic_batch_workspace_bytes", "apic_step_batch", "apic_grid_export", "apic_diagnostics", "apic_get_flags", "apic_clear_flags",
+    "apic_batch_workspace_bytes", "apic_step_batch", "apic_grid_export", "apic_diagnostics", "apic_cfl_dt", "apic_get_flags", "apic_clear_flags",
     "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
     "apic_last_error", "apic_version",
 ]
@@ -82,6 +82,7 @@ _sigs = {
     "apic_step_batch": [_S, ctypes.c_int32, ctypes.c_int32, _V, ctypes.c_size_t, _V],
     "apic_grid_export": [_S, ctypes.c_int32, _V, _V],
     "apic_diagnostics": [_S, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _V],
+    "apic_cfl_dt": [_S, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _V],
     "apic_get_flags": [_S, ctypes.POINTER(ctypes.c_uint32), _V],
     "apic_clear_flags": [_S, _V],
     "apic_positions_from_absolute": [_S, _V, _V],
@@ -172,6 +173,12 @@ def apic_diagnostics(scene: ApicScene, which: int, stream=None) -> np.ndarray:
     out = (ctypes.c_double * 8)()
     _check(_lib.apic_diagnostics(ctypes.byref(scene), int(which), out, _stream(stream)))
     return np.array(out[:], dtype=np.float64)
+
+
+def apic_cfl_dt(scene: ApicScene, nu: float = 1.0, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(_lib.apic_cfl_dt(ctypes.byref(scene), float(nu), ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def apic_get_flags(scene: ApicScene, stream=None) -> int:
@@ -371,6 +378,10 @@ class DeviceScene:
 
     def diagnostics(self, which=APIC_DIAG_PARTICLES):
         return apic_diagnostics(self.s, which)
+
+    def cfl_dt(self, nu=1.0):
+        """Largest dt the CFL rule of Sec. 4.3 admits for the current state."""
+        return apic_cfl_dt(self.s, nu)
 
     def flags(self):
         return apic_get_flags(self.s)

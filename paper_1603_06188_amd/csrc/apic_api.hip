@@ -430,7 +430,7 @@ SceneState &state_of(const apic_scene *s, int64_t cap, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Typed operations
 // ---------------------------------------------------------------------------
-enum class Op { Sort, P2G, GridUpdate, G2P, Export, DiagParticles, DiagGrid, Pack, Unpack };
+enum class Op { Sort, P2G, GridUpdate, G2P, Export, DiagParticles, DiagGrid, Cfl, Pack, Unpack };
 
 struct OpArgs {
     void *ptr;
@@ -548,6 +548,9 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
             break;
         case Op::DiagParticles:
             launch_diag_particles<T, DIM>(v.user, s->grid.dx, v.diag_part, v.diag_out, st);
+            break;
+        case Op::Cfl:
+            launch_cfl_bound<T, DIM>(v.user, s->grid.dx, v.diag_part, v.diag_out, st);
             break;
         case Op::DiagGrid:
             if (ss.grid_meta < 0) return fail(APIC_E_INVAL, "no grid yet: call apic_p2g first");
@@ -937,6 +940,26 @@ apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out
                    "apic_diagnostics copy");
     if (rc != APIC_OK) return rc;
     return hip_check(hipStreamSynchronize(st), "apic_diagnostics sync");
+}
+
+apic_status apic_cfl_dt(const apic_scene *scene, double nu, double *dt_out, void *stream) {
+    if (!dt_out) return fail(APIC_E_INVAL, "dt_out is NULL");
+    if (!(nu > 0.0) || !isfinite(nu)) return fail(APIC_E_INVAL, "nu must be positive and finite");
+    apic_status rc = dispatch(Op::Cfl, scene, stream);
+    if (rc != APIC_OK) return rc;
+    int64_t cap = 0;
+    (void)check_scene(scene, &cap);
+    const Layout L = make_layout(&scene->grid, cap);
+    hipStream_t st = (hipStream_t)stream;
+    double worst = 0.0;
+    rc = hip_check(hipMemcpyAsync(&worst, (char *)scene->workspace + L.o_diag_out, sizeof(double),
+                                  hipMemcpyDeviceToHost, st),
+                   "apic_cfl_dt copy");
+    if (rc != APIC_OK) return rc;
+    rc = hip_check(hipStreamSynchronize(st), "apic_cfl_dt sync");
+    if (rc != APIC_OK) return rc;
+    *dt_out = worst == 0.0 ? INFINITY : nu * scene->grid.dx / worst;
+    return APIC_OK;
 }
 
 apic_status apic_get_flags(const apic_scene *scene, uint32_t *flags, void *stream) {

@@ -107,6 +107,10 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
 template <typename T, int DIM>
 void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);
 
+// max_p (|v_p| + 6 sqrt(d)/dx |B_p|_F) in binary64 into out[0] (Sec. 4.3).
+template <typename T, int DIM>
+void launch_cfl_bound(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);
+
 template <typename T, int DIM, int DEG, bool COMP>
 void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState<T> &g, int which, double dt,
                       double *partials, double *out, hipStream_t st);

@@ -119,6 +119,55 @@ void launch_diag_particles(const Parts<T> &P, double dx, double *partials, doubl
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, nb, out);
 }
 
+// --- CFL bound (Sec. 4.3) -----------------------------------------------------------
+// max_p (|v_p| + c |B_p|_F), c = 6 sqrt(d) / dx, in binary64: per block into
+// partials[block], then one block reduces them into out[0].
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_cfl_bound(Parts<T> P, double c, double *partials) {
+    __shared__ double sh[4];
+    double worst = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += (int64_t)gridDim.x * blockDim.x) {
+        double vv = 0.0, bb = 0.0;
+        for (int a = 0; a < DIM; ++a) {
+            const double x = (double)P.v[a * P.s + p];
+            vv += x * x;
+        }
+        for (int k = 0; k < DIM * DIM; ++k) {
+            const double x = (double)P.B[k * P.s + p];
+            bb += x * x;
+        }
+        const double u = sqrt(vv) + c * sqrt(bb);
+        worst = u > worst || u != u ? u : worst;  // a NaN state propagates
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_down(worst, o, 64);
+        worst = y > worst || y != y ? y : worst;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = worst;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = sh[w] > m || sh[w] != sh[w] ? sh[w] : m;
+        partials[blockIdx.x] = m;
+    }
+}
+
+__global__ void k_cfl_final(const double *partials, int nb, double *out) {
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int b = 0; b < nb; ++b) m = partials[b] > m || partials[b] != partials[b] ? partials[b] : m;
+        out[0] = m;
+    }
+}
+
+template <typename T, int DIM>
+void launch_cfl_bound(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st) {
+    const int nb = blocks_for(P.n, 256, kDiagBlocks);
+    const double c = 6.0 * sqrt((double)DIM) / dx;
+    hipLaunchKernelGGL((k_cfl_bound<T, DIM>), dim3(nb), dim3(256), 0, st, P, c, partials);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, partials, nb, out);
+}
+
 // --- absolute positions <-> cell + offset ---------------------------------------
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_pack_positions(Parts<T> P, const double *x, double inv_dx) {
@@ -165,6 +214,7 @@ void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_
 #define APIC_MISC_INST(T, DIM)                                                                                  \
     template void launch_copy_state<T, DIM>(const Parts<T> &, const Parts<T> &, hipStream_t);                    \
     template void launch_diag_particles<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);     \
+    template void launch_cfl_bound<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);         \
     template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t);         \
     template void launch_unpack_positions<T, DIM>(const Parts<T> &, double *, double, hipStream_t);
 APIC_MISC_INST(float, 2)

@@ -302,3 +302,23 @@ def test_invalid_arguments_are_rejected():
     ds.s.workspace_bytes = 16
     with pytest.raises(b.ApicError):
         ds.p2g()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cfl_dt_matches_oracle(precision):
+    """apic_cfl_dt (Sec. 4.3) against the oracle's rule on the same particle
+    state, before and after a step; the binary32 state is promoted exactly,
+    so both sides reduce the same numbers in binary64."""
+    b = _b()
+    s = scenes.random_particles(5000, dim=3, cells=16, degree=2, seed=61, precision=precision, b_sigma=0.05,
+                                vel_sigma=0.4, model=0)
+    ds = b.DeviceScene(s)
+    assert ds.cfl_dt(0.5) == pytest.approx(oracle.cfl_dt(s.dx, s.v, s.B, nu=0.5), rel=1e-14)
+    ds.step(1)
+    got = ds.state()
+    v, B = np.ascontiguousarray(got["v"]), np.ascontiguousarray(got["B"])
+    assert ds.cfl_dt() == pytest.approx(oracle.cfl_dt(s.dx, v, B), rel=1e-14)
+    with pytest.raises(b.ApicError):
+        ds.cfl_dt(0.0)
+    rest = b.DeviceScene(s.with_state(v=0 * s.v, B=0 * s.B))
+    assert rest.cfl_dt() == float("inf")
