@@ -14,9 +14,11 @@ cites the passage of the paper it follows:
   Piola-Kirchhoff stress of Sec. 3.1 (the neo-Hookean form is a reading: the
   paper names the model in Sec. 6 without writing it)
 * ``p2g``                              -- transfer to grid, Sec. 3.2, plus the
-  force of Sec. 3.3 at F^{n+lambda} = F^n (lambda = 0)
+  force of Sec. 3.3 at F^{n+lambda} = F^n (lambda = 0); ``transfer`` selects
+  APIC, RPIC (Sec. 2.1) or PIC, the three cases of Sec. 5.6
 * ``grid_update``                      -- grid evolution of Sec. 3.3, lambda = 0
-* ``g2p``                              -- transfer to particles, Sec. 3.4
+* ``g2p``                              -- transfer to particles, Sec. 3.4 (RPIC:
+  Sec. 2.1 with K_p and l_p as in Sec. 5.1; PIC: no affine part)
 * ``particle_totals`` / ``grid_totals`` -- momenta of Sec. 3.1 with the
   particle angular momentum of Sec. 5.3 (B term included)
 * ``cfl_dt``                           -- CFL rule of Sec. 4.3
@@ -38,6 +40,11 @@ OR_E_ARG = -1
 OR_E_DOMAIN = -2
 OR_E_SINGULAR = -3
 OR_E_INVERTED = -4
+
+# transfer variants of Sec. 5.6: the affine part C_p is full, skew or zero
+TRANSFER_APIC = 0
+TRANSFER_RPIC = 1
+TRANSFER_PIC = 2
 
 _ERRORS = {
     OR_E_ARG: "invalid argument",
@@ -90,11 +97,11 @@ def _load():
         lib.oracle_neo_hookean_P.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp]
         lib.oracle_p2g.restype = ctypes.c_int
         lib.oracle_p2g.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
-                                   ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp]
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp, _dp]
         lib.oracle_grid_update.restype = ctypes.c_int
         lib.oracle_grid_update.argtypes = [G, _dp, _dp, _dp, ctypes.c_double, _dp, _ip, _dp, _dp, _dp]
         lib.oracle_g2p.restype = ctypes.c_int
-        lib.oracle_g2p.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.oracle_g2p.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
         lib.oracle_particle_totals.restype = None
         lib.oracle_particle_totals.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp]
         lib.oracle_grid_totals.restype = None
@@ -198,8 +205,10 @@ def det(A) -> float:
 
 
 def p2g(grid: Grid, x, v, B, F, m, V, model: int = 0, mu: float = 0.0, lam: float = 0.0,
-        want_D: bool = False):
+        want_D: bool = False, *, transfer: int = TRANSFER_APIC):
     """Transfer to grid (Sec. 3.2) plus the force f_i of Sec. 3.3 (model 1).
+    ``transfer`` selects C_p = B_p D_p^{-1} (APIC), its rotation (RPIC) or
+    zero (PIC), Sec. 5.6.
 
     Returns dict with node-major ``m`` (nodes), ``mv`` (nodes, d), ``f``
     (nodes, d) and optionally ``D`` (np, d, d)."""
@@ -212,7 +221,7 @@ def p2g(grid: Grid, x, v, B, F, m, V, model: int = 0, mu: float = 0.0, lam: floa
     gf = np.zeros((nn, d))
     D = np.zeros((max(npart, 1), d, d)) if want_D else None
     _check(_load().oracle_p2g(grid.ref(), npart, _ptr(x), _ptr(v), _ptr(B), _ptr(F), _ptr(m), _ptr(V),
-                              int(model), float(mu), float(lam), _ptr(gm), _ptr(gmv), _ptr(gf),
+                              int(model), float(mu), float(lam), int(transfer), _ptr(gm), _ptr(gmv), _ptr(gf),
                               _ptr(D) if want_D else None))
     out = {"m": gm, "mv": gmv, "f": gf}
     if want_D:
@@ -238,24 +247,26 @@ def grid_update(grid: Grid, gm, gmv, gf, dt: float, gravity=None, band=None):
     return {"v": gv, "vt": gvt, "xt": gxt}
 
 
-def g2p(grid: Grid, x, F, gvt, gxt):
-    """Transfer to particles (Sec. 3.4) with the weights of time n."""
+def g2p(grid: Grid, x, F, gvt, gxt, *, transfer: int = TRANSFER_APIC):
+    """Transfer to particles (Sec. 3.4) with the weights of time n; the affine
+    state B_p is that of APIC, RPIC (Sec. 2.1) or PIC (zero) per ``transfer``."""
     d = grid.dim
     x, F, gvt, gxt = (_d(a) for a in (x, F, gvt, gxt))
     npart = x.shape[0]
     xo, vo = np.zeros((npart, d)), np.zeros((npart, d))
     Bo, Fo = np.zeros((npart, d, d)), np.zeros((npart, d, d))
-    _check(_load().oracle_g2p(grid.ref(), npart, _ptr(x), _ptr(F), _ptr(gvt), _ptr(gxt),
+    _check(_load().oracle_g2p(grid.ref(), npart, _ptr(x), _ptr(F), _ptr(gvt), _ptr(gxt), int(transfer),
                               _ptr(xo), _ptr(vo), _ptr(Bo), _ptr(Fo)))
     return {"x": xo, "v": vo, "B": Bo, "F": Fo}
 
 
-def step(grid: Grid, x, v, B, F, m, V, model=0, mu=0.0, lam=0.0, dt=0.0, gravity=None, band=None):
+def step(grid: Grid, x, v, B, F, m, V, model=0, mu=0.0, lam=0.0, dt=0.0, gravity=None, band=None,
+         transfer=TRANSFER_APIC):
     """One explicit step: P2G, grid update, G2P.  Returns the grid stage
     arrays and the new particle state."""
-    g = p2g(grid, x, v, B, F, m, V, model, mu, lam)
+    g = p2g(grid, x, v, B, F, m, V, model, mu, lam, transfer=transfer)
     u = grid_update(grid, g["m"], g["mv"], g["f"] if model == 1 else None, dt, gravity, band)
-    p = g2p(grid, x, F, u["vt"], u["xt"])
+    p = g2p(grid, x, F, u["vt"], u["xt"], transfer=transfer)
     out = dict(g)
     out.update(u)
     out.update({"x_new": p["x"], "v_new": p["v"], "B_new": p["B"], "F_new": p["F"]})

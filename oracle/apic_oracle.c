@@ -37,6 +37,14 @@
  *   - Gravity and sticky walls are not in the paper: gravity adds dt*g to the
  *     grid velocity of every node with positive mass; a node inside a sticky
  *     band gets zero velocity.  A node with zero mass gets zero velocity.
+ *   - Transfer variants (Sec. 2.1, Sec. 5.6): the particle-to-grid form is
+ *     (m v)_ip = m_ip (v_p + C_p (x_i - x_p)) with C_p full (APIC), skew
+ *     (RPIC) or zero (PIC).  The particle state keeps the APIC variable B_p
+ *     with C_p = B_p D_p^{-1}; an RPIC particle stores B_p = omega_p^* D_p,
+ *     and a state whose C_p is not skew is read through its rotation:
+ *     omega_p = 1/2 sum eps_abc C_cb.  RPIC's grid to particle solves
+ *     omega_p = K_p^{-1} l_p; the factor m_p of K_p and l_p cancels and is
+ *     left out.  PIC stores B_p = 0.
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,6 +57,11 @@
 #define OR_E_SINGULAR (-3)   /* D_p or F_p could not be inverted             */
 #define OR_E_INVERTED (-4)   /* det F_p <= 0: ln J undefined                 */
 #define OR_E_NOMEM (-5)
+
+/* Transfer variants of Sec. 5.6: C_p full, skew or zero. */
+#define OR_TRANSFER_APIC 0
+#define OR_TRANSFER_RPIC 1
+#define OR_TRANSFER_PIC 2
 
 typedef struct {
     int32_t dim;       /* 2 or 3 */
@@ -299,6 +312,45 @@ int oracle_neo_hookean_P(int d, const double *F, double mu, double lam, double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Rigid rotations (Sec. 2.1).                                               */
+/* ------------------------------------------------------------------------ */
+
+static double levi_civita(int a, int b, int c);
+static void cross3(int d, const double *a, const double *b, double *out);
+
+/* The 3x3 matrix u^* with u^* y = u x y for every y. */
+static void cross_matrix(const double *u, double *M)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            M[r * 3 + c] = 0.0;
+            for (int a = 0; a < 3; ++a) M[r * 3 + c] += levi_civita(r, a, c) * u[a];
+        }
+}
+
+/* omega with omega^* the skew part of the d x d matrix C (d = 2: about z). */
+static void rotation_of(int d, const double *C, double *omega)
+{
+    double C3[9] = {0};
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) C3[r * 3 + c] = C[r * d + c];
+    for (int a = 0; a < 3; ++a) {
+        omega[a] = 0.0;
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) omega[a] += 0.5 * levi_civita(a, b, c) * C3[c * 3 + b];
+    }
+}
+
+/* The d x d block of omega^*. */
+static void skew_from_rotation(int d, const double *omega, double *C)
+{
+    double M[9];
+    cross_matrix(omega, M);
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) C[r * d + c] = M[r * 3 + c];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Particle to grid (Sec. 3.2) and the force of Sec. 3.3 at F^{n+0} = F^n.    */
 /* ------------------------------------------------------------------------ */
 
@@ -307,16 +359,19 @@ int oracle_neo_hookean_P(int d, const double *F, double mu, double lam, double *
  *   m_i       += w_ip m_p
  *   (m v)_i   += w_ip m_p (v_p + B_p D_p^{-1} (x_i - x_p))
  *   f_i       += -V_p P(F_p) F_p^T grad w_ip          (model == 1 only)
+ * with B_p D_p^{-1} replaced by its rotation omega_p^* (RPIC, Sec. 2.1) or
+ * by zero (PIC), as the transfer selects (Sec. 5.6).
  * Grid arrays are overwritten (zeroed first).  Particles are visited in
  * ascending order.  dp_out, when non-NULL, receives D_p (d*d per particle).
  */
 int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *v,
                const double *B, const double *F, const double *m, const double *V,
-               int model, double mu, double lam,
+               int model, double mu, double lam, int transfer,
                double *gm, double *gmv, double *gf, double *dp_out)
 {
     const int d = g->dim;
     if (d < 2 || d > 3 || (g->degree != 2 && g->degree != 3) || !(g->dx > 0.0)) return OR_E_ARG;
+    if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
     const int64_t nn = node_count(g);
     memset(gm, 0, sizeof(double) * nn);
     memset(gmv, 0, sizeof(double) * nn * d);
@@ -336,6 +391,13 @@ int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *
         if (dp_out)
             for (int k = 0; k < d * d; ++k) dp_out[p * d * d + k] = D[k];
         mat_mul(d, B + p * d * d, Dinv, C);
+        if (transfer == OR_TRANSFER_RPIC) {
+            double omega[3];
+            rotation_of(d, C, omega);
+            skew_from_rotation(d, omega, C);
+        } else if (transfer == OR_TRANSFER_PIC) {
+            for (int k = 0; k < d * d; ++k) C[k] = 0.0;
+        }
         if (model == 1) {
             double P[9], Ft[9];
             rc = oracle_neo_hookean_P(d, F + p * d * d, mu, lam, P);
@@ -422,12 +484,18 @@ int oracle_grid_update(const oracle_grid *g, const double *gm, const double *gmv
  *   B_p' = 1/2 sum_i w_ip [ vt_i (x_i - x_p + xt_i - x_p')^T
  *                          + (x_i - x_p - xt_i + x_p') vt_i^T ]
  *   F_p' = (I + sum_i (xt_i - x_i) grad w_ip^T) F_p
+ * for APIC.  RPIC (Sec. 2.1, its grid-to-particle step as written out in
+ * Sec. 5.1) replaces B_p' by omega^* D_p with
+ *   K_p = sum_i w_ip (x_i - x_p)^* (x_i - x_p)^{*T},
+ *   l_p = sum_i w_ip (x_i - x_p) x vt_i,   omega = K_p^{-1} l_p
+ * (vectors embedded in 3D when d = 2); PIC stores B_p' = 0.
  */
 int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *F,
-               const double *gvt, const double *gxt,
+               const double *gvt, const double *gxt, int transfer,
                double *x_out, double *v_out, double *B_out, double *F_out)
 {
     const int d = g->dim;
+    if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
     stencil_entry st[MAX_STENCIL];
     for (int64_t p = 0; p < np; ++p) {
         const double *xp = x + p * d;
@@ -452,6 +520,31 @@ int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *
                     Bn[r * d + c] += 0.5 * e->w * (left + right);
                     G[r * d + c] += (xt[r] - e->xi[r]) * e->gw[c];
                 }
+        }
+        if (transfer == OR_TRANSFER_RPIC) {
+            double K[9] = {0}, Kinv[9], l[3] = {0, 0, 0}, D[9] = {0}, C[9];
+            for (int j = 0; j < cnt; ++j) {
+                const stencil_entry *e = &st[j];
+                double r3[3] = {0, 0, 0}, R[9], lr[3];
+                for (int a = 0; a < d; ++a) r3[a] = e->xi[a] - xp[a];
+                cross_matrix(r3, R);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        for (int c = 0; c < 3; ++c) K[a * 3 + b] += e->w * R[a * 3 + c] * R[b * 3 + c];
+                cross3(d, r3, gvt + e->node * d, lr);
+                for (int a = 0; a < 3; ++a) l[a] += e->w * lr[a];
+                for (int r = 0; r < d; ++r)
+                    for (int c = 0; c < d; ++c) D[r * d + c] += e->w * r3[r] * r3[c];
+            }
+            int rc = mat_inverse(3, K, Kinv, NULL);
+            if (rc != OR_OK) return rc;
+            double omega[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) omega[a] += Kinv[a * 3 + b] * l[b];
+            skew_from_rotation(d, omega, C);
+            mat_mul(d, C, D, Bn);
+        } else if (transfer == OR_TRANSFER_PIC) {
+            for (int k = 0; k < d * d; ++k) Bn[k] = 0.0;
         }
         for (int a = 0; a < d; ++a) G[a * d + a] += 1.0;
         double Fn[9];
@@ -606,15 +699,15 @@ double oracle_cfl_dt(int d, double dx, double nu, int64_t np, const double *v, c
  */
 int oracle_step(const oracle_grid *g, int64_t np, const double *x, const double *v, const double *B,
                 const double *F, const double *m, const double *V, int model, double mu, double lam,
-                double dt, const double *gravity, const int32_t *band,
+                double dt, const double *gravity, const int32_t *band, int transfer,
                 double *gm, double *gmv, double *gf, double *gv, double *gvt, double *gxt,
                 double *x_out, double *v_out, double *B_out, double *F_out)
 {
-    int rc = oracle_p2g(g, np, x, v, B, F, m, V, model, mu, lam, gm, gmv, gf, NULL);
+    int rc = oracle_p2g(g, np, x, v, B, F, m, V, model, mu, lam, transfer, gm, gmv, gf, NULL);
     if (rc != OR_OK) return rc;
     rc = oracle_grid_update(g, gm, gmv, model == 1 ? gf : NULL, dt, gravity, band, gv, gvt, gxt);
     if (rc != OR_OK) return rc;
-    return oracle_g2p(g, np, x, F, gvt, gxt, x_out, v_out, B_out, F_out);
+    return oracle_g2p(g, np, x, F, gvt, gxt, transfer, x_out, v_out, B_out, F_out);
 }
 
 int64_t oracle_node_count(const oracle_grid *g) { return node_count(g); }
