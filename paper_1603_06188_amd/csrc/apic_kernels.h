@@ -104,6 +104,9 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
                             hipStream_t st);
 
 // --- observation ----------------------------------------------------------------
+// out[k] = sum over b < nb of partials[8 b + k], k < 8, in a fixed order.
+void launch_diag_final(const double *partials, int nb, double *out, hipStream_t st);
+
 template <typename T, int DIM>
 void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);
 

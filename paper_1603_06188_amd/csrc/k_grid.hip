@@ -320,14 +320,6 @@ __global__ __launch_bounds__(256) void k_diag_grid(BinLists gm, Slabs<T> slabs, 
     block_reduce8(acc, partials);
 }
 
-__global__ void k_diag_final_grid(const double *partials, int nb, double *out) {
-    if (threadIdx.x < 8) {
-        double t = 0.0;
-        for (int b = 0; b < nb; ++b) t += partials[b * 8 + threadIdx.x];
-        out[threadIdx.x] = t;
-    }
-}
-
 template <typename T, int DIM, int DEG, bool COMP>
 void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState<T> &g, int which, double dt,
                       double *partials, double *out, hipStream_t st) {
@@ -336,7 +328,7 @@ void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState
     const int nb = blocks_for(count, 256, kDiagBlocks);
     hipLaunchKernelGGL((k_diag_grid<T, DIM, DEG, COMP>), dim3(nb), dim3(256), 0, st, gm, slabs, g, which, dt,
                        partials);
-    hipLaunchKernelGGL(k_diag_final_grid, dim3(1), dim3(64), 0, st, partials, nb, out);
+    launch_diag_final(partials, nb, out, st);
 }
 
 #define APIC_GRID_INST(T, DIM, DEG, COMP)                                                                         \

@@ -104,19 +104,29 @@ __global__ __launch_bounds__(256) void k_diag_particles(Parts<T> P, double dx, d
     block_reduce8p(acc, partials);
 }
 
-__global__ void k_diag_final(const double *partials, int nb, double *out) {
-    if (threadIdx.x < 8) {
+// One wavefront: lane l sums the partials of blocks l, l + 64, ... in that
+// order, then a fixed shuffle tree adds the lanes, so the result does not
+// depend on timing.
+__global__ __launch_bounds__(64) void k_diag_final(const double *partials, int nb, double *out) {
+    const int lane = (int)threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
         double t = 0.0;
-        for (int b = 0; b < nb; ++b) t += partials[b * 8 + threadIdx.x];
-        out[threadIdx.x] = t;
+        for (int b = lane; b < nb; b += 64) t += partials[b * 8 + k];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
+        if (lane == 0) out[k] = t;
     }
+}
+
+void launch_diag_final(const double *partials, int nb, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, nb, out);
 }
 
 template <typename T, int DIM>
 void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st) {
     const int nb = blocks_for(P.n, 256, kDiagBlocks);
     hipLaunchKernelGGL((k_diag_particles<T, DIM>), dim3(nb), dim3(256), 0, st, P, dx, partials);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, nb, out);
+    launch_diag_final(partials, nb, out, st);
 }
 
 // --- CFL bound (Sec. 4.3) -----------------------------------------------------------
@@ -152,12 +162,19 @@ __global__ __launch_bounds__(256) void k_cfl_bound(Parts<T> P, double c, double 
     }
 }
 
-__global__ void k_cfl_final(const double *partials, int nb, double *out) {
-    if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int b = 0; b < nb; ++b) m = partials[b] > m || partials[b] != partials[b] ? partials[b] : m;
-        out[0] = m;
+// One wavefront: a lane-strided max, then a shuffle tree (max is exact in any order).
+__global__ __launch_bounds__(64) void k_cfl_final(const double *partials, int nb, double *out) {
+    const int lane = (int)threadIdx.x;
+    double m = 0.0;
+    for (int b = lane; b < nb; b += 64) {
+        const double y = partials[b];
+        m = y > m || y != y ? y : m;
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_down(m, o, 64);
+        m = y > m || y != y ? y : m;
+    }
+    if (lane == 0) out[0] = m;
 }
 
 template <typename T, int DIM>
