@@ -63,6 +63,21 @@ enum { APIC_QUADRATIC = 2, APIC_CUBIC = 3 };      /* B-spline degree (Sec. 3.5) 
 enum { APIC_F32 = 0, APIC_F64 = 1 };              /* element type of planes    */
 enum { APIC_MODEL_NONE = 0, APIC_MODEL_NEO_HOOKEAN = 1 };
 
+/*
+ * apic_params.transfer: the affine part C_p of the particle velocity field
+ * that the transfers carry (Sec. 5.6: full, skew or zero).
+ *   APIC_TRANSFER_APIC  C_p = B_p D_p^{-1} (Sec. 3.2, Sec. 3.4).
+ *   APIC_TRANSFER_RPIC  rigid: C_p is the angular velocity omega_p^* that
+ *                       conserves the grid's angular momentum (Sec. 2.1);
+ *                       B_p holds omega_p^* D_p, the skew part of what APIC
+ *                       would store, and the transfer to grid uses the skew
+ *                       part of the B_p it is given.
+ *   APIC_TRANSFER_PIC   C_p = 0: the transfer to grid ignores B_p and the
+ *                       transfer to particles stores B_p = 0.
+ * Positions and F are updated the same way in all three.
+ */
+enum { APIC_TRANSFER_APIC = 0, APIC_TRANSFER_RPIC = 1, APIC_TRANSFER_PIC = 2 };
+
 /* apic_grid_desc.options bits */
 enum {
     APIC_OPT_COMPENSATED = 1, /* accumulate grid mass/momentum with an error
@@ -113,6 +128,7 @@ typedef struct {
     double gravity[3];  /* added to the velocity of nodes with mass         */
     int32_t model;      /* APIC_MODEL_*                                     */
     int32_t band[6];    /* sticky band width in nodes: -x,+x,-y,+y,-z,+z    */
+    int32_t transfer;   /* APIC_TRANSFER_*                                  */
     double mu;          /* Lame mu of the neo-Hookean model                 */
     double lambda;      /* Lame lambda of the neo-Hookean model             */
     double rho0;        /* rest density: particle volume V_p = m_p / rho0   */

@@ -30,6 +30,7 @@ APIC_E_INVAL, APIC_E_UNSUPPORTED, APIC_E_HIP, APIC_E_WORKSPACE = -1, -2, -3, -4
 APIC_QUADRATIC, APIC_CUBIC = 2, 3
 APIC_F32, APIC_F64 = 0, 1
 APIC_MODEL_NONE, APIC_MODEL_NEO_HOOKEAN = 0, 1
+APIC_TRANSFER_APIC, APIC_TRANSFER_RPIC, APIC_TRANSFER_PIC = 0, 1, 2
 APIC_OPT_COMPENSATED = 1
 APIC_OPT_FUSED_TRANSFER = 2
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
@@ -59,7 +60,7 @@ class ApicParticles(ctypes.Structure):
 
 class ApicParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("model", ctypes.c_int32),
-                ("band", ctypes.c_int32 * 6), ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("band", ctypes.c_int32 * 6), ("transfer", ctypes.c_int32), ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("rho0", ctypes.c_double)]
 
 
@@ -300,6 +301,7 @@ class DeviceScene:
         prm.model = scene.model
         for k in range(6):
             prm.band[k] = scene.band[k]
+        prm.transfer = scene.transfer
         prm.mu = scene.mu
         prm.lambda_ = scene.lam
         prm.rho0 = scene.rho0

@@ -209,6 +209,8 @@ apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
     }
     for (int k = 0; k < 6; ++k)
         if (q.band[k] < 0) return fail(APIC_E_INVAL, "band widths must be >= 0");
+    if (q.transfer != APIC_TRANSFER_APIC && q.transfer != APIC_TRANSFER_RPIC && q.transfer != APIC_TRANSFER_PIC)
+        return fail(APIC_E_INVAL, "unknown transfer %d", q.transfer);
     if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)s->workspace) % kAlign) return fail(APIC_E_WORKSPACE, "workspace must be 256-byte aligned");
     const int64_t cap = capacity_for(&s->grid, s->workspace_bytes);
@@ -376,6 +378,7 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.prm.dt = (T)s->prm.dt;
     for (int a = 0; a < 3; ++a) v.prm.g[a] = (T)s->prm.gravity[a];
     v.prm.model = s->prm.model;
+    v.prm.transfer = s->prm.transfer;
     for (int k = 0; k < 6; ++k) v.prm.band[k] = s->prm.band[k];
     v.prm.mu = (T)s->prm.mu;
     v.prm.lam = (T)s->prm.lambda;

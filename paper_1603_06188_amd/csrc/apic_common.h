@@ -33,6 +33,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "apic.h"
+
 namespace apic {
 
 constexpr int kBuckets = 1024;   // 4 per thread of a 256-thread block
@@ -116,6 +118,7 @@ struct StepParams {
     T dt;
     T g[3];
     int model;
+    int transfer;  // APIC_TRANSFER_*
     int band[6];
     T mu, lam, inv_rho0;
 };
@@ -169,6 +172,27 @@ enum : uint32_t {
 };
 
 constexpr uint32_t kDeadKey = 0xFFFFFFFFu;
+
+// The affine state a transfer carries (Sec. 5.6): all of B (APIC), its skew
+// part (RPIC, Sec. 2.1: B = omega^* D with D a multiple of I) or none (PIC).
+template <typename T, int DIM>
+__device__ __forceinline__ void keep_affine(int transfer, T *B) {
+    if (transfer == APIC_TRANSFER_RPIC) {
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            B[r * DIM + r] = T(0);
+#pragma unroll
+            for (int c = r + 1; c < DIM; ++c) {
+                const T w = T(0.5) * (B[r * DIM + c] - B[c * DIM + r]);
+                B[r * DIM + c] = w;
+                B[c * DIM + r] = -w;
+            }
+        }
+    } else if (transfer == APIC_TRANSFER_PIC) {
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) B[k] = T(0);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Compile-time geometry per (DIM, DEG)

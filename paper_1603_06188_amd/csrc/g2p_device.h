@@ -41,11 +41,15 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 // by both passes: first the x-axis sums Tx_k(a) = sum_{c,b} (wy(b) wz(c))
 // (vt_k(a,b,c) - c_k), nodes in (c, b) order, then
 // v_k = c_k + sum_a wx(a) Tx_k(a).  The reference velocity c (the grid
-// velocity at the particle's base node) is taken out of every node value
-// before the sums: with sum_i w_i = 1, sum_i w_i (x_i - x_p) = 0 and
-// sum_i grad w_i = 0 (Sec. 3.5) it changes none of v, B or grad v, but a
-// large common velocity no longer costs binary32 digits in B and grad v,
-// which are differences of such sums.
+// velocity at the support node nearest the particle, see nearest_node) is
+// taken out of every node value before the sums: with sum_i w_i = 1,
+// sum_i w_i (x_i - x_p) = 0 and sum_i grad w_i = 0 (Sec. 3.5) it changes
+// none of v, B or grad v, but a large common velocity no longer costs
+// binary32 digits in B and grad v, which are differences of such sums.
+// The nearest node carries a weight of at least 1/8 (quadratic, 3D) or
+// about 1/9 (cubic), so c is never far out of scale with v: a corner node
+// can have a weight near zero and, if nothing else reaches it, a velocity
+// thousands of times larger than v, whose rounding would then dominate v.
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], const T (&w)[DIM][DEG + 1],
                                                  const T *cref, T *vn) {
@@ -81,6 +85,17 @@ __device__ __forceinline__ void move_position(const int *ci, const T *off, const
         cn[a] = cc;
         on[a] = o;
     }
+}
+
+// Support index of the node nearest the particle along one axis, from the
+// axis weights: the middle node for quadratic (weight >= 1/2), the heavier
+// of the middle two for cubic (weight >= 0.479).
+template <typename T, int DEG>
+__device__ __forceinline__ int nearest_node(const T (&w)[DEG + 1]) {
+    if constexpr (DEG == 2)
+        return 1;
+    else
+        return w[1] >= w[2] ? 1 : 2;
 }
 
 // Bound of max_i |vt_i| over the slots the grid update raised (wave-wide).
@@ -202,10 +217,11 @@ __device__ __forceinline__ void g2p_load(const Parts<T> &src, uint32_t p, G2PRaw
 // its key tile (`origin`: the tile's first node): new cell index and offset,
 // velocity, B (stored units) and F, and its base node relative to the tile
 // (lk).  Raises FLAG_CFL when the step exceeds one cell along an axis.
+// B keeps the part of the affine field the transfer carries (APIC_TRANSFER_*).
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *reg, const int *origin,
                                            const GridState<T> &g, T dt_inv_dx, T gs, int *lk, int *cn, T *on, T *vn,
-                                           T *Bs, T *Fn) {
+                                           T *Bs, T *Fn, int transfer) {
     constexpr int K = DEG + 1;
     using R = VtRegion<DIM>;
     int ci[3] = {0, 0, 0};
@@ -224,9 +240,11 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
     //   B_k0 = sum_a wx rx Tx_k(a), grad v_k0 = sum_a dwx Tx_k(a),
     // and likewise along y and z.
     T Tx[DIM][K], Ty[DIM][K], Tz[DIM][K], cref[DIM];
+    const int ic = R::at(lk[0] + nearest_node<T, DEG>(wf[0]), lk[1] + nearest_node<T, DEG>(wf[1]),
+                         DIM == 3 ? lk[2] + nearest_node<T, DEG>(wf[DIM - 1]) : 0);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        cref[k] = reg[k * R::SIZE + R::at(lk[0], lk[1], DIM == 3 ? lk[2] : 0)];
+        cref[k] = reg[k * R::SIZE + ic];
 #pragma unroll
         for (int ii = 0; ii < K; ++ii) Tx[k][ii] = Ty[k][ii] = Tz[k][ii] = T(0);
     }
@@ -301,6 +319,7 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
     if (cfl) atomicOr(g.flags, FLAG_CFL);
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) Bs[k] = Bc[k] * g.dx;
+    keep_affine<T, DIM>(transfer, Bs);
 }
 
 // Dead particles (chunk `c` of the dead region after `live` listed ones) are
@@ -337,9 +356,11 @@ __device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const 
     constexpr int K = DEG + 1;
     using R = VtRegion<DIM>;
     T tx[DIM][K], cref[DIM];
+    const int ic = R::at(lk[0] + nearest_node<T, DEG>(w[0]), lk[1] + nearest_node<T, DEG>(w[1]),
+                         DIM == 3 ? lk[2] + nearest_node<T, DEG>(w[DIM - 1]) : 0);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        cref[k] = reg[k * R::SIZE + R::at(lk[0], lk[1], DIM == 3 ? lk[2] : 0)];
+        cref[k] = reg[k * R::SIZE + ic];
 #pragma unroll
         for (int a = 0; a < K; ++a) tx[k][a] = T(0);
     }

@@ -160,15 +160,18 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
     }
 }
 
+// Three waves per SIMD (at most 168 VGPRs): the resolve loop keeps a
+// particle's whole support in registers, and the latency of the queue's
+// LDS traffic needs the third wave.
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) void k_bin_keys_moved(Parts<T> P, BinLists cur, TileTables ctab, GridState<T> g,
-                                                        StepParams<T> prm, BinLists nxt, BinScratch sc) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bin_keys_moved(
+    Parts<T> P, BinLists cur, TileTables ctab, GridState<T> g, StepParams<T> prm, BinLists nxt, BinScratch sc) {
     keys_body<T, DIM, DEG>(P, cur, ctab, g, prm, nxt, sc, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) void k_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
-                                                              int k) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bin_keys_moved_batch(
+    const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k);
     const SceneDesc<T> &d = *b.d;
     keys_body<T, DIM, DEG>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk, b.nblk);
@@ -241,7 +244,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 const uint32_t p = start + i;
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                 T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
-                g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn);
+                g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
                 const T *off = raw.off;
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);

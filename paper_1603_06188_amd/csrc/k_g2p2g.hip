@@ -102,7 +102,7 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
                 if (cnt > j) {
                     int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                     T on[3], vn[3], Bs[9], Fn[9];
-                    g2p_update<T, 3, DEG>(raw, L.vt, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn);
+                    g2p_update<T, 3, DEG>(raw, L.vt, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
                     const uint32_t mykey = t * 64 + (uint32_t)local_of<3>(lk);
                     stays = keeps_key<T, 3, DEG>(raw.off, reach);
                     if (!stays) {

@@ -67,6 +67,7 @@ __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *
         atomicOr(flags, FLAG_NONFINITE);
         return false;
     }
+    keep_affine<T, DIM>(prm.transfer, B);
     bool same = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {

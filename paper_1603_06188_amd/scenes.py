@@ -50,6 +50,7 @@ class Scene:
     dt: float = 0.0
     gravity: tuple = (0.0, 0.0, 0.0)
     band: tuple = (0, 0, 0, 0, 0, 0)   # sticky band width in nodes: -x,+x,-y,+y,-z,+z
+    transfer: int = 0           # affine part carried: 0 APIC, 1 RPIC (skew), 2 PIC (none)
     steps: int = 1
 
     @property

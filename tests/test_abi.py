@@ -40,14 +40,15 @@ def test_binding_mirrors_header():
 def test_struct_layout_matches_c(tmp_path):
     from paper_1603_06188_amd import binding
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "apic.h"\n#include <stddef.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu",'
+    src.write_text('#include <stdio.h>\n#include "apic.h"\n#include <stddef.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu",'
                    'sizeof(apic_scene), sizeof(apic_params), sizeof(apic_particles), sizeof(apic_grid_desc),'
-                   'offsetof(apic_scene, workspace), offsetof(apic_params, mu));}\n')
+                   'offsetof(apic_scene, workspace), offsetof(apic_params, mu), offsetof(apic_params, transfer));}\n')
     exe = tmp_path / "sz"
     assert os.system(f"gcc -I {ROOT}/include {src} -o {exe}") == 0
     got = os.popen(str(exe)).read().split()
     want = [ctypes.sizeof(binding.ApicScene), ctypes.sizeof(binding.ApicParams), ctypes.sizeof(binding.ApicParticles),
-            ctypes.sizeof(binding.ApicGridDesc), binding.ApicScene.workspace.offset, binding.ApicParams.mu.offset]
+            ctypes.sizeof(binding.ApicGridDesc), binding.ApicScene.workspace.offset, binding.ApicParams.mu.offset,
+            binding.ApicParams.transfer.offset]
     assert [int(x) for x in got] == want
 
 
@@ -114,6 +115,7 @@ def test_invalid_scenes_are_rejected_before_any_launch():
         "model": lambda s: setattr(s.prm, "model", 7),
         "rho0": lambda s: (setattr(s.prm, "model", 1), setattr(s.prm, "rho0", 0.0)),
         "band": lambda s: s.prm.band.__setitem__(2, -1),
+        "transfer": lambda s: setattr(s.prm, "transfer", 3),
         "workspace": lambda s: None,
     }
     null_stream = type("NullStream", (), {"cuda_stream": 0})()
@@ -122,4 +124,6 @@ def test_invalid_scenes_are_rejected_before_any_launch():
         spoil(sc)
         with pytest.raises(b.ApicError) as e:
             b.apic_step([sc], 1, stream=null_stream)
-        assert e.value.code in (b.APIC_E_INVAL, b.APIC_E_WORKSPACE), name
+        # every field is checked before the (missing) workspace
+        want = b.APIC_E_WORKSPACE if name == "workspace" else b.APIC_E_INVAL
+        assert e.value.code == want, (name, e.value.code, str(e.value))

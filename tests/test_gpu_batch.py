@@ -64,7 +64,7 @@ def test_batch_matches_chained_oracle_fp64():
         g = oracle.Grid(h.dim, h.degree, h.cells, h.dx)
         x, v, B, F = h.x, h.v, h.B, h.F
         for _ in range(steps):
-            r = oracle.step(g, x, v, B, F, h.m, h.V, h.model, h.mu, h.lam, h.dt, h.gravity, h.band)
+            r = oracle.step(g, x, v, B, F, h.m, h.V, h.model, h.mu, h.lam, h.dt, h.gravity, h.band, transfer=h.transfer)
             x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
         got = d.state()
         assert float(np.abs(got["x"] - x).max() / h.dx) <= 1e-11, k
@@ -135,7 +135,7 @@ def test_batch_fp32_one_step_matches_oracle():
     batch.step(1)
     for k, (h, d) in enumerate(zip(hosts, batch.scenes)):
         g = oracle.Grid(h.dim, h.degree, h.cells, h.dx)
-        r = oracle.step(g, h.x, h.v, h.B, h.F, h.m, h.V, h.model, h.mu, h.lam, h.dt, h.gravity, h.band)
+        r = oracle.step(g, h.x, h.v, h.B, h.F, h.m, h.V, h.model, h.mu, h.lam, h.dt, h.gravity, h.band, transfer=h.transfer)
         got = d.state()
         assert d.flags() == 0
         assert float(np.abs(got["x"] - r["x_new"]).max() / h.dx) <= 1e-5, k

@@ -30,7 +30,7 @@ def test_full_size_step_matches_oracle(cube):
     got = ds.state()
     assert ds.flags() == 0
     g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
-    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band)
+    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
     assert float(np.abs(got["x"] - ref["x_new"]).max() / s.dx) <= 1e-5
     assert rel(got["v"], ref["v_new"]) <= 1e-5
     assert rel(got["B"], ref["B_new"]) <= 1e-5
@@ -103,7 +103,7 @@ def test_spheres_full_size_f32_step_matches_oracle(spheres32):
     got = ds.state()
     assert ds.flags() == 0
     g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
-    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band)
+    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
     assert rel(m, ref["m"]) <= 1e-5
     assert rel(mv, ref["mv"] + s.dt * ref["f"]) <= 1e-5
     assert float(np.abs(got["x"] - ref["x_new"]).max() / s.dx) <= 1e-5

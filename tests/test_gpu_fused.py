@@ -38,7 +38,7 @@ def _chain(s, steps):
     x, v, B, F = s.x, s.v, s.B, s.F
     out = []
     for _ in range(steps):
-        r = oracle.step(g, x, v, B, F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band)
+        r = oracle.step(g, x, v, B, F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
         out.append((x, r))
         x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
     return out

@@ -38,7 +38,7 @@ def compare_step(s, ds, tol, check_grid=True, label=""):
     """Run one GPU step phase by phase and compare every phase with the oracle."""
     b = _b()
     g = ogrid(s)
-    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band)
+    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
     ds.p2g()
     errs = {}
     if check_grid:
@@ -106,7 +106,7 @@ def test_apic_step_matches_chained_oracle_steps(dim, degree):
     x, v, B, F = s.x, s.v, s.B, s.F
     moved_keys = 0
     for _ in range(steps):
-        r = oracle.step(g, x, v, B, F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band)
+        r = oracle.step(g, x, v, B, F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
         moved_keys += int(np.count_nonzero(np.floor(r["x_new"] / s.dx - (0.5 if degree == 2 else 0.0))
                                             != np.floor(x / s.dx - (0.5 if degree == 2 else 0.0))))
         x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
