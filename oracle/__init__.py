@@ -22,6 +22,8 @@ cites the passage of the paper it follows:
 * ``particle_totals`` / ``grid_totals`` -- momenta of Sec. 3.1 with the
   particle angular momentum of Sec. 5.3 (B term included)
 * ``cfl_dt``                           -- CFL rule of Sec. 4.3
+* degree 1 everywhere: multilinear weights with the lagged C_p of Sec. 5.9
+  (the B planes carry C_p), APIC transfer only
 """
 from __future__ import annotations
 
@@ -112,6 +114,9 @@ def _load():
         lib.oracle_cfl_dt.restype = ctypes.c_double
         lib.oracle_cfl_dt.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                       _dp, _dp]
+        lib.oracle_cfl_dt_lagged.restype = ctypes.c_double
+        lib.oracle_cfl_dt_lagged.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                             _dp, _dp]
         lib.oracle_node_count.restype = ctypes.c_int64
         lib.oracle_node_count.argtypes = [G]
         lib.oracle_matrix_det.restype = ctypes.c_double
@@ -301,7 +306,9 @@ def potential(F, V, mu: float, lam: float) -> float:
     return out.value
 
 
-def cfl_dt(dx: float, v, B, nu: float = 1.0) -> float:
-    """Largest dt admitted by the CFL rule of Sec. 4.3."""
+def cfl_dt(dx: float, v, B, nu: float = 1.0, degree: int = 2) -> float:
+    """Largest dt admitted by the CFL rule of Sec. 4.3 (degree 1: the same
+    rule for the lagged C_p of Sec. 5.9, held in B)."""
     v, B = _d(v), _d(B)
-    return _load().oracle_cfl_dt(v.shape[1], float(dx), float(nu), v.shape[0], _ptr(v), _ptr(B))
+    f = _load().oracle_cfl_dt_lagged if degree == 1 else _load().oracle_cfl_dt
+    return f(v.shape[1], float(dx), float(nu), v.shape[0], _ptr(v), _ptr(B))

@@ -13,7 +13,7 @@
  * code, header or table with the GPU library.
  *
  * Conventions
- *   dim d in {2,3}; degree 2 = quadratic, 3 = cubic B-spline.
+ *   dim d in {2,3}; degree 1 = multilinear, 2 = quadratic, 3 = cubic B-spline.
  *   The grid has n[a] cells and n[a]+1 nodes along axis a; node i sits at
  *   x_i = i * dx (origin 0).  Node linear index: ix + N0*(iy + N1*iz),
  *   N_a = n[a]+1.  Grid vectors are stored node-major: g[node*d + a].
@@ -65,7 +65,7 @@
 
 typedef struct {
     int32_t dim;       /* 2 or 3 */
-    int32_t degree;    /* 2 quadratic, 3 cubic */
+    int32_t degree;    /* 1 multilinear, 2 quadratic, 3 cubic */
     int32_t n[3];      /* cells per axis */
     double dx;         /* grid spacing */
 } oracle_grid;
@@ -78,6 +78,7 @@ typedef struct {
 double oracle_bspline(int degree, double t)
 {
     double a = fabs(t);
+    if (degree == 1) return a < 1.0 ? 1.0 - a : 0.0;
     if (degree == 2) {
         if (a < 0.5) return 0.75 - a * a;
         if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
@@ -96,6 +97,7 @@ double oracle_bspline_deriv(int degree, double t)
 {
     double a = fabs(t);
     double s = (t < 0.0) ? -1.0 : 1.0;
+    if (degree == 1) return a < 1.0 ? -s : 0.0; /* one-sided (from above) at t = 0 */
     if (degree == 2) {
         if (a < 0.5) return -2.0 * t;
         if (a < 1.5) return -(1.5 - a) * s;
@@ -109,7 +111,7 @@ double oracle_bspline_deriv(int degree, double t)
     return 0.0;
 }
 
-static double support_half_width(int degree) { return degree == 2 ? 1.5 : 2.0; }
+static double support_half_width(int degree) { return degree == 1 ? 1.0 : (degree == 2 ? 1.5 : 2.0); }
 
 static int nodes_per_axis(const oracle_grid *g, int a) { return g->n[a] + 1; }
 
@@ -360,7 +362,10 @@ static void skew_from_rotation(int d, const double *omega, double *C)
  *   (m v)_i   += w_ip m_p (v_p + B_p D_p^{-1} (x_i - x_p))
  *   f_i       += -V_p P(F_p) F_p^T grad w_ip          (model == 1 only)
  * with B_p D_p^{-1} replaced by its rotation omega_p^* (RPIC, Sec. 2.1) or
- * by zero (PIC), as the transfer selects (Sec. 5.6).
+ * by zero (PIC), as the transfer selects (Sec. 5.6).  Multilinear weights
+ * (degree 1, Sec. 5.9): D_p can be singular, and the particle carries the
+ * lagged affine matrix C_p itself, so the B planes hold C_p and
+ *   (m v)_i   += w_ip m_p (v_p + C_p (x_i - x_p)).
  * Grid arrays are overwritten (zeroed first).  Particles are visited in
  * ascending order.  dp_out, when non-NULL, receives D_p (d*d per particle).
  */
@@ -370,8 +375,9 @@ int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *
                double *gm, double *gmv, double *gf, double *dp_out)
 {
     const int d = g->dim;
-    if (d < 2 || d > 3 || (g->degree != 2 && g->degree != 3) || !(g->dx > 0.0)) return OR_E_ARG;
+    if (d < 2 || d > 3 || g->degree < 1 || g->degree > 3 || !(g->dx > 0.0)) return OR_E_ARG;
     if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
+    if (g->degree == 1 && transfer != OR_TRANSFER_APIC) return OR_E_ARG;
     const int64_t nn = node_count(g);
     memset(gm, 0, sizeof(double) * nn);
     memset(gmv, 0, sizeof(double) * nn * d);
@@ -386,11 +392,16 @@ int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *
             for (int r = 0; r < d; ++r)
                 for (int c = 0; c < d; ++c)
                     D[r * d + c] += st[j].w * (st[j].xi[r] - xp[r]) * (st[j].xi[c] - xp[c]);
-        int rc = mat_inverse(d, D, Dinv, NULL);
-        if (rc != OR_OK) return rc;
+        int rc = OR_OK;
         if (dp_out)
             for (int k = 0; k < d * d; ++k) dp_out[p * d * d + k] = D[k];
-        mat_mul(d, B + p * d * d, Dinv, C);
+        if (g->degree == 1) {
+            for (int k = 0; k < d * d; ++k) C[k] = B[p * d * d + k];
+        } else {
+            rc = mat_inverse(d, D, Dinv, NULL);
+            if (rc != OR_OK) return rc;
+            mat_mul(d, B + p * d * d, Dinv, C);
+        }
         if (transfer == OR_TRANSFER_RPIC) {
             double omega[3];
             rotation_of(d, C, omega);
@@ -488,7 +499,10 @@ int oracle_grid_update(const oracle_grid *g, const double *gm, const double *gmv
  * Sec. 5.1) replaces B_p' by omega^* D_p with
  *   K_p = sum_i w_ip (x_i - x_p)^* (x_i - x_p)^{*T},
  *   l_p = sum_i w_ip (x_i - x_p) x vt_i,   omega = K_p^{-1} l_p
- * (vectors embedded in 3D when d = 2); PIC stores B_p' = 0.
+ * (vectors embedded in 3D when d = 2); PIC stores B_p' = 0.  Multilinear
+ * weights (degree 1, Sec. 5.9) store the lagged C_p' = sum_i vt_i grad w_ip^T
+ * (the paper's form of sum_i w_ip vt_i (D_p^{-1} (x_i - x_p))^T for these
+ * weights), APIC only.
  */
 int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *F,
                const double *gvt, const double *gxt, int transfer,
@@ -496,6 +510,7 @@ int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *
 {
     const int d = g->dim;
     if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
+    if (g->degree == 1 && transfer != OR_TRANSFER_APIC) return OR_E_ARG;
     stencil_entry st[MAX_STENCIL];
     for (int64_t p = 0; p < np; ++p) {
         const double *xp = x + p * d;
@@ -545,6 +560,12 @@ int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *
             mat_mul(d, C, D, Bn);
         } else if (transfer == OR_TRANSFER_PIC) {
             for (int k = 0; k < d * d; ++k) Bn[k] = 0.0;
+        }
+        if (g->degree == 1) {
+            for (int k = 0; k < d * d; ++k) Bn[k] = 0.0;
+            for (int j = 0; j < cnt; ++j)
+                for (int r = 0; r < d; ++r)
+                    for (int c = 0; c < d; ++c) Bn[r * d + c] += gvt[st[j].node * d + r] * st[j].gw[c];
         }
         for (int a = 0; a < d; ++a) G[a * d + a] += 1.0;
         double Fn[9];
@@ -682,6 +703,26 @@ double oracle_cfl_dt(int d, double dx, double nu, int64_t np, const double *v, c
         for (int a = 0; a < d; ++a) vv += v[p * d + a] * v[p * d + a];
         for (int k = 0; k < d * d; ++k) bb += B[p * d * d + k] * B[p * d * d + k];
         double s = sqrt(vv) + 6.0 * sqrt((double)d) / dx * sqrt(bb);
+        if (s > worst) worst = s;
+    }
+    if (worst == 0.0) return INFINITY;
+    return nu * dx / worst;
+}
+
+/*
+ * The same rule for multilinear weights with the lagged C_p of Sec. 5.9:
+ * every grid velocity a particle contributes, v_p + C_p (x_i - x_p), has
+ * |x_i - x_p| <= sqrt(d) dx, so
+ *   dt <= nu dx / max_p (|v_p| + sqrt(d) dx |C_p|_F).
+ */
+double oracle_cfl_dt_lagged(int d, double dx, double nu, int64_t np, const double *v, const double *C)
+{
+    double worst = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        double vv = 0.0, cc = 0.0;
+        for (int a = 0; a < d; ++a) vv += v[p * d + a] * v[p * d + a];
+        for (int k = 0; k < d * d; ++k) cc += C[p * d * d + k] * C[p * d * d + k];
+        double s = sqrt(vv) + sqrt((double)d) * dx * sqrt(cc);
         if (s > worst) worst = s;
     }
     if (worst == 0.0) return INFINITY;
