@@ -281,6 +281,23 @@ def main(argv=None):
     b.apic_timing_enable(False)
     phases = list(timing)
     dur = {p: timing[p][1] for p in phases}
+    # the same K steps with adaptive steps (APIC_OPT_ADAPTIVE_DT, nu = 0.5):
+    # the CFL rule allows ~0.06 here, so the 1e-4 cap is every step's dt and
+    # the work is the fixed-step work plus choosing dt on the device
+    import dataclasses
+    ad = b.DeviceScene(dataclasses.replace(scene, cfl=0.5), compensated=compensated, with_id=False, adaptive=True)
+    ad.step(args.warmup, args.sort_every)
+    ad.upload(scene)
+    ad.clear_flags()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ad.step(args.steps, args.sort_every)
+    torch.cuda.synchronize()
+    el_ad = time.perf_counter() - t2
+    ad_dt, _ = ad.step_time()
+    adaptive = {"ms_per_step": el_ad / args.steps * 1e3, "vs_fixed": el / el_ad, "cfl": 0.5, "dt_last": ad_dt,
+                "flags": ad.flags()}
+    del ad
 
     n = scene.n
     comp_b = 16 if compensated else 0
@@ -316,6 +333,7 @@ def main(argv=None):
         },
         "phase_ms": {p: round(dur[p], 5) for p in phases},
         "cfl": {"dt_max": cfl_dt, "call_ms": round(cfl_ms, 4)},
+        "adaptive_dt": adaptive,
         "flags": flags,
         "roofline": {
             "bound": "hbm",

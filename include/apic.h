@@ -17,7 +17,7 @@
  *     work that call enqueues).  The library never allocates device memory.
  *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *     Every call is asynchronous on that stream except apic_diagnostics,
- *     apic_cfl_dt and apic_get_flags, which synchronize it.
+ *     apic_cfl_dt, apic_step_time and apic_get_flags, which synchronize it.
  *   - Errors: a call returns APIC_OK or a negative apic_status.  Argument
  *     errors are detected on the host before anything is enqueued and leave
  *     all buffers untouched; apic_last_error() then returns a message (per
@@ -83,12 +83,24 @@ enum {
     APIC_OPT_COMPENSATED = 1, /* accumulate grid mass/momentum with an error
                                  term per node (two-sum), folded in by
                                  apic_grid_update                            */
-    APIC_OPT_FUSED_TRANSFER = 2 /* apic_step, binary32 quadratic 3D only:
+    APIC_OPT_FUSED_TRANSFER = 2, /* apic_step, binary32 quadratic 3D only:
                                  the transfer to particles of each step but
                                  the last of a call also forms the next
                                  step's grid sums (Sec. 3.4 fused with
                                  Sec. 3.2); same results up to the order of
-                                 the sums.  Ignored by other combinations. */
+                                 the sums.  Ignored by other combinations
+                                 and with APIC_OPT_ADAPTIVE_DT.              */
+    APIC_OPT_ADAPTIVE_DT = 4  /* apic_step (not apic_step_batch): every step
+                                 chooses its own dt on the device by the CFL
+                                 rule of Sec. 4.3,
+                                   dt_k = min(prm.dt, prm.cfl * dx / b_k),
+                                   b_k  = max_p (|v_p| + 6 sqrt(d)/dx |B_p|_F)
+                                 over the state the step starts from (b_k = 0:
+                                 prm.dt).  The first step of a call bounds all
+                                 particles in a pass of its own; each later
+                                 step takes b_k from the transfer to particles
+                                 that wrote the state (fused into it).  The
+                                 steps' dt are read back by apic_step_time. */
 };
 
 /* Sticky device flag bits (apic_get_flags). */
@@ -132,6 +144,8 @@ typedef struct {
     double mu;          /* Lame mu of the neo-Hookean model                 */
     double lambda;      /* Lame lambda of the neo-Hookean model             */
     double rho0;        /* rest density: particle volume V_p = m_p / rho0   */
+    double cfl;         /* CFL number nu of Sec. 4.3 for APIC_OPT_ADAPTIVE_DT
+                           (0 < nu <= 1); prm.dt is then the largest step   */
 } apic_params;
 
 typedef struct {
@@ -278,6 +292,13 @@ apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out
  * at rest.  nu must be positive and finite.  Synchronizes `stream`.
  */
 apic_status apic_cfl_dt(const apic_scene *scene, double nu, double *dt_out, void *stream);
+
+/*
+ * Time advanced by the adaptive steps (APIC_OPT_ADAPTIVE_DT) of the scene
+ * since its apic_reset: *t_out the sum of their dt, *dt_last the dt of the
+ * most recent one (0 before any).  Host doubles.  Synchronizes `stream`.
+ */
+apic_status apic_step_time(const apic_scene *scene, double *dt_last, double *t_out, void *stream);
 
 /* Reads (host *flags) / clears the sticky flag word.  get synchronizes. */
 apic_status apic_get_flags(const apic_scene *scene, uint32_t *flags, void *stream);

@@ -33,6 +33,7 @@ APIC_MODEL_NONE, APIC_MODEL_NEO_HOOKEAN = 0, 1
 APIC_TRANSFER_APIC, APIC_TRANSFER_RPIC, APIC_TRANSFER_PIC = 0, 1, 2
 APIC_OPT_COMPENSATED = 1
 APIC_OPT_FUSED_TRANSFER = 2
+APIC_OPT_ADAPTIVE_DT = 4
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
 APIC_FLAG_UNSORTED = 16
 APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
@@ -40,7 +41,8 @@ APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
 
 EXPORTED = [
     "apic_workspace_bytes", "apic_reset", "apic_sort", "apic_p2g", "apic_grid_update", "apic_g2p", "apic_step",
-    "apic_batch_workspace_bytes", "apic_step_batch", "apic_grid_export", "apic_diagnostics", "apic_cfl_dt", "apic_get_flags", "apic_clear_flags",
+    "apic_batch_workspace_bytes", "apic_step_batch", "apic_grid_export", "apic_diagnostics", "apic_cfl_dt", "apic_step_time",
+    "apic_get_flags", "apic_clear_flags",
     "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
     "apic_last_error", "apic_version",
 ]
@@ -61,7 +63,7 @@ class ApicParticles(ctypes.Structure):
 class ApicParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("model", ctypes.c_int32),
                 ("band", ctypes.c_int32 * 6), ("transfer", ctypes.c_int32), ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("rho0", ctypes.c_double)]
+                ("rho0", ctypes.c_double), ("cfl", ctypes.c_double)]
 
 
 class ApicScene(ctypes.Structure):
@@ -84,6 +86,7 @@ _sigs = {
     "apic_grid_export": [_S, ctypes.c_int32, _V, _V],
     "apic_diagnostics": [_S, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _V],
     "apic_cfl_dt": [_S, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _V],
+    "apic_step_time": [_S, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _V],
     "apic_get_flags": [_S, ctypes.POINTER(ctypes.c_uint32), _V],
     "apic_clear_flags": [_S, _V],
     "apic_positions_from_absolute": [_S, _V, _V],
@@ -182,6 +185,13 @@ def apic_cfl_dt(scene: ApicScene, nu: float = 1.0, stream=None) -> float:
     return out.value
 
 
+def apic_step_time(scene: ApicScene, stream=None):
+    """(dt of the last adaptive step, time advanced by adaptive steps)."""
+    dt_last, t = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.apic_step_time(ctypes.byref(scene), ctypes.byref(dt_last), ctypes.byref(t), _stream(stream)))
+    return dt_last.value, t.value
+
+
 def apic_get_flags(scene: ApicScene, stream=None) -> int:
     out = ctypes.c_uint32()
     _check(_lib.apic_get_flags(ctypes.byref(scene), ctypes.byref(out), _stream(stream)))
@@ -240,14 +250,15 @@ def unpack_cells(packed: np.ndarray, dim: int) -> np.ndarray:
     return np.stack([p & 0xFFFF, p >> 16], axis=1).astype(np.int64)
 
 
-def grid_desc(scene, precision=None, compensated=False, fused=False) -> ApicGridDesc:
+def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=False) -> ApicGridDesc:
     """The apic_grid_desc of a host scene."""
     precision = precision or scene.precision
     g = ApicGridDesc()
     g.dim = scene.dim
     g.degree = scene.degree
     g.precision = APIC_F32 if precision == "fp32" else APIC_F64
-    g.options = (APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
+    g.options = ((APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
+                 | (APIC_OPT_ADAPTIVE_DT if adaptive else 0))
     for a in range(3):
         g.cells[a] = scene.cells[a] if a < scene.dim else 0
     g.dx = scene.dx
@@ -273,7 +284,7 @@ class DeviceScene:
     off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
 
     def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True,
-                 packed=None, fused=False):
+                 packed=None, fused=False, adaptive=False):
         self.host = scene
         self.dim = scene.dim
         self.precision = precision or scene.precision
@@ -287,7 +298,7 @@ class DeviceScene:
         self.cell = torch.zeros(cap, dtype=torch.int32, device=device)
         self.id = torch.arange(cap, dtype=torch.int32, device=device) if with_id else None
         self.upload(scene, packed)
-        g = grid_desc(scene, self.precision, compensated, fused)
+        g = grid_desc(scene, self.precision, compensated, fused, adaptive)
         self.wbytes = apic_workspace_bytes(g, cap)
         self.ws = torch.empty(self.wbytes + 256, dtype=torch.uint8, device=device)
         s = ApicScene()
@@ -305,6 +316,7 @@ class DeviceScene:
         prm.mu = scene.mu
         prm.lambda_ = scene.lam
         prm.rho0 = scene.rho0
+        prm.cfl = scene.cfl
         self.s = s
         self._bind()
         apic_reset(self.s)
@@ -384,6 +396,10 @@ class DeviceScene:
     def cfl_dt(self, nu=1.0):
         """Largest dt the CFL rule of Sec. 4.3 admits for the current state."""
         return apic_cfl_dt(self.s, nu)
+
+    def step_time(self):
+        """(dt of the last adaptive step, time advanced by adaptive steps)."""
+        return apic_step_time(self.s)
 
     def flags(self):
         return apic_get_flags(self.s)

@@ -58,7 +58,7 @@ struct Layout {
     int64_t rc;     // record (slab) capacity: min(tiles, cap)
     int64_t rcap;   // list capacity per bucket: ceil(tiles / kBuckets)
     int64_t slab_stride;
-    size_t o_vt, o_flags, o_vmax, o_diag_out, o_diag_part, o_key_count, o_scount;
+    size_t o_vt, o_flags, o_vmax, o_cfl, o_dt, o_diag_out, o_diag_part, o_key_count, o_scount;
     ListOff lists[2];
     TabOff tabs[2];
     size_t o_slabs;
@@ -103,6 +103,8 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.o_vt = take(dim * G * e);
     L.o_flags = take(64);
     L.o_vmax = take((size_t)kVmaxSlots * 4);
+    L.o_cfl = take((size_t)kVmaxSlots * 8);
+    L.o_dt = take(2 * sizeof(double));
     L.o_diag_out = take(8 * sizeof(double));
     L.o_diag_part = take((size_t)kDiagBlocks * 8 * sizeof(double));
     L.o_key_count = take(G * 4);
@@ -169,7 +171,7 @@ apic_status check_grid(const apic_grid_desc *g) {
         return fail(APIC_E_INVAL, "degree must be 2 (quadratic) or 3 (cubic) (got %d)", g->degree);
     if (g->precision != APIC_F32 && g->precision != APIC_F64)
         return fail(APIC_E_INVAL, "precision must be APIC_F32 or APIC_F64 (got %d)", g->precision);
-    if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER))
+    if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER | APIC_OPT_ADAPTIVE_DT))
         return fail(APIC_E_INVAL, "unknown option bits 0x%x", g->options);
     const int maxc = g->dim == 3 ? 1024 : 65535;
     for (int a = 0; a < g->dim; ++a)
@@ -211,6 +213,8 @@ apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
         if (q.band[k] < 0) return fail(APIC_E_INVAL, "band widths must be >= 0");
     if (q.transfer != APIC_TRANSFER_APIC && q.transfer != APIC_TRANSFER_RPIC && q.transfer != APIC_TRANSFER_PIC)
         return fail(APIC_E_INVAL, "unknown transfer %d", q.transfer);
+    if ((s->grid.options & APIC_OPT_ADAPTIVE_DT) && !(q.cfl > 0.0 && q.cfl <= 1.0))
+        return fail(APIC_E_INVAL, "adaptive steps need a CFL number 0 < cfl <= 1");
     if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)s->workspace) % kAlign) return fail(APIC_E_WORKSPACE, "workspace must be 256-byte aligned");
     const int64_t cap = capacity_for(&s->grid, s->workspace_bytes);
@@ -372,6 +376,8 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.g.vt = (T *)(w + L.o_vt);
     v.g.flags = (uint32_t *)(w + L.o_flags);
     v.g.vmax = (uint32_t *)(w + L.o_vmax);
+    v.g.cfl = nullptr;
+    v.g.cfl_c = 6.0 * sqrt((double)s->grid.dim) / s->grid.dx;
     v.g.d = L.d;
     v.g.dx = (T)s->grid.dx;
     v.g.inv_dx = (T)(1.0 / s->grid.dx);
@@ -383,6 +389,7 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.prm.mu = (T)s->prm.mu;
     v.prm.lam = (T)s->prm.lambda;
     v.prm.inv_rho0 = s->prm.rho0 > 0.0 ? (T)(1.0 / s->prm.rho0) : T(0);
+    v.prm.dt_dev = nullptr;
     v.diag_part = (double *)(w + L.o_diag_part);
     v.diag_out = (double *)(w + L.o_diag_out);
     return v;
@@ -586,6 +593,19 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         ss.cur = 1 - ss.cur;
         where = 1;
     }
+    // adaptive steps: dt chosen on the device before each step's P2G from the
+    // bound of the state it starts from (a pass over the particles for the
+    // first step, the bound the previous transfer to particles folded in
+    // for the others)
+    const bool adaptive = (s->grid.options & APIC_OPT_ADAPTIVE_DT) != 0;
+    char *w = (char *)s->workspace;
+    unsigned long long *cfl_slots = (unsigned long long *)(w + v.L.o_cfl);
+    double *dt_state = (double *)(w + v.L.o_dt);
+    if (adaptive) {
+        v.g.cfl = cfl_slots;
+        v.prm.dt_dev = dt_state;
+    }
+    const double nu_dx = s->prm.cfl * s->grid.dx;
     bool slabs_ready = false;  // the slabs already hold this step's P2G
     for (int32_t k = 0; k < n_steps; ++k) {
         if (sort_every > 0 && k > 0 && k % sort_every == 0) {
@@ -594,6 +614,14 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
             ss.cur = 1 - ss.cur;
             where = 1 - where;
             slabs_ready = false;
+        }
+        if (adaptive) {
+            if (k == 0) {
+                const int nb = launch_cfl_partials<T, DIM>(bufs[where], s->grid.dx, v.diag_part, st);
+                launch_adapt_dt(v.diag_part, nb, cfl_slots, s->prm.dt, nu_dx, dt_state, st);
+            } else {
+                launch_adapt_dt((const double *)cfl_slots, kVmaxSlots, cfl_slots, s->prm.dt, nu_dx, dt_state, st);
+            }
         }
         if (!slabs_ready) {
             timed(APIC_PHASE_P2G, st, [&] {
@@ -606,7 +634,7 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         });
         ss.grid_meta = ss.cur;
         // the last step of the call leaves the slabs of the step it made
-        const bool fuse = fused_step<T, DIM, DEG>() && (s->grid.options & APIC_OPT_FUSED_TRANSFER) &&
+        const bool fuse = fused_step<T, DIM, DEG>() && (s->grid.options & APIC_OPT_FUSED_TRANSFER) && !adaptive &&
                           k + 1 < n_steps && !(sort_every > 0 && (k + 1) % sort_every == 0);
         if (fuse)
             g2p2g_rebin<T, DIM, DEG, COMP>(v, ss, bufs[where], bufs[1 - where], ss.cur, st);
@@ -906,6 +934,8 @@ apic_status apic_step_batch(apic_scene *scenes, int32_t n_scenes, int32_t n_step
         const apic_grid_desc &a = scenes[0].grid, &b = scenes[k].grid;
         if (a.dim != b.dim || a.degree != b.degree || a.precision != b.precision || a.options != b.options)
             return fail(APIC_E_INVAL, "scene %d differs from scene 0 in dim, degree, precision or options", k);
+        if (b.options & APIC_OPT_ADAPTIVE_DT)
+            return fail(APIC_E_UNSUPPORTED, "adaptive steps are taken by apic_step, not apic_step_batch");
     }
     {
         std::unordered_map<void *, int32_t> seen;
@@ -962,6 +992,25 @@ apic_status apic_cfl_dt(const apic_scene *scene, double nu, double *dt_out, void
     rc = hip_check(hipStreamSynchronize(st), "apic_cfl_dt sync");
     if (rc != APIC_OK) return rc;
     *dt_out = worst == 0.0 ? INFINITY : nu * scene->grid.dx / worst;
+    return APIC_OK;
+}
+
+apic_status apic_step_time(const apic_scene *scene, double *dt_last, double *t_out, void *stream) {
+    if (!dt_last || !t_out) return fail(APIC_E_INVAL, "dt_last or t_out is NULL");
+    int64_t cap = 0;
+    apic_status rc = check_scene(scene, &cap);
+    if (rc != APIC_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    (void)state_of(scene, cap, st);
+    const Layout L = make_layout(&scene->grid, cap);
+    double h[2] = {0.0, 0.0};
+    rc = hip_check(hipMemcpyAsync(h, (char *)scene->workspace + L.o_dt, sizeof h, hipMemcpyDeviceToHost, st),
+                   "apic_step_time copy");
+    if (rc != APIC_OK) return rc;
+    rc = hip_check(hipStreamSynchronize(st), "apic_step_time sync");
+    if (rc != APIC_OK) return rc;
+    *dt_last = h[0];
+    *t_out = h[1];
     return APIC_OK;
 }
 

@@ -109,6 +109,10 @@ struct GridState {
     T *vt;              // dim planes of G nodes: updated velocity
     uint32_t *flags;
     uint32_t *vmax;     // [kVmaxSlots] binary32 bits; their max bounds max_i |vt_i|
+    // [kVmaxSlots] binary64 bits; the transfer to particles raises them to
+    // max_p (|v_p| + cfl_c |B_p|_F) of the state it writes (null: it does not)
+    unsigned long long *cfl;
+    double cfl_c;       // 6 sqrt(d) / dx (Sec. 4.3)
     GridDims d;
     T dx, inv_dx;
 };
@@ -121,7 +125,17 @@ struct StepParams {
     int transfer;  // APIC_TRANSFER_*
     int band[6];
     T mu, lam, inv_rho0;
+    const double *dt_dev;  // non-null: the step's dt is *dt_dev (chosen on the device)
 };
+
+// The parameters with the step's dt resolved: a step whose dt is chosen on
+// the device reads it once per kernel.
+template <typename T>
+__device__ __forceinline__ StepParams<T> with_step_dt(const StepParams<T> &prm) {
+    StepParams<T> q = prm;
+    if (prm.dt_dev) q.dt = (T)*prm.dt_dev;
+    return q;
+}
 
 // Everything the step kernels need for one scene of a batch (the caller's
 // particle planes and the workspace shadow, both list parities, tables,

@@ -113,6 +113,13 @@ void launch_diag_particles(const Parts<T> &P, double dx, double *partials, doubl
 // max_p (|v_p| + 6 sqrt(d)/dx |B_p|_F) in binary64 into out[0] (Sec. 4.3).
 template <typename T, int DIM>
 void launch_cfl_bound(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);
+// The same bound per block into partials[0..nb); returns nb.
+template <typename T, int DIM>
+int launch_cfl_partials(const Parts<T> &P, double dx, double *partials, hipStream_t st);
+// Adaptive step: dt = min(cap, nu_dx / max src[0..n)) (cap when the bound
+// is 0) into state[0], added to state[1]; zeroes the kVmaxSlots bound slots.
+void launch_adapt_dt(const double *src, int n, unsigned long long *slots, double cap, double nu_dx, double *state,
+                     hipStream_t st);
 
 template <typename T, int DIM, int DEG, bool COMP>
 void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState<T> &g, int which, double dt,

@@ -87,6 +87,37 @@ __device__ __forceinline__ void move_position(const int *ci, const T *off, const
     }
 }
 
+// The CFL quantity of Sec. 4.3 of one particle's new state, |v| + c |B|_F
+// in binary64, folded into a running maximum (a NaN state propagates).
+template <typename T, int DIM>
+__device__ __forceinline__ void cfl_fold(const T *v, const T *B, double c, double &m) {
+    double vv = 0.0, bb = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double x = (double)v[a];
+        vv += x * x;
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        const double x = (double)B[k];
+        bb += x * x;
+    }
+    const double u = sqrt(vv) + c * sqrt(bb);
+    m = u > m || u != u ? u : m;
+}
+
+// Wave-wide: the maximum of m over the wavefront raised into one of the
+// kVmaxSlots bound slots (non-negative binary64 values order as their bits;
+// a NaN's bits exceed every finite value's).
+__device__ __forceinline__ void cfl_raise(unsigned long long *slots, uint32_t slot, double m) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(m, o, 64);
+        m = y > m || y != y ? y : m;
+    }
+    if (lane_id() == 0 && m != 0.0)
+        atomicMax(slots + slot % (uint32_t)kVmaxSlots, (unsigned long long)__double_as_longlong(m));
+}
+
 // Support index of the node nearest the particle along one axis, from the
 // axis weights: the middle node for quadratic (weight >= 1/2), the heavier
 // of the middle two for cubic (weight >= 0.479).

@@ -80,8 +80,9 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
 
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur, const TileTables &ctab,
-                                          const GridState<T> &g, const StepParams<T> &prm, const BinLists &nxt,
+                                          const GridState<T> &g, const StepParams<T> &prm_in, const BinLists &nxt,
                                           const BinScratch &sc, uint32_t blk, uint32_t nblk) {
+    const StepParams<T> prm = with_step_dt(prm_in);
     using R = VtRegion<DIM>;
     __shared__ uint32_t lds_stay[4][64];
     __shared__ uint32_t lds_queue[4][64 * kKeyChunks];
@@ -199,11 +200,15 @@ void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTab
 // One wavefront per listed tile walks the tile's particles in chunks of 64
 // (every lane busy).  A stayer's rank in its key continues from the key's
 // mover count (LDS counter); a mover takes the key and rank of pass 1.
-template <typename T, int DIM, int DEG>
+// ADAPT: the step's dt comes from the device and the CFL bound of the
+// written state is folded into g.cfl (adaptive steps); a separate
+// instantiation, so that fixed steps carry none of it.
+template <typename T, int DIM, int DEG, bool ADAPT>
 __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur,
                                          const TileTables &ctab, const BinLists &nxt, const TileTables &ntab,
-                                         const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm,
+                                         const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm_in,
                                          uint32_t blk, uint32_t nblk) {
+    const StepParams<T> prm = ADAPT ? with_step_dt(prm_in) : prm_in;
     constexpr int K = DEG + 1;
     constexpr int TE = DIM == 3 ? 4 : 8;
     using R = VtRegion<DIM>;
@@ -219,6 +224,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     const T dt_inv_dx = prm.dt * g.inv_dx, gs = prm.dt * g.inv_dx;
     const uint32_t items = walk.nrec + dead_chunks(src.n, walk.live);
     const int64_t ss = src.s, ds = dst.s;
+    double cmax = 0.0;  // CFL bound of the particles this lane writes (when asked)
     for (uint32_t r = blk * 4 + (uint32_t)wv; r < items; r += nblk * 4) {
         if (r >= walk.nrec) {
             carry_dead<T, DIM>(src, dst, sc, walk.live, live_nxt, r - walk.nrec);
@@ -245,6 +251,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                 T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
                 g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
+                if constexpr (ADAPT) cfl_fold<T, DIM>(vn, Bs, g.cfl_c, cmax);
                 const T *off = raw.off;
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);
@@ -286,14 +293,16 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         }
         wave_lds_sync();
     }
+    if constexpr (ADAPT) cfl_raise(g.cfl, blk * 4 + (uint32_t)wv, cmax);
+    (void)cmax;
     (void)TE;
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ADAPT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p(
     Parts<T> src, Parts<T> dst, BinLists cur, TileTables ctab, BinLists nxt, TileTables ntab, BinScratch sc,
     GridState<T> g, StepParams<T> prm) {
-    g2p_body<T, DIM, DEG>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
+    g2p_body<T, DIM, DEG, ADAPT>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int DIM, int DEG>
@@ -303,7 +312,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_wav
     const SceneDesc<T> &d = *b.d;
     Parts<T> src = d.bufs[b.sp.src], dst = d.bufs[b.sp.src ^ 1];
     if (!src.id || !dst.id) src.id = dst.id = nullptr;
-    g2p_body<T, DIM, DEG>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm, b.blk, b.nblk);
+    g2p_body<T, DIM, DEG, false>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm, b.blk,
+                                 b.nblk);
 }
 
 template <typename T, int DIM, int DEG>
@@ -321,8 +331,12 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
     int64_t blocks = (max_records + (src.n + 63) / 64 + 3) / 4;
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL((k_g2p<T, DIM, DEG>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2, cur, ctab, nxt, ntab,
-                       sc, g, prm);
+    if (g.cfl)
+        hipLaunchKernelGGL((k_g2p<T, DIM, DEG, true>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2, cur, ctab,
+                           nxt, ntab, sc, g, prm);
+    else
+        hipLaunchKernelGGL((k_g2p<T, DIM, DEG, false>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2, cur, ctab,
+                           nxt, ntab, sc, g, prm);
 }
 
 #define APIC_G2P_INST(T, DIM, DEG)                                                                               \

@@ -48,7 +48,8 @@ template <typename T, int DEG, bool COMP>
 __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur,
                                            const TileTables &ctab, const BinLists &nxt, const TileTables &ntab,
                                            const BinScratch &sc, const Slabs<T> &slabs, const GridState<T> &g,
-                                           const StepParams<T> &prm, uint32_t blk, uint32_t nblk) {
+                                           const StepParams<T> &prm_in, uint32_t blk, uint32_t nblk) {
+    const StepParams<T> &prm = prm_in;  // fixed dt: never used by adaptive steps
     constexpr int K = DEG + 1;
     static_assert(p2g_slices<T, 3, DEG>() == K, "the register sums of all support nodes fit in one pass");
     __shared__ PairLds<T, DEG, COMP> L;
@@ -217,8 +218,9 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
 template <typename T, int DEG, bool COMP>
 __device__ __forceinline__ void p2g_movers_body(const Parts<T> &P, const BinLists &cur, const BinLists &nxt,
                                                 const TileTables &ntab, const Slabs<T> &slabs,
-                                                const GridState<T> &g, const StepParams<T> &prm, uint32_t blk,
+                                                const GridState<T> &g, const StepParams<T> &prm_in, uint32_t blk,
                                                 uint32_t nblk) {
+    const StepParams<T> &prm = prm_in;  // fixed dt: never used by adaptive steps
     constexpr int K = DEG + 1;
     using Gm = Geo<3, DEG>;
     using SL = SlabLds<3, DEG>;

@@ -68,7 +68,8 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, c
 // tiles t + c; they decide ownership and feed the slab gathers.
 template <typename T, int DIM, int DEG, bool COMP>
 __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slabs<T> &slabs, const GridState<T> &g,
-                                                 const StepParams<T> &prm, uint32_t blk, uint32_t nblk) {
+                                                 const StepParams<T> &prm_in, uint32_t blk, uint32_t nblk) {
+    const StepParams<T> prm = with_step_dt(prm_in);
     using Gm = Geo<DIM, DEG>;
     constexpr int TE = Gm::TE, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC, NCOR = 1 << DIM;
     const int lane = lane_id();

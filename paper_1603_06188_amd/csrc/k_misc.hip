@@ -185,6 +185,52 @@ void launch_cfl_bound(const Parts<T> &P, double dx, double *partials, double *ou
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, partials, nb, out);
 }
 
+// --- adaptive step (Sec. 4.3) ------------------------------------------------------
+// One wavefront: b = max of src[0..n) (binary64; NaN propagates), then
+//   dt = b > 0 ? min(cap, nu_dx / b) : cap      (a NaN bound gives cap: the
+// flags of the transfers report a non-finite state), state[0] = dt,
+// state[1] += dt, and the kVmaxSlots bound slots are zeroed for the next
+// transfer to particles (src may be those slots: each lane reads its
+// entries before it clears them).
+__global__ __launch_bounds__(64) void k_adapt_dt(const double *src, int n, unsigned long long *slots, double cap,
+                                                  double nu_dx, double *state) {
+    const int lane = (int)threadIdx.x;
+    double b = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double y = src[i];
+        b = y > b || y != y ? y : b;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(b, o, 64);
+        b = y > b || y != y ? y : b;
+    }
+    for (int i = lane; i < kVmaxSlots; i += 64) slots[i] = 0ull;
+    if (lane == 0) {
+        double dt = cap;
+        if (b > 0.0) {
+            const double c = nu_dx / b;
+            dt = c < cap ? c : cap;
+        }
+        state[0] = dt;
+        state[1] += dt;
+    }
+}
+
+void launch_adapt_dt(const double *src, int n, unsigned long long *slots, double cap, double nu_dx, double *state,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_adapt_dt, dim3(1), dim3(64), 0, st, src, n, slots, cap, nu_dx, state);
+}
+
+// Binary64 bound of every particle into partials[0..nb) (the first pass of
+// launch_cfl_bound); returns nb.
+template <typename T, int DIM>
+int launch_cfl_partials(const Parts<T> &P, double dx, double *partials, hipStream_t st) {
+    const int nb = blocks_for(P.n, 256, kDiagBlocks);
+    const double c = 6.0 * sqrt((double)DIM) / dx;
+    hipLaunchKernelGGL((k_cfl_bound<T, DIM>), dim3(nb), dim3(256), 0, st, P, c, partials);
+    return nb;
+}
+
 // --- absolute positions <-> cell + offset ---------------------------------------
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_pack_positions(Parts<T> P, const double *x, double inv_dx) {
@@ -232,6 +278,7 @@ void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_
     template void launch_copy_state<T, DIM>(const Parts<T> &, const Parts<T> &, hipStream_t);                    \
     template void launch_diag_particles<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);     \
     template void launch_cfl_bound<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);         \
+    template int launch_cfl_partials<T, DIM>(const Parts<T> &, double, double *, hipStream_t);                  \
     template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t);         \
     template void launch_unpack_positions<T, DIM>(const Parts<T> &, double *, double, hipStream_t);
 APIC_MISC_INST(float, 2)

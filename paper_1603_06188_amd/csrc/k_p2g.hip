@@ -22,7 +22,8 @@ namespace apic {
 template <typename T, int DIM, int DEG, bool COMP>
 __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur, const BinLists &nxt,
                                          const TileTables &tab, const Slabs<T> &slabs, const GridState<T> &g,
-                                         const StepParams<T> &prm, uint32_t blk, uint32_t nblk) {
+                                         const StepParams<T> &prm_in, uint32_t blk, uint32_t nblk) {
+    const StepParams<T> prm = with_step_dt(prm_in);
     using Gm = Geo<DIM, DEG>;
     using SL = SlabLds<DIM, DEG>;
     constexpr int K = Gm::K, RN = Gm::RN, NC = Gm::NC, LP = SL::PLANE;

@@ -51,6 +51,7 @@ class Scene:
     gravity: tuple = (0.0, 0.0, 0.0)
     band: tuple = (0, 0, 0, 0, 0, 0)   # sticky band width in nodes: -x,+x,-y,+y,-z,+z
     transfer: int = 0           # affine part carried: 0 APIC, 1 RPIC (skew), 2 PIC (none)
+    cfl: float = 0.0            # CFL number for adaptive steps (dt is then their cap)
     steps: int = 1
 
     @property
