@@ -298,6 +298,37 @@ def main(argv=None):
     adaptive = {"ms_per_step": el_ad / args.steps * 1e3, "vs_fixed": el / el_ad, "cfl": 0.5, "dt_last": ad_dt,
                 "flags": ad.flags()}
     del ad
+    # the same cube with multilinear weights and the lagged affine matrix
+    # (APIC_MULTILINEAR, Sec. 5.9): an 8-node support instead of 27.  Its C_p
+    # grows at the free surface (sum_i vt_i grad w^T weighs nodes of tiny
+    # mass by 1/dx), so only the first 20 steps from the initial state are
+    # timed, and a raised flag voids the figure
+    ml_steps = min(args.steps, 20)
+    ml_scene = scenes.cube3d(cells=args.cells, degree=1)
+    ml = b.DeviceScene(ml_scene, compensated=compensated, with_id=False)
+    ml.step(2, args.sort_every)
+    ml.upload(ml_scene)
+    ml.clear_flags()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ml.step(ml_steps, args.sort_every)
+    torch.cuda.synchronize()
+    el_ml = time.perf_counter() - t3
+    ml_flags = ml.flags()
+    ml.upload(ml_scene)
+    torch.cuda.synchronize()
+    b.apic_timing_enable(True)
+    b.apic_timing_read()
+    ml.step(ml_steps, args.sort_every)
+    torch.cuda.synchronize()
+    tml = b.apic_timing_read()
+    b.apic_timing_enable(False)
+    multilinear = {"value": ml_scene.n * ml_steps / el_ml if ml_flags == 0 else None, "unit": "particle-updates/s",
+                   "steps": ml_steps, "ms_per_step": el_ml / ml_steps * 1e3,
+                   "phase_ms": {p: round(tml[p][1], 5) for p in tml},
+                   "g2p_GBps": (ml_scene.n * G2P_PARTICLE_B) / (tml["g2p"][1] * 1e-3) / 1e9,
+                   "flags": ml_flags}
+    del ml
 
     n = scene.n
     comp_b = 16 if compensated else 0
@@ -334,6 +365,7 @@ def main(argv=None):
         "phase_ms": {p: round(dur[p], 5) for p in phases},
         "cfl": {"dt_max": cfl_dt, "call_ms": round(cfl_ms, 4)},
         "adaptive_dt": adaptive,
+        "multilinear": multilinear,
         "flags": flags,
         "roofline": {
             "bound": "hbm",

@@ -59,7 +59,14 @@ enum {
     APIC_E_WORKSPACE = -4     /* workspace missing, misaligned or too small   */
 };
 
-enum { APIC_QUADRATIC = 2, APIC_CUBIC = 3 };      /* B-spline degree (Sec. 3.5) */
+/* B-spline degree (Sec. 3.5).  APIC_MULTILINEAR (Sec. 5.9): 2 nodes per
+ * axis; its D_p is singular on grid lines, so the particle carries the lagged
+ * affine matrix C_p in the B planes instead of B_p: the transfer to grid adds
+ * w m_p (v_p + C_p (x_i - x_p)) and the transfer to particles stores
+ * C_p = sum_i vt_i grad w_ip^T.  APIC transfer only; its CFL quantity is
+ * |v_p| + sqrt(d) dx |C_p|_F, and the particle angular momentum of
+ * apic_diagnostics has no affine term for it. */
+enum { APIC_MULTILINEAR = 1, APIC_QUADRATIC = 2, APIC_CUBIC = 3 };
 enum { APIC_F32 = 0, APIC_F64 = 1 };              /* element type of planes    */
 enum { APIC_MODEL_NONE = 0, APIC_MODEL_NEO_HOOKEAN = 1 };
 
@@ -116,7 +123,7 @@ enum {
 
 typedef struct {
     int32_t dim;        /* 2 or 3                                        */
-    int32_t degree;     /* APIC_QUADRATIC or APIC_CUBIC                  */
+    int32_t degree;     /* APIC_MULTILINEAR, APIC_QUADRATIC or APIC_CUBIC */
     int32_t precision;  /* APIC_F32 or APIC_F64                          */
     int32_t options;    /* APIC_OPT_* bits                               */
     int32_t cells[3];   /* cells per axis; cells[2] ignored in 2D        */

@@ -27,7 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 APIC_OK = 0
 APIC_E_INVAL, APIC_E_UNSUPPORTED, APIC_E_HIP, APIC_E_WORKSPACE = -1, -2, -3, -4
-APIC_QUADRATIC, APIC_CUBIC = 2, 3
+APIC_MULTILINEAR, APIC_QUADRATIC, APIC_CUBIC = 1, 2, 3
 APIC_F32, APIC_F64 = 0, 1
 APIC_MODEL_NONE, APIC_MODEL_NEO_HOOKEAN = 0, 1
 APIC_TRANSFER_APIC, APIC_TRANSFER_RPIC, APIC_TRANSFER_PIC = 0, 1, 2

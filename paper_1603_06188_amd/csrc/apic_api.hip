@@ -167,8 +167,8 @@ int64_t capacity_for(const apic_grid_desc *g, size_t bytes) {
 apic_status check_grid(const apic_grid_desc *g) {
     if (!g) return fail(APIC_E_INVAL, "grid descriptor is NULL");
     if (g->dim != 2 && g->dim != 3) return fail(APIC_E_INVAL, "dim must be 2 or 3 (got %d)", g->dim);
-    if (g->degree != APIC_QUADRATIC && g->degree != APIC_CUBIC)
-        return fail(APIC_E_INVAL, "degree must be 2 (quadratic) or 3 (cubic) (got %d)", g->degree);
+    if (g->degree != APIC_MULTILINEAR && g->degree != APIC_QUADRATIC && g->degree != APIC_CUBIC)
+        return fail(APIC_E_INVAL, "degree must be 1 (multilinear), 2 (quadratic) or 3 (cubic) (got %d)", g->degree);
     if (g->precision != APIC_F32 && g->precision != APIC_F64)
         return fail(APIC_E_INVAL, "precision must be APIC_F32 or APIC_F64 (got %d)", g->precision);
     if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER | APIC_OPT_ADAPTIVE_DT))
@@ -213,6 +213,8 @@ apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
         if (q.band[k] < 0) return fail(APIC_E_INVAL, "band widths must be >= 0");
     if (q.transfer != APIC_TRANSFER_APIC && q.transfer != APIC_TRANSFER_RPIC && q.transfer != APIC_TRANSFER_PIC)
         return fail(APIC_E_INVAL, "unknown transfer %d", q.transfer);
+    if (s->grid.degree == APIC_MULTILINEAR && q.transfer != APIC_TRANSFER_APIC)
+        return fail(APIC_E_UNSUPPORTED, "the multilinear kernel carries the lagged C of APIC only");
     if ((s->grid.options & APIC_OPT_ADAPTIVE_DT) && !(q.cfl > 0.0 && q.cfl <= 1.0))
         return fail(APIC_E_INVAL, "adaptive steps need a CFL number 0 < cfl <= 1");
     if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
@@ -246,6 +248,15 @@ std::mutex g_mu;
 std::unordered_map<void *, SceneState> g_states;
 
 bool same_grid(const apic_grid_desc &a, const apic_grid_desc &b) { return memcmp(&a, &b, sizeof a) == 0; }
+
+// c of the CFL quantity |v_p| + c |B_p|_F (Sec. 4.3): 6 sqrt(d) / dx for
+// quadratic and cubic weights; sqrt(d) dx for the lagged C_p of the
+// multilinear kernel, whose grid velocities v_p + C_p (x_i - x_p) have
+// |x_i - x_p| <= sqrt(d) dx.
+double cfl_factor(const apic_grid_desc &g) {
+    const double sd = sqrt((double)g.dim);
+    return g.degree == APIC_MULTILINEAR ? sd * g.dx : 6.0 * sd / g.dx;
+}
 
 apic_status hip_check(hipError_t e, const char *what) {
     if (e != hipSuccess) return fail(APIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -377,7 +388,7 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.g.flags = (uint32_t *)(w + L.o_flags);
     v.g.vmax = (uint32_t *)(w + L.o_vmax);
     v.g.cfl = nullptr;
-    v.g.cfl_c = 6.0 * sqrt((double)s->grid.dim) / s->grid.dx;
+    v.g.cfl_c = cfl_factor(s->grid);
     v.g.d = L.d;
     v.g.dx = (T)s->grid.dx;
     v.g.inv_dx = (T)(1.0 / s->grid.dx);
@@ -557,10 +568,11 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
             launch_grid_export<T, DIM, DEG, COMP>(v.lists[ss.grid_meta], v.slabs, v.g, a.which, (T *)a.ptr, st);
             break;
         case Op::DiagParticles:
-            launch_diag_particles<T, DIM>(v.user, s->grid.dx, v.diag_part, v.diag_out, st);
+            launch_diag_particles<T, DIM>(v.user, s->grid.dx, s->grid.degree != APIC_MULTILINEAR, v.diag_part,
+                                          v.diag_out, st);
             break;
         case Op::Cfl:
-            launch_cfl_bound<T, DIM>(v.user, s->grid.dx, v.diag_part, v.diag_out, st);
+            launch_cfl_bound<T, DIM>(v.user, cfl_factor(s->grid), v.diag_part, v.diag_out, st);
             break;
         case Op::DiagGrid:
             if (ss.grid_meta < 0) return fail(APIC_E_INVAL, "no grid yet: call apic_p2g first");
@@ -617,7 +629,7 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         }
         if (adaptive) {
             if (k == 0) {
-                const int nb = launch_cfl_partials<T, DIM>(bufs[where], s->grid.dx, v.diag_part, st);
+                const int nb = launch_cfl_partials<T, DIM>(bufs[where], cfl_factor(s->grid), v.diag_part, st);
                 launch_adapt_dt(v.diag_part, nb, cfl_slots, s->prm.dt, nu_dx, dt_state, st);
             } else {
                 launch_adapt_dt((const double *)cfl_slots, kVmaxSlots, cfl_slots, s->prm.dt, nu_dx, dt_state, st);
@@ -657,10 +669,19 @@ apic_status run_c(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const
     if (s->grid.options & APIC_OPT_COMPENSATED) return run<T, DIM, DEG, true>(op, s, cap, st, a);
     return run<T, DIM, DEG, false>(op, s, cap, st, a);
 }
+// f(std::integral_constant<int, DEG>) for the grid's B-spline degree.
+template <typename F>
+apic_status by_degree(int degree, F &&f) {
+    switch (degree) {
+        case APIC_MULTILINEAR: return f(std::integral_constant<int, 1>{});
+        case APIC_CUBIC: return f(std::integral_constant<int, 3>{});
+        default: return f(std::integral_constant<int, 2>{});
+    }
+}
+
 template <typename T, int DIM>
 apic_status run_k(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
-    if (s->grid.degree == APIC_CUBIC) return run_c<T, DIM, 3>(op, s, cap, st, a);
-    return run_c<T, DIM, 2>(op, s, cap, st, a);
+    return by_degree(s->grid.degree, [&](auto d) { return run_c<T, DIM, decltype(d)::value>(op, s, cap, st, a); });
 }
 template <typename T>
 apic_status run_d(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
@@ -683,14 +704,16 @@ apic_status steps_c(apic_scene *s, int64_t cap, int32_t n, int32_t k, hipStream_
     return run_steps<T, DIM, DEG, false>(s, cap, n, k, st);
 }
 
+template <typename T, int DIM>
+apic_status steps_k(apic_scene *s, int64_t cap, int32_t n, int32_t k, hipStream_t st) {
+    return by_degree(s->grid.degree,
+                     [&](auto d) { return steps_c<T, DIM, decltype(d)::value>(s, cap, n, k, st); });
+}
+
 apic_status dispatch_steps(apic_scene *s, int64_t cap, int32_t n, int32_t k, hipStream_t st) {
-    const bool f64 = s->grid.precision == APIC_F64, d3 = s->grid.dim == 3, cub = s->grid.degree == APIC_CUBIC;
-    if (f64) {
-        if (d3) return cub ? steps_c<double, 3, 3>(s, cap, n, k, st) : steps_c<double, 3, 2>(s, cap, n, k, st);
-        return cub ? steps_c<double, 2, 3>(s, cap, n, k, st) : steps_c<double, 2, 2>(s, cap, n, k, st);
-    }
-    if (d3) return cub ? steps_c<float, 3, 3>(s, cap, n, k, st) : steps_c<float, 3, 2>(s, cap, n, k, st);
-    return cub ? steps_c<float, 2, 3>(s, cap, n, k, st) : steps_c<float, 2, 2>(s, cap, n, k, st);
+    const bool f64 = s->grid.precision == APIC_F64, d3 = s->grid.dim == 3;
+    if (f64) return d3 ? steps_k<double, 3>(s, cap, n, k, st) : steps_k<double, 2>(s, cap, n, k, st);
+    return d3 ? steps_k<float, 3>(s, cap, n, k, st) : steps_k<float, 2>(s, cap, n, k, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -846,14 +869,15 @@ apic_status batch_c(apic_scene *s, int32_t n, int32_t k, void *bws, hipStream_t 
     return run_batch<T, DIM, DEG, false>(s, n, k, bws, st);
 }
 
+template <typename T, int DIM>
+apic_status batch_k(apic_scene *s, int32_t n, int32_t k, void *bws, hipStream_t st) {
+    return by_degree(s[0].grid.degree, [&](auto d) { return batch_c<T, DIM, decltype(d)::value>(s, n, k, bws, st); });
+}
+
 apic_status dispatch_batch(apic_scene *s, int32_t n, int32_t k, void *bws, hipStream_t st) {
-    const bool f64 = s[0].grid.precision == APIC_F64, d3 = s[0].grid.dim == 3, cub = s[0].grid.degree == APIC_CUBIC;
-    if (f64) {
-        if (d3) return cub ? batch_c<double, 3, 3>(s, n, k, bws, st) : batch_c<double, 3, 2>(s, n, k, bws, st);
-        return cub ? batch_c<double, 2, 3>(s, n, k, bws, st) : batch_c<double, 2, 2>(s, n, k, bws, st);
-    }
-    if (d3) return cub ? batch_c<float, 3, 3>(s, n, k, bws, st) : batch_c<float, 3, 2>(s, n, k, bws, st);
-    return cub ? batch_c<float, 2, 3>(s, n, k, bws, st) : batch_c<float, 2, 2>(s, n, k, bws, st);
+    const bool f64 = s[0].grid.precision == APIC_F64, d3 = s[0].grid.dim == 3;
+    if (f64) return d3 ? batch_k<double, 3>(s, n, k, bws, st) : batch_k<double, 2>(s, n, k, bws, st);
+    return d3 ? batch_k<float, 3>(s, n, k, bws, st) : batch_k<float, 2>(s, n, k, bws, st);
 }
 
 }  // namespace

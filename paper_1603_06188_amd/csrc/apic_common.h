@@ -298,6 +298,8 @@ __host__ __device__ __forceinline__ void local_coords(int l, int *c) {
 // Quadratic / cubic B-spline weights along one axis (Sec. 3.5), in cell
 // units, relative to the base node of the kernel support.
 //
+// Multilinear (Sec. 5.9): base = cell, weights 1 - u, u with u the offset;
+// the derivative is taken from above at a node (base = cell).
 // Quadratic: base = node below x/dx - 1/2; with c = x/dx - base - 1 in
 // [-1/2, 1/2) the weights are 1/2 (1/2 - c)^2, 3/4 - c^2, 1/2 (1/2 + c)^2.
 // Cubic: base = cell - 1, u = offset in [0, 1), q = 1 - u:
@@ -313,7 +315,9 @@ struct Axis {
 
 template <typename T, int DEG>
 __device__ __forceinline__ int base_of(int cell, T off) {
-    if constexpr (DEG == 2)
+    if constexpr (DEG == 1)
+        return cell;
+    else if constexpr (DEG == 2)
         return off < T(0.5) ? cell - 1 : cell;
     else
         return cell - 1;
@@ -321,7 +325,15 @@ __device__ __forceinline__ int base_of(int cell, T off) {
 
 template <typename T, int DEG>
 __device__ __forceinline__ void axis_weights(int cell, T off, Axis<T, DEG> &a) {
-    if constexpr (DEG == 2) {
+    if constexpr (DEG == 1) {
+        a.base = cell;
+        a.w[0] = T(1) - off;
+        a.w[1] = off;
+        a.dw[0] = T(-1);
+        a.dw[1] = T(1);
+        a.r[0] = -off;
+        a.r[1] = T(1) - off;
+    } else if constexpr (DEG == 2) {
         const T half = T(0.5);
         bool lower = off < half;
         a.base = lower ? cell - 1 : cell;
@@ -356,8 +368,11 @@ __device__ __forceinline__ void axis_weights(int cell, T off, Axis<T, DEG> &a) {
 }
 
 // 1 / k with D_p = k dx^2 I: k = 1/4 (quadratic), 1/3 (cubic) (Sec. 5.6).
+// Multilinear D_p is not a multiple of I (and is singular on grid lines);
+// that kernel carries C_p instead of B_p and never uses this.
 template <typename T, int DEG>
 __host__ __device__ constexpr T inv_D_factor() {
+    static_assert(DEG == 2 || DEG == 3, "quadratic and cubic only");
     return DEG == 2 ? T(4) : T(3);
 }
 

@@ -108,14 +108,18 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
 void launch_diag_final(const double *partials, int nb, double *out, hipStream_t st);
 
 template <typename T, int DIM>
-void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);
+// affine: include the m_p B_p^T : eps term (not for the lagged C_p of the
+// multilinear kernel)
+void launch_diag_particles(const Parts<T> &P, double dx, bool affine, double *partials, double *out,
+                           hipStream_t st);
 
-// max_p (|v_p| + 6 sqrt(d)/dx |B_p|_F) in binary64 into out[0] (Sec. 4.3).
+// max_p (|v_p| + c |B_p|_F) in binary64 into out[0] (Sec. 4.3; c from the
+// grid's degree and dx).
 template <typename T, int DIM>
-void launch_cfl_bound(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st);
+void launch_cfl_bound(const Parts<T> &P, double c, double *partials, double *out, hipStream_t st);
 // The same bound per block into partials[0..nb); returns nb.
 template <typename T, int DIM>
-int launch_cfl_partials(const Parts<T> &P, double dx, double *partials, hipStream_t st);
+int launch_cfl_partials(const Parts<T> &P, double c, double *partials, hipStream_t st);
 // Adaptive step: dt = min(cap, nu_dx / max src[0..n)) (cap when the bound
 // is 0) into state[0], added to state[1]; zeroes the kVmaxSlots bound slots.
 void launch_adapt_dt(const double *src, int n, unsigned long long *slots, double cap, double nu_dx, double *state,

@@ -11,7 +11,11 @@ namespace apic {
 template <typename T, int DEG>
 __device__ __forceinline__ int axis_w_fixed(int cell, T off, T *w) {
 #pragma clang fp contract(off)
-    if constexpr (DEG == 2) {
+    if constexpr (DEG == 1) {
+        w[0] = T(1) - off;
+        w[1] = off;
+        return cell;
+    } else if constexpr (DEG == 2) {
         const bool lower = off < T(0.5);
         const T c = lower ? off : off - T(1);
         const T l = T(0.5) - c, h = T(0.5) + c;
@@ -119,11 +123,14 @@ __device__ __forceinline__ void cfl_raise(unsigned long long *slots, uint32_t sl
 }
 
 // Support index of the node nearest the particle along one axis, from the
-// axis weights: the middle node for quadratic (weight >= 1/2), the heavier
-// of the middle two for cubic (weight >= 0.479).
+// axis weights: the heavier of the two for multilinear (weight >= 1/2), the
+// middle node for quadratic (weight >= 1/2), the heavier of the middle two
+// for cubic (weight >= 0.479).
 template <typename T, int DEG>
 __device__ __forceinline__ int nearest_node(const T (&w)[DEG + 1]) {
-    if constexpr (DEG == 2)
+    if constexpr (DEG == 1)
+        return w[0] >= w[1] ? 0 : 1;
+    else if constexpr (DEG == 2)
         return 1;
     else
         return w[1] >= w[2] ? 1 : 2;
@@ -349,7 +356,7 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
     move_position<T, DIM>(ci, off, vn, dt_inv_dx, cn, on, cfl);
     if (cfl) atomicOr(g.flags, FLAG_CFL);
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) Bs[k] = Bc[k] * g.dx;
+    for (int k = 0; k < DIM * DIM; ++k) Bs[k] = DEG == 1 ? Gc[k] * g.inv_dx : Bc[k] * g.dx;
     keep_affine<T, DIM>(transfer, Bs);
 }
 

@@ -260,6 +260,8 @@ template void launch_bin_records<3>(const GridDims &, const BinLists &, const Ti
                                                  hipStream_t);                                                    \
     template void launch_bin_scatter_copy<T, DIM>(const Parts<T> &, const Parts<T> &, const BinLists &,           \
                                                   const TileTables &, const BinScratch &, hipStream_t);           \
+    template void launch_bin_keys_static<T, DIM, 1>(const Parts<T> &, const GridDims &, const BinLists &,         \
+                                                    const BinScratch &, uint32_t *, hipStream_t);                 \
     template void launch_bin_keys_static<T, DIM, 2>(const Parts<T> &, const GridDims &, const BinLists &,         \
                                                     const BinScratch &, uint32_t *, hipStream_t);                 \
     template void launch_bin_keys_static<T, DIM, 3>(const Parts<T> &, const GridDims &, const BinLists &,         \

@@ -351,6 +351,10 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
                                           const TileTables &, const BinLists &, const TileTables &,              \
                                           const BinScratch &, const GridState<T> &, const StepParams<T> &,       \
                                           int64_t, hipStream_t);
+APIC_G2P_INST(float, 2, 1)
+APIC_G2P_INST(float, 3, 1)
+APIC_G2P_INST(double, 2, 1)
+APIC_G2P_INST(double, 3, 1)
 APIC_G2P_INST(float, 2, 2)
 APIC_G2P_INST(float, 2, 3)
 APIC_G2P_INST(float, 3, 2)

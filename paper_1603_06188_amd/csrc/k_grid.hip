@@ -342,6 +342,10 @@ void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState
     template void launch_diag_grid<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &,   \
                                                       int, double, double *, double *, hipStream_t);
 #define APIC_GRID_INST2(T, DIM, DEG) APIC_GRID_INST(T, DIM, DEG, false) APIC_GRID_INST(T, DIM, DEG, true)
+APIC_GRID_INST2(float, 2, 1)
+APIC_GRID_INST2(float, 3, 1)
+APIC_GRID_INST2(double, 2, 1)
+APIC_GRID_INST2(double, 3, 1)
 APIC_GRID_INST2(float, 2, 2)
 APIC_GRID_INST2(float, 2, 3)
 APIC_GRID_INST2(float, 3, 2)

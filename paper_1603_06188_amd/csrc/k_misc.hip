@@ -72,7 +72,7 @@ __device__ __forceinline__ void block_reduce8p(double *acc, double *partials) {
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_diag_particles(Parts<T> P, double dx, double *partials) {
+__global__ __launch_bounds__(256) void k_diag_particles(Parts<T> P, double dx, double affine, double *partials) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += (int64_t)gridDim.x * blockDim.x) {
         int ci[3] = {0, 0, 0};
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_diag_particles(Parts<T> P, double dx, d
             x[a] = ((double)ci[a] + (double)P.off[a * P.s + p]) * dx;
             v[a] = (double)P.v[a * P.s + p];
         }
-        for (int k = 0; k < DIM * DIM; ++k) Bm[k] = (double)P.B[k * P.s + p];
+        for (int k = 0; k < DIM * DIM; ++k) Bm[k] = affine * (double)P.B[k * P.s + p];
         const double mv[3] = {m * v[0], m * v[1], m * v[2]};
         acc[0] += mv[0];
         acc[1] += mv[1];
@@ -123,9 +123,10 @@ void launch_diag_final(const double *partials, int nb, double *out, hipStream_t 
 }
 
 template <typename T, int DIM>
-void launch_diag_particles(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st) {
+void launch_diag_particles(const Parts<T> &P, double dx, bool affine, double *partials, double *out,
+                           hipStream_t st) {
     const int nb = blocks_for(P.n, 256, kDiagBlocks);
-    hipLaunchKernelGGL((k_diag_particles<T, DIM>), dim3(nb), dim3(256), 0, st, P, dx, partials);
+    hipLaunchKernelGGL((k_diag_particles<T, DIM>), dim3(nb), dim3(256), 0, st, P, dx, affine ? 1.0 : 0.0, partials);
     launch_diag_final(partials, nb, out, st);
 }
 
@@ -178,9 +179,8 @@ __global__ __launch_bounds__(64) void k_cfl_final(const double *partials, int nb
 }
 
 template <typename T, int DIM>
-void launch_cfl_bound(const Parts<T> &P, double dx, double *partials, double *out, hipStream_t st) {
+void launch_cfl_bound(const Parts<T> &P, double c, double *partials, double *out, hipStream_t st) {
     const int nb = blocks_for(P.n, 256, kDiagBlocks);
-    const double c = 6.0 * sqrt((double)DIM) / dx;
     hipLaunchKernelGGL((k_cfl_bound<T, DIM>), dim3(nb), dim3(256), 0, st, P, c, partials);
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, partials, nb, out);
 }
@@ -224,9 +224,8 @@ void launch_adapt_dt(const double *src, int n, unsigned long long *slots, double
 // Binary64 bound of every particle into partials[0..nb) (the first pass of
 // launch_cfl_bound); returns nb.
 template <typename T, int DIM>
-int launch_cfl_partials(const Parts<T> &P, double dx, double *partials, hipStream_t st) {
+int launch_cfl_partials(const Parts<T> &P, double c, double *partials, hipStream_t st) {
     const int nb = blocks_for(P.n, 256, kDiagBlocks);
-    const double c = 6.0 * sqrt((double)DIM) / dx;
     hipLaunchKernelGGL((k_cfl_bound<T, DIM>), dim3(nb), dim3(256), 0, st, P, c, partials);
     return nb;
 }
@@ -276,7 +275,7 @@ void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_
 
 #define APIC_MISC_INST(T, DIM)                                                                                  \
     template void launch_copy_state<T, DIM>(const Parts<T> &, const Parts<T> &, hipStream_t);                    \
-    template void launch_diag_particles<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);     \
+    template void launch_diag_particles<T, DIM>(const Parts<T> &, double, bool, double *, double *, hipStream_t); \
     template void launch_cfl_bound<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);         \
     template int launch_cfl_partials<T, DIM>(const Parts<T> &, double, double *, hipStream_t);                  \
     template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t);         \

@@ -139,6 +139,10 @@ void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, con
     template void launch_p2g<T, DIM, DEG, true>(const Parts<T> &, const BinLists &, const BinLists &,            \
                                                 const TileTables &, const Slabs<T> &, const GridState<T> &,      \
                                                 const StepParams<T> &, int64_t, hipStream_t);
+APIC_P2G_INST(float, 2, 1)
+APIC_P2G_INST(float, 3, 1)
+APIC_P2G_INST(double, 2, 1)
+APIC_P2G_INST(double, 3, 1)
 APIC_P2G_INST(float, 2, 2)
 APIC_P2G_INST(float, 2, 3)
 APIC_P2G_INST(float, 3, 2)

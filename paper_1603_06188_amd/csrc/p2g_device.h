@@ -79,7 +79,13 @@ __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *
         return false;
     }
     pp.m = m;
-    const T qs = m * inv_D_factor<T, DEG>() * inv_dx;
+    // Q = m C in cell units of r: C = B D^{-1} = B inv_D / dx^2 (quadratic,
+    // cubic); multilinear carries the lagged C itself (Sec. 5.9)
+    T qs;
+    if constexpr (DEG == 1)
+        qs = m / inv_dx;
+    else
+        qs = m * inv_D_factor<T, DEG>() * inv_dx;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) pp.p[a] = m * v[a];
 #pragma unroll

@@ -33,7 +33,7 @@ import numpy as np
 class Scene:
     name: str
     dim: int
-    degree: int                 # 2 quadratic, 3 cubic B-spline
+    degree: int                 # 1 multilinear (lagged C in B), 2 quadratic, 3 cubic B-spline
     cells: tuple                # cells per axis (nodes = cells + 1)
     dx: float
     precision: str              # "fp32" or "fp64"
@@ -265,7 +265,7 @@ def random_particles(n: int, dim: int = 3, cells: int = 8, degree: int = 2, seed
     rng = np.random.default_rng(seed)
     dx = 1.0 / cells
     if margin is None:
-        margin = 1.5 if degree == 2 else 2.0
+        margin = {1: 1.0, 2: 1.5}.get(degree, 2.0)
     x = margin * dx + rng.random((n, dim)) * (cells - 2 * margin) * dx
     v = rng.normal(0.0, vel_sigma, size=(n, dim))
     B = rng.normal(0.0, b_sigma, size=(n, dim, dim))

@@ -62,7 +62,7 @@ def test_host_validation_without_gpu():
     nbytes = b.apic_workspace_bytes(g, 2_097_152)
     # grid planes + shadow state dominate: at least 2M * 104 B
     assert nbytes > 2_097_152 * 104
-    for field, value in (("dim", 4), ("degree", 1), ("precision", 7), ("options", 8)):
+    for field, value in (("dim", 4), ("degree", 0), ("degree", 4), ("precision", 7), ("options", 8)):
         old = getattr(g, field)
         setattr(g, field, value)
         with pytest.raises(b.ApicError) as e:
