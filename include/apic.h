@@ -9,7 +9,11 @@
  *   apic_p2g          Sec. 3.2 transfer to grid + fused force of Sec. 3.3
  *   apic_grid_update  Sec. 3.3 grid evolution at lambda = 0 (symplectic Euler)
  *   apic_g2p          Sec. 3.4 transfer to particles (lambda = 0 forms of Sec. 5.7)
- * and apic_step runs whole steps for one or many scenes.
+ * and apic_step runs whole steps for one or many scenes.  Variants: the
+ * affine part the transfers carry (apic_params.transfer: APIC, RPIC of
+ * Sec. 2.1, PIC; Sec. 5.6), multilinear weights with the lagged affine
+ * matrix (APIC_MULTILINEAR, Sec. 5.9) and steps whose dt follows the CFL
+ * rule of Sec. 4.3 (APIC_OPT_ADAPTIVE_DT).
  *
  * Conventions shared by every call
  *   - Every pointer inside the structs below is a DEVICE pointer owned by the
@@ -294,9 +298,11 @@ apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out
  * particle state:
  *   *dt_out = nu * dx / max_p (|v_p| + (6 sqrt(d) / dx) |B_p|_F)
  * (the paper bounds every grid velocity the next transfer can produce by
- * that maximum; kappa dx / k = 6 sqrt(d) / dx for both kernels), evaluated
- * in binary64 over all n particles.  *dt_out is +inf when every particle is
- * at rest.  nu must be positive and finite.  Synchronizes `stream`.
+ * that maximum; kappa dx / k = 6 sqrt(d) / dx for quadratic and cubic
+ * weights; APIC_MULTILINEAR uses |v_p| + sqrt(d) dx |C_p|_F for its lagged
+ * C_p), evaluated in binary64 over all n particles.  *dt_out is +inf when
+ * every particle is at rest.  nu must be positive and finite.  Synchronizes
+ * `stream`.
  */
 apic_status apic_cfl_dt(const apic_scene *scene, double nu, double *dt_out, void *stream);
 
