@@ -101,9 +101,9 @@ enum {
                                  Sec. 3.2); same results up to the order of
                                  the sums.  Ignored by other combinations
                                  and with APIC_OPT_ADAPTIVE_DT.              */
-    APIC_OPT_ADAPTIVE_DT = 4  /* apic_step (not apic_step_batch): every step
-                                 chooses its own dt on the device by the CFL
-                                 rule of Sec. 4.3,
+    APIC_OPT_ADAPTIVE_DT = 4  /* apic_step and apic_step_batch: every step
+                                 of every scene chooses its own dt on the
+                                 device by the CFL rule of Sec. 4.3,
                                    dt_k = min(prm.dt, prm.cfl * dx / b_k),
                                    b_k  = max_p (|v_p| + 6 sqrt(d)/dx |B_p|_F)
                                  over the state the step starts from (b_k = 0:

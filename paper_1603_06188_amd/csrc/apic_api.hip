@@ -746,6 +746,7 @@ int share_blocks(int64_t n, int cap) {
 
 template <typename T, int DIM, int DEG, bool COMP>
 apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws, hipStream_t st) {
+    const bool adaptive = (scenes[0].grid.options & APIC_OPT_ADAPTIVE_DT) != 0;
     std::vector<SceneDesc<T>> descs((size_t)n);
     std::vector<int32_t> starts((size_t)BK_COUNT * (size_t)(n + 1));
     std::vector<SceneState *> states((size_t)n);
@@ -787,6 +788,13 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         d.rc = v.L.rc;
         d.cur0 = ss.cur;
         d.where0 = where;
+        d.dt_cap = scenes[i].prm.dt;
+        d.nu_dx = scenes[i].prm.cfl * scenes[i].grid.dx;
+        if (adaptive) {
+            char *w = (char *)scenes[i].workspace;
+            d.g.cfl = (unsigned long long *)(w + v.L.o_cfl);
+            d.prm.dt_dev = (const double *)(w + v.L.o_dt);
+        }
         states[(size_t)i] = &ss;
         const int64_t np = scenes[i].p.n;
         const int share[BK_COUNT] = {share_blocks(np, 4096), share_blocks(np, 8192), share_blocks(np, 2048),
@@ -833,6 +841,7 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
     const int32_t *ds = (const int32_t *)((const char *)bws + o_start);
     auto start_of = [&](int k) { return ds + (size_t)k * (n + 1); };
     for (int32_t k = 0; k < n_steps; ++k) {
+        if (adaptive) launch_adapt_dt_batch<T, DIM>(dd, start_of(BK_COPY), n, total[BK_COPY], k == 0, st);
         timed(APIC_PHASE_P2G, st,
               [&] { launch_p2g_batch<T, DIM, DEG, COMP>(dd, start_of(BK_P2G), n, k, total[BK_P2G], st); });
         timed(APIC_PHASE_GRID_UPDATE, st, [&] {
@@ -844,7 +853,7 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
             launch_bin_finalize_batch<T>(dd, start_of(BK_FINAL), n, k, total[BK_FINAL], st);
         });
         timed(APIC_PHASE_G2P, st,
-              [&] { launch_g2p_batch<T, DIM, DEG>(dd, start_of(BK_G2P), n, k, total[BK_G2P], st); });
+              [&] { launch_g2p_batch<T, DIM, DEG>(dd, start_of(BK_G2P), n, k, total[BK_G2P], adaptive, st); });
     }
     launch_copy_back_batch<T, DIM>(dd, start_of(BK_COPY), n, n_steps, total[BK_COPY], st);
     for (int32_t i = 0; i < n; ++i) {
@@ -958,8 +967,6 @@ apic_status apic_step_batch(apic_scene *scenes, int32_t n_scenes, int32_t n_step
         const apic_grid_desc &a = scenes[0].grid, &b = scenes[k].grid;
         if (a.dim != b.dim || a.degree != b.degree || a.precision != b.precision || a.options != b.options)
             return fail(APIC_E_INVAL, "scene %d differs from scene 0 in dim, degree, precision or options", k);
-        if (b.options & APIC_OPT_ADAPTIVE_DT)
-            return fail(APIC_E_UNSUPPORTED, "adaptive steps are taken by apic_step, not apic_step_batch");
     }
     {
         std::unordered_map<void *, int32_t> seen;

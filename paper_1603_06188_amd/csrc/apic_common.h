@@ -152,6 +152,7 @@ struct SceneDesc {
     StepParams<T> prm;
     int64_t rc;            // record capacity
     int32_t cur0, where0;
+    double dt_cap, nu_dx;  // adaptive steps: dt = min(dt_cap, nu_dx / bound)
 };
 
 // Kernels of a batched step; per kind, scene s owns blocks

@@ -97,7 +97,14 @@ template <typename T, int DIM>
 void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
                               hipStream_t st);
 template <typename T, int DIM, int DEG>
-void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st);
+void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, bool adapt,
+                      hipStream_t st);
+// Adaptive batched steps: before each step, every scene's dt from its bound
+// slots (first: the slots cleared and raised by a pass over the particles
+// each scene starts the call with; blocks as the copy-back table).
+template <typename T, int DIM>
+void launch_adapt_dt_batch(const SceneDesc<T> *descs, const int32_t *copy_start, int n, int copy_blocks, bool first,
+                           hipStream_t st);
 // after k steps: scenes whose particles are in the shadow copy them back
 template <typename T, int DIM>
 void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,

@@ -305,20 +305,94 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_wav
     g2p_body<T, DIM, DEG, ADAPT>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ADAPT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p_batch(
     const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k);
     const SceneDesc<T> &d = *b.d;
     Parts<T> src = d.bufs[b.sp.src], dst = d.bufs[b.sp.src ^ 1];
     if (!src.id || !dst.id) src.id = dst.id = nullptr;
-    g2p_body<T, DIM, DEG, false>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm, b.blk,
+    g2p_body<T, DIM, DEG, ADAPT>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm, b.blk,
                                  b.nblk);
 }
 
 template <typename T, int DIM, int DEG>
-void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, bool adapt,
+                      hipStream_t st) {
+    if (adapt)
+        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, true>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
+                           n, k);
+    else
+        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, false>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
+                           n, k);
+}
+
+// --- adaptive batched steps (Sec. 4.3) ---------------------------------------------
+// One block per scene: zero its bound slots.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cfl_clear_batch(const SceneDesc<T> *descs) {
+    unsigned long long *slots = descs[blockIdx.x].g.cfl;
+    for (int i = (int)threadIdx.x; i < kVmaxSlots; i += (int)blockDim.x) slots[i] = 0ull;
+}
+
+// Blocks by particle count (start): each scene's bound over the particles
+// it starts the call with, raised into its slots.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_cfl_bound_batch(const SceneDesc<T> *descs, const int32_t *start, int n) {
+    const int s = scene_of_block(start, n, blockIdx.x);
+    const SceneDesc<T> &d = descs[s];
+    const Parts<T> P = d.bufs[d.where0];
+    const uint32_t b = blockIdx.x - (uint32_t)start[s], nb = (uint32_t)(start[s + 1] - start[s]);
+    double m = 0.0;
+    for (int64_t p = (int64_t)b * 256 + threadIdx.x; p < P.n; p += (int64_t)nb * 256) {
+        T v[DIM], B[DIM * DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) v[a] = P.v[a * P.s + p];
+#pragma unroll
+        for (int q = 0; q < DIM * DIM; ++q) B[q] = P.B[q * P.s + p];
+        cfl_fold<T, DIM>(v, B, d.g.cfl_c, m);
+    }
+    cfl_raise(d.g.cfl, b * 4 + (threadIdx.x >> 6), m);
+}
+
+// One wavefront per scene: dt = min(dt_cap, nu_dx / bound) from its slots
+// (bound 0 or NaN: dt_cap), recorded with the running time; slots zeroed.
+template <typename T>
+__global__ __launch_bounds__(64) void k_adapt_dt_batch(const SceneDesc<T> *descs) {
+    const SceneDesc<T> &d = descs[blockIdx.x];
+    const int lane = (int)threadIdx.x;
+    unsigned long long *slots = d.g.cfl;
+    double bnd = 0.0;
+    for (int i = lane; i < kVmaxSlots; i += 64) {
+        const double y = __longlong_as_double((long long)slots[i]);
+        bnd = y > bnd || y != y ? y : bnd;
+        slots[i] = 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(bnd, o, 64);
+        bnd = y > bnd || y != y ? y : bnd;
+    }
+    if (lane == 0) {
+        double dt = d.dt_cap;
+        if (bnd > 0.0) {
+            const double c = d.nu_dx / bnd;
+            dt = c < dt ? c : dt;
+        }
+        double *state = const_cast<double *>(d.prm.dt_dev);
+        state[0] = dt;
+        state[1] += dt;
+    }
+}
+
+template <typename T, int DIM>
+void launch_adapt_dt_batch(const SceneDesc<T> *descs, const int32_t *copy_start, int n, int copy_blocks, bool first,
+                           hipStream_t st) {
+    if (first) {
+        hipLaunchKernelGGL((k_cfl_clear_batch<T>), dim3((unsigned)n), dim3(256), 0, st, descs);
+        hipLaunchKernelGGL((k_cfl_bound_batch<T, DIM>), dim3((unsigned)copy_blocks), dim3(256), 0, st, descs,
+                           copy_start, n);
+    }
+    hipLaunchKernelGGL((k_adapt_dt_batch<T>), dim3((unsigned)n), dim3(64), 0, st, descs);
 }
 
 template <typename T, int DIM, int DEG>
@@ -342,7 +416,7 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
 #define APIC_G2P_INST(T, DIM, DEG)                                                                               \
     template void launch_bin_keys_moved_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int,  \
                                                            hipStream_t);                                          \
-    template void launch_g2p_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int,             \
+    template void launch_g2p_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int, bool,       \
                                                 hipStream_t);                                                     \
     template void launch_bin_keys_moved<T, DIM, DEG>(const Parts<T> &, const BinLists &, const TileTables &,     \
                                                      const GridState<T> &, const StepParams<T> &,                \
@@ -363,5 +437,12 @@ APIC_G2P_INST(double, 2, 2)
 APIC_G2P_INST(double, 2, 3)
 APIC_G2P_INST(double, 3, 2)
 APIC_G2P_INST(double, 3, 3)
+
+template void launch_adapt_dt_batch<float, 2>(const SceneDesc<float> *, const int32_t *, int, int, bool, hipStream_t);
+template void launch_adapt_dt_batch<float, 3>(const SceneDesc<float> *, const int32_t *, int, int, bool, hipStream_t);
+template void launch_adapt_dt_batch<double, 2>(const SceneDesc<double> *, const int32_t *, int, int, bool,
+                                               hipStream_t);
+template void launch_adapt_dt_batch<double, 3>(const SceneDesc<double> *, const int32_t *, int, int, bool,
+                                               hipStream_t);
 
 }  // namespace apic

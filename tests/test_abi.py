@@ -130,27 +130,3 @@ def test_invalid_scenes_are_rejected_before_any_launch():
         want = b.APIC_E_WORKSPACE if name == "workspace" else b.APIC_E_INVAL
         assert e.value.code == want, (name, e.value.code, str(e.value))
 
-
-def test_batch_refuses_adaptive_steps_before_any_launch():
-    """apic_step_batch leaves adaptive steps to apic_step: a scene that asks
-    for them is refused with APIC_E_UNSUPPORTED during validation (the
-    workspace pointers below are never dereferenced)."""
-    from paper_1603_06188_amd import binding as b
-    sc = b.ApicScene()
-    g = sc.grid
-    g.dim, g.degree, g.precision, g.options = 3, 2, b.APIC_F32, b.APIC_OPT_ADAPTIVE_DT
-    for a in range(3):
-        g.cells[a] = 16
-    g.dx = 1.0 / 16
-    p = sc.p
-    p.n, p.stride = 10, 10
-    fake = 1 << 20
-    p.cell = p.off = p.v = p.B = p.F = p.mass = fake
-    sc.prm.dt, sc.prm.rho0, sc.prm.cfl = 1e-4, 1.0, 0.5
-    sc.workspace = 1 << 30
-    sc.workspace_bytes = b.apic_workspace_bytes(g, 10)
-    arr = (b.ApicScene * 1)(sc)
-    nbytes = ctypes.c_size_t()
-    assert b._lib.apic_batch_workspace_bytes(1, ctypes.byref(nbytes)) == b.APIC_OK
-    rc = b._lib.apic_step_batch(arr, 1, 1, ctypes.c_void_p(1 << 31), nbytes, None)
-    assert rc == b.APIC_E_UNSUPPORTED, (rc, b._lib.apic_last_error())

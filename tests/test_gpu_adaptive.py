@@ -100,3 +100,37 @@ def test_bound_pass_and_folded_bound_agree_with_apic_cfl_dt():
     ds2.step(3)                   # third step: the bound folded into the second G2P
     dt_folded, _ = ds2.step_time()
     assert dt_folded == pytest.approx(full, rel=1e-6)  # two binary32 runs, mover order aside
+
+
+def test_batched_adaptive_steps_match_each_scene_alone():
+    """apic_step_batch with adaptive steps: every scene takes its own dt per
+    step, as when it runs alone (binary64, three scenes of different size
+    and speed), and the smallest matches the oracle chained with the rule."""
+    b = _b()
+    nu, cap, steps = 0.4, 1e-2, 3
+    hosts = [dataclasses.replace(
+        scenes.random_particles(n, dim=3, cells=c, degree=2, seed=70 + k, precision="fp64", vel_sigma=vs,
+                                f_sigma=0.02, b_sigma=0.01, model=1), dt=cap, cfl=nu)
+        for k, (n, c, vs) in enumerate(((1500, 12, 0.5), (6000, 20, 1.0), (900, 10, 0.3)))]
+    batch = b.SceneBatch([b.DeviceScene(h, adaptive=True) for h in hosts])
+    batch.step(steps)
+    alone = [b.DeviceScene(h, adaptive=True) for h in hosts]
+    for a in alone:
+        a.step(steps)
+    times = []
+    for k, (d, a) in enumerate(zip(batch.scenes, alone)):
+        assert d.flags() == 0 and a.flags() == 0, k
+        (dl, t), (dla, ta) = d.step_time(), a.step_time()
+        assert t == pytest.approx(ta, rel=1e-12) and dl == pytest.approx(dla, rel=1e-12), k
+        times.append(t)
+        got, ref = d.state(), a.state()
+        for key in ("x", "v", "B", "F"):
+            assert rel(got[key], ref[key]) <= 1e-12, (k, key)
+    assert len(set(round(t, 12) for t in times)) == 3  # each scene took its own steps
+    h = hosts[2]
+    x, v, B, F, dts = _adaptive_chain(h, steps, cap, nu)
+    assert max(dts) < cap
+    got = batch.scenes[2].state()
+    assert abs(times[2] - sum(dts)) <= 1e-11 * sum(dts)
+    for key, ref in (("v", v), ("B", B), ("F", F)):
+        assert rel(got[key], ref) <= 1e-11, (key, rel(got[key], ref))
