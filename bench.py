@@ -188,6 +188,8 @@ def main(argv=None):
                     help="cube: the 128^3 elastic cube (headline); batch: 512 bodies, batched vs per-scene loop; "
                          "spheres: two spheres on 256^3 cells, cubic, three precision modes")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency replay")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="cube: skip the adaptive-step and multilinear legs (profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-pool", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.7)
@@ -281,53 +283,55 @@ def main(argv=None):
     b.apic_timing_enable(False)
     phases = list(timing)
     dur = {p: timing[p][1] for p in phases}
-    # the same K steps with adaptive steps (APIC_OPT_ADAPTIVE_DT, nu = 0.5):
-    # the CFL rule allows ~0.06 here, so the 1e-4 cap is every step's dt and
-    # the work is the fixed-step work plus choosing dt on the device
-    ad = b.DeviceScene(dataclasses.replace(scene, cfl=0.5), compensated=compensated, with_id=False, adaptive=True)
-    ad.step(args.warmup, args.sort_every)
-    ad.upload(scene)
-    ad.clear_flags()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ad.step(args.steps, args.sort_every)
-    torch.cuda.synchronize()
-    el_ad = time.perf_counter() - t2
-    ad_dt, _ = ad.step_time()
-    adaptive = {"ms_per_step": el_ad / args.steps * 1e3, "vs_fixed": el / el_ad, "cfl": 0.5, "dt_last": ad_dt,
-                "flags": ad.flags()}
-    del ad
-    # the multilinear kernel with the lagged affine matrix (APIC_MULTILINEAR,
-    # Sec. 5.9) against the quadratic one on the same cube as transfer plus
-    # gravity only (model 0): with the neo-Hookean force the lagged C_p grows
-    # tenfold per step at the free surface (the oracle inverts elements by
-    # step 5 at 128^3), so the elastic multilinear cube has no valid steps
-    def transfer_run(degree):
-        sc = dataclasses.replace(scenes.cube3d(cells=args.cells, degree=degree), model=0)
-        dv = b.DeviceScene(sc, compensated=compensated, with_id=False)
-        dv.step(args.warmup, args.sort_every)
-        dv.upload(sc)
-        dv.clear_flags()
+    adaptive = multilinear = None
+    if not args.headline_only:
+        # the same K steps with adaptive steps (APIC_OPT_ADAPTIVE_DT, nu = 0.5):
+        # the CFL rule allows ~0.06 here, so the 1e-4 cap is every step's dt and
+        # the work is the fixed-step work plus choosing dt on the device
+        ad = b.DeviceScene(dataclasses.replace(scene, cfl=0.5), compensated=compensated, with_id=False, adaptive=True)
+        ad.step(args.warmup, args.sort_every)
+        ad.upload(scene)
+        ad.clear_flags()
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        dv.step(args.steps, args.sort_every)
+        t2 = time.perf_counter()
+        ad.step(args.steps, args.sort_every)
         torch.cuda.synchronize()
-        el_t = time.perf_counter() - t
-        fl = dv.flags()
-        dv.upload(sc)
-        torch.cuda.synchronize()
-        b.apic_timing_enable(True)
-        b.apic_timing_read()
-        dv.step(args.steps, args.sort_every)
-        torch.cuda.synchronize()
-        tm = b.apic_timing_read()
-        b.apic_timing_enable(False)
-        del dv
-        return {"value": sc.n * args.steps / el_t if fl == 0 else None, "unit": "particle-updates/s",
-                "ms_per_step": el_t / args.steps * 1e3, "phase_ms": {p: round(tm[p][1], 5) for p in tm},
-                "g2p_GBps": (sc.n * G2P_PARTICLE_B) / (tm["g2p"][1] * 1e-3) / 1e9, "flags": fl}
-    multilinear = {"workload": "the cube as transfer + gravity (model 0)", "multilinear": transfer_run(1),
-                   "quadratic": transfer_run(2)}
+        el_ad = time.perf_counter() - t2
+        ad_dt, _ = ad.step_time()
+        adaptive = {"ms_per_step": el_ad / args.steps * 1e3, "vs_fixed": el / el_ad, "cfl": 0.5, "dt_last": ad_dt,
+                    "flags": ad.flags()}
+        del ad
+        # the multilinear kernel with the lagged affine matrix (APIC_MULTILINEAR,
+        # Sec. 5.9) against the quadratic one on the same cube as transfer plus
+        # gravity only (model 0): with the neo-Hookean force the lagged C_p grows
+        # tenfold per step at the free surface (the oracle inverts elements by
+        # step 5 at 128^3), so the elastic multilinear cube has no valid steps
+        def transfer_run(degree):
+            sc = dataclasses.replace(scenes.cube3d(cells=args.cells, degree=degree), model=0)
+            dv = b.DeviceScene(sc, compensated=compensated, with_id=False)
+            dv.step(args.warmup, args.sort_every)
+            dv.upload(sc)
+            dv.clear_flags()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            dv.step(args.steps, args.sort_every)
+            torch.cuda.synchronize()
+            el_t = time.perf_counter() - t
+            fl = dv.flags()
+            dv.upload(sc)
+            torch.cuda.synchronize()
+            b.apic_timing_enable(True)
+            b.apic_timing_read()
+            dv.step(args.steps, args.sort_every)
+            torch.cuda.synchronize()
+            tm = b.apic_timing_read()
+            b.apic_timing_enable(False)
+            del dv
+            return {"value": sc.n * args.steps / el_t if fl == 0 else None, "unit": "particle-updates/s",
+                    "ms_per_step": el_t / args.steps * 1e3, "phase_ms": {p: round(tm[p][1], 5) for p in tm},
+                    "g2p_GBps": (sc.n * G2P_PARTICLE_B) / (tm["g2p"][1] * 1e-3) / 1e9, "flags": fl}
+        multilinear = {"workload": "the cube as transfer + gravity (model 0)", "multilinear": transfer_run(1),
+                       "quadratic": transfer_run(2)}
 
     n = scene.n
     comp_b = 16 if compensated else 0
@@ -363,8 +367,7 @@ def main(argv=None):
         },
         "phase_ms": {p: round(dur[p], 5) for p in phases},
         "cfl": {"dt_max": cfl_dt, "call_ms": round(cfl_ms, 4)},
-        "adaptive_dt": adaptive,
-        "multilinear": multilinear,
+        **({"adaptive_dt": adaptive, "multilinear": multilinear} if not args.headline_only else {}),
         "flags": flags,
         "roofline": {
             "bound": "hbm",
