@@ -81,10 +81,11 @@ enum { APIC_MODEL_NONE = 0, APIC_MODEL_NEO_HOOKEAN = 1 };
  *   APIC_TRANSFER_RPIC  rigid: C_p is the angular velocity omega_p^* that
  *                       conserves the grid's angular momentum (Sec. 2.1);
  *                       B_p holds omega_p^* D_p, the skew part of what APIC
- *                       would store, and the transfer to grid uses the skew
- *                       part of the B_p it is given.
- *   APIC_TRANSFER_PIC   C_p = 0: the transfer to grid ignores B_p and the
- *                       transfer to particles stores B_p = 0.
+ *                       would store.
+ *   APIC_TRANSFER_PIC   C_p = 0: B_p = 0.
+ * apic_p2g, apic_step and apic_step_batch first put the caller's B_p in that
+ * form, in place (RPIC: its skew part, PIC: zero); the transfers to
+ * particles store it so.
  * Positions and F are updated the same way in all three.
  */
 enum { APIC_TRANSFER_APIC = 0, APIC_TRANSFER_RPIC = 1, APIC_TRANSFER_PIC = 2 };

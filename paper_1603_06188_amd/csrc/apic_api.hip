@@ -543,6 +543,7 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
                 if (rc != APIC_OK) return rc;
                 v = make_view<T>(s, cap, ss);
             }
+            launch_keep_affine<T, DIM>(v.user, s->prm.transfer, st);
             launch_p2g<T, DIM, DEG, COMP>(v.user, v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur], v.slabs, v.g,
                                           v.prm, v.L.rc, st);
             ss.grid_meta = ss.cur;
@@ -618,6 +619,7 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         v.prm.dt_dev = dt_state;
     }
     const double nu_dx = s->prm.cfl * s->grid.dx;
+    launch_keep_affine<T, DIM>(bufs[where], s->prm.transfer, st);
     bool slabs_ready = false;  // the slabs already hold this step's P2G
     for (int32_t k = 0; k < n_steps; ++k) {
         if (sort_every > 0 && k > 0 && k % sort_every == 0) {
@@ -772,6 +774,7 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
             ss.binned = true;
             where = 1;
         }
+        launch_keep_affine<T, DIM>(where ? v.shadow : v.user, scenes[i].prm.transfer, st);
         SceneDesc<T> &d = descs[(size_t)i];
         d.bufs[0] = v.user;
         d.bufs[1] = v.shadow;

@@ -110,6 +110,11 @@ template <typename T, int DIM>
 void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
                             hipStream_t st);
 
+// The caller's B in the form the transfer carries (RPIC: skew part, PIC:
+// zero), in place; nothing for APIC.
+template <typename T, int DIM>
+void launch_keep_affine(const Parts<T> &P, int transfer, hipStream_t st);
+
 // --- observation ----------------------------------------------------------------
 // out[k] = sum over b < nb of partials[8 b + k], k < 8, in a fixed order.
 void launch_diag_final(const double *partials, int nb, double *out, hipStream_t st);

@@ -161,17 +161,23 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
     }
 }
 
-// Three waves per SIMD (at most 168 VGPRs): the resolve loop keeps a
-// particle's whole support in registers, and the latency of the queue's
-// LDS traffic needs the third wave.
+// Three waves per SIMD (at most 168 VGPRs) for binary32 3D quadratic, whose
+// resolve loop otherwise takes 170 VGPRs (two waves): the latency of the
+// queue's LDS traffic needs the third wave.  The other variants are left to
+// the compiler (the hint slowed the cubic pass by 40 % at the same occupancy).
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bin_keys_moved(
+constexpr int keys_min_waves() {
+    return (sizeof(T) == 4 && DIM == 3 && DEG == 2) ? 3 : 1;
+}
+
+template <typename T, int DIM, int DEG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_waves<T, DIM, DEG>()))) void k_bin_keys_moved(
     Parts<T> P, BinLists cur, TileTables ctab, GridState<T> g, StepParams<T> prm, BinLists nxt, BinScratch sc) {
     keys_body<T, DIM, DEG>(P, cur, ctab, g, prm, nxt, sc, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int DIM, int DEG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bin_keys_moved_batch(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_waves<T, DIM, DEG>()))) void k_bin_keys_moved_batch(
     const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k);
     const SceneDesc<T> &d = *b.d;

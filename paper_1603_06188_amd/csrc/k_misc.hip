@@ -185,6 +185,28 @@ void launch_cfl_bound(const Parts<T> &P, double c, double *partials, double *out
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, partials, nb, out);
 }
 
+// --- transfer variants (Sec. 5.6) -------------------------------------------------
+// The caller's B planes in the form the transfer carries (skew part for
+// RPIC, zero for PIC), in place, once per call: the transfers to particles
+// store that form themselves, so the transfers to grid can read B as is.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_keep_affine(Parts<T> P, int transfer) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    T B[DIM * DIM];
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) B[k] = P.B[k * P.s + p];
+    keep_affine<T, DIM>(transfer, B);
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) P.B[k * P.s + p] = B[k];
+}
+
+template <typename T, int DIM>
+void launch_keep_affine(const Parts<T> &P, int transfer, hipStream_t st) {
+    if (P.n == 0 || transfer == APIC_TRANSFER_APIC) return;
+    hipLaunchKernelGGL((k_keep_affine<T, DIM>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, transfer);
+}
+
 // --- adaptive step (Sec. 4.3) ------------------------------------------------------
 // One wavefront: b = max of src[0..n) (binary64; NaN propagates), then
 //   dt = b > 0 ? min(cap, nu_dx / b) : cap      (a NaN bound gives cap: the
@@ -278,6 +300,7 @@ void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_
     template void launch_diag_particles<T, DIM>(const Parts<T> &, double, bool, double *, double *, hipStream_t); \
     template void launch_cfl_bound<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);         \
     template int launch_cfl_partials<T, DIM>(const Parts<T> &, double, double *, hipStream_t);                  \
+    template void launch_keep_affine<T, DIM>(const Parts<T> &, int, hipStream_t);                                \
     template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t);         \
     template void launch_unpack_positions<T, DIM>(const Parts<T> &, double *, double, hipStream_t);
 APIC_MISC_INST(float, 2)

@@ -67,7 +67,6 @@ __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *
         atomicOr(flags, FLAG_NONFINITE);
         return false;
     }
-    keep_affine<T, DIM>(prm.transfer, B);
     bool same = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
