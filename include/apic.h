@@ -111,7 +111,8 @@ enum {
                                  prm.dt).  The first step of a call bounds all
                                  particles in a pass of its own; each later
                                  step takes b_k from the transfer to particles
-                                 that wrote the state (fused into it).  The
+                                 that wrote the state (fused into it,
+                                 evaluated in the state's precision).  The
                                  steps' dt are read back by apic_step_time. */
 };
 

@@ -91,21 +91,29 @@ __device__ __forceinline__ void move_position(const int *ci, const T *off, const
     }
 }
 
-// The CFL quantity of Sec. 4.3 of one particle's new state, |v| + c |B|_F
-// in binary64, folded into a running maximum (a NaN state propagates).
+// The CFL quantity of Sec. 4.3 of one particle's new state, |v| + c |B|_F,
+// evaluated in the state's precision and folded into a running maximum (a
+// NaN state propagates).  The bound passes over particles (first step of a
+// call, apic_cfl_dt) evaluate it in binary64.
 template <typename T, int DIM>
-__device__ __forceinline__ void cfl_fold(const T *v, const T *B, double c, double &m) {
+__device__ __forceinline__ void cfl_fold(const T *v, const T *B, double c, T &m) {
+    T vv = T(0), bb = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) vv += v[a] * v[a];
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) bb += B[k] * B[k];
+    const T u = sqrt(vv) + (T)c * sqrt(bb);
+    m = u > m || u != u ? u : m;
+}
+
+// The same in binary64 (the bound passes over particles).
+template <typename T, int DIM>
+__device__ __forceinline__ void cfl_fold64(const T *v, const T *B, double c, double &m) {
     double vv = 0.0, bb = 0.0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const double x = (double)v[a];
-        vv += x * x;
-    }
+    for (int a = 0; a < DIM; ++a) vv += (double)v[a] * (double)v[a];
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) {
-        const double x = (double)B[k];
-        bb += x * x;
-    }
+    for (int k = 0; k < DIM * DIM; ++k) bb += (double)B[k] * (double)B[k];
     const double u = sqrt(vv) + c * sqrt(bb);
     m = u > m || u != u ? u : m;
 }

@@ -230,7 +230,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     const T dt_inv_dx = prm.dt * g.inv_dx, gs = prm.dt * g.inv_dx;
     const uint32_t items = walk.nrec + dead_chunks(src.n, walk.live);
     const int64_t ss = src.s, ds = dst.s;
-    double cmax = 0.0;  // CFL bound of the particles this lane writes (when asked)
+    T cmax = T(0);  // CFL bound of the particles this lane writes (when asked)
     for (uint32_t r = blk * 4 + (uint32_t)wv; r < items; r += nblk * 4) {
         if (r >= walk.nrec) {
             carry_dead<T, DIM>(src, dst, sc, walk.live, live_nxt, r - walk.nrec);
@@ -257,7 +257,6 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                 T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
                 g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
-                if constexpr (ADAPT) cfl_fold<T, DIM>(vn, Bs, g.cfl_c, cmax);
                 const T *off = raw.off;
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);
@@ -294,18 +293,20 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                     plane_at(dst.B + k * ds, qb) = Bs[k];
                     plane_at(dst.F + k * ds, qb) = Fn[k];
                 }
+                // after the stores, when the particle's other values are dead
+                if constexpr (ADAPT) cfl_fold<T, DIM>(vn, Bs, g.cfl_c, cmax);
             }
             raw = raw_n;
         }
         wave_lds_sync();
     }
-    if constexpr (ADAPT) cfl_raise(g.cfl, blk * 4 + (uint32_t)wv, cmax);
+    if constexpr (ADAPT) cfl_raise(g.cfl, blk * 4 + (uint32_t)wv, (double)cmax);
     (void)cmax;
     (void)TE;
 }
 
 template <typename T, int DIM, int DEG, bool ADAPT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADAPT ? 1 : g2p_min_waves<T, DIM, DEG>()))) void k_g2p(
     Parts<T> src, Parts<T> dst, BinLists cur, TileTables ctab, BinLists nxt, TileTables ntab, BinScratch sc,
     GridState<T> g, StepParams<T> prm) {
     g2p_body<T, DIM, DEG, ADAPT>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(256) void k_cfl_bound_batch(const SceneDesc<T> *des
         for (int a = 0; a < DIM; ++a) v[a] = P.v[a * P.s + p];
 #pragma unroll
         for (int q = 0; q < DIM * DIM; ++q) B[q] = P.B[q * P.s + p];
-        cfl_fold<T, DIM>(v, B, d.g.cfl_c, m);
+        cfl_fold64<T, DIM>(v, B, d.g.cfl_c, m);
     }
     cfl_raise(d.g.cfl, b * 4 + (threadIdx.x >> 6), m);
 }

@@ -83,8 +83,9 @@ def test_cap_binds_and_time_accumulates_over_calls():
 
 
 def test_bound_pass_and_folded_bound_agree_with_apic_cfl_dt():
-    """After a call, the dt the next step would take from the folded bound
-    equals apic_cfl_dt's full pass over the stored state (both binary64)."""
+    """After a call, the dt the first step of the next call takes (a binary64
+    pass) equals apic_cfl_dt's; the dt a third step takes from the bound the
+    second G2P folded in (binary32 here) agrees to binary32 rounding."""
     b = _b()
     s = scenes.random_particles(4000, dim=3, cells=16, degree=2, seed=42, precision="fp32", vel_sigma=0.5,
                                 f_sigma=0.02, b_sigma=0.01, model=1)
