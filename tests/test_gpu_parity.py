@@ -261,6 +261,24 @@ def test_empty_scene():
     assert ds.flags() == 0
 
 
+@pytest.mark.parametrize("degree,transfer", [(2, 1), (1, 0), (3, 2)])
+def test_empty_scene_adaptive_and_variants(degree, transfer):
+    """No particles with adaptive steps (the bound is 0, so every step takes
+    the cap), an RPIC or PIC transfer, or the multilinear kernel: the steps
+    run, the clock advances by the cap and nothing is flagged."""
+    import dataclasses
+    b = _b()
+    s = scenes.cube3d(cells=8, precision="fp32", degree=degree).subset(np.arange(0))
+    s = dataclasses.replace(s, transfer=transfer, cfl=0.5)
+    ds = b.DeviceScene(s, adaptive=True)
+    ds.step(3)
+    dt_last, t = ds.step_time()
+    assert dt_last == s.dt and t == s.dt + s.dt + s.dt
+    assert np.all(ds.export(b.APIC_GRID_MASS) == 0)
+    assert ds.flags() == 0
+    assert ds.cfl_dt(0.5) == np.inf
+
+
 def test_lone_particle_is_stable_on_gpu():
     """Sec. 5.4 on the GPU: v and B unchanged, x moves by dt v."""
     b = _b()
