@@ -135,3 +135,23 @@ def test_batched_adaptive_steps_match_each_scene_alone():
     assert abs(times[2] - sum(dts)) <= 1e-11 * sum(dts)
     for key, ref in (("v", v), ("B", B), ("F", F)):
         assert rel(got[key], ref) <= 1e-11, (key, rel(got[key], ref))
+
+
+def test_fused_option_is_off_with_adaptive_steps():
+    """Asking for the fused transfer and adaptive steps together runs the
+    adaptive, unfused path: the same dt and state as adaptive steps alone
+    (binary32 quadratic 3D, where fusion would otherwise apply)."""
+    b = _b()
+    s = scenes.random_particles(4000, dim=3, cells=16, degree=2, seed=43, precision="fp32", vel_sigma=0.5,
+                                f_sigma=0.02, b_sigma=0.01, model=1)
+    s = dataclasses.replace(s, dt=1e-2, cfl=0.4)
+    both = b.DeviceScene(s, compensated=True, fused=True, adaptive=True)
+    alone = b.DeviceScene(s, compensated=True, adaptive=True)
+    both.step(3)
+    alone.step(3)
+    assert both.flags() == alone.flags() == 0
+    (d1, t1), (d2, t2) = both.step_time(), alone.step_time()
+    assert t1 == pytest.approx(t2, rel=1e-6) and d1 == pytest.approx(d2, rel=1e-6)
+    got, ref = both.state(), alone.state()
+    for key in ("x", "v", "B", "F"):
+        assert rel(got[key], ref[key]) <= 1e-6, key  # same kernels; mover order aside
