@@ -99,8 +99,15 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
     }
 }
 
+// Binary32 3D cubic: two waves per SIMD (256 VGPRs, a few spilled) instead
+// of one; its accumulation issues VALU for under half of its time at one.
+template <typename T, int DIM, int DEG>
+constexpr int p2g_min_waves() {
+    return (sizeof(T) == 4 && DIM == 3 && DEG == 3) ? 2 : 1;
+}
+
 template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_p2g(Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(p2g_min_waves<T, DIM, DEG>()))) void k_p2g(Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs,
                                              GridState<T> g, StepParams<T> prm) {
     p2g_body<T, DIM, DEG, COMP>(P, cur, nxt, tab, slabs, g, prm, blockIdx.x, gridDim.x);
 }
