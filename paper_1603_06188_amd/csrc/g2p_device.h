@@ -232,10 +232,12 @@ __device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> 
 }
 
 // Occupancy target: binary32 quadratic 3D fits 128 registers (4 waves per
-// SIMD); other variants are left to the compiler.
+// SIMD); binary64 cubic 3D runs at 2 (256 registers, a few spilled) rather
+// than the compiler's 1; other variants are left to the compiler.
 template <typename T, int DIM, int DEG>
 constexpr int g2p_min_waves() {
-    return (sizeof(T) == 4 && DEG == 2) ? 4 : 1;
+    if (sizeof(T) == 4 && DEG == 2) return 4;
+    return (sizeof(T) == 8 && DIM == 3 && DEG == 3) ? 2 : 1;
 }
 
 // What G2P reads of a particle (loaded one chunk ahead of its use).
