@@ -24,6 +24,12 @@ cites the passage of the paper it follows:
 * ``cfl_dt``                           -- CFL rule of Sec. 4.3
 * degree 1 everywhere: multilinear weights with the lagged C_p of Sec. 5.9
   (the B planes carry C_p), APIC transfer only
+* ``neo_hookean_dP`` / ``forces_at`` / ``force_differential`` -- the stress
+  differential and the force and force-derivative product of Sec. 3.3 with
+  the nodes displaced
+* ``midpoint_step``                    -- the implicit midpoint member
+  (lambda = 1/2) of Sec. 3.3, solved as the minimization of Sec. 4.1 by
+  Newton's method with the mass-inner-product conjugate gradient of Sec. 4.2
 """
 from __future__ import annotations
 
@@ -117,6 +123,16 @@ def _load():
         lib.oracle_cfl_dt_lagged.restype = ctypes.c_double
         lib.oracle_cfl_dt_lagged.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                              _dp, _dp]
+        lib.oracle_neo_hookean_dP.restype = ctypes.c_int
+        lib.oracle_neo_hookean_dP.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        lib.oracle_forces_at.restype = ctypes.c_int
+        lib.oracle_forces_at.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                         _dp, _dp, _dp]
+        lib.oracle_force_differential.restype = ctypes.c_int
+        lib.oracle_force_differential.argtypes = [G, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
+                                                  ctypes.c_double, _dp, _dp, _dp]
+        lib.oracle_node_in_band.restype = ctypes.c_int
+        lib.oracle_node_in_band.argtypes = [G, _ip, _ip]
         lib.oracle_node_count.restype = ctypes.c_int64
         lib.oracle_node_count.argtypes = [G]
         lib.oracle_matrix_det.restype = ctypes.c_double
@@ -312,3 +328,157 @@ def cfl_dt(dx: float, v, B, nu: float = 1.0, degree: int = 2) -> float:
     v, B = _d(v), _d(B)
     f = _load().oracle_cfl_dt_lagged if degree == 1 else _load().oracle_cfl_dt
     return f(v.shape[1], float(dx), float(nu), v.shape[0], _ptr(v), _ptr(B))
+
+
+# ---------------------------------------------------------------------------
+# Implicit midpoint (Sec. 3.3 at lambda = 1/2; Sec. 4.1, 4.2)
+# ---------------------------------------------------------------------------
+
+def neo_hookean_dP(F, mu: float, lam: float, dF) -> np.ndarray:
+    """dP/dF : dF of the neo-Hookean stress (the product in the force
+    derivative of Sec. 3.3)."""
+    F, dF = _d(F), _d(dF)
+    out = np.zeros_like(F)
+    _check(_load().oracle_neo_hookean_dP(F.shape[0], _ptr(F), float(mu), float(lam), _ptr(dF), _ptr(out)))
+    return out
+
+
+def forces_at(grid: Grid, x, F, V, mu: float, lam: float, u):
+    """Grid forces f_i = -dPhi/dx_i and Phi = sum_p V_p Psi(F_hat_p) with
+    node i moved by u_i (Sec. 3.3).  Returns (f (nodes, d), Phi)."""
+    x, F, V, u = _d(x), _d(F), _d(V), _d(u)
+    f = np.zeros((grid.node_count, grid.dim))
+    phi = ctypes.c_double(0.0)
+    _check(_load().oracle_forces_at(grid.ref(), x.shape[0], _ptr(x), _ptr(F), _ptr(V), float(mu), float(lam),
+                                    _ptr(u), _ptr(f), ctypes.byref(phi)))
+    return f, phi.value
+
+
+def force_differential(grid: Grid, x, F, V, mu: float, lam: float, u, du) -> np.ndarray:
+    """sum_j (df_i/dx_j) du_j at the state displaced by u (Sec. 3.3, the force
+    derivative and its helper)."""
+    x, F, V, u, du = _d(x), _d(F), _d(V), _d(u), _d(du)
+    df = np.zeros((grid.node_count, grid.dim))
+    _check(_load().oracle_force_differential(grid.ref(), x.shape[0], _ptr(x), _ptr(F), _ptr(V), float(mu),
+                                             float(lam), _ptr(u), _ptr(du), _ptr(df)))
+    return df
+
+
+def band_mask(grid: Grid, band) -> np.ndarray:
+    """Nodes in the sticky band, by the rule of ``grid_update``."""
+    mask = np.zeros(grid.node_count, dtype=bool)
+    if band is None:
+        return mask
+    bd = np.ascontiguousarray(list(band) + [0] * (6 - len(band)), dtype=np.int32)
+    lib = _load()
+    idx = np.zeros(3, dtype=np.int32)
+    for k, pos in enumerate(np.rint(grid.node_positions() / grid.dx).astype(np.int64)):
+        idx[:grid.dim] = pos
+        mask[k] = bool(lib.oracle_node_in_band(grid.ref(), idx.ctypes.data_as(_ip), bd.ctypes.data_as(_ip)))
+    return mask
+
+
+def midpoint_step(grid: Grid, x, v, B, F, m, V, model=1, mu=0.0, lam=0.0, dt=0.0, gravity=None, band=None,
+                  newton_tol=1e-12, max_newton=12, cg_tol=1e-12, max_cg=400):
+    """One implicit midpoint step (lambda = 1/2 of Sec. 3.3), APIC transfers.
+
+    Grid: m_i and v_i = (m v)_i / m_i from the transfer of Sec. 3.2.  The
+    unknown is dv_i = vt_i - v_i (Sec. 4.1), the minimizer of
+        E(dv) = sum_i m_i/8 |dv_i|^2 - dt/4 sum_i m_i g.dv_i + Phi(x_i + u_i),
+        u_i = dt/2 v_i + dt/4 dv_i,
+    whose gradient (m_i/4) r_i with r_i = dv_i - dt (f_i/m_i + g) vanishes
+    exactly at the midpoint equations.  Sticky-band nodes hold v_i = vt_i = 0
+    and, with massless nodes, are not unknowns.
+
+    Newton: each step solves (I - dt^2/4 M^{-1} K) delta = -r with
+    K = df/dx (the operator of Sec. 4.2 that maps velocity-like vectors to
+    velocity-like vectors) by the conjugate gradient of Sec. 4.2 in the mass
+    inner product <a, b> = sum_i m_i a_i.b_i, starting from delta = 0 and
+    stopping at <r, r> <= cg_tol^2 <b, b> or at non-positive curvature (then
+    the iterate so far, or b itself on the first iteration); then a
+    backtracking line search (halving from 1, at most 30 times, until E does
+    not increase or |r|_M decreases: near the minimum E is flat to within its
+    rounding while the gradient still falls).  Newton stops when
+    |r|_M <= newton_tol |r_0|_M.
+
+    Then vt_i = v_i + dv_i, xt_i = x_i + dt (v_i + vt_i)/2 and the transfer to
+    particles of Sec. 3.4 in its general form.  Returns the new particle
+    state and solver statistics."""
+    d = grid.dim
+    x, v, B, F, m, V = (_d(a) for a in (x, v, B, F, m, V))
+    g = p2g(grid, x, v, B, F, m, V, 0)
+    gm = g["m"]
+    sticky = band_mask(grid, band)
+    free = (gm > 0) & ~sticky
+    mf = np.where(free, gm, 0.0)
+    gv = np.zeros((grid.node_count, d))
+    gv[free] = g["mv"][free] / gm[free, None]
+    grav = np.zeros(d) if gravity is None else np.asarray(gravity, dtype=np.float64)[:d]
+    Vp = V if model == 1 else V * 0.0
+
+    def dot_m(a, b):
+        return float(np.sum(mf[:, None] * a * b))
+
+    def residual_energy(dv):
+        u = 0.5 * dt * gv + 0.25 * dt * dv
+        f, phi = forces_at(grid, x, F, Vp, mu, lam, u)
+        r = np.zeros_like(dv)
+        r[free] = dv[free] - dt * (f[free] / gm[free, None] + grav)
+        E = float(np.sum(mf[:, None] * (0.125 * dv * dv - 0.25 * dt * grav * dv))) + phi
+        return r, E
+
+    def apply_A(dv, p):
+        u = 0.5 * dt * gv + 0.25 * dt * dv
+        df = force_differential(grid, x, F, Vp, mu, lam, u, p)
+        s = np.zeros_like(p)
+        s[free] = p[free] - 0.25 * dt * dt * df[free] / gm[free, None]
+        return s
+
+    dv = np.zeros((grid.node_count, d))
+    stats = {"newton": 0, "cg": 0, "halvings": 0, "res0": 0.0, "res": 0.0}
+    r, E = residual_energy(dv)
+    res0 = np.sqrt(dot_m(r, r))
+    stats["res0"] = res0
+    for it in range(max_newton):
+        if res0 == 0.0 or np.sqrt(dot_m(r, r)) <= newton_tol * res0:
+            break
+        # conjugate gradient on A delta = b, mass inner product (Sec. 4.2)
+        b = -r
+        delta = np.zeros_like(b)
+        rc = b.copy()
+        p = rc.copy()
+        gamma = dot_m(rc, rc)
+        gamma0 = gamma
+        for k in range(max_cg):
+            if gamma <= cg_tol * cg_tol * gamma0:
+                break
+            s = apply_A(dv, p)
+            ps = dot_m(p, s)
+            stats["cg"] += 1
+            if ps <= 0.0:
+                if k == 0:
+                    delta = b.copy()
+                break
+            alpha = gamma / ps
+            delta = delta + alpha * p
+            rc = rc - alpha * s
+            kappa = dot_m(rc, rc)
+            p = rc + (kappa / gamma) * p
+            gamma = kappa
+        # backtracking line search on E
+        step = 1.0
+        for k in range(30):
+            r_new, E_new = residual_energy(dv + step * delta)
+            if E_new <= E or np.sqrt(dot_m(r_new, r_new)) < np.sqrt(dot_m(r, r)) or k == 29:
+                break
+            step *= 0.5
+            stats["halvings"] += 1
+        dv = dv + step * delta
+        r, E = r_new, E_new
+        stats["newton"] = it + 1
+    stats["res"] = float(np.sqrt(dot_m(r, r)))
+    gvt = np.where(free[:, None], gv + dv, 0.0)
+    gxt = grid.node_positions() + dt * 0.5 * (gv + gvt)
+    out = g2p(grid, x, F, gvt, gxt)
+    return {"m": gm, "v": gv, "vt": gvt, "xt": gxt, "x_new": out["x"], "v_new": out["v"], "B_new": out["B"],
+            "F_new": out["F"], "stats": stats}

@@ -751,6 +751,129 @@ int oracle_step(const oracle_grid *g, int64_t np, const double *x, const double 
     return oracle_g2p(g, np, x, F, gvt, gxt, transfer, x_out, v_out, B_out, F_out);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Implicit midpoint pieces (Sec. 3.3 at lambda = 1/2, Sec. 4.1).            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Differential of the neo-Hookean first Piola-Kirchhoff stress,
+ * dP = dP/dF : dF, the product the force derivative of Sec. 3.3 needs:
+ * from P = mu (F - F^{-T}) + lam ln J F^{-T}, d(F^{-T}) = -F^{-T} dF^T F^{-T}
+ * and d(ln J) = tr(F^{-1} dF),
+ *   dP = mu dF + (mu - lam ln J) F^{-T} dF^T F^{-T} + lam tr(F^{-1} dF) F^{-T}.
+ */
+int oracle_neo_hookean_dP(int d, const double *F, double mu, double lam, const double *dF, double *dP)
+{
+    double Finv[9], FinvT[9], dFT[9], T1[9], T2[9], J;
+    int rc = mat_inverse(d, F, Finv, &J);
+    if (rc != OR_OK) return rc;
+    if (!(J > 0.0)) return OR_E_INVERTED;
+    mat_transpose(d, Finv, FinvT);
+    mat_transpose(d, dF, dFT);
+    mat_mul(d, FinvT, dFT, T1);
+    mat_mul(d, T1, FinvT, T2);
+    double tr = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) tr += Finv[a * d + b] * dF[b * d + a];
+    double lnJ = log(J);
+    for (int k = 0; k < d * d; ++k) dP[k] = mu * dF[k] + (mu - lam * lnJ) * T2[k] + lam * tr * FinvT[k];
+    return OR_OK;
+}
+
+/* F_hat = (I + sum_i u_i grad w_ip^T) F_p for a node displacement field u. */
+static void displaced_F(int d, const stencil_entry *st, int cnt, const double *u, const double *Fp, double *Fh)
+{
+    double G[9] = {0};
+    for (int j = 0; j < cnt; ++j)
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) G[r * d + c] += u[st[j].node * d + r] * st[j].gw[c];
+    for (int a = 0; a < d; ++a) G[a * d + a] += 1.0;
+    mat_mul(d, G, Fp, Fh);
+}
+
+/*
+ * Grid forces and potential energy with the nodes moved to x_i + u_i
+ * (Sec. 3.3): F_hat_p as above, Phi = sum_p V_p Psi(F_hat_p) and
+ * f_i = -dPhi/dx_i = -sum_p V_p P(F_hat_p) F_p^T grad w_ip.  f (node-major,
+ * node_count * d) is overwritten.  Returns OR_E_INVERTED when some
+ * det F_hat_p <= 0 (Phi is then +infinity).
+ */
+int oracle_forces_at(const oracle_grid *g, int64_t np, const double *x, const double *F, const double *V,
+                     double mu, double lam, const double *u, double *f, double *phi)
+{
+    const int d = g->dim;
+    stencil_entry st[MAX_STENCIL];
+    for (int64_t i = 0; i < node_count(g) * d; ++i) f[i] = 0.0;
+    *phi = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        int cnt = particle_stencil(g, x + p * d, st);
+        if (cnt < 0) return cnt;
+        const double *Fp = F + p * d * d;
+        double Fh[9], P[9], FT[9], PFT[9], psi;
+        displaced_F(d, st, cnt, u, Fp, Fh);
+        int rc = oracle_neo_hookean_psi(d, Fh, mu, lam, &psi);
+        if (rc == OR_OK) rc = oracle_neo_hookean_P(d, Fh, mu, lam, P);
+        if (rc != OR_OK) {
+            *phi = INFINITY;
+            return rc;
+        }
+        *phi += V[p] * psi;
+        mat_transpose(d, Fp, FT);
+        mat_mul(d, P, FT, PFT);
+        for (int j = 0; j < cnt; ++j)
+            for (int r = 0; r < d; ++r) {
+                double s = 0.0;
+                for (int c = 0; c < d; ++c) s += PFT[r * d + c] * st[j].gw[c];
+                f[st[j].node * d + r] -= V[p] * s;
+            }
+    }
+    return OR_OK;
+}
+
+/*
+ * Product of the force derivative with a node vector du at the displaced
+ * state (Sec. 3.3, force derivative and its helper):
+ *   dF_p = (sum_j du_j grad w_jp^T) F_p,  A_p = dP/dF(F_hat_p) : dF_p,
+ *   df_i = sum_j (df_i/dx_j) du_j = -sum_p V_p A_p F_p^T grad w_ip.
+ * df is overwritten.
+ */
+int oracle_force_differential(const oracle_grid *g, int64_t np, const double *x, const double *F,
+                              const double *V, double mu, double lam, const double *u, const double *du,
+                              double *df)
+{
+    const int d = g->dim;
+    stencil_entry st[MAX_STENCIL];
+    for (int64_t i = 0; i < node_count(g) * d; ++i) df[i] = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        int cnt = particle_stencil(g, x + p * d, st);
+        if (cnt < 0) return cnt;
+        const double *Fp = F + p * d * d;
+        double Fh[9], G[9] = {0}, dF[9], A[9], FT[9], AFT[9];
+        displaced_F(d, st, cnt, u, Fp, Fh);
+        for (int j = 0; j < cnt; ++j)
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c) G[r * d + c] += du[st[j].node * d + r] * st[j].gw[c];
+        mat_mul(d, G, Fp, dF);
+        int rc = oracle_neo_hookean_dP(d, Fh, mu, lam, dF, A);
+        if (rc != OR_OK) return rc;
+        mat_transpose(d, Fp, FT);
+        mat_mul(d, A, FT, AFT);
+        for (int j = 0; j < cnt; ++j)
+            for (int r = 0; r < d; ++r) {
+                double s = 0.0;
+                for (int c = 0; c < d; ++c) s += AFT[r * d + c] * st[j].gw[c];
+                df[st[j].node * d + r] -= V[p] * s;
+            }
+    }
+    return OR_OK;
+}
+
+/* 1 when node idx lies in the sticky band (the rule of oracle_grid_update). */
+int oracle_node_in_band(const oracle_grid *g, const int *idx, const int32_t *band)
+{
+    return node_in_band(g, idx, band);
+}
+
 int64_t oracle_node_count(const oracle_grid *g) { return node_count(g); }
 
 double oracle_matrix_det(int d, const double *A) { return mat_det(d, A); }
