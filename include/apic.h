@@ -352,6 +352,72 @@ const char *apic_last_error(void);
 /* Library version string. */
 const char *apic_version(void);
 
+/*
+ * Implicit midpoint steps (the lambda = 1/2 member of the grid update of
+ * Sec. 3.3, the integrator the paper uses for its examples), binary64 only.
+ *
+ * Each step: the transfer to grid of mass and momentum (Sec. 3.2); grid
+ * velocities v_i = (m v)_i / m_i; then dv_i = vt_i - v_i solves the midpoint
+ * equations m_i dv_i = dt f_i(x_i + dt/2 v_i + dt/4 dv_i) + dt m_i g
+ * (Sec. 4.1), found as the minimizer of
+ *   E(dv) = sum_i m_i/8 |dv_i|^2 - dt/4 sum_i m_i g.dv_i + Phi(x_i + dt/2 v_i + dt/4 dv_i)
+ * by Newton's method: each Newton step solves
+ *   (I - dt^2/4 M^{-1} df/dx) delta = -r,  r_i = dv_i - dt (f_i / m_i + g),
+ * with the conjugate gradient of Sec. 4.2 in the mass inner product
+ * <a, b> = sum_i m_i a_i.b_i (the operator is symmetric in it and keeps every
+ * vector velocity-like), stopping at |r_cg|_M <= cg_tol |r_cg,0|_M or at
+ * non-positive curvature (then the iterate so far; -r on the first
+ * iteration), and is followed by a backtracking line search (halving from
+ * 1, at most 30 times, until E does not increase or |r|_M decreases: near the
+ * minimum E is flat to within its rounding).  Newton stops when
+ * |r|_M <= newton_tol |r_0|_M.  Then vt_i = v_i + dv_i,
+ * xt_i = x_i + dt (v_i + vt_i)/2, and the transfer to particles of Sec. 3.4
+ * in its general form updates x, v, B, F (APIC transfer).
+ *
+ * Nodes without mass and nodes in the sticky band are not unknowns: they
+ * keep v_i = vt_i = 0 (a sticky node does not move during the step).  The
+ * force is that of the neo-Hookean model (APIC_MODEL_NEO_HOOKEAN) at
+ * F_hat_p = (I + sum_i u_i grad w_ip^T) F_p, u_i = xt_i/2 - x_i/2 (its
+ * derivative products use dP/dF of that model); APIC_MODEL_NONE has no force
+ * (dv_i = dt g exactly).
+ *
+ * Precision APIC_F64, degree 2 or 3, transfer APIC, no APIC_OPT_ADAPTIVE_DT:
+ * else APIC_E_UNSUPPORTED.  Particles need not be sorted and keep their
+ * order.  The scene's workspace must hold apic_midpoint_workspace_bytes
+ * (dense node arrays: about (2 + 9 dim) doubles per node); the step uses it
+ * as scratch, so the explicit entry points see a fresh workspace afterwards
+ * (their binning and grid are rebuilt on their next call).  Synchronizes the
+ * stream once per conjugate-gradient iteration (its inner products are read
+ * back).  Particles whose support leaves the grid are skipped and set
+ * APIC_FLAG_OUT_OF_DOMAIN in stats->flags; an element with det F_hat <= 0
+ * sets APIC_FLAG_INVERTED and makes E infinite (the line search backs off).
+ */
+typedef struct {
+    double newton_tol;   /* relative Newton tolerance, 0 = default 1e-10      */
+    double cg_tol;       /* relative CG tolerance, 0 = default 1e-8            */
+    int32_t max_newton;  /* Newton iterations per step, 0 = default 20         */
+    int32_t max_cg;      /* CG iterations per Newton step, 0 = default 500     */
+} apic_midpoint_opts;
+
+typedef struct {
+    int32_t newton_iters;   /* summed over the steps of the call             */
+    int32_t cg_iters;       /* summed over the steps of the call             */
+    int32_t halvings;       /* line-search halvings, summed                  */
+    int32_t converged;      /* 1 when every step met newton_tol              */
+    uint32_t flags;         /* APIC_FLAG_* raised during the call            */
+    int32_t reserved;
+    double res0;            /* |r|_M at dv = 0, last step                     */
+    double res;             /* |r|_M at the end, last step                    */
+} apic_midpoint_stats;
+
+/* Workspace bytes apic_step_midpoint needs for a grid and particle count. */
+apic_status apic_midpoint_workspace_bytes(const apic_grid_desc *grid, int64_t max_particles, size_t *bytes);
+
+/* n_steps implicit midpoint steps of dt = prm.dt.  opts may be NULL
+ * (defaults); stats receives the solver counts (required). */
+apic_status apic_step_midpoint(apic_scene *scene, int32_t n_steps, const apic_midpoint_opts *opts,
+                               apic_midpoint_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

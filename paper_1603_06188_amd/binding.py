@@ -44,7 +44,7 @@ EXPORTED = [
     "apic_batch_workspace_bytes", "apic_step_batch", "apic_grid_export", "apic_diagnostics", "apic_cfl_dt", "apic_step_time",
     "apic_get_flags", "apic_clear_flags",
     "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
-    "apic_last_error", "apic_version",
+    "apic_last_error", "apic_version", "apic_midpoint_workspace_bytes", "apic_step_midpoint",
 ]
 APIC_PHASES = ["p2g", "grid_update", "bin", "g2p", "sort"]
 
@@ -71,6 +71,17 @@ class ApicScene(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
+class ApicMidpointOpts(ctypes.Structure):
+    _fields_ = [("newton_tol", ctypes.c_double), ("cg_tol", ctypes.c_double), ("max_newton", ctypes.c_int32),
+                ("max_cg", ctypes.c_int32)]
+
+
+class ApicMidpointStats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("halvings", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("res0", ctypes.c_double), ("res", ctypes.c_double)]
+
+
 _S = ctypes.POINTER(ApicScene)
 _V = ctypes.c_void_p
 _sigs = {
@@ -91,6 +102,8 @@ _sigs = {
     "apic_clear_flags": [_S, _V],
     "apic_positions_from_absolute": [_S, _V, _V],
     "apic_positions_to_absolute": [_S, _V, _V],
+    "apic_midpoint_workspace_bytes": [ctypes.POINTER(ApicGridDesc), ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+    "apic_step_midpoint": [_S, ctypes.c_int32, ctypes.POINTER(ApicMidpointOpts), ctypes.POINTER(ApicMidpointStats), _V],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -129,6 +142,22 @@ def apic_workspace_bytes(grid: ApicGridDesc, max_particles: int) -> int:
     out = ctypes.c_size_t()
     _check(_lib.apic_workspace_bytes(ctypes.byref(grid), int(max_particles), ctypes.byref(out)))
     return out.value
+
+
+def apic_midpoint_workspace_bytes(grid: ApicGridDesc, max_particles: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.apic_midpoint_workspace_bytes(ctypes.byref(grid), int(max_particles), ctypes.byref(out)))
+    return out.value
+
+
+def apic_step_midpoint(scene: ApicScene, n_steps: int = 1, newton_tol: float = 0.0, cg_tol: float = 0.0,
+                       max_newton: int = 0, max_cg: int = 0, stream=None) -> dict:
+    """Implicit midpoint steps; returns the solver statistics."""
+    o = ApicMidpointOpts(float(newton_tol), float(cg_tol), int(max_newton), int(max_cg))
+    st = ApicMidpointStats()
+    _check(_lib.apic_step_midpoint(ctypes.byref(scene), int(n_steps), ctypes.byref(o), ctypes.byref(st),
+                                   _stream(stream)))
+    return {k: getattr(st, k) for k, _ in ApicMidpointStats._fields_ if k != "reserved"}
 
 
 def apic_reset(scene: ApicScene, stream=None) -> None:
@@ -284,7 +313,7 @@ class DeviceScene:
     off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
 
     def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True,
-                 packed=None, fused=False, adaptive=False):
+                 packed=None, fused=False, adaptive=False, midpoint=False):
         self.host = scene
         self.dim = scene.dim
         self.precision = precision or scene.precision
@@ -300,6 +329,8 @@ class DeviceScene:
         self.upload(scene, packed)
         g = grid_desc(scene, self.precision, compensated, fused, adaptive)
         self.wbytes = apic_workspace_bytes(g, cap)
+        if midpoint:
+            self.wbytes = max(self.wbytes, apic_midpoint_workspace_bytes(g, cap))
         self.ws = torch.empty(self.wbytes + 256, dtype=torch.uint8, device=device)
         s = ApicScene()
         s.grid = g
@@ -375,6 +406,10 @@ class DeviceScene:
 
     def step(self, n_steps=1, sort_every=0):
         apic_step([self.s], n_steps, sort_every)
+
+    def step_midpoint(self, n_steps=1, **opts):
+        """Implicit midpoint steps (needs ``midpoint=True``); solver stats."""
+        return apic_step_midpoint(self.s, n_steps, **opts)
 
     # --- observation (copies to host) ---------------------------------------
     @property

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libapic.so")
-SOURCES = ["apic_api.hip", "k_bin.hip", "k_p2g.hip", "k_grid.hip", "k_g2p.hip", "k_g2p2g.hip", "k_misc.hip"]
+SOURCES = ["apic_api.hip", "k_bin.hip", "k_p2g.hip", "k_grid.hip", "k_g2p.hip", "k_g2p2g.hip", "k_misc.hip", "k_midpoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -183,7 +183,8 @@ apic_status check_grid(const apic_grid_desc *g) {
     return APIC_OK;
 }
 
-apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
+// Grid, particle planes and parameters (not the workspace).
+apic_status check_fields(const apic_scene *s) {
     if (!s) return fail(APIC_E_INVAL, "scene is NULL");
     apic_status rc = check_grid(&s->grid);
     if (rc != APIC_OK) return rc;
@@ -217,6 +218,13 @@ apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
         return fail(APIC_E_UNSUPPORTED, "the multilinear kernel carries the lagged C of APIC only");
     if ((s->grid.options & APIC_OPT_ADAPTIVE_DT) && !(q.cfl > 0.0 && q.cfl <= 1.0))
         return fail(APIC_E_INVAL, "adaptive steps need a CFL number 0 < cfl <= 1");
+    return APIC_OK;
+}
+
+apic_status check_scene(const apic_scene *s, int64_t *cap_out) {
+    apic_status rc = check_fields(s);
+    if (rc != APIC_OK) return rc;
+    const apic_particles &p = s->p;
     if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)s->workspace) % kAlign) return fail(APIC_E_WORKSPACE, "workspace must be 256-byte aligned");
     const int64_t cap = capacity_for(&s->grid, s->workspace_bytes);
@@ -1125,5 +1133,237 @@ apic_status apic_timing_read(int64_t *counts, double *mean_ms) {
 const char *apic_last_error(void) { return g_last_error.c_str(); }
 
 const char *apic_version(void) { return "libapic 0.2 (gfx950)"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Implicit midpoint step (Sec. 3.3 at lambda = 1/2; Sec. 4.1, 4.2)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct MidLayout {
+    size_t gm, mf, gv, dv, dvt, f, r, rc, pv, s, delta, part, out, flags, total;
+    int64_t nodes, nblk;
+};
+
+MidLayout mid_layout(const apic_grid_desc &g, int64_t n) {
+    MidLayout L{};
+    int64_t nodes = 1;
+    for (int a = 0; a < g.dim; ++a) nodes *= (int64_t)g.cells[a] + 1;
+    L.nodes = nodes;
+    L.nblk = std::max(mid_particle_blocks(std::max<int64_t>(n, 1)), mid_node_blocks(nodes));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(o + bytes);
+        return o;
+    };
+    const size_t vb = (size_t)nodes * g.dim * sizeof(double);
+    L.gm = take((size_t)nodes * sizeof(double));
+    L.mf = take((size_t)nodes * sizeof(double));
+    L.gv = take(vb);
+    L.dv = take(vb);
+    L.dvt = take(vb);
+    L.f = take(vb);
+    L.r = take(vb);
+    L.rc = take(vb);
+    L.pv = take(vb);
+    L.s = take(vb);
+    L.delta = take(vb);
+    L.part = take((size_t)L.nblk * 2 * sizeof(double));
+    L.out = take(4 * sizeof(double));
+    L.flags = take(sizeof(uint32_t));
+    L.total = off;
+    return L;
+}
+
+struct MidOpts {
+    double newton_tol, cg_tol;
+    int max_newton, max_cg;
+};
+
+template <int DIM, int DEG>
+apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpoint_stats *stats, hipStream_t st) {
+    const MidLayout L = mid_layout(s->grid, s->p.n);
+    char *ws = (char *)s->workspace;
+    double *gm = (double *)(ws + L.gm), *mf = (double *)(ws + L.mf), *gv = (double *)(ws + L.gv);
+    double *dv = (double *)(ws + L.dv), *dvt = (double *)(ws + L.dvt), *f = (double *)(ws + L.f);
+    double *r = (double *)(ws + L.r), *rc = (double *)(ws + L.rc), *pv = (double *)(ws + L.pv);
+    double *sv = (double *)(ws + L.s), *delta = (double *)(ws + L.delta), *part = (double *)(ws + L.part);
+    double *out = (double *)(ws + L.out);
+    uint32_t *flags = (uint32_t *)(ws + L.flags);
+
+    MidGrid g{};
+    for (int a = 0; a < 3; ++a) g.N[a] = a < DIM ? s->grid.cells[a] + 1 : 1;
+    for (int k = 0; k < 6; ++k) g.band[k] = s->prm.band[k];
+    g.nodes = L.nodes;
+    g.dx = s->grid.dx;
+    const MidMaterial mat{s->prm.mu, s->prm.lambda, s->prm.rho0};
+    Parts<double> P{};
+    P.cell = s->p.cell;
+    P.off = (double *)s->p.off;
+    P.v = (double *)s->p.v;
+    P.B = (double *)s->p.B;
+    P.F = (double *)s->p.F;
+    P.m = (double *)s->p.mass;
+    P.id = s->p.id;
+    P.n = s->p.n;
+    P.s = s->p.stride;
+    const double dt = s->prm.dt;
+    const double *grav = s->prm.gravity;
+    const bool elastic = s->prm.model == APIC_MODEL_NEO_HOOKEAN && P.n > 0;
+    const int64_t nv = L.nodes * DIM;
+    const int64_t pb = mid_particle_blocks(std::max<int64_t>(P.n, 1)), nb = mid_node_blocks(L.nodes);
+    double host[4] = {0, 0, 0, 0};
+    apic_status rc0 = APIC_OK;
+    // final reduction of K block partials, read back (synchronizes)
+    auto read = [&](int64_t nblk, int K) {
+        if (rc0 != APIC_OK) return;
+        launch_mid_reduce(part, nblk, K, out, st);
+        rc0 = hip_check(hipMemcpyAsync(host, out, K * sizeof(double), hipMemcpyDeviceToHost, st), "apic_step_midpoint");
+        if (rc0 == APIC_OK) rc0 = hip_check(hipStreamSynchronize(st), "apic_step_midpoint");
+    };
+    // E(dv) and |r|_M with r written to `r` (Sec. 4.1)
+    auto eval = [&](const double *dvx, double &E, double &res) {
+        double phi = 0.0;
+        launch_mid_fill(f, nv, 0.0, st);
+        if (elastic) {
+            launch_mid_force<DIM, DEG>(P, g, mat, gv, dvx, dt, f, part, flags, st);
+            read(pb, 1);
+            phi = host[0];
+        }
+        launch_mid_residual<DIM>(g, mf, f, dvx, dt, grav, r, part, st);
+        read(nb, 2);
+        res = sqrt(host[0]);
+        E = host[1] + phi;
+    };
+
+    launch_fill<uint32_t>(flags, 1, 0u, st);
+    *stats = apic_midpoint_stats{};
+    stats->converged = 1;
+    for (int32_t step = 0; step < n_steps && rc0 == APIC_OK; ++step) {
+        launch_mid_fill(gm, L.nodes, 0.0, st);
+        launch_mid_fill(gv, nv, 0.0, st);
+        launch_mid_p2g<DIM, DEG>(P, g, gm, gv, flags, st);
+        launch_mid_nodes<DIM>(g, gm, gv, mf, st);
+        launch_mid_fill(dv, nv, 0.0, st);
+        double E = 0.0, res = 0.0;
+        eval(dv, E, res);
+        const double res0 = res;
+        int it = 0;
+        for (; it < o.max_newton && rc0 == APIC_OK; ++it) {
+            if (res0 == 0.0 || res <= o.newton_tol * res0) break;
+            // conjugate gradient in the mass inner product (Sec. 4.2) on
+            // (I - dt^2/4 M^{-1} df/dx) delta = -r
+            launch_mid_cg_init<DIM>(g, mf, r, delta, rc, pv, part, st);
+            read(nb, 1);
+            double gamma = host[0];
+            const double gamma0 = gamma;
+            for (int k = 0; k < o.max_cg && rc0 == APIC_OK; ++k) {
+                if (gamma <= o.cg_tol * o.cg_tol * gamma0) break;
+                launch_mid_fill(dvt, nv, 0.0, st);  // df/dx p
+                if (elastic) launch_mid_dforce<DIM, DEG>(P, g, mat, gv, dv, dt, pv, dvt, st);
+                launch_mid_apply<DIM>(g, mf, pv, dvt, dt, sv, part, st);
+                read(nb, 1);
+                const double ps = host[0];
+                stats->cg_iters += 1;
+                if (!(ps > 0.0)) {
+                    if (k == 0) launch_mid_axpy(nv, nullptr, -1.0, r, delta, st);
+                    break;
+                }
+                const double alpha = gamma / ps;
+                launch_mid_cg_step<DIM>(g, mf, alpha, pv, sv, delta, rc, part, st);
+                read(nb, 1);
+                const double kappa = host[0];
+                launch_mid_axpy(nv, rc, kappa / gamma, pv, pv, st);
+                gamma = kappa;
+            }
+            // backtracking line search: E must not increase, or |r|_M must
+            // fall (near the minimum E is flat to within its rounding)
+            double stepl = 1.0, En = 0.0, resn = 0.0;
+            for (int k = 0; k < 30 && rc0 == APIC_OK; ++k) {
+                launch_mid_axpy(nv, dv, stepl, delta, dvt, st);
+                eval(dvt, En, resn);
+                if (En <= E || resn < res || k == 29) break;
+                stepl *= 0.5;
+                stats->halvings += 1;
+            }
+            std::swap(dv, dvt);
+            E = En;
+            res = resn;
+        }
+        stats->newton_iters += it;
+        stats->res0 = res0;
+        stats->res = res;
+        if (!(res0 == 0.0 || res <= o.newton_tol * res0)) stats->converged = 0;
+        launch_mid_finish<DIM>(g, mf, gv, dv, dt, rc, sv, st);
+        launch_mid_g2p<DIM, DEG>(P, g, rc, sv, st);
+    }
+    if (rc0 != APIC_OK) return rc0;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(APIC_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    uint32_t fl = 0;
+    rc0 = hip_check(hipMemcpyAsync(&fl, flags, sizeof fl, hipMemcpyDeviceToHost, st), "apic_step_midpoint");
+    if (rc0 == APIC_OK) rc0 = hip_check(hipStreamSynchronize(st), "apic_step_midpoint");
+    stats->flags = fl;
+    return rc0;
+}
+
+}  // namespace
+
+extern "C" {
+
+apic_status apic_midpoint_workspace_bytes(const apic_grid_desc *grid, int64_t max_particles, size_t *bytes) {
+    apic_status rc = check_grid(grid);
+    if (rc != APIC_OK) return rc;
+    if (!bytes) return fail(APIC_E_INVAL, "bytes is NULL");
+    if (max_particles < 0) return fail(APIC_E_INVAL, "max_particles must be >= 0");
+    *bytes = mid_layout(*grid, max_particles).total;
+    return APIC_OK;
+}
+
+apic_status apic_step_midpoint(apic_scene *s, int32_t n_steps, const apic_midpoint_opts *opts,
+                               apic_midpoint_stats *stats, void *stream) {
+    apic_status rc = check_fields(s);
+    if (rc != APIC_OK) return rc;
+    if (!stats) return fail(APIC_E_INVAL, "stats is NULL");
+    if (n_steps < 0) return fail(APIC_E_INVAL, "n_steps must be >= 0");
+    if (s->grid.precision != APIC_F64) return fail(APIC_E_UNSUPPORTED, "the midpoint step runs in binary64 only");
+    if (s->grid.degree != APIC_QUADRATIC && s->grid.degree != APIC_CUBIC)
+        return fail(APIC_E_UNSUPPORTED, "the midpoint step takes quadratic or cubic weights");
+    if (s->prm.transfer != APIC_TRANSFER_APIC)
+        return fail(APIC_E_UNSUPPORTED, "the midpoint step uses the APIC transfers only");
+    if (s->grid.options & APIC_OPT_ADAPTIVE_DT)
+        return fail(APIC_E_UNSUPPORTED, "adaptive steps are not available with the midpoint step");
+    MidOpts o{1e-10, 1e-8, 20, 500};
+    if (opts) {
+        if (!(opts->newton_tol >= 0.0) || !(opts->cg_tol >= 0.0) || !isfinite(opts->newton_tol) ||
+            !isfinite(opts->cg_tol) || opts->max_newton < 0 || opts->max_cg < 0)
+            return fail(APIC_E_INVAL, "midpoint options: tolerances must be finite and >= 0, limits >= 0");
+        if (opts->newton_tol > 0.0) o.newton_tol = opts->newton_tol;
+        if (opts->cg_tol > 0.0) o.cg_tol = opts->cg_tol;
+        if (opts->max_newton > 0) o.max_newton = opts->max_newton;
+        if (opts->max_cg > 0) o.max_cg = opts->max_cg;
+    }
+    if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)s->workspace) % kAlign) return fail(APIC_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t need = mid_layout(s->grid, s->p.n).total;
+    if (s->workspace_bytes < need)
+        return fail(APIC_E_WORKSPACE, "workspace of %zu bytes is below the %zu the midpoint step needs",
+                    s->workspace_bytes, need);
+    {
+        // the workspace no longer holds the explicit path's binning or grid
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_states.erase(s->workspace);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int key = s->grid.dim * 10 + s->grid.degree;
+    switch (key) {
+        case 22: return mid_run<2, 2>(s, n_steps, o, stats, st);
+        case 23: return mid_run<2, 3>(s, n_steps, o, stats, st);
+        case 32: return mid_run<3, 2>(s, n_steps, o, stats, st);
+        default: return mid_run<3, 3>(s, n_steps, o, stats, st);
+    }
+}
 
 }  // extern "C"

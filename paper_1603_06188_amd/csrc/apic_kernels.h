@@ -151,4 +151,50 @@ void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStr
 template <typename T, int DIM>
 void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st);
 
+// --- implicit midpoint (binary64, dense node arrays) ------------------------
+struct MidGrid {
+    int N[3];        // nodes per axis (N[2] = 1 in 2D)
+    int band[6];     // sticky band widths in nodes
+    int64_t nodes;   // node count
+    double dx;
+};
+
+struct MidMaterial {
+    double mu, lambda, rho0;
+};
+
+void launch_mid_fill(double *a, int64_t n, double val, hipStream_t st);
+void launch_mid_reduce(const double *part, int64_t nblk, int K, double *out, hipStream_t st);
+void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, double *out, hipStream_t st);
+int64_t mid_particle_blocks(int64_t n);
+int64_t mid_node_blocks(int64_t nodes);
+template <int DIM, int DEG>
+void launch_mid_p2g(const Parts<double> &P, const MidGrid &g, double *gm, double *gmv, uint32_t *flags,
+                    hipStream_t st);
+template <int DIM>
+void launch_mid_nodes(const MidGrid &g, const double *gm, double *gv, double *mf, hipStream_t st);
+template <int DIM, int DEG>
+void launch_mid_force(const Parts<double> &P, const MidGrid &g, const MidMaterial &mat, const double *gv,
+                      const double *dv, double dt, double *f, double *part, uint32_t *flags, hipStream_t st);
+template <int DIM, int DEG>
+void launch_mid_dforce(const Parts<double> &P, const MidGrid &g, const MidMaterial &mat, const double *gv,
+                       const double *dv, double dt, const double *du, double *df, hipStream_t st);
+template <int DIM>
+void launch_mid_residual(const MidGrid &g, const double *mf, const double *f, const double *dv, double dt,
+                         const double *grav, double *r, double *part, hipStream_t st);
+template <int DIM>
+void launch_mid_cg_init(const MidGrid &g, const double *mf, const double *r, double *delta, double *rc, double *pv,
+                        double *part, hipStream_t st);
+template <int DIM>
+void launch_mid_apply(const MidGrid &g, const double *mf, const double *pv, const double *df, double dt, double *s,
+                      double *part, hipStream_t st);
+template <int DIM>
+void launch_mid_cg_step(const MidGrid &g, const double *mf, double alpha, const double *pv, const double *s,
+                        double *delta, double *rc, double *part, hipStream_t st);
+template <int DIM>
+void launch_mid_finish(const MidGrid &g, const double *mf, const double *gv, const double *dv, double dt, double *gvt,
+                       double *gu, hipStream_t st);
+template <int DIM, int DEG>
+void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt, const double *gu, hipStream_t st);
+
 }  // namespace apic

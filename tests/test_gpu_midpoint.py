@@ -1,0 +1,153 @@
+"""Implicit midpoint steps (apic_step_midpoint: lambda = 1/2 of Sec. 3.3,
+solved as in Sec. 4.1 and 4.2) on the GPU against the FP64 oracle.  Both
+sides run Newton with the mass-inner-product conjugate gradient to a
+relative residual of 1e-12, so each holds the solution of the midpoint
+equations to that level; the state bar is the binary64 one (1e-12 per field
+per step)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_06188_amd import scenes
+from tests.test_gpu_parity import ogrid, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+SOLVER = dict(newton_tol=1e-12, cg_tol=1e-12)
+
+
+def _b():
+    from paper_1603_06188_amd import binding
+    return binding
+
+
+def _scene(dim, degree, n, seed, **kw):
+    args = dict(precision="fp64", vel_sigma=0.5, f_sigma=0.05, b_sigma=0.05, model=1)
+    args.update(kw)
+    return scenes.random_particles(n, dim=dim, cells=16, degree=degree, seed=seed, **args)
+
+
+def _oracle_chain(s, steps, dt=None, gravity="scene", band="scene"):
+    g = ogrid(s)
+    x, v, B, F = s.x, s.v, s.B, s.F
+    grav = s.gravity if gravity == "scene" else gravity
+    bd = s.band if band == "scene" else band
+    stats = []
+    for _ in range(steps):
+        r = oracle.midpoint_step(g, x, v, B, F, s.m, s.V, s.model, s.mu, s.lam, s.dt if dt is None else dt, grav, bd,
+                                 newton_tol=SOLVER["newton_tol"], cg_tol=SOLVER["cg_tol"], max_newton=20)
+        x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
+        stats.append(r["stats"])
+    return x, v, B, F, stats
+
+
+def _compare(got, x, v, B, F, dx, tol, label):
+    errs = {"x": float(np.abs(got["x"] - x).max() / dx), "v": rel(got["v"], v), "B": rel(got["B"], B),
+            "F": rel(got["F"], F)}
+    print(label, errs, flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+
+
+@pytest.mark.parametrize("dim,degree", [(3, 2), (3, 3), (2, 2), (2, 3)])
+def test_one_step_matches_oracle(dim, degree):
+    s = _scene(dim, degree, 3000 if dim == 3 else 2000, seed=81)
+    ds = _b().DeviceScene(s, midpoint=True)
+    st = ds.step_midpoint(1, **SOLVER)
+    x, v, B, F, ost = _oracle_chain(s, 1)
+    print(st, ost, flush=True)
+    assert st["converged"] == 1 and st["flags"] == 0
+    assert st["newton_iters"] >= 2
+    _compare(ds.state(), x, v, B, F, s.dx, TOL, f"midpoint {dim}d deg{degree}")
+
+
+@pytest.mark.parametrize("dim,degree", [(3, 2), (2, 3)])
+def test_steps_in_one_call_match_chained_oracle(dim, degree):
+    """Four steps in one call at four times the scene's dt, against four
+    chained oracle steps (per-step bar times the step count)."""
+    s = _scene(dim, degree, 2500 if dim == 3 else 1500, seed=82, vel_sigma=1.0)
+    s = dataclasses.replace(s, dt=4 * s.dt)
+    ds = _b().DeviceScene(s, midpoint=True)
+    st = ds.step_midpoint(4, **SOLVER)
+    x, v, B, F, _ = _oracle_chain(s, 4)
+    assert st["converged"] == 1 and st["flags"] == 0
+    _compare(ds.state(), x, v, B, F, s.dx, 4 * TOL, f"midpoint chain {dim}d deg{degree}")
+
+
+def test_sticky_band_and_gravity_match_oracle():
+    s = scenes.random_particles(3000, dim=3, cells=12, degree=2, seed=83, precision="fp64", margin=1.0,
+                                vel_sigma=1.0, f_sigma=0.05, b_sigma=0.05, model=1)
+    s = dataclasses.replace(s, band=[2, 2, 2, 2, 2, 2], gravity=[0.0, -9.8, 0.0])
+    ds = _b().DeviceScene(s, midpoint=True)
+    st = ds.step_midpoint(2, **SOLVER)
+    x, v, B, F, _ = _oracle_chain(s, 2)
+    assert st["converged"] == 1 and st["flags"] == 0
+    _compare(ds.state(), x, v, B, F, s.dx, 2 * TOL, "midpoint band + gravity")
+
+
+def test_constant_acceleration_is_exact():
+    """Model without force, uniform v, B = 0: x' = x + dt v + dt^2 g / 2 and
+    v' = v + dt g, the midpoint rule on a constant force."""
+    s = scenes.random_particles(2000, dim=3, cells=12, degree=3, seed=84, precision="fp64", vel_sigma=0.0,
+                                b_sigma=0.0, f_sigma=0.0, model=0)
+    v0, gvec, dt = np.array([0.3, -0.2, 0.1]), [0.5, -9.8, 1.5], 0.01
+    s = dataclasses.replace(s.with_state(v=np.tile(v0, (s.n, 1)), B=np.zeros_like(s.B)), dt=dt, gravity=gvec)
+    ds = _b().DeviceScene(s, midpoint=True)
+    st = ds.step_midpoint(1)
+    got = ds.state()
+    assert st["converged"] == 1
+    np.testing.assert_allclose(got["x"], s.x + dt * v0 + 0.5 * dt * dt * np.array(gvec), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(got["v"], np.tile(v0 + dt * np.array(gvec), (s.n, 1)), rtol=0, atol=1e-13)
+    assert np.abs(got["B"]).max() <= 1e-14
+
+
+def test_momentum_is_conserved_on_the_device():
+    """No gravity or walls: particle p and l (B term included) after three
+    steps equal their initial values to rounding (Sec. 3.3, Sec. 5)."""
+    b = _b()
+    s = _scene(3, 2, 4000, seed=85, vel_sigma=1.0)
+    s = dataclasses.replace(s, dt=4 * s.dt, gravity=[0.0, 0.0, 0.0])
+    ds = b.DeviceScene(s, midpoint=True)
+    t0 = oracle.particle_totals(s.x, s.v, s.B, s.m)
+    st = ds.step_midpoint(3, **SOLVER)
+    t1 = ds.diagnostics(b.APIC_DIAG_PARTICLES)
+    assert st["converged"] == 1
+    S = float(np.sum(s.m * (np.linalg.norm(s.x, axis=1) + 1.0) * np.linalg.norm(s.v, axis=1)))
+    assert np.abs(t1[:6] - t0[:6]).max() <= 1e-12 * S, (t1[:6], t0[:6])
+
+
+def test_explicit_steps_after_a_midpoint_step():
+    """The midpoint step uses the workspace as scratch: explicit steps after
+    it rebuild their binning and match the oracle from the midpoint state."""
+    b = _b()
+    s = _scene(3, 2, 3000, seed=86)
+    ds = b.DeviceScene(s, midpoint=True)
+    ds.step(1)
+    ds.step_midpoint(1, **SOLVER)
+    mid = ds.state()
+    ds.step(1)
+    got = ds.state()
+    assert ds.flags() == 0
+    g = ogrid(s)
+    r = oracle.step(g, mid["x"], mid["v"], mid["B"], mid["F"], s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity,
+                    s.band)
+    _compare(got, r["x_new"], r["v_new"], r["B_new"], r["F_new"], s.dx, TOL, "explicit after midpoint")
+
+
+def test_empty_scene_and_zero_steps():
+    b = _b()
+    s = _scene(3, 2, 1000, seed=87)
+    ds = b.DeviceScene(s, midpoint=True)
+    before = ds.state()
+    st = ds.step_midpoint(0)
+    assert st["newton_iters"] == 0 and st["cg_iters"] == 0
+    after = ds.state()
+    for k in ("x", "v", "B", "F"):
+        np.testing.assert_array_equal(after[k], before[k])
+    e = scenes.random_particles(0, dim=3, cells=8, degree=3, seed=1, precision="fp64", model=1)
+    de = b.DeviceScene(e, midpoint=True)
+    st = de.step_midpoint(2)
+    assert st["converged"] == 1 and st["flags"] == 0
