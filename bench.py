@@ -173,6 +173,49 @@ def spheres(steps: int):
     return out
 
 
+def midpoint(steps: int, cells: int = 128):
+    """Implicit midpoint steps (apic_step_midpoint, binary64) on the elastic
+    cube at two step sizes, with the explicit binary64 step beside it:
+    particle-updates/s and simulated time per wall second."""
+    import dataclasses
+
+    import torch
+
+    from paper_1603_06188_amd import binding as b
+    from paper_1603_06188_amd import scenes
+
+    base = scenes.cube3d(cells=cells, precision="fp64")
+    out = {"particles": base.n}
+    ds = b.DeviceScene(base, with_id=False)
+    ds.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ds.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["explicit_dt1e-4"] = {"value": base.n * steps / el, "ms_per_step": el / steps * 1e3,
+                              "sim_time_per_s": base.dt * steps / el, "flags": ds.flags()}
+    del ds
+    torch.cuda.empty_cache()
+    for dt in (1e-3, 5e-3):
+        s = dataclasses.replace(base, dt=dt)
+        ds = b.DeviceScene(s, with_id=False, midpoint=True)
+        ds.step_midpoint(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ds.step_midpoint(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"midpoint_dt{dt:g}"] = {"value": s.n * steps / el, "ms_per_step": el / steps * 1e3,
+                                     "sim_time_per_s": dt * steps / el, "newton_per_step": st["newton_iters"] / steps,
+                                     "cg_per_step": st["cg_iters"] / steps, "halvings": st["halvings"],
+                                     "converged": st["converged"], "flags": st["flags"]}
+        print(f"midpoint dt={dt:g}: {out[f'midpoint_dt{dt:g}']}", file=sys.stderr, flush=True)
+        del ds
+        torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,9 +227,10 @@ def main(argv=None):
     ap.add_argument("--fused", action="store_true",
                     help="APIC_OPT_FUSED_TRANSFER: G2P fused with the next step's P2G")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["cube", "batch", "spheres"], default="cube",
+    ap.add_argument("--workload", choices=["cube", "batch", "spheres", "midpoint"], default="cube",
                     help="cube: the 128^3 elastic cube (headline); batch: 512 bodies, batched vs per-scene loop; "
-                         "spheres: two spheres on 256^3 cells, cubic, three precision modes")
+                         "spheres: two spheres on 256^3 cells, cubic, three precision modes; midpoint: implicit "
+                         "midpoint steps on the cube in binary64")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency replay")
     ap.add_argument("--headline-only", action="store_true",
                     help="cube: skip the adaptive-step and multilinear legs (profiling runs)")
@@ -234,6 +278,20 @@ def main(argv=None):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "two spheres r=0.2 at 8 ppc, 256^3 cells, cubic B-spline, neo-Hookean, g=0, "
                                    "dt=1e-4", "particles": main_mode["particles"]},
+            "modes": res}), flush=True)
+        return 0
+    if args.workload == "midpoint":
+        nsteps = args.steps if args.steps != 100 else 3
+        res = midpoint(nsteps, args.cells)
+        main_mode = res["midpoint_dt0.005"]
+        print(json.dumps({
+            "metric": "implicit midpoint APIC particle-updates/s, elastic cube 128^3 (2,097,152 particles)",
+            "value": main_mode["value"], "unit": "particle-updates/s", "n_gpus": 1, "steps": nsteps, "warmup": 1,
+            "ms_per_step": main_mode["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "elastic cube 128^3, quadratic, neo-Hookean, gravity, sticky floor, implicit "
+                                   "midpoint (Newton + mass-inner-product CG), dt=5e-3",
+                       "particles": res["particles"]},
             "modes": res}), flush=True)
         return 0
     if args.calibrate_copy:

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <unordered_map>
 #include <type_traits>
@@ -1198,6 +1199,13 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     for (int k = 0; k < 6; ++k) g.band[k] = s->prm.band[k];
     g.nodes = L.nodes;
     g.dx = s->grid.dx;
+    // an odd stride near 0.618 n that is coprime to n
+    g.pstride = 1;
+    if (s->p.n > 2) {
+        int64_t k = (int64_t)(0.6180339887498949 * (double)s->p.n) | 1;
+        while (std::gcd(k, (int64_t)s->p.n) != 1) k += 2;
+        g.pstride = k % s->p.n;
+    }
     const MidMaterial mat{s->prm.mu, s->prm.lambda, s->prm.rho0};
     Parts<double> P{};
     P.cell = s->p.cell;

@@ -157,6 +157,7 @@ struct MidGrid {
     int band[6];     // sticky band widths in nodes
     int64_t nodes;   // node count
     double dx;
+    int64_t pstride; // scattering kernels: thread t takes particle (t * pstride) mod n
 };
 
 struct MidMaterial {

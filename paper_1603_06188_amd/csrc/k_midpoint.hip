@@ -17,6 +17,12 @@ constexpr int kMidBlock = 256;
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * kMidBlock + threadIdx.x; }
 
+// Particle of thread t in the scattering kernels: (t * pstride) mod n with
+// pstride coprime to n (a bijection).  Particles stored cell by cell put the
+// lanes of a wave on the same few nodes, whose binary64 atomics then
+// serialize; the stride spreads a wave's lanes over the whole body.
+__device__ __forceinline__ int64_t spread(int64_t t, const MidGrid &g, int64_t n) { return (t * g.pstride) % n; }
+
 // Sum of K values over the block; thread 0 writes them to part[blockIdx * K].
 template <int K>
 __device__ __forceinline__ void block_partials(double (&acc)[K], double *part) {
@@ -205,8 +211,9 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_fill(double *a, int64_t n, do
 template <int DIM, int DEG>
 __global__ __launch_bounds__(kMidBlock) void k_mid_p2g(Parts<double> P, MidGrid g, double *gm, double *gmv,
                                                        uint32_t *flags) {
-    const int64_t p = gtid();
-    if (p >= P.n) return;
+    const int64_t t = gtid();
+    if (t >= P.n) return;
+    const int64_t p = spread(t, g, P.n);
     Axis<double, DEG> ax[DIM];
     if (!particle_axes<DIM, DEG>(P, p, g, ax)) {
         atomicOr(flags, (uint32_t)APIC_FLAG_OUT_OF_DOMAIN);
@@ -256,10 +263,11 @@ template <int DIM, int DEG>
 __global__ __launch_bounds__(kMidBlock) void k_mid_force(Parts<double> P, MidGrid g, MidMaterial mat,
                                                          const double *gv, const double *dv, double dt, double *f,
                                                          double *part, uint32_t *flags) {
-    const int64_t p = gtid();
+    const int64_t t = gtid();
+    const int64_t p = t < P.n ? spread(t, g, P.n) : 0;
     double acc[1] = {0.0};
     Axis<double, DEG> ax[DIM];
-    if (p < P.n && particle_axes<DIM, DEG>(P, p, g, ax)) {
+    if (t < P.n && particle_axes<DIM, DEG>(P, p, g, ax)) {
         double F[DIM * DIM], G[DIM * DIM], Fh[DIM * DIM], IT[DIM * DIM];
         load_mat<DIM>(P.F, P.s, p, F);
         gather_grad<DIM, DEG>(ax, g, gv, dv, 0.5 * dt, 0.25 * dt, G);
@@ -294,8 +302,9 @@ template <int DIM, int DEG>
 __global__ __launch_bounds__(kMidBlock) void k_mid_dforce(Parts<double> P, MidGrid g, MidMaterial mat,
                                                           const double *gv, const double *dv, double dt,
                                                           const double *du, double *df) {
-    const int64_t p = gtid();
-    if (p >= P.n) return;
+    const int64_t t = gtid();
+    if (t >= P.n) return;
+    const int64_t p = spread(t, g, P.n);
     Axis<double, DEG> ax[DIM];
     if (!particle_axes<DIM, DEG>(P, p, g, ax)) return;
     double F[DIM * DIM], G[DIM * DIM], H[DIM * DIM], Fh[DIM * DIM], dF[DIM * DIM], IT[DIM * DIM];
