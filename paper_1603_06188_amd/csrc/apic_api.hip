@@ -6,7 +6,6 @@
 #include <string.h>
 
 #include <mutex>
-#include <numeric>
 #include <string>
 #include <unordered_map>
 #include <type_traits>
@@ -1143,7 +1142,8 @@ const char *apic_version(void) { return "libapic 0.2 (gfx950)"; }
 namespace {
 
 struct MidLayout {
-    size_t gm, mf, gv, dv, dvt, f, r, rc, pv, s, delta, part, out, flags, total;
+    size_t gm, mf, gv, dv, dvt, f, r, rc, pv, s, delta, part, out, flags;
+    size_t key, perm, count, cursor, start, bsum, scell, soff, sF, sm, smv, sM, total;
     int64_t nodes, nblk;
 };
 
@@ -1174,6 +1174,20 @@ MidLayout mid_layout(const apic_grid_desc &g, int64_t n) {
     L.part = take((size_t)L.nblk * 2 * sizeof(double));
     L.out = take(4 * sizeof(double));
     L.flags = take(sizeof(uint32_t));
+    // particles sorted by base node
+    const size_t np = (size_t)std::max<int64_t>(n, 1);
+    L.key = take(np * 4);
+    L.perm = take(np * 4);
+    L.count = take((size_t)nodes * 4);
+    L.cursor = take((size_t)nodes * 4);
+    L.start = take((size_t)(nodes + 1) * 4);
+    L.bsum = take((size_t)mid_scan_blocks(nodes) * 4);
+    L.scell = take(np * 4);
+    L.soff = take(np * g.dim * sizeof(double));
+    L.sF = take(np * g.dim * g.dim * sizeof(double));
+    L.sm = take(np * sizeof(double));
+    L.smv = take(np * g.dim * sizeof(double));
+    L.sM = take(np * g.dim * g.dim * sizeof(double));
     L.total = off;
     return L;
 }
@@ -1199,13 +1213,6 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     for (int k = 0; k < 6; ++k) g.band[k] = s->prm.band[k];
     g.nodes = L.nodes;
     g.dx = s->grid.dx;
-    // an odd stride near 0.618 n that is coprime to n
-    g.pstride = 1;
-    if (s->p.n > 2) {
-        int64_t k = (int64_t)(0.6180339887498949 * (double)s->p.n) | 1;
-        while (std::gcd(k, (int64_t)s->p.n) != 1) k += 2;
-        g.pstride = k % s->p.n;
-    }
     const MidMaterial mat{s->prm.mu, s->prm.lambda, s->prm.rho0};
     Parts<double> P{};
     P.cell = s->p.cell;
@@ -1217,6 +1224,21 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     P.id = s->p.id;
     P.n = s->p.n;
     P.s = s->p.stride;
+    const int64_t np = std::max<int64_t>(P.n, 1);
+    MidSorted S{};
+    S.perm = (const uint32_t *)(ws + L.perm);
+    S.start = (const uint32_t *)(ws + L.start);
+    S.cell = (uint32_t *)(ws + L.scell);
+    S.off = (double *)(ws + L.soff);
+    S.F = (double *)(ws + L.sF);
+    S.m = (double *)(ws + L.sm);
+    S.mv = (double *)(ws + L.smv);
+    S.M = (double *)(ws + L.sM);
+    S.n = np;
+    S.nodes = L.nodes;
+    S.dx = s->grid.dx;
+    uint32_t *key = (uint32_t *)(ws + L.key), *count = (uint32_t *)(ws + L.count);
+    uint32_t *cursor = (uint32_t *)(ws + L.cursor), *bsum = (uint32_t *)(ws + L.bsum);
     const double dt = s->prm.dt;
     const double *grav = s->prm.gravity;
     const bool elastic = s->prm.model == APIC_MODEL_NEO_HOOKEAN && P.n > 0;
@@ -1234,11 +1256,13 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     // E(dv) and |r|_M with r written to `r` (Sec. 4.1)
     auto eval = [&](const double *dvx, double &E, double &res) {
         double phi = 0.0;
-        launch_mid_fill(f, nv, 0.0, st);
         if (elastic) {
-            launch_mid_force<DIM, DEG>(P, g, mat, gv, dvx, dt, f, part, flags, st);
+            launch_mid_stress<DIM, DEG, false>(S, g, mat, gv, dvx, dt, nullptr, part, flags, st);
             read(pb, 1);
             phi = host[0];
+            launch_mid_collect_force<DIM, DEG>(S, g, f, st);
+        } else {
+            launch_mid_fill(f, nv, 0.0, st);
         }
         launch_mid_residual<DIM>(g, mf, f, dvx, dt, grav, r, part, st);
         read(nb, 2);
@@ -1250,10 +1274,11 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     *stats = apic_midpoint_stats{};
     stats->converged = 1;
     for (int32_t step = 0; step < n_steps && rc0 == APIC_OK; ++step) {
-        launch_mid_fill(gm, L.nodes, 0.0, st);
-        launch_mid_fill(gv, nv, 0.0, st);
-        launch_mid_p2g<DIM, DEG>(P, g, gm, gv, flags, st);
+        launch_mid_sort<DIM, DEG>(P, g, S, key, count, cursor, bsum, flags, st);
+        launch_mid_collect_p2g<DIM, DEG>(S, g, gm, gv, st);
         launch_mid_nodes<DIM>(g, gm, gv, mf, st);
+        // without a force the differential is zero: its matrices stay 0
+        if (!elastic) launch_mid_fill(S.M, (int64_t)np * DIM * DIM, 0.0, st);
         launch_mid_fill(dv, nv, 0.0, st);
         double E = 0.0, res = 0.0;
         eval(dv, E, res);
@@ -1269,9 +1294,8 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
             const double gamma0 = gamma;
             for (int k = 0; k < o.max_cg && rc0 == APIC_OK; ++k) {
                 if (gamma <= o.cg_tol * o.cg_tol * gamma0) break;
-                launch_mid_fill(dvt, nv, 0.0, st);  // df/dx p
-                if (elastic) launch_mid_dforce<DIM, DEG>(P, g, mat, gv, dv, dt, pv, dvt, st);
-                launch_mid_apply<DIM>(g, mf, pv, dvt, dt, sv, part, st);
+                if (elastic) launch_mid_stress<DIM, DEG, true>(S, g, mat, gv, dv, dt, pv, nullptr, flags, st);
+                launch_mid_collect_apply<DIM, DEG>(S, g, mf, pv, dt, sv, part, st);
                 read(nb, 1);
                 const double ps = host[0];
                 stats->cg_iters += 1;

@@ -157,7 +157,21 @@ struct MidGrid {
     int band[6];     // sticky band widths in nodes
     int64_t nodes;   // node count
     double dx;
-    int64_t pstride; // scattering kernels: thread t takes particle (t * pstride) mod n
+};
+
+// Particles sorted by base node (positions [0, start[nodes]) are filled).
+struct MidSorted {
+    const uint32_t *perm;   // sorted position -> particle
+    const uint32_t *start;  // nodes + 1 entries: first position of each base key
+    uint32_t *cell;         // packed cell, sorted
+    double *off;            // dim planes
+    double *F;              // dim*dim planes
+    double *m;
+    double *mv;             // dim planes: m v
+    double *M;              // dim*dim planes: the per-particle matrix of the current collect
+    int64_t n;              // plane stride (particle count)
+    int64_t nodes;
+    double dx;
 };
 
 struct MidMaterial {
@@ -169,26 +183,28 @@ void launch_mid_reduce(const double *part, int64_t nblk, int K, double *out, hip
 void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, double *out, hipStream_t st);
 int64_t mid_particle_blocks(int64_t n);
 int64_t mid_node_blocks(int64_t nodes);
+int64_t mid_scan_blocks(int64_t nodes);
 template <int DIM, int DEG>
-void launch_mid_p2g(const Parts<double> &P, const MidGrid &g, double *gm, double *gmv, uint32_t *flags,
-                    hipStream_t st);
+void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, uint32_t *key, uint32_t *count,
+                     uint32_t *cursor, uint32_t *bsum, uint32_t *flags, hipStream_t st);
 template <int DIM>
 void launch_mid_nodes(const MidGrid &g, const double *gm, double *gv, double *mf, hipStream_t st);
+template <int DIM, int DEG, bool DIFF>
+void launch_mid_stress(const MidSorted &S, const MidGrid &g, const MidMaterial &mat, const double *gv,
+                       const double *dv, double dt, const double *du, double *part, uint32_t *flags, hipStream_t st);
 template <int DIM, int DEG>
-void launch_mid_force(const Parts<double> &P, const MidGrid &g, const MidMaterial &mat, const double *gv,
-                      const double *dv, double dt, double *f, double *part, uint32_t *flags, hipStream_t st);
+void launch_mid_collect_p2g(const MidSorted &S, const MidGrid &g, double *gm, double *gmv, hipStream_t st);
 template <int DIM, int DEG>
-void launch_mid_dforce(const Parts<double> &P, const MidGrid &g, const MidMaterial &mat, const double *gv,
-                       const double *dv, double dt, const double *du, double *df, hipStream_t st);
+void launch_mid_collect_force(const MidSorted &S, const MidGrid &g, double *f, hipStream_t st);
+template <int DIM, int DEG>
+void launch_mid_collect_apply(const MidSorted &S, const MidGrid &g, const double *mf, const double *pv, double dt,
+                              double *s, double *part, hipStream_t st);
 template <int DIM>
 void launch_mid_residual(const MidGrid &g, const double *mf, const double *f, const double *dv, double dt,
                          const double *grav, double *r, double *part, hipStream_t st);
 template <int DIM>
 void launch_mid_cg_init(const MidGrid &g, const double *mf, const double *r, double *delta, double *rc, double *pv,
                         double *part, hipStream_t st);
-template <int DIM>
-void launch_mid_apply(const MidGrid &g, const double *mf, const double *pv, const double *df, double dt, double *s,
-                      double *part, hipStream_t st);
 template <int DIM>
 void launch_mid_cg_step(const MidGrid &g, const double *mf, double alpha, const double *pv, const double *s,
                         double *delta, double *rc, double *part, hipStream_t st);

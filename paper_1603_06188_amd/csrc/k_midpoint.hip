@@ -3,10 +3,13 @@
 // the mass-inner-product conjugate gradient of Sec. 4.2.  Binary64 throughout.
 //
 // Layout: dense node arrays (node ix + N0 (iy + N1 iz)), component-major
-// vectors (component a of node i at a * nodes + i).  Particle kernels run one
-// thread per particle in the caller's order (no binning) and scatter with
-// binary64 atomics; node kernels run one thread per node and leave one
-// partial sum per block, summed in a fixed order by k_mid_reduce.
+// vectors (component a of node i at a * nodes + i).  Once per step the
+// particles are counting-sorted by base node and what the solve reads is
+// copied in that order; particle kernels then write one matrix per particle
+// and node kernels collect it over the sorted ranges of the base keys around
+// each node (no atomics in the Newton loop).  Node kernels leave one partial
+// sum per block, summed in a fixed order by k_mid_reduce.  The transfer to
+// particles reads the caller's order.
 #include "apic_kernels.h"
 
 namespace apic {
@@ -14,14 +17,10 @@ namespace apic {
 namespace {
 
 constexpr int kMidBlock = 256;
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * kMidBlock + threadIdx.x; }
 
-// Particle of thread t in the scattering kernels: (t * pstride) mod n with
-// pstride coprime to n (a bijection).  Particles stored cell by cell put the
-// lanes of a wave on the same few nodes, whose binary64 atomics then
-// serialize; the stride spreads a wave's lanes over the whole body.
-__device__ __forceinline__ int64_t spread(int64_t t, const MidGrid &g, int64_t n) { return (t * g.pstride) % n; }
 
 // Sum of K values over the block; thread 0 writes them to part[blockIdx * K].
 template <int K>
@@ -174,31 +173,6 @@ __device__ __forceinline__ void load_mat(const double *plane, int64_t s, int64_t
     for (int k = 0; k < DIM * DIM; ++k) M[k] = plane[k * s + p];
 }
 
-// Scatters -V (M F^T) grad w_ip into out (component-major node vectors).
-template <int DIM, int DEG>
-__device__ __forceinline__ void scatter_stress(const Axis<double, DEG> (&ax)[DIM], const MidGrid &g, const double *M,
-                                               const double *F, double V, double *out) {
-    double MFt[DIM * DIM];
-#pragma unroll
-    for (int r = 0; r < DIM; ++r)
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) s += M[r * DIM + k] * F[c * DIM + k];
-            MFt[r * DIM + c] = -V * s / g.dx;
-        }
-    for_support<DIM, DEG>(ax, g, [&](int64_t i, double, const double *gw, const double *) {
-#pragma unroll
-        for (int r = 0; r < DIM; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) s += MFt[r * DIM + c] * gw[c];
-            atomicAdd(&out[r * g.nodes + i], s);
-        }
-    });
-}
-
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
@@ -207,36 +181,129 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_fill(double *a, int64_t n, do
     if (i < n) a[i] = val;
 }
 
-// Transfer to grid of mass and affine momentum (Sec. 3.2).
+// --- particles sorted by base node (once per step) --------------------------
+// Key = linear index of the particle's base node; particles whose support
+// leaves the grid get no key (they take no part in the step).
 template <int DIM, int DEG>
-__global__ __launch_bounds__(kMidBlock) void k_mid_p2g(Parts<double> P, MidGrid g, double *gm, double *gmv,
-                                                       uint32_t *flags) {
-    const int64_t t = gtid();
-    if (t >= P.n) return;
-    const int64_t p = spread(t, g, P.n);
+__global__ __launch_bounds__(kMidBlock) void k_mid_keys(Parts<double> P, MidGrid g, uint32_t *key, uint32_t *count,
+                                                        uint32_t *flags) {
+    const int64_t p = gtid();
+    if (p >= P.n) return;
     Axis<double, DEG> ax[DIM];
     if (!particle_axes<DIM, DEG>(P, p, g, ax)) {
+        key[p] = kNoKey;
         atomicOr(flags, (uint32_t)APIC_FLAG_OUT_OF_DOMAIN);
         return;
     }
-    const double m = P.m[p];
-    double v[DIM], B[DIM * DIM];
+    int64_t k = ax[DIM - 1].base;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) v[a] = P.v[a * P.s + p];
-    load_mat<DIM>(P.B, P.s, p, B);
-    // B D^{-1} (x_i - x_p) with D = dx^2 / k I and x_i - x_p = r dx
-    const double q = inv_D_factor<double, DEG>() / g.dx;
-    for_support<DIM, DEG>(ax, g, [&](int64_t i, double w, const double *, const double *r) {
-        const double wm = w * m;
-        atomicAdd(&gm[i], wm);
+    for (int a = DIM - 2; a >= 0; --a) k = k * g.N[a] + ax[a].base;
+    key[p] = (uint32_t)k;
+    atomicAdd(&count[k], 1u);
+}
+
+// Exclusive prefix sum of count[0, n) into start[0, n], start[n] = total:
+// blocks of 1024 entries (scan1), the block totals in one block (scan2),
+// then the block offsets added (scan3).
+__global__ __launch_bounds__(kMidBlock) void k_mid_scan1(const uint32_t *count, int64_t n, uint32_t *start,
+                                                         uint32_t *bsum) {
+    __shared__ uint32_t sh[kMidBlock];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * 1024 + tid * 4;
+    uint32_t v[4], tsum = 0;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            double br = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = base + j < n ? count[base + j] : 0u;
+        tsum += v[j];
+    }
+    sh[tid] = tsum;
+    __syncthreads();
+    for (int o = 1; o < kMidBlock; o <<= 1) {
+        const uint32_t t = tid >= o ? sh[tid - o] : 0u;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    uint32_t run = sh[tid] - tsum;
 #pragma unroll
-            for (int b = 0; b < DIM; ++b) br += B[a * DIM + b] * r[b];
-            atomicAdd(&gmv[a * g.nodes + i], wm * (v[a] + q * br));
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n) start[base + j] = run;
+        run += v[j];
+    }
+    if (tid == kMidBlock - 1) bsum[blockIdx.x] = sh[tid];
+}
+
+__global__ __launch_bounds__(kMidBlock) void k_mid_scan2(uint32_t *bsum, int64_t nb, uint32_t *start, int64_t n) {
+    __shared__ uint32_t sh[kMidBlock];
+    __shared__ uint32_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0u;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += kMidBlock) {
+        const int64_t i = c0 + tid;
+        const uint32_t v = i < nb ? bsum[i] : 0u;
+        sh[tid] = v;
+        __syncthreads();
+        for (int o = 1; o < kMidBlock; o <<= 1) {
+            const uint32_t t = tid >= o ? sh[tid - o] : 0u;
+            __syncthreads();
+            sh[tid] += t;
+            __syncthreads();
         }
-    });
+        const uint32_t excl = sh[tid] - v + carry;
+        __syncthreads();
+        if (i < nb) bsum[i] = excl;
+        if (tid == kMidBlock - 1) carry += sh[tid];
+        __syncthreads();
+    }
+    if (tid == 0) start[n] = carry;
+}
+
+__global__ __launch_bounds__(kMidBlock) void k_mid_scan3(uint32_t *start, int64_t n, const uint32_t *bsum) {
+    const int64_t i = gtid();
+    if (i < n) start[i] += bsum[i >> 10];
+}
+
+// perm[position] = particle, positions of one key in any order.
+__global__ __launch_bounds__(kMidBlock) void k_mid_place(int64_t n, const uint32_t *key, const uint32_t *start,
+                                                         uint32_t *cursor, uint32_t *perm) {
+    const int64_t p = gtid();
+    if (p >= n) return;
+    const uint32_t k = key[p];
+    if (k == kNoKey) return;
+    perm[start[k] + atomicAdd(&cursor[k], 1u)] = (uint32_t)p;
+}
+
+// Sorted copies of what the solve reads (cell, offset, F, m) and the P2G
+// terms: mv = m v and Q = m (k / dx) B, so that node i receives
+// w (mv + Q r) with r = (x_i - x_p) / dx (B D^{-1} (x_i - x_p), D = dx^2 / k I).
+template <int DIM, int DEG>
+__global__ __launch_bounds__(kMidBlock) void k_mid_sort_state(Parts<double> P, MidSorted S) {
+    const int64_t pos = gtid();
+    if (pos >= S.n || pos >= (int64_t)S.start[S.nodes]) return;
+    const int64_t q = S.perm[pos];
+    S.cell[pos] = P.cell[q];
+    const double m = P.m[q];
+    S.m[pos] = m;
+    const double kq = m * inv_D_factor<double, DEG>() / S.dx;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        S.off[a * S.n + pos] = P.off[a * P.s + q];
+        S.mv[a * S.n + pos] = m * P.v[a * P.s + q];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        S.F[k * S.n + pos] = P.F[k * P.s + q];
+        S.M[k * S.n + pos] = kq * P.B[k * P.s + q];
+    }
+}
+
+template <int DIM, int DEG>
+__device__ __forceinline__ void sorted_axes(const MidSorted &S, int64_t pos, Axis<double, DEG> (&ax)[DIM]) {
+    int ci[3];
+    unpack_cell<DIM>(S.cell[pos], ci);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) axis_weights<double, DEG>(ci[a], S.off[a * S.n + pos], ax[a]);
 }
 
 // v_i = (m v)_i / m_i on free nodes (mass, outside the sticky band); 0
@@ -257,84 +324,187 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_nodes(MidGrid g, const double
     for (int a = 0; a < DIM; ++a) gv[a * g.nodes + i] = free_node ? gv[a * g.nodes + i] / m : 0.0;
 }
 
-// Forces at the displaced nodes x_i + u_i, u_i = dt/2 v_i + dt/4 dv_i
-// (Sec. 4.1), and Phi = sum_p V_p Psi(F_hat_p) (Sec. 3.3).
-template <int DIM, int DEG>
-__global__ __launch_bounds__(kMidBlock) void k_mid_force(Parts<double> P, MidGrid g, MidMaterial mat,
-                                                         const double *gv, const double *dv, double dt, double *f,
-                                                         double *part, uint32_t *flags) {
-    const int64_t t = gtid();
-    const int64_t p = t < P.n ? spread(t, g, P.n) : 0;
+// Per sorted particle, the matrix that the node collect contracts with
+// grad w (cell units): -V P(F_hat) F^T / dx for the force (DIFF = false;
+// block partials of Phi = sum V Psi(F_hat)), -V (dP/dF(F_hat) : dF) F^T / dx
+// for the force differential along du (DIFF = true), with
+// F_hat = (I + sum_i u_i grad w^T) F, u_i = dt/2 v_i + dt/4 dv_i, and
+// dF = (sum_i du_i grad w^T) F (Sec. 3.3, Sec. 4.1).
+template <int DIM, int DEG, bool DIFF>
+__global__ __launch_bounds__(kMidBlock) void k_mid_stress(MidSorted S, MidGrid g, MidMaterial mat, const double *gv,
+                                                          const double *dv, double dt, const double *du, double *part,
+                                                          uint32_t *flags) {
+    const int64_t pos = gtid();
     double acc[1] = {0.0};
-    Axis<double, DEG> ax[DIM];
-    if (t < P.n && particle_axes<DIM, DEG>(P, p, g, ax)) {
-        double F[DIM * DIM], G[DIM * DIM], Fh[DIM * DIM], IT[DIM * DIM];
-        load_mat<DIM>(P.F, P.s, p, F);
+    if (pos < S.n && pos < (int64_t)S.start[S.nodes]) {
+        Axis<double, DEG> ax[DIM];
+        sorted_axes<DIM, DEG>(S, pos, ax);
+        double F[DIM * DIM], G[DIM * DIM], Fh[DIM * DIM], IT[DIM * DIM], M[DIM * DIM];
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) F[k] = S.F[k * S.n + pos];
         gather_grad<DIM, DEG>(ax, g, gv, dv, 0.5 * dt, 0.25 * dt, G);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
         mat_mul<DIM>(G, F, Fh);
         const double J = det_inv_t<DIM>(Fh, IT);
-        const double V = P.m[p] / mat.rho0;
+        const double V = S.m[pos] / mat.rho0;
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) M[k] = 0.0;
         if (!(J > 0.0)) {
-            atomicOr(flags, (uint32_t)APIC_FLAG_INVERTED);
-            acc[0] = INFINITY;
+            if (!DIFF) {
+                atomicOr(flags, (uint32_t)APIC_FLAG_INVERTED);
+                acc[0] = INFINITY;
+            }
         } else {
             const double lnJ = log(J);
-            double tr = 0.0, Pk[DIM * DIM];
+            double Pk[DIM * DIM];
+            if constexpr (!DIFF) {
+                double tr = 0.0;
 #pragma unroll
-            for (int k = 0; k < DIM * DIM; ++k) {
-                tr += Fh[k] * Fh[k];
-                Pk[k] = mat.mu * (Fh[k] - IT[k]) + mat.lambda * lnJ * IT[k];
+                for (int k = 0; k < DIM * DIM; ++k) {
+                    tr += Fh[k] * Fh[k];
+                    Pk[k] = mat.mu * (Fh[k] - IT[k]) + mat.lambda * lnJ * IT[k];
+                }
+                acc[0] = V * (0.5 * mat.mu * (tr - DIM) - mat.mu * lnJ + 0.5 * mat.lambda * lnJ * lnJ);
+            } else {
+                double H[DIM * DIM], dF[DIM * DIM], dFt[DIM * DIM], T1[DIM * DIM], T2[DIM * DIM];
+                gather_grad<DIM, DEG>(ax, g, du, du, 1.0, 0.0, H);
+                mat_mul<DIM>(H, F, dF);
+                // tr(F_hat^{-1} dF) = sum_ab IT_ab dF_ab;  T2 = F_hat^{-T} dF^T F_hat^{-T}
+                double tr = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM * DIM; ++k) tr += IT[k] * dF[k];
+#pragma unroll
+                for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) dFt[r * DIM + c] = dF[c * DIM + r];
+                mat_mul<DIM>(IT, dFt, T1);
+                mat_mul<DIM>(T1, IT, T2);
+                const double cT = mat.mu - mat.lambda * lnJ;
+#pragma unroll
+                for (int k = 0; k < DIM * DIM; ++k) Pk[k] = mat.mu * dF[k] + cT * T2[k] + mat.lambda * tr * IT[k];
             }
-            acc[0] = V * (0.5 * mat.mu * (tr - DIM) - mat.mu * lnJ + 0.5 * mat.lambda * lnJ * lnJ);
-            scatter_stress<DIM, DEG>(ax, g, Pk, F, V, f);
+            // M = -V Pk F^T / dx
+#pragma unroll
+            for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) sum += Pk[r * DIM + k] * F[c * DIM + k];
+                    M[r * DIM + c] = -V * sum / g.dx;
+                }
         }
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) S.M[k * S.n + pos] = M[k];
     }
-    block_partials<1>(acc, part);
+    if constexpr (!DIFF) block_partials<1>(acc, part);
 }
 
-// Force differential at the displaced state for the node vector du
-// (Sec. 3.3): dF_p = (sum_j du_j grad w_jp^T) F_p,
-// A_p = mu dF + (mu - lam ln J) F_hat^{-T} dF^T F_hat^{-T} + lam tr(F_hat^{-1} dF) F_hat^{-T},
-// df_i = -sum_p V_p A_p F_p^T grad w_ip.
-template <int DIM, int DEG>
-__global__ __launch_bounds__(kMidBlock) void k_mid_dforce(Parts<double> P, MidGrid g, MidMaterial mat,
-                                                          const double *gv, const double *dv, double dt,
-                                                          const double *du, double *df) {
-    const int64_t t = gtid();
-    if (t >= P.n) return;
-    const int64_t p = spread(t, g, P.n);
-    Axis<double, DEG> ax[DIM];
-    if (!particle_axes<DIM, DEG>(P, p, g, ax)) return;
-    double F[DIM * DIM], G[DIM * DIM], H[DIM * DIM], Fh[DIM * DIM], dF[DIM * DIM], IT[DIM * DIM];
-    load_mat<DIM>(P.F, P.s, p, F);
-    gather_grad<DIM, DEG>(ax, g, gv, dv, 0.5 * dt, 0.25 * dt, G);
-    gather_grad<DIM, DEG>(ax, g, du, du, 1.0, 0.0, H);
+// Node collect: node i sums over the sorted particles whose base key lies in
+// [c - DEG, c] per axis (exactly the particles whose support holds node i).
+//   COLLECT_P2G:   gm_i = sum w m,  gv_i = sum w (mv + Q r)       (Sec. 3.2)
+//   COLLECT_FORCE: f_i = sum M grad w                             (Sec. 3.3)
+//   COLLECT_APPLY: df_i = sum M grad w, then s_i = p_i - dt^2/4 df_i / m_i on
+//                  free nodes (0 elsewhere) and block partials of <p, s>_M
+enum { COLLECT_P2G = 0, COLLECT_FORCE = 1, COLLECT_APPLY = 2 };
+
+template <int DIM, int DEG, int MODE>
+__global__ __launch_bounds__(kMidBlock) void k_mid_collect(MidSorted S, MidGrid g, double *out_m, double *out_v,
+                                                           const double *mf, const double *pv, double dt,
+                                                           double *part) {
+    const int64_t i = gtid();
+    double acc[1] = {0.0};
+    if (i < g.nodes) {
+        int c[3] = {0, 0, 0};
+        node_coords<DIM>(i, g, c);
+        double sm = 0.0, sv[DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
-    mat_mul<DIM>(G, F, Fh);
-    mat_mul<DIM>(H, F, dF);
-    const double J = det_inv_t<DIM>(Fh, IT);
-    if (!(J > 0.0)) return;
-    const double lnJ = log(J);
-    // tr(F_hat^{-1} dF) = sum_{a,b} IT[b][a] ... with F_hat^{-1} = IT^T: sum_ab IT[a][b] dF[a][b]
-    double tr = 0.0;
+        for (int a = 0; a < DIM; ++a) sv[a] = 0.0;
+        const int lo0 = c[0] - DEG > 0 ? c[0] - DEG : 0;
+        const int hi0 = c[0] < g.N[0] - 1 - DEG ? c[0] : g.N[0] - 1 - DEG;
+        constexpr int NZ = DIM == 3 ? DEG + 1 : 1;
+        for (int dz = 0; dz < NZ; ++dz) {
+            const int bz = DIM == 3 ? c[2] - dz : 0;
+            if (DIM == 3 && (bz < 0 || bz + DEG > g.N[2] - 1)) continue;
+            for (int dy = 0; dy <= DEG; ++dy) {
+                const int by = c[1] - dy;
+                if (by < 0 || by + DEG > g.N[1] - 1 || lo0 > hi0) continue;
+                const int64_t row = (int64_t)g.N[0] * (by + (int64_t)g.N[1] * bz);
+                const int64_t p0 = S.start[row + lo0], p1 = S.start[row + hi0 + 1];
+                for (int64_t pos = p0; pos < p1; ++pos) {
+                    Axis<double, DEG> ax[DIM];
+                    sorted_axes<DIM, DEG>(S, pos, ax);
+                    double w1[DIM], d1[DIM], r1[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) tr += IT[k] * dF[k];
-    // T = IT dF^T IT
-    double T1[DIM * DIM], T2[DIM * DIM], dFt[DIM * DIM];
+                    for (int a = 0; a < DIM; ++a) {
+                        const int k = c[a] - ax[a].base;
+                        w1[a] = 0.0;
+                        d1[a] = 0.0;
+                        r1[a] = 0.0;
 #pragma unroll
-    for (int r = 0; r < DIM; ++r)
+                        for (int j = 0; j <= DEG; ++j)
+                            if (j == k) {
+                                w1[a] = ax[a].w[j];
+                                d1[a] = ax[a].dw[j];
+                                r1[a] = ax[a].r[j];
+                            }
+                    }
+                    double w = w1[0], gw[DIM];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) dFt[r * DIM + c] = dF[c * DIM + r];
-    mat_mul<DIM>(IT, dFt, T1);
-    mat_mul<DIM>(T1, IT, T2);
-    double A[DIM * DIM];
-    const double cT = mat.mu - mat.lambda * lnJ;
+                    for (int a = 1; a < DIM; ++a) w *= w1[a];
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) A[k] = mat.mu * dF[k] + cT * T2[k] + mat.lambda * tr * IT[k];
-    scatter_stress<DIM, DEG>(ax, g, A, F, P.m[p] / mat.rho0, df);
+                    for (int a = 0; a < DIM; ++a) {
+                        double t = d1[a];
+#pragma unroll
+                        for (int b = 0; b < DIM; ++b)
+                            if (b != a) t *= w1[b];
+                        gw[a] = t;
+                    }
+                    if constexpr (MODE == COLLECT_P2G) {
+                        sm += w * S.m[pos];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) {
+                            double qr = 0.0;
+#pragma unroll
+                            for (int b = 0; b < DIM; ++b) qr += S.M[(a * DIM + b) * S.n + pos] * r1[b];
+                            sv[a] += w * (S.mv[a * S.n + pos] + qr);
+                        }
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) {
+                            double t = 0.0;
+#pragma unroll
+                            for (int b = 0; b < DIM; ++b) t += S.M[(a * DIM + b) * S.n + pos] * gw[b];
+                            sv[a] += t;
+                        }
+                    }
+                }
+            }
+        }
+        if constexpr (MODE == COLLECT_P2G) {
+            out_m[i] = sm;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = sv[a];
+        } else if constexpr (MODE == COLLECT_FORCE) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = sv[a];
+        } else {
+            const double m = mf[i];
+            const double cc = 0.25 * dt * dt;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const int64_t k = a * g.nodes + i;
+                double sa = 0.0;
+                if (m > 0.0) {
+                    sa = pv[k] - cc * sv[a] / m;
+                    acc[0] += m * pv[k] * sa;
+                }
+                out_v[k] = sa;
+            }
+        }
+    }
+    if constexpr (MODE == COLLECT_APPLY) block_partials<1>(acc, part);
 }
 
 // r_i = dv_i - dt (f_i / m_i + g) on free nodes (the gradient of E over
@@ -379,29 +549,6 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_cg_init(MidGrid g, const doub
             pv[k] = b;
             delta[k] = 0.0;
             acc[0] += m * b * b;
-        }
-    }
-    block_partials<1>(acc, part);
-}
-
-// s = A p = p - dt^2/4 M^{-1} (df/dx) p on free nodes; partial <p, s>_M.
-template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_apply(MidGrid g, const double *mf, const double *pv,
-                                                         const double *df, double dt, double *s, double *part) {
-    const int64_t i = gtid();
-    double acc[1] = {0.0};
-    if (i < g.nodes) {
-        const double m = mf[i];
-        const double c = 0.25 * dt * dt;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const int64_t k = a * g.nodes + i;
-            double sa = 0.0;
-            if (m > 0.0) {
-                sa = pv[k] - c * df[k] / m;
-                acc[0] += m * pv[k] * sa;
-            }
-            s[k] = sa;
         }
     }
     block_partials<1>(acc, part);
@@ -554,11 +701,23 @@ void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, 
 
 int64_t mid_particle_blocks(int64_t n) { return blocks_for(n); }
 int64_t mid_node_blocks(int64_t nodes) { return blocks_for(nodes); }
+int64_t mid_scan_blocks(int64_t nodes) { return (nodes + 1023) / 1024; }
 
 template <int DIM, int DEG>
-void launch_mid_p2g(const Parts<double> &P, const MidGrid &g, double *gm, double *gmv, uint32_t *flags,
-                    hipStream_t st) {
-    if (P.n > 0) k_mid_p2g<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, gm, gmv, flags);
+void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, uint32_t *key, uint32_t *count,
+                     uint32_t *cursor, uint32_t *bsum, uint32_t *flags, hipStream_t st) {
+    launch_fill<uint32_t>(count, g.nodes, 0u, st);
+    launch_fill<uint32_t>(cursor, g.nodes, 0u, st);
+    if (P.n > 0) k_mid_keys<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, key, count, flags);
+    const int64_t nb = mid_scan_blocks(g.nodes);
+    uint32_t *start = const_cast<uint32_t *>(S.start);
+    k_mid_scan1<<<(unsigned)nb, kMidBlock, 0, st>>>(count, g.nodes, start, bsum);
+    k_mid_scan2<<<1, kMidBlock, 0, st>>>(bsum, nb, start, g.nodes);
+    k_mid_scan3<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(start, g.nodes, bsum);
+    if (P.n > 0) {
+        k_mid_place<<<blocks_for(P.n), kMidBlock, 0, st>>>(P.n, key, S.start, cursor, const_cast<uint32_t *>(S.perm));
+        k_mid_sort_state<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, S);
+    }
 }
 
 template <int DIM>
@@ -566,16 +725,30 @@ void launch_mid_nodes(const MidGrid &g, const double *gm, double *gv, double *mf
     k_mid_nodes<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, gm, gv, mf);
 }
 
-template <int DIM, int DEG>
-void launch_mid_force(const Parts<double> &P, const MidGrid &g, const MidMaterial &mat, const double *gv,
-                      const double *dv, double dt, double *f, double *part, uint32_t *flags, hipStream_t st) {
-    k_mid_force<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, mat, gv, dv, dt, f, part, flags);
+template <int DIM, int DEG, bool DIFF>
+void launch_mid_stress(const MidSorted &S, const MidGrid &g, const MidMaterial &mat, const double *gv,
+                       const double *dv, double dt, const double *du, double *part, uint32_t *flags, hipStream_t st) {
+    if (S.n > 0) k_mid_stress<DIM, DEG, DIFF><<<blocks_for(S.n), kMidBlock, 0, st>>>(S, g, mat, gv, dv, dt, du, part,
+                                                                                     flags);
 }
 
 template <int DIM, int DEG>
-void launch_mid_dforce(const Parts<double> &P, const MidGrid &g, const MidMaterial &mat, const double *gv,
-                       const double *dv, double dt, const double *du, double *df, hipStream_t st) {
-    if (P.n > 0) k_mid_dforce<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, mat, gv, dv, dt, du, df);
+void launch_mid_collect_p2g(const MidSorted &S, const MidGrid &g, double *gm, double *gmv, hipStream_t st) {
+    k_mid_collect<DIM, DEG, COLLECT_P2G><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(S, g, gm, gmv, nullptr, nullptr,
+                                                                                    0.0, nullptr);
+}
+
+template <int DIM, int DEG>
+void launch_mid_collect_force(const MidSorted &S, const MidGrid &g, double *f, hipStream_t st) {
+    k_mid_collect<DIM, DEG, COLLECT_FORCE><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(S, g, nullptr, f, nullptr,
+                                                                                      nullptr, 0.0, nullptr);
+}
+
+template <int DIM, int DEG>
+void launch_mid_collect_apply(const MidSorted &S, const MidGrid &g, const double *mf, const double *pv, double dt,
+                              double *s, double *part, hipStream_t st) {
+    k_mid_collect<DIM, DEG, COLLECT_APPLY><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(S, g, nullptr, s, mf, pv, dt,
+                                                                                      part);
 }
 
 template <int DIM>
@@ -589,12 +762,6 @@ template <int DIM>
 void launch_mid_cg_init(const MidGrid &g, const double *mf, const double *r, double *delta, double *rc, double *pv,
                         double *part, hipStream_t st) {
     k_mid_cg_init<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, mf, r, delta, rc, pv, part);
-}
-
-template <int DIM>
-void launch_mid_apply(const MidGrid &g, const double *mf, const double *pv, const double *df, double dt, double *s,
-                      double *part, hipStream_t st) {
-    k_mid_apply<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, mf, pv, df, dt, s, part);
 }
 
 template <int DIM>
@@ -615,14 +782,19 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
 }
 
 #define APIC_MID_INST_DD(DIM, DEG)                                                                                   \
-    template void launch_mid_p2g<DIM, DEG>(const Parts<double> &, const MidGrid &, double *, double *, uint32_t *,   \
-                                           hipStream_t);                                                             \
-    template void launch_mid_force<DIM, DEG>(const Parts<double> &, const MidGrid &, const MidMaterial &,            \
-                                             const double *, const double *, double, double *, double *, uint32_t *, \
-                                             hipStream_t);                                                           \
-    template void launch_mid_dforce<DIM, DEG>(const Parts<double> &, const MidGrid &, const MidMaterial &,           \
-                                              const double *, const double *, double, const double *, double *,      \
-                                              hipStream_t);                                                          \
+    template void launch_mid_sort<DIM, DEG>(const Parts<double> &, const MidGrid &, const MidSorted &, uint32_t *,   \
+                                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, hipStream_t);            \
+    template void launch_mid_stress<DIM, DEG, false>(const MidSorted &, const MidGrid &, const MidMaterial &,         \
+                                                     const double *, const double *, double, const double *,         \
+                                                     double *, uint32_t *, hipStream_t);                             \
+    template void launch_mid_stress<DIM, DEG, true>(const MidSorted &, const MidGrid &, const MidMaterial &,          \
+                                                    const double *, const double *, double, const double *,          \
+                                                    double *, uint32_t *, hipStream_t);                              \
+    template void launch_mid_collect_p2g<DIM, DEG>(const MidSorted &, const MidGrid &, double *, double *,           \
+                                                   hipStream_t);                                                     \
+    template void launch_mid_collect_force<DIM, DEG>(const MidSorted &, const MidGrid &, double *, hipStream_t);     \
+    template void launch_mid_collect_apply<DIM, DEG>(const MidSorted &, const MidGrid &, const double *,             \
+                                                     const double *, double, double *, double *, hipStream_t);       \
     template void launch_mid_g2p<DIM, DEG>(const Parts<double> &, const MidGrid &, const double *, const double *,   \
                                            hipStream_t);
 #define APIC_MID_INST_D(DIM)                                                                                          \
@@ -631,8 +803,6 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
                                            const double *, double *, double *, hipStream_t);                         \
     template void launch_mid_cg_init<DIM>(const MidGrid &, const double *, const double *, double *, double *,       \
                                           double *, double *, hipStream_t);                                          \
-    template void launch_mid_apply<DIM>(const MidGrid &, const double *, const double *, const double *, double,     \
-                                        double *, double *, hipStream_t);                                            \
     template void launch_mid_cg_step<DIM>(const MidGrid &, const double *, double, const double *, const double *,   \
                                           double *, double *, double *, hipStream_t);                                \
     template void launch_mid_finish<DIM>(const MidGrid &, const double *, const double *, const double *, double,    \
