@@ -1152,7 +1152,10 @@ MidLayout mid_layout(const apic_grid_desc &g, int64_t n) {
     int64_t nodes = 1;
     for (int a = 0; a < g.dim; ++a) nodes *= (int64_t)g.cells[a] + 1;
     L.nodes = nodes;
-    L.nblk = std::max(mid_particle_blocks(std::max<int64_t>(n, 1)), mid_node_blocks(nodes));
+    int N[3] = {1, 1, 1};
+    for (int a = 0; a < g.dim; ++a) N[a] = g.cells[a] + 1;
+    L.nblk = std::max(std::max(mid_particle_blocks(std::max<int64_t>(n, 1)), mid_node_blocks(nodes)),
+                      mid_collect_blocks(g.dim, N));
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -1244,6 +1247,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     const bool elastic = s->prm.model == APIC_MODEL_NEO_HOOKEAN && P.n > 0;
     const int64_t nv = L.nodes * DIM;
     const int64_t pb = mid_particle_blocks(std::max<int64_t>(P.n, 1)), nb = mid_node_blocks(L.nodes);
+    const int64_t cb = mid_collect_blocks(DIM, g.N);
     double host[4] = {0, 0, 0, 0};
     apic_status rc0 = APIC_OK;
     // final reduction of K block partials, read back (synchronizes)
@@ -1296,7 +1300,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
                 if (gamma <= o.cg_tol * o.cg_tol * gamma0) break;
                 if (elastic) launch_mid_stress<DIM, DEG, true>(S, g, mat, gv, dv, dt, pv, nullptr, flags, st);
                 launch_mid_collect_apply<DIM, DEG>(S, g, mf, pv, dt, sv, part, st);
-                read(nb, 1);
+                read(cb, 1);
                 const double ps = host[0];
                 stats->cg_iters += 1;
                 if (!(ps > 0.0)) {

@@ -184,6 +184,7 @@ void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, 
 int64_t mid_particle_blocks(int64_t n);
 int64_t mid_node_blocks(int64_t nodes);
 int64_t mid_scan_blocks(int64_t nodes);
+int64_t mid_collect_blocks(int dim, const int *N);  // blocks (and partials) of a node collect
 template <int DIM, int DEG>
 void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, uint32_t *key, uint32_t *count,
                      uint32_t *cursor, uint32_t *bsum, uint32_t *flags, hipStream_t st);

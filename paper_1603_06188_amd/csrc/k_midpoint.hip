@@ -401,94 +401,118 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_stress(MidSorted S, MidGrid g
     if constexpr (!DIFF) block_partials<1>(acc, part);
 }
 
-// Node collect: node i sums over the sorted particles whose base key lies in
-// [c - DEG, c] per axis (exactly the particles whose support holds node i).
+// Node collect, one block per tile of kRowTile nodes along x of one node row
+// (fixed y, z).  The particles whose support holds a node of the row are
+// those whose base key lies in rows y - DEG..y, z - DEG..z: DEG + 1 (2D) or
+// (DEG + 1)^2 (3D) contiguous runs of the sorted order.  The block's lanes
+// stride over each run (coalesced loads) and add each particle's terms for
+// its DEG + 1 nodes of the row into LDS; the row tile is written once.
 //   COLLECT_P2G:   gm_i = sum w m,  gv_i = sum w (mv + Q r)       (Sec. 3.2)
 //   COLLECT_FORCE: f_i = sum M grad w                             (Sec. 3.3)
 //   COLLECT_APPLY: df_i = sum M grad w, then s_i = p_i - dt^2/4 df_i / m_i on
 //                  free nodes (0 elsewhere) and block partials of <p, s>_M
 enum { COLLECT_P2G = 0, COLLECT_FORCE = 1, COLLECT_APPLY = 2 };
+constexpr int kRowTile = 256;
+
+template <int DIM>
+__host__ __device__ __forceinline__ int64_t collect_blocks(const int *N) {
+    const int64_t tiles = (N[0] + kRowTile - 1) / kRowTile;
+    return DIM == 3 ? tiles * N[1] * N[2] : tiles * N[1];
+}
 
 template <int DIM, int DEG, int MODE>
 __global__ __launch_bounds__(kMidBlock) void k_mid_collect(MidSorted S, MidGrid g, double *out_m, double *out_v,
                                                            const double *mf, const double *pv, double dt,
                                                            double *part) {
-    const int64_t i = gtid();
-    double acc[1] = {0.0};
-    if (i < g.nodes) {
-        int c[3] = {0, 0, 0};
-        node_coords<DIM>(i, g, c);
-        double sm = 0.0, sv[DIM];
+    constexpr int NC = MODE == COLLECT_P2G ? 1 + DIM : DIM;
+    __shared__ double acc[kRowTile * NC];
+    const int tid = threadIdx.x;
+    const int ntile = (g.N[0] + kRowTile - 1) / kRowTile;
+    const int64_t row = blockIdx.x / ntile;
+    const int x0 = (int)(blockIdx.x % ntile) * kRowTile;
+    const int x1 = (x0 + kRowTile < g.N[0] ? x0 + kRowTile : g.N[0]) - 1;
+    const int cy = (int)(row % g.N[1]);
+    const int cz = DIM == 3 ? (int)(row / g.N[1]) : 0;
+    for (int k = tid; k < kRowTile * NC; k += kMidBlock) acc[k] = 0.0;
+    __syncthreads();
+    const int lo = x0 - DEG > 0 ? x0 - DEG : 0;
+    const int hi = x1 < g.N[0] - 1 - DEG ? x1 : g.N[0] - 1 - DEG;
+    constexpr int NZ = DIM == 3 ? DEG + 1 : 1;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) sv[a] = 0.0;
-        const int lo0 = c[0] - DEG > 0 ? c[0] - DEG : 0;
-        const int hi0 = c[0] < g.N[0] - 1 - DEG ? c[0] : g.N[0] - 1 - DEG;
-        constexpr int NZ = DIM == 3 ? DEG + 1 : 1;
-        for (int dz = 0; dz < NZ; ++dz) {
-            const int bz = DIM == 3 ? c[2] - dz : 0;
-            if (DIM == 3 && (bz < 0 || bz + DEG > g.N[2] - 1)) continue;
-            for (int dy = 0; dy <= DEG; ++dy) {
-                const int by = c[1] - dy;
-                if (by < 0 || by + DEG > g.N[1] - 1 || lo0 > hi0) continue;
-                const int64_t row = (int64_t)g.N[0] * (by + (int64_t)g.N[1] * bz);
-                const int64_t p0 = S.start[row + lo0], p1 = S.start[row + hi0 + 1];
-                for (int64_t pos = p0; pos < p1; ++pos) {
-                    Axis<double, DEG> ax[DIM];
-                    sorted_axes<DIM, DEG>(S, pos, ax);
-                    double w1[DIM], d1[DIM], r1[DIM];
+    for (int dz = 0; dz < NZ; ++dz) {
+        const int bz = cz - dz;
+        if (DIM == 3 && (bz < 0 || bz + DEG > g.N[2] - 1)) continue;
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        const int k = c[a] - ax[a].base;
-                        w1[a] = 0.0;
-                        d1[a] = 0.0;
-                        r1[a] = 0.0;
+        for (int dy = 0; dy <= DEG; ++dy) {
+            const int by = cy - dy;
+            if (by < 0 || by + DEG > g.N[1] - 1 || lo > hi) continue;
+            const int64_t krow = (int64_t)g.N[0] * (by + (int64_t)g.N[1] * bz);
+            const int64_t p1 = S.start[krow + hi + 1];
+            for (int64_t pos = S.start[krow + lo] + tid; pos < p1; pos += kMidBlock) {
+                Axis<double, DEG> ax[DIM];
+                sorted_axes<DIM, DEG>(S, pos, ax);
+                // the particle's weights along y (and z) at this row are fixed: index dy (dz)
+                const double wy = ax[1].w[dy], dwy = ax[1].dw[dy], ry = ax[1].r[dy];
+                const double wz = DIM == 3 ? ax[DIM - 1].w[dz] : 1.0;
+                const double dwz = DIM == 3 ? ax[DIM - 1].dw[dz] : 0.0;
+                const double rz = DIM == 3 ? ax[DIM - 1].r[dz] : 0.0;
+                double Mq[DIM * DIM], mq = 0.0, mvq[DIM];
+                if constexpr (MODE == COLLECT_P2G) {
+                    mq = S.m[pos];
 #pragma unroll
-                        for (int j = 0; j <= DEG; ++j)
-                            if (j == k) {
-                                w1[a] = ax[a].w[j];
-                                d1[a] = ax[a].dw[j];
-                                r1[a] = ax[a].r[j];
-                            }
-                    }
-                    double w = w1[0], gw[DIM];
+                    for (int a = 0; a < DIM; ++a) mvq[a] = S.mv[a * S.n + pos];
+                }
 #pragma unroll
-                    for (int a = 1; a < DIM; ++a) w *= w1[a];
+                for (int k = 0; k < DIM * DIM; ++k) Mq[k] = S.M[k * S.n + pos];
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        double t = d1[a];
-#pragma unroll
-                        for (int b = 0; b < DIM; ++b)
-                            if (b != a) t *= w1[b];
-                        gw[a] = t;
-                    }
+                for (int kx = 0; kx <= DEG; ++kx) {
+                    const int x = ax[0].base + kx;
+                    if (x < x0 || x > x1) continue;
+                    double* cell = acc + (x - x0) * NC;
+                    const double w = ax[0].w[kx] * wy * wz;
                     if constexpr (MODE == COLLECT_P2G) {
-                        sm += w * S.m[pos];
+                        double r[DIM];
+                        r[0] = ax[0].r[kx];
+                        r[1] = ry;
+                        if constexpr (DIM == 3) r[2] = rz;
+                        atomicAdd(&cell[0], w * mq);
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) {
                             double qr = 0.0;
 #pragma unroll
-                            for (int b = 0; b < DIM; ++b) qr += S.M[(a * DIM + b) * S.n + pos] * r1[b];
-                            sv[a] += w * (S.mv[a * S.n + pos] + qr);
+                            for (int b = 0; b < DIM; ++b) qr += Mq[a * DIM + b] * r[b];
+                            atomicAdd(&cell[1 + a], w * (mvq[a] + qr));
                         }
                     } else {
+                        double gw[DIM];
+                        gw[0] = ax[0].dw[kx] * wy * wz;
+                        gw[1] = ax[0].w[kx] * dwy * wz;
+                        if constexpr (DIM == 3) gw[2] = ax[0].w[kx] * wy * dwz;
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) {
                             double t = 0.0;
 #pragma unroll
-                            for (int b = 0; b < DIM; ++b) t += S.M[(a * DIM + b) * S.n + pos] * gw[b];
-                            sv[a] += t;
+                            for (int b = 0; b < DIM; ++b) t += Mq[a * DIM + b] * gw[b];
+                            atomicAdd(&cell[a], t);
                         }
                     }
                 }
             }
         }
+    }
+    __syncthreads();
+    double part_acc[1] = {0.0};
+    const int64_t rowbase = (int64_t)g.N[0] * row;
+    for (int x = x0 + tid; x <= x1; x += kMidBlock) {
+        const int64_t i = rowbase + x;
+        const double *cell = acc + (x - x0) * NC;
         if constexpr (MODE == COLLECT_P2G) {
-            out_m[i] = sm;
+            out_m[i] = cell[0];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = sv[a];
+            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = cell[1 + a];
         } else if constexpr (MODE == COLLECT_FORCE) {
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = sv[a];
+            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = cell[a];
         } else {
             const double m = mf[i];
             const double cc = 0.25 * dt * dt;
@@ -497,14 +521,14 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_collect(MidSorted S, MidGrid 
                 const int64_t k = a * g.nodes + i;
                 double sa = 0.0;
                 if (m > 0.0) {
-                    sa = pv[k] - cc * sv[a] / m;
-                    acc[0] += m * pv[k] * sa;
+                    sa = pv[k] - cc * cell[a] / m;
+                    part_acc[0] += m * pv[k] * sa;
                 }
                 out_v[k] = sa;
             }
         }
     }
-    if constexpr (MODE == COLLECT_APPLY) block_partials<1>(acc, part);
+    if constexpr (MODE == COLLECT_APPLY) block_partials<1>(part_acc, part);
 }
 
 // r_i = dv_i - dt (f_i / m_i + g) on free nodes (the gradient of E over
@@ -702,6 +726,7 @@ void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, 
 int64_t mid_particle_blocks(int64_t n) { return blocks_for(n); }
 int64_t mid_node_blocks(int64_t nodes) { return blocks_for(nodes); }
 int64_t mid_scan_blocks(int64_t nodes) { return (nodes + 1023) / 1024; }
+int64_t mid_collect_blocks(int dim, const int *N) { return dim == 3 ? collect_blocks<3>(N) : collect_blocks<2>(N); }
 
 template <int DIM, int DEG>
 void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, uint32_t *key, uint32_t *count,
@@ -734,20 +759,20 @@ void launch_mid_stress(const MidSorted &S, const MidGrid &g, const MidMaterial &
 
 template <int DIM, int DEG>
 void launch_mid_collect_p2g(const MidSorted &S, const MidGrid &g, double *gm, double *gmv, hipStream_t st) {
-    k_mid_collect<DIM, DEG, COLLECT_P2G><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(S, g, gm, gmv, nullptr, nullptr,
+    k_mid_collect<DIM, DEG, COLLECT_P2G><<<(unsigned)collect_blocks<DIM>(g.N), kMidBlock, 0, st>>>(S, g, gm, gmv, nullptr, nullptr,
                                                                                     0.0, nullptr);
 }
 
 template <int DIM, int DEG>
 void launch_mid_collect_force(const MidSorted &S, const MidGrid &g, double *f, hipStream_t st) {
-    k_mid_collect<DIM, DEG, COLLECT_FORCE><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(S, g, nullptr, f, nullptr,
+    k_mid_collect<DIM, DEG, COLLECT_FORCE><<<(unsigned)collect_blocks<DIM>(g.N), kMidBlock, 0, st>>>(S, g, nullptr, f, nullptr,
                                                                                       nullptr, 0.0, nullptr);
 }
 
 template <int DIM, int DEG>
 void launch_mid_collect_apply(const MidSorted &S, const MidGrid &g, const double *mf, const double *pv, double dt,
                               double *s, double *part, hipStream_t st) {
-    k_mid_collect<DIM, DEG, COLLECT_APPLY><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(S, g, nullptr, s, mf, pv, dt,
+    k_mid_collect<DIM, DEG, COLLECT_APPLY><<<(unsigned)collect_blocks<DIM>(g.N), kMidBlock, 0, st>>>(S, g, nullptr, s, mf, pv, dt,
                                                                                       part);
 }
 
