@@ -144,3 +144,54 @@ def test_invalid_scenes_are_rejected_before_any_launch():
         want = b.APIC_E_WORKSPACE if name == "workspace" else b.APIC_E_INVAL
         assert e.value.code == want, (name, e.value.code, str(e.value))
 
+
+
+def test_midpoint_entry_point_validation_without_gpu():
+    """apic_step_midpoint rejects what it does not run (binary32, multilinear,
+    RPIC/PIC, adaptive steps: APIC_E_UNSUPPORTED), bad options and a small
+    workspace before anything is enqueued; its workspace grows with the grid
+    and the particle count."""
+    from paper_1603_06188_amd import binding as b
+
+    def scene():
+        sc = b.ApicScene()
+        g = sc.grid
+        g.dim, g.degree, g.precision, g.options = 3, 2, b.APIC_F64, 0
+        for a in range(3):
+            g.cells[a] = 16
+        g.dx = 1.0 / 16
+        p = sc.p
+        p.n, p.stride = 10, 10
+        fake = 1 << 20  # never dereferenced: validation fails first
+        p.cell = p.off = p.v = p.B = p.F = p.mass = fake
+        sc.prm.dt, sc.prm.model, sc.prm.rho0 = 1e-3, 1, 1.0
+        sc.workspace = 1 << 24
+        sc.workspace_bytes = 0
+        return sc
+
+    null_stream = type("NullStream", (), {"cuda_stream": 0})()
+    g = scene().grid
+    small = b.apic_midpoint_workspace_bytes(g, 10)
+    assert b.apic_midpoint_workspace_bytes(g, 100_000) > small
+    assert small > 17 ** 3 * (2 + 9 * 3) * 8
+    cases = {
+        "binary32": (lambda s: setattr(s.grid, "precision", b.APIC_F32), -2),
+        "multilinear": (lambda s: setattr(s.grid, "degree", b.APIC_MULTILINEAR), -2),
+        "rpic": (lambda s: setattr(s.prm, "transfer", b.APIC_TRANSFER_RPIC), -2),
+        "adaptive": (lambda s: (setattr(s.grid, "options", b.APIC_OPT_ADAPTIVE_DT), setattr(s.prm, "cfl", 0.5)), -2),
+        "workspace": (lambda s: None, -4),
+        "dt": (lambda s: setattr(s.prm, "dt", -1.0), -1),
+    }
+    for name, (spoil, code) in cases.items():
+        sc = scene()
+        spoil(sc)
+        with pytest.raises(b.ApicError) as e:
+            b.apic_step_midpoint(sc, 1, stream=null_stream)
+        assert e.value.code == code, (name, e.value.code, b.apic_last_error())
+    sc = scene()
+    with pytest.raises(b.ApicError) as e:
+        b.apic_step_midpoint(sc, 1, newton_tol=-1.0, stream=null_stream)
+    assert e.value.code == -1
+    with pytest.raises(b.ApicError) as e:
+        b.apic_step_midpoint(sc, -1, stream=null_stream)
+    assert e.value.code == -1
