@@ -79,8 +79,8 @@ template <int DIM, int DEG, typename Fn>
 __device__ __forceinline__ void for_support(const Axis<double, DEG> (&ax)[DIM], const MidGrid &g, Fn &&fn) {
     constexpr int K = DEG + 1;
     if constexpr (DIM == 3) {
-        // z rows one at a time: unrolling all K^3 nodes hoists every load
-#pragma unroll 1
+        // cubic: z rows one at a time (unrolling all 64 nodes hoists every load)
+#pragma unroll (DEG == 2 ? K : 1)
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int j = 0; j < K; ++j) {
