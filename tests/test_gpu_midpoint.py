@@ -151,3 +151,22 @@ def test_empty_scene_and_zero_steps():
     de = b.DeviceScene(e, midpoint=True)
     st = de.step_midpoint(2)
     assert st["converged"] == 1 and st["flags"] == 0
+
+
+def test_full_size_cube_conserves_momentum():
+    """The bench's cube (128^3 cells, 2,097,152 particles, binary64) at the
+    bench's dt = 5e-3, with gravity and the sticky floor off so that p and l
+    are conserved: one midpoint step converges, raises no flag, and keeps p
+    and l (B term included) to rounding.  (The oracle's Newton solve is too
+    slow at this size; this property holds at any size.)"""
+    b = _b()
+    s = scenes.cube3d(cells=128, precision="fp64", gravity=0.0, floor_band=0, vel_sigma=0.5)
+    s = dataclasses.replace(s, dt=5e-3)
+    ds = b.DeviceScene(s, with_id=False, midpoint=True)
+    t0 = ds.diagnostics(b.APIC_DIAG_PARTICLES)
+    st = ds.step_midpoint(1)
+    t1 = ds.diagnostics(b.APIC_DIAG_PARTICLES)
+    print(st, flush=True)
+    assert st["converged"] == 1 and st["flags"] == 0 and st["halvings"] == 0
+    S = float(np.sum(s.m * (np.linalg.norm(s.x, axis=1) + 1.0) * np.linalg.norm(s.v, axis=1)))
+    assert np.abs(t1[:6] - t0[:6]).max() <= 1e-12 * S, (t1[:6], t0[:6])
