@@ -387,8 +387,8 @@ const char *apic_version(void);
  * (dense node arrays: about (2 + 9 dim) doubles per node); the step uses it
  * as scratch, so the explicit entry points see a fresh workspace afterwards
  * (their binning and grid are rebuilt on their next call).  Synchronizes the
- * stream once per conjugate-gradient iteration (its inner products are read
- * back).  Particles whose support leaves the grid are skipped and set
+ * stream for every inner product it reads back: two per conjugate-gradient
+ * iteration, two per energy evaluation.  Particles whose support leaves the grid are skipped and set
  * APIC_FLAG_OUT_OF_DOMAIN in stats->flags; an element with det F_hat <= 0
  * sets APIC_FLAG_INVERTED and makes E infinite (the line search backs off).
  */
