@@ -170,3 +170,25 @@ def test_full_size_cube_conserves_momentum():
     assert st["converged"] == 1 and st["flags"] == 0 and st["halvings"] == 0
     S = float(np.sum(s.m * (np.linalg.norm(s.x, axis=1) + 1.0) * np.linalg.norm(s.v, axis=1)))
     assert np.abs(t1[:6] - t0[:6]).max() <= 1e-12 * S, (t1[:6], t0[:6])
+
+
+def test_particle_outside_the_grid_is_flagged_and_left_alone():
+    """A particle whose support leaves the grid takes no part in the step:
+    APIC_FLAG_OUT_OF_DOMAIN is raised, its state is unchanged, and the other
+    particles match the oracle run without it."""
+    b = _b()
+    s = _scene(3, 2, 800, seed=88)
+    x = s.x.copy()
+    x[0, 0] = 0.2 * s.dx
+    s = s.with_state(x=x)
+    ds = b.DeviceScene(s, midpoint=True)
+    before = ds.state()
+    st = ds.step_midpoint(1, **SOLVER)
+    got = ds.state()
+    assert st["flags"] & b.APIC_FLAG_OUT_OF_DOMAIN and st["converged"] == 1
+    for k in ("x", "v", "B", "F"):
+        np.testing.assert_array_equal(got[k][0], before[k][0])
+    r = oracle.midpoint_step(ogrid(s), s.x[1:], s.v[1:], s.B[1:], s.F[1:], s.m[1:], s.V[1:], s.model, s.mu, s.lam,
+                             s.dt, s.gravity, s.band, newton_tol=SOLVER["newton_tol"], cg_tol=SOLVER["cg_tol"])
+    rest = {k: got[k][1:] for k in ("x", "v", "B", "F")}
+    _compare(rest, r["x_new"], r["v_new"], r["B_new"], r["F_new"], s.dx, TOL, "midpoint with an outside particle")
