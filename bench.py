@@ -216,6 +216,49 @@ def midpoint(steps: int, cells: int = 128):
     return out
 
 
+MIDPOINT_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                "midpoint_cube128_kernel_trace.md")
+
+
+def midpoint_roofline(particles: int = 2_097_152, active_nodes: int = 300_763):
+    """Roofline of the midpoint step's dominant kernel (the force-differential
+    collect of each CG iteration) from the committed rocprofv3 summary: its
+    mean duration (kernel trace) and HBM bytes (FETCH_SIZE + WRITE_SIZE).
+    Algorithmic bytes per launch: 100 B per particle (cell, offset, matrix)
+    and 56 B per active node (p and s read and written, m)."""
+    if not os.path.exists(MIDPOINT_PROFILE):
+        return None
+    kern = "k_mid_collect<3, 2, 2>"
+    rows = [ln for ln in open(MIDPOINT_PROFILE) if ln.startswith(f"| `{kern}` |")]
+    if len(rows) < 2:
+        return None
+    avg_us = float(rows[0].split("|")[3])
+    fetch_mb, write_mb = (float(rows[1].split("|")[k]) for k in (2, 3))
+    alg = particles * 100 + active_nodes * 56
+    achieved = alg / avg_us / 1e3
+    return {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+            "frac": achieved / 8000.0, "traffic": (fetch_mb + write_mb) * 1e6, "duration_us": avg_us,
+            "duration_source": "profiles/midpoint_cube128_kernel_trace.md (rocprofv3 kernel trace, same workload)"}
+
+
+def midpoint_cpu_baseline(cells: int = 64, dt: float = 5e-3):
+    """The oracle's midpoint step (single thread) on a bounded sample: the
+    elastic cube on cells^3, one step."""
+    import oracle
+
+    from paper_1603_06188_amd import scenes
+
+    s = scenes.cube3d(cells=cells, precision="fp64")
+    g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
+    t0 = time.perf_counter()
+    r = oracle.midpoint_step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, dt, s.gravity, s.band,
+                             newton_tol=1e-10, cg_tol=1e-8, max_newton=20, max_cg=500)
+    el = time.perf_counter() - t0
+    return {"value": s.n / el, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"elastic cube {cells}^3 cells ({s.n} particles), one midpoint step at dt={dt:g} "
+                      f"({r['stats']['newton']} Newton, {r['stats']['cg']} CG iterations), {el:.1f} s"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +335,8 @@ def main(argv=None):
             "config": {"workload": "elastic cube 128^3, quadratic, neo-Hookean, gravity, sticky floor, implicit "
                                    "midpoint (Newton + mass-inner-product CG), dt=5e-3",
                        "particles": res["particles"]},
+            "roofline": midpoint_roofline(res["particles"]),
+            "cpu_baseline": None if args.no_cpu_baseline else midpoint_cpu_baseline(),
             "modes": res}), flush=True)
         return 0
     if args.calibrate_copy:
