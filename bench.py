@@ -40,6 +40,10 @@ P2G_PARTICLE_B = 104
 G2P_PARTICLE_B = 52 + 100
 NODE_MMV_B = 16
 NODE_VT_B = 12
+# whole step: state read once (104 B) and written once (100 B) per particle;
+# per active node m and m v written and read (2 x 16 B), vt written and read (2 x 12 B)
+STEP_PARTICLE_B = 204
+STEP_NODE_B = 56
 
 
 def _ensure_built():
@@ -66,29 +70,65 @@ def measured_traffic(phase: str):
     return float(v) if v is not None else None
 
 
-def cpu_baseline(scene, budget_s: float = 12.0, max_steps: int = 3):
-    """Time the FP64 oracle (single thread, as written) on the full particle
-    set of the workload for as many steps as fit in about budget_s."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads() -> int:
+    """Cores this process may use: its affinity set, capped by OMP_NUM_THREADS
+    when that is set (the share of the host the job was given)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(n, 1)
+
+
+def cpu_baseline(scene, budget_s: float = 10.0, max_steps: int = 5):
+    """Time the FP64 oracle on the full particle set of the workload: on all
+    the host cores this job has (particles split into blocks, private grids
+    summed in thread order) for as many steps as fit in about budget_s, and
+    on one thread (the serial checker) for one step."""
     import oracle
 
     g = oracle.Grid(scene.dim, scene.degree, scene.cells, scene.dx)
-    x, v, B, F = scene.x, scene.v, scene.B, scene.F
-    steps = 0
-    t0 = time.perf_counter()
-    while steps < max_steps:
-        r = oracle.step(g, x, v, B, F, scene.m, scene.V, scene.model, scene.mu, scene.lam, scene.dt,
-                        scene.gravity, scene.band)
-        x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
-        steps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
+
+    def run(threads, steps_max, budget):
+        oracle.set_threads(threads)
+        x, v, B, F = scene.x, scene.v, scene.B, scene.F
+        steps = 0
+        t0 = time.perf_counter()
+        try:
+            while steps < steps_max:
+                r = oracle.step(g, x, v, B, F, scene.m, scene.V, scene.model, scene.mu, scene.lam, scene.dt,
+                                scene.gravity, scene.band)
+                x, v, B, F = r["x_new"], r["v_new"], r["B_new"], r["F_new"]
+                steps += 1
+                if time.perf_counter() - t0 >= budget:
+                    break
+        finally:
+            oracle.set_threads(1)
+        return steps, time.perf_counter() - t0
+
+    cores = _host_threads()
+    steps, el = run(cores, max_steps, budget_s)
+    steps1, el1 = run(1, 1, 0.0)
     return {
         "value": scene.n * steps / el,
         "unit": "particle-updates/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"full {scene.n}-particle cube, {steps} step(s), {el:.1f} s, single-threaded FP64 C oracle",
+        "cpu_model": _cpu_model(),
+        "sample": f"full {scene.n}-particle cube, {steps} step(s) in {el:.1f} s on {cores} thread(s) "
+                  f"(FP64 C oracle, OpenMP over particle blocks)",
+        "single_thread": {"value": scene.n * steps1 / el1, "steps": steps1, "seconds": round(el1, 2)},
     }
 
 
@@ -446,6 +486,12 @@ def main(argv=None):
     dom = max(("p2g", "grid_update", "g2p"), key=lambda p: dur[p])
     achieved = alg_bytes[dom] / (dur[dom] * 1e-3) / 1e9
     value = n * args.steps / el
+    # the whole step against the roofline: what the method itself moves per
+    # step (particle state read once and written once, 204 B; m, m v written
+    # and read and vt written and read, 56 B per active node) over the
+    # measured time per step
+    step_bytes = n * STEP_PARTICLE_B + active * STEP_NODE_B
+    step_achieved = step_bytes / (el / args.steps) / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -480,13 +526,27 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None if args.fused else measured_traffic(dom),  # counters cover the unfused kernels
+            "step_bytes": step_bytes,
+            "step_achieved": step_achieved,
+            "step_frac": step_achieved / HBM_PEAK_GBS,
         },
     }
-    if not args.no_serve:
-        del ds
+    del ds
+    torch.cuda.empty_cache()
+    if not args.headline_only:
+        # config 4 (many bodies, batched vs the per-scene loop) and config 3
+        # (two spheres, cubic, three precision modes), a few steps each
+        print("bench: batch leg", file=sys.stderr, flush=True)
+        out["batch"] = batched(args.scenes, 10)
         torch.cuda.empty_cache()
+        print("bench: spheres leg", file=sys.stderr, flush=True)
+        out["spheres"] = spheres(10)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        print("bench: served leg", file=sys.stderr, flush=True)
         out["served"] = served(args.serve_pool, args.serve_seconds, args.serve_load)
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out), flush=True)
     return 0

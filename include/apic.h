@@ -180,7 +180,8 @@ enum {
 enum {
     APIC_DIAG_PARTICLES = 0,  /* p, l (with the B term of Sec. 5.3), KE, M    */
     APIC_DIAG_GRID = 1,       /* p, l, KE, M of (m v)_i + dt f_i at x_i       */
-    APIC_DIAG_GRID_NEW = 2    /* p, l, KE, M of m_i vt_i at x_i + dt vt_i     */
+    APIC_DIAG_GRID_NEW = 2,   /* p, l, KE, M of m_i vt_i at x_i + dt vt_i     */
+    APIC_DIAG_ENERGY = 3      /* energies of the particle state, see below     */
 };
 
 /*
@@ -291,7 +292,13 @@ apic_status apic_grid_export(const apic_scene *scene, int32_t field, void *out, 
  * Binary64 totals (Sec. 3.1 momenta; Sec. 5.3 particle angular momentum):
  * out[0..2] linear momentum, out[3..5] angular momentum about the origin (in
  * 2D the scalar is out[5]), out[6] kinetic energy 1/2 sum m |v|^2, out[7]
- * mass.  `out` is a HOST array of 8 doubles.  Synchronizes `stream`.
+ * mass.  APIC_DIAG_ENERGY instead gives the energies of the particle state:
+ * out[0] kinetic energy 1/2 sum_p m_p |v_p|^2 (Sec. 3.1, with the factor
+ * 1/2), out[1] potential energy Phi = sum_p V_p Psi(F_p) of Sec. 3.3 with the
+ * neo-Hookean density Psi = mu/2 (tr F^T F - d) - mu ln J + lambda/2 (ln J)^2
+ * and V_p = m_p / rho0 (0 for APIC_MODEL_NONE, +inf if some det F_p <= 0),
+ * out[2] = out[0] + out[1], out[3..6] = 0, out[7] mass.  `out` is a HOST
+ * array of 8 doubles.  Synchronizes `stream`.
  */
 apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out, void *stream);
 
@@ -389,8 +396,10 @@ const char *apic_version(void);
  * (their binning and grid are rebuilt on their next call).  Synchronizes the
  * stream for every inner product it reads back: two per conjugate-gradient
  * iteration, two per energy evaluation.  Particles whose support leaves the grid are skipped and set
- * APIC_FLAG_OUT_OF_DOMAIN in stats->flags; an element with det F_hat <= 0
- * sets APIC_FLAG_INVERTED and makes E infinite (the line search backs off).
+ * APIC_FLAG_OUT_OF_DOMAIN in stats->flags.  A trial iterate with some
+ * det F_hat <= 0 has E = +inf and the line search halves it (it is never
+ * accepted while a halving is left); APIC_FLAG_INVERTED is raised only when
+ * an accepted iterate (the start of a step, or the 30th trial) is inverted.
  */
 typedef struct {
     double newton_tol;   /* relative Newton tolerance, 0 = default 1e-10      */

@@ -71,7 +71,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
              "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -137,6 +137,10 @@ def _load():
         lib.oracle_node_count.argtypes = [G]
         lib.oracle_matrix_det.restype = ctypes.c_double
         lib.oracle_matrix_det.argtypes = [ctypes.c_int, _dp]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_get_threads.restype = ctypes.c_int
+        lib.oracle_get_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -182,6 +186,16 @@ class Grid:
 
     def ref(self):
         return ctypes.byref(self._s)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the transfers (1, the default, is the serial checker the
+    tests use; more split the particles into blocks, for the CPU baseline)."""
+    _load().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().oracle_get_threads())
 
 
 def bspline(degree: int, t: float) -> float:
@@ -398,7 +412,8 @@ def midpoint_step(grid: Grid, x, v, B, F, m, V, model=1, mu=0.0, lam=0.0, dt=0.0
     the iterate so far, or b itself on the first iteration); then a
     backtracking line search (halving from 1, at most 30 times, until E does
     not increase or |r|_M decreases: near the minimum E is flat to within its
-    rounding while the gradient still falls).  Newton stops when
+    rounding while the gradient still falls; a trial that inverts an element
+    has E = +inf, since Psi grows without bound as J -> 0+, and is halved).  Newton stops when
     |r|_M <= newton_tol |r_0|_M.
 
     Then vt_i = v_i + dv_i, xt_i = x_i + dt (v_i + vt_i)/2 and the transfer to
@@ -421,7 +436,13 @@ def midpoint_step(grid: Grid, x, v, B, F, m, V, model=1, mu=0.0, lam=0.0, dt=0.0
 
     def residual_energy(dv):
         u = 0.5 * dt * gv + 0.25 * dt * dv
-        f, phi = forces_at(grid, x, F, Vp, mu, lam, u)
+        try:
+            f, phi = forces_at(grid, x, F, Vp, mu, lam, u)
+        except OracleError as e:
+            # an inverted element: Psi -> +inf as J -> 0+, so E is +inf there
+            if str(e) != _ERRORS[OR_E_INVERTED]:
+                raise
+            return None, np.inf
         r = np.zeros_like(dv)
         r[free] = dv[free] - dt * (f[free] / gm[free, None] + grav)
         E = float(np.sum(mf[:, None] * (0.125 * dv * dv - 0.25 * dt * grav * dv))) + phi
@@ -437,6 +458,8 @@ def midpoint_step(grid: Grid, x, v, B, F, m, V, model=1, mu=0.0, lam=0.0, dt=0.0
     dv = np.zeros((grid.node_count, d))
     stats = {"newton": 0, "cg": 0, "halvings": 0, "res0": 0.0, "res": 0.0}
     r, E = residual_energy(dv)
+    if r is None:
+        raise OracleError(_ERRORS[OR_E_INVERTED])
     res0 = np.sqrt(dot_m(r, r))
     stats["res0"] = res0
     for it in range(max_newton):
@@ -465,14 +488,18 @@ def midpoint_step(grid: Grid, x, v, B, F, m, V, model=1, mu=0.0, lam=0.0, dt=0.0
             kappa = dot_m(rc, rc)
             p = rc + (kappa / gamma) * p
             gamma = kappa
-        # backtracking line search on E
+        # backtracking line search on E; a trial with an inverted element
+        # (E = +inf) is always halved
         step = 1.0
         for k in range(30):
             r_new, E_new = residual_energy(dv + step * delta)
-            if E_new <= E or np.sqrt(dot_m(r_new, r_new)) < np.sqrt(dot_m(r, r)) or k == 29:
+            ok = np.isfinite(E_new) and (E_new <= E or np.sqrt(dot_m(r_new, r_new)) < np.sqrt(dot_m(r, r)))
+            if ok or k == 29:
                 break
             step *= 0.5
             stats["halvings"] += 1
+        if not np.isfinite(E_new):
+            raise OracleError(_ERRORS[OR_E_INVERTED])
         dv = dv + step * delta
         r, E = r_new, E_new
         stats["newton"] = it + 1

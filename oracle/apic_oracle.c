@@ -20,6 +20,10 @@
  *   Particle vectors are stored particle-major: x[p*d + a],
  *   matrices row-major: B[p*d*d + r*d + c].
  *   All arithmetic is IEEE binary64; build with -ffp-contract=off.
+ *   The transfers run on one thread unless oracle_set_threads asks for more
+ *   (the CPU baseline of the benchmark): particles are then split into
+ *   contiguous blocks, one per thread, and the transfer to grid sums the
+ *   threads' private grids in thread order.  The tests use one thread.
  *
  * Readings of the paper that this file takes (each listed in the design notes):
  *   - N is the tensor product of the cardinal quadratic / cubic B-spline
@@ -62,6 +66,12 @@
 #define OR_TRANSFER_APIC 0
 #define OR_TRANSFER_RPIC 1
 #define OR_TRANSFER_PIC 2
+
+/* Threads of oracle_p2g and oracle_g2p (1: the plain serial checker). */
+static int g_threads = 1;
+
+void oracle_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
+int oracle_get_threads(void) { return g_threads; }
 
 typedef struct {
     int32_t dim;       /* 2 or 3 */
@@ -369,21 +379,16 @@ static void skew_from_rotation(int d, const double *omega, double *C)
  * Grid arrays are overwritten (zeroed first).  Particles are visited in
  * ascending order.  dp_out, when non-NULL, receives D_p (d*d per particle).
  */
-int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *v,
-               const double *B, const double *F, const double *m, const double *V,
-               int model, double mu, double lam, int transfer,
-               double *gm, double *gmv, double *gf, double *dp_out)
+/* Adds the contributions of particles [p0, p1), in ascending order, to the
+ * grid arrays (which the caller zeroed). */
+static int p2g_range(const oracle_grid *g, int64_t p0, int64_t p1, const double *x, const double *v,
+                     const double *B, const double *F, const double *m, const double *V,
+                     int model, double mu, double lam, int transfer,
+                     double *gm, double *gmv, double *gf, double *dp_out)
 {
     const int d = g->dim;
-    if (d < 2 || d > 3 || g->degree < 1 || g->degree > 3 || !(g->dx > 0.0)) return OR_E_ARG;
-    if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
-    if (g->degree == 1 && transfer != OR_TRANSFER_APIC) return OR_E_ARG;
-    const int64_t nn = node_count(g);
-    memset(gm, 0, sizeof(double) * nn);
-    memset(gmv, 0, sizeof(double) * nn * d);
-    if (gf) memset(gf, 0, sizeof(double) * nn * d);
     stencil_entry st[MAX_STENCIL];
-    for (int64_t p = 0; p < np; ++p) {
+    for (int64_t p = p0; p < p1; ++p) {
         const double *xp = x + p * d;
         int cnt = particle_stencil(g, xp, st);
         if (cnt < 0) return cnt;
@@ -436,6 +441,59 @@ int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *
         }
     }
     return OR_OK;
+}
+
+int oracle_p2g(const oracle_grid *g, int64_t np, const double *x, const double *v,
+               const double *B, const double *F, const double *m, const double *V,
+               int model, double mu, double lam, int transfer,
+               double *gm, double *gmv, double *gf, double *dp_out)
+{
+    const int d = g->dim;
+    if (d < 2 || d > 3 || g->degree < 1 || g->degree > 3 || !(g->dx > 0.0)) return OR_E_ARG;
+    if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
+    if (g->degree == 1 && transfer != OR_TRANSFER_APIC) return OR_E_ARG;
+    const int64_t nn = node_count(g);
+    memset(gm, 0, sizeof(double) * nn);
+    memset(gmv, 0, sizeof(double) * nn * d);
+    if (gf) memset(gf, 0, sizeof(double) * nn * d);
+    const int T = g_threads;
+    if (T <= 1 || np < 2)
+        return p2g_range(g, 0, np, x, v, B, F, m, V, model, mu, lam, transfer, gm, gmv, gf, dp_out);
+    /* T threads: thread t adds the contiguous particle range
+     * [t np / T, (t+1) np / T) into a grid of its own; the grids are then
+     * summed in thread order, so the result depends on T only through the
+     * grouping of the sums. */
+    const int64_t per = nn * (1 + 2 * d);
+    double *priv = (double *)calloc((size_t)T * (size_t)per, sizeof(double));
+    int *rcs = (int *)calloc((size_t)T, sizeof(int));
+    if (!priv || !rcs) {
+        free(priv);
+        free(rcs);
+        return OR_E_NOMEM;
+    }
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+    for (int t = 0; t < T; ++t) {
+        double *pm = priv + (int64_t)t * per, *pmv = pm + nn, *pf = pmv + nn * d;
+        rcs[t] = p2g_range(g, np * t / T, np * (t + 1) / T, x, v, B, F, m, V, model, mu, lam, transfer, pm,
+                           pmv, gf ? pf : NULL, dp_out);
+    }
+    int rc = OR_OK;
+    for (int t = 0; t < T && rc == OR_OK; ++t) rc = rcs[t];
+    if (rc == OR_OK) {
+#pragma omp parallel for num_threads(T) schedule(static)
+        for (int64_t i = 0; i < nn; ++i)
+            for (int t = 0; t < T; ++t) {
+                const double *pm = priv + (int64_t)t * per, *pmv = pm + nn, *pf = pmv + nn * d;
+                gm[i] += pm[i];
+                for (int a = 0; a < d; ++a) {
+                    gmv[i * d + a] += pmv[i * d + a];
+                    if (gf) gf[i * d + a] += pf[i * d + a];
+                }
+            }
+    }
+    free(priv);
+    free(rcs);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -511,11 +569,24 @@ int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *
     const int d = g->dim;
     if (transfer < OR_TRANSFER_APIC || transfer > OR_TRANSFER_PIC) return OR_E_ARG;
     if (g->degree == 1 && transfer != OR_TRANSFER_APIC) return OR_E_ARG;
-    stencil_entry st[MAX_STENCIL];
+    /* particles are independent: with several threads each takes a block
+     * of them and the results are the same bits as with one; the error of
+     * the lowest failing particle is returned */
+    int64_t bad = np;
+    int bad_rc = OR_OK;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t p = 0; p < np; ++p) {
+        stencil_entry st[MAX_STENCIL];
         const double *xp = x + p * d;
         int cnt = particle_stencil(g, xp, st);
-        if (cnt < 0) return cnt;
+        if (cnt < 0) {
+#pragma omp critical(oracle_g2p_err)
+            if (p < bad) {
+                bad = p;
+                bad_rc = cnt;
+            }
+            continue;
+        }
         double vn[3] = {0, 0, 0}, xn[3] = {0, 0, 0}, Bn[9] = {0}, G[9] = {0};
         for (int j = 0; j < cnt; ++j) {
             const stencil_entry *e = &st[j];
@@ -552,7 +623,14 @@ int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *
                     for (int c = 0; c < d; ++c) D[r * d + c] += e->w * r3[r] * r3[c];
             }
             int rc = mat_inverse(3, K, Kinv, NULL);
-            if (rc != OR_OK) return rc;
+            if (rc != OR_OK) {
+#pragma omp critical(oracle_g2p_err)
+                if (p < bad) {
+                    bad = p;
+                    bad_rc = rc;
+                }
+                continue;
+            }
             double omega[3] = {0, 0, 0};
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) omega[a] += Kinv[a * 3 + b] * l[b];
@@ -579,7 +657,7 @@ int oracle_g2p(const oracle_grid *g, int64_t np, const double *x, const double *
             F_out[p * d * d + k] = Fn[k];
         }
     }
-    return OR_OK;
+    return bad < np ? bad_rc : OR_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -37,7 +37,7 @@ APIC_OPT_ADAPTIVE_DT = 4
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
 APIC_FLAG_UNSORTED = 16
 APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
-APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW = 0, 1, 2
+APIC_DIAG_PARTICLES, APIC_DIAG_GRID, APIC_DIAG_GRID_NEW, APIC_DIAG_ENERGY = 0, 1, 2, 3
 
 EXPORTED = [
     "apic_workspace_bytes", "apic_reset", "apic_sort", "apic_p2g", "apic_grid_update", "apic_g2p", "apic_step",

@@ -459,7 +459,7 @@ SceneState &state_of(const apic_scene *s, int64_t cap, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Typed operations
 // ---------------------------------------------------------------------------
-enum class Op { Sort, P2G, GridUpdate, G2P, Export, DiagParticles, DiagGrid, Cfl, Pack, Unpack };
+enum class Op { Sort, P2G, GridUpdate, G2P, Export, DiagParticles, DiagEnergy, DiagGrid, Cfl, Pack, Unpack };
 
 struct OpArgs {
     void *ptr;
@@ -579,6 +579,10 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
         case Op::DiagParticles:
             launch_diag_particles<T, DIM>(v.user, s->grid.dx, s->grid.degree != APIC_MULTILINEAR, v.diag_part,
                                           v.diag_out, st);
+            break;
+        case Op::DiagEnergy:
+            launch_diag_energy<T, DIM>(v.user, s->prm.model, s->prm.mu, s->prm.lambda, s->prm.rho0, v.diag_part,
+                                       v.diag_out, st);
             break;
         case Op::Cfl:
             launch_cfl_bound<T, DIM>(v.user, cfl_factor(s->grid), v.diag_part, v.diag_out, st);
@@ -1001,6 +1005,8 @@ apic_status apic_diagnostics(const apic_scene *scene, int32_t which, double *out
     apic_status rc;
     if (which == APIC_DIAG_PARTICLES)
         rc = dispatch(Op::DiagParticles, scene, stream);
+    else if (which == APIC_DIAG_ENERGY)
+        rc = dispatch(Op::DiagEnergy, scene, stream);
     else if (which == APIC_DIAG_GRID || which == APIC_DIAG_GRID_NEW)
         rc = dispatch(Op::DiagGrid, scene, stream, OpArgs{nullptr, which});
     else
@@ -1142,7 +1148,7 @@ const char *apic_version(void) { return "libapic 0.2 (gfx950)"; }
 namespace {
 
 struct MidLayout {
-    size_t gm, mf, gv, dv, dvt, f, r, rc, pv, s, delta, part, out, flags;
+    size_t gm, mf, gv, dv, dvt, f, r, rc, pv, s, delta, part, out, flags, tflags;
     size_t key, perm, count, cursor, start, bsum, scell, soff, sF, sm, smv, sM, total;
     int64_t nodes, nblk;
 };
@@ -1177,6 +1183,7 @@ MidLayout mid_layout(const apic_grid_desc &g, int64_t n) {
     L.part = take((size_t)L.nblk * 2 * sizeof(double));
     L.out = take(4 * sizeof(double));
     L.flags = take(sizeof(uint32_t));
+    L.tflags = take(sizeof(uint32_t));
     // particles sorted by base node
     const size_t np = (size_t)std::max<int64_t>(n, 1);
     L.key = take(np * 4);
@@ -1210,6 +1217,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     double *sv = (double *)(ws + L.s), *delta = (double *)(ws + L.delta), *part = (double *)(ws + L.part);
     double *out = (double *)(ws + L.out);
     uint32_t *flags = (uint32_t *)(ws + L.flags);
+    uint32_t *tflags = (uint32_t *)(ws + L.tflags);  // flags of the iterate being tried
 
     MidGrid g{};
     for (int a = 0; a < 3; ++a) g.N[a] = a < DIM ? s->grid.cells[a] + 1 : 1;
@@ -1257,11 +1265,13 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
         rc0 = hip_check(hipMemcpyAsync(host, out, K * sizeof(double), hipMemcpyDeviceToHost, st), "apic_step_midpoint");
         if (rc0 == APIC_OK) rc0 = hip_check(hipStreamSynchronize(st), "apic_step_midpoint");
     };
-    // E(dv) and |r|_M with r written to `r` (Sec. 4.1)
+    // E(dv) and |r|_M with r written to `r` (Sec. 4.1); an inverted element
+    // makes E infinite and raises its flag in tflags
     auto eval = [&](const double *dvx, double &E, double &res) {
         double phi = 0.0;
+        launch_fill<uint32_t>(tflags, 1, 0u, st);
         if (elastic) {
-            launch_mid_stress<DIM, DEG, false>(S, g, mat, gv, dvx, dt, nullptr, part, flags, st);
+            launch_mid_stress<DIM, DEG, false>(S, g, mat, gv, dvx, dt, nullptr, part, tflags, st);
             read(pb, 1);
             phi = host[0];
             launch_mid_collect_force<DIM, DEG>(S, g, f, st);
@@ -1286,6 +1296,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
         launch_mid_fill(dv, nv, 0.0, st);
         double E = 0.0, res = 0.0;
         eval(dv, E, res);
+        launch_mid_flags_accept(flags, tflags, st);
         const double res0 = res;
         int it = 0;
         for (; it < o.max_newton && rc0 == APIC_OK; ++it) {
@@ -1315,15 +1326,17 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
                 gamma = kappa;
             }
             // backtracking line search: E must not increase, or |r|_M must
-            // fall (near the minimum E is flat to within its rounding)
+            // fall (near the minimum E is flat to within its rounding); a
+            // trial that inverts an element has E = +inf and is halved
             double stepl = 1.0, En = 0.0, resn = 0.0;
             for (int k = 0; k < 30 && rc0 == APIC_OK; ++k) {
                 launch_mid_axpy(nv, dv, stepl, delta, dvt, st);
                 eval(dvt, En, resn);
-                if (En <= E || resn < res || k == 29) break;
+                if ((isfinite(En) && (En <= E || resn < res)) || k == 29) break;
                 stepl *= 0.5;
                 stats->halvings += 1;
             }
+            launch_mid_flags_accept(flags, tflags, st);
             std::swap(dv, dvt);
             E = En;
             res = resn;

@@ -125,6 +125,12 @@ template <typename T, int DIM>
 void launch_diag_particles(const Parts<T> &P, double dx, bool affine, double *partials, double *out,
                            hipStream_t st);
 
+// Kinetic and neo-Hookean potential energy of the particles in binary64:
+// out[0] T, out[1] Phi (0 for model 0), out[2] T + Phi, out[7] mass.
+template <typename T, int DIM>
+void launch_diag_energy(const Parts<T> &P, int model, double mu, double lam, double rho0, double *partials,
+                        double *out, hipStream_t st);
+
 // max_p (|v_p| + c |B_p|_F) in binary64 into out[0] (Sec. 4.3; c from the
 // grid's degree and dx).
 template <typename T, int DIM>
@@ -181,6 +187,7 @@ struct MidMaterial {
 void launch_mid_fill(double *a, int64_t n, double val, hipStream_t st);
 void launch_mid_reduce(const double *part, int64_t nblk, int K, double *out, hipStream_t st);
 void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, double *out, hipStream_t st);
+void launch_mid_flags_accept(uint32_t *flags, uint32_t *trial, hipStream_t st);
 int64_t mid_particle_blocks(int64_t n);
 int64_t mid_node_blocks(int64_t nodes);
 int64_t mid_scan_blocks(int64_t nodes);

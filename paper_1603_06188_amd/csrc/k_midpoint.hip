@@ -723,6 +723,19 @@ void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, 
     if (n > 0) k_mid_axpy<<<blocks_for(n), kMidBlock, 0, st>>>(n, a, alpha, b, out);
 }
 
+// flags |= trial, trial = 0: the flag bits of the iterate the line search
+// accepted join the call's flags (rejected trials leave none).
+__global__ void k_mid_flags_accept(uint32_t *flags, uint32_t *trial) {
+    if (threadIdx.x == 0) {
+        flags[0] |= trial[0];
+        trial[0] = 0u;
+    }
+}
+
+void launch_mid_flags_accept(uint32_t *flags, uint32_t *trial, hipStream_t st) {
+    k_mid_flags_accept<<<1, 64, 0, st>>>(flags, trial);
+}
+
 int64_t mid_particle_blocks(int64_t n) { return blocks_for(n); }
 int64_t mid_node_blocks(int64_t nodes) { return blocks_for(nodes); }
 int64_t mid_scan_blocks(int64_t nodes) { return (nodes + 1023) / 1024; }

@@ -130,6 +130,60 @@ void launch_diag_particles(const Parts<T> &P, double dx, bool affine, double *pa
     launch_diag_final(partials, nb, out, st);
 }
 
+// --- binary64 energies (Sec. 3.1 kinetic, Sec. 3.3 potential) -------------
+// acc[0] = 1/2 sum m |v|^2, acc[1] = Phi = sum V_p Psi(F_p) with the
+// neo-Hookean density Psi = mu/2 (tr F^T F - d) - mu ln J + lambda/2 (ln J)^2
+// (V_p = m_p / rho0; 0 without a model; +inf for det F <= 0), acc[2] their
+// sum, acc[7] the mass.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_diag_energy(Parts<T> P, int model, double mu, double lam, double inv_rho0,
+                                                     double *partials) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += (int64_t)gridDim.x * blockDim.x) {
+        const double m = (double)P.m[p];
+        double v2 = 0.0;
+        for (int a = 0; a < DIM; ++a) {
+            const double x = (double)P.v[a * P.s + p];
+            v2 += x * x;
+        }
+        const double ke = 0.5 * m * v2;
+        double phi = 0.0;
+        if (model == APIC_MODEL_NEO_HOOKEAN) {
+            double F[DIM * DIM], tr = 0.0;
+            for (int k = 0; k < DIM * DIM; ++k) {
+                F[k] = (double)P.F[k * P.s + p];
+                tr += F[k] * F[k];
+            }
+            double J;
+            if constexpr (DIM == 3)
+                J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                    F[2] * (F[3] * F[7] - F[4] * F[6]);
+            else
+                J = F[0] * F[3] - F[1] * F[2];
+            if (J > 0.0) {
+                const double lj = log(J);
+                phi = m * inv_rho0 * (0.5 * mu * (tr - (double)DIM) - mu * lj + 0.5 * lam * lj * lj);
+            } else {
+                phi = INFINITY;
+            }
+        }
+        acc[0] += ke;
+        acc[1] += phi;
+        acc[2] += ke + phi;
+        acc[7] += m;
+    }
+    block_reduce8p(acc, partials);
+}
+
+template <typename T, int DIM>
+void launch_diag_energy(const Parts<T> &P, int model, double mu, double lam, double rho0, double *partials,
+                        double *out, hipStream_t st) {
+    const int nb = blocks_for(P.n, 256, kDiagBlocks);
+    hipLaunchKernelGGL((k_diag_energy<T, DIM>), dim3(nb), dim3(256), 0, st, P, model, mu, lam,
+                       rho0 > 0.0 ? 1.0 / rho0 : 0.0, partials);
+    launch_diag_final(partials, nb, out, st);
+}
+
 // --- CFL bound (Sec. 4.3) -----------------------------------------------------------
 // max_p (|v_p| + c |B_p|_F), c = 6 sqrt(d) / dx, in binary64: per block into
 // partials[block], then one block reduces them into out[0].
@@ -298,6 +352,8 @@ void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_
 #define APIC_MISC_INST(T, DIM)                                                                                  \
     template void launch_copy_state<T, DIM>(const Parts<T> &, const Parts<T> &, hipStream_t);                    \
     template void launch_diag_particles<T, DIM>(const Parts<T> &, double, bool, double *, double *, hipStream_t); \
+    template void launch_diag_energy<T, DIM>(const Parts<T> &, int, double, double, double, double *, double *,    \
+                                             hipStream_t);                                                     \
     template void launch_cfl_bound<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);         \
     template int launch_cfl_partials<T, DIM>(const Parts<T> &, double, double *, hipStream_t);                  \
     template void launch_keep_affine<T, DIM>(const Parts<T> &, int, hipStream_t);                                \

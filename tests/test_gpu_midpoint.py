@@ -192,3 +192,22 @@ def test_particle_outside_the_grid_is_flagged_and_left_alone():
                              s.dt, s.gravity, s.band, newton_tol=SOLVER["newton_tol"], cg_tol=SOLVER["cg_tol"])
     rest = {k: got[k][1:] for k in ("x", "v", "B", "F")}
     _compare(rest, r["x_new"], r["v_new"], r["B_new"], r["F_new"], s.dx, TOL, "midpoint with an outside particle")
+
+
+def test_line_search_halvings_match_oracle():
+    """The implosion of the oracle's line-search pin: full Newton steps that
+    would invert elements are halved on both sides (an inverted trial has
+    infinite energy and is never accepted), no flag is raised, and the
+    converged state matches the oracle's."""
+    from tests.test_oracle_midpoint import implosion_scene
+    s = implosion_scene()
+    opts = dict(newton_tol=1e-10, cg_tol=1e-8, max_newton=30, max_cg=500)
+    ds = _b().DeviceScene(s, midpoint=True)
+    st = ds.step_midpoint(1, **opts)
+    r = oracle.midpoint_step(ogrid(s), s.x, s.v, s.B, s.F, s.m, s.V, 1, s.mu, s.lam, s.dt, **opts)
+    print(st, r["stats"], flush=True)
+    assert r["stats"]["halvings"] > 0
+    assert st["halvings"] > 0
+    assert st["converged"] == 1 and st["flags"] == 0
+    # both sides stop at |r|_M <= 1e-10 |r_0|_M: the states agree to that level
+    _compare(ds.state(), r["x_new"], r["v_new"], r["B_new"], r["F_new"], s.dx, 1e-9, "implosion")

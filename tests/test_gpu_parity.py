@@ -39,8 +39,11 @@ def compare_step(s, ds, tol, check_grid=True, label=""):
     b = _b()
     g = ogrid(s)
     ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
-    ds.p2g()
     errs = {}
+    # kinetic energy of the input state (Sec. 3.1): the same numbers on both sides
+    ke = oracle.particle_totals(s.x, s.v, s.B, s.m)[6]
+    errs["KE_in"] = rel(ds.diagnostics(b.APIC_DIAG_PARTICLES)[6], ke)
+    ds.p2g()
     if check_grid:
         m = ds.export(b.APIC_GRID_MASS)
         mv = ds.export(b.APIC_GRID_MOMENTUM)
@@ -196,6 +199,12 @@ def test_disk2d_fp64_ten_round_trips():
         for key, a, bb in (("v", got["v"], ref["v_new"]), ("B", got["B"], ref["B_new"])):
             assert rel(a, bb) <= 1e-12, (k, key, rel(a, bb))
         assert np.abs(got["x"] - s.x).max() == 0.0
+        # kinetic energy (Sec. 3.1): particles before, grid, particles after
+        t_g = oracle.grid_totals(g, ref["m"], ref["v"])
+        t_p1 = oracle.particle_totals(ref["x_new"], ref["v_new"], ref["B_new"], s.m)
+        assert pd[6] == pytest.approx(t_p[6], rel=1e-13), k
+        assert gd[6] == pytest.approx(t_g[6], rel=1e-12), k
+        assert pd1[6] == pytest.approx(t_p1[6], rel=1e-12), k
         # conservation per transfer (Sec. 5.2, 5.3): particles -> grid -> particles
         for t in (gd, pd1):
             assert np.abs(t[:2] - t_p[:2]).max() <= 1e-12 * scale
@@ -340,3 +349,53 @@ def test_cfl_dt_matches_oracle(precision):
         ds.cfl_dt(0.0)
     rest = b.DeviceScene(s.with_state(v=0 * s.v, B=0 * s.B))
     assert rest.cfl_dt() == float("inf")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_energy_diagnostics_match_oracle(precision):
+    """APIC_DIAG_ENERGY on the small elastic cube: kinetic energy (Sec. 3.1)
+    and neo-Hookean potential Phi = sum V_p Psi(F_p) (Sec. 3.3) of the input
+    state (both sides reduce the same numbers in binary64: 1e-12), then of
+    the state after one step against the oracle's step (binary64: 1e-11;
+    binary32: the first-order effect of the 1e-5 per-field bar on T and on
+    Phi through P:dF).  The sticky band and gravity are on."""
+    b = _b()
+    s = scenes.cube3d(cells=24, precision=precision, steps=1)
+    rng = np.random.default_rng(9)
+    F = s.F + 0.02 * rng.normal(size=s.F.shape)            # stressed: Phi > 0
+    if precision == "fp32":
+        F = F.astype(np.float32).astype(np.float64)
+    s = s.with_state(F=F)
+    ds = b.DeviceScene(s)
+    e0 = ds.diagnostics(b.APIC_DIAG_ENERGY)
+    T0 = oracle.particle_totals(s.x, s.v, s.B, s.m)[6]
+    P0 = oracle.potential(s.F, s.V, s.mu, s.lam)
+    assert P0 > 0.0
+    assert e0[0] == pytest.approx(T0, rel=1e-12)
+    assert e0[1] == pytest.approx(P0, rel=1e-12)
+    assert e0[2] == pytest.approx(T0 + P0, rel=1e-12)
+    assert e0[7] == pytest.approx(float(s.m.sum()), rel=1e-13)
+    ref = oracle.step(ogrid(s), s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band)
+    ds.step(1)
+    assert ds.flags() == 0
+    e1 = ds.diagnostics(b.APIC_DIAG_ENERGY)
+    T1 = oracle.particle_totals(ref["x_new"], ref["v_new"], ref["B_new"], s.m)[6]
+    P1 = oracle.potential(ref["F_new"], s.V, s.mu, s.lam)
+    if precision == "fp64":
+        tol_t, tol_p = 1e-11 * T1, 1e-11 * P1
+    else:
+        vn = np.linalg.norm(ref["v_new"], axis=1)
+        tol_t = 2 * TOL["fp32"] * float(np.abs(ref["v_new"]).max()) * float(np.sum(s.m * vn)) * np.sqrt(3)
+        Pn = np.array([np.linalg.norm(oracle.neo_hookean_P(Fp, s.mu, s.lam)) for Fp in ref["F_new"]])
+        tol_p = 2 * TOL["fp32"] * float(np.abs(ref["F_new"]).max()) * float(np.sum(s.V * Pn)) * 3
+    assert abs(e1[0] - T1) <= tol_t, (e1[0], T1, tol_t)
+    assert abs(e1[1] - P1) <= tol_p, (e1[1], P1, tol_p)
+    # no model: no potential
+    s0 = dataclasses_replace(s, model=0)
+    ds0 = b.DeviceScene(s0)
+    assert ds0.diagnostics(b.APIC_DIAG_ENERGY)[1] == 0.0
+
+
+def dataclasses_replace(s, **kw):
+    import dataclasses
+    return dataclasses.replace(s, **kw)

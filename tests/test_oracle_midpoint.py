@@ -12,14 +12,20 @@ of the oracle's own formulas:
   lambda family conserves both, Sec. 3.3; the proof in Sec. 5);
 * constant acceleration integrated exactly (model without force);
 * the midpoint and the symplectic-Euler step agree to O(dt^2);
-* sticky nodes do not move.
+* sticky nodes do not move;
+* an implosion whose full Newton steps would invert elements: the line
+  search halves them (an inverted trial has infinite energy) and the step
+  still solves the midpoint equations.
 """
 import numpy as np
 import pytest
 
 import oracle
 from paper_1603_06188_amd import scenes
-from tests.test_gpu_parity import ogrid
+
+
+def ogrid(s):
+    return oracle.Grid(s.dim, s.degree, s.cells, s.dx)
 
 
 def _scene(dim=3, degree=2, n=400, seed=3, cells=8, **kw):
@@ -152,3 +158,31 @@ def test_sticky_band_nodes_stay_put():
     assert (sticky & (r["m"] > 0)).any()
     assert not r["vt"][sticky].any()
     np.testing.assert_array_equal(r["xt"][sticky], g.node_positions()[sticky])
+
+
+def implosion_scene(E=1e2, rate=10.0, dt=0.1):
+    """2D particles collapsing toward the centre (v = -rate (x - c)) on a
+    soft material with a large step: the first Newton steps overshoot into
+    inverted elements."""
+    import dataclasses
+    s = _scene(2, 2, n=300, cells=8, seed=3, vel_sigma=0.5, f_sigma=0.05, E=E)
+    s = s.with_state(v=-rate * (s.x - np.array([0.5, 0.5])))
+    return dataclasses.replace(s, dt=dt)
+
+
+def test_line_search_halves_inverted_trials_and_the_step_still_solves():
+    s = implosion_scene()
+    g = ogrid(s)
+    r = oracle.midpoint_step(g, s.x, s.v, s.B, s.F, s.m, s.V, 1, s.mu, s.lam, s.dt, newton_tol=1e-10,
+                             cg_tol=1e-8, max_newton=30, max_cg=500)
+    st = r["stats"]
+    assert st["halvings"] > 0
+    assert st["res"] <= 1e-10 * st["res0"]
+    xi = g.node_positions()
+    f, _ = oracle.forces_at(g, s.x, s.F, s.V, s.mu, s.lam, 0.5 * (r["xt"] - xi))
+    free = r["m"] > 0
+    lhs = r["m"][free, None] * (r["vt"][free] - r["v"][free])
+    rhs = s.dt * f[free]
+    assert np.abs(lhs - rhs).max() <= 1e-9 * np.abs(rhs).max()
+    assert (np.linalg.det(r["F_new"]) > 0).all()
+
