@@ -91,7 +91,7 @@ def _host_threads() -> int:
     return max(n, 1)
 
 
-def cpu_baseline(scene, budget_s: float = 10.0, max_steps: int = 5):
+def cpu_baseline(scene, budget_s: float = 12.0, max_steps: int = 40):
     """Time the FP64 oracle on the full particle set of the workload: on all
     the host cores this job has (particles split into blocks, private grids
     summed in thread order) for as many steps as fit in about budget_s, and

@@ -58,7 +58,7 @@ struct Layout {
     int64_t rc;     // record (slab) capacity: min(tiles, cap)
     int64_t rcap;   // list capacity per bucket: ceil(tiles / kBuckets)
     int64_t slab_stride;
-    size_t o_vt, o_flags, o_vmax, o_cfl, o_dt, o_diag_out, o_diag_part, o_key_count, o_scount;
+    size_t o_vt, o_uref, o_nref, o_flags, o_vmax, o_cfl, o_dt, o_diag_out, o_diag_part, o_key_count, o_scount;
     ListOff lists[2];
     TabOff tabs[2];
     size_t o_slabs;
@@ -101,6 +101,8 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         return at;
     };
     L.o_vt = take(dim * G * e);
+    L.o_uref = take(dim * TT * e);
+    L.o_nref = take(dim * TT * e);
     L.o_flags = take(64);
     L.o_vmax = take((size_t)kVmaxSlots * 4);
     L.o_cfl = take((size_t)kVmaxSlots * 8);
@@ -393,6 +395,8 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.slabs.v = (T *)(w + L.o_slabs);
     v.slabs.stride = L.slab_stride;
     v.g.vt = (T *)(w + L.o_vt);
+    v.g.uref = (T *)(w + L.o_uref);
+    v.g.nref = (T *)(w + L.o_nref);
     v.g.flags = (uint32_t *)(w + L.o_flags);
     v.g.vmax = (uint32_t *)(w + L.o_vmax);
     v.g.cfl = nullptr;

@@ -40,7 +40,7 @@ namespace apic {
 constexpr int kBuckets = 1024;   // 4 per thread of a 256-thread block
 constexpr int kMaxLevels = 32;
 constexpr int kVmaxSlots = 1024;
-constexpr int kKeyChunks = 8;     // key pass: chunks of 64 particles loaded together
+constexpr int kKeyChunks = 4;     // key pass: chunks of 64 particles loaded together
 
 struct GridDims {
     int dim, deg;
@@ -104,9 +104,35 @@ struct Slabs {
     int64_t stride;     // elements per record
 };
 
+// Velocities on the grid are carried relative to reference velocities:
+// every listed key tile t has one, uref[t] (chosen by the transfer to grid
+// that forms its slab), and the slab holds m_i and sum w m_p (v_p - uref[t])
+// + ...; every node tile tau updated by the grid update has one, nref[tau]
+// (the reference of the first listed key tile whose slab covers it), and vt
+// holds vt_i - nref[tau].  References are multiples of kRefQuantum below
+// kRefMax in magnitude, so their sums and differences are exact in binary32
+// and the rounding of the sums scales with |v - reference| instead of |v|
+// (a body that moves fast as a whole keeps the digits of its velocity
+// differences, which B and grad v are made of).  Mathematically nothing
+// changes: every reference is added back exactly where the velocity is used.
+constexpr float kRefQuantum = 1.0f / 1024.0f;
+constexpr float kRefMax = 4096.0f;
+
+__device__ __forceinline__ float rint_t(float x) { return __builtin_rintf(x); }
+__device__ __forceinline__ double rint_t(double x) { return __builtin_rint(x); }
+
+// Reference velocity from a velocity: rounded to a multiple of kRefQuantum;
+// 0 when not finite or not below kRefMax in magnitude.
+template <typename T>
+__device__ __forceinline__ T quantize_ref(T x) {
+    return (x == x && x < T(kRefMax) && x > -T(kRefMax)) ? rint_t(x * T(1024)) * T(kRefQuantum) : T(0);
+}
+
 template <typename T>
 struct GridState {
-    T *vt;              // dim planes of G nodes: updated velocity
+    T *vt;              // dim planes of G nodes: updated velocity minus nref of its node tile
+    T *uref;            // dim planes of `tiles`: reference velocity of each listed key tile
+    T *nref;            // dim planes of `tiles`: reference velocity of each updated node tile
     uint32_t *flags;
     uint32_t *vmax;     // [kVmaxSlots] binary32 bits; their max bounds max_i |vt_i|
     // [kVmaxSlots] binary64 bits; the transfer to particles raises them to
@@ -398,6 +424,17 @@ __device__ __forceinline__ double floor_t<double>(double x) { return floor(x); }
 
 // wave64 helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+// A value that is the same on every lane, held once per wavefront (scalar
+// register) instead of once per lane.
+__device__ __forceinline__ float wave_uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double wave_uniform(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }

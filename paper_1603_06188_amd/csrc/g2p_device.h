@@ -54,16 +54,18 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 // about 1/9 (cubic), so c is never far out of scale with v: a corner node
 // can have a weight near zero and, if nothing else reaches it, a velocity
 // thousands of times larger than v, whose rounding would then dominate v.
+// The staged values are relative to the key tile's reference velocity uref
+// (see stage_velocities), which is added last: v_k = uref_k + (c_k + sum).
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], const T (&w)[DIM][DEG + 1],
-                                                 const T *cref, T *vn) {
+                                                 const T *cref, const T *uref, T *vn) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < DEG + 1; ++a) s = fma_t(w[0][a], tx[k][a], s);
-        vn[k] = cref[k] + s;
+        vn[k] = uref[k] + (cref[k] + s);
     }
 }
 
@@ -197,8 +199,12 @@ struct VtRegion {
     __device__ static constexpr int at(int x, int y, int z) { return x + SY * y + SZ * z; }
 };
 
+// Staged values are relative to the reference velocity uref of key tile t
+// (its own reference, also that of the node tile t): node tile tau holds
+// vt - nref[tau], to which nref[tau] - uref (exact) is added; a node tile
+// outside the grid stages vt = 0.
 template <typename T, int DIM>
-__device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> &g, T *reg) {
+__device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> &g, const T *uref, T *reg) {
     using R = VtRegion<DIM>;
     constexpr int TE = DIM == 3 ? 4 : 8;
     const int lane = lane_id();
@@ -227,8 +233,19 @@ __device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> 
         }
         const int idx = R::at(rc[0], rc[1], rc[2]);
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) reg[k * R::SIZE + idx] = ok ? g.vt[k * G + tau * 64 + lane] : T(0);
+        for (int k = 0; k < DIM; ++k) {
+            const T shift = ok ? wave_uniform(g.nref[k * g.d.tiles + tau]) - uref[k] : -uref[k];
+            reg[k * R::SIZE + idx] = ok ? g.vt[k * G + tau * 64 + lane] + shift : shift;
+        }
     }
+}
+
+// Reference velocity of key tile t (t is the same on every lane; the values
+// are kept once per wavefront).
+template <typename T, int DIM>
+__device__ __forceinline__ void tile_uref(uint32_t t, const GridState<T> &g, T *uref) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) uref[k] = wave_uniform(g.uref[k * g.d.tiles + t]);
 }
 
 // Occupancy target: binary32 quadratic 3D fits 128 registers (4 waves per
@@ -268,8 +285,8 @@ __device__ __forceinline__ void g2p_load(const Parts<T> &src, uint32_t p, G2PRaw
 // B keeps the part of the affine field the transfer carries (APIC_TRANSFER_*).
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *reg, const int *origin,
-                                           const GridState<T> &g, T dt_inv_dx, T gs, int *lk, int *cn, T *on, T *vn,
-                                           T *Bs, T *Fn, int transfer) {
+                                           const T *uref, const GridState<T> &g, T dt_inv_dx, T gs, int *lk,
+                                           int *cn, T *on, T *vn, T *Bs, T *Fn, int transfer) {
     constexpr int K = DEG + 1;
     using R = VtRegion<DIM>;
     int ci[3] = {0, 0, 0};
@@ -328,7 +345,7 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
                     }
             }
     }
-    velocity_from_tx<T, DIM, DEG>(Tx, wf, cref, vn);
+    velocity_from_tx<T, DIM, DEG>(Tx, wf, cref, uref, vn);
     // B and grad v (cell units) from the axis sums; weight
     // derivatives and node offsets from the offsets
     T Gc[DIM * DIM];
@@ -399,7 +416,8 @@ __device__ __forceinline__ void carry_dead(const Parts<T> &src, const Parts<T> &
 // order, then velocity_from_tx -- the operation sequence of the G2P sweep,
 // so both give the same bits.
 template <typename T, int DIM, int DEG>
-__device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const T (&w)[DIM][DEG + 1], T *vn) {
+__device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const T (&w)[DIM][DEG + 1],
+                                             const T *uref, T *vn) {
 #pragma clang fp contract(off)
     constexpr int K = DEG + 1;
     using R = VtRegion<DIM>;
@@ -425,7 +443,7 @@ __device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const 
                     tx[k][a] = fma_t(wyz, reg[k * R::SIZE + idx] - cref[k], tx[k][a]);
             }
         }
-    velocity_from_tx<T, DIM, DEG>(tx, w, cref, vn);
+    velocity_from_tx<T, DIM, DEG>(tx, w, cref, uref, vn);
 }
 
 }  // namespace apic

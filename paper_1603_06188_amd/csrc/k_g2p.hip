@@ -44,7 +44,7 @@ template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<T> &g, const StepParams<T> &prm,
                                              const BinLists &nxt, const BinScratch &sc, const uint32_t *queue,
                                              uint32_t count, uint32_t t, const int *origin, const T *reg,
-                                             uint32_t *stay) {
+                                             const T *uref, uint32_t *stay) {
     const int lane = lane_id();
     const bool act = (uint32_t)lane < count;
     uint32_t nkey = kDeadKey, q = 0;
@@ -61,7 +61,7 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
             lk[a] = base[a] - origin[a];
         }
         const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(base);
-        velocity_lds<T, DIM, DEG>(reg, lk, w, vn);
+        velocity_lds<T, DIM, DEG>(reg, lk, w, uref, vn);
         bool cfl, finite;
         move_position<T, DIM>(ci, off, vn, prm.dt * g.inv_dx, cn, on, cfl);
         nkey = key_of<T, DIM, DEG>(cn, on, g.d, finite);
@@ -105,6 +105,8 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
         bool staged = false;  // grid velocities around the tile, on first use
+        T uref[DIM];
+        tile_uref<T, DIM>(t, g, uref);
         stay[lane] = 0u;
         wave_lds_sync();
         uint32_t queued = 0;
@@ -143,12 +145,12 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
             // the group's queued particles, 64 at a time
             for (uint32_t q0 = 0; q0 < queued; q0 += 64u) {
                 if (!staged) {
-                    stage_velocities<T, DIM>(t, g, reg);
+                    stage_velocities<T, DIM>(t, g, uref, reg);
                     staged = true;
                 }
                 wave_lds_sync();
                 const uint32_t take = queued - q0 < 64u ? queued - q0 : 64u;
-                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue + q0, take, t, origin, reg, stay);
+                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue + q0, take, t, origin, reg, uref, stay);
             }
             queued = 0;
             wave_lds_sync();
@@ -240,7 +242,9 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         const uint32_t t = tile_range(walk, r, cur, ctab, start, total);
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
-        stage_velocities<T, DIM>(t, g, reg);
+        T uref[DIM];
+        tile_uref<T, DIM>(t, g, uref);
+        stage_velocities<T, DIM>(t, g, uref, reg);
         // stayers of a key follow its movers in the new layout
         rankc[lane] = ntab.kmov[t * 64 + (uint32_t)lane];
         const uint32_t tbase = bases[bucket_of(t)];
@@ -256,7 +260,8 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 const uint32_t p = start + i;
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                 T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
-                g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
+                g2p_update<T, DIM, DEG>(raw, reg, origin, uref, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn,
+                                        prm.transfer);
                 const T *off = raw.off;
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);

@@ -74,9 +74,13 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
         const uint32_t t = tile_of_record(walk, r, cur, ctab, start, cnt, maxc, kstart);
         int origin[3] = {0, 0, 0};
         tile_origin<3>(t, g.d.TN, origin);
+        // the tile keeps its reference velocity: the slab this pass forms for
+        // the new layout holds momenta relative to the same uref[t]
+        T uref[3];
+        tile_uref<T, 3>(t, g, uref);
         if (producer) {
             // --- wavefront 0: G2P, write, hand the stayers over ---------------------
-            stage_velocities<T, 3>(t, g, L.vt);
+            stage_velocities<T, 3>(t, g, uref, L.vt);
             // stayers of a key follow its movers, in their old order
             uint32_t srank = ntab.kmov[t * 64 + (uint32_t)lane];
             const uint32_t tbase = bases[bucket_of(t)];
@@ -103,7 +107,8 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
                 if (cnt > j) {
                     int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                     T on[3], vn[3], Bs[9], Fn[9];
-                    g2p_update<T, 3, DEG>(raw, L.vt, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
+                    g2p_update<T, 3, DEG>(raw, L.vt, origin, uref, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn,
+                                          prm.transfer);
                     const uint32_t mykey = t * 64 + (uint32_t)local_of<3>(lk);
                     stays = keeps_key<T, 3, DEG>(raw.off, reach);
                     if (!stays) {
@@ -201,7 +206,7 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
                         pr.F[k] = h[16 + k][lane];
                     }
                     P2GParticle<T, 3, DEG> pp;
-                    if (p2g_prepare<T, 3, DEG>(pr, key, prm, g.inv_dx, g.flags, pp))
+                    if (p2g_prepare<T, 3, DEG>(pr, key, prm, g.inv_dx, g.flags, uref, pp))
                         p2g_accumulate3<T, DEG, 0, K>(pp, acc_m, acc_v);
                 }
             }
@@ -253,21 +258,30 @@ __device__ __forceinline__ void p2g_movers_body(const Parts<T> &P, const BinList
 #pragma unroll
         for (int a = 0; a < 3; ++a) key[a] += lcoord[a];
         T *slab = slabs.v + (int64_t)r * slabs.stride;
+        T uref[3];
         if (cur.tile_gen[t] == cur.gen) {
+            // listed before: its slab (stored by k_g2p2g) and its reference
             slab_load<T, 3, DEG, COMP>(slab, lds);
+            tile_uref<T, 3>(t, g, uref);
         } else {
+            // new in this layout (only movers): the reference of its movers
             for (int i = lane; i < LSLAB; i += 64) lds[i] = T(0);
+            tile_reference<T, 3>(P, start, kstart, mov, maxc, uref);
+            if (lane == 0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) g.uref[a * g.d.tiles + t] = uref[a];
+            }
         }
         wave_lds_sync();
         constexpr int CZ = p2g_slices<T, 3, DEG>();
         p2g_pass3<T, DEG, COMP, 0, CZ, true>(P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx,
-                                             g.flags, lds);
+                                             g.flags, uref, lds);
         if constexpr (CZ < K) p2g_pass3<T, DEG, COMP, CZ, (2 * CZ <= K ? CZ : K - CZ), true>(
-            P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx, g.flags, lds);
+            P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx, g.flags, uref, lds);
         if constexpr (2 * CZ < K) p2g_pass3<T, DEG, COMP, 2 * CZ, (3 * CZ <= K ? CZ : K - 2 * CZ), true>(
-            P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx, g.flags, lds);
+            P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx, g.flags, uref, lds);
         if constexpr (3 * CZ < K) p2g_pass3<T, DEG, COMP, 3 * CZ, K - 3 * CZ, true>(
-            P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx, g.flags, lds);
+            P, key, lcoord, start, kstart, cnt, maxc, mov, jend, prm, g.inv_dx, g.flags, uref, lds);
         slab_store<T, 3, DEG, COMP>(lds, slab);
         wave_lds_sync();
     }

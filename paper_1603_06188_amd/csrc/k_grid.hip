@@ -14,10 +14,12 @@ static inline int blocks_for(int64_t work, int threads, int cap) {
     return (int)b;
 }
 
-// Mass and momentum of node `nc`: out[0] = m, out[1..DIM] = (m v) + dt f.
+// Mass and momentum of node `nc`: out[0] = m, out[1..DIM] = (m v) + dt f
+// (each slab's momentum plus its mass times the reference velocity of its
+// key tile).
 template <typename T, int DIM, int DEG, bool COMP>
 __device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, const Slabs<T> &slabs,
-                                            const GridDims &d, T *out) {
+                                            const GridDims &d, const T *uref, T *out) {
     using Gm = Geo<DIM, DEG>;
     constexpr int TE = Gm::TE, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC;
     T hi[NC], lo[NC];
@@ -44,12 +46,14 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, c
         if (tag != gm.gen) continue;
         const int idx = DIM == 3 ? loc[0] + RE * (loc[1] + RE * loc[2]) : loc[0] + RE * loc[1];
         const T *s = slabs.v + (int64_t)rec * slabs.stride;
+        const T ms = s[idx], ms_lo = COMP ? s[NC * RN + idx] : T(0);
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const T x = s[k * RN + idx];
+            const T u = k == 0 ? T(0) : uref[(k - 1) * d.tiles + t];
+            const T x = s[k * RN + idx] + ms * u;
             if constexpr (COMP) {
                 const T sum = hi[k] + x;
-                lo[k] += two_sum_err(hi[k], x, sum) + s[(NC + k) * RN + idx];
+                lo[k] += two_sum_err(hi[k], x, sum) + (s[(NC + k) * RN + idx] + ms_lo * u);
                 hi[k] = sum;
             } else {
                 hi[k] += x;
@@ -105,10 +109,20 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
         }
         uint32_t rec = 0u;
         bool listed = false;
+        T ur[DIM];  // reference velocity of the key tile (read as is; used only when listed)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ur[a] = T(0);
         if (key_in) {
             listed = cur.tile_gen[k] == cur.gen;
             rec = cur.slot[k];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ur[a] = g.uref[a * g.d.tiles + k];
         }
+        // this wave's key tile t owns the node tiles it updates: their
+        // reference is t's (lane (0, 0) holds it)
+        T own[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) own[a] = wave_uniform(ur[a]);
         const uint64_t lmask = ballot(listed);
         const uint64_t nmask = ballot(node_in && my_e == 0);
         for (int c = 0; c < NCOR; ++c) {
@@ -130,13 +144,18 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
                 valid = valid && nc[a] < g.d.N[a];
                 sticky = sticky || nc[a] < prm.band[2 * a] || nc[a] > g.d.n[a] - prm.band[2 * a + 1];
             }
-            // sum of the covering slabs, e in increasing order
+            // sum of the covering slabs, e in increasing order, each slab's
+            // momentum moved to this node tile's reference (the difference of
+            // two references is exact)
             T hi[NC], lo[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) hi[q] = lo[q] = T(0);
 #pragma unroll
             for (int e = 0; e < NCOR; ++e) {
                 const uint32_t srec = __shfl(rec, c * NCOR + e, 64);
+                T du[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) du[a] = __shfl(ur[a], c * NCOR + e, 64) - own[a];
                 if (!((lst >> e) & 1u)) continue;
                 int loc[3] = {0, 0, 0};
                 bool ok = valid;
@@ -148,12 +167,14 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
                 if (!ok) continue;
                 const int idx = DIM == 3 ? loc[0] + RE * (loc[1] + RE * loc[2]) : loc[0] + RE * loc[1];
                 const T *sp = slabs.v + (int64_t)srec * slabs.stride;
+                const T ms = sp[idx], ms_lo = COMP ? sp[NC * RN + idx] : T(0);
 #pragma unroll
                 for (int q = 0; q < NC; ++q) {
-                    const T x = sp[q * RN + idx];
+                    const T u = q == 0 ? T(0) : du[q - 1];
+                    const T x = sp[q * RN + idx] + ms * u;
                     if constexpr (COMP) {
                         const T sum = hi[q] + x;
-                        lo[q] += two_sum_err(hi[q], x, sum) + sp[(NC + q) * RN + idx];
+                        lo[q] += two_sum_err(hi[q], x, sum) + (sp[(NC + q) * RN + idx] + ms_lo * u);
                         hi[q] = sum;
                     } else {
                         hi[q] += x;
@@ -166,13 +187,20 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
             const bool live = valid && mm[0] > T(0) && !sticky;
             const T inv_m = live ? T(1) / mm[0] : T(0);
             const int64_t node = tau * 64 + lane;
+            if (lane == 0) {
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) g.nref[a * g.d.tiles + tau] = own[a];
+            }
             float vabs = 0.f;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                const T vt = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : T(0);
+                // stored relative to the node tile's reference; vt = 0 (no mass,
+                // sticky) is -reference
+                const T vt = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : -own[a];
                 g.vt[a * G + node] = vt;
-                // binary32 value not below |vt| (NaN propagates as the largest bits)
-                const T va = vt < T(0) ? -vt : vt;
+                // binary32 value not below |vt + reference| (NaN propagates as the
+                // largest bits)
+                const T va = (vt < T(0) ? -vt : vt) + (own[a] < T(0) ? -own[a] : own[a]);
                 float f = (float)va;
                 if ((T)f < va) f = __uint_as_float(__float_as_uint(f) + 1u);  // next binary32 up
                 vabs = (f > vabs || f != f) ? f : vabs;
@@ -235,14 +263,15 @@ __global__ __launch_bounds__(256) void k_grid_export(BinLists gm, Slabs<T> slabs
             r /= g.d.N[a];
         }
         T mm[1 + DIM];
-        gather_node<T, DIM, DEG, COMP>(nc, gm, slabs, g.d, mm);
+        gather_node<T, DIM, DEG, COMP>(nc, gm, slabs, g.d, g.uref, mm);
         if (field == 0) {
             out[j] = mm[0];
         } else if (field == 1) {
             for (int a = 0; a < DIM; ++a) out[a * count + j] = mm[1 + a];
         } else {
-            const int64_t node = node_index<DIM>(nc, g.d.TN);
-            for (int a = 0; a < DIM; ++a) out[a * count + j] = mm[0] > T(0) ? g.vt[a * G + node] : T(0);
+            const int64_t node = node_index<DIM>(nc, g.d.TN), tau = node >> 6;
+            for (int a = 0; a < DIM; ++a)
+                out[a * count + j] = mm[0] > T(0) ? g.vt[a * G + node] + g.nref[a * g.d.tiles + tau] : T(0);
         }
     }
 }
@@ -290,17 +319,17 @@ __global__ __launch_bounds__(256) void k_diag_grid(BinLists gm, Slabs<T> slabs, 
             r /= g.d.N[a];
         }
         T mm[1 + DIM];
-        gather_node<T, DIM, DEG, COMP>(nc, gm, slabs, g.d, mm);
+        gather_node<T, DIM, DEG, COMP>(nc, gm, slabs, g.d, g.uref, mm);
         const double m = (double)mm[0];
         if (!(m > 0.0)) continue;
-        const int64_t node = node_index<DIM>(nc, g.d.TN);
+        const int64_t node = node_index<DIM>(nc, g.d.TN), tau = node >> 6;
         double x[3] = {0, 0, 0}, mv[3] = {0, 0, 0};
         for (int a = 0; a < DIM; ++a) {
             x[a] = (double)nc[a] * dx;
             if (which == 1) {
                 mv[a] = (double)mm[1 + a];
             } else {
-                const double vt = (double)g.vt[a * G + node];
+                const double vt = (double)g.vt[a * G + node] + (double)g.nref[a * g.d.tiles + tau];
                 mv[a] = m * vt;
                 x[a] += dt * vt;
             }

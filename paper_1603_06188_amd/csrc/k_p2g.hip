@@ -53,18 +53,25 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
         tile_origin<DIM>(t, g.d.TN, key);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) key[a] += lcoord[a];
+        // the tile's reference velocity: the slab holds momenta relative to it
+        T uref[DIM];
+        tile_reference<T, DIM>(P, start, kstart, cnt, maxc, uref);
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) g.uref[a * g.d.tiles + t] = uref[a];
+        }
         for (int i = lane; i < LSLAB; i += 64) lds[i] = T(0);
         wave_lds_sync();
         if constexpr (DIM == 3) {
             constexpr int CZ = p2g_slices<T, 3, DEG>();
             p2g_pass3<T, DEG, COMP, 0, CZ>(P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx,
-                                           g.flags, lds);
+                                           g.flags, uref, lds);
             if constexpr (CZ < K) p2g_pass3<T, DEG, COMP, CZ, (2 * CZ <= K ? CZ : K - CZ)>(
-                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, lds);
+                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
             if constexpr (2 * CZ < K) p2g_pass3<T, DEG, COMP, 2 * CZ, (3 * CZ <= K ? CZ : K - 2 * CZ)>(
-                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, lds);
+                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
             if constexpr (3 * CZ < K) p2g_pass3<T, DEG, COMP, 3 * CZ, K - 3 * CZ>(
-                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, lds);
+                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
         } else {
             T acc_m[K][K], acc_v[2][K][K];
 #pragma unroll
@@ -79,7 +86,7 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
                     P2GRaw<T, 2> raw;
                     p2g_load<T, 2>(P, (uint32_t)q, raw);
                     P2GParticle<T, 2, DEG> pp;
-                    if (p2g_prepare<T, 2, DEG>(raw, key, prm, g.inv_dx, g.flags, pp))
+                    if (p2g_prepare<T, 2, DEG>(raw, key, prm, g.inv_dx, g.flags, uref, pp))
                         p2g_accumulate2<T, DEG>(pp, acc_m, acc_v);
                 }
                 level += (uint32_t)popc64(mask);

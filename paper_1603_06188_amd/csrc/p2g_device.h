@@ -11,7 +11,7 @@ template <typename T, int DIM, int DEG>
 struct P2GParticle {
     Axis<T, DEG> ax[DIM];
     T m;
-    T p[DIM];              // m v
+    T p[DIM];              // m (v - uref): momentum relative to the tile's reference velocity
     T Qc[DIM * DIM];
     T Ac[DIM * DIM];
 };
@@ -41,11 +41,13 @@ __device__ __forceinline__ void p2g_load(const Parts<T> &P, uint32_t q, P2GRaw<T
     }
 }
 
-// Checks a loaded particle and forms its per-particle terms.  Returns false
-// (and sets a flag) when the particle must be skipped.
+// Checks a loaded particle and forms its per-particle terms, its momentum
+// relative to the reference velocity uref of its tile.  Returns false (and
+// sets a flag) when the particle must be skipped.
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *key, const StepParams<T> &prm,
-                                            T inv_dx, uint32_t *flags, P2GParticle<T, DIM, DEG> &pp) {
+                                            T inv_dx, uint32_t *flags, const T *uref,
+                                            P2GParticle<T, DIM, DEG> &pp) {
     int ci[3] = {0, 0, 0};
     unpack_cell<DIM>(r.cell, ci);
     T off[DIM], v[DIM], B[DIM * DIM], F[DIM * DIM];
@@ -86,7 +88,7 @@ __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *
     else
         qs = m * inv_D_factor<T, DEG>() * inv_dx;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) pp.p[a] = m * v[a];
+    for (int a = 0; a < DIM; ++a) pp.p[a] = m * (v[a] - uref[a]);
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) {
         pp.Qc[k] = qs * B[k];
@@ -290,13 +292,43 @@ __device__ __forceinline__ void slab_load(const T *in, T *lds) {
     for (int i = lane_id(); i < SLAB; i += 64) lds[(i / RN) * LP + SL::from_compact(i % RN)] = in[i];
 }
 
+// Reference velocity of a tile (wave-wide): the mean velocity of the
+// particles at level 0 of its keys (lanes with act > 0), rounded by
+// quantize_ref; every lane gets the same value (the butterfly adds the same
+// pairs on every lane).  0 for a tile without particles.
+template <typename T, int DIM>
+__device__ __forceinline__ void tile_reference(const Parts<T> &P, uint32_t start, uint32_t kstart, uint32_t act,
+                                               uint32_t maxc, T *uref) {
+    const int lane = lane_id();
+    const uint64_t mask = ballot(act > 0);
+    T v[DIM];
+    if (act > 0) {
+        const uint32_t q = (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) v[a] = P.v[a * P.s + q];
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) v[a] = T(0);
+    }
+    const T inv_n = mask ? T(1) / (T)popc64(mask) : T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        T x = v[a];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
+        uref[a] = wave_uniform(quantize_ref(x * inv_n));
+    }
+}
+
 // Register sums of a key's particles (cnt per key, maxc the tile's busiest)
 // for z-slices [C0, C0+CZ), added into the slab.  MOV: only the first `act`
-// particles of each key (its movers), levels [0, jend).
+// particles of each key (its movers), levels [0, jend).  Momenta are taken
+// relative to the tile's reference velocity uref.
 template <typename T, int DEG, bool COMP, int C0, int CZ, bool MOV = false>
 __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int lcoord[3], uint32_t start,
                                           uint32_t kstart, uint32_t cnt, uint32_t maxc, uint32_t act, uint32_t jend,
-                                          const StepParams<T> &prm, T inv_dx, uint32_t *flags, T *lds) {
+                                          const StepParams<T> &prm, T inv_dx, uint32_t *flags, const T *uref,
+                                          T *lds) {
     constexpr int K = DEG + 1;
     const int lane = lane_id();
     const uint32_t n_act = MOV ? act : cnt, j_end = MOV ? jend : maxc;
@@ -323,7 +355,7 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
             p2g_load<T, 3>(P, (uint32_t)particle_at(start, kstart, level_n, mask_n, j + 1, maxc, lane), raw_n);
         if (n_act > j) {
             P2GParticle<T, 3, DEG> pp;
-            if (p2g_prepare<T, 3, DEG>(raw, key, prm, inv_dx, flags, pp))
+            if (p2g_prepare<T, 3, DEG>(raw, key, prm, inv_dx, flags, uref, pp))
                 p2g_accumulate3<T, DEG, C0, CZ>(pp, acc_m, acc_v);
         }
         raw = raw_n;

@@ -104,19 +104,16 @@ def test_spheres_full_size_f32_step_matches_oracle(spheres32):
     assert ds.flags() == 0
     g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
     ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
-    assert rel(m, ref["m"]) <= 1e-5
-    assert rel(mv, ref["mv"] + s.dt * ref["f"]) <= 1e-5
-    assert float(np.abs(got["x"] - ref["x_new"]).max() / s.dx) <= 1e-5
-    for key in ("v", "F"):
-        assert rel(got[key], ref[key + "_new"]) <= 1e-5, key
-    # B = sum w vt r^T sums terms of size |v| dx ~ 8e-3 into |B| ~ 2.5e-5: binary32
-    # resolves it to about u |v| dx / |B| of itself (u = 2^-24), not 1e-5
-    bmax = float(np.abs(ref["B_new"]).max())
-    vmax = float(np.abs(ref["v_new"]).max())
-    tol_b = max(1e-5, 2 * 2.0 ** -24 * vmax * s.dx / bmax)
-    err_b = rel(got["B"], ref["B_new"])
-    print("B", err_b, "bar", tol_b, flush=True)
-    assert err_b <= tol_b, (err_b, tol_b)
+    errs = {"m": rel(m, ref["m"]), "mv": rel(mv, ref["mv"] + s.dt * ref["f"]),
+            "x_cells": float(np.abs(got["x"] - ref["x_new"]).max() / s.dx)}
+    for key in ("v", "B", "F"):
+        errs[key] = rel(got[key], ref[key + "_new"])
+    # B sums terms of size |v| dx ~ 8e-3 into |B| ~ 2.5e-5; the grid carries
+    # velocities relative to per-tile reference velocities, so its rounding
+    # scales with the velocity differences inside a tile, not with |v|
+    print("spheres f32 compensated per-field errors", errs, flush=True)
+    for key, e in errs.items():
+        assert e <= 1e-5, (key, e)
 
 
 def test_spheres_full_size_f32_momenta_drift_within_roundoff(spheres32):
