@@ -43,11 +43,11 @@ int slab_nodes(int dim, int degree) {
 // Workspace layout for a grid and a particle capacity `cap`.
 // ---------------------------------------------------------------------------
 struct ListOff {
-    size_t tile_gen, slot, rec_count, rec_list, rec_tile, tot, rpre, bpre, dead;
+    size_t tile_gen, slot, rec_count, rec_list, rec_tile, tot, rpre, bpre, ctr;
 };
 
 struct TabOff {
-    size_t kcount, kmov, kprefix, maxc, tcount, off, lvl_off, lvl_mask;
+    size_t kcount, kmov, kmpre, mbase, kprefix, maxc, tcount, off, lvl_off, lvl_mask;
 };
 
 struct Layout {
@@ -63,7 +63,7 @@ struct Layout {
     TabOff tabs[2];
     size_t o_slabs;
     size_t fixed_end;
-    size_t o_pkey, o_prank, o_sh_cell, o_sh_id, o_sh_f;
+    size_t o_pkey, o_prank, o_pord, o_mlist, o_who, o_sh_cell, o_sh_id, o_sh_f;
     size_t total;
 };
 
@@ -121,12 +121,14 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         l.tot = take((size_t)kBuckets * 4);
         l.rpre = take((size_t)(kBuckets + 1) * 4);
         l.bpre = take((size_t)(kBuckets + 1) * 4);
-        l.dead = take(4);
+        l.ctr = take((size_t)kCtrCount * 4);
     }
     for (int k = 0; k < 2; ++k) {
         TabOff &t = L.tabs[k];
         t.kcount = take(TT * 64 * 4);
         t.kmov = take(TT * 64 * 4);
+        t.kmpre = take(TT * 64 * 4);
+        t.mbase = take(TT * 4);
         t.kprefix = take(TT * 64 * 4);
         t.maxc = take(TT * 4);
         t.tcount = take(TT * 4);
@@ -138,6 +140,9 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.fixed_end = o;
     L.o_pkey = take(cp * 4);
     L.o_prank = take(cp * 4);
+    L.o_pord = take(cp * 8);
+    L.o_mlist = take(cp * 4);
+    L.o_who = take(cp * 8);
     L.o_sh_cell = take(cp * 4);
     L.o_sh_id = take(cp * 4);
     L.o_sh_f = take((2 * dim + 2 * dim * dim + 1) * cp * e);
@@ -373,7 +378,7 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         b.tot = (uint32_t *)(w + o.tot);
         b.rpre = (uint32_t *)(w + o.rpre);
         b.bpre = (uint32_t *)(w + o.bpre);
-        b.dead = (uint32_t *)(w + o.dead);
+        b.ctr = (uint32_t *)(w + o.ctr);
         b.rcap = L.rcap;
     }
     for (int k = 0; k < 2; ++k) {
@@ -381,6 +386,8 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         TileTables &t = v.tab[k];
         t.kcount = (uint32_t *)(w + o.kcount);
         t.kmov = (uint32_t *)(w + o.kmov);
+        t.kmpre = (uint32_t *)(w + o.kmpre);
+        t.mbase = (uint32_t *)(w + o.mbase);
         t.kprefix = (uint32_t *)(w + o.kprefix);
         t.maxc = (uint32_t *)(w + o.maxc);
         t.tcount = (uint32_t *)(w + o.tcount);
@@ -392,6 +399,9 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.sc.scount = (uint32_t *)(w + L.o_scount);
     v.sc.pkey = (uint32_t *)(w + L.o_pkey);
     v.sc.prank = (uint32_t *)(w + L.o_prank);
+    v.sc.pord = (uint64_t *)(w + L.o_pord);
+    v.sc.mlist = (uint32_t *)(w + L.o_mlist);
+    v.sc.who = (uint64_t *)(w + L.o_who);
     v.slabs.v = (T *)(w + L.o_slabs);
     v.slabs.stride = L.slab_stride;
     v.g.vt = (T *)(w + L.o_vt);
@@ -478,7 +488,7 @@ void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> 
     launch_bin_reset(v.lists[nxt], st);
     launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, st);
     launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-    launch_bin_finalize(v.lists[nxt], st);
+    launch_bin_finalize(v.lists[nxt], v.tab[nxt], v.sc, v.L.cap, st);
     launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab[nxt], v.sc, st);
 }
 
@@ -495,7 +505,7 @@ void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &
         launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
                                            st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-        launch_bin_finalize(v.lists[nxt], st);
+        launch_bin_finalize(v.lists[nxt], v.tab[nxt], v.sc, v.L.cap, st);
     });
     timed(APIC_PHASE_G2P, st, [&] {
         launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
@@ -520,7 +530,7 @@ void g2p2g_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T>
         launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
                                            st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-        launch_bin_finalize(v.lists[nxt], st);
+        launch_bin_finalize(v.lists[nxt], v.tab[nxt], v.sc, v.L.cap, st);
     });
     if constexpr (fused_step<T, DIM, DEG>()) {
         timed(APIC_PHASE_G2P, st, [&] {
@@ -816,8 +826,10 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         }
         states[(size_t)i] = &ss;
         const int64_t np = scenes[i].p.n;
+        // finalize: one block for the prefix tables, the rest for the mover slots
         const int share[BK_COUNT] = {share_blocks(np, 4096), share_blocks(np, 8192), share_blocks(np, 2048),
-                                     share_blocks(np, 1024), share_blocks(np, 4096), share_blocks(np, 4096), 1};
+                                     share_blocks(np, 1024), share_blocks(np, 4096), share_blocks(np, 4096),
+                                     1 + share_blocks(np, 64)};
         for (int k = 0; k < BK_COUNT; ++k) {
             starts[(size_t)k * (n + 1) + i] = total[k];
             total[k] += share[k];

@@ -149,16 +149,37 @@ __device__ __forceinline__ uint32_t tile_of_record(const TileWalk &w, uint32_t r
 }
 
 // Lists the key's tile in `nxt` on first touch (generation tag + bucketed
-// append) and takes a rank within the key; dead particles take a rank in
-// the dead region.  `active` false for lanes without a particle.
-__device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, const BinLists &nxt,
-                                                  const BinScratch &sc) {
+// append), takes a provisional rank within the key and lists the mover (old
+// position p, order value ord) for the final ranking; dead particles take a
+// rank in the dead region.  `active` false for lanes without a particle.
+// Wave-wide.
+__device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, uint32_t p, uint64_t ord,
+                                                  const BinLists &nxt, const BinScratch &sc) {
     const bool live = active && key != kDeadKey;
     const uint32_t t = key >> 6;
     if (first_lane_of_value(t, live)) list_tile(t, nxt);
+    const uint64_t lm = ballot(live);
+    uint32_t at = 0u;
+    if (lane_id() == 0 && lm) at = atomicAdd(nxt.ctr + kCtrMovers, (uint32_t)popc64(lm));
+    at = __shfl(at, 0, 64);
+    if (live) {
+        sc.mlist[at + (uint32_t)popc64(lm & lanes_below(lane_id()))] = p;
+        sc.pord[p] = ord;
+    }
     if (!active) return 0u;
-    if (key == kDeadKey) return atomicAdd(nxt.dead, 1u);
+    if (key == kDeadKey) return atomicAdd(nxt.ctr + kCtrDead, 1u);
     return atomicAdd(sc.key_count + key, 1u);
+}
+
+// Final rank of a mover (order value ord) among the movers into its key:
+// how many of them precede it in the old layout's order.
+__device__ __forceinline__ uint32_t mover_rank(uint32_t key, uint64_t ord, const TileTables &tab,
+                                               const BinScratch &sc) {
+    const uint32_t n = tab.kmov[key];
+    const uint64_t *w = sc.who + tab.mbase[key >> 6] + tab.kmpre[key];
+    uint32_t r = 0u;
+    for (uint32_t j = 0; j < n; ++j) r += w[j] < ord ? 1u : 0u;
+    return r;
 }
 
 // One scene's view of step k of a batched launch: its descriptor, the lists

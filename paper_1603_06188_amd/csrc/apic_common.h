@@ -40,7 +40,7 @@ namespace apic {
 constexpr int kBuckets = 1024;   // 4 per thread of a 256-thread block
 constexpr int kMaxLevels = 32;
 constexpr int kVmaxSlots = 1024;
-constexpr int kKeyChunks = 4;     // key pass: chunks of 64 particles loaded together
+constexpr int kKeyChunks = 8;     // key pass: chunks of 64 particles loaded together
 
 struct GridDims {
     int dim, deg;
@@ -71,17 +71,24 @@ struct BinLists {
     uint32_t *rpre;        // [kBuckets + 1] exclusive prefix of rec_count; [kBuckets] = records
     uint32_t *rec_tile;    // [records] tile id of record r (bucket order)
     uint32_t *bpre;        // [kBuckets + 1] exclusive prefix of tot; [kBuckets] = live particles
-    uint32_t *dead;        // [1] dead particles
+    uint32_t *ctr;         // [4] counters of a build (kCtr*), zero when it starts
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
 };
 
+// Counters of a build: dead particles, movers listed, mover slots handed out.
+enum : int { kCtrDead = 0, kCtrMovers = 1, kCtrSlots = 2, kCtrCount = 4 };
+
 // Per-tile tables of one layout (dense, indexed by tile id; entries of tiles
 // not listed are stale and never read).  Within a key, particles that came
-// from other keys (movers) take ranks [0, kmov) and particles that stayed
-// take ranks [kmov, kcount) in their old order.
+// from other keys (movers) take ranks [0, kmov) in the order of their
+// positions in the layout they came from, and particles that stayed take
+// ranks [kmov, kcount) in their old order: a layout is a function of the
+// one before it, whatever order the device's atomics ran in.
 struct TileTables {
     uint32_t *kcount;      // [tiles * 64] particles per key
     uint32_t *kmov;        // [tiles * 64] of which movers
+    uint32_t *kmpre;       // [tiles * 64] exclusive prefix of kmov in the tile
+    uint32_t *mbase;       // [tiles] first mover slot of the tile (BinScratch::who)
     uint32_t *kprefix;     // [tiles * 64] exclusive prefix of kcount in the tile
     uint32_t *maxc;        // [tiles] largest per-key count
     uint32_t *tcount;      // [tiles] particles in the tile
@@ -90,13 +97,29 @@ struct TileTables {
     uint64_t *lvl_mask;    // [tiles * kMaxLevels] keys present in level j
 };
 
-// Scratch of the binning passes (counters are zero between passes).
+// Scratch of the binning passes (counters are zero between passes).  A
+// mover first takes a provisional rank in its new key from a counter (the
+// order the device runs its atomics in); its final rank is the number of
+// movers into the same key that precede it in the old layout's order, read
+// from the `who` slots of the key (mover slot mbase[t] + kmpre[key] +
+// provisional rank holds the mover's order value).  The order value of a
+// particle is (tile << 32 | index within the tile) for a re-binning (tiles
+// sit in the particle planes in the order their counters ran, so absolute
+// positions would not do) and its position for a binning from scratch.
 struct BinScratch {
     uint32_t *key_count;  // [G]   movers entering each key
     uint32_t *scount;     // [G]   particles staying in each key
     uint32_t *pkey;       // [cap] new key of a mover (kDeadKey: dead)
-    uint32_t *prank;      // [cap] rank of a mover within its key / among the dead
+    uint32_t *prank;      // [cap] provisional rank of a mover within its key / rank among the dead
+    uint64_t *pord;       // [cap] order value of a mover
+    uint32_t *mlist;      // [cap] old positions of the movers of a build (ctr[kCtrMovers] of them)
+    uint64_t *who;        // [cap] order value of the mover in each mover slot
 };
+
+// Order value of the particle at index i within tile t of a layout.
+__host__ __device__ __forceinline__ uint64_t tile_order(uint32_t t, uint32_t i) {
+    return ((uint64_t)t << 32) | (uint64_t)i;
+}
 
 template <typename T>
 struct Slabs {

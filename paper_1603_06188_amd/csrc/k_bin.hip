@@ -19,7 +19,7 @@ __global__ void k_bin_reset(BinLists nxt) {
         nxt.rec_count[t] = 0u;
         nxt.tot[t] = 0u;
     }
-    if (threadIdx.x == 0) nxt.dead[0] = 0u;
+    if (threadIdx.x < kCtrCount) nxt.ctr[threadIdx.x] = 0u;
 }
 
 void launch_bin_reset(const BinLists &nxt, hipStream_t st) {
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_bin_keys_static(Parts<T> P, GridDims d,
         key = key_of<T, DIM, DEG>(ci, off, d, finite);
         if (key == kDeadKey) atomicOr(flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
     }
-    const uint32_t rank = bin_take_slot(key, active, nxt, sc);
+    const uint32_t rank = bin_take_slot(key, active, (uint32_t)p, (uint64_t)p, nxt, sc);
     if (active) {
         sc.pkey[p] = key;
         sc.prank[p] = rank;
@@ -86,16 +86,19 @@ __device__ __forceinline__ void records_body(const BinLists &nxt, const TileTabl
         const uint32_t c = mov + sc.scount[key];
         sc.key_count[key] = 0u;
         sc.scount[key] = 0u;
-        uint32_t total;
+        uint32_t total, mtotal;
         const uint32_t kp = wave_excl_scan(c, total);
+        const uint32_t kmp = wave_excl_scan(mov, mtotal);
         const uint32_t mx = wave_max_u32(c);
         tab.kcount[key] = c;
         tab.kmov[key] = mov;
         tab.kprefix[key] = kp;
+        tab.kmpre[key] = kmp;
         if (lane == 0) {
             tab.maxc[t] = mx;
             tab.tcount[t] = total;
             tab.off[t] = atomicAdd(nxt.tot + b, total);
+            tab.mbase[t] = mtotal ? atomicAdd(nxt.ctr + kCtrSlots, mtotal) : 0u;
             nxt.slot[t] = r;
             nxt.rec_tile[r] = t;
         }
@@ -169,8 +172,19 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
     hipLaunchKernelGGL((k_copy_back_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
 }
 
-// --- prefix tables of a finished layout (one block) ----------------------------------
-__device__ __forceinline__ void finalize_body(const BinLists &nxt) {
+// --- prefix tables of a finished layout (block 0) and the mover slots (the
+// other blocks: each listed mover's old position goes to slot
+// mbase[tile] + kmpre[key] + provisional rank) -------------------------------------
+__device__ __forceinline__ void finalize_body(const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
+                                              uint32_t blk, uint32_t nblk) {
+    if (blk > 0) {
+        const uint32_t nm = nxt.ctr[kCtrMovers];
+        for (uint32_t i = (blk - 1) * blockDim.x + threadIdx.x; i < nm; i += (nblk - 1) * blockDim.x) {
+            const uint32_t p = sc.mlist[i], key = sc.pkey[p];
+            sc.who[tab.mbase[key >> 6] + tab.kmpre[key] + sc.prank[p]] = sc.pord[p];
+        }
+        return;
+    }
     __shared__ uint32_t tmp[kBuckets + 8];
     const uint32_t nrec = block_bucket_prefix(nxt.rec_count, tmp, tmp + kBuckets);
     for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) nxt.rpre[i] = tmp[i];
@@ -183,17 +197,23 @@ __device__ __forceinline__ void finalize_body(const BinLists &nxt) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt) { finalize_body(nxt); }
+__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt, TileTables tab, BinScratch sc) {
+    finalize_body(nxt, tab, sc, blockIdx.x, gridDim.x);
+}
 
-void launch_bin_finalize(const BinLists &nxt, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, st, nxt);
+// One block for the prefix tables and up to 256 for the mover slots of at
+// most `cap` movers.
+void launch_bin_finalize(const BinLists &nxt, const TileTables &tab, const BinScratch &sc, int64_t cap,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_finalize, dim3(1 + blocks_for(cap, 256, 256)), dim3(256), 0, st, nxt, tab, sc);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
                                                             int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    finalize_body(b.nxt);
+    const SceneDesc<T> &d = *b.d;
+    finalize_body(b.nxt, d.tab[b.sp.nxt], d.sc, b.blk, b.nblk);
 }
 
 template <typename T>
@@ -220,7 +240,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter_copy(Parts<T> src, Parts<T>
     if (p >= src.n) return;
     const uint32_t live = nxt.bpre[kBuckets];
     const uint32_t key = sc.pkey[p];
-    const uint32_t rank = sc.prank[p];
+    const uint32_t rank = key == kDeadKey ? sc.prank[p] : mover_rank(key, (uint64_t)p, tab, sc);
     const int64_t q = bin_destination(key, rank, tab, bucket_base_of(key, nxt.bpre), live);
     dst.cell[q] = src.cell[p];
     dst.m[q] = src.m[p];

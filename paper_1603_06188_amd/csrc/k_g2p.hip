@@ -43,8 +43,8 @@ __device__ __forceinline__ int local_key(const int *ci, const T *off) {
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<T> &g, const StepParams<T> &prm,
                                              const BinLists &nxt, const BinScratch &sc, const uint32_t *queue,
-                                             uint32_t count, uint32_t t, const int *origin, const T *reg,
-                                             const T *uref, uint32_t *stay) {
+                                             uint32_t count, uint32_t t, uint32_t start, const int *origin,
+                                             const T *reg, uint32_t *stay) {
     const int lane = lane_id();
     const bool act = (uint32_t)lane < count;
     uint32_t nkey = kDeadKey, q = 0;
@@ -61,7 +61,7 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
             lk[a] = base[a] - origin[a];
         }
         const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(base);
-        velocity_lds<T, DIM, DEG>(reg, lk, w, uref, vn);
+        velocity_lds<T, DIM, DEG>(reg, lk, w, vn);
         bool cfl, finite;
         move_position<T, DIM>(ci, off, vn, prm.dt * g.inv_dx, cn, on, cfl);
         nkey = key_of<T, DIM, DEG>(cn, on, g.d, finite);
@@ -71,7 +71,7 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
         else
             mover = true;
     }
-    const uint32_t rank = bin_take_slot(nkey, mover, nxt, sc);
+    const uint32_t rank = bin_take_slot(nkey, mover, q, tile_order(t, q - start), nxt, sc);
     if (mover) {
         sc.pkey[q] = nkey;
         sc.prank[q] = rank;
@@ -86,10 +86,10 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
     using R = VtRegion<DIM>;
     __shared__ uint32_t lds_stay[4][64];
     __shared__ uint32_t lds_queue[4][64 * kKeyChunks];
-    __shared__ T lds_vt[4 * DIM * R::SIZE];
+    __shared__ T lds_vt[4 * R::TOTAL];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
     uint32_t *stay = lds_stay[wv], *queue = lds_queue[wv];
-    T *reg = lds_vt + wv * (DIM * R::SIZE);
+    T *reg = lds_vt + wv * R::TOTAL;
     const TileWalk walk = tile_walk(cur);
     const T reach = step_reach<T>(wave_vmax(g.vmax), prm, g.inv_dx);
     const uint32_t items = walk.nrec + dead_chunks(P.n, walk.live);
@@ -97,7 +97,7 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         if (r >= walk.nrec) {
             // particles that could not be binned stay in the dead region
             const int64_t p = (int64_t)walk.live + (int64_t)(r - walk.nrec) * 64 + lane;
-            if (p < P.n) sc.prank[p] = atomicAdd(nxt.dead, 1u);
+            if (p < P.n) sc.prank[p] = atomicAdd(nxt.ctr + kCtrDead, 1u);
             continue;
         }
         uint32_t start, total;
@@ -105,8 +105,6 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
         bool staged = false;  // grid velocities around the tile, on first use
-        T uref[DIM];
-        tile_uref<T, DIM>(t, g, uref);
         stay[lane] = 0u;
         wave_lds_sync();
         uint32_t queued = 0;
@@ -145,12 +143,12 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
             // the group's queued particles, 64 at a time
             for (uint32_t q0 = 0; q0 < queued; q0 += 64u) {
                 if (!staged) {
-                    stage_velocities<T, DIM>(t, g, uref, reg);
+                    stage_velocities<T, DIM>(t, g, reg);
                     staged = true;
                 }
                 wave_lds_sync();
                 const uint32_t take = queued - q0 < 64u ? queued - q0 : 64u;
-                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue + q0, take, t, origin, reg, uref, stay);
+                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue + q0, take, t, start, origin, reg, stay);
             }
             queued = 0;
             wave_lds_sync();
@@ -220,10 +218,10 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     constexpr int K = DEG + 1;
     constexpr int TE = DIM == 3 ? 4 : 8;
     using R = VtRegion<DIM>;
-    __shared__ T lds_vt[4 * DIM * R::SIZE];
+    __shared__ T lds_vt[4 * R::TOTAL];
     __shared__ uint32_t lds_rank[4][64];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
-    T *reg = lds_vt + wv * (DIM * R::SIZE);
+    T *reg = lds_vt + wv * R::TOTAL;
     uint32_t *rankc = lds_rank[wv];
     const TileWalk walk = tile_walk(cur);
     const uint32_t *bases = nxt.bpre;
@@ -242,9 +240,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         const uint32_t t = tile_range(walk, r, cur, ctab, start, total);
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
-        T uref[DIM];
-        tile_uref<T, DIM>(t, g, uref);
-        stage_velocities<T, DIM>(t, g, uref, reg);
+        stage_velocities<T, DIM>(t, g, reg);
         // stayers of a key follow its movers in the new layout
         rankc[lane] = ntab.kmov[t * 64 + (uint32_t)lane];
         const uint32_t tbase = bases[bucket_of(t)];
@@ -260,8 +256,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 const uint32_t p = start + i;
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                 T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
-                g2p_update<T, DIM, DEG>(raw, reg, origin, uref, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn,
-                                        prm.transfer);
+                g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
                 const T *off = raw.off;
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);
@@ -276,7 +271,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                     base = tbase;
                 } else {
                     dkey = sc.pkey[p];
-                    drank = sc.prank[p];
+                    drank = dkey == kDeadKey ? sc.prank[p] : mover_rank(dkey, tile_order(t, i), ntab, sc);
                     base = bucket_base_of(dkey, bases);
                 }
                 const uint32_t q = bin_destination(dkey, drank, ntab, base, live_nxt);

@@ -35,7 +35,7 @@ constexpr int kHandFields = 25;  // m, off[3], v[3], B[9], F[9] (the cell travel
 // The LDS of one k_g2p2g block.
 template <typename T, int DEG, bool COMP>
 struct PairLds {
-    static constexpr int VT = 3 * VtRegion<3>::SIZE;
+    static constexpr int VT = VtRegion<3>::TOTAL;
     static constexpr int SLAB = Geo<3, DEG>::NC * (COMP ? 2 : 1) * SlabLds<3, DEG>::PLANE;
     T vt[VT];                         // grid velocities around the tile (wavefront 0)
     T slab[SLAB];                     // slab of the new layout (wavefront 1)
@@ -74,13 +74,9 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
         const uint32_t t = tile_of_record(walk, r, cur, ctab, start, cnt, maxc, kstart);
         int origin[3] = {0, 0, 0};
         tile_origin<3>(t, g.d.TN, origin);
-        // the tile keeps its reference velocity: the slab this pass forms for
-        // the new layout holds momenta relative to the same uref[t]
-        T uref[3];
-        tile_uref<T, 3>(t, g, uref);
         if (producer) {
             // --- wavefront 0: G2P, write, hand the stayers over ---------------------
-            stage_velocities<T, 3>(t, g, uref, L.vt);
+            stage_velocities<T, 3>(t, g, L.vt);
             // stayers of a key follow its movers, in their old order
             uint32_t srank = ntab.kmov[t * 64 + (uint32_t)lane];
             const uint32_t tbase = bases[bucket_of(t)];
@@ -107,8 +103,7 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
                 if (cnt > j) {
                     int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                     T on[3], vn[3], Bs[9], Fn[9];
-                    g2p_update<T, 3, DEG>(raw, L.vt, origin, uref, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn,
-                                          prm.transfer);
+                    g2p_update<T, 3, DEG>(raw, L.vt, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
                     const uint32_t mykey = t * 64 + (uint32_t)local_of<3>(lk);
                     stays = keeps_key<T, 3, DEG>(raw.off, reach);
                     if (!stays) {
@@ -122,7 +117,7 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
                         base = tbase;
                     } else {
                         dkey = sc.pkey[p];
-                        drank = sc.prank[p];
+                        drank = dkey == kDeadKey ? sc.prank[p] : mover_rank(dkey, tile_order(t, p - start), ntab, sc);
                         base = bucket_base_of(dkey, bases);
                     }
                     const uint32_t q = bin_destination(dkey, drank, ntab, base, live_nxt);
@@ -173,6 +168,10 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
         } else {
             // --- wavefront 1: register sums of the stayers, slab ---------------------
             const int key[3] = {origin[0] + lcoord[0], origin[1] + lcoord[1], origin[2] + lcoord[2]};
+            // the tile keeps its reference velocity: the slab this pass forms
+            // for the new layout holds momenta relative to the same uref[t]
+            T uref[3];
+            tile_uref<T, 3>(t, g, uref);
             // the tile in the new layout: listed there when a particle stays in it
             const bool listed = nxt.tile_gen[t] == nxt.gen;
             const uint32_t rnew = nxt.slot[t];
@@ -244,7 +243,7 @@ __device__ __forceinline__ void p2g_movers_body(const Parts<T> &P, const BinList
             cur.rec_count[i] = 0u;
             cur.tot[i] = 0u;
         }
-        if (threadIdx.x == 0) cur.dead[0] = 0u;
+        if (threadIdx.x < kCtrCount) cur.ctr[threadIdx.x] = 0u;
     }
     const TileWalk walk = tile_walk(nxt);
     for (uint32_t r = blk * 4 + (threadIdx.x >> 6); r < walk.nrec; r += nblk * 4) {

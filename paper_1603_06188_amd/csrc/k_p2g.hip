@@ -43,7 +43,7 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
             nxt.rec_count[i] = 0u;
             nxt.tot[i] = 0u;
         }
-        if (threadIdx.x == 0) nxt.dead[0] = 0u;
+        if (threadIdx.x < kCtrCount) nxt.ctr[threadIdx.x] = 0u;
     }
     const TileWalk walk = tile_walk(cur);
     for (uint32_t r = blk * 4 + (threadIdx.x >> 6); r < walk.nrec; r += nblk * 4) {
