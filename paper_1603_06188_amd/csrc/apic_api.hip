@@ -47,7 +47,7 @@ struct ListOff {
 };
 
 struct TabOff {
-    size_t kcount, kmov, kmpre, mbase, kprefix, maxc, tcount, off, lvl_off, lvl_mask;
+    size_t kcount, kmov, kprefix, maxc, tcount, off, lvl_off, lvl_mask;
 };
 
 struct Layout {
@@ -58,12 +58,13 @@ struct Layout {
     int64_t rc;     // record (slab) capacity: min(tiles, cap)
     int64_t rcap;   // list capacity per bucket: ceil(tiles / kBuckets)
     int64_t slab_stride;
-    size_t o_vt, o_uref, o_nref, o_flags, o_vmax, o_cfl, o_dt, o_diag_out, o_diag_part, o_key_count, o_scount;
+    size_t o_vt, o_uref, o_flags, o_vmax, o_cfl, o_dt, o_diag_out, o_diag_part, o_key_count, o_scount,
+        o_head;
     ListOff lists[2];
     TabOff tabs[2];
     size_t o_slabs;
     size_t fixed_end;
-    size_t o_pkey, o_prank, o_pord, o_mlist, o_who, o_sh_cell, o_sh_id, o_sh_f;
+    size_t o_pkey, o_prank, o_next, o_pord, o_sh_cell, o_sh_id, o_sh_f;
     size_t total;
 };
 
@@ -102,7 +103,6 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     };
     L.o_vt = take(dim * G * e);
     L.o_uref = take(dim * TT * e);
-    L.o_nref = take(dim * TT * e);
     L.o_flags = take(64);
     L.o_vmax = take((size_t)kVmaxSlots * 4);
     L.o_cfl = take((size_t)kVmaxSlots * 8);
@@ -111,6 +111,7 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.o_diag_part = take((size_t)kDiagBlocks * 8 * sizeof(double));
     L.o_key_count = take(G * 4);
     L.o_scount = take(G * 4);
+    L.o_head = take(G * 4);
     for (int k = 0; k < 2; ++k) {
         ListOff &l = L.lists[k];
         l.tile_gen = take(TT * 4);
@@ -127,8 +128,6 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         TabOff &t = L.tabs[k];
         t.kcount = take(TT * 64 * 4);
         t.kmov = take(TT * 64 * 4);
-        t.kmpre = take(TT * 64 * 4);
-        t.mbase = take(TT * 4);
         t.kprefix = take(TT * 64 * 4);
         t.maxc = take(TT * 4);
         t.tcount = take(TT * 4);
@@ -140,9 +139,8 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.fixed_end = o;
     L.o_pkey = take(cp * 4);
     L.o_prank = take(cp * 4);
+    L.o_next = take(cp * 4);
     L.o_pord = take(cp * 8);
-    L.o_mlist = take(cp * 4);
-    L.o_who = take(cp * 8);
     L.o_sh_cell = take(cp * 4);
     L.o_sh_id = take(cp * 4);
     L.o_sh_f = take((2 * dim + 2 * dim * dim + 1) * cp * e);
@@ -386,8 +384,6 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         TileTables &t = v.tab[k];
         t.kcount = (uint32_t *)(w + o.kcount);
         t.kmov = (uint32_t *)(w + o.kmov);
-        t.kmpre = (uint32_t *)(w + o.kmpre);
-        t.mbase = (uint32_t *)(w + o.mbase);
         t.kprefix = (uint32_t *)(w + o.kprefix);
         t.maxc = (uint32_t *)(w + o.maxc);
         t.tcount = (uint32_t *)(w + o.tcount);
@@ -399,14 +395,13 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.sc.scount = (uint32_t *)(w + L.o_scount);
     v.sc.pkey = (uint32_t *)(w + L.o_pkey);
     v.sc.prank = (uint32_t *)(w + L.o_prank);
+    v.sc.next = (uint32_t *)(w + L.o_next);
     v.sc.pord = (uint64_t *)(w + L.o_pord);
-    v.sc.mlist = (uint32_t *)(w + L.o_mlist);
-    v.sc.who = (uint64_t *)(w + L.o_who);
+    v.sc.head = (uint32_t *)(w + L.o_head);
     v.slabs.v = (T *)(w + L.o_slabs);
     v.slabs.stride = L.slab_stride;
     v.g.vt = (T *)(w + L.o_vt);
     v.g.uref = (T *)(w + L.o_uref);
-    v.g.nref = (T *)(w + L.o_nref);
     v.g.flags = (uint32_t *)(w + L.o_flags);
     v.g.vmax = (uint32_t *)(w + L.o_vmax);
     v.g.cfl = nullptr;
@@ -488,7 +483,7 @@ void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> 
     launch_bin_reset(v.lists[nxt], st);
     launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, st);
     launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-    launch_bin_finalize(v.lists[nxt], v.tab[nxt], v.sc, v.L.cap, st);
+    launch_bin_finalize(v.lists[nxt], st);
     launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab[nxt], v.sc, st);
 }
 
@@ -505,7 +500,7 @@ void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &
         launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
                                            st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-        launch_bin_finalize(v.lists[nxt], v.tab[nxt], v.sc, v.L.cap, st);
+        launch_bin_finalize(v.lists[nxt], st);
     });
     timed(APIC_PHASE_G2P, st, [&] {
         launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
@@ -530,7 +525,7 @@ void g2p2g_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T>
         launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
                                            st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-        launch_bin_finalize(v.lists[nxt], v.tab[nxt], v.sc, v.L.cap, st);
+        launch_bin_finalize(v.lists[nxt], st);
     });
     if constexpr (fused_step<T, DIM, DEG>()) {
         timed(APIC_PHASE_G2P, st, [&] {
@@ -826,10 +821,8 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         }
         states[(size_t)i] = &ss;
         const int64_t np = scenes[i].p.n;
-        // finalize: one block for the prefix tables, the rest for the mover slots
         const int share[BK_COUNT] = {share_blocks(np, 4096), share_blocks(np, 8192), share_blocks(np, 2048),
-                                     share_blocks(np, 1024), share_blocks(np, 4096), share_blocks(np, 4096),
-                                     1 + share_blocks(np, 64)};
+                                     share_blocks(np, 1024), share_blocks(np, 4096), share_blocks(np, 4096), 1};
         for (int k = 0; k < BK_COUNT; ++k) {
             starts[(size_t)k * (n + 1) + i] = total[k];
             total[k] += share[k];

@@ -149,37 +149,39 @@ __device__ __forceinline__ uint32_t tile_of_record(const TileWalk &w, uint32_t r
 }
 
 // Lists the key's tile in `nxt` on first touch (generation tag + bucketed
-// append), takes a provisional rank within the key and lists the mover (old
-// position p, order value ord) for the final ranking; dead particles take a
-// rank in the dead region.  `active` false for lanes without a particle.
-// Wave-wide.
+// append), takes a provisional rank within the key and pushes the mover (old
+// position p, order value ord) on the key's list for its final rank; dead
+// particles take a rank in the dead region.  `active` false for lanes
+// without a particle.  Wave-wide.
 __device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, uint32_t p, uint64_t ord,
                                                   const BinLists &nxt, const BinScratch &sc) {
     const bool live = active && key != kDeadKey;
     const uint32_t t = key >> 6;
     if (first_lane_of_value(t, live)) list_tile(t, nxt);
-    const uint64_t lm = ballot(live);
-    uint32_t at = 0u;
-    if (lane_id() == 0 && lm) at = atomicAdd(nxt.ctr + kCtrMovers, (uint32_t)popc64(lm));
-    at = __shfl(at, 0, 64);
-    if (live) {
-        sc.mlist[at + (uint32_t)popc64(lm & lanes_below(lane_id()))] = p;
-        sc.pord[p] = ord;
-    }
     if (!active) return 0u;
     if (key == kDeadKey) return atomicAdd(nxt.ctr + kCtrDead, 1u);
+    sc.pord[p] = ord;
+    sc.next[p] = atomicExch(sc.head + key, p + 1u);
     return atomicAdd(sc.key_count + key, 1u);
 }
 
-// Final rank of a mover (order value ord) among the movers into its key:
-// how many of them precede it in the old layout's order.
-__device__ __forceinline__ uint32_t mover_rank(uint32_t key, uint64_t ord, const TileTables &tab,
-                                               const BinScratch &sc) {
-    const uint32_t n = tab.kmov[key];
-    const uint64_t *w = sc.who + tab.mbase[key >> 6] + tab.kmpre[key];
-    uint32_t r = 0u;
-    for (uint32_t j = 0; j < n; ++j) r += w[j] < ord ? 1u : 0u;
-    return r;
+// Final ranks of the n movers on a key's list (head: first old position +
+// 1): each mover's rank is the number of movers on the list with a smaller
+// order value.  Clears the list.
+__device__ __forceinline__ void rank_movers(uint32_t *head, uint32_t n, const BinScratch &sc) {
+    const uint32_t h = *head;
+    if (!h) return;
+    *head = 0u;
+    if (n == 1u) {
+        sc.prank[h - 1] = 0u;
+        return;
+    }
+    for (uint32_t a = h; a; a = sc.next[a - 1]) {
+        const uint64_t oa = sc.pord[a - 1];
+        uint32_t r = 0u;
+        for (uint32_t b = h; b; b = sc.next[b - 1]) r += sc.pord[b - 1] < oa ? 1u : 0u;
+        sc.prank[a - 1] = r;
+    }
 }
 
 // One scene's view of step k of a batched launch: its descriptor, the lists

@@ -71,12 +71,12 @@ struct BinLists {
     uint32_t *rpre;        // [kBuckets + 1] exclusive prefix of rec_count; [kBuckets] = records
     uint32_t *rec_tile;    // [records] tile id of record r (bucket order)
     uint32_t *bpre;        // [kBuckets + 1] exclusive prefix of tot; [kBuckets] = live particles
-    uint32_t *ctr;         // [4] counters of a build (kCtr*), zero when it starts
+    uint32_t *ctr;         // [kCtrCount] counters of a build, zero when it starts
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
 };
 
-// Counters of a build: dead particles, movers listed, mover slots handed out.
-enum : int { kCtrDead = 0, kCtrMovers = 1, kCtrSlots = 2, kCtrCount = 4 };
+// Counters of a build: dead particles.
+enum : int { kCtrDead = 0, kCtrCount = 4 };
 
 // Per-tile tables of one layout (dense, indexed by tile id; entries of tiles
 // not listed are stale and never read).  Within a key, particles that came
@@ -87,8 +87,6 @@ enum : int { kCtrDead = 0, kCtrMovers = 1, kCtrSlots = 2, kCtrCount = 4 };
 struct TileTables {
     uint32_t *kcount;      // [tiles * 64] particles per key
     uint32_t *kmov;        // [tiles * 64] of which movers
-    uint32_t *kmpre;       // [tiles * 64] exclusive prefix of kmov in the tile
-    uint32_t *mbase;       // [tiles] first mover slot of the tile (BinScratch::who)
     uint32_t *kprefix;     // [tiles * 64] exclusive prefix of kcount in the tile
     uint32_t *maxc;        // [tiles] largest per-key count
     uint32_t *tcount;      // [tiles] particles in the tile
@@ -98,22 +96,22 @@ struct TileTables {
 };
 
 // Scratch of the binning passes (counters are zero between passes).  A
-// mover first takes a provisional rank in its new key from a counter (the
-// order the device runs its atomics in); its final rank is the number of
-// movers into the same key that precede it in the old layout's order, read
-// from the `who` slots of the key (mover slot mbase[t] + kmpre[key] +
-// provisional rank holds the mover's order value).  The order value of a
-// particle is (tile << 32 | index within the tile) for a re-binning (tiles
-// sit in the particle planes in the order their counters ran, so absolute
-// positions would not do) and its position for a binning from scratch.
+// mover takes a provisional rank in its new key from a counter (the order
+// the device runs its atomics in) and is pushed on its new key's list; the
+// records pass walks each key's list and gives every mover its final rank:
+// the number of movers into the key that precede it in the old layout's
+// order.  The order value of a particle is (tile << 32 | index within the
+// tile) for a re-binning (tiles sit in the particle planes in the order their
+// counters ran, so absolute positions would not do) and its position for a
+// binning from scratch.
 struct BinScratch {
     uint32_t *key_count;  // [G]   movers entering each key
     uint32_t *scount;     // [G]   particles staying in each key
+    uint32_t *head;       // [G]   list of the movers entering each key: first old position + 1 (0: none)
     uint32_t *pkey;       // [cap] new key of a mover (kDeadKey: dead)
-    uint32_t *prank;      // [cap] provisional rank of a mover within its key / rank among the dead
+    uint32_t *prank;      // [cap] rank of a mover within its key / among the dead
+    uint32_t *next;       // [cap] next mover of the same key's list, old position + 1 (0: end)
     uint64_t *pord;       // [cap] order value of a mover
-    uint32_t *mlist;      // [cap] old positions of the movers of a build (ctr[kCtrMovers] of them)
-    uint64_t *who;        // [cap] order value of the mover in each mover slot
 };
 
 // Order value of the particle at index i within tile t of a layout.
@@ -127,17 +125,16 @@ struct Slabs {
     int64_t stride;     // elements per record
 };
 
-// Velocities on the grid are carried relative to reference velocities:
-// every listed key tile t has one, uref[t] (chosen by the transfer to grid
-// that forms its slab), and the slab holds m_i and sum w m_p (v_p - uref[t])
-// + ...; every node tile tau updated by the grid update has one, nref[tau]
-// (the reference of the first listed key tile whose slab covers it), and vt
-// holds vt_i - nref[tau].  References are multiples of kRefQuantum below
-// kRefMax in magnitude, so their sums and differences are exact in binary32
-// and the rounding of the sums scales with |v - reference| instead of |v|
-// (a body that moves fast as a whole keeps the digits of its velocity
-// differences, which B and grad v are made of).  Mathematically nothing
-// changes: every reference is added back exactly where the velocity is used.
+// The transfer to grid sums momenta relative to a reference velocity per
+// listed key tile, uref[t] (chosen by the transfer to grid that forms the
+// tile's slab): the slab holds m_i and sum w m_p (v_p - uref[t]) + ...; the
+// grid update moves each slab's sums to the reference of the node tile it
+// updates (a difference of two references) and adds that reference back to
+// the velocity it stores.  References are multiples of kRefQuantum below
+// kRefMax in magnitude, so their differences are exact in binary32, and the
+// rounding of the sums scales with |v - reference| instead of |v| (a body
+// that moves fast as a whole keeps the digits of its velocity differences,
+// which B and grad v are made of).  Mathematically nothing changes.
 constexpr float kRefQuantum = 1.0f / 1024.0f;
 constexpr float kRefMax = 4096.0f;
 
@@ -153,9 +150,8 @@ __device__ __forceinline__ T quantize_ref(T x) {
 
 template <typename T>
 struct GridState {
-    T *vt;              // dim planes of G nodes: updated velocity minus nref of its node tile
+    T *vt;              // dim planes of G nodes: updated velocity
     T *uref;            // dim planes of `tiles`: reference velocity of each listed key tile
-    T *nref;            // dim planes of `tiles`: reference velocity of each updated node tile
     uint32_t *flags;
     uint32_t *vmax;     // [kVmaxSlots] binary32 bits; their max bounds max_i |vt_i|
     // [kVmaxSlots] binary64 bits; the transfer to particles raises them to

@@ -54,18 +54,16 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 // about 1/9 (cubic), so c is never far out of scale with v: a corner node
 // can have a weight near zero and, if nothing else reaches it, a velocity
 // thousands of times larger than v, whose rounding would then dominate v.
-// The staged values are relative to the key tile's reference velocity uref
-// (see stage_velocities), which is added last: v_k = uref_k + (c_k + sum).
 template <typename T, int DIM, int DEG>
 __device__ __forceinline__ void velocity_from_tx(const T (&tx)[DIM][DEG + 1], const T (&w)[DIM][DEG + 1],
-                                                 const T *cref, const T *uref, T *vn) {
+                                                 const T *cref, T *vn) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < DEG + 1; ++a) s = fma_t(w[0][a], tx[k][a], s);
-        vn[k] = uref[k] + (cref[k] + s);
+        vn[k] = cref[k] + s;
     }
 }
 
@@ -191,23 +189,17 @@ __device__ __forceinline__ uint32_t dead_chunks(int64_t n, uint32_t live) {
 // Grid velocities of the 2^DIM node tiles from the key tile on, in LDS:
 // 3D 8x8x8 nodes at x + 8 y + 68 z (the z pad spreads a wavefront's 4x4x4
 // reads over the banks), 2D 16x16 nodes at x + 16 y; component-major.
-// After the DIM planes, the key tile's reference velocity (UREF, DIM values),
-// read from LDS where it is added back so that it occupies no registers
-// through the particle loop.
+// Grid velocities of the 2^DIM node tiles from the key tile on, in LDS:
+// 3D 8x8x8 nodes at x + 8 y + 68 z (the z pad spreads a wavefront's 4x4x4
+// reads over the banks), 2D 16x16 nodes at x + 16 y; component-major.
 template <int DIM>
 struct VtRegion {
     static constexpr int SY = DIM == 3 ? 8 : 16;
     static constexpr int SZ = DIM == 3 ? 68 : 0;
     static constexpr int SIZE = DIM == 3 ? 8 * 68 : 256;
-    static constexpr int UREF = DIM * SIZE;
-    static constexpr int TOTAL = DIM * SIZE + 4;
     __device__ static constexpr int at(int x, int y, int z) { return x + SY * y + SZ * z; }
 };
 
-// Staged values are relative to the reference velocity uref of key tile t
-// (its own reference, also that of the node tile t): node tile tau holds
-// vt - nref[tau], to which nref[tau] - uref (exact) is added; a node tile
-// outside the grid stages vt = 0.  uref itself goes to reg[R::UREF + k].
 template <typename T, int DIM>
 __device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> &g, T *reg) {
     using R = VtRegion<DIM>;
@@ -223,10 +215,6 @@ __device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> 
         tc[1] = (int)(t / (uint32_t)g.d.TN[0]);
     }
     local_coords<DIM>(lane, lc);
-    T uref[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) uref[k] = g.uref[k * g.d.tiles + t];
-    if (lane < DIM) reg[R::UREF + lane] = g.uref[lane * g.d.tiles + t];
 #pragma unroll
     for (int corner = 0; corner < (1 << DIM); ++corner) {
         bool ok = true;
@@ -242,20 +230,8 @@ __device__ __forceinline__ void stage_velocities(uint32_t t, const GridState<T> 
         }
         const int idx = R::at(rc[0], rc[1], rc[2]);
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            const T shift = ok ? g.nref[k * g.d.tiles + tau] - uref[k] : -uref[k];
-            reg[k * R::SIZE + idx] = ok ? g.vt[k * G + tau * 64 + lane] + shift : shift;
-        }
+        for (int k = 0; k < DIM; ++k) reg[k * R::SIZE + idx] = ok ? g.vt[k * G + tau * 64 + lane] : T(0);
     }
-}
-
-// Reference velocity of key tile t (t is the same on every lane).  Plain
-// loads: taking them into scalar registers would make the wavefront wait for
-// every memory operation in flight, stores included.
-template <typename T, int DIM>
-__device__ __forceinline__ void tile_uref(uint32_t t, const GridState<T> &g, T *uref) {
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) uref[k] = g.uref[k * g.d.tiles + t];
 }
 
 // Occupancy target: binary32 quadratic 3D fits 128 registers (4 waves per
@@ -355,7 +331,7 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
                     }
             }
     }
-    velocity_from_tx<T, DIM, DEG>(Tx, wf, cref, reg + R::UREF, vn);
+    velocity_from_tx<T, DIM, DEG>(Tx, wf, cref, vn);
     // B and grad v (cell units) from the axis sums; weight
     // derivatives and node offsets from the offsets
     T Gc[DIM * DIM];
@@ -452,7 +428,7 @@ __device__ __forceinline__ void velocity_lds(const T *reg, const int *lk, const 
                     tx[k][a] = fma_t(wyz, reg[k * R::SIZE + idx] - cref[k], tx[k][a]);
             }
         }
-    velocity_from_tx<T, DIM, DEG>(tx, w, cref, reg + R::UREF, vn);
+    velocity_from_tx<T, DIM, DEG>(tx, w, cref, vn);
 }
 
 }  // namespace apic

@@ -86,19 +86,17 @@ __device__ __forceinline__ void records_body(const BinLists &nxt, const TileTabl
         const uint32_t c = mov + sc.scount[key];
         sc.key_count[key] = 0u;
         sc.scount[key] = 0u;
-        uint32_t total, mtotal;
+        if (mov) rank_movers(sc.head + key, mov, sc);
+        uint32_t total;
         const uint32_t kp = wave_excl_scan(c, total);
-        const uint32_t kmp = wave_excl_scan(mov, mtotal);
         const uint32_t mx = wave_max_u32(c);
         tab.kcount[key] = c;
         tab.kmov[key] = mov;
         tab.kprefix[key] = kp;
-        tab.kmpre[key] = kmp;
         if (lane == 0) {
             tab.maxc[t] = mx;
             tab.tcount[t] = total;
             tab.off[t] = atomicAdd(nxt.tot + b, total);
-            tab.mbase[t] = mtotal ? atomicAdd(nxt.ctr + kCtrSlots, mtotal) : 0u;
             nxt.slot[t] = r;
             nxt.rec_tile[r] = t;
         }
@@ -172,19 +170,8 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
     hipLaunchKernelGGL((k_copy_back_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
 }
 
-// --- prefix tables of a finished layout (block 0) and the mover slots (the
-// other blocks: each listed mover's old position goes to slot
-// mbase[tile] + kmpre[key] + provisional rank) -------------------------------------
-__device__ __forceinline__ void finalize_body(const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
-                                              uint32_t blk, uint32_t nblk) {
-    if (blk > 0) {
-        const uint32_t nm = nxt.ctr[kCtrMovers];
-        for (uint32_t i = (blk - 1) * blockDim.x + threadIdx.x; i < nm; i += (nblk - 1) * blockDim.x) {
-            const uint32_t p = sc.mlist[i], key = sc.pkey[p];
-            sc.who[tab.mbase[key >> 6] + tab.kmpre[key] + sc.prank[p]] = sc.pord[p];
-        }
-        return;
-    }
+// --- prefix tables of a finished layout (one block) ----------------------------------
+__device__ __forceinline__ void finalize_body(const BinLists &nxt) {
     __shared__ uint32_t tmp[kBuckets + 8];
     const uint32_t nrec = block_bucket_prefix(nxt.rec_count, tmp, tmp + kBuckets);
     for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) nxt.rpre[i] = tmp[i];
@@ -197,23 +184,17 @@ __device__ __forceinline__ void finalize_body(const BinLists &nxt, const TileTab
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt, TileTables tab, BinScratch sc) {
-    finalize_body(nxt, tab, sc, blockIdx.x, gridDim.x);
-}
+__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt) { finalize_body(nxt); }
 
-// One block for the prefix tables and up to 256 for the mover slots of at
-// most `cap` movers.
-void launch_bin_finalize(const BinLists &nxt, const TileTables &tab, const BinScratch &sc, int64_t cap,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_finalize, dim3(1 + blocks_for(cap, 256, 256)), dim3(256), 0, st, nxt, tab, sc);
+void launch_bin_finalize(const BinLists &nxt, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, st, nxt);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
                                                             int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    const SceneDesc<T> &d = *b.d;
-    finalize_body(b.nxt, d.tab[b.sp.nxt], d.sc, b.blk, b.nblk);
+    finalize_body(b.nxt);
 }
 
 template <typename T>
@@ -240,7 +221,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter_copy(Parts<T> src, Parts<T>
     if (p >= src.n) return;
     const uint32_t live = nxt.bpre[kBuckets];
     const uint32_t key = sc.pkey[p];
-    const uint32_t rank = key == kDeadKey ? sc.prank[p] : mover_rank(key, (uint64_t)p, tab, sc);
+    const uint32_t rank = sc.prank[p];
     const int64_t q = bin_destination(key, rank, tab, bucket_base_of(key, nxt.bpre), live);
     dst.cell[q] = src.cell[p];
     dst.m[q] = src.m[p];

@@ -86,10 +86,10 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
     using R = VtRegion<DIM>;
     __shared__ uint32_t lds_stay[4][64];
     __shared__ uint32_t lds_queue[4][64 * kKeyChunks];
-    __shared__ T lds_vt[4 * R::TOTAL];
+    __shared__ T lds_vt[4 * DIM * R::SIZE];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
     uint32_t *stay = lds_stay[wv], *queue = lds_queue[wv];
-    T *reg = lds_vt + wv * R::TOTAL;
+    T *reg = lds_vt + wv * (DIM * R::SIZE);
     const TileWalk walk = tile_walk(cur);
     const T reach = step_reach<T>(wave_vmax(g.vmax), prm, g.inv_dx);
     const uint32_t items = walk.nrec + dead_chunks(P.n, walk.live);
@@ -218,10 +218,10 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     constexpr int K = DEG + 1;
     constexpr int TE = DIM == 3 ? 4 : 8;
     using R = VtRegion<DIM>;
-    __shared__ T lds_vt[4 * R::TOTAL];
+    __shared__ T lds_vt[4 * DIM * R::SIZE];
     __shared__ uint32_t lds_rank[4][64];
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
-    T *reg = lds_vt + wv * R::TOTAL;
+    T *reg = lds_vt + wv * (DIM * R::SIZE);
     uint32_t *rankc = lds_rank[wv];
     const TileWalk walk = tile_walk(cur);
     const uint32_t *bases = nxt.bpre;
@@ -271,7 +271,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                     base = tbase;
                 } else {
                     dkey = sc.pkey[p];
-                    drank = dkey == kDeadKey ? sc.prank[p] : mover_rank(dkey, tile_order(t, i), ntab, sc);
+                    drank = sc.prank[p];
                     base = bucket_base_of(dkey, bases);
                 }
                 const uint32_t q = bin_destination(dkey, drank, ntab, base, live_nxt);

@@ -35,7 +35,7 @@ constexpr int kHandFields = 25;  // m, off[3], v[3], B[9], F[9] (the cell travel
 // The LDS of one k_g2p2g block.
 template <typename T, int DEG, bool COMP>
 struct PairLds {
-    static constexpr int VT = VtRegion<3>::TOTAL;
+    static constexpr int VT = 3 * VtRegion<3>::SIZE;
     static constexpr int SLAB = Geo<3, DEG>::NC * (COMP ? 2 : 1) * SlabLds<3, DEG>::PLANE;
     T vt[VT];                         // grid velocities around the tile (wavefront 0)
     T slab[SLAB];                     // slab of the new layout (wavefront 1)
@@ -117,7 +117,7 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
                         base = tbase;
                     } else {
                         dkey = sc.pkey[p];
-                        drank = dkey == kDeadKey ? sc.prank[p] : mover_rank(dkey, tile_order(t, p - start), ntab, sc);
+                        drank = sc.prank[p];
                         base = bucket_base_of(dkey, bases);
                     }
                     const uint32_t q = bin_destination(dkey, drank, ntab, base, live_nxt);

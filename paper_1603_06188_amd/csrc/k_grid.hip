@@ -187,20 +187,14 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
             const bool live = valid && mm[0] > T(0) && !sticky;
             const T inv_m = live ? T(1) / mm[0] : T(0);
             const int64_t node = tau * 64 + lane;
-            if (lane == 0) {
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) g.nref[a * g.d.tiles + tau] = own[a];
-            }
             float vabs = 0.f;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                // stored relative to the node tile's reference; vt = 0 (no mass,
-                // sticky) is -reference
-                const T vt = live ? mm[1 + a] * inv_m + prm.dt * prm.g[a] : -own[a];
+                // the node tile's reference added back last
+                const T vt = live ? (mm[1 + a] * inv_m + prm.dt * prm.g[a]) + own[a] : T(0);
                 g.vt[a * G + node] = vt;
-                // binary32 value not below |vt + reference| (NaN propagates as the
-                // largest bits)
-                const T va = (vt < T(0) ? -vt : vt) + (own[a] < T(0) ? -own[a] : own[a]);
+                // binary32 value not below |vt| (NaN propagates as the largest bits)
+                const T va = vt < T(0) ? -vt : vt;
                 float f = (float)va;
                 if ((T)f < va) f = __uint_as_float(__float_as_uint(f) + 1u);  // next binary32 up
                 vabs = (f > vabs || f != f) ? f : vabs;
@@ -269,9 +263,8 @@ __global__ __launch_bounds__(256) void k_grid_export(BinLists gm, Slabs<T> slabs
         } else if (field == 1) {
             for (int a = 0; a < DIM; ++a) out[a * count + j] = mm[1 + a];
         } else {
-            const int64_t node = node_index<DIM>(nc, g.d.TN), tau = node >> 6;
-            for (int a = 0; a < DIM; ++a)
-                out[a * count + j] = mm[0] > T(0) ? g.vt[a * G + node] + g.nref[a * g.d.tiles + tau] : T(0);
+            const int64_t node = node_index<DIM>(nc, g.d.TN);
+            for (int a = 0; a < DIM; ++a) out[a * count + j] = mm[0] > T(0) ? g.vt[a * G + node] : T(0);
         }
     }
 }
@@ -322,14 +315,14 @@ __global__ __launch_bounds__(256) void k_diag_grid(BinLists gm, Slabs<T> slabs, 
         gather_node<T, DIM, DEG, COMP>(nc, gm, slabs, g.d, g.uref, mm);
         const double m = (double)mm[0];
         if (!(m > 0.0)) continue;
-        const int64_t node = node_index<DIM>(nc, g.d.TN), tau = node >> 6;
+        const int64_t node = node_index<DIM>(nc, g.d.TN);
         double x[3] = {0, 0, 0}, mv[3] = {0, 0, 0};
         for (int a = 0; a < DIM; ++a) {
             x[a] = (double)nc[a] * dx;
             if (which == 1) {
                 mv[a] = (double)mm[1 + a];
             } else {
-                const double vt = (double)g.vt[a * G + node] + (double)g.nref[a * g.d.tiles + tau];
+                const double vt = (double)g.vt[a * G + node];
                 mv[a] = m * vt;
                 x[a] += dt * vt;
             }

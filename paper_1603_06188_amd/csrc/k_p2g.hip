@@ -53,19 +53,15 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
         tile_origin<DIM>(t, g.d.TN, key);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) key[a] += lcoord[a];
-        // the tile's reference velocity: the slab holds momenta relative to it
+        // the tile's reference velocity (the first pass derives it from the
+        // level-0 particles it loads): the slab holds momenta relative to it
         T uref[DIM];
-        tile_reference<T, DIM>(P, start, kstart, cnt, maxc, uref);
-        if (lane == 0) {
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) g.uref[a * g.d.tiles + t] = uref[a];
-        }
         for (int i = lane; i < LSLAB; i += 64) lds[i] = T(0);
         wave_lds_sync();
         if constexpr (DIM == 3) {
             constexpr int CZ = p2g_slices<T, 3, DEG>();
-            p2g_pass3<T, DEG, COMP, 0, CZ>(P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx,
-                                           g.flags, uref, lds);
+            p2g_pass3<T, DEG, COMP, 0, CZ, false, true>(P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm,
+                                                        g.inv_dx, g.flags, uref, lds);
             if constexpr (CZ < K) p2g_pass3<T, DEG, COMP, CZ, (2 * CZ <= K ? CZ : K - CZ)>(
                 P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
             if constexpr (2 * CZ < K) p2g_pass3<T, DEG, COMP, 2 * CZ, (3 * CZ <= K ? CZ : K - 2 * CZ)>(
@@ -73,6 +69,7 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
             if constexpr (3 * CZ < K) p2g_pass3<T, DEG, COMP, 3 * CZ, K - 3 * CZ>(
                 P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
         } else {
+            tile_reference<T, DIM>(P, start, kstart, cnt, maxc, uref);
             T acc_m[K][K], acc_v[2][K][K];
 #pragma unroll
             for (int bb = 0; bb < K; ++bb)
@@ -100,6 +97,10 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
                     slab_add_node<T, COMP, LP, NC>(lds, idx, x);
                     wave_lds_sync();
                 }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) g.uref[a * g.d.tiles + t] = uref[a];
         }
         slab_store<T, DIM, DEG, COMP>(lds, slabs.v + (int64_t)r * slabs.stride);
         wave_lds_sync();

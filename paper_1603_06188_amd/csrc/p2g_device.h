@@ -292,42 +292,56 @@ __device__ __forceinline__ void slab_load(const T *in, T *lds) {
     for (int i = lane_id(); i < SLAB; i += 64) lds[(i / RN) * LP + SL::from_compact(i % RN)] = in[i];
 }
 
-// Reference velocity of a tile (wave-wide): the mean velocity of the
-// particles at level 0 of its keys (lanes with act > 0), rounded by
-// quantize_ref; every lane gets the same value (the butterfly adds the same
-// pairs on every lane).  0 for a tile without particles.
+// Reference velocity of a tile (wave-wide) from the velocities v of the
+// particles at level 0 of its keys (lanes with has = true): their mean,
+// rounded by quantize_ref; every lane gets the same value (the butterfly adds
+// the same pairs on every lane).  0 for a tile without particles.
 template <typename T, int DIM>
-__device__ __forceinline__ void tile_reference(const Parts<T> &P, uint32_t start, uint32_t kstart, uint32_t act,
-                                               uint32_t maxc, T *uref) {
-    const int lane = lane_id();
-    const uint64_t mask = ballot(act > 0);
-    T v[DIM];
-    if (act > 0) {
-        const uint32_t q = (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) v[a] = P.v[a * P.s + q];
-    } else {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) v[a] = T(0);
-    }
+__device__ __forceinline__ void reference_of_level0(const T *v, bool has, T *uref) {
+    const uint64_t mask = ballot(has);
     const T inv_n = mask ? T(1) / (T)popc64(mask) : T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        T x = v[a];
+        T x = has ? v[a] : T(0);
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
         uref[a] = wave_uniform(quantize_ref(x * inv_n));
     }
 }
 
+// The same with the level-0 velocities loaded here (lanes with act > 0).
+template <typename T, int DIM>
+__device__ __forceinline__ void tile_reference(const Parts<T> &P, uint32_t start, uint32_t kstart, uint32_t act,
+                                               uint32_t maxc, T *uref) {
+    const int lane = lane_id();
+    const uint64_t mask = ballot(act > 0);
+    T v[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) v[a] = T(0);
+    if (act > 0) {
+        const uint32_t q = (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) v[a] = P.v[a * P.s + q];
+    }
+    reference_of_level0<T, DIM>(v, act > 0, uref);
+}
+
+// Reference velocity the slab of key tile t was formed with.
+template <typename T, int DIM>
+__device__ __forceinline__ void tile_uref(uint32_t t, const GridState<T> &g, T *uref) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) uref[k] = g.uref[k * g.d.tiles + t];
+}
+
 // Register sums of a key's particles (cnt per key, maxc the tile's busiest)
 // for z-slices [C0, C0+CZ), added into the slab.  MOV: only the first `act`
 // particles of each key (its movers), levels [0, jend).  Momenta are taken
-// relative to the tile's reference velocity uref.
-template <typename T, int DEG, bool COMP, int C0, int CZ, bool MOV = false>
+// relative to the tile's reference velocity uref; DERIVE: uref is first set
+// from the level-0 particles this pass loads (reference_of_level0).
+template <typename T, int DEG, bool COMP, int C0, int CZ, bool MOV = false, bool DERIVE = false>
 __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int lcoord[3], uint32_t start,
                                           uint32_t kstart, uint32_t cnt, uint32_t maxc, uint32_t act, uint32_t jend,
-                                          const StepParams<T> &prm, T inv_dx, uint32_t *flags, const T *uref,
+                                          const StepParams<T> &prm, T inv_dx, uint32_t *flags, T *uref,
                                           T *lds) {
     constexpr int K = DEG + 1;
     const int lane = lane_id();
@@ -347,6 +361,7 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
     uint64_t mask = ballot(cnt > 0);
     P2GRaw<T, 3> raw;
     if (n_act > 0) p2g_load<T, 3>(P, (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane), raw);
+    if constexpr (DERIVE) reference_of_level0<T, 3>(raw.v, n_act > 0, uref);
     for (uint32_t j = 0; j < j_end; ++j) {
         const uint32_t level_n = level + (uint32_t)popc64(mask);
         const uint64_t mask_n = ballot(cnt > j + 1);
