@@ -262,6 +262,32 @@ apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int
                       void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * steps as apic_step(scene, 1, n_steps, 0, stream) on one scene, without a
+ * caller workspace.  scene->workspace and scene->workspace_bytes are
+ * ignored; the library uses a device array of its own instead, one per GPU,
+ * of apic_noalloc_max_bytes() bytes (128 MiB), which it holds until the
+ * process ends.  The call allocates nothing: no hipMalloc, no hipFree, no
+ * allocating library routine, no timing events (apic_timing_enable does not
+ * apply to it).
+ *   - Limit: the scene's workspace (apic_workspace_bytes for its grid and
+ *     particle count) must fit in that array, else APIC_E_WORKSPACE before
+ *     anything is enqueued (a 64^3-cell grid with 262,144 binary32
+ *     particles fits; the 128^3 cube with 2M does not).
+ *   - Every call starts from a cleared array (a fill kernel on `stream`) and
+ *     bins the particles from scratch, so nothing carries over between calls;
+ *     the results are those of apic_step on a freshly reset workspace.
+ *   - All calls on one GPU share its array: calls whose work overlaps on the
+ *     device (different streams, or threads without ordering) race and
+ *     corrupt each other.  Order them on one stream.  The host part of the
+ *     call is serialized by a lock.
+ * Particles end in the caller's planes (binned, as after apic_step).
+ */
+apic_status apic_noalloc_max_bytes(size_t *bytes);
+apic_status apic_step_noalloc(apic_scene *scene, int32_t n_steps, void *stream);
+
+/*
  * Batched steps: the same computation as apic_step for n_scenes independent
  * scenes, but each phase of a step (P2G, grid update, keys, records, G2P)
  * is ONE kernel launch covering every scene, so many small scenes fill the

@@ -45,6 +45,7 @@ EXPORTED = [
     "apic_get_flags", "apic_clear_flags",
     "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
     "apic_last_error", "apic_version", "apic_midpoint_workspace_bytes", "apic_step_midpoint",
+    "apic_noalloc_max_bytes", "apic_step_noalloc",
 ]
 APIC_PHASES = ["p2g", "grid_update", "bin", "g2p", "sort"]
 
@@ -104,6 +105,8 @@ _sigs = {
     "apic_positions_to_absolute": [_S, _V, _V],
     "apic_midpoint_workspace_bytes": [ctypes.POINTER(ApicGridDesc), ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
     "apic_step_midpoint": [_S, ctypes.c_int32, ctypes.POINTER(ApicMidpointOpts), ctypes.POINTER(ApicMidpointStats), _V],
+    "apic_noalloc_max_bytes": [ctypes.POINTER(ctypes.c_size_t)],
+    "apic_step_noalloc": [_S, ctypes.c_int32, _V],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -158,6 +161,17 @@ def apic_step_midpoint(scene: ApicScene, n_steps: int = 1, newton_tol: float = 0
     _check(_lib.apic_step_midpoint(ctypes.byref(scene), int(n_steps), ctypes.byref(o), ctypes.byref(st),
                                    _stream(stream)))
     return {k: getattr(st, k) for k, _ in ApicMidpointStats._fields_ if k != "reserved"}
+
+
+def apic_noalloc_max_bytes() -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.apic_noalloc_max_bytes(ctypes.byref(out)))
+    return out.value
+
+
+def apic_step_noalloc(scene: ApicScene, n_steps: int = 1, stream=None) -> None:
+    """Steps without a workspace (the library's own device array)."""
+    _check(_lib.apic_step_noalloc(ctypes.byref(scene), int(n_steps), _stream(stream)))
 
 
 def apic_reset(scene: ApicScene, stream=None) -> None:

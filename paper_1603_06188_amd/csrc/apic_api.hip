@@ -302,13 +302,17 @@ struct Timing {
 };
 Timing g_timing;
 
+// Set while apic_step_noalloc runs on this thread: no timing events (their
+// creation is left out of a call that promises no allocation).
+thread_local bool g_untimed = false;
+
 // Runs `launch` bracketed by timing events when timing is enabled.
 template <typename F>
 void timed(int phase, hipStream_t st, F &&launch) {
     hipEvent_t a = nullptr, b = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_timing.mu);
-        if (g_timing.enabled) {
+        if (g_timing.enabled && !g_untimed) {
             a = g_timing.take();
             b = g_timing.take();
         }
@@ -965,6 +969,86 @@ apic_status apic_step(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, int
         if (rc != APIC_OK) return rc;
     }
     return APIC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Steps without a caller workspace (apic_step_noalloc): the workspace is a
+// file-scope device array of fixed size, one per GPU, whose address is taken
+// once per device with hipGetSymbolAddress (in host code the array's name is
+// not a device address).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;            // also serializes the calls' host work
+void *g_scratch_ptr[kMaxDevices] = {};
+
+apic_status scratch_address(void **out) {
+    int dev = 0;
+    apic_status rc = hip_check(hipGetDevice(&dev), "apic_step_noalloc: hipGetDevice");
+    if (rc != APIC_OK) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return fail(APIC_E_UNSUPPORTED, "device index %d above %d", dev, kMaxDevices);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "apic_step_noalloc: hipGetSymbolAddress");
+        if (rc != APIC_OK) return rc;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return APIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+apic_status apic_noalloc_max_bytes(size_t *bytes) {
+    if (!bytes) return fail(APIC_E_INVAL, "bytes is NULL");
+    *bytes = kNoAllocBytes;
+    return APIC_OK;
+}
+
+apic_status apic_step_noalloc(apic_scene *scene, int32_t n_steps, void *stream) {
+    if (n_steps < 0) return fail(APIC_E_INVAL, "n_steps must be >= 0");
+    apic_status rc = check_fields(scene);
+    if (rc != APIC_OK) return rc;
+    const int64_t n = scene->p.n > 0 ? scene->p.n : 1;
+    const size_t need = make_layout(&scene->grid, n).total;
+    if (need > kNoAllocBytes)
+        return fail(APIC_E_WORKSPACE,
+                    "apic_step_noalloc: this grid and %lld particles need %zu bytes of workspace, above the %zu "
+                    "the library holds for calls without one",
+                    (long long)scene->p.n, need, kNoAllocBytes);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    void *ptr = nullptr;
+    rc = scratch_address(&ptr);
+    if (rc != APIC_OK) return rc;
+    apic_scene s = *scene;
+    s.workspace = ptr;
+    s.workspace_bytes = kNoAllocBytes;
+    int64_t cap = 0;
+    rc = check_scene(&s, &cap);
+    if (rc != APIC_OK) return rc;
+    {
+        // the array holds whatever the last call left: start from a cleared
+        // workspace (its counters, tags and tables; a fill kernel, no memset)
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_states.erase(ptr);
+    }
+    g_untimed = true;
+    rc = dispatch_steps(&s, cap, n_steps, 0, (hipStream_t)stream);
+    g_untimed = false;
+    {
+        // the next call starts from a cleared array too
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_states.erase(ptr);
+    }
+    return rc;
 }
 
 apic_status apic_batch_workspace_bytes(int32_t n_scenes, size_t *bytes) {
