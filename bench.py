@@ -180,7 +180,8 @@ def batched(n_scenes: int, steps: int):
 
 def spheres(steps: int):
     """Config 3: two spinning spheres, 256^3 cells, cubic B-spline, no gravity,
-    in three precision modes.  Momenta are conserved to round-off while the
+    in binary32 with positions as cell + offset (compensated and plain
+    accumulation) and as plain binary32 coordinates, and in binary64.  Momenta are conserved to round-off while the
     spheres touch neither each other nor a wall; the drift per step is
     reported relative to S = sum_p m_p (|x_p| |v_p| + |B_p|_F)."""
     import numpy as np
@@ -190,12 +191,16 @@ def spheres(steps: int):
     from paper_1603_06188_amd import scenes
 
     out = {}
-    for mode, precision, comp in (("f32_compensated", "fp32", True), ("f32_uncompensated", "fp32", False),
-                                  ("f64", "fp64", False)):
+    for mode, precision, comp, absolute in (("f32_compensated", "fp32", True, False),
+                                            ("f32_uncompensated", "fp32", False, False),
+                                            ("f32_absolute_positions", "fp32", True, True),
+                                            ("f64", "fp64", False, False)):
         s = scenes.spheres3d(precision=precision)
+        if absolute:
+            s = s.with_state(x=s.x.astype(np.float32).astype(np.float64))
         S = float(np.sum(s.m * (np.linalg.norm(s.x, axis=1) * np.linalg.norm(s.v, axis=1)
                                 + np.linalg.norm(s.B.reshape(s.n, -1), axis=1))))
-        ds = b.DeviceScene(s, compensated=comp, with_id=False)
+        ds = b.DeviceScene(s, compensated=comp, with_id=False, absolute=absolute)
         ds.step(2)
         torch.cuda.synchronize()
         d0 = ds.diagnostics()

@@ -102,7 +102,7 @@ enum {
                                  Sec. 3.2); same results up to the order of
                                  the sums.  Ignored by other combinations
                                  and with APIC_OPT_ADAPTIVE_DT.              */
-    APIC_OPT_ADAPTIVE_DT = 4  /* apic_step and apic_step_batch: every step
+    APIC_OPT_ADAPTIVE_DT = 4, /* apic_step and apic_step_batch: every step
                                  of every scene chooses its own dt on the
                                  device by the CFL rule of Sec. 4.3,
                                    dt_k = min(prm.dt, prm.cfl * dx / b_k),
@@ -114,6 +114,21 @@ enum {
                                  that wrote the state (fused into it,
                                  evaluated in the state's precision).  The
                                  steps' dt are read back by apic_step_time. */
+    APIC_OPT_ABSOLUTE_POSITIONS = 8 /* binary32, quadratic or cubic weights,
+                                 not with APIC_OPT_ADAPTIVE_DT nor in
+                                 apic_step_batch: the position is held as the
+                                 plain binary32 coordinate x_p in the `off`
+                                 planes (world units, not cell units), the
+                                 way a plain binary32 code stores it, and the
+                                 kernels derive cell and offset from it
+                                 (s = x / dx, c = floor(s), o = s - c) and
+                                 write x + dt v back.  `cell` must still
+                                 point to a plane of n entries; the library
+                                 writes the derived cell there and never
+                                 reads it.  A comparison mode: cell + offset
+                                 keeps the position to ~2^-24 dx, this one to
+                                 ~2^-24 |x| (Sec. 5.3: the particle's angular
+                                 momentum uses x_p and B_p).                 */
 };
 
 /* Sticky device flag bits (apic_get_flags). */

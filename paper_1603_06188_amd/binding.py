@@ -34,6 +34,7 @@ APIC_TRANSFER_APIC, APIC_TRANSFER_RPIC, APIC_TRANSFER_PIC = 0, 1, 2
 APIC_OPT_COMPENSATED = 1
 APIC_OPT_FUSED_TRANSFER = 2
 APIC_OPT_ADAPTIVE_DT = 4
+APIC_OPT_ABSOLUTE_POSITIONS = 8
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
 APIC_FLAG_UNSORTED = 16
 APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
@@ -293,7 +294,8 @@ def unpack_cells(packed: np.ndarray, dim: int) -> np.ndarray:
     return np.stack([p & 0xFFFF, p >> 16], axis=1).astype(np.int64)
 
 
-def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=False) -> ApicGridDesc:
+def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=False,
+              absolute=False) -> ApicGridDesc:
     """The apic_grid_desc of a host scene."""
     precision = precision or scene.precision
     g = ApicGridDesc()
@@ -301,7 +303,7 @@ def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=Fa
     g.degree = scene.degree
     g.precision = APIC_F32 if precision == "fp32" else APIC_F64
     g.options = ((APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
-                 | (APIC_OPT_ADAPTIVE_DT if adaptive else 0))
+                 | (APIC_OPT_ADAPTIVE_DT if adaptive else 0) | (APIC_OPT_ABSOLUTE_POSITIONS if absolute else 0))
     for a in range(3):
         g.cells[a] = scene.cells[a] if a < scene.dim else 0
     g.dx = scene.dx
@@ -327,8 +329,9 @@ class DeviceScene:
     off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
 
     def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True,
-                 packed=None, fused=False, adaptive=False, midpoint=False):
+                 packed=None, fused=False, adaptive=False, midpoint=False, absolute=False):
         self.host = scene
+        self.absolute = bool(absolute)   # positions as plain binary32 coordinates (APIC_OPT_ABSOLUTE_POSITIONS)
         self.dim = scene.dim
         self.precision = precision or scene.precision
         self.dtype = torch.float32 if self.precision == "fp32" else torch.float64
@@ -341,7 +344,7 @@ class DeviceScene:
         self.cell = torch.zeros(cap, dtype=torch.int32, device=device)
         self.id = torch.arange(cap, dtype=torch.int32, device=device) if with_id else None
         self.upload(scene, packed)
-        g = grid_desc(scene, self.precision, compensated, fused, adaptive)
+        g = grid_desc(scene, self.precision, compensated, fused, adaptive, self.absolute)
         self.wbytes = apic_workspace_bytes(g, cap)
         if midpoint:
             self.wbytes = max(self.wbytes, apic_midpoint_workspace_bytes(g, cap))
@@ -383,20 +386,28 @@ class DeviceScene:
         p.id = self.id.data_ptr() if self.id is not None else None
 
     @staticmethod
-    def pack(scene, dtype):
-        """Host tensors in the device layout: planes [2d+2d^2+1, n] and packed cells [n]."""
+    def pack(scene, dtype, absolute=False):
+        """Host tensors in the device layout: planes [2d+2d^2+1, n] and packed cells [n].
+        absolute: the position planes hold the coordinates x_p (rounded to the
+        plane type) instead of the offsets in the cell."""
         d, n = scene.dim, scene.n
-        planes = np.concatenate([scene.off.T, scene.v.T, scene.B.reshape(n, d * d).T, scene.F.reshape(n, d * d).T,
+        pos = scene.off.T
+        cell = scene.cell
+        if absolute:
+            x = scene.x.astype(np.float32 if dtype == torch.float32 else np.float64)
+            pos = x.T.astype(np.float64)
+            cell = np.floor(x.astype(np.float64) / scene.dx).astype(np.int64)
+        planes = np.concatenate([pos, scene.v.T, scene.B.reshape(n, d * d).T, scene.F.reshape(n, d * d).T,
                                  scene.m[None, :]], axis=0)
         return (torch.from_numpy(np.ascontiguousarray(planes)).to(dtype),
-                torch.from_numpy(pack_cells(scene.cell).view(np.int32)))
+                torch.from_numpy(pack_cells(cell).view(np.int32)))
 
     def upload(self, scene, packed=None):
         n = scene.n
         if n > self.capacity:
             raise ValueError("scene larger than capacity")
         self.n = n
-        host, cells = packed if packed is not None else self.pack(scene, self.dtype)
+        host, cells = packed if packed is not None else self.pack(scene, self.dtype, self.absolute)
         self.f[:, :n].copy_(host, non_blocking=True)
         self.cell[:n].copy_(cells, non_blocking=True)
         if self.id is not None:
@@ -471,10 +482,16 @@ class DeviceScene:
             f = f[:, order]
             cell = cell[order]
         off = f[0:d].T.copy()
+        if self.absolute:
+            # the position planes hold the coordinates
+            x = off
+            off = x / self.host.dx - cell
+        else:
+            x = (cell.astype(np.float64) + off) * self.host.dx
         out = {
             "cell": cell,
             "off": off,
-            "x": (cell.astype(np.float64) + off) * self.host.dx,
+            "x": x,
             "v": f[d:2 * d].T.copy(),
             "B": f[2 * d:2 * d + d * d].T.reshape(n, d, d).copy(),
             "F": f[2 * d + d * d:2 * d + 2 * d * d].T.reshape(n, d, d).copy(),

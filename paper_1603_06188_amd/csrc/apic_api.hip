@@ -176,8 +176,15 @@ apic_status check_grid(const apic_grid_desc *g) {
         return fail(APIC_E_INVAL, "degree must be 1 (multilinear), 2 (quadratic) or 3 (cubic) (got %d)", g->degree);
     if (g->precision != APIC_F32 && g->precision != APIC_F64)
         return fail(APIC_E_INVAL, "precision must be APIC_F32 or APIC_F64 (got %d)", g->precision);
-    if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER | APIC_OPT_ADAPTIVE_DT))
+    if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER | APIC_OPT_ADAPTIVE_DT |
+                       APIC_OPT_ABSOLUTE_POSITIONS))
         return fail(APIC_E_INVAL, "unknown option bits 0x%x", g->options);
+    if (g->options & APIC_OPT_ABSOLUTE_POSITIONS) {
+        if (g->precision != APIC_F32 || g->degree == APIC_MULTILINEAR)
+            return fail(APIC_E_UNSUPPORTED, "absolute positions need binary32 and quadratic or cubic weights");
+        if (g->options & APIC_OPT_ADAPTIVE_DT)
+            return fail(APIC_E_UNSUPPORTED, "absolute positions are not offered with adaptive steps");
+    }
     const int maxc = g->dim == 3 ? 1024 : 65535;
     for (int a = 0; a < g->dim; ++a)
         if (g->cells[a] < g->degree + 1 || g->cells[a] > maxc)
@@ -481,11 +488,11 @@ struct OpArgs {
 
 // Bins the particles of `src` (at their current positions) into list
 // parity `nxt` and writes them, in the new order, to `dst`.
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS = false>
 void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &dst, int nxt, hipStream_t st) {
     begin_build(v, ss, nxt, st);
     launch_bin_reset(v.lists[nxt], st);
-    launch_bin_keys_static<T, DIM, DEG>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, st);
+    launch_bin_keys_static<T, DIM, DEG, ABS>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, v.g.inv_dx, st);
     launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
     launch_bin_finalize(v.lists[nxt], st);
     launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab[nxt], v.sc, st);
@@ -494,21 +501,21 @@ void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> 
 // One G2P from `src` (layout `cur`) into `dst` (layout 1 - cur).  The
 // counters of the new layout were zeroed by the preceding P2G; `reset`
 // zeroes them again (calls outside a whole step).
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS = false>
 void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &dst, int cur, bool reset,
                hipStream_t st) {
     const int nxt = 1 - cur;
     begin_build(v, ss, nxt, st);
     timed(APIC_PHASE_BIN, st, [&] {
         if (reset) launch_bin_reset(v.lists[nxt], st);
-        launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
-                                           st);
+        launch_bin_keys_moved<T, DIM, DEG, ABS>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc,
+                                                v.L.rc, st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
         launch_bin_finalize(v.lists[nxt], st);
     });
     timed(APIC_PHASE_G2P, st, [&] {
-        launch_g2p<T, DIM, DEG>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
-                                v.L.rc, st);
+        launch_g2p<T, DIM, DEG, ABS>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
+                                     v.L.rc, st);
     });
 }
 
@@ -543,14 +550,14 @@ void g2p2g_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T>
     }
 }
 
-template <typename T, int DIM, int DEG, bool COMP>
+template <typename T, int DIM, int DEG, bool COMP, bool ABS>
 apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
     SceneState &ss = state_of(s, cap, st);
     View<T> v = make_view<T>(s, cap, ss);
     switch (op) {
         case Op::Sort: {
             const int nxt = 1 - ss.cur;
-            bin_static<T, DIM, DEG>(v, ss, v.user, v.shadow, nxt, st);
+            bin_static<T, DIM, DEG, ABS>(v, ss, v.user, v.shadow, nxt, st);
             launch_copy_state<T, DIM>(v.shadow, v.user, st);
             ss.cur = nxt;
             ss.binned = true;
@@ -560,12 +567,12 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
         }
         case Op::P2G: {
             if (!ss.binned) {
-                apic_status rc = run<T, DIM, DEG, COMP>(Op::Sort, s, cap, st, a);
+                apic_status rc = run<T, DIM, DEG, COMP, ABS>(Op::Sort, s, cap, st, a);
                 if (rc != APIC_OK) return rc;
                 v = make_view<T>(s, cap, ss);
             }
             launch_keep_affine<T, DIM>(v.user, s->prm.transfer, st);
-            launch_p2g<T, DIM, DEG, COMP>(v.user, v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur], v.slabs, v.g,
+            launch_p2g<T, DIM, DEG, COMP, ABS>(v.user, v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur], v.slabs, v.g,
                                           v.prm, v.L.rc, st);
             ss.grid_meta = ss.cur;
             ss.vt_valid = false;
@@ -580,7 +587,7 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
         case Op::G2P:
             if (!ss.vt_valid || !ss.binned || ss.grid_meta != ss.cur)
                 return fail(APIC_E_INVAL, "apic_g2p needs apic_p2g and apic_grid_update on the current particles");
-            g2p_rebin<T, DIM, DEG>(v, ss, v.user, v.shadow, ss.cur, true, st);
+            g2p_rebin<T, DIM, DEG, ABS>(v, ss, v.user, v.shadow, ss.cur, true, st);
             launch_copy_state<T, DIM>(v.shadow, v.user, st);
             ss.cur = 1 - ss.cur;
             ss.vt_valid = false;
@@ -591,7 +598,7 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
             break;
         case Op::DiagParticles:
             launch_diag_particles<T, DIM>(v.user, s->grid.dx, s->grid.degree != APIC_MULTILINEAR, v.diag_part,
-                                          v.diag_out, st);
+                                          v.diag_out, st, ABS);
             break;
         case Op::DiagEnergy:
             launch_diag_energy<T, DIM>(v.user, s->prm.model, s->prm.mu, s->prm.lambda, s->prm.rho0, v.diag_part,
@@ -606,11 +613,11 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
                                                 v.diag_out, st);
             break;
         case Op::Pack:
-            launch_pack_positions<T, DIM>(v.user, (const double *)a.ptr, s->grid.dx, st);
+            launch_pack_positions<T, DIM>(v.user, (const double *)a.ptr, s->grid.dx, st, ABS);
             ss.binned = false;
             break;
         case Op::Unpack:
-            launch_unpack_positions<T, DIM>(v.user, (double *)a.ptr, s->grid.dx, st);
+            launch_unpack_positions<T, DIM>(v.user, (double *)a.ptr, s->grid.dx, st, ABS);
             break;
     }
     hipError_t e = hipGetLastError();
@@ -620,14 +627,14 @@ apic_status run(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const O
 
 // Whole steps for one scene with the particle state alternating between the
 // caller's buffers and the workspace shadow; ends in the caller's buffers.
-template <typename T, int DIM, int DEG, bool COMP>
+template <typename T, int DIM, int DEG, bool COMP, bool ABS>
 apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_every, hipStream_t st) {
     SceneState &ss = state_of(s, cap, st);
     View<T> v = make_view<T>(s, cap, ss);
     Parts<T> bufs[2] = {v.user, v.shadow};
     int where = 0;
     if (!ss.binned) {
-        timed(APIC_PHASE_SORT, st, [&] { bin_static<T, DIM, DEG>(v, ss, v.user, v.shadow, 1 - ss.cur, st); });
+        timed(APIC_PHASE_SORT, st, [&] { bin_static<T, DIM, DEG, ABS>(v, ss, v.user, v.shadow, 1 - ss.cur, st); });
         ss.cur = 1 - ss.cur;
         where = 1;
     }
@@ -649,7 +656,7 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
     for (int32_t k = 0; k < n_steps; ++k) {
         if (sort_every > 0 && k > 0 && k % sort_every == 0) {
             timed(APIC_PHASE_SORT, st,
-                  [&] { bin_static<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], 1 - ss.cur, st); });
+                  [&] { bin_static<T, DIM, DEG, ABS>(v, ss, bufs[where], bufs[1 - where], 1 - ss.cur, st); });
             ss.cur = 1 - ss.cur;
             where = 1 - where;
             slabs_ready = false;
@@ -664,7 +671,7 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         }
         if (!slabs_ready) {
             timed(APIC_PHASE_P2G, st, [&] {
-                launch_p2g<T, DIM, DEG, COMP>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur],
+                launch_p2g<T, DIM, DEG, COMP, ABS>(bufs[where], v.lists[ss.cur], v.lists[1 - ss.cur], v.tab[ss.cur],
                                               v.slabs, v.g, v.prm, v.L.rc, st);
             });
         }
@@ -673,12 +680,12 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
         });
         ss.grid_meta = ss.cur;
         // the last step of the call leaves the slabs of the step it made
-        const bool fuse = fused_step<T, DIM, DEG>() && (s->grid.options & APIC_OPT_FUSED_TRANSFER) && !adaptive &&
+        const bool fuse = fused_step<T, DIM, DEG>() && !ABS && (s->grid.options & APIC_OPT_FUSED_TRANSFER) && !adaptive &&
                           k + 1 < n_steps && !(sort_every > 0 && (k + 1) % sort_every == 0);
         if (fuse)
             g2p2g_rebin<T, DIM, DEG, COMP>(v, ss, bufs[where], bufs[1 - where], ss.cur, st);
         else
-            g2p_rebin<T, DIM, DEG>(v, ss, bufs[where], bufs[1 - where], ss.cur, false, st);
+            g2p_rebin<T, DIM, DEG, ABS>(v, ss, bufs[where], bufs[1 - where], ss.cur, false, st);
         slabs_ready = fuse;
         ss.cur = 1 - ss.cur;
         where = 1 - where;
@@ -691,10 +698,22 @@ apic_status run_steps(apic_scene *s, int64_t cap, int32_t n_steps, int32_t sort_
     return APIC_OK;
 }
 
+// Absolute binary32 positions exist for binary32 quadratic and cubic weights
+// (checked on the host before any launch).
+template <typename T, int DEG>
+constexpr bool abs_supported() {
+    return std::is_same<T, float>::value && DEG >= 2;
+}
+
 template <typename T, int DIM, int DEG>
 apic_status run_c(Op op, const apic_scene *s, int64_t cap, hipStream_t st, const OpArgs &a) {
-    if (s->grid.options & APIC_OPT_COMPENSATED) return run<T, DIM, DEG, true>(op, s, cap, st, a);
-    return run<T, DIM, DEG, false>(op, s, cap, st, a);
+    const bool comp = (s->grid.options & APIC_OPT_COMPENSATED) != 0;
+    if (s->grid.options & APIC_OPT_ABSOLUTE_POSITIONS) {
+        if constexpr (abs_supported<T, DEG>())
+            return comp ? run<T, DIM, DEG, true, true>(op, s, cap, st, a) : run<T, DIM, DEG, false, true>(op, s, cap, st, a);
+        return fail(APIC_E_UNSUPPORTED, "absolute positions need binary32 and quadratic or cubic weights");
+    }
+    return comp ? run<T, DIM, DEG, true, false>(op, s, cap, st, a) : run<T, DIM, DEG, false, false>(op, s, cap, st, a);
 }
 // f(std::integral_constant<int, DEG>) for the grid's B-spline degree.
 template <typename F>
@@ -727,8 +746,15 @@ apic_status dispatch(Op op, const apic_scene *s, void *stream, const OpArgs &a =
 
 template <typename T, int DIM, int DEG>
 apic_status steps_c(apic_scene *s, int64_t cap, int32_t n, int32_t k, hipStream_t st) {
-    if (s->grid.options & APIC_OPT_COMPENSATED) return run_steps<T, DIM, DEG, true>(s, cap, n, k, st);
-    return run_steps<T, DIM, DEG, false>(s, cap, n, k, st);
+    const bool comp = (s->grid.options & APIC_OPT_COMPENSATED) != 0;
+    if (s->grid.options & APIC_OPT_ABSOLUTE_POSITIONS) {
+        if constexpr (abs_supported<T, DEG>())
+            return comp ? run_steps<T, DIM, DEG, true, true>(s, cap, n, k, st)
+                        : run_steps<T, DIM, DEG, false, true>(s, cap, n, k, st);
+        return fail(APIC_E_UNSUPPORTED, "absolute positions need binary32 and quadratic or cubic weights");
+    }
+    return comp ? run_steps<T, DIM, DEG, true, false>(s, cap, n, k, st)
+                : run_steps<T, DIM, DEG, false, false>(s, cap, n, k, st);
 }
 
 template <typename T, int DIM>
@@ -1075,6 +1101,8 @@ apic_status apic_step_batch(apic_scene *scenes, int32_t n_scenes, int32_t n_step
         const apic_grid_desc &a = scenes[0].grid, &b = scenes[k].grid;
         if (a.dim != b.dim || a.degree != b.degree || a.precision != b.precision || a.options != b.options)
             return fail(APIC_E_INVAL, "scene %d differs from scene 0 in dim, degree, precision or options", k);
+        if (b.options & APIC_OPT_ABSOLUTE_POSITIONS)
+            return fail(APIC_E_UNSUPPORTED, "apic_step_batch does not take absolute positions");
     }
     {
         std::unordered_map<void *, int32_t> seen;

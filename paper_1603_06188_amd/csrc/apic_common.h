@@ -441,6 +441,32 @@ __device__ __forceinline__ float floor_t<float>(float x) { return floorf(x); }
 template <>
 __device__ __forceinline__ double floor_t<double>(double x) { return floor(x); }
 
+// Absolute binary32 positions (APIC_OPT_ABSOLUTE_POSITIONS): the offset
+// planes hold the coordinate x_p itself, and the cell index and offset follow
+// from it as a plain binary32 code computes them: s = x / dx (one rounding),
+// c = floor(s), o = s - c (exact).
+template <typename T>
+__device__ __forceinline__ void cell_of_absolute(T x, T inv_dx, int &c, T &o) {
+    const T s = x * inv_dx;
+    const T f = floor_t(s);
+    c = (int)f;
+    o = s - f;
+}
+
+// Cell index and offset of a particle: from the packed cell and the offset
+// planes, or (ABS) from the absolute coordinates in the offset planes.
+template <typename T, int DIM, bool ABS>
+__device__ __forceinline__ void particle_cells(uint32_t cell, const T *x, T inv_dx, int *ci, T *off) {
+    if constexpr (ABS) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) cell_of_absolute(x[a], inv_dx, ci[a], off[a]);
+    } else {
+        unpack_cell<DIM>(cell, ci);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) off[a] = x[a];
+    }
+}
+
 // wave64 helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 // A value that is the same on every lane, held once per wavefront (scalar

@@ -19,9 +19,9 @@ void launch_copy_state(const Parts<T> &src, const Parts<T> &dst, hipStream_t st)
 void launch_bin_reset(const BinLists &nxt, hipStream_t st);
 
 // Keys of particles at their current positions (apic_sort).
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS = false>
 void launch_bin_keys_static(const Parts<T> &P, const GridDims &d, const BinLists &nxt, const BinScratch &sc,
-                            uint32_t *flags, hipStream_t st);
+                            uint32_t *flags, T inv_dx, hipStream_t st);
 
 // Per listed tile of `nxt`: key counts and prefix sums, the tile's place in
 // its bucket, its record index, level tables and the node tiles of the
@@ -44,7 +44,7 @@ void launch_bin_scatter_copy(const Parts<T> &src, const Parts<T> &dst, const Bin
 // --- transfers ----------------------------------------------------------------
 // P2G over the layout `cur`; also zeroes the counters of `nxt` and the
 // bounds of max |vt| for the grid update and re-binning that follow.
-template <typename T, int DIM, int DEG, bool COMP>
+template <typename T, int DIM, int DEG, bool COMP, bool ABS = false>
 void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, const TileTables &tab,
                 const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm, int64_t max_records,
                 hipStream_t st);
@@ -55,13 +55,13 @@ void launch_grid_update(const BinLists &cur, const Slabs<T> &slabs, const GridSt
 
 // New keys of the particles of layout `cur` after G2P (first pass of
 // apic_g2p): stayer counts per key, movers' keys and ranks, dead ranks.
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS = false>
 void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTables &ctab, const GridState<T> &g,
                            const StepParams<T> &prm, const BinLists &nxt, const BinScratch &sc, int64_t max_records,
                            hipStream_t st);
 
 // G2P proper, writing each particle to its place in layout `nxt`.
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS = false>
 void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const TileTables &ctab,
                 const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const GridState<T> &g,
                 const StepParams<T> &prm, int64_t max_records, hipStream_t st);
@@ -123,7 +123,7 @@ template <typename T, int DIM>
 // affine: include the m_p B_p^T : eps term (not for the lagged C_p of the
 // multilinear kernel)
 void launch_diag_particles(const Parts<T> &P, double dx, bool affine, double *partials, double *out,
-                           hipStream_t st);
+                           hipStream_t st, bool absolute = false);
 
 // Kinetic and neo-Hookean potential energy of the particles in binary64:
 // out[0] T, out[1] Phi (0 for model 0), out[2] T + Phi, out[7] mass.
@@ -152,10 +152,10 @@ void launch_grid_export(const BinLists &gm, const Slabs<T> &slabs, const GridSta
                         hipStream_t st);
 
 template <typename T, int DIM>
-void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStream_t st);
+void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStream_t st, bool absolute);
 
 template <typename T, int DIM>
-void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st);
+void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st, bool absolute);
 
 // --- implicit midpoint (binary64, dense node arrays) ------------------------
 struct MidGrid {

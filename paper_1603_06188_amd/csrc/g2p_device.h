@@ -91,6 +91,24 @@ __device__ __forceinline__ void move_position(const int *ci, const T *off, const
     }
 }
 
+// The same for absolute binary32 positions (APIC_OPT_ABSOLUTE_POSITIONS):
+// xn = x + dt v in absolute coordinates, then its cell and offset as
+// cell_of_absolute derives them; fixed operation order.
+template <typename T, int DIM>
+__device__ __forceinline__ void move_absolute(const T *x, const T *vn, T dt, T inv_dx, T *xn, int *cn, T *on,
+                                              bool &cfl) {
+#pragma clang fp contract(off)
+    cfl = false;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T step = dt * vn[a];
+        const T cells = step * inv_dx;
+        cfl = cfl || !(cells <= T(1) && cells >= T(-1));
+        xn[a] = x[a] + step;
+        cell_of_absolute(xn[a], inv_dx, cn[a], on[a]);
+    }
+}
+
 // The CFL quantity of Sec. 4.3 of one particle's new state, |v| + c |B|_F,
 // evaluated in the state's precision and folded into a running maximum (a
 // NaN state propagates).  The bound passes over particles (first step of a
@@ -251,11 +269,11 @@ struct G2PRaw {
     T m, off[DIM], F[DIM * DIM];
 };
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool ABS = false>
 __device__ __forceinline__ void g2p_load(const Parts<T> &src, uint32_t p, G2PRaw<T, DIM> &r) {
     const int64_t ss = src.s;
     const uint32_t pb = p * (uint32_t)sizeof(T);
-    r.cell = src.cell[p];
+    r.cell = ABS ? 0u : src.cell[p];
     r.m = plane_at(src.m, pb);
     r.id = src.id ? plane_at(src.id, p * 4u) : 0;
 #pragma unroll
@@ -269,20 +287,20 @@ __device__ __forceinline__ void g2p_load(const Parts<T> &src, uint32_t p, G2PRaw
 // velocity, B (stored units) and F, and its base node relative to the tile
 // (lk).  Raises FLAG_CFL when the step exceeds one cell along an axis.
 // B keeps the part of the affine field the transfer carries (APIC_TRANSFER_*).
-template <typename T, int DIM, int DEG>
+// ABS (absolute binary32 positions): `xs` receives the new coordinates (what
+// the offset planes store), and on/cn the cell and offset derived from them;
+// otherwise xs = on.
+template <typename T, int DIM, int DEG, bool ABS = false>
 __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *reg, const int *origin,
                                            const GridState<T> &g, T dt_inv_dx, T gs, int *lk, int *cn, T *on, T *vn,
-                                           T *Bs, T *Fn, int transfer) {
+                                           T *Bs, T *Fn, int transfer, T *xs = nullptr, T dt = T(0)) {
     constexpr int K = DEG + 1;
     using R = VtRegion<DIM>;
     int ci[3] = {0, 0, 0};
-    unpack_cell<DIM>(raw.cell, ci);
     T off[DIM], wf[DIM][K], Bc[DIM * DIM];
+    particle_cells<T, DIM, ABS>(raw.cell, raw.off, g.inv_dx, ci, off);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        off[a] = raw.off[a];
-        lk[a] = axis_w_fixed<T, DEG>(ci[a], off[a], wf[a]) - origin[a];
-    }
+    for (int a = 0; a < DIM; ++a) lk[a] = axis_w_fixed<T, DEG>(ci[a], off[a], wf[a]) - origin[a];
     // One sweep over the support nodes (c, b, a) from LDS: the
     // axis-pair sums Tx_k(a) = sum_{b,c} wy wz vt_k (in the
     // sequence of pass 1), Ty_k(b) = sum_{a,c} wx wz vt_k and
@@ -366,7 +384,10 @@ __device__ __forceinline__ void g2p_update(const G2PRaw<T, DIM> &raw, const T *r
             Fn[rr * DIM + c] = F[rr * DIM + c] + gs * acc;
         }
     bool cfl;
-    move_position<T, DIM>(ci, off, vn, dt_inv_dx, cn, on, cfl);
+    if constexpr (ABS)
+        move_absolute<T, DIM>(raw.off, vn, dt, g.inv_dx, xs, cn, on, cfl);
+    else
+        move_position<T, DIM>(ci, off, vn, dt_inv_dx, cn, on, cfl);
     if (cfl) atomicOr(g.flags, FLAG_CFL);
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) Bs[k] = DEG == 1 ? Gc[k] * g.inv_dx : Bc[k] * g.dx;

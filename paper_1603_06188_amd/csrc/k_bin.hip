@@ -28,18 +28,18 @@ void launch_bin_reset(const BinLists &nxt, hipStream_t st) {
 
 // --- keys of particles at their current position (apic_sort); every particle
 // counts as a mover, so ranks come from the per-key counters ---------------------
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 __global__ __launch_bounds__(256) void k_bin_keys_static(Parts<T> P, GridDims d, BinLists nxt, BinScratch sc,
-                                                         uint32_t *flags) {
+                                                         uint32_t *flags, T inv_dx) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < P.n;
     uint32_t key = kDeadKey;
     if (active) {
         int ci[3] = {0, 0, 0};
-        unpack_cell<DIM>(P.cell[p], ci);
-        T off[DIM];
+        T x[DIM], off[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) off[a] = P.off[a * P.s + p];
+        for (int a = 0; a < DIM; ++a) x[a] = P.off[a * P.s + p];
+        particle_cells<T, DIM, ABS>(ABS ? 0u : P.cell[p], x, inv_dx, ci, off);
         bool finite;
         key = key_of<T, DIM, DEG>(ci, off, d, finite);
         if (key == kDeadKey) atomicOr(flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
@@ -51,12 +51,12 @@ __global__ __launch_bounds__(256) void k_bin_keys_static(Parts<T> P, GridDims d,
     }
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 void launch_bin_keys_static(const Parts<T> &P, const GridDims &d, const BinLists &nxt, const BinScratch &sc,
-                            uint32_t *flags, hipStream_t st) {
+                            uint32_t *flags, T inv_dx, hipStream_t st) {
     if (P.n == 0) return;
-    hipLaunchKernelGGL((k_bin_keys_static<T, DIM, DEG>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P,
-                       d, nxt, sc, flags);
+    hipLaunchKernelGGL((k_bin_keys_static<T, DIM, DEG, ABS>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st,
+                       P, d, nxt, sc, flags, inv_dx);
 }
 
 // --- per listed tile: counts, prefix sums, tile offset, level table ------------------
@@ -261,15 +261,23 @@ template void launch_bin_records<3>(const GridDims &, const BinLists &, const Ti
                                                  hipStream_t);                                                    \
     template void launch_bin_scatter_copy<T, DIM>(const Parts<T> &, const Parts<T> &, const BinLists &,           \
                                                   const TileTables &, const BinScratch &, hipStream_t);           \
-    template void launch_bin_keys_static<T, DIM, 1>(const Parts<T> &, const GridDims &, const BinLists &,         \
-                                                    const BinScratch &, uint32_t *, hipStream_t);                 \
-    template void launch_bin_keys_static<T, DIM, 2>(const Parts<T> &, const GridDims &, const BinLists &,         \
-                                                    const BinScratch &, uint32_t *, hipStream_t);                 \
-    template void launch_bin_keys_static<T, DIM, 3>(const Parts<T> &, const GridDims &, const BinLists &,         \
-                                                    const BinScratch &, uint32_t *, hipStream_t);
+    template void launch_bin_keys_static<T, DIM, 1, false>(const Parts<T> &, const GridDims &, const BinLists &,  \
+                                                           const BinScratch &, uint32_t *, T, hipStream_t);      \
+    template void launch_bin_keys_static<T, DIM, 2, false>(const Parts<T> &, const GridDims &, const BinLists &,  \
+                                                           const BinScratch &, uint32_t *, T, hipStream_t);      \
+    template void launch_bin_keys_static<T, DIM, 3, false>(const Parts<T> &, const GridDims &, const BinLists &,  \
+                                                           const BinScratch &, uint32_t *, T, hipStream_t);
 APIC_BIN_INST(float, 2)
 APIC_BIN_INST(float, 3)
 APIC_BIN_INST(double, 2)
 APIC_BIN_INST(double, 3)
+template void launch_bin_keys_static<float, 2, 2, true>(const Parts<float> &, const GridDims &, const BinLists &,
+                                                        const BinScratch &, uint32_t *, float, hipStream_t);
+template void launch_bin_keys_static<float, 2, 3, true>(const Parts<float> &, const GridDims &, const BinLists &,
+                                                        const BinScratch &, uint32_t *, float, hipStream_t);
+template void launch_bin_keys_static<float, 3, 2, true>(const Parts<float> &, const GridDims &, const BinLists &,
+                                                        const BinScratch &, uint32_t *, float, hipStream_t);
+template void launch_bin_keys_static<float, 3, 3, true>(const Parts<float> &, const GridDims &, const BinLists &,
+                                                        const BinScratch &, uint32_t *, float, hipStream_t);
 
 }  // namespace apic

@@ -40,7 +40,7 @@ __device__ __forceinline__ int local_key(const int *ci, const T *off) {
 // movers take a rank in their new key (or among the dead).  The grid
 // velocities around tile t (first node `origin`) are staged in `reg`.
 // Wave-wide.
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<T> &g, const StepParams<T> &prm,
                                              const BinLists &nxt, const BinScratch &sc, const uint32_t *queue,
                                              uint32_t count, uint32_t t, uint32_t start, const int *origin,
@@ -52,18 +52,24 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
     if (act) {
         q = queue[lane];
         int ci[3] = {0, 0, 0}, base[3] = {0, 0, 0}, lk[3] = {0, 0, 0}, cn[3] = {0, 0, 0};
-        unpack_cell<DIM>(P.cell[q], ci);
-        T off[DIM], w[DIM][DEG + 1], vn[DIM], on[DIM];
+        T x[DIM], off[DIM], w[DIM][DEG + 1], vn[DIM], on[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) x[a] = P.off[a * P.s + q];
+        particle_cells<T, DIM, ABS>(ABS ? 0u : P.cell[q], x, g.inv_dx, ci, off);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            off[a] = P.off[a * P.s + q];
             base[a] = axis_w_fixed<T, DEG>(ci[a], off[a], w[a]);
             lk[a] = base[a] - origin[a];
         }
         const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(base);
         velocity_lds<T, DIM, DEG>(reg, lk, w, vn);
         bool cfl, finite;
-        move_position<T, DIM>(ci, off, vn, prm.dt * g.inv_dx, cn, on, cfl);
+        if constexpr (ABS) {
+            T xn[DIM];
+            move_absolute<T, DIM>(x, vn, prm.dt, g.inv_dx, xn, cn, on, cfl);
+        } else {
+            move_position<T, DIM>(ci, off, vn, prm.dt * g.inv_dx, cn, on, cfl);
+        }
         nkey = key_of<T, DIM, DEG>(cn, on, g.d, finite);
         if (nkey == kDeadKey) atomicOr(g.flags, finite ? FLAG_OUT_OF_DOMAIN : FLAG_NONFINITE);
         if (nkey == mykey)
@@ -78,7 +84,7 @@ __device__ __forceinline__ void resolve_near(const Parts<T> &P, const GridState<
     }
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur, const TileTables &ctab,
                                           const GridState<T> &g, const StepParams<T> &prm_in, const BinLists &nxt,
                                           const BinScratch &sc, uint32_t blk, uint32_t nblk) {
@@ -118,7 +124,7 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
                 const uint32_t i = g0 + 64u * u + (uint32_t)lane;
                 cell[u] = 0u;
                 if (i < total) {
-                    cell[u] = P.cell[start + i];
+                    if constexpr (!ABS) cell[u] = P.cell[start + i];
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) off[u][a] = P.off[a * P.s + start + i];
                 }
@@ -130,9 +136,10 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
                 bool near = false;
                 if (i < total) {
                     int ci[3] = {0, 0, 0};
-                    unpack_cell<DIM>(cell[u], ci);
-                    if (keeps_key<T, DIM, DEG>(off[u], reach))
-                        atomicAdd(stay + local_key<T, DIM, DEG>(ci, off[u]), 1u);
+                    T o[DIM];
+                    particle_cells<T, DIM, ABS>(cell[u], off[u], g.inv_dx, ci, o);
+                    if (keeps_key<T, DIM, DEG>(o, reach))
+                        atomicAdd(stay + local_key<T, DIM, DEG>(ci, o), 1u);
                     else
                         near = true;
                 }
@@ -148,7 +155,7 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
                 }
                 wave_lds_sync();
                 const uint32_t take = queued - q0 < 64u ? queued - q0 : 64u;
-                resolve_near<T, DIM, DEG>(P, g, prm, nxt, sc, queue + q0, take, t, start, origin, reg, stay);
+                resolve_near<T, DIM, DEG, ABS>(P, g, prm, nxt, sc, queue + q0, take, t, start, origin, reg, stay);
             }
             queued = 0;
             wave_lds_sync();
@@ -170,10 +177,10 @@ constexpr int keys_min_waves() {
     return (sizeof(T) == 4 && DIM == 3 && DEG == 2) ? 3 : 1;
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_waves<T, DIM, DEG>()))) void k_bin_keys_moved(
     Parts<T> P, BinLists cur, TileTables ctab, GridState<T> g, StepParams<T> prm, BinLists nxt, BinScratch sc) {
-    keys_body<T, DIM, DEG>(P, cur, ctab, g, prm, nxt, sc, blockIdx.x, gridDim.x);
+    keys_body<T, DIM, DEG, ABS>(P, cur, ctab, g, prm, nxt, sc, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int DIM, int DEG>
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_wa
     const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k);
     const SceneDesc<T> &d = *b.d;
-    keys_body<T, DIM, DEG>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk, b.nblk);
+    keys_body<T, DIM, DEG, false>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk, b.nblk);
 }
 
 template <typename T, int DIM, int DEG>
@@ -191,15 +198,15 @@ void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start
                        n, k);
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTables &ctab, const GridState<T> &g,
                            const StepParams<T> &prm, const BinLists &nxt, const BinScratch &sc, int64_t max_records,
                            hipStream_t st) {
     int64_t blocks = (max_records + (P.n + 63) / 64 + 3) / 4;
     if (blocks < 1) blocks = 1;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((k_bin_keys_moved<T, DIM, DEG>), dim3((unsigned)blocks), dim3(256), 0, st, P, cur, ctab, g,
-                       prm, nxt, sc);
+    hipLaunchKernelGGL((k_bin_keys_moved<T, DIM, DEG, ABS>), dim3((unsigned)blocks), dim3(256), 0, st, P, cur, ctab,
+                       g, prm, nxt, sc);
 }
 
 // --- pass 2: the transfer, written to the new layout ------------------------------------
@@ -209,7 +216,7 @@ void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTab
 // ADAPT: the step's dt comes from the device and the CFL bound of the
 // written state is folded into g.cfl (adaptive steps); a separate
 // instantiation, so that fixed steps carry none of it.
-template <typename T, int DIM, int DEG, bool ADAPT>
+template <typename T, int DIM, int DEG, bool ADAPT, bool ABS = false>
 __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur,
                                          const TileTables &ctab, const BinLists &nxt, const TileTables &ntab,
                                          const BinScratch &sc, const GridState<T> &g, const StepParams<T> &prm_in,
@@ -246,18 +253,26 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         const uint32_t tbase = bases[bucket_of(t)];
         wave_lds_sync();
         G2PRaw<T, DIM> raw;
-        if ((uint32_t)lane < total) g2p_load<T, DIM>(src, start + (uint32_t)lane, raw);
+        if ((uint32_t)lane < total) g2p_load<T, DIM, ABS>(src, start + (uint32_t)lane, raw);
         for (uint32_t c0 = 0; c0 < total; c0 += 64) {
             const uint32_t i = c0 + (uint32_t)lane;
             // the next chunk is in flight while this one is computed
             G2PRaw<T, DIM> raw_n;
-            if (i + 64 < total) g2p_load<T, DIM>(src, start + i + 64, raw_n);
+            if (i + 64 < total) g2p_load<T, DIM, ABS>(src, start + i + 64, raw_n);
             if (i < total) {
                 const uint32_t p = start + i;
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
-                T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM];
-                g2p_update<T, DIM, DEG>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer);
-                const T *off = raw.off;
+                T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM], xs[DIM];
+                g2p_update<T, DIM, DEG, ABS>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer,
+                                             xs, prm.dt);
+                T off[DIM];
+                if constexpr (ABS) {
+                    int ci[3];
+                    particle_cells<T, DIM, true>(0u, raw.off, g.inv_dx, ci, off);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) off[a] = raw.off[a];
+                }
                 const uint32_t mykey = t * 64 + (uint32_t)local_of<DIM>(lk);
                 bool stays = keeps_key<T, DIM, DEG>(off, reach);
                 if (!stays) {
@@ -285,7 +300,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                 if (src.id) plane_at(dst.id, q4) = raw.id;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    plane_at(dst.off + a * ds, qb) = on[a];
+                    plane_at(dst.off + a * ds, qb) = ABS ? xs[a] : on[a];
                     plane_at(dst.v + a * ds, qb) = vn[a];
                 }
 #pragma unroll
@@ -305,11 +320,11 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
     (void)TE;
 }
 
-template <typename T, int DIM, int DEG, bool ADAPT>
+template <typename T, int DIM, int DEG, bool ADAPT, bool ABS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADAPT ? 1 : g2p_min_waves<T, DIM, DEG>()))) void k_g2p(
     Parts<T> src, Parts<T> dst, BinLists cur, TileTables ctab, BinLists nxt, TileTables ntab, BinScratch sc,
     GridState<T> g, StepParams<T> prm) {
-    g2p_body<T, DIM, DEG, ADAPT>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
+    g2p_body<T, DIM, DEG, ADAPT, ABS>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int DIM, int DEG, bool ADAPT>
@@ -402,7 +417,7 @@ void launch_adapt_dt_batch(const SceneDesc<T> *descs, const int32_t *copy_start,
     hipLaunchKernelGGL((k_adapt_dt_batch<T>), dim3((unsigned)n), dim3(64), 0, st, descs);
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS>
 void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, const TileTables &ctab,
                 const BinLists &nxt, const TileTables &ntab, const BinScratch &sc, const GridState<T> &g,
                 const StepParams<T> &prm, int64_t max_records, hipStream_t st) {
@@ -412,12 +427,15 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
     int64_t blocks = (max_records + (src.n + 63) / 64 + 3) / 4;
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
-    if (g.cfl)
-        hipLaunchKernelGGL((k_g2p<T, DIM, DEG, true>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2, cur, ctab,
-                           nxt, ntab, sc, g, prm);
-    else
-        hipLaunchKernelGGL((k_g2p<T, DIM, DEG, false>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2, cur, ctab,
-                           nxt, ntab, sc, g, prm);
+    if constexpr (!ABS) {
+        if (g.cfl) {
+            hipLaunchKernelGGL((k_g2p<T, DIM, DEG, true, false>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2,
+                               cur, ctab, nxt, ntab, sc, g, prm);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_g2p<T, DIM, DEG, false, ABS>), dim3((unsigned)blocks), dim3(256), 0, st, s2, d2, cur, ctab,
+                       nxt, ntab, sc, g, prm);
 }
 
 #define APIC_G2P_INST(T, DIM, DEG)                                                                               \
@@ -425,13 +443,14 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
                                                            hipStream_t);                                          \
     template void launch_g2p_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int, bool,       \
                                                 hipStream_t);                                                     \
-    template void launch_bin_keys_moved<T, DIM, DEG>(const Parts<T> &, const BinLists &, const TileTables &,     \
-                                                     const GridState<T> &, const StepParams<T> &,                \
-                                                     const BinLists &, const BinScratch &, int64_t, hipStream_t); \
-    template void launch_g2p<T, DIM, DEG>(const Parts<T> &, const Parts<T> &, const BinLists &,                  \
-                                          const TileTables &, const BinLists &, const TileTables &,              \
-                                          const BinScratch &, const GridState<T> &, const StepParams<T> &,       \
-                                          int64_t, hipStream_t);
+    template void launch_bin_keys_moved<T, DIM, DEG, false>(const Parts<T> &, const BinLists &, const TileTables &, \
+                                                            const GridState<T> &, const StepParams<T> &,         \
+                                                            const BinLists &, const BinScratch &, int64_t,       \
+                                                            hipStream_t);                                         \
+    template void launch_g2p<T, DIM, DEG, false>(const Parts<T> &, const Parts<T> &, const BinLists &,           \
+                                                 const TileTables &, const BinLists &, const TileTables &,       \
+                                                 const BinScratch &, const GridState<T> &, const StepParams<T> &, \
+                                                 int64_t, hipStream_t);
 APIC_G2P_INST(float, 2, 1)
 APIC_G2P_INST(float, 3, 1)
 APIC_G2P_INST(double, 2, 1)
@@ -444,6 +463,20 @@ APIC_G2P_INST(double, 2, 2)
 APIC_G2P_INST(double, 2, 3)
 APIC_G2P_INST(double, 3, 2)
 APIC_G2P_INST(double, 3, 3)
+
+// absolute binary32 positions: binary32, quadratic and cubic, fixed steps
+#define APIC_G2P_ABS_INST(DIM, DEG)                                                                               \
+    template void launch_bin_keys_moved<float, DIM, DEG, true>(                                                   \
+        const Parts<float> &, const BinLists &, const TileTables &, const GridState<float> &,                    \
+        const StepParams<float> &, const BinLists &, const BinScratch &, int64_t, hipStream_t);                  \
+    template void launch_g2p<float, DIM, DEG, true>(const Parts<float> &, const Parts<float> &, const BinLists &, \
+                                                    const TileTables &, const BinLists &, const TileTables &,    \
+                                                    const BinScratch &, const GridState<float> &,                \
+                                                    const StepParams<float> &, int64_t, hipStream_t);
+APIC_G2P_ABS_INST(2, 2)
+APIC_G2P_ABS_INST(2, 3)
+APIC_G2P_ABS_INST(3, 2)
+APIC_G2P_ABS_INST(3, 3)
 
 template void launch_adapt_dt_batch<float, 2>(const SceneDesc<float> *, const int32_t *, int, int, bool, hipStream_t);
 template void launch_adapt_dt_batch<float, 3>(const SceneDesc<float> *, const int32_t *, int, int, bool, hipStream_t);

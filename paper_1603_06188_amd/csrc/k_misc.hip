@@ -71,16 +71,16 @@ __device__ __forceinline__ void block_reduce8p(double *acc, double *partials) {
     }
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool ABS>
 __global__ __launch_bounds__(256) void k_diag_particles(Parts<T> P, double dx, double affine, double *partials) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += (int64_t)gridDim.x * blockDim.x) {
         int ci[3] = {0, 0, 0};
-        unpack_cell<DIM>(P.cell[p], ci);
+        if constexpr (!ABS) unpack_cell<DIM>(P.cell[p], ci);
         double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, Bm[9];
         const double m = (double)P.m[p];
         for (int a = 0; a < DIM; ++a) {
-            x[a] = ((double)ci[a] + (double)P.off[a * P.s + p]) * dx;
+            x[a] = ABS ? (double)P.off[a * P.s + p] : ((double)ci[a] + (double)P.off[a * P.s + p]) * dx;
             v[a] = (double)P.v[a * P.s + p];
         }
         for (int k = 0; k < DIM * DIM; ++k) Bm[k] = affine * (double)P.B[k * P.s + p];
@@ -124,9 +124,14 @@ void launch_diag_final(const double *partials, int nb, double *out, hipStream_t 
 
 template <typename T, int DIM>
 void launch_diag_particles(const Parts<T> &P, double dx, bool affine, double *partials, double *out,
-                           hipStream_t st) {
+                           hipStream_t st, bool absolute) {
     const int nb = blocks_for(P.n, 256, kDiagBlocks);
-    hipLaunchKernelGGL((k_diag_particles<T, DIM>), dim3(nb), dim3(256), 0, st, P, dx, affine ? 1.0 : 0.0, partials);
+    if (absolute)
+        hipLaunchKernelGGL((k_diag_particles<T, DIM, true>), dim3(nb), dim3(256), 0, st, P, dx, affine ? 1.0 : 0.0,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_diag_particles<T, DIM, false>), dim3(nb), dim3(256), 0, st, P, dx, affine ? 1.0 : 0.0,
+                           partials);
     launch_diag_final(partials, nb, out, st);
 }
 
@@ -308,10 +313,24 @@ int launch_cfl_partials(const Parts<T> &P, double c, double *partials, hipStream
 
 // --- absolute positions <-> cell + offset ---------------------------------------
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_pack_positions(Parts<T> P, const double *x, double inv_dx) {
+__global__ __launch_bounds__(256) void k_pack_positions(Parts<T> P, const double *x, double inv_dx, int absolute) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P.n) return;
     int ci[3] = {0, 0, 0};
+    if (absolute) {
+        // the coordinate itself, rounded to the plane's type (the cell plane
+        // gets the cell that rounded coordinate lies in)
+        for (int a = 0; a < DIM; ++a) {
+            const T xa = (T)x[a * P.s + p];
+            T o;
+            cell_of_absolute(xa, (T)inv_dx, ci[a], o);
+            const int lim = DIM == 3 ? 1023 : 65535;
+            ci[a] = ci[a] < 0 ? 0 : (ci[a] > lim ? lim : ci[a]);
+            P.off[a * P.s + p] = xa;
+        }
+        P.cell[p] = pack_cell<DIM>(ci);
+        return;
+    }
     for (int a = 0; a < DIM; ++a) {
         const double sx = x[a * P.s + p] * inv_dx;
         double c = floor(sx);
@@ -328,37 +347,43 @@ __global__ __launch_bounds__(256) void k_pack_positions(Parts<T> P, const double
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_unpack_positions(Parts<T> P, double *x, double dx) {
+__global__ __launch_bounds__(256) void k_unpack_positions(Parts<T> P, double *x, double dx, int absolute) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P.n) return;
+    if (absolute) {
+        for (int a = 0; a < DIM; ++a) x[a * P.s + p] = (double)P.off[a * P.s + p];
+        return;
+    }
     int ci[3] = {0, 0, 0};
     unpack_cell<DIM>(P.cell[p], ci);
     for (int a = 0; a < DIM; ++a) x[a * P.s + p] = ((double)ci[a] + (double)P.off[a * P.s + p]) * dx;
 }
 
 template <typename T, int DIM>
-void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStream_t st) {
+void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStream_t st, bool absolute) {
     if (P.n == 0) return;
     hipLaunchKernelGGL((k_pack_positions<T, DIM>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, x,
-                       1.0 / dx);
+                       1.0 / dx, absolute ? 1 : 0);
 }
 
 template <typename T, int DIM>
-void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st) {
+void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st, bool absolute) {
     if (P.n == 0) return;
-    hipLaunchKernelGGL((k_unpack_positions<T, DIM>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, x, dx);
+    hipLaunchKernelGGL((k_unpack_positions<T, DIM>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, x, dx,
+                       absolute ? 1 : 0);
 }
 
 #define APIC_MISC_INST(T, DIM)                                                                                  \
     template void launch_copy_state<T, DIM>(const Parts<T> &, const Parts<T> &, hipStream_t);                    \
-    template void launch_diag_particles<T, DIM>(const Parts<T> &, double, bool, double *, double *, hipStream_t); \
+    template void launch_diag_particles<T, DIM>(const Parts<T> &, double, bool, double *, double *, hipStream_t,  \
+                                                bool);                                                            \
     template void launch_diag_energy<T, DIM>(const Parts<T> &, int, double, double, double, double *, double *,    \
                                              hipStream_t);                                                     \
     template void launch_cfl_bound<T, DIM>(const Parts<T> &, double, double *, double *, hipStream_t);         \
     template int launch_cfl_partials<T, DIM>(const Parts<T> &, double, double *, hipStream_t);                  \
     template void launch_keep_affine<T, DIM>(const Parts<T> &, int, hipStream_t);                                \
-    template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t);         \
-    template void launch_unpack_positions<T, DIM>(const Parts<T> &, double *, double, hipStream_t);
+    template void launch_pack_positions<T, DIM>(const Parts<T> &, const double *, double, hipStream_t, bool);   \
+    template void launch_unpack_positions<T, DIM>(const Parts<T> &, double *, double, hipStream_t, bool);
 APIC_MISC_INST(float, 2)
 APIC_MISC_INST(float, 3)
 APIC_MISC_INST(double, 2)

@@ -19,7 +19,7 @@
 
 namespace apic {
 
-template <typename T, int DIM, int DEG, bool COMP>
+template <typename T, int DIM, int DEG, bool COMP, bool ABS = false>
 __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur, const BinLists &nxt,
                                          const TileTables &tab, const Slabs<T> &slabs, const GridState<T> &g,
                                          const StepParams<T> &prm_in, uint32_t blk, uint32_t nblk) {
@@ -60,13 +60,14 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
         wave_lds_sync();
         if constexpr (DIM == 3) {
             constexpr int CZ = p2g_slices<T, 3, DEG>();
-            p2g_pass3<T, DEG, COMP, 0, CZ, false, true>(P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm,
-                                                        g.inv_dx, g.flags, uref, lds);
-            if constexpr (CZ < K) p2g_pass3<T, DEG, COMP, CZ, (2 * CZ <= K ? CZ : K - CZ)>(
+            p2g_pass3<T, DEG, COMP, 0, CZ, false, true, ABS>(P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc,
+                                                             prm, g.inv_dx, g.flags, uref, lds);
+            if constexpr (CZ < K) p2g_pass3<T, DEG, COMP, CZ, (2 * CZ <= K ? CZ : K - CZ), false, false, ABS>(
                 P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
-            if constexpr (2 * CZ < K) p2g_pass3<T, DEG, COMP, 2 * CZ, (3 * CZ <= K ? CZ : K - 2 * CZ)>(
-                P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
-            if constexpr (3 * CZ < K) p2g_pass3<T, DEG, COMP, 3 * CZ, K - 3 * CZ>(
+            if constexpr (2 * CZ < K)
+                p2g_pass3<T, DEG, COMP, 2 * CZ, (3 * CZ <= K ? CZ : K - 2 * CZ), false, false, ABS>(
+                    P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
+            if constexpr (3 * CZ < K) p2g_pass3<T, DEG, COMP, 3 * CZ, K - 3 * CZ, false, false, ABS>(
                 P, key, lcoord, start, kstart, cnt, maxc, cnt, maxc, prm, g.inv_dx, g.flags, uref, lds);
         } else {
             tile_reference<T, DIM>(P, start, kstart, cnt, maxc, uref);
@@ -81,9 +82,9 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
                 if (cnt > jj) {
                     const int64_t q = particle_at(start, kstart, level, mask, jj, maxc, lane);
                     P2GRaw<T, 2> raw;
-                    p2g_load<T, 2>(P, (uint32_t)q, raw);
+                    p2g_load<T, 2, ABS>(P, (uint32_t)q, raw);
                     P2GParticle<T, 2, DEG> pp;
-                    if (p2g_prepare<T, 2, DEG>(raw, key, prm, g.inv_dx, g.flags, uref, pp))
+                    if (p2g_prepare<T, 2, DEG, ABS>(raw, key, prm, g.inv_dx, g.flags, uref, pp))
                         p2g_accumulate2<T, DEG>(pp, acc_m, acc_v);
                 }
                 level += (uint32_t)popc64(mask);
@@ -114,10 +115,10 @@ constexpr int p2g_min_waves() {
     return (sizeof(T) == 4 && DIM == 3 && DEG == 3) ? 2 : 1;
 }
 
-template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(p2g_min_waves<T, DIM, DEG>()))) void k_p2g(Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs,
-                                             GridState<T> g, StepParams<T> prm) {
-    p2g_body<T, DIM, DEG, COMP>(P, cur, nxt, tab, slabs, g, prm, blockIdx.x, gridDim.x);
+template <typename T, int DIM, int DEG, bool COMP, bool ABS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(p2g_min_waves<T, DIM, DEG>()))) void k_p2g(
+    Parts<T> P, BinLists cur, BinLists nxt, TileTables tab, Slabs<T> slabs, GridState<T> g, StepParams<T> prm) {
+    p2g_body<T, DIM, DEG, COMP, ABS>(P, cur, nxt, tab, slabs, g, prm, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
@@ -132,15 +133,15 @@ void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, in
     hipLaunchKernelGGL((k_p2g_batch<T, DIM, DEG, COMP>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
 }
 
-template <typename T, int DIM, int DEG, bool COMP>
+template <typename T, int DIM, int DEG, bool COMP, bool ABS>
 void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, const TileTables &tab,
                 const Slabs<T> &slabs, const GridState<T> &g, const StepParams<T> &prm, int64_t max_records,
                 hipStream_t st) {
     int64_t blocks = (max_records + 3) / 4;
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL((k_p2g<T, DIM, DEG, COMP>), dim3((unsigned)blocks), dim3(256), 0, st, P, cur, nxt, tab, slabs,
-                       g, prm);
+    hipLaunchKernelGGL((k_p2g<T, DIM, DEG, COMP, ABS>), dim3((unsigned)blocks), dim3(256), 0, st, P, cur, nxt, tab,
+                       slabs, g, prm);
 }
 
 #define APIC_P2G_INST(T, DIM, DEG)                                                                                \
@@ -148,12 +149,12 @@ void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, con
                                                        hipStream_t);                                              \
     template void launch_p2g_batch<T, DIM, DEG, true>(const SceneDesc<T> *, const int32_t *, int, int, int,         \
                                                       hipStream_t);                                               \
-    template void launch_p2g<T, DIM, DEG, false>(const Parts<T> &, const BinLists &, const BinLists &,           \
-                                                 const TileTables &, const Slabs<T> &, const GridState<T> &,     \
-                                                 const StepParams<T> &, int64_t, hipStream_t);                   \
-    template void launch_p2g<T, DIM, DEG, true>(const Parts<T> &, const BinLists &, const BinLists &,            \
-                                                const TileTables &, const Slabs<T> &, const GridState<T> &,      \
-                                                const StepParams<T> &, int64_t, hipStream_t);
+    template void launch_p2g<T, DIM, DEG, false, false>(const Parts<T> &, const BinLists &, const BinLists &,    \
+                                                        const TileTables &, const Slabs<T> &, const GridState<T> &, \
+                                                        const StepParams<T> &, int64_t, hipStream_t);            \
+    template void launch_p2g<T, DIM, DEG, true, false>(const Parts<T> &, const BinLists &, const BinLists &,     \
+                                                       const TileTables &, const Slabs<T> &, const GridState<T> &, \
+                                                       const StepParams<T> &, int64_t, hipStream_t);
 APIC_P2G_INST(float, 2, 1)
 APIC_P2G_INST(float, 3, 1)
 APIC_P2G_INST(double, 2, 1)
@@ -166,5 +167,20 @@ APIC_P2G_INST(double, 2, 2)
 APIC_P2G_INST(double, 2, 3)
 APIC_P2G_INST(double, 3, 2)
 APIC_P2G_INST(double, 3, 3)
+
+// absolute binary32 positions: binary32, quadratic and cubic
+#define APIC_P2G_ABS_INST(DIM, DEG)                                                                                \
+    template void launch_p2g<float, DIM, DEG, false, true>(const Parts<float> &, const BinLists &,              \
+                                                           const BinLists &, const TileTables &,                 \
+                                                           const Slabs<float> &, const GridState<float> &,       \
+                                                           const StepParams<float> &, int64_t, hipStream_t);     \
+    template void launch_p2g<float, DIM, DEG, true, true>(const Parts<float> &, const BinLists &, const BinLists &, \
+                                                          const TileTables &, const Slabs<float> &,              \
+                                                          const GridState<float> &, const StepParams<float> &,   \
+                                                          int64_t, hipStream_t);
+APIC_P2G_ABS_INST(2, 2)
+APIC_P2G_ABS_INST(2, 3)
+APIC_P2G_ABS_INST(3, 2)
+APIC_P2G_ABS_INST(3, 3)
 
 }  // namespace apic

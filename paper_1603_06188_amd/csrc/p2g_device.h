@@ -23,11 +23,12 @@ struct P2GRaw {
     T m, off[DIM], v[DIM], B[DIM * DIM], F[DIM * DIM];
 };
 
-template <typename T, int DIM>
+// ABS: absolute positions in the offset planes; the cell plane is not read.
+template <typename T, int DIM, bool ABS = false>
 __device__ __forceinline__ void p2g_load(const Parts<T> &P, uint32_t q, P2GRaw<T, DIM> &r) {
     const int64_t s = P.s;
     const uint32_t qb = q * (uint32_t)sizeof(T);
-    r.cell = P.cell[q];
+    r.cell = ABS ? 0u : P.cell[q];
     r.m = plane_at(P.m, qb);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -44,21 +45,20 @@ __device__ __forceinline__ void p2g_load(const Parts<T> &P, uint32_t q, P2GRaw<T
 // Checks a loaded particle and forms its per-particle terms, its momentum
 // relative to the reference velocity uref of its tile.  Returns false (and
 // sets a flag) when the particle must be skipped.
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool ABS = false>
 __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *key, const StepParams<T> &prm,
                                             T inv_dx, uint32_t *flags, const T *uref,
                                             P2GParticle<T, DIM, DEG> &pp) {
     int ci[3] = {0, 0, 0};
-    unpack_cell<DIM>(r.cell, ci);
     T off[DIM], v[DIM], B[DIM * DIM], F[DIM * DIM];
     const T m = r.m;
     bool finite = is_finite(m);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        off[a] = r.off[a];
         v[a] = r.v[a];
-        finite = finite && is_finite(off[a]) && is_finite(v[a]);
+        finite = finite && is_finite(r.off[a]) && is_finite(v[a]);
     }
+    particle_cells<T, DIM, ABS>(r.cell, r.off, inv_dx, ci, off);
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) {
         B[k] = r.B[k];
@@ -338,7 +338,7 @@ __device__ __forceinline__ void tile_uref(uint32_t t, const GridState<T> &g, T *
 // particles of each key (its movers), levels [0, jend).  Momenta are taken
 // relative to the tile's reference velocity uref; DERIVE: uref is first set
 // from the level-0 particles this pass loads (reference_of_level0).
-template <typename T, int DEG, bool COMP, int C0, int CZ, bool MOV = false, bool DERIVE = false>
+template <typename T, int DEG, bool COMP, int C0, int CZ, bool MOV = false, bool DERIVE = false, bool ABS = false>
 __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int lcoord[3], uint32_t start,
                                           uint32_t kstart, uint32_t cnt, uint32_t maxc, uint32_t act, uint32_t jend,
                                           const StepParams<T> &prm, T inv_dx, uint32_t *flags, T *uref,
@@ -360,17 +360,17 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
     uint32_t level = 0;
     uint64_t mask = ballot(cnt > 0);
     P2GRaw<T, 3> raw;
-    if (n_act > 0) p2g_load<T, 3>(P, (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane), raw);
+    if (n_act > 0) p2g_load<T, 3, ABS>(P, (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane), raw);
     if constexpr (DERIVE) reference_of_level0<T, 3>(raw.v, n_act > 0, uref);
     for (uint32_t j = 0; j < j_end; ++j) {
         const uint32_t level_n = level + (uint32_t)popc64(mask);
         const uint64_t mask_n = ballot(cnt > j + 1);
         P2GRaw<T, 3> raw_n;
         if (n_act > j + 1)
-            p2g_load<T, 3>(P, (uint32_t)particle_at(start, kstart, level_n, mask_n, j + 1, maxc, lane), raw_n);
+            p2g_load<T, 3, ABS>(P, (uint32_t)particle_at(start, kstart, level_n, mask_n, j + 1, maxc, lane), raw_n);
         if (n_act > j) {
             P2GParticle<T, 3, DEG> pp;
-            if (p2g_prepare<T, 3, DEG>(raw, key, prm, inv_dx, flags, uref, pp))
+            if (p2g_prepare<T, 3, DEG, ABS>(raw, key, prm, inv_dx, flags, uref, pp))
                 p2g_accumulate3<T, DEG, C0, CZ>(pp, acc_m, acc_v);
         }
         raw = raw_n;

@@ -76,13 +76,25 @@ def test_host_validation_without_gpu():
     nbytes = b.apic_workspace_bytes(g, 2_097_152)
     # grid planes + shadow state dominate: at least 2M * 104 B
     assert nbytes > 2_097_152 * 104
-    for field, value in (("dim", 4), ("degree", 0), ("degree", 4), ("precision", 7), ("options", 8)):
+    for field, value in (("dim", 4), ("degree", 0), ("degree", 4), ("precision", 7), ("options", 16)):
         old = getattr(g, field)
         setattr(g, field, value)
         with pytest.raises(b.ApicError) as e:
             b.apic_workspace_bytes(g, 10)
         assert e.value.code == -1
         setattr(g, field, old)
+    # absolute binary32 positions: binary32, quadratic or cubic, fixed steps only
+    g.options = b.APIC_OPT_ABSOLUTE_POSITIONS
+    assert b.apic_workspace_bytes(g, 10) > 0
+    for field, value in (("precision", b.APIC_F64), ("degree", b.APIC_MULTILINEAR),
+                         ("options", b.APIC_OPT_ABSOLUTE_POSITIONS | b.APIC_OPT_ADAPTIVE_DT)):
+        old = getattr(g, field)
+        setattr(g, field, value)
+        with pytest.raises(b.ApicError) as e:
+            b.apic_workspace_bytes(g, 10)
+        assert e.value.code == b.APIC_E_UNSUPPORTED
+        setattr(g, field, old)
+    g.options = 0
     g.cells[1] = 2000
     with pytest.raises(b.ApicError):
         b.apic_workspace_bytes(g, 10)

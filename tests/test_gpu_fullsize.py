@@ -87,14 +87,11 @@ def spheres32():
     return scenes.spheres3d(precision="fp32")
 
 
-def test_spheres_full_size_f32_step_matches_oracle(spheres32):
-    """The two-sphere workload at full size (256^3 cells, cubic, ~9.0M
-    particles), compensated binary32: one step against the FP64 oracle on the
-    same input, within the binary32 bar of 1e-5 per field (grid mass and
-    momentum included)."""
+def _spheres_step_errors(s, ref, **kw):
+    """One GPU step phase by phase; per-field errors against the oracle's step."""
+    import torch
     from paper_1603_06188_amd import binding as b
-    s = spheres32
-    ds = b.DeviceScene(s, compensated=True)
+    ds = b.DeviceScene(s, with_id=True, **kw)
     ds.p2g()
     m = ds.export(b.APIC_GRID_MASS)
     mv = ds.export(b.APIC_GRID_MOMENTUM)
@@ -102,18 +99,55 @@ def test_spheres_full_size_f32_step_matches_oracle(spheres32):
     ds.g2p()
     got = ds.state()
     assert ds.flags() == 0
-    g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
-    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
     errs = {"m": rel(m, ref["m"]), "mv": rel(mv, ref["mv"] + s.dt * ref["f"]),
             "x_cells": float(np.abs(got["x"] - ref["x_new"]).max() / s.dx)}
     for key in ("v", "B", "F"):
         errs[key] = rel(got[key], ref[key + "_new"])
-    # B sums terms of size |v| dx ~ 8e-3 into |B| ~ 2.5e-5; the grid carries
-    # velocities relative to per-tile reference velocities, so its rounding
-    # scales with the velocity differences inside a tile, not with |v|
-    print("spheres f32 compensated per-field errors", errs, flush=True)
-    for key, e in errs.items():
-        assert e <= 1e-5, (key, e)
+    del ds
+    torch.cuda.empty_cache()
+    return errs
+
+
+def test_spheres_full_size_f32_step_matches_oracle(spheres32):
+    """The two-sphere workload at full size (256^3 cells, cubic, ~9.0M
+    particles), binary32 with positions as cell + offset, compensated and
+    plain accumulation: one step against the FP64 oracle on the same input,
+    within the binary32 bar of 1e-5 per field (grid mass and momentum
+    included).  B sums terms of size |v| dx ~ 8e-3 into |B| ~ 2.5e-5: the
+    transfer to grid sums momenta relative to per-tile reference velocities,
+    so its rounding scales with the velocity differences inside a tile, not
+    with |v|."""
+    s = spheres32
+    g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
+    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
+    for label, comp in (("compensated", True), ("plain accumulation", False)):
+        errs = _spheres_step_errors(s, ref, compensated=comp)
+        print(f"spheres f32 cell+offset {label} per-field errors", errs, flush=True)
+        for key, e in errs.items():
+            assert e <= 1e-5, (label, key, e)
+
+
+def test_spheres_full_size_absolute_f32_step(spheres32):
+    """The same step with positions held as plain binary32 coordinates
+    (APIC_OPT_ABSOLUTE_POSITIONS), from the binary32-rounded coordinates on
+    both sides: the transfers see the same offsets (dx is a power of two, so
+    x / dx - floor(x / dx) is exact), so m, mv, v, B and F stay within 1e-5;
+    the stored position is rounded to a unit in the last place of x, not of
+    the offset: the bound in cell units is half an ulp of max |x| over dx
+    plus dt times the velocity bar, a few 1e-6 cells here against ~1e-8 for
+    cell + offset."""
+    s0 = spheres32
+    s = s0.with_state(x=s0.x.astype(np.float32).astype(np.float64))
+    g = oracle.Grid(s.dim, s.degree, s.cells, s.dx)
+    ref = oracle.step(g, s.x, s.v, s.B, s.F, s.m, s.V, s.model, s.mu, s.lam, s.dt, s.gravity, s.band, transfer=s.transfer)
+    errs = _spheres_step_errors(s, ref, compensated=True, absolute=True)
+    print("spheres f32 absolute positions per-field errors", errs, flush=True)
+    for key in ("m", "mv", "v", "B", "F"):
+        assert errs[key] <= 1e-5, (key, errs[key])
+    xmax = float(np.abs(ref["x_new"]).max())
+    half_ulp = np.spacing(np.float32(xmax)).astype(np.float64) / 2
+    bound = (half_ulp + s.dt * 1e-5 * float(np.abs(ref["v_new"]).max())) / s.dx * 1.01
+    assert errs["x_cells"] <= bound, (errs["x_cells"], bound)
 
 
 def test_spheres_full_size_f32_momenta_drift_within_roundoff(spheres32):
