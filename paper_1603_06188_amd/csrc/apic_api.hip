@@ -1268,57 +1268,61 @@ const char *apic_version(void) { return "libapic 0.2 (gfx950)"; }
 // ---------------------------------------------------------------------------
 namespace {
 
+// sticky bands do not change the workspace layout
+constexpr int32_t kNoBand[6] = {0, 0, 0, 0, 0, 0};
+
 struct MidLayout {
-    size_t gm, mf, gv, dv, dvt, f, r, rc, pv, s, delta, part, out, flags, tflags;
-    size_t key, perm, count, cursor, start, bsum, scell, soff, sF, sm, smv, sM, total;
-    int64_t nodes, nblk;
+    size_t mf, gv, dv, dvt, r, rc, pv, s, delta, part, epart, out, flags, tflags, counts, cg;
+    size_t key, perm, count, cursor, start, bsum, klist, nlist, slot, slab, scell, soff, sF, sm, smv, sM, total;
+    MidGrid g;
 };
 
-MidLayout mid_layout(const apic_grid_desc &g, int64_t n) {
+MidLayout mid_layout(const apic_grid_desc &gd, const int32_t *band, int64_t n) {
     MidLayout L{};
-    int64_t nodes = 1;
-    for (int a = 0; a < g.dim; ++a) nodes *= (int64_t)g.cells[a] + 1;
-    L.nodes = nodes;
-    int N[3] = {1, 1, 1};
-    for (int a = 0; a < g.dim; ++a) N[a] = g.cells[a] + 1;
-    L.nblk = std::max(std::max(mid_particle_blocks(std::max<int64_t>(n, 1)), mid_node_blocks(nodes)),
-                      mid_collect_blocks(g.dim, N));
+    L.g = mid_grid(gd.dim, gd.cells, band, gd.dx);
+    const MidGrid &g = L.g;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = align_up(o + bytes);
         return o;
     };
-    const size_t vb = (size_t)nodes * g.dim * sizeof(double);
-    L.gm = take((size_t)nodes * sizeof(double));
-    L.mf = take((size_t)nodes * sizeof(double));
+    const size_t vb = (size_t)g.nodes * gd.dim * sizeof(double);
+    const size_t np = (size_t)std::max<int64_t>(n, 1);
+    // a key tile is listed only when it holds a particle
+    const size_t maxk = (size_t)std::min<int64_t>(g.tiles, std::max<int64_t>(n, 1));
+    L.mf = take((size_t)g.nodes * sizeof(double));
     L.gv = take(vb);
     L.dv = take(vb);
     L.dvt = take(vb);
-    L.f = take(vb);
     L.r = take(vb);
     L.rc = take(vb);
     L.pv = take(vb);
     L.s = take(vb);
     L.delta = take(vb);
-    L.part = take((size_t)L.nblk * 2 * sizeof(double));
+    L.part = take((size_t)mid_node_blocks(g.tiles) * 2 * sizeof(double));
+    L.epart = take(maxk * sizeof(double));
     L.out = take(4 * sizeof(double));
     L.flags = take(sizeof(uint32_t));
     L.tflags = take(sizeof(uint32_t));
-    // particles sorted by base node
-    const size_t np = (size_t)std::max<int64_t>(n, 1);
+    L.counts = take(2 * sizeof(int32_t));
+    L.cg = take(sizeof(MidCg));
     L.key = take(np * 4);
     L.perm = take(np * 4);
-    L.count = take((size_t)nodes * 4);
-    L.cursor = take((size_t)nodes * 4);
-    L.start = take((size_t)(nodes + 1) * 4);
-    L.bsum = take((size_t)mid_scan_blocks(nodes) * 4);
+    L.count = take((size_t)g.nodes * 4);
+    L.cursor = take((size_t)g.nodes * 4);
+    L.start = take((size_t)(g.nodes + 1) * 4);
+    L.bsum = take((size_t)mid_scan_blocks(g.nodes) * 4);
+    L.klist = take((size_t)g.tiles * 4);
+    L.nlist = take((size_t)g.tiles * 4);
+    L.slot = take((size_t)g.tiles * 4);
+    L.slab = take(maxk * (size_t)(1 + gd.dim) * mid_region_nodes(gd.dim, gd.degree) * sizeof(double));
     L.scell = take(np * 4);
-    L.soff = take(np * g.dim * sizeof(double));
-    L.sF = take(np * g.dim * g.dim * sizeof(double));
+    L.soff = take(np * gd.dim * sizeof(double));
+    L.sF = take(np * gd.dim * gd.dim * sizeof(double));
     L.sm = take(np * sizeof(double));
-    L.smv = take(np * g.dim * sizeof(double));
-    L.sM = take(np * g.dim * g.dim * sizeof(double));
+    L.smv = take(np * gd.dim * sizeof(double));
+    L.sM = take(np * (gd.dim * gd.dim + 1) * sizeof(double));
     L.total = off;
     return L;
 }
@@ -1328,23 +1332,24 @@ struct MidOpts {
     int max_newton, max_cg;
 };
 
+// CG iterations launched between two looks at the device's stop flag.
+constexpr int kCgPoll = 8;
+
 template <int DIM, int DEG>
 apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpoint_stats *stats, hipStream_t st) {
-    const MidLayout L = mid_layout(s->grid, s->p.n);
+    const MidLayout L = mid_layout(s->grid, s->prm.band, s->p.n);
+    const MidGrid &g = L.g;
     char *ws = (char *)s->workspace;
-    double *gm = (double *)(ws + L.gm), *mf = (double *)(ws + L.mf), *gv = (double *)(ws + L.gv);
-    double *dv = (double *)(ws + L.dv), *dvt = (double *)(ws + L.dvt), *f = (double *)(ws + L.f);
+    double *mf = (double *)(ws + L.mf), *gv = (double *)(ws + L.gv);
+    double *dv = (double *)(ws + L.dv), *dvt = (double *)(ws + L.dvt);
     double *r = (double *)(ws + L.r), *rc = (double *)(ws + L.rc), *pv = (double *)(ws + L.pv);
     double *sv = (double *)(ws + L.s), *delta = (double *)(ws + L.delta), *part = (double *)(ws + L.part);
-    double *out = (double *)(ws + L.out);
+    double *epart = (double *)(ws + L.epart), *out = (double *)(ws + L.out);
     uint32_t *flags = (uint32_t *)(ws + L.flags);
     uint32_t *tflags = (uint32_t *)(ws + L.tflags);  // flags of the iterate being tried
+    int32_t *counts = (int32_t *)(ws + L.counts);
+    MidCg *cg = (MidCg *)(ws + L.cg);
 
-    MidGrid g{};
-    for (int a = 0; a < 3; ++a) g.N[a] = a < DIM ? s->grid.cells[a] + 1 : 1;
-    for (int k = 0; k < 6; ++k) g.band[k] = s->prm.band[k];
-    g.nodes = L.nodes;
-    g.dx = s->grid.dx;
     const MidMaterial mat{s->prm.mu, s->prm.lambda, s->prm.rho0};
     Parts<double> P{};
     P.cell = s->p.cell;
@@ -1356,9 +1361,8 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     P.id = s->p.id;
     P.n = s->p.n;
     P.s = s->p.stride;
-    const int64_t np = std::max<int64_t>(P.n, 1);
     MidSorted S{};
-    S.perm = (const uint32_t *)(ws + L.perm);
+    S.perm = (uint32_t *)(ws + L.perm);
     S.start = (const uint32_t *)(ws + L.start);
     S.cell = (uint32_t *)(ws + L.scell);
     S.off = (double *)(ws + L.soff);
@@ -1366,55 +1370,52 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     S.m = (double *)(ws + L.sm);
     S.mv = (double *)(ws + L.smv);
     S.M = (double *)(ws + L.sM);
-    S.n = np;
-    S.nodes = L.nodes;
+    S.n = std::max<int64_t>(P.n, 1);
     S.dx = s->grid.dx;
+    MidTiles tl{};
+    tl.klist = (int32_t *)(ws + L.klist);
+    tl.nlist = (int32_t *)(ws + L.nlist);
+    tl.slot = (int32_t *)(ws + L.slot);
+    tl.slab = (double *)(ws + L.slab);
     uint32_t *key = (uint32_t *)(ws + L.key), *count = (uint32_t *)(ws + L.count);
     uint32_t *cursor = (uint32_t *)(ws + L.cursor), *bsum = (uint32_t *)(ws + L.bsum);
     const double dt = s->prm.dt;
     const double *grav = s->prm.gravity;
     const bool elastic = s->prm.model == APIC_MODEL_NEO_HOOKEAN && P.n > 0;
-    const int64_t nv = L.nodes * DIM;
-    const int64_t pb = mid_particle_blocks(std::max<int64_t>(P.n, 1)), nb = mid_node_blocks(L.nodes);
-    const int64_t cb = mid_collect_blocks(DIM, g.N);
-    double host[4] = {0, 0, 0, 0};
     apic_status rc0 = APIC_OK;
-    // final reduction of K block partials, read back (synchronizes)
-    auto read = [&](int64_t nblk, int K) {
+    auto fetch = [&](void *dst, const void *src, size_t bytes) {
         if (rc0 != APIC_OK) return;
-        launch_mid_reduce(part, nblk, K, out, st);
-        rc0 = hip_check(hipMemcpyAsync(host, out, K * sizeof(double), hipMemcpyDeviceToHost, st), "apic_step_midpoint");
+        rc0 = hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st), "apic_step_midpoint");
         if (rc0 == APIC_OK) rc0 = hip_check(hipStreamSynchronize(st), "apic_step_midpoint");
     };
     // E(dv) and |r|_M with r written to `r` (Sec. 4.1); an inverted element
     // makes E infinite and raises its flag in tflags
     auto eval = [&](const double *dvx, double &E, double &res) {
-        double phi = 0.0;
+        double host[2] = {0.0, 0.0};
         launch_fill<uint32_t>(tflags, 1, 0u, st);
-        if (elastic) {
-            launch_mid_stress<DIM, DEG, false>(S, g, mat, gv, dvx, dt, nullptr, part, tflags, st);
-            read(pb, 1);
-            phi = host[0];
-            launch_mid_collect_force<DIM, DEG>(S, g, f, st);
-        } else {
-            launch_mid_fill(f, nv, 0.0, st);
-        }
-        launch_mid_residual<DIM>(g, mf, f, dvx, dt, grav, r, part, st);
-        read(nb, 2);
+        launch_mid_force<DIM, DEG>(S, g, tl, mat, elastic, gv, dvx, dt, grav, mf, r, epart, part, out, tflags, st);
+        fetch(host, out, sizeof host);
         res = sqrt(host[0]);
-        E = host[1] + phi;
+        E = host[1];
     };
 
     launch_fill<uint32_t>(flags, 1, 0u, st);
+    launch_fill<uint32_t>((uint32_t *)cg, sizeof(MidCg) / sizeof(uint32_t), 0u, st);
     *stats = apic_midpoint_stats{};
     stats->converged = 1;
+    const double tol2 = o.cg_tol * o.cg_tol;
     for (int32_t step = 0; step < n_steps && rc0 == APIC_OK; ++step) {
-        launch_mid_sort<DIM, DEG>(P, g, S, key, count, cursor, bsum, flags, st);
-        launch_mid_collect_p2g<DIM, DEG>(S, g, gm, gv, st);
-        launch_mid_nodes<DIM>(g, gm, gv, mf, st);
-        // without a force the differential is zero: its matrices stay 0
-        if (!elastic) launch_mid_fill(S.M, (int64_t)np * DIM * DIM, 0.0, st);
-        launch_mid_fill(dv, nv, 0.0, st);
+        launch_mid_sort<DIM, DEG>(P, g, S, tl, key, count, cursor, bsum, counts, flags, st);
+        int32_t nkn[2] = {0, 0};
+        fetch(nkn, counts, sizeof nkn);
+        tl.nk = nkn[0];
+        tl.nn = nkn[1];
+        stats->res0 = 0.0;
+        stats->res = 0.0;
+        if (tl.nk == 0 || rc0 != APIC_OK) continue;  // no particle inside the grid: nothing moves
+        launch_mid_sort_state<DIM, DEG>(P, S, tl, st);
+        launch_mid_p2g<DIM, DEG>(S, g, tl, mf, gv, st);
+        launch_mid_axpy<DIM>(g, tl, nullptr, 0.0, gv, dv, st);  // dv = 0
         double E = 0.0, res = 0.0;
         eval(dv, E, res);
         launch_mid_flags_accept(flags, tflags, st);
@@ -1423,37 +1424,28 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
         for (; it < o.max_newton && rc0 == APIC_OK; ++it) {
             if (res0 == 0.0 || res <= o.newton_tol * res0) break;
             // conjugate gradient in the mass inner product (Sec. 4.2) on
-            // (I - dt^2/4 M^{-1} df/dx) delta = -r
-            launch_mid_cg_init<DIM>(g, mf, r, delta, rc, pv, part, st);
-            read(nb, 1);
-            double gamma = host[0];
-            const double gamma0 = gamma;
-            for (int k = 0; k < o.max_cg && rc0 == APIC_OK; ++k) {
-                if (gamma <= o.cg_tol * o.cg_tol * gamma0) break;
-                if (elastic) launch_mid_stress<DIM, DEG, true>(S, g, mat, gv, dv, dt, pv, nullptr, flags, st);
-                launch_mid_collect_apply<DIM, DEG>(S, g, mf, pv, dt, sv, part, st);
-                read(cb, 1);
-                const double ps = host[0];
-                stats->cg_iters += 1;
-                if (!(ps > 0.0)) {
-                    if (k == 0) launch_mid_axpy(nv, nullptr, -1.0, r, delta, st);
-                    break;
+            // (I - dt^2/4 M^{-1} df/dx) delta = -r, its scalars on the device
+            launch_mid_cg_init<DIM>(g, tl, mf, r, delta, rc, pv, part, cg, tol2, (uint32_t)o.max_cg, st);
+            for (int k = 0; k < o.max_cg && rc0 == APIC_OK;) {
+                const int chunk = std::min(kCgPoll, o.max_cg - k);
+                for (int j = 0; j < chunk; ++j) {
+                    launch_mid_apply<DIM, DEG>(S, g, tl, mat, elastic, pv, mf, dt, sv, part, cg, st);
+                    launch_mid_cg_step<DIM>(g, tl, mf, r, pv, sv, delta, rc, part, cg, st);
+                    launch_mid_cg_dir<DIM>(g, tl, rc, pv, cg, st);
                 }
-                const double alpha = gamma / ps;
-                launch_mid_cg_step<DIM>(g, mf, alpha, pv, sv, delta, rc, part, st);
-                read(nb, 1);
-                const double kappa = host[0];
-                launch_mid_axpy(nv, rc, kappa / gamma, pv, pv, st);
-                gamma = kappa;
+                k += chunk;
+                uint32_t done = 0;
+                fetch(&done, &cg->done, sizeof done);
+                if (done) break;
             }
             // backtracking line search: E must not increase, or |r|_M must
             // fall (near the minimum E is flat to within its rounding); a
             // trial that inverts an element has E = +inf and is halved
             double stepl = 1.0, En = 0.0, resn = 0.0;
             for (int k = 0; k < 30 && rc0 == APIC_OK; ++k) {
-                launch_mid_axpy(nv, dv, stepl, delta, dvt, st);
+                launch_mid_axpy<DIM>(g, tl, dv, stepl, delta, dvt, st);
                 eval(dvt, En, resn);
-                if ((isfinite(En) && (En <= E || resn < res)) || k == 29) break;
+                if ((std::isfinite(En) && (En <= E || resn < res)) || k == 29) break;
                 stepl *= 0.5;
                 stats->halvings += 1;
             }
@@ -1466,16 +1458,18 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
         stats->res0 = res0;
         stats->res = res;
         if (!(res0 == 0.0 || res <= o.newton_tol * res0)) stats->converged = 0;
-        launch_mid_finish<DIM>(g, mf, gv, dv, dt, rc, sv, st);
+        launch_mid_finish<DIM>(g, tl, mf, gv, dv, dt, rc, sv, st);
         launch_mid_g2p<DIM, DEG>(P, g, rc, sv, st);
     }
     if (rc0 != APIC_OK) return rc0;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(APIC_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     uint32_t fl = 0;
-    rc0 = hip_check(hipMemcpyAsync(&fl, flags, sizeof fl, hipMemcpyDeviceToHost, st), "apic_step_midpoint");
-    if (rc0 == APIC_OK) rc0 = hip_check(hipStreamSynchronize(st), "apic_step_midpoint");
+    MidCg cgh{};
+    fetch(&fl, flags, sizeof fl);
+    fetch(&cgh, cg, sizeof cgh);
     stats->flags = fl;
+    stats->cg_iters = (int32_t)cgh.iters;
     return rc0;
 }
 
@@ -1488,7 +1482,7 @@ apic_status apic_midpoint_workspace_bytes(const apic_grid_desc *grid, int64_t ma
     if (rc != APIC_OK) return rc;
     if (!bytes) return fail(APIC_E_INVAL, "bytes is NULL");
     if (max_particles < 0) return fail(APIC_E_INVAL, "max_particles must be >= 0");
-    *bytes = mid_layout(*grid, max_particles).total;
+    *bytes = mid_layout(*grid, kNoBand, max_particles).total;
     return APIC_OK;
 }
 
@@ -1517,7 +1511,7 @@ apic_status apic_step_midpoint(apic_scene *s, int32_t n_steps, const apic_midpoi
     }
     if (!s->workspace) return fail(APIC_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)s->workspace) % kAlign) return fail(APIC_E_WORKSPACE, "workspace must be 256-byte aligned");
-    const size_t need = mid_layout(s->grid, s->p.n).total;
+    const size_t need = mid_layout(s->grid, s->prm.band, s->p.n).total;
     if (s->workspace_bytes < need)
         return fail(APIC_E_WORKSPACE, "workspace of %zu bytes is below the %zu the midpoint step needs",
                     s->workspace_bytes, need);

@@ -157,68 +157,102 @@ void launch_pack_positions(const Parts<T> &P, const double *x, double dx, hipStr
 template <typename T, int DIM>
 void launch_unpack_positions(const Parts<T> &P, double *x, double dx, hipStream_t st, bool absolute);
 
-// --- implicit midpoint (binary64, dense node arrays) ------------------------
+// --- implicit midpoint (binary64, node vectors in tiles of 64 nodes) --------
+// Node (x, y, z) has slot 64 t + l: t is its tile (4^3 nodes in 3D, 8^2 in 2D),
+// l its place in the tile (x fastest).  Node vectors are component-major over
+// the slots (component a of slot i at a * nodes + i).
 struct MidGrid {
     int N[3];        // nodes per axis (N[2] = 1 in 2D)
+    int T[3];        // tiles per axis (T[2] = 1 in 2D)
     int band[6];     // sticky band widths in nodes
-    int64_t nodes;   // node count
+    int64_t tiles;   // T[0] T[1] T[2]
+    int64_t nodes;   // node slots: 64 tiles
     double dx;
 };
 
-// Particles sorted by base node (positions [0, start[nodes]) are filled).
+// Host-side geometry of the tiled node layout.
+MidGrid mid_grid(int dim, const int *cells, const int *band, double dx);
+// Nodes in the region of one key tile (the tile plus DEG nodes up each axis).
+int mid_region_nodes(int dim, int degree);
+// Blocks (and block partials) of a node pass over nn node tiles.
+int64_t mid_node_blocks(int64_t nn);
+int64_t mid_scan_blocks(int64_t nodes);
+
+// Particles counting-sorted by base node (key = the base node's slot); the
+// copies are level-major within a key tile: level r holds, in key order, the
+// r-th particle (ascending index) of every key of the tile with more than r.
 struct MidSorted {
-    const uint32_t *perm;   // sorted position -> particle
-    const uint32_t *start;  // nodes + 1 entries: first position of each base key
-    uint32_t *cell;         // packed cell, sorted
+    uint32_t *perm;         // key-major position -> particle
+    const uint32_t *start;  // nodes + 1 entries: first position of each key
+    uint32_t *cell;         // packed cell
     double *off;            // dim planes
     double *F;              // dim*dim planes
     double *m;
     double *mv;             // dim planes: m v
-    double *M;              // dim*dim planes: the per-particle matrix of the current collect
-    int64_t n;              // plane stride (particle count)
-    int64_t nodes;
+    double *M;              // dim*dim + 1 planes: m (k / dx) B for the transfer to grid, then F_hat^{-T} and
+                            // mu - lambda ln J of the last force pass
+    int64_t n;              // plane stride
     double dx;
+};
+
+// Key tiles that hold particles and the node tiles within their reach.
+struct MidTiles {
+    int32_t *klist;   // key tiles holding particles, ascending
+    int32_t *nlist;   // node tiles that some listed key tile's region touches, ascending
+    int32_t *slot;    // per tile: its index in klist, -1 when it holds no particle
+    double *slab;     // per listed key tile: the sums over its region, component planes of mid_region_nodes
+    int64_t nk, nn;   // list lengths (host copies)
+};
+
+// Conjugate-gradient scalars, formed and kept on the device.
+struct MidCg {
+    double gamma, gamma0, alpha, beta, tol2;
+    uint32_t done, fallback, k, max_iters, iters;
 };
 
 struct MidMaterial {
     double mu, lambda, rho0;
 };
 
-void launch_mid_fill(double *a, int64_t n, double val, hipStream_t st);
-void launch_mid_reduce(const double *part, int64_t nblk, int K, double *out, hipStream_t st);
-void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, double *out, hipStream_t st);
 void launch_mid_flags_accept(uint32_t *flags, uint32_t *trial, hipStream_t st);
-int64_t mid_particle_blocks(int64_t n);
-int64_t mid_node_blocks(int64_t nodes);
-int64_t mid_scan_blocks(int64_t nodes);
-int64_t mid_collect_blocks(int dim, const int *N);  // blocks (and partials) of a node collect
+// Keys, counting sort and tile lists; counts[0] = nk, counts[1] = nn.
 template <int DIM, int DEG>
-void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, uint32_t *key, uint32_t *count,
-                     uint32_t *cursor, uint32_t *bsum, uint32_t *flags, hipStream_t st);
-template <int DIM>
-void launch_mid_nodes(const MidGrid &g, const double *gm, double *gv, double *mf, hipStream_t st);
-template <int DIM, int DEG, bool DIFF>
-void launch_mid_stress(const MidSorted &S, const MidGrid &g, const MidMaterial &mat, const double *gv,
-                       const double *dv, double dt, const double *du, double *part, uint32_t *flags, hipStream_t st);
+void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, const MidTiles &tl, uint32_t *key,
+                     uint32_t *count, uint32_t *cursor, uint32_t *bsum, int32_t *counts, uint32_t *flags,
+                     hipStream_t st);
+// Level-major copies of the particles of the nk listed key tiles.
 template <int DIM, int DEG>
-void launch_mid_collect_p2g(const MidSorted &S, const MidGrid &g, double *gm, double *gmv, hipStream_t st);
+void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const MidTiles &tl, hipStream_t st);
+// Transfer to grid: free-node mass mf and velocity gv.
 template <int DIM, int DEG>
-void launch_mid_collect_force(const MidSorted &S, const MidGrid &g, double *f, hipStream_t st);
+void launch_mid_p2g(const MidSorted &S, const MidGrid &g, const MidTiles &tl, double *mf, double *gv, hipStream_t st);
+// Forces at the iterate dv, residual r and out[0] = |r|_M^2, out[1] = E(dv).
 template <int DIM, int DEG>
-void launch_mid_collect_apply(const MidSorted &S, const MidGrid &g, const double *mf, const double *pv, double dt,
-                              double *s, double *part, hipStream_t st);
+void launch_mid_force(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
+                      const double *gv, const double *dv, double dt, const double *grav, const double *mf, double *r,
+                      double *epart, double *part, double *out, uint32_t *flags, hipStream_t st);
+// One application of the Newton operator to the search direction pv (s = A pv) and alpha.
+template <int DIM, int DEG>
+void launch_mid_apply(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
+                      const double *pv, const double *mf, double dt, double *s, double *part, MidCg *cg,
+                      hipStream_t st);
 template <int DIM>
-void launch_mid_residual(const MidGrid &g, const double *mf, const double *f, const double *dv, double dt,
-                         const double *grav, double *r, double *part, hipStream_t st);
+void launch_mid_cg_init(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, double *delta,
+                        double *rc, double *pv, double *part, MidCg *cg, double tol2, uint32_t max_iters,
+                        hipStream_t st);
 template <int DIM>
-void launch_mid_cg_init(const MidGrid &g, const double *mf, const double *r, double *delta, double *rc, double *pv,
-                        double *part, hipStream_t st);
+void launch_mid_cg_step(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, const double *pv,
+                        const double *s, double *delta, double *rc, double *part, MidCg *cg, hipStream_t st);
 template <int DIM>
-void launch_mid_cg_step(const MidGrid &g, const double *mf, double alpha, const double *pv, const double *s,
-                        double *delta, double *rc, double *part, hipStream_t st);
+void launch_mid_cg_dir(const MidGrid &g, const MidTiles &tl, const double *rc, double *pv, const MidCg *cg,
+                       hipStream_t st);
+// out = a + alpha b on the listed node tiles (a = nullptr reads as 0).
 template <int DIM>
-void launch_mid_finish(const MidGrid &g, const double *mf, const double *gv, const double *dv, double dt, double *gvt,
-                       double *gu, hipStream_t st);
+void launch_mid_axpy(const MidGrid &g, const MidTiles &tl, const double *a, double alpha, const double *b, double *out,
+                     hipStream_t st);
+template <int DIM>
+void launch_mid_finish(const MidGrid &g, const MidTiles &tl, const double *mf, const double *gv, const double *dv,
+                       double dt, double *gvt, double *gu, hipStream_t st);
 template <int DIM, int DEG>
 void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt, const double *gu, hipStream_t st);
 

@@ -2,27 +2,115 @@
 // Sec. 3.3), solved as the minimization of Sec. 4.1 with Newton's method and
 // the mass-inner-product conjugate gradient of Sec. 4.2.  Binary64 throughout.
 //
-// Layout: dense node arrays (node ix + N0 (iy + N1 iz)), component-major
-// vectors (component a of node i at a * nodes + i).  Once per step the
-// particles are counting-sorted by base node and what the solve reads is
-// copied in that order; particle kernels then write one matrix per particle
-// and node kernels collect it over the sorted ranges of the base keys around
-// each node (no atomics in the Newton loop).  Node kernels leave one partial
-// sum per block, summed in a fixed order by k_mid_reduce.  The transfer to
-// particles reads the caller's order.
+// Layout.  Nodes are grouped in tiles of 64 (4^3 in 3D, 8^2 in 2D); node
+// vectors are component-major over the node slots (64 tile + place in tile).
+// A particle's key is its base node.  Once per step the particles are
+// counting-sorted by key, the key tiles that hold particles and the node tiles
+// their regions touch are listed (a key tile's region is the tile plus DEG
+// nodes up each axis: the support of every particle keyed in it), and what
+// the solve reads is copied level-major per key tile.
+//
+// Particle terms.  One wavefront per listed key tile, one lane per key, walks
+// the levels: it gathers node values of the region, staged in LDS, computes
+// the particle's term and adds it into an LDS copy of the region.  Within one
+// add every lane targets a different node (the lanes hold different base
+// nodes and visit the support in the same order), so each node's sum has a
+// fixed order.  The region sums go to the tile's slab.
+//
+// Node passes.  One wavefront per listed node tile, one lane per node, adds
+// the (at most 2^dim) slabs that cover the node in a fixed order and finishes
+// the node's update.  Reductions leave one partial per block, summed in block
+// order by a one-block kernel that also forms the conjugate gradient's
+// scalars on the device, so no iteration waits for the host.
+//
+// The transfer to particles reads the caller's particle order.
 #include "apic_kernels.h"
 
 namespace apic {
 
 namespace {
 
-constexpr int kMidBlock = 256;
+constexpr int kMidBlock = 256;  // node passes: four node tiles per block
+constexpr int kNodeTilesPerBlock = kMidBlock / 64;
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * kMidBlock + threadIdx.x; }
 
+template <int DIM>
+__host__ __device__ constexpr int tile_edge() {
+    return DIM == 3 ? 4 : 8;
+}
+template <int DIM, int DEG>
+__host__ __device__ constexpr int region_edge() {
+    return tile_edge<DIM>() + DEG;
+}
+template <int DIM, int DEG>
+__host__ __device__ constexpr int region_nodes() {
+    return DIM == 3 ? region_edge<DIM, DEG>() * region_edge<DIM, DEG>() * region_edge<DIM, DEG>()
+                    : region_edge<DIM, DEG>() * region_edge<DIM, DEG>();
+}
 
-// Sum of K values over the block; thread 0 writes them to part[blockIdx * K].
+template <int DIM>
+__device__ __forceinline__ int64_t tile_index(const MidGrid &g, const int *tc) {
+    return DIM == 3 ? tc[0] + (int64_t)g.T[0] * (tc[1] + (int64_t)g.T[1] * tc[2]) : tc[0] + (int64_t)g.T[0] * tc[1];
+}
+
+// Slot of node (x, y, z).
+template <int DIM>
+__device__ __forceinline__ int64_t node_slot(const MidGrid &g, int x, int y, int z) {
+    if constexpr (DIM == 3) {
+        const int tc[3] = {x >> 2, y >> 2, z >> 2};
+        return tile_index<3>(g, tc) * 64 + ((x & 3) | ((y & 3) << 2) | ((z & 3) << 4));
+    } else {
+        const int tc[3] = {x >> 3, y >> 3, 0};
+        return tile_index<2>(g, tc) * 64 + ((x & 7) | ((y & 7) << 3));
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void tile_coords(const MidGrid &g, int64_t t, int *tc) {
+    tc[0] = (int)(t % g.T[0]);
+    const int64_t q = t / g.T[0];
+    if constexpr (DIM == 3) {
+        tc[1] = (int)(q % g.T[1]);
+        tc[2] = (int)(q / g.T[1]);
+    } else {
+        tc[1] = (int)q;
+        tc[2] = 0;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void local_coords(int l, int *lc) {
+    if constexpr (DIM == 3) {
+        lc[0] = l & 3;
+        lc[1] = (l >> 2) & 3;
+        lc[2] = l >> 4;
+    } else {
+        lc[0] = l & 7;
+        lc[1] = l >> 3;
+        lc[2] = 0;
+    }
+}
+
+// Sum over the block's threads of a[b * K + k] for b < n (each thread its
+// stride of b in order, then a fixed tree); every thread returns the total.
+__device__ __forceinline__ double block_total(const double *a, int64_t n, int K, int k) {
+    __shared__ double red[kMidBlock];
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < n; b += kMidBlock) s += a[b * K + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kMidBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// Block sums of K values to part[blockIdx * K + k] (thread 0 writes them).
 template <int K>
 __device__ __forceinline__ void block_partials(double (&acc)[K], double *part) {
     __shared__ double red[K][kMidBlock / 64];
@@ -47,18 +135,6 @@ __device__ __forceinline__ void block_partials(double (&acc)[K], double *part) {
         }
 }
 
-template <int DIM>
-__device__ __forceinline__ void node_coords(int64_t i, const MidGrid &g, int *c) {
-    c[0] = (int)(i % g.N[0]);
-    const int64_t q = i / g.N[0];
-    if constexpr (DIM == 3) {
-        c[1] = (int)(q % g.N[1]);
-        c[2] = (int)(q / g.N[1]);
-    } else {
-        c[1] = (int)q;
-    }
-}
-
 // Per-axis weights of particle p; false when its support leaves the grid.
 template <int DIM, int DEG>
 __device__ __forceinline__ bool particle_axes(const Parts<double> &P, int64_t p, const MidGrid &g,
@@ -74,39 +150,110 @@ __device__ __forceinline__ bool particle_axes(const Parts<double> &P, int64_t p,
     return ok;
 }
 
-// Visits the support: f(node index, w, grad w (cell units), r (cell units)).
-template <int DIM, int DEG, typename Fn>
-__device__ __forceinline__ void for_support(const Axis<double, DEG> (&ax)[DIM], const MidGrid &g, Fn &&fn) {
+template <int DIM, int DEG>
+__device__ __forceinline__ void sorted_axes(const MidSorted &S, int64_t pos, Axis<double, DEG> (&ax)[DIM]) {
+    int ci[3];
+    unpack_cell<DIM>(S.cell[pos], ci);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) axis_weights<double, DEG>(ci[a], S.off[a * S.n + pos], ax[a]);
+}
+
+// Visits the support: f(w, grad w (cell units), r (cell units), i, j, k),
+// (i, j, k) the offsets from the base node.  In 3D the z planes are a loop
+// unless ZFULL (unrolling all of them lets the compiler hoist every load and
+// keep every weight product live); the plane's z weights are rotated into
+// element 0, so no register array is indexed dynamically.
+template <int DIM, int DEG, bool ZFULL = false, typename Fn>
+__device__ __forceinline__ void for_support(const Axis<double, DEG> (&ax)[DIM], Fn &&fn) {
     constexpr int K = DEG + 1;
-    if constexpr (DIM == 3) {
-        // cubic: z rows one at a time (unrolling all 64 nodes hoists every load)
-#pragma unroll (DEG == 2 ? K : 1)
+    if constexpr (DIM == 3 && ZFULL) {
+#pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const double wyz = ax[1].w[j] * ax[2].w[k];
-                const int64_t row = (int64_t)g.N[0] * ((ax[1].base + j) + (int64_t)g.N[1] * (ax[2].base + k));
+                const double wyz = ax[1].w[j] * ax[DIM - 1].w[k];
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     const double w = ax[0].w[i] * wyz;
-                    const double gw[3] = {ax[0].dw[i] * wyz, ax[0].w[i] * ax[1].dw[j] * ax[2].w[k],
-                                          ax[0].w[i] * ax[1].w[j] * ax[2].dw[k]};
-                    const double r[3] = {ax[0].r[i], ax[1].r[j], ax[2].r[k]};
-                    fn(row + ax[0].base + i, w, gw, r);
+                    const double gw[3] = {ax[0].dw[i] * wyz, ax[0].w[i] * ax[1].dw[j] * ax[DIM - 1].w[k],
+                                          ax[0].w[i] * ax[1].w[j] * ax[DIM - 1].dw[k]};
+                    const double r[3] = {ax[0].r[i], ax[1].r[j], ax[DIM - 1].r[k]};
+                    fn(w, gw, r, i, j, k);
                 }
             }
+    } else if constexpr (DIM == 3) {
+        double wz[K], dwz[K], rz[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            wz[q] = ax[2].w[q];
+            dwz[q] = ax[2].dw[q];
+            rz[q] = ax[2].r[q];
+        }
+#pragma unroll 1
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double wyz = ax[1].w[j] * wz[0];
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const double w = ax[0].w[i] * wyz;
+                    const double gw[3] = {ax[0].dw[i] * wyz, ax[0].w[i] * ax[1].dw[j] * wz[0],
+                                          ax[0].w[i] * ax[1].w[j] * dwz[0]};
+                    const double r[3] = {ax[0].r[i], ax[1].r[j], rz[0]};
+                    fn(w, gw, r, i, j, k);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q + 1 < K; ++q) {
+                wz[q] = wz[q + 1];
+                dwz[q] = dwz[q + 1];
+                rz[q] = rz[q + 1];
+            }
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t row = (int64_t)g.N[0] * (ax[1].base + j);
+        for (int j = 0; j < K; ++j)
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const double w = ax[0].w[i] * ax[1].w[j];
                 const double gw[2] = {ax[0].dw[i] * ax[1].w[j], ax[0].w[i] * ax[1].dw[j]};
                 const double r[2] = {ax[0].r[i], ax[1].r[j]};
-                fn(row + ax[0].base + i, w, gw, r);
+                fn(w, gw, r, i, j, 0);
+            }
+    }
+}
+
+// Visits the support row by row (a row: the DEG + 1 nodes along x at the
+// y, z offsets j, k): f(j, k, c0, c1, c2, ry, rz) with c0 = w_j w_k,
+// c1 = dw_j w_k, c2 = w_j dw_k (y, z factors of w and of the gradient's
+// components; in 2D c0 = w_j, c1 = dw_j, c2 = 0) and ry, rz the row's
+// offsets from the particle (cell units).  3D planes as in for_support.
+template <int DIM, int DEG, typename Fn>
+__device__ __forceinline__ void for_rows(const Axis<double, DEG> (&ax)[DIM], Fn &&fn) {
+    constexpr int K = DEG + 1;
+    if constexpr (DIM == 3) {
+        double wz[K], dwz[K], rz[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            wz[q] = ax[DIM - 1].w[q];
+            dwz[q] = ax[DIM - 1].dw[q];
+            rz[q] = ax[DIM - 1].r[q];
+        }
+#pragma unroll 1
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                fn(j, k, ax[1].w[j] * wz[0], ax[1].dw[j] * wz[0], ax[1].w[j] * dwz[0], ax[1].r[j], rz[0]);
+#pragma unroll
+            for (int q = 0; q + 1 < K; ++q) {
+                wz[q] = wz[q + 1];
+                dwz[q] = dwz[q + 1];
+                rz[q] = rz[q + 1];
             }
         }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) fn(j, 0, ax[1].w[j], ax[1].dw[j], 0.0, ax[1].r[j], 0.0);
     }
 }
 
@@ -148,42 +295,40 @@ __device__ __forceinline__ double det_inv_t(const double *A, double *IT) {
     }
 }
 
-// G = sum_i u_i grad w_ip^T (physical gradient = cell-unit gradient / dx).
-template <int DIM, int DEG>
-__device__ __forceinline__ void gather_grad(const Axis<double, DEG> (&ax)[DIM], const MidGrid &g, const double *gv,
-                                            const double *dv, double cv, double cd, double *G) {
+// Walks the particles of key tile t level by level, in the lane of each
+// particle's key: fn(sorted position, level, first key-major position of the
+// key).  Positions of one level are consecutive (key order).
+template <typename Fn>
+__device__ __forceinline__ void for_levels(const uint32_t *start, int64_t t, Fn &&fn) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t k0 = start[t * 64 + lane];
+    const uint32_t cnt = start[t * 64 + lane + 1] - k0;
+    uint32_t maxc = cnt;
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) G[k] = 0.0;
-    for_support<DIM, DEG>(ax, g, [&](int64_t i, double, const double *gw, const double *) {
-#pragma unroll
-        for (int r = 0; r < DIM; ++r) {
-            const double u = cv * gv[r * g.nodes + i] + cd * dv[r * g.nodes + i];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) G[r * DIM + c] += u * gw[c];
-        }
-    });
-    const double s = 1.0 / g.dx;
-#pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) G[k] *= s;
-}
-
-template <int DIM>
-__device__ __forceinline__ void load_mat(const double *plane, int64_t s, int64_t p, double *M) {
-#pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) M[k] = plane[k * s + p];
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t other = __shfl_xor(maxc, o, 64);
+        maxc = other > maxc ? other : maxc;
+    }
+    int64_t pos0 = start[t * 64];
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (uint32_t r = 0; r < maxc; ++r) {
+        const bool act = r < cnt;
+        const uint64_t bal = ballot(act);
+        if (act) fn(pos0 + __popcll(bal & below), r, k0);
+        pos0 += __popcll(bal);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Kernels
+// Sort (once per step)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMidBlock) void k_mid_fill(double *a, int64_t n, double val) {
+__global__ __launch_bounds__(kMidBlock) void k_mid_fill_u32(uint32_t *a, int64_t n) {
     const int64_t i = gtid();
-    if (i < n) a[i] = val;
+    if (i < n) a[i] = 0u;
 }
 
-// --- particles sorted by base node (once per step) --------------------------
-// Key = linear index of the particle's base node; particles whose support
-// leaves the grid get no key (they take no part in the step).
+// Key = slot of the particle's base node; particles whose support leaves the
+// grid get no key (they take no part in the step).
 template <int DIM, int DEG>
 __global__ __launch_bounds__(kMidBlock) void k_mid_keys(Parts<double> P, MidGrid g, uint32_t *key, uint32_t *count,
                                                         uint32_t *flags) {
@@ -195,9 +340,7 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_keys(Parts<double> P, MidGrid
         atomicOr(flags, (uint32_t)APIC_FLAG_OUT_OF_DOMAIN);
         return;
     }
-    int64_t k = ax[DIM - 1].base;
-#pragma unroll
-    for (int a = DIM - 2; a >= 0; --a) k = k * g.N[a] + ax[a].base;
+    const int64_t k = node_slot<DIM>(g, ax[0].base, ax[1].base, DIM == 3 ? ax[DIM - 1].base : 0);
     key[p] = (uint32_t)k;
     atomicAdd(&count[k], 1u);
 }
@@ -264,7 +407,8 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_scan3(uint32_t *start, int64_
     if (i < n) start[i] += bsum[i >> 10];
 }
 
-// perm[position] = particle, positions of one key in any order.
+// perm[position] = particle; the positions of one key in any order (the
+// level-major copy orders them).
 __global__ __launch_bounds__(kMidBlock) void k_mid_place(int64_t n, const uint32_t *key, const uint32_t *start,
                                                          uint32_t *cursor, uint32_t *perm) {
     const int64_t p = gtid();
@@ -274,280 +418,388 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_place(int64_t n, const uint32
     perm[start[k] + atomicAdd(&cursor[k], 1u)] = (uint32_t)p;
 }
 
-// Sorted copies of what the solve reads (cell, offset, F, m) and the P2G
-// terms: mv = m v and Q = m (k / dx) B, so that node i receives
-// w (mv + Q r) with r = (x_i - x_p) / dx (B D^{-1} (x_i - x_p), D = dx^2 / k I).
-template <int DIM, int DEG>
-__global__ __launch_bounds__(kMidBlock) void k_mid_sort_state(Parts<double> P, MidSorted S) {
-    const int64_t pos = gtid();
-    if (pos >= S.n || pos >= (int64_t)S.start[S.nodes]) return;
-    const int64_t q = S.perm[pos];
-    S.cell[pos] = P.cell[q];
-    const double m = P.m[q];
-    S.m[pos] = m;
-    const double kq = m * inv_D_factor<double, DEG>() / S.dx;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        S.off[a * S.n + pos] = P.off[a * P.s + q];
-        S.mv[a * S.n + pos] = m * P.v[a * P.s + q];
-    }
-#pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) {
-        S.F[k * S.n + pos] = P.F[k * P.s + q];
-        S.M[k * S.n + pos] = kq * P.B[k * P.s + q];
-    }
-}
-
-template <int DIM, int DEG>
-__device__ __forceinline__ void sorted_axes(const MidSorted &S, int64_t pos, Axis<double, DEG> (&ax)[DIM]) {
-    int ci[3];
-    unpack_cell<DIM>(S.cell[pos], ci);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) axis_weights<double, DEG>(ci[a], S.off[a * S.n + pos], ax[a]);
-}
-
-// v_i = (m v)_i / m_i on free nodes (mass, outside the sticky band); 0
-// elsewhere.  mf_i = m_i on free nodes, 0 elsewhere.
+// Tile lists: klist = tiles holding particles, nlist = tiles t with a tile
+// holding particles among t - d, d in {0, 1}^dim (the regions reach one tile
+// up each axis), both ascending; slot[t] = index in klist or -1.  Flags per
+// tile, their prefix sums (the scan kernels above), then the placement.
 template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_nodes(MidGrid g, const double *gm, double *gv, double *mf) {
-    const int64_t i = gtid();
-    if (i >= g.nodes) return;
-    int c[3];
-    node_coords<DIM>(i, g, c);
-    bool sticky = false;
+__global__ __launch_bounds__(kMidBlock) void k_mid_tile_flags(MidGrid g, const uint32_t *start, uint32_t *kf,
+                                                              uint32_t *nf) {
+    const int64_t t = gtid();
+    if (t >= g.tiles) return;
+    int tc[3];
+    tile_coords<DIM>(g, t, tc);
+    bool nact = false;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) sticky = sticky || c[a] < g.band[2 * a] || c[a] > g.N[a] - 1 - g.band[2 * a + 1];
-    const double m = gm[i];
-    const bool free_node = m > 0.0 && !sticky;
-    mf[i] = free_node ? m : 0.0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) gv[a * g.nodes + i] = free_node ? gv[a * g.nodes + i] / m : 0.0;
+    for (int d = 0; d < (1 << DIM); ++d) {
+        const int u[3] = {tc[0] - (d & 1), tc[1] - ((d >> 1) & 1), DIM == 3 ? tc[2] - (d >> 2) : 0};
+        if (u[0] < 0 || u[1] < 0 || u[2] < 0) continue;
+        const int64_t ut = tile_index<DIM>(g, u);
+        nact = nact || start[ut * 64 + 64] > start[ut * 64];
+    }
+    kf[t] = start[t * 64 + 64] > start[t * 64] ? 1u : 0u;
+    nf[t] = nact ? 1u : 0u;
 }
 
-// Per sorted particle, the matrix that the node collect contracts with
-// grad w (cell units): -V P(F_hat) F^T / dx for the force (DIFF = false;
-// block partials of Phi = sum V Psi(F_hat)), -V (dP/dF(F_hat) : dF) F^T / dx
-// for the force differential along du (DIFF = true), with
-// F_hat = (I + sum_i u_i grad w^T) F, u_i = dt/2 v_i + dt/4 dv_i, and
-// dF = (sum_i du_i grad w^T) F (Sec. 3.3, Sec. 4.1).
-template <int DIM, int DEG, bool DIFF>
-__global__ __launch_bounds__(kMidBlock) void k_mid_stress(MidSorted S, MidGrid g, MidMaterial mat, const double *gv,
-                                                          const double *dv, double dt, const double *du, double *part,
-                                                          uint32_t *flags) {
-    const int64_t pos = gtid();
-    double acc[1] = {0.0};
-    if (pos < S.n && pos < (int64_t)S.start[S.nodes]) {
+__global__ __launch_bounds__(kMidBlock) void k_mid_tile_place(int64_t tiles, const uint32_t *kf, const uint32_t *nf,
+                                                              const uint32_t *ks, const uint32_t *ns, MidTiles tl,
+                                                              int32_t *counts) {
+    const int64_t t = gtid();
+    if (t == 0) {
+        counts[0] = (int32_t)ks[tiles];
+        counts[1] = (int32_t)ns[tiles];
+    }
+    if (t >= tiles) return;
+    tl.slot[t] = kf[t] ? (int32_t)ks[t] : -1;
+    if (kf[t]) tl.klist[ks[t]] = (int32_t)t;
+    if (nf[t]) tl.nlist[ns[t]] = (int32_t)t;
+}
+
+// Level-major copies of what the solve reads (cell, offset, F, m) and the
+// transfer-to-grid terms mv = m v and Q = m (k / dx) B, so that node i
+// receives w (mv + Q r) with r = (x_i - x_p) / dx (the B D^{-1} (x_i - x_p)
+// term of Sec. 3.2 with D = dx^2 / k I).  A key's particles are first put in
+// ascending index order, so the copy and every sum after it are the same on
+// every run.
+template <int DIM, int DEG>
+__global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorted S, MidTiles tl) {
+    const int lane = threadIdx.x;
+    const int64_t t = tl.klist[blockIdx.x];
+    const uint32_t k0 = S.start[t * 64 + lane], cnt = S.start[t * 64 + lane + 1] - k0;
+    uint32_t *seg = S.perm + k0;
+    for (uint32_t i = 1; i < cnt; ++i) {
+        const uint32_t v = seg[i];
+        uint32_t j = i;
+        while (j > 0 && seg[j - 1] > v) {
+            seg[j] = seg[j - 1];
+            --j;
+        }
+        seg[j] = v;
+    }
+    const double kD = inv_D_factor<double, DEG>() / S.dx;
+    for_levels(S.start, t, [&](int64_t pos, uint32_t r, uint32_t) {
+        const int64_t q = seg[r];
+        S.cell[pos] = P.cell[q];
+        const double m = P.m[q];
+        S.m[pos] = m;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            S.off[a * S.n + pos] = P.off[a * P.s + q];
+            S.mv[a * S.n + pos] = m * P.v[a * P.s + q];
+        }
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) {
+            S.F[k * S.n + pos] = P.F[k * P.s + q];
+            S.M[k * S.n + pos] = m * kD * P.B[k * P.s + q];
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Particle terms, one wavefront per listed key tile
+// ---------------------------------------------------------------------------
+//   TILE_P2G:   node i receives w m and w (mv + Q r)                     (Sec. 3.2)
+//   TILE_FORCE: F_hat = (I + sum_i u_i grad w^T) F with u_i = dt/2 v_i + dt/4 dv_i
+//               (staged), the energy V Psi(F_hat) and node i receives
+//               -V P(F_hat) F^T grad w / dx; F_hat is kept for TILE_APPLY (Sec. 3.3, 4.1)
+//   TILE_APPLY: dF = (sum_i p_i grad w^T) F (p staged) and node i receives
+//               -V (dP/dF(F_hat) : dF) F^T grad w / dx                       (Sec. 4.2)
+enum { TILE_P2G = 0, TILE_FORCE = 1, TILE_APPLY = 2 };
+
+// Waves per SIMD the register allocation of a tile kernel aims at (1: no
+// target).
+template <int DIM, int DEG, int MODE>
+constexpr int tile_waves() {
+    return MODE == TILE_APPLY && DIM == 3 && DEG == 2 ? 3 : 1;
+}
+
+template <int DIM, int DEG, int MODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(tile_waves<DIM, DEG, MODE>()))) void k_mid_tile(MidSorted S, MidGrid g, MidTiles tl, MidMaterial mat, const double *va,
+                                                 const double *vb, double ca, double cb, double *epart,
+                                                 uint32_t *flags, const MidCg *cg) {
+    constexpr int R = region_nodes<DIM, DEG>(), RE = region_edge<DIM, DEG>(), E = tile_edge<DIM>();
+    constexpr int CIN = MODE == TILE_P2G ? 0 : DIM;
+    constexpr int COUT = MODE == TILE_P2G ? 1 + DIM : DIM;
+    constexpr int D2 = DIM * DIM;
+    __shared__ double acc[COUT * R];
+    __shared__ double stage[(CIN > 0 ? CIN : 1) * R];
+    if constexpr (MODE == TILE_APPLY) {
+        if (cg->done) return;
+    }
+    const int lane = threadIdx.x;
+    const int64_t t = tl.klist[blockIdx.x];
+    int tc[3];
+    tile_coords<DIM>(g, t, tc);
+    const int org[3] = {tc[0] * E, tc[1] * E, tc[2] * E};
+    for (int k = lane; k < COUT * R; k += 64) acc[k] = 0.0;
+    if constexpr (CIN > 0) {
+        for (int k = lane; k < R; k += 64) {
+            const int rx = k % RE, ry = DIM == 3 ? (k / RE) % RE : k / RE, rz = DIM == 3 ? k / (RE * RE) : 0;
+            const int x = org[0] + rx, y = org[1] + ry, z = org[2] + rz;
+            const bool in = x < g.N[0] && y < g.N[1] && (DIM == 2 || z < g.N[2]);
+            const int64_t i = in ? node_slot<DIM>(g, x, y, z) : 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double u = 0.0;
+                if (in) {
+                    u = ca * va[a * g.nodes + i];
+                    if (vb) u += cb * vb[a * g.nodes + i];
+                }
+                stage[a * R + k] = u;
+            }
+        }
+    }
+    __syncthreads();
+    double energy = 0.0;
+    const double inv_dx = 1.0 / g.dx, inv_rho0 = 1.0 / mat.rho0;
+    for_levels(S.start, t, [&](int64_t pos, uint32_t, uint32_t) {
         Axis<double, DEG> ax[DIM];
         sorted_axes<DIM, DEG>(S, pos, ax);
-        double F[DIM * DIM], G[DIM * DIM], Fh[DIM * DIM], IT[DIM * DIM], M[DIM * DIM];
+        const int rb[3] = {ax[0].base - org[0], ax[1].base - org[1], DIM == 3 ? ax[DIM - 1].base - org[2] : 0};
+        // region index of the first node of support row (j, k)
+        auto row_start = [&](int j, int k) {
+            return DIM == 3 ? rb[0] + RE * ((rb[1] + j) + RE * (rb[2] + k)) : rb[0] + RE * (rb[1] + j);
+        };
+        if constexpr (MODE == TILE_P2G) {
+            // node i receives w m and w (mv + Q r): per row, mv + Q r without the x term
+            double Q[D2], mvq[DIM];
+            const double mq = S.m[pos];
 #pragma unroll
-        for (int k = 0; k < DIM * DIM; ++k) F[k] = S.F[k * S.n + pos];
-        gather_grad<DIM, DEG>(ax, g, gv, dv, 0.5 * dt, 0.25 * dt, G);
+            for (int a = 0; a < DIM; ++a) mvq[a] = S.mv[a * S.n + pos];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
-        mat_mul<DIM>(G, F, Fh);
-        const double J = det_inv_t<DIM>(Fh, IT);
-        const double V = S.m[pos] / mat.rho0;
+            for (int k = 0; k < D2; ++k) Q[k] = S.M[k * S.n + pos];
+            for_rows<DIM, DEG>(ax, [&](int j, int k, double wr, double, double, double ry, double rz) {
+                const int r0 = row_start(j, k);
+                double base[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM * DIM; ++k) M[k] = 0.0;
-        if (!(J > 0.0)) {
-            if (!DIFF) {
-                atomicOr(flags, (uint32_t)APIC_FLAG_INVERTED);
-                acc[0] = INFINITY;
-            }
-        } else {
-            const double lnJ = log(J);
-            double Pk[DIM * DIM];
-            if constexpr (!DIFF) {
-                double tr = 0.0;
-#pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) {
-                    tr += Fh[k] * Fh[k];
-                    Pk[k] = mat.mu * (Fh[k] - IT[k]) + mat.lambda * lnJ * IT[k];
+                for (int a = 0; a < DIM; ++a) {
+                    base[a] = mvq[a] + Q[a * DIM + 1] * ry;
+                    if constexpr (DIM == 3) base[a] += Q[a * DIM + 2] * rz;
                 }
-                acc[0] = V * (0.5 * mat.mu * (tr - DIM) - mat.mu * lnJ + 0.5 * mat.lambda * lnJ * lnJ);
+#pragma unroll
+                for (int i = 0; i <= DEG; ++i) {
+                    const double w = ax[0].w[i] * wr;
+                    atomicAdd(&acc[r0 + i], w * mq);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a)
+                        atomicAdd(&acc[(1 + a) * R + r0 + i], w * (base[a] + Q[a * DIM] * ax[0].r[i]));
+                }
+            });
+        } else {
+            double F[D2], G[D2], IT[D2], Pk[D2];
+#pragma unroll
+            for (int k = 0; k < D2; ++k) {
+                F[k] = S.F[k * S.n + pos];
+                G[k] = 0.0;
+            }
+            // G = sum_i u_i grad w^T over the staged node values (cell units),
+            // per row: the x sums of w u and dw u, then the row's y, z factors
+            for_rows<DIM, DEG>(ax, [&](int j, int k, double c0, double c1, double c2, double, double) {
+                const int r0 = row_start(j, k);
+                double sw[DIM], sdw[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    sw[a] = 0.0;
+                    sdw[a] = 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i <= DEG; ++i)
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        const double u = stage[a * R + r0 + i];
+                        sw[a] += ax[0].w[i] * u;
+                        sdw[a] += ax[0].dw[i] * u;
+                    }
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    G[a * DIM] += sdw[a] * c0;
+                    G[a * DIM + 1] += sw[a] * c1;
+                    if constexpr (DIM == 3) G[a * DIM + 2] += sw[a] * c2;
+                }
+            });
+#pragma unroll
+            for (int k = 0; k < D2; ++k) G[k] *= inv_dx;
+            const double V = S.m[pos] * inv_rho0;
+            bool ok;
+            if constexpr (MODE == TILE_FORCE) {
+                double Fh[D2];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
+                mat_mul<DIM>(G, F, Fh);
+                const double J = det_inv_t<DIM>(Fh, IT);
+                ok = J > 0.0;
+                if (!ok) {
+                    atomicOr(flags, (uint32_t)APIC_FLAG_INVERTED);
+                    energy = INFINITY;
+                } else {
+                    const double lnJ = log(J);
+                    double tr = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D2; ++k) {
+                        tr += Fh[k] * Fh[k];
+                        Pk[k] = mat.mu * (Fh[k] - IT[k]) + mat.lambda * lnJ * IT[k];
+                    }
+                    energy += V * (0.5 * mat.mu * (tr - DIM) - mat.mu * lnJ + 0.5 * mat.lambda * lnJ * lnJ);
+                    // kept for the differential: F_hat^{-T} and mu - lambda ln J
+#pragma unroll
+                    for (int k = 0; k < D2; ++k) S.M[k * S.n + pos] = IT[k];
+                    S.M[D2 * S.n + pos] = mat.mu - mat.lambda * lnJ;
+                }
             } else {
-                double H[DIM * DIM], dF[DIM * DIM], dFt[DIM * DIM], T1[DIM * DIM], T2[DIM * DIM];
-                gather_grad<DIM, DEG>(ax, g, du, du, 1.0, 0.0, H);
-                mat_mul<DIM>(H, F, dF);
-                // tr(F_hat^{-1} dF) = sum_ab IT_ab dF_ab;  T2 = F_hat^{-T} dF^T F_hat^{-T}
+                // dP = mu dF + (mu - lambda ln J) F_hat^{-T} dF^T F_hat^{-T} + lambda tr(F_hat^{-1} dF) F_hat^{-T}
+                // (an inverted F_hat was rejected by the line search: its element is not kept)
+#pragma unroll
+                for (int k = 0; k < D2; ++k) IT[k] = S.M[k * S.n + pos];
+                const double cT = S.M[D2 * S.n + pos];
+                ok = true;
+                double dF[D2], dFt[D2], T1[D2], T2[D2];
+                mat_mul<DIM>(G, F, dF);
                 double tr = 0.0;
 #pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) tr += IT[k] * dF[k];
+                for (int k = 0; k < D2; ++k) tr += IT[k] * dF[k];
 #pragma unroll
                 for (int r = 0; r < DIM; ++r)
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) dFt[r * DIM + c] = dF[c * DIM + r];
                 mat_mul<DIM>(IT, dFt, T1);
                 mat_mul<DIM>(T1, IT, T2);
-                const double cT = mat.mu - mat.lambda * lnJ;
 #pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) Pk[k] = mat.mu * dF[k] + cT * T2[k] + mat.lambda * tr * IT[k];
+                for (int k = 0; k < D2; ++k) Pk[k] = mat.mu * dF[k] + cT * T2[k] + mat.lambda * tr * IT[k];
             }
-            // M = -V Pk F^T / dx
+            if (ok) {
+                // M = -V Pk F^T / dx; node i receives M grad w = dw_x (M e_x) c0 + w_x (M_y c1 + M_z c2)
+                double M[D2];
+                const double cm = -V * inv_dx;
 #pragma unroll
-            for (int r = 0; r < DIM; ++r)
+                for (int r = 0; r < DIM; ++r)
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    double sum = 0.0;
+                    for (int c = 0; c < DIM; ++c) {
+                        double sum = 0.0;
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) sum += Pk[r * DIM + k] * F[c * DIM + k];
-                    M[r * DIM + c] = -V * sum / g.dx;
-                }
+                        for (int k = 0; k < DIM; ++k) sum += Pk[r * DIM + k] * F[c * DIM + k];
+                        M[r * DIM + c] = cm * sum;
+                    }
+                for_rows<DIM, DEG>(ax, [&](int j, int k, double c0, double c1, double c2, double, double) {
+                    const int r0 = row_start(j, k);
+                    double A[DIM], Bv[DIM];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        A[a] = M[a * DIM] * c0;
+                        Bv[a] = M[a * DIM + 1] * c1;
+                        if constexpr (DIM == 3) Bv[a] += M[a * DIM + 2] * c2;
+                    }
+#pragma unroll
+                    for (int i = 0; i <= DEG; ++i)
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a)
+                            atomicAdd(&acc[a * R + r0 + i], ax[0].dw[i] * A[a] + ax[0].w[i] * Bv[a]);
+                });
+            }
         }
+    });
+    __syncthreads();
+    double *sl = tl.slab + (int64_t)blockIdx.x * COUT * R;
+    for (int k = lane; k < COUT * R; k += 64) sl[k] = acc[k];
+    if constexpr (MODE == TILE_FORCE) {
 #pragma unroll
-        for (int k = 0; k < DIM * DIM; ++k) S.M[k * S.n + pos] = M[k];
+        for (int o = 32; o > 0; o >>= 1) energy += __shfl_xor(energy, o, 64);
+        if (lane == 0) epart[blockIdx.x] = energy;
     }
-    if constexpr (!DIFF) block_partials<1>(acc, part);
 }
 
-// Node collect, one block per tile of kRowTile nodes along x of one node row
-// (fixed y, z).  The particles whose support holds a node of the row are
-// those whose base key lies in rows y - DEG..y, z - DEG..z: DEG + 1 (2D) or
-// (DEG + 1)^2 (3D) contiguous runs of the sorted order.  The block's lanes
-// stride over each run (coalesced loads) and add each particle's terms for
-// its DEG + 1 nodes of the row into LDS; the row tile is written once.
-//   COLLECT_P2G:   gm_i = sum w m,  gv_i = sum w (mv + Q r)       (Sec. 3.2)
-//   COLLECT_FORCE: f_i = sum M grad w                             (Sec. 3.3)
-//   COLLECT_APPLY: df_i = sum M grad w, then s_i = p_i - dt^2/4 df_i / m_i on
-//                  free nodes (0 elsewhere) and block partials of <p, s>_M
-enum { COLLECT_P2G = 0, COLLECT_FORCE = 1, COLLECT_APPLY = 2 };
-constexpr int kRowTile = 256;
+// ---------------------------------------------------------------------------
+// Node passes, one wavefront per listed node tile
+// ---------------------------------------------------------------------------
+struct NodeAt {
+    int64_t i;         // slot
+    int c[3], tc[3], lc[3];  // node, tile and in-tile coordinates
+};
 
 template <int DIM>
-__host__ __device__ __forceinline__ int64_t collect_blocks(const int *N) {
-    const int64_t tiles = (N[0] + kRowTile - 1) / kRowTile;
-    return DIM == 3 ? tiles * N[1] * N[2] : tiles * N[1];
+__device__ __forceinline__ bool node_at(const MidGrid &g, const MidTiles &tl, NodeAt &n) {
+    constexpr int E = tile_edge<DIM>();
+    const int64_t li = (int64_t)blockIdx.x * kNodeTilesPerBlock + (threadIdx.x >> 6);
+    if (li >= tl.nn) return false;
+    const int64_t u = tl.nlist[li];
+    tile_coords<DIM>(g, u, n.tc);
+    local_coords<DIM>(threadIdx.x & 63, n.lc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) n.c[a] = n.tc[a] * E + n.lc[a];
+    n.i = u * 64 + (threadIdx.x & 63);
+    return true;
 }
 
-template <int DIM, int DEG, int MODE>
-__global__ __launch_bounds__(kMidBlock) void k_mid_collect(MidSorted S, MidGrid g, double *out_m, double *out_v,
-                                                           const double *mf, const double *pv, double dt,
-                                                           double *part) {
-    constexpr int NC = MODE == COLLECT_P2G ? 1 + DIM : DIM;
-    __shared__ double acc[kRowTile * NC];
-    const int tid = threadIdx.x;
-    const int ntile = (g.N[0] + kRowTile - 1) / kRowTile;
-    const int64_t row = blockIdx.x / ntile;
-    const int x0 = (int)(blockIdx.x % ntile) * kRowTile;
-    const int x1 = (x0 + kRowTile < g.N[0] ? x0 + kRowTile : g.N[0]) - 1;
-    const int cy = (int)(row % g.N[1]);
-    const int cz = DIM == 3 ? (int)(row / g.N[1]) : 0;
-    for (int k = tid; k < kRowTile * NC; k += kMidBlock) acc[k] = 0.0;
-    __syncthreads();
-    const int lo = x0 - DEG > 0 ? x0 - DEG : 0;
-    const int hi = x1 < g.N[0] - 1 - DEG ? x1 : g.N[0] - 1 - DEG;
-    constexpr int NZ = DIM == 3 ? DEG + 1 : 1;
+// Sum of the COUT region sums that cover the node, over the key tiles
+// tc - d, d in {0, 1}^dim, in that order.
+template <int DIM, int DEG, int COUT>
+__device__ __forceinline__ void slab_sum(const MidGrid &g, const MidTiles &tl, const NodeAt &n, double *out) {
+    constexpr int R = region_nodes<DIM, DEG>(), RE = region_edge<DIM, DEG>(), E = tile_edge<DIM>();
 #pragma unroll
-    for (int dz = 0; dz < NZ; ++dz) {
-        const int bz = cz - dz;
-        if (DIM == 3 && (bz < 0 || bz + DEG > g.N[2] - 1)) continue;
+    for (int c = 0; c < COUT; ++c) out[c] = 0.0;
 #pragma unroll
-        for (int dy = 0; dy <= DEG; ++dy) {
-            const int by = cy - dy;
-            if (by < 0 || by + DEG > g.N[1] - 1 || lo > hi) continue;
-            const int64_t krow = (int64_t)g.N[0] * (by + (int64_t)g.N[1] * bz);
-            const int64_t p1 = S.start[krow + hi + 1];
-            for (int64_t pos = S.start[krow + lo] + tid; pos < p1; pos += kMidBlock) {
-                Axis<double, DEG> ax[DIM];
-                sorted_axes<DIM, DEG>(S, pos, ax);
-                // the particle's weights along y (and z) at this row are fixed: index dy (dz)
-                const double wy = ax[1].w[dy], dwy = ax[1].dw[dy], ry = ax[1].r[dy];
-                const double wz = DIM == 3 ? ax[DIM - 1].w[dz] : 1.0;
-                const double dwz = DIM == 3 ? ax[DIM - 1].dw[dz] : 0.0;
-                const double rz = DIM == 3 ? ax[DIM - 1].r[dz] : 0.0;
-                double Mq[DIM * DIM], mq = 0.0, mvq[DIM];
-                if constexpr (MODE == COLLECT_P2G) {
-                    mq = S.m[pos];
+    for (int d = 0; d < (1 << DIM); ++d) {
+        const int dd[3] = {d & 1, (d >> 1) & 1, DIM == 3 ? d >> 2 : 0};
+        int T[3], rc[3];
+        bool ok = true;
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) mvq[a] = S.mv[a * S.n + pos];
-                }
-#pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) Mq[k] = S.M[k * S.n + pos];
-#pragma unroll
-                for (int kx = 0; kx <= DEG; ++kx) {
-                    const int x = ax[0].base + kx;
-                    if (x < x0 || x > x1) continue;
-                    double* cell = acc + (x - x0) * NC;
-                    const double w = ax[0].w[kx] * wy * wz;
-                    if constexpr (MODE == COLLECT_P2G) {
-                        double r[DIM];
-                        r[0] = ax[0].r[kx];
-                        r[1] = ry;
-                        if constexpr (DIM == 3) r[2] = rz;
-                        atomicAdd(&cell[0], w * mq);
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            double qr = 0.0;
-#pragma unroll
-                            for (int b = 0; b < DIM; ++b) qr += Mq[a * DIM + b] * r[b];
-                            atomicAdd(&cell[1 + a], w * (mvq[a] + qr));
-                        }
-                    } else {
-                        double gw[DIM];
-                        gw[0] = ax[0].dw[kx] * wy * wz;
-                        gw[1] = ax[0].w[kx] * dwy * wz;
-                        if constexpr (DIM == 3) gw[2] = ax[0].w[kx] * wy * dwz;
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            double t = 0.0;
-#pragma unroll
-                            for (int b = 0; b < DIM; ++b) t += Mq[a * DIM + b] * gw[b];
-                            atomicAdd(&cell[a], t);
-                        }
-                    }
-                }
-            }
+        for (int a = 0; a < 3; ++a) {
+            T[a] = n.tc[a] - dd[a];
+            rc[a] = n.lc[a] + E * dd[a];
+            ok = ok && T[a] >= 0 && (a >= DIM || rc[a] < RE);
         }
+        if (!ok) continue;
+        const int32_t s = tl.slot[tile_index<DIM>(g, T)];
+        if (s < 0) continue;
+        const int ri = DIM == 3 ? rc[0] + RE * (rc[1] + RE * rc[2]) : rc[0] + RE * rc[1];
+        const double *sl = tl.slab + (int64_t)s * COUT * R + ri;
+#pragma unroll
+        for (int c = 0; c < COUT; ++c) out[c] += sl[c * R];
     }
-    __syncthreads();
-    double part_acc[1] = {0.0};
-    const int64_t rowbase = (int64_t)g.N[0] * row;
-    for (int x = x0 + tid; x <= x1; x += kMidBlock) {
-        const int64_t i = rowbase + x;
-        const double *cell = acc + (x - x0) * NC;
-        if constexpr (MODE == COLLECT_P2G) {
-            out_m[i] = cell[0];
+}
+
+// mf_i = m_i and v_i = (m v)_i / m_i on free nodes (mass, outside the sticky
+// band); 0 elsewhere.
+template <int DIM, int DEG>
+__global__ __launch_bounds__(kMidBlock) void k_mid_node_p2g(MidGrid g, MidTiles tl, double *mf, double *gv) {
+    NodeAt n;
+    if (!node_at<DIM>(g, tl, n)) return;
+    double sum[1 + DIM];
+    slab_sum<DIM, DEG, 1 + DIM>(g, tl, n, sum);
+    bool sticky = false;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = cell[1 + a];
-        } else if constexpr (MODE == COLLECT_FORCE) {
+    for (int a = 0; a < DIM; ++a)
+        sticky = sticky || n.c[a] < g.band[2 * a] || n.c[a] > g.N[a] - 1 - g.band[2 * a + 1];
+    const double m = sum[0];
+    const bool free_node = m > 0.0 && !sticky;
+    mf[n.i] = free_node ? m : 0.0;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) out_v[a * g.nodes + i] = cell[a];
-        } else {
-            const double m = mf[i];
-            const double cc = 0.25 * dt * dt;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                const int64_t k = a * g.nodes + i;
-                double sa = 0.0;
-                if (m > 0.0) {
-                    sa = pv[k] - cc * cell[a] / m;
-                    part_acc[0] += m * pv[k] * sa;
-                }
-                out_v[k] = sa;
-            }
-        }
-    }
-    if constexpr (MODE == COLLECT_APPLY) block_partials<1>(part_acc, part);
+    for (int a = 0; a < DIM; ++a) gv[a * g.nodes + n.i] = free_node ? sum[1 + a] / m : 0.0;
 }
 
 // r_i = dv_i - dt (f_i / m_i + g) on free nodes (the gradient of E over
-// m_i / 4); partials: sum m |r|^2 and sum m (|dv|^2 / 8 - dt/4 g.dv).
-template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_residual(MidGrid g, const double *mf, const double *f,
-                                                            const double *dv, double dt, double3 grav, double *r,
-                                                            double *part) {
-    const int64_t i = gtid();
+// m_i / 4, Sec. 4.1); block partials of sum m |r|^2 and sum m (|dv|^2 / 8 -
+// dt/4 g.dv).
+template <int DIM, int DEG, bool ELASTIC>
+__global__ __launch_bounds__(kMidBlock) void k_mid_node_force(MidGrid g, MidTiles tl, const double *mf,
+                                                              const double *dv, double dt, double3 grav, double *r,
+                                                              double *part) {
     double acc[2] = {0.0, 0.0};
-    if (i < g.nodes) {
-        const double m = mf[i];
+    NodeAt n;
+    if (node_at<DIM>(g, tl, n)) {
+        double f[DIM];
+        if constexpr (ELASTIC)
+            slab_sum<DIM, DEG, DIM>(g, tl, n, f);
+        else
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) f[a] = 0.0;
+        const double m = mf[n.i];
         const double gr[3] = {grav.x, grav.y, grav.z};
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const int64_t k = a * g.nodes + i;
+            const int64_t k = a * g.nodes + n.i;
             double ra = 0.0;
             if (m > 0.0) {
-                ra = dv[k] - dt * (f[k] / m + gr[a]);
+                ra = dv[k] - dt * (f[a] / m + gr[a]);
                 acc[0] += m * ra * ra;
                 acc[1] += m * (0.125 * dv[k] * dv[k] - 0.25 * dt * gr[a] * dv[k]);
             }
@@ -557,17 +809,49 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_residual(MidGrid g, const dou
     block_partials<2>(acc, part);
 }
 
-// CG start: rc = b = -r, p = rc, delta = 0; partial <rc, rc>_M.
-template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_cg_init(MidGrid g, const double *mf, const double *r,
-                                                           double *delta, double *rc, double *pv, double *part) {
-    const int64_t i = gtid();
+// s_i = p_i - dt^2/4 (df/dx p)_i / m_i on free nodes (0 elsewhere); block
+// partials of <p, s>_M.
+template <int DIM, int DEG, bool ELASTIC>
+__global__ __launch_bounds__(kMidBlock) void k_mid_node_apply(MidGrid g, MidTiles tl, const double *mf,
+                                                              const double *pv, double dt, double *s, double *part,
+                                                              const MidCg *cg) {
+    if (cg->done) return;
     double acc[1] = {0.0};
-    if (i < g.nodes) {
-        const double m = mf[i];
+    NodeAt n;
+    if (node_at<DIM>(g, tl, n)) {
+        double df[DIM];
+        if constexpr (ELASTIC)
+            slab_sum<DIM, DEG, DIM>(g, tl, n, df);
+        else
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) df[a] = 0.0;
+        const double m = mf[n.i];
+        const double cc = 0.25 * dt * dt;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const int64_t k = a * g.nodes + i;
+            const int64_t k = a * g.nodes + n.i;
+            double sa = 0.0;
+            if (m > 0.0) {
+                sa = pv[k] - cc * df[a] / m;
+                acc[0] += m * pv[k] * sa;
+            }
+            s[k] = sa;
+        }
+    }
+    block_partials<1>(acc, part);
+}
+
+// CG start: rc = b = -r, p = rc, delta = 0; block partials of <rc, rc>_M.
+template <int DIM>
+__global__ __launch_bounds__(kMidBlock) void k_mid_cg_init(MidGrid g, MidTiles tl, const double *mf, const double *r,
+                                                           double *delta, double *rc, double *pv, double *part) {
+    double acc[1] = {0.0};
+    NodeAt n;
+    if (node_at<DIM>(g, tl, n)) {
+        const double m = mf[n.i];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int64_t k = a * g.nodes + n.i;
             const double b = -r[k];
             rc[k] = b;
             pv[k] = b;
@@ -578,18 +862,28 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_cg_init(MidGrid g, const doub
     block_partials<1>(acc, part);
 }
 
-// delta += alpha p, rc -= alpha s; partial <rc, rc>_M.
+// delta += alpha p, rc -= alpha s; block partials of <rc, rc>_M.  When the
+// first <p, s>_M was not positive, delta = -r (the steepest-descent
+// direction) instead.
 template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_cg_step(MidGrid g, const double *mf, double alpha,
+__global__ __launch_bounds__(kMidBlock) void k_mid_cg_step(MidGrid g, MidTiles tl, const double *mf, const double *r,
                                                            const double *pv, const double *s, double *delta,
-                                                           double *rc, double *part) {
-    const int64_t i = gtid();
+                                                           double *rc, double *part, const MidCg *cg) {
+    NodeAt n;
+    if (cg->fallback) {
+        if (node_at<DIM>(g, tl, n))
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) delta[a * g.nodes + n.i] = -r[a * g.nodes + n.i];
+        return;
+    }
+    if (cg->done) return;
+    const double alpha = cg->alpha;
     double acc[1] = {0.0};
-    if (i < g.nodes) {
-        const double m = mf[i];
+    if (node_at<DIM>(g, tl, n)) {
+        const double m = mf[n.i];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const int64_t k = a * g.nodes + i;
+            const int64_t k = a * g.nodes + n.i;
             delta[k] += alpha * pv[k];
             const double ra = rc[k] - alpha * s[k];
             rc[k] = ra;
@@ -599,24 +893,101 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_cg_step(MidGrid g, const doub
     block_partials<1>(acc, part);
 }
 
-// out = a + alpha b over n values.
-__global__ __launch_bounds__(kMidBlock) void k_mid_axpy(int64_t n, const double *a, double alpha, const double *b,
-                                                        double *out) {
-    const int64_t i = gtid();
-    if (i < n) out[i] = (a ? a[i] : 0.0) + alpha * b[i];
+// Scalars from the block partials of the node pass before it (one block; the
+// partials are summed in block order per thread stride, then a fixed tree):
+//   SC_EVAL:  out[0] = sum m |r|^2, out[1] = E = sum m (|dv|^2/8 - dt/4 g.dv)
+//             + sum V Psi (the key tiles' energy partials)
+//   SC_INIT:  gamma = gamma0 = <rc, rc>_M; stop at once when gamma0 is 0 or
+//             no iteration is allowed
+//   SC_ALPHA: alpha = gamma / <p, s>_M, or stop when <p, s>_M is not positive
+//   SC_BETA:  kappa = <rc, rc>_M, beta = kappa / gamma, gamma = kappa; stop at
+//             the tolerance or the iteration cap
+enum { SC_EVAL = 0, SC_INIT = 1, SC_ALPHA = 2, SC_BETA = 3 };
+
+template <int OP>
+__global__ __launch_bounds__(kMidBlock) void k_mid_scalars(const double *part, int64_t nblk, const double *epart,
+                                                           int64_t nk, double *out, MidCg *cg, double tol2,
+                                                           uint32_t max_iters) {
+    if constexpr (OP == SC_ALPHA) {
+        if (cg->done) return;
+    }
+    if constexpr (OP == SC_BETA) {
+        if (cg->done || cg->fallback) return;
+    }
+    if constexpr (OP == SC_EVAL) {
+        const double res2 = block_total(part, nblk, 2, 0);
+        const double kin = block_total(part, nblk, 2, 1);
+        const double phi = epart ? block_total(epart, nk, 1, 0) : 0.0;
+        if (threadIdx.x == 0) {
+            out[0] = res2;
+            out[1] = kin + phi;
+        }
+    } else {
+        const double t = block_total(part, nblk, 1, 0);
+        if (threadIdx.x != 0) return;
+        if constexpr (OP == SC_INIT) {
+            cg->gamma = t;
+            cg->gamma0 = t;
+            cg->tol2 = tol2;
+            cg->k = 0;
+            cg->fallback = 0;
+            cg->max_iters = max_iters;
+            cg->done = (t <= tol2 * t || max_iters == 0) ? 1u : 0u;
+        } else if constexpr (OP == SC_ALPHA) {
+            cg->iters += 1;
+            if (!(t > 0.0)) {
+                cg->done = 1;
+                cg->fallback = cg->k == 0 ? 1u : 0u;
+            } else {
+                cg->alpha = cg->gamma / t;
+            }
+        } else {
+            cg->beta = t / cg->gamma;
+            cg->gamma = t;
+            cg->k += 1;
+            if (t <= cg->tol2 * cg->gamma0 || cg->k >= cg->max_iters) cg->done = 1;
+        }
+    }
+}
+
+// p = rc + beta p.
+template <int DIM>
+__global__ __launch_bounds__(kMidBlock) void k_mid_cg_dir(MidGrid g, MidTiles tl, const double *rc, double *pv,
+                                                          const MidCg *cg) {
+    if (cg->done) return;
+    const double beta = cg->beta;
+    NodeAt n;
+    if (!node_at<DIM>(g, tl, n)) return;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int64_t k = a * g.nodes + n.i;
+        pv[k] = rc[k] + beta * pv[k];
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kMidBlock) void k_mid_axpy(MidGrid g, MidTiles tl, const double *a, double alpha,
+                                                        const double *b, double *out) {
+    NodeAt n;
+    if (!node_at<DIM>(g, tl, n)) return;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const int64_t k = c * g.nodes + n.i;
+        out[k] = (a ? a[k] : 0.0) + alpha * b[k];
+    }
 }
 
 // vt_i = v_i + dv_i on free nodes (0 elsewhere); u_i = xt_i - x_i =
 // dt (v_i + vt_i) / 2.
 template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_finish(MidGrid g, const double *mf, const double *gv,
+__global__ __launch_bounds__(kMidBlock) void k_mid_finish(MidGrid g, MidTiles tl, const double *mf, const double *gv,
                                                           const double *dv, double dt, double *gvt, double *gu) {
-    const int64_t i = gtid();
-    if (i >= g.nodes) return;
-    const bool free_node = mf[i] > 0.0;
+    NodeAt n;
+    if (!node_at<DIM>(g, tl, n)) return;
+    const bool free_node = mf[n.i] > 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const int64_t k = a * g.nodes + i;
+        const int64_t k = a * g.nodes + n.i;
         const double vt = free_node ? gv[k] + dv[k] : 0.0;
         gvt[k] = vt;
         gu[k] = 0.5 * dt * (gv[k] + vt);
@@ -636,32 +1007,39 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_g2p(Parts<double> P, MidGrid 
     if (p >= P.n) return;
     Axis<double, DEG> ax[DIM];
     if (!particle_axes<DIM, DEG>(P, p, g, ax)) return;
+    auto slot = [&](int i, int j, int k) {
+        return node_slot<DIM>(g, ax[0].base + i, ax[1].base + j, DIM == 3 ? ax[DIM - 1].base + k : 0);
+    };
     double v[DIM] = {}, U[DIM] = {};
-    for_support<DIM, DEG>(ax, g, [&](int64_t i, double w, const double *, const double *) {
+    for_support<DIM, DEG, DEG == 2>(ax, [&](double w, const double *, const double *, int i, int j, int k) {
+        const int64_t ni = slot(i, j, k);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            v[a] += w * gvt[a * g.nodes + i];
-            U[a] += w * gu[a * g.nodes + i];
+            v[a] += w * gvt[a * g.nodes + ni];
+            U[a] += w * gu[a * g.nodes + ni];
         }
     });
     double B[DIM * DIM] = {}, G[DIM * DIM] = {};
-    for_support<DIM, DEG>(ax, g, [&](int64_t i, double w, const double *gw, const double *r) {
-        double vt[DIM], e[DIM];
+    for_support<DIM, DEG, DEG == 2>(ax, [&](double w, const double *gw, const double *r, int i, int j, int k) {
+        const int64_t ni = slot(i, j, k);
+        double vt[DIM], e[DIM], un[DIM];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            vt[a] = gvt[a * g.nodes + i];
-            e[a] = gu[a * g.nodes + i] - U[a];
+            vt[a] = gvt[a * g.nodes + ni];
+            un[a] = gu[a * g.nodes + ni];
+            e[a] = un[a] - U[a];
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
 #pragma unroll
             for (int b = 0; b < DIM; ++b) {
                 B[a * DIM + b] += w * (vt[a] * r[b] * g.dx + 0.5 * (vt[a] * e[b] - e[a] * vt[b]));
-                G[a * DIM + b] += gu[a * g.nodes + i] * gw[b];
+                G[a * DIM + b] += un[a] * gw[b];
             }
     });
     double F[DIM * DIM], Fn[DIM * DIM];
-    load_mat<DIM>(P.F, P.s, p, F);
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) F[k] = P.F[k * P.s + p];
     const double s = 1.0 / g.dx;
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) G[k] *= s;
@@ -686,24 +1064,6 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_g2p(Parts<double> P, MidGrid 
     }
 }
 
-// out[k] = sum over nblk blocks of part[b * K + k], in block order per thread
-// stride, then a fixed tree (deterministic for a given nblk).
-__global__ __launch_bounds__(kMidBlock) void k_mid_reduce(const double *part, int64_t nblk, int K, double *out) {
-    __shared__ double red[kMidBlock];
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int64_t b = threadIdx.x; b < nblk; b += kMidBlock) s += part[b * K + k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = kMidBlock / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = red[0];
-        __syncthreads();
-    }
-}
-
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kMidBlock - 1) / kMidBlock); }
 
 }  // namespace
@@ -711,17 +1071,28 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kMidBlock - 1) / 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-void launch_mid_fill(double *a, int64_t n, double val, hipStream_t st) {
-    if (n > 0) k_mid_fill<<<blocks_for(n), kMidBlock, 0, st>>>(a, n, val);
+MidGrid mid_grid(int dim, const int *cells, const int *band, double dx) {
+    MidGrid g{};
+    const int E = dim == 3 ? tile_edge<3>() : tile_edge<2>();
+    g.tiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.N[a] = a < dim ? cells[a] + 1 : 1;
+        g.T[a] = a < dim ? (g.N[a] + E - 1) / E : 1;
+        g.tiles *= g.T[a];
+    }
+    for (int k = 0; k < 6; ++k) g.band[k] = band[k];
+    g.nodes = g.tiles * 64;
+    g.dx = dx;
+    return g;
 }
 
-void launch_mid_reduce(const double *part, int64_t nblk, int K, double *out, hipStream_t st) {
-    k_mid_reduce<<<1, kMidBlock, 0, st>>>(part, nblk, K, out);
+int mid_region_nodes(int dim, int degree) {
+    if (dim == 3) return degree == 2 ? region_nodes<3, 2>() : region_nodes<3, 3>();
+    return degree == 2 ? region_nodes<2, 2>() : region_nodes<2, 3>();
 }
 
-void launch_mid_axpy(int64_t n, const double *a, double alpha, const double *b, double *out, hipStream_t st) {
-    if (n > 0) k_mid_axpy<<<blocks_for(n), kMidBlock, 0, st>>>(n, a, alpha, b, out);
-}
+int64_t mid_node_blocks(int64_t nn) { return (nn + kNodeTilesPerBlock - 1) / kNodeTilesPerBlock; }
+int64_t mid_scan_blocks(int64_t nodes) { return (nodes + 1023) / 1024; }
 
 // flags |= trial, trial = 0: the flag bits of the iterate the line search
 // accepted join the call's flags (rejected trials leave none).
@@ -736,82 +1107,117 @@ void launch_mid_flags_accept(uint32_t *flags, uint32_t *trial, hipStream_t st) {
     k_mid_flags_accept<<<1, 64, 0, st>>>(flags, trial);
 }
 
-int64_t mid_particle_blocks(int64_t n) { return blocks_for(n); }
-int64_t mid_node_blocks(int64_t nodes) { return blocks_for(nodes); }
-int64_t mid_scan_blocks(int64_t nodes) { return (nodes + 1023) / 1024; }
-int64_t mid_collect_blocks(int dim, const int *N) { return dim == 3 ? collect_blocks<3>(N) : collect_blocks<2>(N); }
-
 template <int DIM, int DEG>
-void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, uint32_t *key, uint32_t *count,
-                     uint32_t *cursor, uint32_t *bsum, uint32_t *flags, hipStream_t st) {
-    launch_fill<uint32_t>(count, g.nodes, 0u, st);
-    launch_fill<uint32_t>(cursor, g.nodes, 0u, st);
+void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, const MidTiles &tl, uint32_t *key,
+                     uint32_t *count, uint32_t *cursor, uint32_t *bsum, int32_t *counts, uint32_t *flags,
+                     hipStream_t st) {
+    k_mid_fill_u32<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(count, g.nodes);
+    k_mid_fill_u32<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(cursor, g.nodes);
     if (P.n > 0) k_mid_keys<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, key, count, flags);
     const int64_t nb = mid_scan_blocks(g.nodes);
     uint32_t *start = const_cast<uint32_t *>(S.start);
     k_mid_scan1<<<(unsigned)nb, kMidBlock, 0, st>>>(count, g.nodes, start, bsum);
     k_mid_scan2<<<1, kMidBlock, 0, st>>>(bsum, nb, start, g.nodes);
     k_mid_scan3<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(start, g.nodes, bsum);
-    if (P.n > 0) {
-        k_mid_place<<<blocks_for(P.n), kMidBlock, 0, st>>>(P.n, key, S.start, cursor, const_cast<uint32_t *>(S.perm));
-        k_mid_sort_state<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, S);
+    if (P.n > 0) k_mid_place<<<blocks_for(P.n), kMidBlock, 0, st>>>(P.n, key, S.start, cursor, S.perm);
+    // count and cursor are free again: tile flags and their prefix sums
+    uint32_t *kf = count, *nf = count + g.tiles, *ks = cursor, *ns = cursor + g.tiles + 1;
+    const int64_t tb = mid_scan_blocks(g.tiles);
+    k_mid_tile_flags<DIM><<<blocks_for(g.tiles), kMidBlock, 0, st>>>(g, S.start, kf, nf);
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t *f = q == 0 ? kf : nf;
+        uint32_t *sc = q == 0 ? ks : ns;
+        k_mid_scan1<<<(unsigned)tb, kMidBlock, 0, st>>>(f, g.tiles, sc, bsum);
+        k_mid_scan2<<<1, kMidBlock, 0, st>>>(bsum, tb, sc, g.tiles);
+        k_mid_scan3<<<blocks_for(g.tiles), kMidBlock, 0, st>>>(sc, g.tiles, bsum);
     }
-}
-
-template <int DIM>
-void launch_mid_nodes(const MidGrid &g, const double *gm, double *gv, double *mf, hipStream_t st) {
-    k_mid_nodes<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, gm, gv, mf);
-}
-
-template <int DIM, int DEG, bool DIFF>
-void launch_mid_stress(const MidSorted &S, const MidGrid &g, const MidMaterial &mat, const double *gv,
-                       const double *dv, double dt, const double *du, double *part, uint32_t *flags, hipStream_t st) {
-    if (S.n > 0) k_mid_stress<DIM, DEG, DIFF><<<blocks_for(S.n), kMidBlock, 0, st>>>(S, g, mat, gv, dv, dt, du, part,
-                                                                                     flags);
+    k_mid_tile_place<<<blocks_for(g.tiles), kMidBlock, 0, st>>>(g.tiles, kf, nf, ks, ns, tl, counts);
 }
 
 template <int DIM, int DEG>
-void launch_mid_collect_p2g(const MidSorted &S, const MidGrid &g, double *gm, double *gmv, hipStream_t st) {
-    k_mid_collect<DIM, DEG, COLLECT_P2G><<<(unsigned)collect_blocks<DIM>(g.N), kMidBlock, 0, st>>>(S, g, gm, gmv, nullptr, nullptr,
-                                                                                    0.0, nullptr);
+void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const MidTiles &tl, hipStream_t st) {
+    if (tl.nk > 0) k_mid_sort_state<DIM, DEG><<<(unsigned)tl.nk, 64, 0, st>>>(P, S, tl);
 }
 
 template <int DIM, int DEG>
-void launch_mid_collect_force(const MidSorted &S, const MidGrid &g, double *f, hipStream_t st) {
-    k_mid_collect<DIM, DEG, COLLECT_FORCE><<<(unsigned)collect_blocks<DIM>(g.N), kMidBlock, 0, st>>>(S, g, nullptr, f, nullptr,
-                                                                                      nullptr, 0.0, nullptr);
+void launch_mid_p2g(const MidSorted &S, const MidGrid &g, const MidTiles &tl, double *mf, double *gv, hipStream_t st) {
+    if (tl.nk == 0) return;
+    k_mid_tile<DIM, DEG, TILE_P2G><<<(unsigned)tl.nk, 64, 0, st>>>(S, g, tl, MidMaterial{}, nullptr, nullptr, 0.0, 0.0,
+                                                                   nullptr, nullptr, nullptr);
+    k_mid_node_p2g<DIM, DEG><<<(unsigned)mid_node_blocks(tl.nn), kMidBlock, 0, st>>>(g, tl, mf, gv);
 }
 
 template <int DIM, int DEG>
-void launch_mid_collect_apply(const MidSorted &S, const MidGrid &g, const double *mf, const double *pv, double dt,
-                              double *s, double *part, hipStream_t st) {
-    k_mid_collect<DIM, DEG, COLLECT_APPLY><<<(unsigned)collect_blocks<DIM>(g.N), kMidBlock, 0, st>>>(S, g, nullptr, s, mf, pv, dt,
-                                                                                      part);
-}
-
-template <int DIM>
-void launch_mid_residual(const MidGrid &g, const double *mf, const double *f, const double *dv, double dt,
-                         const double *grav, double *r, double *part, hipStream_t st) {
+void launch_mid_force(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
+                      const double *gv, const double *dv, double dt, const double *grav, const double *mf, double *r,
+                      double *epart, double *part, double *out, uint32_t *flags, hipStream_t st) {
+    if (tl.nk == 0) return;
     const double3 gr = make_double3(grav[0], grav[1], grav[2]);
-    k_mid_residual<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, mf, f, dv, dt, gr, r, part);
+    const int64_t nb = mid_node_blocks(tl.nn);
+    if (elastic) {
+        k_mid_tile<DIM, DEG, TILE_FORCE><<<(unsigned)tl.nk, 64, 0, st>>>(S, g, tl, mat, gv, dv, 0.5 * dt, 0.25 * dt,
+                                                                         epart, flags, nullptr);
+        k_mid_node_force<DIM, DEG, true><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, dv, dt, gr, r, part);
+    } else {
+        k_mid_node_force<DIM, DEG, false><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, dv, dt, gr, r, part);
+    }
+    k_mid_scalars<SC_EVAL><<<1, kMidBlock, 0, st>>>(part, nb, elastic ? epart : nullptr, tl.nk, out, nullptr, 0.0, 0);
+}
+
+template <int DIM, int DEG>
+void launch_mid_apply(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
+                      const double *pv, const double *mf, double dt, double *s, double *part, MidCg *cg,
+                      hipStream_t st) {
+    if (tl.nk == 0) return;
+    const int64_t nb = mid_node_blocks(tl.nn);
+    if (elastic) {
+        k_mid_tile<DIM, DEG, TILE_APPLY><<<(unsigned)tl.nk, 64, 0, st>>>(S, g, tl, mat, pv, nullptr, 1.0, 0.0, nullptr,
+                                                                         nullptr, cg);
+        k_mid_node_apply<DIM, DEG, true><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, pv, dt, s, part, cg);
+    } else {
+        k_mid_node_apply<DIM, DEG, false><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, pv, dt, s, part, cg);
+    }
+    k_mid_scalars<SC_ALPHA><<<1, kMidBlock, 0, st>>>(part, nb, nullptr, 0, nullptr, cg, 0.0, 0);
 }
 
 template <int DIM>
-void launch_mid_cg_init(const MidGrid &g, const double *mf, const double *r, double *delta, double *rc, double *pv,
-                        double *part, hipStream_t st) {
-    k_mid_cg_init<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, mf, r, delta, rc, pv, part);
+void launch_mid_cg_init(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, double *delta,
+                        double *rc, double *pv, double *part, MidCg *cg, double tol2, uint32_t max_iters,
+                        hipStream_t st) {
+    if (tl.nn == 0) return;
+    const int64_t nb = mid_node_blocks(tl.nn);
+    k_mid_cg_init<DIM><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, r, delta, rc, pv, part);
+    k_mid_scalars<SC_INIT><<<1, kMidBlock, 0, st>>>(part, nb, nullptr, 0, nullptr, cg, tol2, max_iters);
 }
 
 template <int DIM>
-void launch_mid_cg_step(const MidGrid &g, const double *mf, double alpha, const double *pv, const double *s,
-                        double *delta, double *rc, double *part, hipStream_t st) {
-    k_mid_cg_step<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, mf, alpha, pv, s, delta, rc, part);
+void launch_mid_cg_step(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, const double *pv,
+                        const double *s, double *delta, double *rc, double *part, MidCg *cg, hipStream_t st) {
+    if (tl.nn == 0) return;
+    const int64_t nb = mid_node_blocks(tl.nn);
+    k_mid_cg_step<DIM><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, r, pv, s, delta, rc, part, cg);
+    k_mid_scalars<SC_BETA><<<1, kMidBlock, 0, st>>>(part, nb, nullptr, 0, nullptr, cg, 0.0, 0);
 }
 
 template <int DIM>
-void launch_mid_finish(const MidGrid &g, const double *mf, const double *gv, const double *dv, double dt, double *gvt,
-                       double *gu, hipStream_t st) {
-    k_mid_finish<DIM><<<blocks_for(g.nodes), kMidBlock, 0, st>>>(g, mf, gv, dv, dt, gvt, gu);
+void launch_mid_cg_dir(const MidGrid &g, const MidTiles &tl, const double *rc, double *pv, const MidCg *cg,
+                       hipStream_t st) {
+    if (tl.nn == 0) return;
+    k_mid_cg_dir<DIM><<<(unsigned)mid_node_blocks(tl.nn), kMidBlock, 0, st>>>(g, tl, rc, pv, cg);
+}
+
+template <int DIM>
+void launch_mid_axpy(const MidGrid &g, const MidTiles &tl, const double *a, double alpha, const double *b, double *out,
+                     hipStream_t st) {
+    if (tl.nn == 0) return;
+    k_mid_axpy<DIM><<<(unsigned)mid_node_blocks(tl.nn), kMidBlock, 0, st>>>(g, tl, a, alpha, b, out);
+}
+
+template <int DIM>
+void launch_mid_finish(const MidGrid &g, const MidTiles &tl, const double *mf, const double *gv, const double *dv,
+                       double dt, double *gvt, double *gu, hipStream_t st) {
+    if (tl.nn == 0) return;
+    k_mid_finish<DIM><<<(unsigned)mid_node_blocks(tl.nn), kMidBlock, 0, st>>>(g, tl, mf, gv, dv, dt, gvt, gu);
 }
 
 template <int DIM, int DEG>
@@ -819,32 +1225,36 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
     if (P.n > 0) k_mid_g2p<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, gvt, gu);
 }
 
-#define APIC_MID_INST_DD(DIM, DEG)                                                                                   \
-    template void launch_mid_sort<DIM, DEG>(const Parts<double> &, const MidGrid &, const MidSorted &, uint32_t *,   \
-                                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, hipStream_t);            \
-    template void launch_mid_stress<DIM, DEG, false>(const MidSorted &, const MidGrid &, const MidMaterial &,         \
-                                                     const double *, const double *, double, const double *,         \
-                                                     double *, uint32_t *, hipStream_t);                             \
-    template void launch_mid_stress<DIM, DEG, true>(const MidSorted &, const MidGrid &, const MidMaterial &,          \
-                                                    const double *, const double *, double, const double *,          \
-                                                    double *, uint32_t *, hipStream_t);                              \
-    template void launch_mid_collect_p2g<DIM, DEG>(const MidSorted &, const MidGrid &, double *, double *,           \
-                                                   hipStream_t);                                                     \
-    template void launch_mid_collect_force<DIM, DEG>(const MidSorted &, const MidGrid &, double *, hipStream_t);     \
-    template void launch_mid_collect_apply<DIM, DEG>(const MidSorted &, const MidGrid &, const double *,             \
-                                                     const double *, double, double *, double *, hipStream_t);       \
-    template void launch_mid_g2p<DIM, DEG>(const Parts<double> &, const MidGrid &, const double *, const double *,   \
+#define APIC_MID_INST_DD(DIM, DEG)                                                                                    \
+    template void launch_mid_sort<DIM, DEG>(const Parts<double> &, const MidGrid &, const MidSorted &,                \
+                                            const MidTiles &, uint32_t *, uint32_t *, uint32_t *, uint32_t *,         \
+                                            int32_t *, uint32_t *, hipStream_t);                                      \
+    template void launch_mid_sort_state<DIM, DEG>(const Parts<double> &, const MidSorted &, const MidTiles &,         \
+                                                  hipStream_t);                                                       \
+    template void launch_mid_p2g<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &, double *, double *,  \
+                                           hipStream_t);                                                              \
+    template void launch_mid_force<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,                    \
+                                             const MidMaterial &, bool, const double *, const double *, double,       \
+                                             const double *, const double *, double *, double *, double *,            \
+                                             double *, uint32_t *, hipStream_t);                                      \
+    template void launch_mid_apply<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,                    \
+                                             const MidMaterial &, bool, const double *, const double *, double,       \
+                                             double *, double *, MidCg *, hipStream_t);                               \
+    template void launch_mid_g2p<DIM, DEG>(const Parts<double> &, const MidGrid &, const double *, const double *,    \
                                            hipStream_t);
 #define APIC_MID_INST_D(DIM)                                                                                          \
-    template void launch_mid_nodes<DIM>(const MidGrid &, const double *, double *, double *, hipStream_t);           \
-    template void launch_mid_residual<DIM>(const MidGrid &, const double *, const double *, const double *, double,  \
-                                           const double *, double *, double *, hipStream_t);                         \
-    template void launch_mid_cg_init<DIM>(const MidGrid &, const double *, const double *, double *, double *,       \
-                                          double *, double *, hipStream_t);                                          \
-    template void launch_mid_cg_step<DIM>(const MidGrid &, const double *, double, const double *, const double *,   \
-                                          double *, double *, double *, hipStream_t);                                \
-    template void launch_mid_finish<DIM>(const MidGrid &, const double *, const double *, const double *, double,    \
-                                         double *, double *, hipStream_t);
+    template void launch_mid_cg_init<DIM>(const MidGrid &, const MidTiles &, const double *, const double *,          \
+                                          double *, double *, double *, double *, MidCg *, double, uint32_t,          \
+                                          hipStream_t);                                                               \
+    template void launch_mid_cg_step<DIM>(const MidGrid &, const MidTiles &, const double *, const double *,          \
+                                          const double *, const double *, double *, double *, double *, MidCg *,      \
+                                          hipStream_t);                                                               \
+    template void launch_mid_cg_dir<DIM>(const MidGrid &, const MidTiles &, const double *, double *, const MidCg *,  \
+                                         hipStream_t);                                                                \
+    template void launch_mid_axpy<DIM>(const MidGrid &, const MidTiles &, const double *, double, const double *,     \
+                                       double *, hipStream_t);                                                        \
+    template void launch_mid_finish<DIM>(const MidGrid &, const MidTiles &, const double *, const double *,           \
+                                         const double *, double, double *, double *, hipStream_t);
 
 APIC_MID_INST_DD(2, 2)
 APIC_MID_INST_DD(2, 3)
