@@ -221,7 +221,9 @@ def spheres(steps: int):
 def midpoint(steps: int, cells: int = 128):
     """Implicit midpoint steps (apic_step_midpoint, binary64) on the elastic
     cube at two step sizes, with the explicit binary64 step beside it:
-    particle-updates/s and simulated time per wall second."""
+    particle-updates/s and simulated time per wall second.  The library
+    brackets the particle pass of every CG iteration (and of every force
+    evaluation) with HIP events on this stream during the timed steps."""
     import dataclasses
 
     import torch
@@ -230,7 +232,7 @@ def midpoint(steps: int, cells: int = 128):
     from paper_1603_06188_amd import scenes
 
     base = scenes.cube3d(cells=cells, precision="fp64")
-    out = {"particles": base.n}
+    out = {"particles": base.n, "tiles": midpoint_tiles(base)}
     ds = b.DeviceScene(base, with_id=False)
     ds.step(2)
     torch.cuda.synchronize()
@@ -247,43 +249,74 @@ def midpoint(steps: int, cells: int = 128):
         ds = b.DeviceScene(s, with_id=False, midpoint=True)
         ds.step_midpoint(1)
         torch.cuda.synchronize()
+        b.apic_timing_enable(True)
+        b.apic_timing_read()
         t0 = time.perf_counter()
         st = ds.step_midpoint(steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        tm = b.apic_timing_read()
+        b.apic_timing_enable(False)
         out[f"midpoint_dt{dt:g}"] = {"value": s.n * steps / el, "ms_per_step": el / steps * 1e3,
                                      "sim_time_per_s": dt * steps / el, "newton_per_step": st["newton_iters"] / steps,
                                      "cg_per_step": st["cg_iters"] / steps, "halvings": st["halvings"],
-                                     "converged": st["converged"], "flags": st["flags"]}
+                                     "converged": st["converged"], "flags": st["flags"],
+                                     "apply_launches": tm["mid_apply"][0], "apply_us": tm["mid_apply"][1] * 1e3,
+                                     "force_launches": tm["mid_force"][0], "force_us": tm["mid_force"][1] * 1e3}
         print(f"midpoint dt={dt:g}: {out[f'midpoint_dt{dt:g}']}", file=sys.stderr, flush=True)
         del ds
         torch.cuda.empty_cache()
     return out
 
 
-MIDPOINT_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                                "midpoint_cube128_kernel_trace.md")
+def midpoint_tiles(scene):
+    """Key tiles (4^3 base nodes holding particles) and the node tiles their
+    regions touch, for the initial state of a 3D scene."""
+    import numpy as np
+
+    h = scene.x / scene.dx
+    cell = np.floor(h).astype(np.int64)
+    off = h - cell
+    if scene.degree == 2:
+        base = np.where(off < 0.5, cell - 1, cell)
+    elif scene.degree == 3:
+        base = cell - 1
+    else:
+        base = cell
+    kt = np.unique(base // 4, axis=0)
+    near = np.unique(np.concatenate([kt + np.array(d) for d in np.ndindex(2, 2, 2)]), axis=0)
+    return {"key_tiles": int(len(kt)), "node_tiles": int(len(near))}
 
 
-def midpoint_roofline(particles: int = 2_097_152, active_nodes: int = 300_763):
-    """Roofline of the midpoint step's dominant kernel (the force-differential
-    collect of each CG iteration) from the committed rocprofv3 summary: its
-    mean duration (kernel trace) and HBM bytes (FETCH_SIZE + WRITE_SIZE).
-    Algorithmic bytes per launch: 100 B per particle (cell, offset, matrix)
-    and 56 B per active node (p and s read and written, m)."""
-    if not os.path.exists(MIDPOINT_PROFILE):
+MIDPOINT_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_midpoint_cube128.txt")
+MIDPOINT_APPLY_KERNEL = "k_mid_tile<3, 2, 2>"
+MIDPOINT_PARTICLE_B = 188  # cell 4, offset 24, F 72, F_hat^{-T} 72, mu - lambda ln J 8, m 8
+
+
+def midpoint_roofline(res):
+    """Roofline of the midpoint step's dominant kernel, the particle pass of
+    each CG iteration (operator application), timed live: algorithmic bytes
+    per launch = particles x 188 B + the key tiles' region slabs written
+    (216 nodes x 3 x 8 B) + the direction p read on the listed node tiles
+    (64 nodes x 3 x 8 B), over the mean launch duration; traffic from the
+    committed FETCH_SIZE / WRITE_SIZE summary when it matches the sources."""
+    mode = res["midpoint_dt0.005"]
+    if not mode.get("apply_launches"):
         return None
-    kern = "k_mid_collect<3, 2, 2>"
-    rows = [ln for ln in open(MIDPOINT_PROFILE) if ln.startswith(f"| `{kern}` |")]
-    if len(rows) < 2:
-        return None
-    avg_us = float(rows[0].split("|")[3])
-    fetch_mb, write_mb = (float(rows[1].split("|")[k]) for k in (2, 3))
-    alg = particles * 100 + active_nodes * 56
-    achieved = alg / avg_us / 1e3
-    return {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-            "frac": achieved / 8000.0, "traffic": (fetch_mb + write_mb) * 1e6, "duration_us": avg_us,
-            "duration_source": "profiles/midpoint_cube128_kernel_trace.md (rocprofv3 kernel trace, same workload)"}
+    tiles = res["tiles"]
+    alg = res["particles"] * MIDPOINT_PARTICLE_B + tiles["key_tiles"] * 216 * 24 + tiles["node_tiles"] * 64 * 24
+    achieved = alg / (mode["apply_us"] * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(MIDPOINT_TRAFFIC):
+        from paper_1603_06188_amd import profile_traffic
+
+        summ = profile_traffic.read_summary(MIDPOINT_TRAFFIC)
+        if summ.get("source_sha256") == profile_traffic.source_hash():
+            v = summ.get("k_mid_tile_3_2_2_traffic_bytes")
+            traffic = float(v) if v is not None else None
+    return {"bound": "hbm", "kernel": MIDPOINT_APPLY_KERNEL, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+            "frac": achieved / 8000.0, "traffic": traffic, "algorithmic_bytes": alg,
+            "duration_us": mode["apply_us"], "launches": mode["apply_launches"]}
 
 
 def midpoint_cpu_baseline(cells: int = 64, dt: float = 5e-3):
@@ -368,6 +401,13 @@ def main(argv=None):
                                    "dt=1e-4", "particles": main_mode["particles"]},
             "modes": res}), flush=True)
         return 0
+    if args.calibrate_copy and args.workload == "midpoint":
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "midpoint":
         nsteps = args.steps if args.steps != 100 else 3
         res = midpoint(nsteps, args.cells)
@@ -380,7 +420,7 @@ def main(argv=None):
             "config": {"workload": "elastic cube 128^3, quadratic, neo-Hookean, gravity, sticky floor, implicit "
                                    "midpoint (Newton + mass-inner-product CG), dt=5e-3",
                        "particles": res["particles"]},
-            "roofline": midpoint_roofline(res["particles"]),
+            "roofline": midpoint_roofline(res),
             "cpu_baseline": None if args.no_cpu_baseline else midpoint_cpu_baseline(),
             "modes": res}), flush=True)
         return 0

@@ -376,8 +376,9 @@ apic_status apic_positions_to_absolute(const apic_scene *scene, double *x, void 
 
 /*
  * Kernel timing, for benchmarks.  While enabled, apic_step brackets each of
- * its phases (per scene and step) with a pair of HIP events on the call's
- * stream.  apic_timing_read waits for the recorded events, writes per phase
+ * its phases (per scene and step), and apic_step_midpoint the particle pass
+ * of each force evaluation and CG iteration, with a pair of HIP events on the
+ * call's stream.  apic_timing_read waits for the recorded events, writes per phase
  * (index APIC_PHASE_*) the number of recorded launches to counts[] and their
  * mean duration in milliseconds to mean_ms[] (host arrays of
  * APIC_PHASE_COUNT entries), and forgets the records.  Events are created by
@@ -389,7 +390,11 @@ enum {
     APIC_PHASE_BIN = 2,          /* keys at the advected positions + binning */
     APIC_PHASE_G2P = 3,          /* transfer to particles (re-binned write)  */
     APIC_PHASE_SORT = 4,         /* full re-bin from positions               */
-    APIC_PHASE_COUNT = 5
+    APIC_PHASE_MID_FORCE = 5,    /* midpoint: particle pass of a force evaluation */
+    APIC_PHASE_MID_APPLY = 6,    /* midpoint: particle pass of one CG operator
+                                    application (launches after the CG stopped
+                                    are left out of the records)             */
+    APIC_PHASE_COUNT = 7
 };
 apic_status apic_timing_enable(int32_t enable);
 apic_status apic_timing_read(int64_t *counts, double *mean_ms);

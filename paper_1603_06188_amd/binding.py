@@ -48,7 +48,7 @@ EXPORTED = [
     "apic_last_error", "apic_version", "apic_midpoint_workspace_bytes", "apic_step_midpoint",
     "apic_noalloc_max_bytes", "apic_step_noalloc",
 ]
-APIC_PHASES = ["p2g", "grid_update", "bin", "g2p", "sort"]
+APIC_PHASES = ["p2g", "grid_update", "bin", "g2p", "sort", "mid_force", "mid_apply"]
 
 
 class ApicGridDesc(ctypes.Structure):

@@ -333,6 +333,42 @@ void timed(int phase, hipStream_t st, F &&launch) {
     }
 }
 
+// Like timed(), for a launcher that takes the events itself and has the
+// kernel dispatch stamp them (its start and end, not the stream's
+// surroundings): launch(a, b), a and b null when timing is off.
+template <typename F>
+void timed_kernel(int phase, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        if (g_timing.enabled && !g_untimed) {
+            a = g_timing.take();
+            b = g_timing.take();
+            if (!a || !b) a = b = nullptr;
+        }
+    }
+    launch(a, b);
+    if (a && b) {
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        g_timing.recs.push_back({phase, a, b});
+    }
+}
+
+// Drops the last `count` timing records of `phase` (launches that did no
+// work), returning their events to the pool.
+void untime_last(int phase, int count) {
+    if (count <= 0) return;
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    auto &recs = g_timing.recs;
+    for (size_t i = recs.size(); i > 0 && count > 0; --i) {
+        if (recs[i - 1].phase != phase) continue;
+        g_timing.pool.push_back(recs[i - 1].a);
+        g_timing.pool.push_back(recs[i - 1].b);
+        recs.erase(recs.begin() + (i - 1));
+        --count;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Typed views of one scene
 // ---------------------------------------------------------------------------
@@ -1393,7 +1429,11 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     auto eval = [&](const double *dvx, double &E, double &res) {
         double host[2] = {0.0, 0.0};
         launch_fill<uint32_t>(tflags, 1, 0u, st);
-        launch_mid_force<DIM, DEG>(S, g, tl, mat, elastic, gv, dvx, dt, grav, mf, r, epart, part, out, tflags, st);
+        if (elastic)
+            timed_kernel(APIC_PHASE_MID_FORCE, [&](hipEvent_t a, hipEvent_t b) {
+                launch_mid_force_tiles<DIM, DEG>(S, g, tl, mat, gv, dvx, dt, epart, tflags, st, a, b);
+            });
+        launch_mid_force_nodes<DIM, DEG>(g, tl, elastic, dvx, dt, grav, mf, r, epart, part, out, st);
         fetch(host, out, sizeof host);
         res = sqrt(host[0]);
         E = host[1];
@@ -1404,6 +1444,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     *stats = apic_midpoint_stats{};
     stats->converged = 1;
     const double tol2 = o.cg_tol * o.cg_tol;
+    uint32_t cg_seen = 0;  // CG iterations counted on the device at the last look
     for (int32_t step = 0; step < n_steps && rc0 == APIC_OK; ++step) {
         launch_mid_sort<DIM, DEG>(P, g, S, tl, key, count, cursor, bsum, counts, flags, st);
         int32_t nkn[2] = {0, 0};
@@ -1429,14 +1470,21 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
             for (int k = 0; k < o.max_cg && rc0 == APIC_OK;) {
                 const int chunk = std::min(kCgPoll, o.max_cg - k);
                 for (int j = 0; j < chunk; ++j) {
-                    launch_mid_apply<DIM, DEG>(S, g, tl, mat, elastic, pv, mf, dt, sv, part, cg, st);
+                    if (elastic)
+                        timed_kernel(APIC_PHASE_MID_APPLY, [&](hipEvent_t a, hipEvent_t b) {
+                            launch_mid_apply_tiles<DIM, DEG>(S, g, tl, mat, pv, cg, st, a, b);
+                        });
+                    launch_mid_apply_nodes<DIM, DEG>(g, tl, elastic, pv, mf, dt, sv, part, cg, st);
                     launch_mid_cg_step<DIM>(g, tl, mf, r, pv, sv, delta, rc, part, cg, st);
                     launch_mid_cg_dir<DIM>(g, tl, rc, pv, cg, st);
                 }
                 k += chunk;
-                uint32_t done = 0;
-                fetch(&done, &cg->done, sizeof done);
-                if (done) break;
+                uint32_t poll[5] = {0, 0, 0, 0, 0};  // done, fallback, k, max_iters, iters
+                fetch(poll, &cg->done, sizeof poll);
+                // launches after the stop did no work: out of the timing records
+                if (elastic) untime_last(APIC_PHASE_MID_APPLY, chunk - (int)(poll[4] - cg_seen));
+                cg_seen = poll[4];
+                if (poll[0]) break;
             }
             // backtracking line search: E must not increase, or |r|_M must
             // fall (near the minimum E is flat to within its rounding); a

@@ -226,16 +226,27 @@ void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const Mid
 // Transfer to grid: free-node mass mf and velocity gv.
 template <int DIM, int DEG>
 void launch_mid_p2g(const MidSorted &S, const MidGrid &g, const MidTiles &tl, double *mf, double *gv, hipStream_t st);
-// Forces at the iterate dv, residual r and out[0] = |r|_M^2, out[1] = E(dv).
+// Force evaluation at the iterate dv: the particle pass (F_hat, energy
+// partials, force slabs; ev0 / ev1, when given, take the kernel's start and
+// end times) and the node pass (residual r, out[0] = |r|_M^2,
+// out[1] = E(dv)).
 template <int DIM, int DEG>
-void launch_mid_force(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
-                      const double *gv, const double *dv, double dt, const double *grav, const double *mf, double *r,
-                      double *epart, double *part, double *out, uint32_t *flags, hipStream_t st);
-// One application of the Newton operator to the search direction pv (s = A pv) and alpha.
+void launch_mid_force_tiles(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat,
+                            const double *gv, const double *dv, double dt, double *epart, uint32_t *flags,
+                            hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <int DIM, int DEG>
-void launch_mid_apply(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
-                      const double *pv, const double *mf, double dt, double *s, double *part, MidCg *cg,
-                      hipStream_t st);
+void launch_mid_force_nodes(const MidGrid &g, const MidTiles &tl, bool elastic, const double *dv, double dt,
+                            const double *grav, const double *mf, double *r, const double *epart, double *part,
+                            double *out, hipStream_t st);
+// One application of the Newton operator to the search direction pv (s = A pv) and alpha:
+// the particle pass (force-differential slabs) and the node pass.
+template <int DIM, int DEG>
+void launch_mid_apply_tiles(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat,
+                            const double *pv, MidCg *cg, hipStream_t st, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
+template <int DIM, int DEG>
+void launch_mid_apply_nodes(const MidGrid &g, const MidTiles &tl, bool elastic, const double *pv, const double *mf,
+                            double dt, double *s, double *part, MidCg *cg, hipStream_t st);
 template <int DIM>
 void launch_mid_cg_init(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, double *delta,
                         double *rc, double *pv, double *part, MidCg *cg, double tol2, uint32_t max_iters,

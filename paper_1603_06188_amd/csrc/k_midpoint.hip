@@ -24,6 +24,8 @@
 // scalars on the device, so no iteration waits for the host.
 //
 // The transfer to particles reads the caller's particle order.
+#include <hip/hip_ext.h>
+
 #include "apic_kernels.h"
 
 namespace apic {
@@ -295,14 +297,35 @@ __device__ __forceinline__ double det_inv_t(const double *A, double *IT) {
     }
 }
 
+// Key (place in the tile) that a lane walks.  Lanes are processed in groups
+// of 16 by LDS; the maps put, in each group, keys whose region addresses
+// (x + RE y + RE^2 z, in doubles) differ modulo 16, so that a group's LDS
+// accesses at one support offset fall in different bank pairs: 3D quadratic,
+// a group is one y layer; 3D cubic, the keys with y ^ z = group; 2D
+// quadratic, the rows y = group, group + 4 (x = key mod 4 / 8 in 3D / 2D).
+template <int DIM, int DEG>
+__device__ __forceinline__ int lane_key(int lane) {
+    if constexpr (DIM == 3) {
+        const int x = lane & 3, z = (lane >> 2) & 3, g = lane >> 4;
+        const int y = DEG == 3 ? g ^ z : g;
+        return x | (y << 2) | (z << 4);
+    } else if constexpr (DEG == 2) {
+        const int x = lane & 7, y = (lane >> 4) | (((lane >> 3) & 1) << 2);
+        return x | (y << 3);
+    } else {
+        return lane;
+    }
+}
+
 // Walks the particles of key tile t level by level, in the lane of each
 // particle's key: fn(sorted position, level, first key-major position of the
-// key).  Positions of one level are consecutive (key order).
-template <typename Fn>
+// key).  Positions of one level are consecutive, in lane order.
+template <int DIM, int DEG, typename Fn>
 __device__ __forceinline__ void for_levels(const uint32_t *start, int64_t t, Fn &&fn) {
     const int lane = threadIdx.x & 63;
-    const uint32_t k0 = start[t * 64 + lane];
-    const uint32_t cnt = start[t * 64 + lane + 1] - k0;
+    const int64_t key = t * 64 + lane_key<DIM, DEG>(lane);
+    const uint32_t k0 = start[key];
+    const uint32_t cnt = start[key + 1] - k0;
     uint32_t maxc = cnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -463,9 +486,9 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_tile_place(int64_t tiles, con
 // every run.
 template <int DIM, int DEG>
 __global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorted S, MidTiles tl) {
-    const int lane = threadIdx.x;
     const int64_t t = tl.klist[blockIdx.x];
-    const uint32_t k0 = S.start[t * 64 + lane], cnt = S.start[t * 64 + lane + 1] - k0;
+    const int64_t key = t * 64 + lane_key<DIM, DEG>(threadIdx.x);
+    const uint32_t k0 = S.start[key], cnt = S.start[key + 1] - k0;
     uint32_t *seg = S.perm + k0;
     for (uint32_t i = 1; i < cnt; ++i) {
         const uint32_t v = seg[i];
@@ -477,7 +500,7 @@ __global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorte
         seg[j] = v;
     }
     const double kD = inv_D_factor<double, DEG>() / S.dx;
-    for_levels(S.start, t, [&](int64_t pos, uint32_t r, uint32_t) {
+    for_levels<DIM, DEG>(S.start, t, [&](int64_t pos, uint32_t r, uint32_t) {
         const int64_t q = seg[r];
         S.cell[pos] = P.cell[q];
         const double m = P.m[q];
@@ -552,7 +575,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(tile_waves<D
     __syncthreads();
     double energy = 0.0;
     const double inv_dx = 1.0 / g.dx, inv_rho0 = 1.0 / mat.rho0;
-    for_levels(S.start, t, [&](int64_t pos, uint32_t, uint32_t) {
+    for_levels<DIM, DEG>(S.start, t, [&](int64_t pos, uint32_t, uint32_t) {
         Axis<double, DEG> ax[DIM];
         sorted_axes<DIM, DEG>(S, pos, ax);
         const int rb[3] = {ax[0].base - org[0], ax[1].base - org[1], DIM == 3 ? ax[DIM - 1].base - org[2] : 0};
@@ -1148,35 +1171,46 @@ void launch_mid_p2g(const MidSorted &S, const MidGrid &g, const MidTiles &tl, do
 }
 
 template <int DIM, int DEG>
-void launch_mid_force(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
-                      const double *gv, const double *dv, double dt, const double *grav, const double *mf, double *r,
-                      double *epart, double *part, double *out, uint32_t *flags, hipStream_t st) {
+void launch_mid_force_tiles(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat,
+                            const double *gv, const double *dv, double dt, double *epart, uint32_t *flags,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (tl.nk == 0) return;
+    hipExtLaunchKernelGGL(k_mid_tile<DIM, DEG, TILE_FORCE>, dim3((unsigned)tl.nk), dim3(64), 0, st, ev0, ev1, 0, S, g,
+                          tl, mat, gv, dv, 0.5 * dt, 0.25 * dt, epart, flags, (const MidCg *)nullptr);
+}
+
+template <int DIM, int DEG>
+void launch_mid_force_nodes(const MidGrid &g, const MidTiles &tl, bool elastic, const double *dv, double dt,
+                            const double *grav, const double *mf, double *r, const double *epart, double *part,
+                            double *out, hipStream_t st) {
     if (tl.nk == 0) return;
     const double3 gr = make_double3(grav[0], grav[1], grav[2]);
     const int64_t nb = mid_node_blocks(tl.nn);
-    if (elastic) {
-        k_mid_tile<DIM, DEG, TILE_FORCE><<<(unsigned)tl.nk, 64, 0, st>>>(S, g, tl, mat, gv, dv, 0.5 * dt, 0.25 * dt,
-                                                                         epart, flags, nullptr);
+    if (elastic)
         k_mid_node_force<DIM, DEG, true><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, dv, dt, gr, r, part);
-    } else {
+    else
         k_mid_node_force<DIM, DEG, false><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, dv, dt, gr, r, part);
-    }
     k_mid_scalars<SC_EVAL><<<1, kMidBlock, 0, st>>>(part, nb, elastic ? epart : nullptr, tl.nk, out, nullptr, 0.0, 0);
 }
 
 template <int DIM, int DEG>
-void launch_mid_apply(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat, bool elastic,
-                      const double *pv, const double *mf, double dt, double *s, double *part, MidCg *cg,
-                      hipStream_t st) {
+void launch_mid_apply_tiles(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat,
+                            const double *pv, MidCg *cg, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (tl.nk == 0) return;
+    hipExtLaunchKernelGGL(k_mid_tile<DIM, DEG, TILE_APPLY>, dim3((unsigned)tl.nk), dim3(64), 0, st, ev0, ev1, 0, S, g,
+                          tl, mat, pv, (const double *)nullptr, 1.0, 0.0, (double *)nullptr, (uint32_t *)nullptr,
+                          (const MidCg *)cg);
+}
+
+template <int DIM, int DEG>
+void launch_mid_apply_nodes(const MidGrid &g, const MidTiles &tl, bool elastic, const double *pv, const double *mf,
+                            double dt, double *s, double *part, MidCg *cg, hipStream_t st) {
     if (tl.nk == 0) return;
     const int64_t nb = mid_node_blocks(tl.nn);
-    if (elastic) {
-        k_mid_tile<DIM, DEG, TILE_APPLY><<<(unsigned)tl.nk, 64, 0, st>>>(S, g, tl, mat, pv, nullptr, 1.0, 0.0, nullptr,
-                                                                         nullptr, cg);
+    if (elastic)
         k_mid_node_apply<DIM, DEG, true><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, pv, dt, s, part, cg);
-    } else {
+    else
         k_mid_node_apply<DIM, DEG, false><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, pv, dt, s, part, cg);
-    }
     k_mid_scalars<SC_ALPHA><<<1, kMidBlock, 0, st>>>(part, nb, nullptr, 0, nullptr, cg, 0.0, 0);
 }
 
@@ -1233,13 +1267,17 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
                                                   hipStream_t);                                                       \
     template void launch_mid_p2g<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &, double *, double *,  \
                                            hipStream_t);                                                              \
-    template void launch_mid_force<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,                    \
-                                             const MidMaterial &, bool, const double *, const double *, double,       \
-                                             const double *, const double *, double *, double *, double *,            \
-                                             double *, uint32_t *, hipStream_t);                                      \
-    template void launch_mid_apply<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,                    \
-                                             const MidMaterial &, bool, const double *, const double *, double,       \
-                                             double *, double *, MidCg *, hipStream_t);                               \
+    template void launch_mid_force_tiles<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,              \
+                                                   const MidMaterial &, const double *, const double *, double,       \
+                                                   double *, uint32_t *, hipStream_t, hipEvent_t, hipEvent_t);        \
+    template void launch_mid_force_nodes<DIM, DEG>(const MidGrid &, const MidTiles &, bool, const double *, double,   \
+                                                   const double *, const double *, double *, const double *,          \
+                                                   double *, double *, hipStream_t);                                  \
+    template void launch_mid_apply_tiles<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,              \
+                                                   const MidMaterial &, const double *, MidCg *, hipStream_t,         \
+                                                   hipEvent_t, hipEvent_t);                                           \
+    template void launch_mid_apply_nodes<DIM, DEG>(const MidGrid &, const MidTiles &, bool, const double *,           \
+                                                   const double *, double, double *, double *, MidCg *, hipStream_t); \
     template void launch_mid_g2p<DIM, DEG>(const Parts<double> &, const MidGrid &, const double *, const double *,    \
                                            hipStream_t);
 #define APIC_MID_INST_D(DIM)                                                                                          \

@@ -7,7 +7,11 @@ bytes), and writes a short text summary with the per-launch traffic of the
 step kernels and a hash of the kernel sources, so that a later bench run can
 tell whether the kernels still match the counters.
 
-    python -m paper_1603_06188_amd.profile_traffic FETCH.csv WRITE.csv OUT.txt "COMMAND"
+    python -m paper_1603_06188_amd.profile_traffic FETCH.csv WRITE.csv OUT.txt "COMMAND" [KERNELS]
+
+KERNELS (optional): comma-separated kernel-name prefixes to summarize instead
+of the explicit step's kernels; their keys keep the template arguments
+(k_mid_tile<3, 2, 2> -> k_mid_tile_3_2_2).
 """
 from __future__ import annotations
 
@@ -43,7 +47,7 @@ def _per_kernel(path: str, counter: str):
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+        name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("(anonymous namespace)::", "")).replace("void ", "")
         val = float(r["Counter_Value"])
         if "copyBuffer" in name:
             copies.append((int(r["Grid_Size"]), val))
@@ -67,8 +71,16 @@ def read_summary(path: str):
     return out
 
 
+def _key(name: str, templated: bool) -> str:
+    name = re.sub(r"^.*::", "", name.split("<")[0]) + ("<" + name.split("<", 1)[1] if "<" in name else "")
+    if not templated:
+        return name.split("<")[0]
+    return re.sub(r"[<>, ]+", "_", name).strip("_")
+
+
 def main(argv):
     fetch_csv, write_csv, out_path, command = argv[1:5]
+    select = tuple(argv[5].split(",")) if len(argv) > 5 else None
     fetch, fetch_copy = _per_kernel(fetch_csv, "FETCH_SIZE")
     write, write_copy = _per_kernel(write_csv, "WRITE_SIZE")
     fs, ws = COPY_KIB / fetch_copy, COPY_KIB / write_copy
@@ -85,9 +97,15 @@ def main(argv):
         "",
     ]
     for k in sorted(set(fetch) | set(write)):
-        if not any(s in k for s in STEP_KERNELS):
-            continue
-        key = k.split("<")[0].replace("apic::", "")
+        short = _key(k, False) + ("<" + k.split("<", 1)[1] if "<" in k else "")
+        if select is not None:
+            if not short.startswith(select):
+                continue
+            key = _key(k, True)
+        else:
+            if not any(s in k for s in STEP_KERNELS):
+                continue
+            key = k.split("<")[0].replace("apic::", "")
         fb = fetch.get(k, 0.0) * 1024 * fs
         wb = write.get(k, 0.0) * 1024 * ws
         lines.append(f"{key}_fetch_bytes: {fb:.0f}")
