@@ -114,7 +114,7 @@ enum {
                                  that wrote the state (fused into it,
                                  evaluated in the state's precision).  The
                                  steps' dt are read back by apic_step_time. */
-    APIC_OPT_ABSOLUTE_POSITIONS = 8 /* binary32, quadratic or cubic weights,
+    APIC_OPT_ABSOLUTE_POSITIONS = 8, /* binary32, quadratic or cubic weights,
                                  not with APIC_OPT_ADAPTIVE_DT nor in
                                  apic_step_batch: the position is held as the
                                  plain binary32 coordinate x_p in the `off`
@@ -129,6 +129,14 @@ enum {
                                  keeps the position to ~2^-24 dx, this one to
                                  ~2^-24 |x| (Sec. 5.3: the particle's angular
                                  momentum uses x_p and B_p).                 */
+    APIC_OPT_BATCH_GRAPH = 16   /* apic_step_batch (set on every scene): the
+                                 K-step launch sequence of a call is captured
+                                 in a HIP graph once per scene set, step
+                                 count and launch plan, and replayed by later
+                                 calls with the same set (the scene table is
+                                 still written per call, ahead of the
+                                 replay).  Results equal the launches'.
+                                 Ignored while kernel timing is enabled.     */
 };
 
 /* Sticky device flag bits (apic_get_flags). */
@@ -320,6 +328,29 @@ apic_status apic_step_noalloc(apic_scene *scene, int32_t n_steps, void *stream);
 apic_status apic_batch_workspace_bytes(int32_t n_scenes, size_t *bytes);
 apic_status apic_step_batch(apic_scene *scenes, int32_t n_scenes, int32_t n_steps, void *batch_ws,
                             size_t batch_ws_bytes, void *stream);
+
+/*
+ * Launch plans of apic_step_batch.  A plan fixes how many particles one
+ * block of a scene's share covers (the share: ceil(n / particles) blocks,
+ * capped per kernel) and how blocks find their work: one block per
+ * (scene, share block) item, or a persistent launch of blocks_per_cu blocks
+ * per compute unit that take items from a device queue until none is left.
+ * Every plan computes the same results (each item's work is the same).
+ *
+ * By default the plan is tuned: per (precision, dim, degree, options,
+ * scene-count and particle-count octaves) the first calls each run one
+ * plan, timed with HIP events around their steps (each plan twice, the
+ * faster time kept), and later calls use the plan with the least time per
+ * particle-step.  apic_batch_set_plan(p) forces plan p for every later call
+ * (-1: back to tuning).  apic_batch_plan_info describes plan p.
+ * apic_batch_tuning reports, for the key a call with these scenes would
+ * use, the chosen plan (-1 while tuning) and the measured nanoseconds per
+ * particle-step of each plan (+inf if not measured) in ns[count].
+ */
+apic_status apic_batch_plan_count(int32_t *count);
+apic_status apic_batch_plan_info(int32_t plan, int32_t *particles_per_block, int32_t *blocks_per_cu);
+apic_status apic_batch_set_plan(int32_t plan);
+apic_status apic_batch_tuning(const apic_scene *scenes, int32_t n_scenes, int32_t *plan, double *ns);
 
 /*
  * Copies one grid field (APIC_GRID_*) into `out`, a device buffer of

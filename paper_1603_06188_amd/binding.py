@@ -35,6 +35,7 @@ APIC_OPT_COMPENSATED = 1
 APIC_OPT_FUSED_TRANSFER = 2
 APIC_OPT_ADAPTIVE_DT = 4
 APIC_OPT_ABSOLUTE_POSITIONS = 8
+APIC_OPT_BATCH_GRAPH = 16
 APIC_FLAG_OUT_OF_DOMAIN, APIC_FLAG_NONFINITE, APIC_FLAG_INVERTED, APIC_FLAG_CFL = 1, 2, 4, 8
 APIC_FLAG_UNSORTED = 16
 APIC_GRID_MASS, APIC_GRID_MOMENTUM, APIC_GRID_VELOCITY = 0, 1, 2
@@ -47,6 +48,7 @@ EXPORTED = [
     "apic_positions_from_absolute", "apic_positions_to_absolute", "apic_timing_enable", "apic_timing_read",
     "apic_last_error", "apic_version", "apic_midpoint_workspace_bytes", "apic_step_midpoint",
     "apic_noalloc_max_bytes", "apic_step_noalloc",
+    "apic_batch_plan_count", "apic_batch_plan_info", "apic_batch_set_plan", "apic_batch_tuning",
 ]
 APIC_PHASES = ["p2g", "grid_update", "bin", "g2p", "sort", "mid_force", "mid_apply"]
 
@@ -108,6 +110,10 @@ _sigs = {
     "apic_step_midpoint": [_S, ctypes.c_int32, ctypes.POINTER(ApicMidpointOpts), ctypes.POINTER(ApicMidpointStats), _V],
     "apic_noalloc_max_bytes": [ctypes.POINTER(ctypes.c_size_t)],
     "apic_step_noalloc": [_S, ctypes.c_int32, _V],
+    "apic_batch_plan_count": [ctypes.POINTER(ctypes.c_int32)],
+    "apic_batch_plan_info": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "apic_batch_set_plan": [ctypes.c_int32],
+    "apic_batch_tuning": [_S, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -213,6 +219,34 @@ def apic_step_batch(scenes, n_steps: int, batch_ws_ptr: int, batch_ws_bytes: int
                                 int(batch_ws_bytes), _stream(stream)))
 
 
+def apic_batch_plan_count() -> int:
+    out = ctypes.c_int32()
+    _check(_lib.apic_batch_plan_count(ctypes.byref(out)))
+    return out.value
+
+
+def apic_batch_plan_info(plan: int):
+    """(particles per share block, blocks per CU; 0: one block per item)."""
+    pb, bc = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.apic_batch_plan_info(int(plan), ctypes.byref(pb), ctypes.byref(bc)))
+    return pb.value, bc.value
+
+
+def apic_batch_set_plan(plan: int) -> None:
+    """Force launch plan `plan` for later apic_step_batch calls (-1: tune)."""
+    _check(_lib.apic_batch_set_plan(int(plan)))
+
+
+def apic_batch_tuning(scenes):
+    """(chosen plan or -1, measured ns per particle-step of each plan)."""
+    arr = (ApicScene * len(scenes))(*scenes)
+    plan = ctypes.c_int32()
+    n = apic_batch_plan_count()
+    ns = (ctypes.c_double * n)()
+    _check(_lib.apic_batch_tuning(arr, len(scenes), ctypes.byref(plan), ns))
+    return plan.value, [float(v) for v in ns]
+
+
 def apic_grid_export(scene: ApicScene, field: int, out_ptr: int, stream=None) -> None:
     _check(_lib.apic_grid_export(ctypes.byref(scene), int(field), ctypes.c_void_p(out_ptr), _stream(stream)))
 
@@ -295,7 +329,7 @@ def unpack_cells(packed: np.ndarray, dim: int) -> np.ndarray:
 
 
 def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=False,
-              absolute=False) -> ApicGridDesc:
+              absolute=False, batch_graph=False) -> ApicGridDesc:
     """The apic_grid_desc of a host scene."""
     precision = precision or scene.precision
     g = ApicGridDesc()
@@ -303,7 +337,8 @@ def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=Fa
     g.degree = scene.degree
     g.precision = APIC_F32 if precision == "fp32" else APIC_F64
     g.options = ((APIC_OPT_COMPENSATED if compensated else 0) | (APIC_OPT_FUSED_TRANSFER if fused else 0)
-                 | (APIC_OPT_ADAPTIVE_DT if adaptive else 0) | (APIC_OPT_ABSOLUTE_POSITIONS if absolute else 0))
+                 | (APIC_OPT_ADAPTIVE_DT if adaptive else 0) | (APIC_OPT_ABSOLUTE_POSITIONS if absolute else 0)
+                 | (APIC_OPT_BATCH_GRAPH if batch_graph else 0))
     for a in range(3):
         g.cells[a] = scene.cells[a] if a < scene.dim else 0
     g.dx = scene.dx
@@ -329,7 +364,7 @@ class DeviceScene:
     off (dim), v (dim), B (dim*dim), F (dim*dim), mass (1)."""
 
     def __init__(self, scene, device="cuda", precision=None, compensated=False, capacity=None, with_id=True,
-                 packed=None, fused=False, adaptive=False, midpoint=False, absolute=False):
+                 packed=None, fused=False, adaptive=False, midpoint=False, absolute=False, batch_graph=False):
         self.host = scene
         self.absolute = bool(absolute)   # positions as plain binary32 coordinates (APIC_OPT_ABSOLUTE_POSITIONS)
         self.dim = scene.dim
@@ -344,7 +379,7 @@ class DeviceScene:
         self.cell = torch.zeros(cap, dtype=torch.int32, device=device)
         self.id = torch.arange(cap, dtype=torch.int32, device=device) if with_id else None
         self.upload(scene, packed)
-        g = grid_desc(scene, self.precision, compensated, fused, adaptive, self.absolute)
+        g = grid_desc(scene, self.precision, compensated, fused, adaptive, self.absolute, batch_graph)
         self.wbytes = apic_workspace_bytes(g, cap)
         if midpoint:
             self.wbytes = max(self.wbytes, apic_midpoint_workspace_bytes(g, cap))
@@ -515,6 +550,10 @@ class SceneBatch:
 
     def step(self, n_steps=1, stream=None):
         apic_step_batch([d.s for d in self.scenes], n_steps, self.bptr, self.bbytes, stream)
+
+    def tuning(self):
+        """(chosen launch plan or -1, ns per particle-step of each plan)."""
+        return apic_batch_tuning([d.s for d in self.scenes])
 
     def step_each(self, n_steps=1, stream=None):
         """The same steps as one apic_step call over the scenes (per-scene

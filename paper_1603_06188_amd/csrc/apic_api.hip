@@ -5,8 +5,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <type_traits>
 #include <vector>
@@ -177,7 +180,7 @@ apic_status check_grid(const apic_grid_desc *g) {
     if (g->precision != APIC_F32 && g->precision != APIC_F64)
         return fail(APIC_E_INVAL, "precision must be APIC_F32 or APIC_F64 (got %d)", g->precision);
     if (g->options & ~(APIC_OPT_COMPENSATED | APIC_OPT_FUSED_TRANSFER | APIC_OPT_ADAPTIVE_DT |
-                       APIC_OPT_ABSOLUTE_POSITIONS))
+                       APIC_OPT_ABSOLUTE_POSITIONS | APIC_OPT_BATCH_GRAPH))
         return fail(APIC_E_INVAL, "unknown option bits 0x%x", g->options);
     if (g->options & APIC_OPT_ABSOLUTE_POSITIONS) {
         if (g->precision != APIC_F32 || g->degree == APIC_MULTILINEAR)
@@ -810,9 +813,13 @@ apic_status dispatch_steps(apic_scene *s, int64_t cap, int32_t n, int32_t k, hip
 // ---------------------------------------------------------------------------
 constexpr size_t kDescBytes = (sizeof(SceneDesc<double>) + 15) / 16 * 16;
 
-size_t batch_bytes(int32_t n) {
+// The scene table (descriptors, then the per-kind item starts), then the
+// queue counter of persistent launches.
+size_t batch_table_bytes(int32_t n) {
     return align_up((size_t)n * kDescBytes) + align_up((size_t)BK_COUNT * (size_t)(n + 1) * 4);
 }
+
+size_t batch_bytes(int32_t n) { return batch_table_bytes(n) + align_up(sizeof(uint32_t)); }
 
 // Host staging of the scene table, per batch workspace; `done` guards reuse.
 struct BatchHost {
@@ -824,22 +831,151 @@ struct BatchHost {
 std::unordered_map<void *, BatchHost> g_batch;
 std::mutex g_batch_mu;
 
-// Blocks of one scene's share of a batched launch, by particle count (about
-// 256 particles per wavefront; the kernels stride over any remainder).
-int share_blocks(int64_t n, int cap) {
-    int64_t b = (n + 1023) / 1024;
+// --- launch plans ---------------------------------------------------------------
+struct BatchPlan {
+    int32_t per_block;      // particles per block of a scene's share
+    int32_t blocks_per_cu;  // 0: one block per item; else a persistent launch of this many blocks per CU
+};
+constexpr BatchPlan kBatchPlans[] = {{1024, 0}, {512, 0}, {2048, 0}, {1024, 4}, {512, 8}};
+constexpr int kBatchPlanCount = (int)(sizeof(kBatchPlans) / sizeof(kBatchPlans[0]));
+constexpr int kTuneRounds = 2;
+int g_forced_plan = -1;
+
+// Blocks of one scene's share of a batched launch, by particle count (the
+// kernels stride over any remainder).
+int share_blocks(int64_t n, int per_block, int cap) {
+    int64_t b = (n + per_block - 1) / per_block;
     if (b < 1) b = 1;
     if (b > cap) b = cap;
     return (int)b;
 }
 
+int octave(int64_t v) {
+    int o = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++o;
+    }
+    return o;
+}
+
+// Tuning state per (precision, dim, degree, options, scene-count octave,
+// particle-count octave).
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+struct TuneState {
+    double best_ns[kBatchPlanCount];
+    int rounds[kBatchPlanCount] = {};
+    int chosen = -1;
+    bool pending = false;  // a timed call whose events are not read yet
+    int plan = 0;
+    double updates = 0.0;  // particle-steps of the timed call
+    hipEvent_t a = nullptr, b = nullptr;
+    TuneState() {
+        for (double &v : best_ns) v = INFINITY;
+    }
+};
+std::map<TuneKey, TuneState> g_tune;
+
+TuneKey tune_key(const apic_scene *s, int32_t n) {
+    int64_t np = 0;
+    for (int32_t i = 0; i < n; ++i) np += s[i].p.n;
+    const apic_grid_desc &g = s[0].grid;
+    return TuneKey{g.precision, g.dim, g.degree, g.options & ~APIC_OPT_BATCH_GRAPH, octave(n), octave(np)};
+}
+
+// Reads a finished measurement into the state.
+apic_status tune_collect(TuneState &ts) {
+    if (!ts.pending) return APIC_OK;
+    apic_status rc = hip_check(hipEventSynchronize(ts.b), "apic_step_batch tuning");
+    float ms = 0.f;
+    if (rc == APIC_OK) rc = hip_check(hipEventElapsedTime(&ms, ts.a, ts.b), "apic_step_batch tuning");
+    ts.pending = false;
+    if (rc != APIC_OK) return rc;
+    const double ns = ts.updates > 0.0 ? (double)ms * 1e6 / ts.updates : INFINITY;
+    ts.best_ns[ts.plan] = std::min(ts.best_ns[ts.plan], ns);
+    ts.rounds[ts.plan] += 1;
+    return APIC_OK;
+}
+
+// Plan of the next call: the tuned one, else the next plan to time.
+int tune_next(TuneState &ts) {
+    if (ts.chosen >= 0) return ts.chosen;
+    for (int r = 0; r < kTuneRounds; ++r)
+        for (int p = 0; p < kBatchPlanCount; ++p)
+            if (ts.rounds[p] <= r) return p;
+    int best = 0;
+    for (int p = 1; p < kBatchPlanCount; ++p)
+        if (ts.best_ns[p] < ts.best_ns[best]) best = p;
+    ts.chosen = best;
+    return best;
+}
+
+int device_cus() {
+    static std::mutex mu;
+    static std::unordered_map<int, int> cus;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cus[dev] = c;
+    return c;
+}
+
+// --- graphs of batched calls ------------------------------------------------------
+struct BatchGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::unordered_map<std::string, BatchGraph> g_graphs;
+constexpr size_t kMaxGraphs = 64;
+
+// Stream the launch sequences are captured on (one per device, default
+// priority; the graphs are launched on the caller's stream).
+hipStream_t capture_stream() {
+    static std::mutex mu;
+    static std::unordered_map<int, hipStream_t> streams;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = s;
+    return s;
+}
+
+void drop_graphs() {
+    for (auto &kv : g_graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    g_graphs.clear();
+}
+
+template <typename V>
+void key_put(std::string &k, const V &v) {
+    k.append((const char *)&v, sizeof v);
+}
+
 template <typename T, int DIM, int DEG, bool COMP>
 apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws, hipStream_t st) {
     const bool adaptive = (scenes[0].grid.options & APIC_OPT_ADAPTIVE_DT) != 0;
+    const TuneKey tkey = tune_key(scenes, n);
+    TuneState &ts = g_tune[tkey];
+    apic_status rc0 = tune_collect(ts);
+    if (rc0 != APIC_OK) return rc0;
+    const bool tuning = g_forced_plan < 0 && ts.chosen < 0 && n_steps > 0;
+    const int plan_id = g_forced_plan >= 0 ? g_forced_plan : tune_next(ts);
+    const BatchPlan plan = kBatchPlans[plan_id];
     std::vector<SceneDesc<T>> descs((size_t)n);
     std::vector<int32_t> starts((size_t)BK_COUNT * (size_t)(n + 1));
     std::vector<SceneState *> states((size_t)n);
     int32_t total[BK_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    double updates = 0.0;
     for (int32_t i = 0; i < n; ++i) {
         int64_t cap = 0;
         (void)check_scene(&scenes[i], &cap);
@@ -887,8 +1023,11 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         }
         states[(size_t)i] = &ss;
         const int64_t np = scenes[i].p.n;
-        const int share[BK_COUNT] = {share_blocks(np, 4096), share_blocks(np, 8192), share_blocks(np, 2048),
-                                     share_blocks(np, 1024), share_blocks(np, 4096), share_blocks(np, 4096), 1};
+        updates += (double)np * (double)n_steps;
+        const int pb = plan.per_block;
+        const int share[BK_COUNT] = {share_blocks(np, pb, 4096), share_blocks(np, pb, 8192), share_blocks(np, pb, 2048),
+                                     share_blocks(np, pb, 1024), share_blocks(np, pb, 4096), share_blocks(np, 1024, 4096),
+                                     1};
         for (int k = 0; k < BK_COUNT; ++k) {
             starts[(size_t)k * (n + 1) + i] = total[k];
             total[k] += share[k];
@@ -921,7 +1060,8 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
     const size_t o_start = align_up((size_t)n * kDescBytes);
     memcpy(host + o_start, starts.data(), starts.size() * 4);
     // descriptors are packed at sizeof(SceneDesc<T>) (<= kDescBytes per entry)
-    apic_status rc = hip_check(hipMemcpyAsync(bws, host, need, hipMemcpyHostToDevice, st), "apic_step_batch table");
+    apic_status rc = hip_check(hipMemcpyAsync(bws, host, batch_table_bytes(n), hipMemcpyHostToDevice, st),
+                               "apic_step_batch table");
     if (rc != APIC_OK) return rc;
     rc = hip_check(hipEventRecord(bh.done, st), "apic_step_batch event");
     if (rc != APIC_OK) return rc;
@@ -929,23 +1069,105 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
 
     const SceneDesc<T> *dd = (const SceneDesc<T> *)bws;
     const int32_t *ds = (const int32_t *)((const char *)bws + o_start);
+    uint32_t *ctr = (uint32_t *)((char *)bws + batch_table_bytes(n));
     auto start_of = [&](int k) { return ds + (size_t)k * (n + 1); };
-    for (int32_t k = 0; k < n_steps; ++k) {
-        if (adaptive) launch_adapt_dt_batch<T, DIM>(dd, start_of(BK_COPY), n, total[BK_COPY], k == 0, st);
-        timed(APIC_PHASE_P2G, st,
-              [&] { launch_p2g_batch<T, DIM, DEG, COMP>(dd, start_of(BK_P2G), n, k, total[BK_P2G], st); });
-        timed(APIC_PHASE_GRID_UPDATE, st, [&] {
-            launch_grid_update_batch<T, DIM, DEG, COMP>(dd, start_of(BK_GRID), n, k, total[BK_GRID], st);
-        });
-        timed(APIC_PHASE_BIN, st, [&] {
-            launch_bin_keys_moved_batch<T, DIM, DEG>(dd, start_of(BK_KEYS), n, k, total[BK_KEYS], st);
-            launch_bin_records_batch<T, DIM>(dd, start_of(BK_RECORDS), n, k, total[BK_RECORDS], st);
-            launch_bin_finalize_batch<T>(dd, start_of(BK_FINAL), n, k, total[BK_FINAL], st);
-        });
-        timed(APIC_PHASE_G2P, st,
-              [&] { launch_g2p_batch<T, DIM, DEG>(dd, start_of(BK_G2P), n, k, total[BK_G2P], adaptive, st); });
+    const int qblocks = plan.blocks_per_cu * device_cus();
+    // the launches of the call's steps on stream s
+    auto emit = [&](hipStream_t s) {
+        uint32_t base = 0;
+        // how the blocks of a launch of kind `kind` take its items
+        auto queue_of = [&](int kind, int &blocks) {
+            BatchQueue q{nullptr, 0u, (uint32_t)total[kind]};
+            blocks = total[kind];
+            if (plan.blocks_per_cu > 0) {
+                blocks = std::min(total[kind], qblocks);
+                q.ctr = ctr;
+                q.base = base;
+                base += (uint32_t)total[kind] + (uint32_t)blocks;
+            }
+            return q;
+        };
+        if (plan.blocks_per_cu > 0 && n_steps > 0) launch_fill<uint32_t>(ctr, 1, 0u, s);
+        for (int32_t k = 0; k < n_steps; ++k) {
+            int nb = 0;
+            if (adaptive) launch_adapt_dt_batch<T, DIM>(dd, start_of(BK_COPY), n, total[BK_COPY], k == 0, s);
+            BatchQueue q = queue_of(BK_P2G, nb);
+            timed(APIC_PHASE_P2G, s, [&] { launch_p2g_batch<T, DIM, DEG, COMP>(dd, start_of(BK_P2G), n, k, q, nb, s); });
+            q = queue_of(BK_GRID, nb);
+            timed(APIC_PHASE_GRID_UPDATE, s,
+                  [&] { launch_grid_update_batch<T, DIM, DEG, COMP>(dd, start_of(BK_GRID), n, k, q, nb, s); });
+            timed(APIC_PHASE_BIN, s, [&] {
+                int nk = 0, nr = 0;
+                const BatchQueue qk = queue_of(BK_KEYS, nk);
+                launch_bin_keys_moved_batch<T, DIM, DEG>(dd, start_of(BK_KEYS), n, k, qk, nk, s);
+                const BatchQueue qr = queue_of(BK_RECORDS, nr);
+                launch_bin_records_batch<T, DIM>(dd, start_of(BK_RECORDS), n, k, qr, nr, s);
+                launch_bin_finalize_batch<T>(dd, start_of(BK_FINAL), n, k, total[BK_FINAL], s);
+            });
+            q = queue_of(BK_G2P, nb);
+            timed(APIC_PHASE_G2P, s,
+                  [&] { launch_g2p_batch<T, DIM, DEG>(dd, start_of(BK_G2P), n, k, q, nb, adaptive, s); });
+        }
+        launch_copy_back_batch<T, DIM>(dd, start_of(BK_COPY), n, n_steps, total[BK_COPY], s);
+    };
+
+    if (tuning) {
+        if (!ts.a) rc = hip_check(hipEventCreate(&ts.a), "apic_step_batch tuning");
+        if (rc == APIC_OK && !ts.b) rc = hip_check(hipEventCreate(&ts.b), "apic_step_batch tuning");
+        if (rc == APIC_OK) rc = hip_check(hipEventRecord(ts.a, st), "apic_step_batch tuning");
+        if (rc != APIC_OK) return rc;
     }
-    launch_copy_back_batch<T, DIM>(dd, start_of(BK_COPY), n, n_steps, total[BK_COPY], st);
+    bool timing = false;
+    {
+        std::lock_guard<std::mutex> lock(g_timing.mu);
+        timing = g_timing.enabled;
+    }
+    if ((scenes[0].grid.options & APIC_OPT_BATCH_GRAPH) && !timing && n_steps > 0) {
+        // the graph of this scene set, step count and plan: every kernel
+        // argument is fixed by them (the table behind `bws` is written above)
+        std::string key;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        key_put(key, dev);
+        key_put(key, bws);
+        key_put(key, n);
+        key_put(key, n_steps);
+        key_put(key, plan_id);
+        key_put(key, (int)sizeof(T));
+        key_put(key, DIM * 100 + DEG * 10 + (COMP ? 1 : 0));
+        key_put(key, (int)adaptive);
+        key_put(key, qblocks);
+        key.append((const char *)starts.data(), starts.size() * 4);
+        auto it = g_graphs.find(key);
+        if (it == g_graphs.end()) {
+            if (g_graphs.size() >= kMaxGraphs) drop_graphs();
+            hipStream_t cs = capture_stream();
+            if (!cs) return fail(APIC_E_HIP, "apic_step_batch: no capture stream");
+            BatchGraph bg;
+            rc = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "apic_step_batch capture");
+            if (rc != APIC_OK) return rc;
+            emit(cs);
+            rc = hip_check(hipStreamEndCapture(cs, &bg.graph), "apic_step_batch capture");
+            if (rc == APIC_OK) rc = hip_check(hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0),
+                                              "apic_step_batch graph");
+            if (rc != APIC_OK) {
+                if (bg.graph) (void)hipGraphDestroy(bg.graph);
+                return rc;
+            }
+            it = g_graphs.emplace(key, bg).first;
+        }
+        rc = hip_check(hipGraphLaunch(it->second.exec, st), "apic_step_batch graph launch");
+        if (rc != APIC_OK) return rc;
+    } else {
+        emit(st);
+    }
+    if (tuning) {
+        rc = hip_check(hipEventRecord(ts.b, st), "apic_step_batch tuning");
+        if (rc != APIC_OK) return rc;
+        ts.pending = true;
+        ts.plan = plan_id;
+        ts.updates = updates;
+    }
     for (int32_t i = 0; i < n; ++i) {
         SceneState &ss = *states[(size_t)i];
         const int cur0 = ss.cur;
@@ -1111,6 +1333,44 @@ apic_status apic_step_noalloc(apic_scene *scene, int32_t n_steps, void *stream) 
         g_states.erase(ptr);
     }
     return rc;
+}
+
+apic_status apic_batch_plan_count(int32_t *count) {
+    if (!count) return fail(APIC_E_INVAL, "count is NULL");
+    *count = kBatchPlanCount;
+    return APIC_OK;
+}
+
+apic_status apic_batch_plan_info(int32_t plan, int32_t *particles_per_block, int32_t *blocks_per_cu) {
+    if (plan < 0 || plan >= kBatchPlanCount) return fail(APIC_E_INVAL, "plan %d outside [0, %d)", plan, kBatchPlanCount);
+    if (!particles_per_block || !blocks_per_cu) return fail(APIC_E_INVAL, "output pointer is NULL");
+    *particles_per_block = kBatchPlans[plan].per_block;
+    *blocks_per_cu = kBatchPlans[plan].blocks_per_cu;
+    return APIC_OK;
+}
+
+apic_status apic_batch_set_plan(int32_t plan) {
+    if (plan < -1 || plan >= kBatchPlanCount)
+        return fail(APIC_E_INVAL, "plan %d outside [-1, %d)", plan, kBatchPlanCount);
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    g_forced_plan = plan;
+    return APIC_OK;
+}
+
+apic_status apic_batch_tuning(const apic_scene *scenes, int32_t n_scenes, int32_t *plan, double *ns) {
+    if (!scenes || n_scenes <= 0) return fail(APIC_E_INVAL, "scenes is NULL or n_scenes <= 0");
+    if (!plan || !ns) return fail(APIC_E_INVAL, "output pointer is NULL");
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    auto it = g_tune.find(tune_key(scenes, n_scenes));
+    *plan = -1;
+    for (int p = 0; p < kBatchPlanCount; ++p) ns[p] = INFINITY;
+    if (it == g_tune.end()) return APIC_OK;
+    apic_status rc = tune_collect(it->second);
+    if (rc != APIC_OK) return rc;
+    if (it->second.chosen < 0) (void)tune_next(it->second);  // chooses once every plan is timed
+    *plan = it->second.chosen;
+    for (int p = 0; p < kBatchPlanCount; ++p) ns[p] = it->second.best_ns[p];
+    return APIC_OK;
 }
 
 apic_status apic_batch_workspace_bytes(int32_t n_scenes, size_t *bytes) {

@@ -194,10 +194,33 @@ struct BatchStep {
     uint32_t blk, nblk;
 };
 
+// Runs fn(item) for the block's work items: item blockIdx.x, or (QUEUE)
+// items taken from the device counter until none is left.  The taken item
+// passes through LDS behind block barriers, so every thread of the block
+// takes part.  (Two kernels rather than one with a run-time test: the loop
+// keeps more registers live than the one-item body needs.)
+template <bool QUEUE, typename Fn>
+__device__ __forceinline__ void batch_items(const BatchQueue &q, Fn &&fn) {
+    if constexpr (!QUEUE) {
+        fn((uint32_t)blockIdx.x);
+    } else {
+        __shared__ uint32_t item;
+        for (;;) {
+            __syncthreads();
+            if (threadIdx.x == 0) item = atomicAdd(q.ctr, 1u) - q.base;
+            __syncthreads();
+            const uint32_t it = item;
+            if (it >= q.items) break;
+            fn(it);
+        }
+    }
+}
+
 template <typename T>
-__device__ __forceinline__ BatchStep<T> batch_step(const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
+__device__ __forceinline__ BatchStep<T> batch_step(const SceneDesc<T> *descs, const int32_t *start, int n, int k,
+                                                   uint32_t item) {
     BatchStep<T> b;
-    const int s = scene_of_block(start, n, blockIdx.x);
+    const int s = scene_of_block(start, n, item);
     b.d = descs + s;
     const uint32_t gen0[2] = {b.d->lists[0].gen, b.d->lists[1].gen};
     b.sp = step_parity(b.d->cur0, b.d->where0, gen0, k);
@@ -205,7 +228,7 @@ __device__ __forceinline__ BatchStep<T> batch_step(const SceneDesc<T> *descs, co
     b.cur.gen = b.sp.gen_cur;
     b.nxt = b.d->lists[b.sp.nxt];
     b.nxt.gen = b.sp.gen_nxt;
-    b.blk = blockIdx.x - (uint32_t)start[s];
+    b.blk = item - (uint32_t)start[s];
     b.nblk = (uint32_t)(start[s + 1] - start[s]);
     return b;
 }

@@ -200,10 +200,23 @@ struct SceneDesc {
     double dt_cap, nu_dx;  // adaptive steps: dt = min(dt_cap, nu_dx / bound)
 };
 
-// Kernels of a batched step; per kind, scene s owns blocks
-// [start[s], start[s + 1]) of the launch.
+// Kernels of a batched step; per kind, scene s owns work items
+// [start[s], start[s + 1]) of the launch (item j: the j-th block of the
+// scene's share).
 enum BatchKernel : int { BK_P2G = 0, BK_GRID = 1, BK_KEYS = 2, BK_RECORDS = 3, BK_G2P = 4, BK_COPY = 5,
                          BK_FINAL = 6, BK_COUNT = 7 };
+
+// How the blocks of a batched launch find their work items.  ctr null: one
+// block per item, item = block index.  Otherwise a persistent launch: every
+// block takes items from the device counter *ctr (a queue over (scene, share
+// block) items) until they run out; this launch's items are the counter
+// values base .. base + items - 1, and each block takes one value past them
+// on its way out, so the next launch on the counter starts at base + items +
+// (blocks of this launch).
+struct BatchQueue {
+    uint32_t *ctr;
+    uint32_t base, items;
+};
 
 // Layout parities and generations at step k of a batched call: step k
 // reads parity (cur0 + k) & 1 and builds the other one; the j-th build of a

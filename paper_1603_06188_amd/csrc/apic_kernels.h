@@ -83,22 +83,24 @@ void launch_p2g_movers(const Parts<T> &P, const BinLists &cur, const BinLists &n
                        hipStream_t st);
 
 // --- batched steps: one launch per phase for every scene of a batch -------------
-// `start` holds, per scene, its first block of the launch (n + 1 entries);
-// `k` is the step index within the batched call.
+// `start` holds, per scene, its first work item (n + 1 entries); `k` is the
+// step index within the batched call; `q` says how the `blocks` blocks of
+// the launch take the items (one each, or from a device queue).
 template <typename T, int DIM, int DEG, bool COMP>
-void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st);
-template <typename T, int DIM, int DEG, bool COMP>
-void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
-                              hipStream_t st);
-template <typename T, int DIM, int DEG>
-void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
-                                 hipStream_t st);
-template <typename T, int DIM>
-void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
-                              hipStream_t st);
-template <typename T, int DIM, int DEG>
-void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, bool adapt,
+void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q, int blocks,
                       hipStream_t st);
+template <typename T, int DIM, int DEG, bool COMP>
+void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q,
+                              int blocks, hipStream_t st);
+template <typename T, int DIM, int DEG>
+void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q,
+                                 int blocks, hipStream_t st);
+template <typename T, int DIM>
+void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q,
+                              int blocks, hipStream_t st);
+template <typename T, int DIM, int DEG>
+void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q, int blocks,
+                      bool adapt, hipStream_t st);
 // Adaptive batched steps: before each step, every scene's dt from its bound
 // slots (first: the slots cleared and raised by a pass over the particles
 // each scene starts the call with; blocks as the copy-back table).

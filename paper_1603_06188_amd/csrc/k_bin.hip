@@ -125,18 +125,25 @@ __global__ __launch_bounds__(256) void k_bin_records(BinLists nxt, TileTables ta
     records_body<DIM>(nxt, tab, sc, d, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool QUEUE>
 __global__ __launch_bounds__(256) void k_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
-                                                           int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    const SceneDesc<T> &d = *b.d;
-    records_body<DIM>(b.nxt, d.tab[b.sp.nxt], d.sc, d.g.d, b.blk, b.nblk);
+                                                           int k, BatchQueue q) {
+    batch_items<QUEUE>(q, [&](uint32_t it) {
+        const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
+        const SceneDesc<T> &d = *b.d;
+        records_body<DIM>(b.nxt, d.tab[b.sp.nxt], d.sc, d.g.d, b.blk, b.nblk);
+    });
 }
 
 template <typename T, int DIM>
-void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
-                              hipStream_t st) {
-    hipLaunchKernelGGL((k_bin_records_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q,
+                              int blocks, hipStream_t st) {
+    if (q.ctr)
+        hipLaunchKernelGGL((k_bin_records_batch<T, DIM, true>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
+                           n, k, q);
+    else
+        hipLaunchKernelGGL((k_bin_records_batch<T, DIM, false>), dim3((unsigned)blocks), dim3(256), 0, st, descs,
+                           start, n, k, q);
 }
 
 // copies the particles of every scene that ended in the workspace shadow
@@ -144,7 +151,7 @@ void launch_bin_records_batch(const SceneDesc<T> *descs, const int32_t *start, i
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
                                                          int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k, blockIdx.x);
     if (b.sp.src != 1) return;
     const Parts<T> &src = b.d->bufs[1], &dst = b.d->bufs[0];
     for (int64_t j = (int64_t)b.blk * blockDim.x + threadIdx.x; j < src.n; j += (int64_t)b.nblk * blockDim.x) {
@@ -193,7 +200,7 @@ void launch_bin_finalize(const BinLists &nxt, hipStream_t st) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
                                                             int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
+    const BatchStep<T> b = batch_step<T>(descs, start, n, k, blockIdx.x);
     finalize_body(b.nxt);
 }
 
@@ -255,7 +262,8 @@ template void launch_bin_records<3>(const GridDims &, const BinLists &, const Ti
                                     int64_t, hipStream_t);
 
 #define APIC_BIN_INST(T, DIM)                                                                                    \
-    template void launch_bin_records_batch<T, DIM>(const SceneDesc<T> *, const int32_t *, int, int, int,          \
+    template void launch_bin_records_batch<T, DIM>(const SceneDesc<T> *, const int32_t *, int, int,                   \
+                                                   const BatchQueue &, int,                                           \
                                                    hipStream_t);                                                  \
     template void launch_copy_back_batch<T, DIM>(const SceneDesc<T> *, const int32_t *, int, int, int,            \
                                                  hipStream_t);                                                    \

@@ -183,19 +183,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_wa
     keys_body<T, DIM, DEG, ABS>(P, cur, ctab, g, prm, nxt, sc, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int DIM, int DEG>
+template <typename T, int DIM, int DEG, bool QUEUE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_waves<T, DIM, DEG>()))) void k_bin_keys_moved_batch(
-    const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    const SceneDesc<T> &d = *b.d;
-    keys_body<T, DIM, DEG, false>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk, b.nblk);
+    const SceneDesc<T> *descs, const int32_t *start, int n, int k, BatchQueue q) {
+    batch_items<QUEUE>(q, [&](uint32_t it) {
+        const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
+        const SceneDesc<T> &d = *b.d;
+        keys_body<T, DIM, DEG, false>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk,
+                                      b.nblk);
+    });
 }
 
 template <typename T, int DIM, int DEG>
-void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL((k_bin_keys_moved_batch<T, DIM, DEG>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
-                       n, k);
+void launch_bin_keys_moved_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q,
+                                 int blocks, hipStream_t st) {
+    if (q.ctr)
+        hipLaunchKernelGGL((k_bin_keys_moved_batch<T, DIM, DEG, true>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           descs, start, n, k, q);
+    else
+        hipLaunchKernelGGL((k_bin_keys_moved_batch<T, DIM, DEG, false>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           descs, start, n, k, q);
 }
 
 template <typename T, int DIM, int DEG, bool ABS>
@@ -327,26 +334,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADAPT ? 1 :
     g2p_body<T, DIM, DEG, ADAPT, ABS>(src, dst, cur, ctab, nxt, ntab, sc, g, prm, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int DIM, int DEG, bool ADAPT>
+template <typename T, int DIM, int DEG, bool ADAPT, bool QUEUE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p_batch(
-    const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    const SceneDesc<T> &d = *b.d;
-    Parts<T> src = d.bufs[b.sp.src], dst = d.bufs[b.sp.src ^ 1];
-    if (!src.id || !dst.id) src.id = dst.id = nullptr;
-    g2p_body<T, DIM, DEG, ADAPT>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm, b.blk,
-                                 b.nblk);
+    const SceneDesc<T> *descs, const int32_t *start, int n, int k, BatchQueue q) {
+    batch_items<QUEUE>(q, [&](uint32_t it) {
+        const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
+        const SceneDesc<T> &d = *b.d;
+        Parts<T> src = d.bufs[b.sp.src], dst = d.bufs[b.sp.src ^ 1];
+        if (!src.id || !dst.id) src.id = dst.id = nullptr;
+        g2p_body<T, DIM, DEG, ADAPT>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm,
+                                     b.blk, b.nblk);
+    });
 }
 
 template <typename T, int DIM, int DEG>
-void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, bool adapt,
-                      hipStream_t st) {
-    if (adapt)
-        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, true>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
-                           n, k);
+void launch_g2p_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q, int blocks,
+                      bool adapt, hipStream_t st) {
+    const dim3 grid((unsigned)blocks), block(256);
+    if (adapt && q.ctr)
+        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, true, true>), grid, block, 0, st, descs, start, n, k, q);
+    else if (adapt)
+        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, true, false>), grid, block, 0, st, descs, start, n, k, q);
+    else if (q.ctr)
+        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, false, true>), grid, block, 0, st, descs, start, n, k, q);
     else
-        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, false>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start,
-                           n, k);
+        hipLaunchKernelGGL((k_g2p_batch<T, DIM, DEG, false, false>), grid, block, 0, st, descs, start, n, k, q);
 }
 
 // --- adaptive batched steps (Sec. 4.3) ---------------------------------------------
@@ -439,9 +451,11 @@ void launch_g2p(const Parts<T> &src, const Parts<T> &dst, const BinLists &cur, c
 }
 
 #define APIC_G2P_INST(T, DIM, DEG)                                                                               \
-    template void launch_bin_keys_moved_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int,  \
+    template void launch_bin_keys_moved_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int,           \
+                                                           const BatchQueue &, int,                                   \
                                                            hipStream_t);                                          \
-    template void launch_g2p_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int, int, bool,       \
+    template void launch_g2p_batch<T, DIM, DEG>(const SceneDesc<T> *, const int32_t *, int, int,                      \
+                                                const BatchQueue &, int, bool,                                        \
                                                 hipStream_t);                                                     \
     template void launch_bin_keys_moved<T, DIM, DEG, false>(const Parts<T> &, const BinLists &, const TileTables &, \
                                                             const GridState<T> &, const StepParams<T> &,         \

@@ -221,19 +221,25 @@ __global__ __launch_bounds__(256) void k_grid_update(BinLists cur, Slabs<T> slab
     grid_update_body<T, DIM, DEG, COMP>(cur, slabs, g, prm, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int DIM, int DEG, bool COMP>
+template <typename T, int DIM, int DEG, bool COMP, bool QUEUE>
 __global__ __launch_bounds__(256) void k_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
-                                                           int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    const SceneDesc<T> &d = *b.d;
-    grid_update_body<T, DIM, DEG, COMP>(b.cur, d.slabs, d.g, d.prm, b.blk, b.nblk);
+                                                           int k, BatchQueue q) {
+    batch_items<QUEUE>(q, [&](uint32_t it) {
+        const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
+        const SceneDesc<T> &d = *b.d;
+        grid_update_body<T, DIM, DEG, COMP>(b.cur, d.slabs, d.g, d.prm, b.blk, b.nblk);
+    });
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
-                              hipStream_t st) {
-    hipLaunchKernelGGL((k_grid_update_batch<T, DIM, DEG, COMP>), dim3((unsigned)blocks), dim3(256), 0, st, descs,
-                       start, n, k);
+void launch_grid_update_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q,
+                              int blocks, hipStream_t st) {
+    if (q.ctr)
+        hipLaunchKernelGGL((k_grid_update_batch<T, DIM, DEG, COMP, true>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           descs, start, n, k, q);
+    else
+        hipLaunchKernelGGL((k_grid_update_batch<T, DIM, DEG, COMP, false>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           descs, start, n, k, q);
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
@@ -355,7 +361,8 @@ void launch_diag_grid(const BinLists &gm, const Slabs<T> &slabs, const GridState
 }
 
 #define APIC_GRID_INST(T, DIM, DEG, COMP)                                                                         \
-    template void launch_grid_update_batch<T, DIM, DEG, COMP>(const SceneDesc<T> *, const int32_t *, int, int, int, \
+    template void launch_grid_update_batch<T, DIM, DEG, COMP>(const SceneDesc<T> *, const int32_t *, int, int,        \
+                                                              const BatchQueue &, int,                                \
                                                               hipStream_t);                                       \
     template void launch_grid_update<T, DIM, DEG, COMP>(const BinLists &, const Slabs<T> &, const GridState<T> &, \
                                                         const StepParams<T> &, int64_t, hipStream_t);            \

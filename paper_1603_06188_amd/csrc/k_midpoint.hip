@@ -537,9 +537,9 @@ constexpr int tile_waves() {
 }
 
 template <int DIM, int DEG, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(tile_waves<DIM, DEG, MODE>()))) void k_mid_tile(MidSorted S, MidGrid g, MidTiles tl, MidMaterial mat, const double *va,
-                                                 const double *vb, double ca, double cb, double *epart,
-                                                 uint32_t *flags, const MidCg *cg) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(tile_waves<DIM, DEG, MODE>()))) void k_mid_tile(
+    MidSorted S, MidGrid g, MidTiles tl, MidMaterial mat, const double *va, const double *vb, double ca, double cb,
+    double *epart, uint32_t *flags, const MidCg *cg) {
     constexpr int R = region_nodes<DIM, DEG>(), RE = region_edge<DIM, DEG>(), E = tile_edge<DIM>();
     constexpr int CIN = MODE == TILE_P2G ? 0 : DIM;
     constexpr int COUT = MODE == TILE_P2G ? 1 + DIM : DIM;

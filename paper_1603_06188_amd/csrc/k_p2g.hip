@@ -121,16 +121,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(p2g_min_wav
     p2g_body<T, DIM, DEG, COMP, ABS>(P, cur, nxt, tab, slabs, g, prm, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int DIM, int DEG, bool COMP>
-__global__ __launch_bounds__(256) void k_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k) {
-    const BatchStep<T> b = batch_step<T>(descs, start, n, k);
-    const SceneDesc<T> &d = *b.d;
-    p2g_body<T, DIM, DEG, COMP>(d.bufs[b.sp.src], b.cur, b.nxt, d.tab[b.sp.cur], d.slabs, d.g, d.prm, b.blk, b.nblk);
+template <typename T, int DIM, int DEG, bool COMP, bool QUEUE>
+__global__ __launch_bounds__(256) void k_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k,
+                                                   BatchQueue q) {
+    batch_items<QUEUE>(q, [&](uint32_t it) {
+        const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
+        const SceneDesc<T> &d = *b.d;
+        p2g_body<T, DIM, DEG, COMP>(d.bufs[b.sp.src], b.cur, b.nxt, d.tab[b.sp.cur], d.slabs, d.g, d.prm, b.blk,
+                                    b.nblk);
+    });
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
-void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_p2g_batch<T, DIM, DEG, COMP>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
+void launch_p2g_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, const BatchQueue &q, int blocks,
+                      hipStream_t st) {
+    if (q.ctr)
+        hipLaunchKernelGGL((k_p2g_batch<T, DIM, DEG, COMP, true>), dim3((unsigned)blocks), dim3(256), 0, st, descs,
+                           start, n, k, q);
+    else
+        hipLaunchKernelGGL((k_p2g_batch<T, DIM, DEG, COMP, false>), dim3((unsigned)blocks), dim3(256), 0, st, descs,
+                           start, n, k, q);
 }
 
 template <typename T, int DIM, int DEG, bool COMP, bool ABS>
@@ -145,9 +155,11 @@ void launch_p2g(const Parts<T> &P, const BinLists &cur, const BinLists &nxt, con
 }
 
 #define APIC_P2G_INST(T, DIM, DEG)                                                                                \
-    template void launch_p2g_batch<T, DIM, DEG, false>(const SceneDesc<T> *, const int32_t *, int, int, int,        \
+    template void launch_p2g_batch<T, DIM, DEG, false>(const SceneDesc<T> *, const int32_t *, int, int,               \
+                                                       const BatchQueue &, int,                                       \
                                                        hipStream_t);                                              \
-    template void launch_p2g_batch<T, DIM, DEG, true>(const SceneDesc<T> *, const int32_t *, int, int, int,         \
+    template void launch_p2g_batch<T, DIM, DEG, true>(const SceneDesc<T> *, const int32_t *, int, int,                \
+                                                      const BatchQueue &, int,                                        \
                                                       hipStream_t);                                               \
     template void launch_p2g<T, DIM, DEG, false, false>(const Parts<T> &, const BinLists &, const BinLists &,    \
                                                         const TileTables &, const Slabs<T> &, const GridState<T> &, \

@@ -76,7 +76,7 @@ def test_host_validation_without_gpu():
     nbytes = b.apic_workspace_bytes(g, 2_097_152)
     # grid planes + shadow state dominate: at least 2M * 104 B
     assert nbytes > 2_097_152 * 104
-    for field, value in (("dim", 4), ("degree", 0), ("degree", 4), ("precision", 7), ("options", 16)):
+    for field, value in (("dim", 4), ("degree", 0), ("degree", 4), ("precision", 7), ("options", 32)):
         old = getattr(g, field)
         setattr(g, field, value)
         with pytest.raises(b.ApicError) as e:
@@ -94,6 +94,9 @@ def test_host_validation_without_gpu():
             b.apic_workspace_bytes(g, 10)
         assert e.value.code == b.APIC_E_UNSUPPORTED
         setattr(g, field, old)
+    # the batch graph option is accepted on its own and with the others
+    g.options = b.APIC_OPT_BATCH_GRAPH | b.APIC_OPT_COMPENSATED
+    assert b.apic_workspace_bytes(g, 10) > 0
     g.options = 0
     g.cells[1] = 2000
     with pytest.raises(b.ApicError):
@@ -207,3 +210,25 @@ def test_midpoint_entry_point_validation_without_gpu():
     with pytest.raises(b.ApicError) as e:
         b.apic_step_midpoint(sc, -1, stream=null_stream)
     assert e.value.code == -1
+
+
+def test_batch_plans_without_gpu():
+    """The launch plans of apic_step_batch: a count, a description of each,
+    and forcing one (or -1 for tuning) is validated on the host."""
+    from paper_1603_06188_amd import binding as b
+    n = b.apic_batch_plan_count()
+    assert n >= 3
+    seen = set()
+    for p in range(n):
+        per_block, per_cu = b.apic_batch_plan_info(p)
+        assert per_block > 0 and per_cu >= 0
+        seen.add((per_block, per_cu))
+    assert len(seen) == n
+    assert any(c == 0 for _, c in seen) and any(c > 0 for _, c in seen)
+    for bad in (n, -2):
+        with pytest.raises(b.ApicError):
+            b.apic_batch_plan_info(bad)
+        with pytest.raises(b.ApicError):
+            b.apic_batch_set_plan(bad)
+    b.apic_batch_set_plan(n - 1)
+    b.apic_batch_set_plan(-1)

@@ -139,3 +139,71 @@ def test_batch_fp32_one_step_matches_oracle():
         assert float(np.abs(got["x"] - r["x_new"]).max() / h.dx) <= 1e-5, k
         for key in ("v", "B", "F"):
             assert rel(got[key], r[key + "_new"]) <= 1e-5, (k, key, rel(got[key], r[key + "_new"]))
+
+
+def test_every_launch_plan_gives_the_same_bits():
+    """Each launch plan of apic_step_batch (blocks per scene share, one block
+    per work item or a persistent launch taking items from a device queue)
+    runs the same work items, so four batched steps under every plan equal
+    the scenes stepped alone bit for bit."""
+    b = _b()
+    hosts = _bodies("fp32", sizes=(1200, 5000, 20000, 3000, 800), seed=600)
+    alone = [b.DeviceScene(h, compensated=True) for h in hosts]
+    for d in alone:
+        d.step(4)
+    want = [d.state() for d in alone]
+    try:
+        for p in range(b.apic_batch_plan_count()):
+            b.apic_batch_set_plan(p)
+            batch = b.SceneBatch([b.DeviceScene(h, compensated=True) for h in hosts])
+            batch.step(4)
+            for k, d in enumerate(batch.scenes):
+                _close(d.state(), want[k], 0.0, f"plan {p} scene {k}")
+                assert d.flags() == 0
+    finally:
+        b.apic_batch_set_plan(-1)
+
+
+@pytest.mark.parametrize("plan", [0, 3])
+def test_graph_replays_equal_direct_launches(plan):
+    """APIC_OPT_BATCH_GRAPH: the call's step sequence is captured once and
+    replayed by the later calls.  Three calls, with per-scene steps (eager
+    launches) between them, give on every replay the bits of the same calls
+    launched directly."""
+    b = _b()
+    hosts = _bodies("fp32", sizes=(900, 4000, 1600, 12000), seed=700)
+    direct = b.SceneBatch([b.DeviceScene(h, compensated=True) for h in hosts])
+    graph = b.SceneBatch([b.DeviceScene(h, compensated=True, batch_graph=True) for h in hosts])
+    try:
+        b.apic_batch_set_plan(plan)
+        for call in range(3):
+            direct.step(2)
+            graph.step(2)
+            for k, (dd, dg) in enumerate(zip(direct.scenes, graph.scenes)):
+                _close(dg.state(), dd.state(), 0.0, f"call {call} scene {k}")
+                assert dg.flags() == 0
+            direct.step_each(1)
+            graph.step_each(1)
+    finally:
+        b.apic_batch_set_plan(-1)
+    for k, (dd, dg) in enumerate(zip(direct.scenes, graph.scenes)):
+        _close(dg.state(), dd.state(), 0.0, f"end scene {k}")
+
+
+def test_tuner_times_every_plan_then_keeps_the_fastest():
+    """With no plan forced, the first calls of a batch time each plan (twice)
+    and later calls use the one with the least time per particle-step."""
+    b = _b()
+    b.apic_batch_set_plan(-1)
+    hosts = _bodies("fp64", sizes=(3000, 700, 1500, 2200, 900, 1300, 600), seed=800)
+    batch = b.SceneBatch([b.DeviceScene(h) for h in hosts])
+    count = b.apic_batch_plan_count()
+    for _ in range(2 * count + 1):
+        batch.step(1)
+    plan, ns = batch.tuning()
+    print("tuned plan", plan, ns, flush=True)
+    assert 0 <= plan < count
+    assert all(np.isfinite(v) and v > 0 for v in ns)
+    assert ns[plan] == min(ns)
+    for d in batch.scenes:
+        assert d.flags() == 0
