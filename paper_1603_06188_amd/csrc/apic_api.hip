@@ -1568,7 +1568,7 @@ namespace {
 constexpr int32_t kNoBand[6] = {0, 0, 0, 0, 0, 0};
 
 struct MidLayout {
-    size_t mf, gv, dv, dvt, r, rc, pv, s, delta, part, epart, out, flags, tflags, counts, cg;
+    size_t mf, gv, dv, dvt, r, rc, pv, s, delta, part, part2, epart, out, flags, tflags, counts, cg;
     size_t key, perm, count, cursor, start, bsum, klist, nlist, slot, slab, scell, soff, sF, sm, smv, sM, total;
     MidGrid g;
 };
@@ -1597,6 +1597,7 @@ MidLayout mid_layout(const apic_grid_desc &gd, const int32_t *band, int64_t n) {
     L.s = take(vb);
     L.delta = take(vb);
     L.part = take((size_t)mid_node_blocks(g.tiles) * 2 * sizeof(double));
+    L.part2 = take((size_t)mid_node_blocks(g.tiles) * sizeof(double));
     L.epart = take(maxk * sizeof(double));
     L.out = take(4 * sizeof(double));
     L.flags = take(sizeof(uint32_t));
@@ -1628,7 +1629,8 @@ struct MidOpts {
     int max_newton, max_cg;
 };
 
-// CG iterations launched between two looks at the device's stop flag.
+// CG iterations launched before the first look at the device's stop flag
+// (later looks come after the iterations the convergence rate says are left).
 constexpr int kCgPoll = 8;
 
 template <int DIM, int DEG>
@@ -1640,6 +1642,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     double *dv = (double *)(ws + L.dv), *dvt = (double *)(ws + L.dvt);
     double *r = (double *)(ws + L.r), *rc = (double *)(ws + L.rc), *pv = (double *)(ws + L.pv);
     double *sv = (double *)(ws + L.s), *delta = (double *)(ws + L.delta), *part = (double *)(ws + L.part);
+    double *part2 = (double *)(ws + L.part2);
     double *epart = (double *)(ws + L.epart), *out = (double *)(ws + L.out);
     uint32_t *flags = (uint32_t *)(ws + L.flags);
     uint32_t *tflags = (uint32_t *)(ws + L.tflags);  // flags of the iterate being tried
@@ -1727,24 +1730,34 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
             // conjugate gradient in the mass inner product (Sec. 4.2) on
             // (I - dt^2/4 M^{-1} df/dx) delta = -r, its scalars on the device
             launch_mid_cg_init<DIM>(g, tl, mf, r, delta, rc, pv, part, cg, tol2, (uint32_t)o.max_cg, st);
+            int chunk = kCgPoll;
             for (int k = 0; k < o.max_cg && rc0 == APIC_OK;) {
-                const int chunk = std::min(kCgPoll, o.max_cg - k);
-                for (int j = 0; j < chunk; ++j) {
+                chunk = std::min(chunk, o.max_cg - k);
+                for (int j = 0; j < chunk; ++j, ++k) {
                     if (elastic)
                         timed_kernel(APIC_PHASE_MID_APPLY, [&](hipEvent_t a, hipEvent_t b) {
                             launch_mid_apply_tiles<DIM, DEG>(S, g, tl, mat, pv, cg, st, a, b);
                         });
                     launch_mid_apply_nodes<DIM, DEG>(g, tl, elastic, pv, mf, dt, sv, part, cg, st);
-                    launch_mid_cg_step<DIM>(g, tl, mf, r, pv, sv, delta, rc, part, cg, st);
-                    launch_mid_cg_dir<DIM>(g, tl, rc, pv, cg, st);
+                    launch_mid_cg_step<DIM>(g, tl, mf, r, pv, sv, delta, rc, part, part2, cg, k, st);
+                    launch_mid_cg_dir<DIM>(g, tl, rc, pv, part2, cg, k, st);
                 }
-                k += chunk;
-                uint32_t poll[5] = {0, 0, 0, 0, 0};  // done, fallback, k, max_iters, iters
-                fetch(poll, &cg->done, sizeof poll);
+                MidCg now{};
+                fetch(&now, cg, sizeof now);
                 // launches after the stop did no work: out of the timing records
-                if (elastic) untime_last(APIC_PHASE_MID_APPLY, chunk - (int)(poll[4] - cg_seen));
-                cg_seen = poll[4];
-                if (poll[0]) break;
+                if (elastic) untime_last(APIC_PHASE_MID_APPLY, chunk - (int)(now.iters - cg_seen));
+                cg_seen = now.iters;
+                if (now.done) break;
+                // next look after the iterations the rate so far says are left
+                // (launches past the stop cost a few microseconds each, a look
+                // a synchronization)
+                const double gam = now.gamma[k & 1];
+                chunk = kCgPoll;
+                if (gam > 0.0 && gam < now.gamma0 && now.tol2 > 0.0) {
+                    const double per = std::log(gam / now.gamma0) / k;
+                    const double left = std::log(now.tol2 * now.gamma0 / gam) / per;
+                    chunk = (int)std::min(32.0, std::max(1.0, std::ceil(left)));
+                }
             }
             // backtracking line search: E must not increase, or |r|_M must
             // fall (near the minimum E is flat to within its rounding); a

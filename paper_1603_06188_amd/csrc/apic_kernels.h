@@ -208,8 +208,12 @@ struct MidTiles {
 
 // Conjugate-gradient scalars, formed and kept on the device.
 struct MidCg {
-    double gamma, gamma0, alpha, beta, tol2;
-    uint32_t done, fallback, k, max_iters, iters;
+    double gamma[2];  // <rc, rc>_M of the current iteration in slot it & 1 (the next one is written to the other)
+    double gamma0, tol2;
+    uint32_t done;    // the CG has stopped
+    uint32_t stop;    // stop raised by an iteration's step kernel, made `done` by its direction kernel
+    uint32_t iters;   // iterations run in the call
+    uint32_t max_iters;
 };
 
 struct MidMaterial {
@@ -240,8 +244,8 @@ template <int DIM, int DEG>
 void launch_mid_force_nodes(const MidGrid &g, const MidTiles &tl, bool elastic, const double *dv, double dt,
                             const double *grav, const double *mf, double *r, const double *epart, double *part,
                             double *out, hipStream_t st);
-// One application of the Newton operator to the search direction pv (s = A pv) and alpha:
-// the particle pass (force-differential slabs) and the node pass.
+// One application of the Newton operator to the search direction pv (s = A pv): the
+// particle pass (force-differential slabs) and the node pass (s and partials of <p, s>_M).
 template <int DIM, int DEG>
 void launch_mid_apply_tiles(const MidSorted &S, const MidGrid &g, const MidTiles &tl, const MidMaterial &mat,
                             const double *pv, MidCg *cg, hipStream_t st, hipEvent_t ev0 = nullptr,
@@ -253,12 +257,16 @@ template <int DIM>
 void launch_mid_cg_init(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, double *delta,
                         double *rc, double *pv, double *part, MidCg *cg, double tol2, uint32_t max_iters,
                         hipStream_t st);
+// CG iteration `it` after the operator application: alpha from the partials
+// of <p, s>_M (part_ps), delta and rc updated, partials of <rc, rc>_M (part);
+// then beta and the direction from those partials.
 template <int DIM>
 void launch_mid_cg_step(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, const double *pv,
-                        const double *s, double *delta, double *rc, double *part, MidCg *cg, hipStream_t st);
+                        const double *s, double *delta, double *rc, const double *part_ps, double *part, MidCg *cg,
+                        int it, hipStream_t st);
 template <int DIM>
-void launch_mid_cg_dir(const MidGrid &g, const MidTiles &tl, const double *rc, double *pv, const MidCg *cg,
-                       hipStream_t st);
+void launch_mid_cg_dir(const MidGrid &g, const MidTiles &tl, const double *rc, double *pv, const double *part,
+                       MidCg *cg, int it, hipStream_t st);
 // out = a + alpha b on the listed node tiles (a = nullptr reads as 0).
 template <int DIM>
 void launch_mid_axpy(const MidGrid &g, const MidTiles &tl, const double *a, double alpha, const double *b, double *out,

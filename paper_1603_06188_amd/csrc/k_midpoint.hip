@@ -19,9 +19,11 @@
 //
 // Node passes.  One wavefront per listed node tile, one lane per node, adds
 // the (at most 2^dim) slabs that cover the node in a fixed order and finishes
-// the node's update.  Reductions leave one partial per block, summed in block
-// order by a one-block kernel that also forms the conjugate gradient's
-// scalars on the device, so no iteration waits for the host.
+// the node's update.  Reductions leave one partial per block; the kernel that
+// needs the total has every block sum the partials in the same fixed order
+// (one-block kernels where only the host or the next solve reads it), so the
+// conjugate gradient's scalars are formed on the device and no iteration
+// waits for the host.
 //
 // The transfer to particles reads the caller's particle order.
 #include <hip/hip_ext.h>
@@ -885,24 +887,36 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_cg_init(MidGrid g, MidTiles t
     block_partials<1>(acc, part);
 }
 
-// delta += alpha p, rc -= alpha s; block partials of <rc, rc>_M.  When the
-// first <p, s>_M was not positive, delta = -r (the steepest-descent
-// direction) instead.
+// CG iteration `it`, after the operator application.  Every block sums the
+// partials of <p, s>_M (nps blocks) in the same fixed order, so all take the
+// same alpha = gamma / <p, s>_M; then delta += alpha p, rc -= alpha s, and
+// block partials of <rc, rc>_M.  A non-positive <p, s>_M stops the CG (the
+// direction has no positive curvature): at the first iteration delta = -r,
+// the steepest-descent direction, instead.  Block 0 counts the iteration and
+// raises the stop for the next kernel (no block of this one reads either).
 template <int DIM>
 __global__ __launch_bounds__(kMidBlock) void k_mid_cg_step(MidGrid g, MidTiles tl, const double *mf, const double *r,
                                                            const double *pv, const double *s, double *delta,
-                                                           double *rc, double *part, const MidCg *cg) {
+                                                           double *rc, const double *part_ps, int64_t nps,
+                                                           double *part, MidCg *cg, int it) {
+    if (cg->done) return;
+    const double ps = block_total(part_ps, nps, 1, 0);
     NodeAt n;
-    if (cg->fallback) {
-        if (node_at<DIM>(g, tl, n))
+    const bool have = node_at<DIM>(g, tl, n);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(ps > 0.0)) {
+        if (it == 0 && have)
 #pragma unroll
             for (int a = 0; a < DIM; ++a) delta[a * g.nodes + n.i] = -r[a * g.nodes + n.i];
+        if (lead) {
+            cg->iters += 1;
+            cg->stop = 1;
+        }
         return;
     }
-    if (cg->done) return;
-    const double alpha = cg->alpha;
+    const double alpha = cg->gamma[it & 1] / ps;
     double acc[1] = {0.0};
-    if (node_at<DIM>(g, tl, n)) {
+    if (have) {
         const double m = mf[n.i];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -914,6 +928,40 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_cg_step(MidGrid g, MidTiles t
         }
     }
     block_partials<1>(acc, part);
+    if (lead) cg->iters += 1;
+}
+
+// CG iteration `it`, last kernel: every block sums the partials of
+// kappa = <rc, rc>_M in the same fixed order; beta = kappa / gamma; unless the
+// CG stops (tolerance, iteration cap, or the curvature stop raised by the
+// step kernel) p = rc + beta p.  Block 0 stores kappa as the next gamma (the
+// other slot of two: this kernel's blocks read the current one) and the stop
+// flag; a block that starts after it and sees the flag skips the update,
+// which it would skip anyway.
+template <int DIM>
+__global__ __launch_bounds__(kMidBlock) void k_mid_cg_dir(MidGrid g, MidTiles tl, const double *rc, double *pv,
+                                                          const double *part, int64_t nblk, MidCg *cg, int it) {
+    if (cg->done) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (cg->stop) {
+        if (lead) cg->done = 1;
+        return;
+    }
+    const double kappa = block_total(part, nblk, 1, 0);
+    const double beta = kappa / cg->gamma[it & 1];
+    const bool stop = kappa <= cg->tol2 * cg->gamma0 || (uint32_t)it + 1u >= cg->max_iters;
+    if (lead) {
+        cg->gamma[(it + 1) & 1] = kappa;
+        if (stop) cg->done = 1;
+    }
+    if (stop) return;
+    NodeAt n;
+    if (!node_at<DIM>(g, tl, n)) return;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int64_t k = a * g.nodes + n.i;
+        pv[k] = rc[k] + beta * pv[k];
+    }
 }
 
 // Scalars from the block partials of the node pass before it (one block; the
@@ -922,21 +970,12 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_cg_step(MidGrid g, MidTiles t
 //             + sum V Psi (the key tiles' energy partials)
 //   SC_INIT:  gamma = gamma0 = <rc, rc>_M; stop at once when gamma0 is 0 or
 //             no iteration is allowed
-//   SC_ALPHA: alpha = gamma / <p, s>_M, or stop when <p, s>_M is not positive
-//   SC_BETA:  kappa = <rc, rc>_M, beta = kappa / gamma, gamma = kappa; stop at
-//             the tolerance or the iteration cap
-enum { SC_EVAL = 0, SC_INIT = 1, SC_ALPHA = 2, SC_BETA = 3 };
+enum { SC_EVAL = 0, SC_INIT = 1 };
 
 template <int OP>
 __global__ __launch_bounds__(kMidBlock) void k_mid_scalars(const double *part, int64_t nblk, const double *epart,
                                                            int64_t nk, double *out, MidCg *cg, double tol2,
                                                            uint32_t max_iters) {
-    if constexpr (OP == SC_ALPHA) {
-        if (cg->done) return;
-    }
-    if constexpr (OP == SC_BETA) {
-        if (cg->done || cg->fallback) return;
-    }
     if constexpr (OP == SC_EVAL) {
         const double res2 = block_total(part, nblk, 2, 0);
         const double kin = block_total(part, nblk, 2, 1);
@@ -948,43 +987,12 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_scalars(const double *part, i
     } else {
         const double t = block_total(part, nblk, 1, 0);
         if (threadIdx.x != 0) return;
-        if constexpr (OP == SC_INIT) {
-            cg->gamma = t;
-            cg->gamma0 = t;
-            cg->tol2 = tol2;
-            cg->k = 0;
-            cg->fallback = 0;
-            cg->max_iters = max_iters;
-            cg->done = (t <= tol2 * t || max_iters == 0) ? 1u : 0u;
-        } else if constexpr (OP == SC_ALPHA) {
-            cg->iters += 1;
-            if (!(t > 0.0)) {
-                cg->done = 1;
-                cg->fallback = cg->k == 0 ? 1u : 0u;
-            } else {
-                cg->alpha = cg->gamma / t;
-            }
-        } else {
-            cg->beta = t / cg->gamma;
-            cg->gamma = t;
-            cg->k += 1;
-            if (t <= cg->tol2 * cg->gamma0 || cg->k >= cg->max_iters) cg->done = 1;
-        }
-    }
-}
-
-// p = rc + beta p.
-template <int DIM>
-__global__ __launch_bounds__(kMidBlock) void k_mid_cg_dir(MidGrid g, MidTiles tl, const double *rc, double *pv,
-                                                          const MidCg *cg) {
-    if (cg->done) return;
-    const double beta = cg->beta;
-    NodeAt n;
-    if (!node_at<DIM>(g, tl, n)) return;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const int64_t k = a * g.nodes + n.i;
-        pv[k] = rc[k] + beta * pv[k];
+        cg->gamma[0] = t;
+        cg->gamma0 = t;
+        cg->tol2 = tol2;
+        cg->stop = 0;
+        cg->max_iters = max_iters;
+        cg->done = (t <= tol2 * t || max_iters == 0) ? 1u : 0u;
     }
 }
 
@@ -1211,7 +1219,6 @@ void launch_mid_apply_nodes(const MidGrid &g, const MidTiles &tl, bool elastic, 
         k_mid_node_apply<DIM, DEG, true><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, pv, dt, s, part, cg);
     else
         k_mid_node_apply<DIM, DEG, false><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, pv, dt, s, part, cg);
-    k_mid_scalars<SC_ALPHA><<<1, kMidBlock, 0, st>>>(part, nb, nullptr, 0, nullptr, cg, 0.0, 0);
 }
 
 template <int DIM>
@@ -1226,18 +1233,19 @@ void launch_mid_cg_init(const MidGrid &g, const MidTiles &tl, const double *mf, 
 
 template <int DIM>
 void launch_mid_cg_step(const MidGrid &g, const MidTiles &tl, const double *mf, const double *r, const double *pv,
-                        const double *s, double *delta, double *rc, double *part, MidCg *cg, hipStream_t st) {
+                        const double *s, double *delta, double *rc, const double *part_ps, double *part, MidCg *cg,
+                        int it, hipStream_t st) {
     if (tl.nn == 0) return;
     const int64_t nb = mid_node_blocks(tl.nn);
-    k_mid_cg_step<DIM><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, r, pv, s, delta, rc, part, cg);
-    k_mid_scalars<SC_BETA><<<1, kMidBlock, 0, st>>>(part, nb, nullptr, 0, nullptr, cg, 0.0, 0);
+    k_mid_cg_step<DIM><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, mf, r, pv, s, delta, rc, part_ps, nb, part, cg, it);
 }
 
 template <int DIM>
-void launch_mid_cg_dir(const MidGrid &g, const MidTiles &tl, const double *rc, double *pv, const MidCg *cg,
-                       hipStream_t st) {
+void launch_mid_cg_dir(const MidGrid &g, const MidTiles &tl, const double *rc, double *pv, const double *part,
+                       MidCg *cg, int it, hipStream_t st) {
     if (tl.nn == 0) return;
-    k_mid_cg_dir<DIM><<<(unsigned)mid_node_blocks(tl.nn), kMidBlock, 0, st>>>(g, tl, rc, pv, cg);
+    const int64_t nb = mid_node_blocks(tl.nn);
+    k_mid_cg_dir<DIM><<<(unsigned)nb, kMidBlock, 0, st>>>(g, tl, rc, pv, part, nb, cg, it);
 }
 
 template <int DIM>
@@ -1285,10 +1293,10 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
                                           double *, double *, double *, double *, MidCg *, double, uint32_t,          \
                                           hipStream_t);                                                               \
     template void launch_mid_cg_step<DIM>(const MidGrid &, const MidTiles &, const double *, const double *,          \
-                                          const double *, const double *, double *, double *, double *, MidCg *,      \
-                                          hipStream_t);                                                               \
-    template void launch_mid_cg_dir<DIM>(const MidGrid &, const MidTiles &, const double *, double *, const MidCg *,  \
-                                         hipStream_t);                                                                \
+                                          const double *, const double *, double *, double *, const double *,         \
+                                          double *, MidCg *, int, hipStream_t);                                       \
+    template void launch_mid_cg_dir<DIM>(const MidGrid &, const MidTiles &, const double *, double *, const double *, \
+                                         MidCg *, int, hipStream_t);                                                  \
     template void launch_mid_axpy<DIM>(const MidGrid &, const MidTiles &, const double *, double, const double *,     \
                                        double *, hipStream_t);                                                        \
     template void launch_mid_finish<DIM>(const MidGrid &, const MidTiles &, const double *, const double *,           \
