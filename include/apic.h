@@ -466,14 +466,19 @@ const char *apic_version(void);
  * (dv_i = dt g exactly).
  *
  * Precision APIC_F64, degree 2 or 3, transfer APIC, no APIC_OPT_ADAPTIVE_DT:
- * else APIC_E_UNSUPPORTED.  Particles need not be sorted and keep their
- * order.  The scene's workspace must hold apic_midpoint_workspace_bytes
- * (dense node arrays: about (2 + 9 dim) doubles per node); the step uses it
+ * else APIC_E_UNSUPPORTED.  Particles need not be sorted.  Each step leaves
+ * them in the caller's planes reordered by base node (tiles of 4^3 base
+ * nodes, 8^2 in 2D), ids (when p.id is given) moving with them; particles
+ * whose support leaves the grid take no part, keep their state, follow all
+ * others and set APIC_FLAG_OUT_OF_DOMAIN in stats->flags.  The scene's
+ * workspace must hold apic_midpoint_workspace_bytes (node vectors over tiles
+ * of 64 nodes, per-particle sorted copies, per-tile slabs); the step uses it
  * as scratch, so the explicit entry points see a fresh workspace afterwards
- * (their binning and grid are rebuilt on their next call).  Synchronizes the
- * stream for every inner product it reads back: two per conjugate-gradient
- * iteration, two per energy evaluation.  Particles whose support leaves the grid are skipped and set
- * APIC_FLAG_OUT_OF_DOMAIN in stats->flags.  A trial iterate with some
+ * (their binning and grid are rebuilt on their next call).  The CG's scalars
+ * stay on the device; the call synchronizes the stream once per step (tile
+ * counts), once per energy evaluation (E and |r|_M for the line search) and
+ * when it looks at the CG's stop flag (first after 8 iterations, then after
+ * the iterations the convergence rate so far says are left).  A trial iterate with some
  * det F_hat <= 0 has E = +inf and the line search halves it (it is never
  * accepted while a halving is left); APIC_FLAG_INVERTED is raised only when
  * an accepted iterate (the start of a step, or the 30th trial) is inverted.

@@ -1569,7 +1569,7 @@ constexpr int32_t kNoBand[6] = {0, 0, 0, 0, 0, 0};
 
 struct MidLayout {
     size_t mf, gv, dv, dvt, r, rc, pv, s, delta, part, part2, epart, out, flags, tflags, counts, cg;
-    size_t key, perm, count, cursor, start, bsum, klist, nlist, slot, slab, scell, soff, sF, sm, smv, sM, total;
+    size_t key, perm, count, cursor, start, bsum, klist, nlist, slot, slab, scell, soff, sF, sm, smv, sM, sid, total;
     MidGrid g;
 };
 
@@ -1606,10 +1606,11 @@ MidLayout mid_layout(const apic_grid_desc &gd, const int32_t *band, int64_t n) {
     L.cg = take(sizeof(MidCg));
     L.key = take(np * 4);
     L.perm = take(np * 4);
-    L.count = take((size_t)g.nodes * 4);
-    L.cursor = take((size_t)g.nodes * 4);
-    L.start = take((size_t)(g.nodes + 1) * 4);
-    L.bsum = take((size_t)mid_scan_blocks(g.nodes) * 4);
+    // counting sort: one bucket per node slot, then one for the particles outside the grid
+    L.count = take((size_t)(g.nodes + 1) * 4);
+    L.cursor = take((size_t)(g.nodes + 1) * 4);
+    L.start = take((size_t)(g.nodes + 2) * 4);
+    L.bsum = take((size_t)mid_scan_blocks(g.nodes + 1) * 4);
     L.klist = take((size_t)g.tiles * 4);
     L.nlist = take((size_t)g.tiles * 4);
     L.slot = take((size_t)g.tiles * 4);
@@ -1620,6 +1621,7 @@ MidLayout mid_layout(const apic_grid_desc &gd, const int32_t *band, int64_t n) {
     L.sm = take(np * sizeof(double));
     L.smv = take(np * gd.dim * sizeof(double));
     L.sM = take(np * (gd.dim * gd.dim + 1) * sizeof(double));
+    L.sid = take(np * 4);
     L.total = off;
     return L;
 }
@@ -1669,6 +1671,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
     S.m = (double *)(ws + L.sm);
     S.mv = (double *)(ws + L.smv);
     S.M = (double *)(ws + L.sM);
+    S.id = P.id ? (uint32_t *)(ws + L.sid) : nullptr;
     S.n = std::max<int64_t>(P.n, 1);
     S.dx = s->grid.dx;
     MidTiles tl{};
@@ -1717,7 +1720,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
         stats->res0 = 0.0;
         stats->res = 0.0;
         if (tl.nk == 0 || rc0 != APIC_OK) continue;  // no particle inside the grid: nothing moves
-        launch_mid_sort_state<DIM, DEG>(P, S, tl, st);
+        launch_mid_sort_state<DIM, DEG>(P, S, tl, g.nodes, st);
         launch_mid_p2g<DIM, DEG>(S, g, tl, mf, gv, st);
         launch_mid_axpy<DIM>(g, tl, nullptr, 0.0, gv, dv, st);  // dv = 0
         double E = 0.0, res = 0.0;
@@ -1780,7 +1783,7 @@ apic_status mid_run(apic_scene *s, int32_t n_steps, const MidOpts &o, apic_midpo
         stats->res = res;
         if (!(res0 == 0.0 || res <= o.newton_tol * res0)) stats->converged = 0;
         launch_mid_finish<DIM>(g, tl, mf, gv, dv, dt, rc, sv, st);
-        launch_mid_g2p<DIM, DEG>(P, g, rc, sv, st);
+        launch_mid_g2p<DIM, DEG>(P, S, g, tl, rc, sv, st);
     }
     if (rc0 != APIC_OK) return rc0;
     hipError_t e = hipGetLastError();

@@ -180,12 +180,14 @@ int mid_region_nodes(int dim, int degree);
 int64_t mid_node_blocks(int64_t nn);
 int64_t mid_scan_blocks(int64_t nodes);
 
-// Particles counting-sorted by base node (key = the base node's slot); the
-// copies are level-major within a key tile: level r holds, in key order, the
-// r-th particle (ascending index) of every key of the tile with more than r.
+// Particles counting-sorted by base node (key = the base node's slot; the
+// particles that take no part follow every node's, at positions
+// start[nodes] .. start[nodes + 1] - 1); the copies are level-major within a
+// key tile: level r holds, in lane order, the r-th particle (ascending index)
+// of every key of the tile with more than r.
 struct MidSorted {
     uint32_t *perm;         // key-major position -> particle
-    const uint32_t *start;  // nodes + 1 entries: first position of each key
+    const uint32_t *start;  // nodes + 2 entries: first position of each key (and of the rest)
     uint32_t *cell;         // packed cell
     double *off;            // dim planes
     double *F;              // dim*dim planes
@@ -193,6 +195,7 @@ struct MidSorted {
     double *mv;             // dim planes: m v
     double *M;              // dim*dim + 1 planes: m (k / dx) B for the transfer to grid, then F_hat^{-T} and
                             // mu - lambda ln J of the last force pass
+    uint32_t *id;           // particle ids (the caller's, else the particle's index); null: not kept
     int64_t n;              // plane stride
     double dx;
 };
@@ -226,9 +229,11 @@ template <int DIM, int DEG>
 void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, const MidTiles &tl, uint32_t *key,
                      uint32_t *count, uint32_t *cursor, uint32_t *bsum, int32_t *counts, uint32_t *flags,
                      hipStream_t st);
-// Level-major copies of the particles of the nk listed key tiles.
+// Level-major copies of the particles of the nk listed key tiles, and full
+// copies of the particles that take no part.
 template <int DIM, int DEG>
-void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const MidTiles &tl, hipStream_t st);
+void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const MidTiles &tl, int64_t nodes,
+                           hipStream_t st);
 // Transfer to grid: free-node mass mf and velocity gv.
 template <int DIM, int DEG>
 void launch_mid_p2g(const MidSorted &S, const MidGrid &g, const MidTiles &tl, double *mf, double *gv, hipStream_t st);
@@ -274,7 +279,10 @@ void launch_mid_axpy(const MidGrid &g, const MidTiles &tl, const double *a, doub
 template <int DIM>
 void launch_mid_finish(const MidGrid &g, const MidTiles &tl, const double *mf, const double *gv, const double *dv,
                        double dt, double *gvt, double *gu, hipStream_t st);
+// Transfer to particles from the sorted copies (one wavefront per listed key
+// tile), written to P in the sorted order; the particles outside the grid last.
 template <int DIM, int DEG>
-void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt, const double *gu, hipStream_t st);
+void launch_mid_g2p(const Parts<double> &P, const MidSorted &S, const MidGrid &g, const MidTiles &tl,
+                    const double *gvt, const double *gu, hipStream_t st);
 
 }  // namespace apic

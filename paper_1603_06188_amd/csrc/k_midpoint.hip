@@ -25,7 +25,8 @@
 // conjugate gradient's scalars are formed on the device and no iteration
 // waits for the host.
 //
-// The transfer to particles reads the caller's particle order.
+// The transfer to particles writes the particles back to the caller's planes
+// in the solve's order (ids move with them), those outside the grid last.
 #include <hip/hip_ext.h>
 
 #include "apic_kernels.h"
@@ -36,7 +37,6 @@ namespace {
 
 constexpr int kMidBlock = 256;  // node passes: four node tiles per block
 constexpr int kNodeTilesPerBlock = kMidBlock / 64;
-constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * kMidBlock + threadIdx.x; }
 
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_fill_u32(uint32_t *a, int64_t
 }
 
 // Key = slot of the particle's base node; particles whose support leaves the
-// grid get no key (they take no part in the step).
+// grid take no part in the step and get the key `nodes`, after every node.
 template <int DIM, int DEG>
 __global__ __launch_bounds__(kMidBlock) void k_mid_keys(Parts<double> P, MidGrid g, uint32_t *key, uint32_t *count,
                                                         uint32_t *flags) {
@@ -361,7 +361,8 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_keys(Parts<double> P, MidGrid
     if (p >= P.n) return;
     Axis<double, DEG> ax[DIM];
     if (!particle_axes<DIM, DEG>(P, p, g, ax)) {
-        key[p] = kNoKey;
+        key[p] = (uint32_t)g.nodes;  // the bucket after every node: particles that take no part
+        atomicAdd(&count[g.nodes], 1u);
         atomicOr(flags, (uint32_t)APIC_FLAG_OUT_OF_DOMAIN);
         return;
     }
@@ -439,7 +440,6 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_place(int64_t n, const uint32
     const int64_t p = gtid();
     if (p >= n) return;
     const uint32_t k = key[p];
-    if (k == kNoKey) return;
     perm[start[k] + atomicAdd(&cursor[k], 1u)] = (uint32_t)p;
 }
 
@@ -505,6 +505,7 @@ __global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorte
     for_levels<DIM, DEG>(S.start, t, [&](int64_t pos, uint32_t r, uint32_t) {
         const int64_t q = seg[r];
         S.cell[pos] = P.cell[q];
+        if (S.id) S.id[pos] = P.id[q];
         const double m = P.m[q];
         S.m[pos] = m;
 #pragma unroll
@@ -518,6 +519,29 @@ __global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorte
             S.M[k * S.n + pos] = m * kD * P.B[k * P.s + q];
         }
     });
+}
+
+// Full copies of the particles that take no part (positions after every
+// keyed one): v into the m v planes, B into the first d^2 M planes, for the
+// transfer to particles to put back after the others.
+template <int DIM>
+__global__ __launch_bounds__(kMidBlock) void k_mid_sort_dead(Parts<double> P, MidSorted S, int64_t nodes) {
+    const int64_t pos = (int64_t)S.start[nodes] + gtid();
+    if (pos >= (int64_t)S.start[nodes + 1]) return;
+    const int64_t q = S.perm[pos];
+    S.cell[pos] = P.cell[q];
+    S.m[pos] = P.m[q];
+    if (S.id) S.id[pos] = P.id ? P.id[q] : (uint32_t)q;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        S.off[a * S.n + pos] = P.off[a * P.s + q];
+        S.mv[a * S.n + pos] = P.v[a * P.s + q];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        S.F[k * S.n + pos] = P.F[k * P.s + q];
+        S.M[k * S.n + pos] = P.B[k * P.s + q];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1031,67 +1055,117 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_finish(MidGrid g, MidTiles tl
 //   B_p' = sum_i w vt_i r_i^T + 1/2 sum_i w (vt_i e_i^T - e_i vt_i^T),
 //          r_i = x_i - x_p, e_i = u_i - U_p
 //   F_p' = (I + sum_i u_i grad w^T) F_p,  x_p' = x_p + U_p.
+// One wavefront per listed key tile, vt and u of the tile's region staged in
+// LDS, the particles walked level by level as in the particle passes: the
+// old state comes from the sorted copies and the new state goes to the
+// caller's planes at the particle's sorted position, so the particles leave
+// the step in the solve's order (the next step's sort reads them nearly in
+// place).
 template <int DIM, int DEG>
-__global__ __launch_bounds__(kMidBlock) void k_mid_g2p(Parts<double> P, MidGrid g, const double *gvt,
-                                                       const double *gu) {
-    const int64_t p = gtid();
-    if (p >= P.n) return;
-    Axis<double, DEG> ax[DIM];
-    if (!particle_axes<DIM, DEG>(P, p, g, ax)) return;
-    auto slot = [&](int i, int j, int k) {
-        return node_slot<DIM>(g, ax[0].base + i, ax[1].base + j, DIM == 3 ? ax[DIM - 1].base + k : 0);
-    };
-    double v[DIM] = {}, U[DIM] = {};
-    for_support<DIM, DEG, DEG == 2>(ax, [&](double w, const double *, const double *, int i, int j, int k) {
-        const int64_t ni = slot(i, j, k);
+__global__ __launch_bounds__(64) void k_mid_g2p(Parts<double> P, MidSorted S, MidGrid g, MidTiles tl,
+                                                const double *gvt, const double *gu) {
+    constexpr int R = region_nodes<DIM, DEG>(), RE = region_edge<DIM, DEG>(), E = tile_edge<DIM>();
+    constexpr int D2 = DIM * DIM;
+    __shared__ double stage[2 * DIM * R];  // vt planes, then u planes
+    const int lane = threadIdx.x;
+    const int64_t t = tl.klist[blockIdx.x];
+    int tc[3];
+    tile_coords<DIM>(g, t, tc);
+    const int org[3] = {tc[0] * E, tc[1] * E, tc[2] * E};
+    for (int k = lane; k < R; k += 64) {
+        const int rx = k % RE, ry = DIM == 3 ? (k / RE) % RE : k / RE, rz = DIM == 3 ? k / (RE * RE) : 0;
+        const int x = org[0] + rx, y = org[1] + ry, z = org[2] + rz;
+        const bool in = x < g.N[0] && y < g.N[1] && (DIM == 2 || z < g.N[2]);
+        const int64_t i = in ? node_slot<DIM>(g, x, y, z) : 0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            v[a] += w * gvt[a * g.nodes + ni];
-            U[a] += w * gu[a * g.nodes + ni];
+            stage[a * R + k] = in ? gvt[a * g.nodes + i] : 0.0;
+            stage[(DIM + a) * R + k] = in ? gu[a * g.nodes + i] : 0.0;
         }
-    });
-    double B[DIM * DIM] = {}, G[DIM * DIM] = {};
-    for_support<DIM, DEG, DEG == 2>(ax, [&](double w, const double *gw, const double *r, int i, int j, int k) {
-        const int64_t ni = slot(i, j, k);
-        double vt[DIM], e[DIM], un[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            vt[a] = gvt[a * g.nodes + ni];
-            un[a] = gu[a * g.nodes + ni];
-            e[a] = un[a] - U[a];
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) {
-                B[a * DIM + b] += w * (vt[a] * r[b] * g.dx + 0.5 * (vt[a] * e[b] - e[a] * vt[b]));
-                G[a * DIM + b] += un[a] * gw[b];
-            }
-    });
-    double F[DIM * DIM], Fn[DIM * DIM];
-#pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) F[k] = P.F[k * P.s + p];
+    }
+    __syncthreads();
     const double s = 1.0 / g.dx;
+    for_levels<DIM, DEG>(S.start, t, [&](int64_t p, uint32_t, uint32_t) {
+        Axis<double, DEG> ax[DIM];
+        sorted_axes<DIM, DEG>(S, p, ax);
+        const int rb[3] = {ax[0].base - org[0], ax[1].base - org[1], DIM == 3 ? ax[DIM - 1].base - org[2] : 0};
+        auto region = [&](int i, int j, int k) {
+            return DIM == 3 ? (rb[0] + i) + RE * ((rb[1] + j) + RE * (rb[2] + k)) : (rb[0] + i) + RE * (rb[1] + j);
+        };
+        double v[DIM] = {}, U[DIM] = {};
+        for_support<DIM, DEG>(ax, [&](double w, const double *, const double *, int i, int j, int k) {
+            const int ri = region(i, j, k);
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) G[k] *= s;
+            for (int a = 0; a < DIM; ++a) {
+                v[a] += w * stage[a * R + ri];
+                U[a] += w * stage[(DIM + a) * R + ri];
+            }
+        });
+        double B[D2] = {}, G[D2] = {};
+        for_support<DIM, DEG>(ax, [&](double w, const double *gw, const double *r, int i, int j, int k) {
+            const int ri = region(i, j, k);
+            double vt[DIM], e[DIM], un[DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
-    mat_mul<DIM>(G, F, Fn);
-    int ci[3];
-    unpack_cell<DIM>(P.cell[p], ci);
+            for (int a = 0; a < DIM; ++a) {
+                vt[a] = stage[a * R + ri];
+                un[a] = stage[(DIM + a) * R + ri];
+                e[a] = un[a] - U[a];
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) {
+                    B[a * DIM + b] += w * (vt[a] * r[b] * g.dx + 0.5 * (vt[a] * e[b] - e[a] * vt[b]));
+                    G[a * DIM + b] += un[a] * gw[b];
+                }
+        });
+        double F[D2], Fn[D2];
+#pragma unroll
+        for (int k = 0; k < D2; ++k) F[k] = S.F[k * S.n + p];
+#pragma unroll
+        for (int k = 0; k < D2; ++k) G[k] *= s;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
+        mat_mul<DIM>(G, F, Fn);
+        int ci[3];
+        unpack_cell<DIM>(S.cell[p], ci);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double o = S.off[a * S.n + p] + U[a] * s;
+            const double c = floor(o);
+            ci[a] += (int)c;
+            P.off[a * P.s + p] = o - c;
+            P.v[a * P.s + p] = v[a];
+        }
+        P.cell[p] = pack_cell<DIM>(ci);
+        P.m[p] = S.m[p];
+        if (P.id) P.id[p] = S.id[p];
+#pragma unroll
+        for (int k = 0; k < D2; ++k) {
+            P.B[k * P.s + p] = B[k];
+            P.F[k * P.s + p] = Fn[k];
+        }
+    });
+}
+
+// The particles that took no part, back after all others, unchanged (staged
+// by k_mid_sort_dead: v in the m v planes, B in the first d^2 M planes).
+template <int DIM>
+__global__ __launch_bounds__(kMidBlock) void k_mid_put_dead(Parts<double> P, MidSorted S, int64_t nodes) {
+    const int64_t p = (int64_t)S.start[nodes] + gtid();
+    if (p >= (int64_t)S.start[nodes + 1]) return;
+    P.cell[p] = S.cell[p];
+    P.m[p] = S.m[p];
+    if (P.id) P.id[p] = S.id[p];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double o = P.off[a * P.s + p] + U[a] * s;
-        const double c = floor(o);
-        ci[a] += (int)c;
-        P.off[a * P.s + p] = o - c;
-        P.v[a * P.s + p] = v[a];
+        P.off[a * P.s + p] = S.off[a * S.n + p];
+        P.v[a * P.s + p] = S.mv[a * S.n + p];
     }
-    P.cell[p] = pack_cell<DIM>(ci);
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) {
-        P.B[k * P.s + p] = B[k];
-        P.F[k * P.s + p] = Fn[k];
+        P.B[k * P.s + p] = S.M[k * S.n + p];
+        P.F[k * P.s + p] = S.F[k * S.n + p];
     }
 }
 
@@ -1142,14 +1216,16 @@ template <int DIM, int DEG>
 void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &S, const MidTiles &tl, uint32_t *key,
                      uint32_t *count, uint32_t *cursor, uint32_t *bsum, int32_t *counts, uint32_t *flags,
                      hipStream_t st) {
-    k_mid_fill_u32<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(count, g.nodes);
-    k_mid_fill_u32<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(cursor, g.nodes);
+    // buckets: one per node slot, then one for the particles that take no part
+    const int64_t nbk = g.nodes + 1;
+    k_mid_fill_u32<<<blocks_for(nbk), kMidBlock, 0, st>>>(count, nbk);
+    k_mid_fill_u32<<<blocks_for(nbk), kMidBlock, 0, st>>>(cursor, nbk);
     if (P.n > 0) k_mid_keys<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, key, count, flags);
-    const int64_t nb = mid_scan_blocks(g.nodes);
+    const int64_t nb = mid_scan_blocks(nbk);
     uint32_t *start = const_cast<uint32_t *>(S.start);
-    k_mid_scan1<<<(unsigned)nb, kMidBlock, 0, st>>>(count, g.nodes, start, bsum);
-    k_mid_scan2<<<1, kMidBlock, 0, st>>>(bsum, nb, start, g.nodes);
-    k_mid_scan3<<<blocks_for(g.nodes), kMidBlock, 0, st>>>(start, g.nodes, bsum);
+    k_mid_scan1<<<(unsigned)nb, kMidBlock, 0, st>>>(count, nbk, start, bsum);
+    k_mid_scan2<<<1, kMidBlock, 0, st>>>(bsum, nb, start, nbk);
+    k_mid_scan3<<<blocks_for(nbk), kMidBlock, 0, st>>>(start, nbk, bsum);
     if (P.n > 0) k_mid_place<<<blocks_for(P.n), kMidBlock, 0, st>>>(P.n, key, S.start, cursor, S.perm);
     // count and cursor are free again: tile flags and their prefix sums
     uint32_t *kf = count, *nf = count + g.tiles, *ks = cursor, *ns = cursor + g.tiles + 1;
@@ -1166,8 +1242,10 @@ void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &
 }
 
 template <int DIM, int DEG>
-void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const MidTiles &tl, hipStream_t st) {
+void launch_mid_sort_state(const Parts<double> &P, const MidSorted &S, const MidTiles &tl, int64_t nodes,
+                           hipStream_t st) {
     if (tl.nk > 0) k_mid_sort_state<DIM, DEG><<<(unsigned)tl.nk, 64, 0, st>>>(P, S, tl);
+    if (P.n > 0) k_mid_sort_dead<DIM><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, S, nodes);
 }
 
 template <int DIM, int DEG>
@@ -1263,8 +1341,10 @@ void launch_mid_finish(const MidGrid &g, const MidTiles &tl, const double *mf, c
 }
 
 template <int DIM, int DEG>
-void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt, const double *gu, hipStream_t st) {
-    if (P.n > 0) k_mid_g2p<DIM, DEG><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, g, gvt, gu);
+void launch_mid_g2p(const Parts<double> &P, const MidSorted &S, const MidGrid &g, const MidTiles &tl,
+                    const double *gvt, const double *gu, hipStream_t st) {
+    if (tl.nk > 0) k_mid_g2p<DIM, DEG><<<(unsigned)tl.nk, 64, 0, st>>>(P, S, g, tl, gvt, gu);
+    if (P.n > 0) k_mid_put_dead<DIM><<<blocks_for(P.n), kMidBlock, 0, st>>>(P, S, g.nodes);
 }
 
 #define APIC_MID_INST_DD(DIM, DEG)                                                                                    \
@@ -1272,7 +1352,7 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
                                             const MidTiles &, uint32_t *, uint32_t *, uint32_t *, uint32_t *,         \
                                             int32_t *, uint32_t *, hipStream_t);                                      \
     template void launch_mid_sort_state<DIM, DEG>(const Parts<double> &, const MidSorted &, const MidTiles &,         \
-                                                  hipStream_t);                                                       \
+                                                  int64_t, hipStream_t);                                              \
     template void launch_mid_p2g<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &, double *, double *,  \
                                            hipStream_t);                                                              \
     template void launch_mid_force_tiles<DIM, DEG>(const MidSorted &, const MidGrid &, const MidTiles &,              \
@@ -1286,8 +1366,8 @@ void launch_mid_g2p(const Parts<double> &P, const MidGrid &g, const double *gvt,
                                                    hipEvent_t, hipEvent_t);                                           \
     template void launch_mid_apply_nodes<DIM, DEG>(const MidGrid &, const MidTiles &, bool, const double *,           \
                                                    const double *, double, double *, double *, MidCg *, hipStream_t); \
-    template void launch_mid_g2p<DIM, DEG>(const Parts<double> &, const MidGrid &, const double *, const double *,    \
-                                           hipStream_t);
+    template void launch_mid_g2p<DIM, DEG>(const Parts<double> &, const MidSorted &, const MidGrid &,                 \
+                                           const MidTiles &, const double *, const double *, hipStream_t);
 #define APIC_MID_INST_D(DIM)                                                                                          \
     template void launch_mid_cg_init<DIM>(const MidGrid &, const MidTiles &, const double *, const double *,          \
                                           double *, double *, double *, double *, MidCg *, double, uint32_t,          \
