@@ -606,13 +606,20 @@ def main(argv=None):
     del ds
     torch.cuda.empty_cache()
     if not args.headline_only:
-        # config 4 (many bodies, batched vs the per-scene loop) and config 3
-        # (two spheres, cubic, three precision modes), a few steps each
+        # config 4 (many bodies, batched vs the per-scene loop), config 3
+        # (two spheres, cubic, four precision modes) and the implicit
+        # midpoint step, a few steps each
         print("bench: batch leg", file=sys.stderr, flush=True)
         out["batch"] = batched(args.scenes, 10)
         torch.cuda.empty_cache()
         print("bench: spheres leg", file=sys.stderr, flush=True)
         out["spheres"] = spheres(10)
+        torch.cuda.empty_cache()
+        # the implicit midpoint step on the same cube in binary64 (Sec. 4.1, 4.2)
+        print("bench: midpoint leg", file=sys.stderr, flush=True)
+        mres = midpoint(3, args.cells)
+        out["midpoint"] = {"dt5e-3": mres["midpoint_dt0.005"], "dt1e-3": mres["midpoint_dt0.001"],
+                           "explicit_f64_dt1e-4": mres["explicit_dt1e-4"], "roofline": midpoint_roofline(mres)}
         torch.cuda.empty_cache()
     if not args.no_serve:
         print("bench: served leg", file=sys.stderr, flush=True)
