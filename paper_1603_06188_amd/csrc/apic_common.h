@@ -280,6 +280,60 @@ struct Geo {
     static constexpr int NC = 1 + DIM;                    // m, mv
 };
 
+// Order of a key tile's slab (its RE^DIM region) in global memory: 2^DIM
+// blocks, block e holding the nodes that lie past the tile's own TE nodes
+// (in the DEG nodes beyond it) exactly along the axes whose bit is set in e;
+// blocks in increasing e, x fastest inside a block.  Block e is the part of
+// the slab that node tile (key tile + e) adds up, so each gather of a node
+// tile reads one contiguous run of every plane.
+template <int DIM, int DEG>
+struct SlabMap {
+    static constexpr int TE = Geo<DIM, DEG>::TE;
+    __host__ __device__ static constexpr int edge(int e, int a) { return ((e >> a) & 1) ? DEG : TE; }
+    __host__ __device__ static constexpr int size(int e) {
+        int s = 1;
+        for (int a = 0; a < DIM; ++a) s *= edge(e, a);
+        return s;
+    }
+    __host__ __device__ static constexpr int start(int e) {
+        int s = 0;
+        for (int b = 0; b < e; ++b) s += size(b);
+        return s;
+    }
+    // position of the node at l (coordinates within block e)
+    __host__ __device__ static constexpr int in_block(int e, const int *l) {
+        return DIM == 3 ? start(e) + l[0] + edge(e, 0) * (l[1] + edge(e, 1) * l[2])
+                        : start(e) + l[0] + edge(e, 0) * l[1];
+    }
+    // position of region node c (0 <= c[a] < RE)
+    __host__ __device__ static int at(const int *c) {
+        int e = 0, l[3] = {0, 0, 0};
+        for (int a = 0; a < DIM; ++a) {
+            const bool past = c[a] >= TE;
+            e |= (int)past << a;
+            l[a] = past ? c[a] - TE : c[a];
+        }
+        int pos = 0;
+        for (int b = 0; b < (1 << DIM); ++b)
+            if (b == e) pos = in_block(b, l);
+        return pos;
+    }
+    // region coordinates of position j (0 <= j < RN); c is left as is for j >= RN
+    __host__ __device__ static void coords(int j, int *c) {
+#pragma unroll
+        for (int e = 0; e < (1 << DIM); ++e) {
+            if (j >= start(e) && j < start(e) + size(e)) {
+                int l = j - start(e);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    c[a] = l % edge(e, a) + (((e >> a) & 1) ? TE : 0);
+                    l /= edge(e, a);
+                }
+            }
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Packed cell index and tiled node index
 // ---------------------------------------------------------------------------

@@ -44,7 +44,10 @@ __device__ __forceinline__ void gather_node(const int *nc, const BinLists &gm, c
         // membership tag and record index are independent loads
         const uint32_t tag = gm.tile_gen[t], rec = gm.slot[t];
         if (tag != gm.gen) continue;
-        const int idx = DIM == 3 ? loc[0] + RE * (loc[1] + RE * loc[2]) : loc[0] + RE * loc[1];
+        int lb[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) lb[a] = loc[a] - ((corner >> a) & 1) * TE;
+        const int idx = SlabMap<DIM, DEG>::in_block(corner, lb);
         const T *s = slabs.v + (int64_t)rec * slabs.stride;
         const T ms = s[idx], ms_lo = COMP ? s[NC * RN + idx] : T(0);
 #pragma unroll
@@ -165,7 +168,8 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
                     ok = ok && loc[a] < RE;
                 }
                 if (!ok) continue;
-                const int idx = DIM == 3 ? loc[0] + RE * (loc[1] + RE * loc[2]) : loc[0] + RE * loc[1];
+                // block e of the slab: one contiguous run per plane
+                const int idx = SlabMap<DIM, DEG>::in_block(e, lc);
                 const T *sp = slabs.v + (int64_t)srec * slabs.stride;
                 const T ms = sp[idx], ms_lo = COMP ? sp[NC * RN + idx] : T(0);
 #pragma unroll

@@ -492,14 +492,25 @@ __global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorte
     const int64_t key = t * 64 + lane_key<DIM, DEG>(threadIdx.x);
     const uint32_t k0 = S.start[key], cnt = S.start[key + 1] - k0;
     uint32_t *seg = S.perm + k0;
-    for (uint32_t i = 1; i < cnt; ++i) {
-        const uint32_t v = seg[i];
-        uint32_t j = i;
-        while (j > 0 && seg[j - 1] > v) {
-            seg[j] = seg[j - 1];
-            --j;
+    // ascending particle index within the key: a Shell sort of the lane's own
+    // segment (gaps 701, 301, 132, 57, 23, 10, 4, 1, then 2.25x above), so a
+    // key that gathers many particles costs about cnt^1.3, not cnt^2
+    uint32_t gap = 1;
+    while (gap < cnt / 3) gap = gap < 701 ? (gap < 4 ? 4 : gap < 10 ? 10 : gap < 23 ? 23 : gap < 57 ? 57 :
+                                             gap < 132 ? 132 : gap < 301 ? 301 : 701)
+                                          : gap * 9 / 4;
+    for (;; gap = gap > 701 ? max(gap * 4 / 9, 701u) : (gap == 701 ? 301 : gap == 301 ? 132 : gap == 132 ? 57 :
+                                                gap == 57 ? 23 : gap == 23 ? 10 : gap == 10 ? 4 : 1)) {
+        for (uint32_t i = gap; i < cnt; ++i) {
+            const uint32_t v = seg[i];
+            uint32_t j = i;
+            while (j >= gap && seg[j - gap] > v) {
+                seg[j] = seg[j - gap];
+                j -= gap;
+            }
+            seg[j] = v;
         }
-        seg[j] = v;
+        if (gap == 1) break;
     }
     const double kD = inv_D_factor<double, DEG>() / S.dx;
     for_levels<DIM, DEG>(S.start, t, [&](int64_t pos, uint32_t r, uint32_t) {

@@ -211,7 +211,8 @@ __device__ __forceinline__ void p2g_accumulate2(const P2GParticle<T, 2, DEG> &pp
 
 // Slab planes in LDS, padded so that the 64 lanes of one round (a 4x4x4 or
 // 8x8 block of distinct nodes) fall in distinct banks of each half-wave:
-// 3D x + 8 y + 68 z, 2D x + 40 y.  The slab in global memory is compact.
+// 3D x + 8 y + 68 z, 2D x + 40 y.  The slab in global memory is compact, in
+// the block order of SlabMap.
 template <int DIM, int DEG>
 struct SlabLds {
     static constexpr int RE = Geo<DIM, DEG>::RE;
@@ -219,10 +220,11 @@ struct SlabLds {
     static constexpr int SZ = DIM == 3 ? 68 : 0;
     static constexpr int PLANE = DIM == 3 ? SZ * RE : SY * RE;
     __device__ static constexpr int at(int x, int y, int z) { return x + SY * y + SZ * z; }
-    // compact index (x + RE (y + RE z)) -> padded index
-    __device__ static int from_compact(int i) {
-        const int x = i % RE, y = (i / RE) % RE, z = i / (RE * RE);
-        return at(x, y, DIM == 3 ? z : 0);
+    // global position j -> padded index
+    __device__ static int from_global(int j) {
+        int c[3] = {0, 0, 0};
+        SlabMap<DIM, DEG>::coords(j, c);
+        return at(c[0], c[1], c[2]);
     }
 };
 
@@ -275,21 +277,38 @@ __device__ __forceinline__ void slab_flush3(const int *lcoord, const T (&acc_m)[
 }
 
 // Slab planes between the padded LDS layout and the compact global one
-// (one wavefront).
+// (one wavefront): the lane's padded indices are formed once and serve every
+// plane.
 template <typename T, int DIM, int DEG, bool COMP>
 __device__ __forceinline__ void slab_store(const T *lds, T *out) {
     using Gm = Geo<DIM, DEG>;
     using SL = SlabLds<DIM, DEG>;
-    constexpr int RN = Gm::RN, LP = SL::PLANE, SLAB = Gm::NC * (COMP ? 2 : 1) * RN;
-    for (int i = lane_id(); i < SLAB; i += 64) out[i] = lds[(i / RN) * LP + SL::from_compact(i % RN)];
+    constexpr int RN = Gm::RN, LP = SL::PLANE, NP = Gm::NC * (COMP ? 2 : 1), R = (RN + 63) / 64;
+    const int lane = lane_id();
+    int pad[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) pad[k] = SL::from_global(lane + 64 * k);
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (lane + 64 * k < RN) out[q * RN + lane + 64 * k] = lds[q * LP + pad[k]];
 }
 
 template <typename T, int DIM, int DEG, bool COMP>
 __device__ __forceinline__ void slab_load(const T *in, T *lds) {
     using Gm = Geo<DIM, DEG>;
     using SL = SlabLds<DIM, DEG>;
-    constexpr int RN = Gm::RN, LP = SL::PLANE, SLAB = Gm::NC * (COMP ? 2 : 1) * RN;
-    for (int i = lane_id(); i < SLAB; i += 64) lds[(i / RN) * LP + SL::from_compact(i % RN)] = in[i];
+    constexpr int RN = Gm::RN, LP = SL::PLANE, NP = Gm::NC * (COMP ? 2 : 1), R = (RN + 63) / 64;
+    const int lane = lane_id();
+    int pad[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) pad[k] = SL::from_global(lane + 64 * k);
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (lane + 64 * k < RN) lds[q * LP + pad[k]] = in[q * RN + lane + 64 * k];
 }
 
 // Reference velocity of a tile (wave-wide) from the velocities v of the
