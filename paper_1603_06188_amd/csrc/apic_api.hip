@@ -46,7 +46,7 @@ int slab_nodes(int dim, int degree) {
 // Workspace layout for a grid and a particle capacity `cap`.
 // ---------------------------------------------------------------------------
 struct ListOff {
-    size_t tile_gen, slot, rec_count, rec_list, rec_tile, tot, rpre, bpre, ctr;
+    size_t tile_gen, slot, rec_count, nfull, nsparse, rec_list, rec_tile, tot, rpre, bpre, ctr;
 };
 
 struct TabOff {
@@ -120,6 +120,8 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
         l.tile_gen = take(TT * 4);
         l.slot = take(TT * 4);
         l.rec_count = take((size_t)kBuckets * 4);
+        l.nfull = take((size_t)kBuckets * 4);
+        l.nsparse = take((size_t)kBuckets * 4);
         l.rec_list = take(LB * 4);
         l.rec_tile = take(RC * 4);
         l.tot = take((size_t)kBuckets * 4);
@@ -421,6 +423,8 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
         b.tile_gen = (uint32_t *)(w + o.tile_gen);
         b.slot = (uint32_t *)(w + o.slot);
         b.rec_count = (uint32_t *)(w + o.rec_count);
+        b.nfull = (uint32_t *)(w + o.nfull);
+        b.nsparse = (uint32_t *)(w + o.nsparse);
         b.rec_list = (uint32_t *)(w + o.rec_list);
         b.rec_tile = (uint32_t *)(w + o.rec_tile);
         b.tot = (uint32_t *)(w + o.tot);
@@ -533,7 +537,7 @@ void bin_static(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> 
     launch_bin_reset(v.lists[nxt], st);
     launch_bin_keys_static<T, DIM, DEG, ABS>(src, v.L.d, v.lists[nxt], v.sc, v.g.flags, v.g.inv_dx, st);
     launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-    launch_bin_finalize(v.lists[nxt], st);
+    launch_bin_finalize(v.lists[nxt], v.L.rc, st);
     launch_bin_scatter_copy<T, DIM>(src, dst, v.lists[nxt], v.tab[nxt], v.sc, st);
 }
 
@@ -550,7 +554,7 @@ void g2p_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T> &
         launch_bin_keys_moved<T, DIM, DEG, ABS>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc,
                                                 v.L.rc, st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-        launch_bin_finalize(v.lists[nxt], st);
+        launch_bin_finalize(v.lists[nxt], v.L.rc, st);
     });
     timed(APIC_PHASE_G2P, st, [&] {
         launch_g2p<T, DIM, DEG, ABS>(src, dst, v.lists[cur], v.tab[cur], v.lists[nxt], v.tab[nxt], v.sc, v.g, v.prm,
@@ -575,7 +579,7 @@ void g2p2g_rebin(View<T> &v, SceneState &ss, const Parts<T> &src, const Parts<T>
         launch_bin_keys_moved<T, DIM, DEG>(src, v.lists[cur], v.tab[cur], v.g, v.prm, v.lists[nxt], v.sc, v.L.rc,
                                            st);
         launch_bin_records<DIM>(v.L.d, v.lists[nxt], v.tab[nxt], v.sc, v.L.rc, st);
-        launch_bin_finalize(v.lists[nxt], st);
+        launch_bin_finalize(v.lists[nxt], v.L.rc, st);
     });
     if constexpr (fused_step<T, DIM, DEG>()) {
         timed(APIC_PHASE_G2P, st, [&] {

@@ -64,12 +64,15 @@ struct Parts {
 struct BinLists {
     uint32_t gen;          // generation tag of this layout
     uint32_t *tile_gen;    // [tiles] == gen: tile listed
-    uint32_t *slot;        // [tiles] record index of a listed tile (its slab)
+    uint32_t *slot;        // [tiles] record index of a listed tile (its slab; its rank in its
+                           // bucket's class between the records and finalize passes)
     uint32_t *rec_count;   // [kBuckets] listed tiles per bucket
+    uint32_t *nfull;       // [kBuckets] of them holding >= kFullTile particles
+    uint32_t *nsparse;     // [kBuckets] the others
     uint32_t *rec_list;    // [kBuckets * rcap] tile ids, bucket b from b * rcap
     uint32_t *tot;         // [kBuckets] particles per bucket
     uint32_t *rpre;        // [kBuckets + 1] exclusive prefix of rec_count; [kBuckets] = records
-    uint32_t *rec_tile;    // [records] tile id of record r (bucket order)
+    uint32_t *rec_tile;    // [records] tile id of record r (tiles of >= kFullTile particles first)
     uint32_t *bpre;        // [kBuckets + 1] exclusive prefix of tot; [kBuckets] = live particles
     uint32_t *ctr;         // [kCtrCount] counters of a build, zero when it starts
     int64_t rcap;          // list capacity per bucket: ceil(tiles / kBuckets)
@@ -77,6 +80,9 @@ struct BinLists {
 
 // Counters of a build: dead particles.
 enum : int { kCtrDead = 0, kCtrCount = 4 };
+// Tiles of at least this many particles (four per key on average) take the
+// first record numbers, so every tile walk ends with the short tiles.
+constexpr uint32_t kFullTile = 4 * 64;
 
 // Per-tile tables of one layout (dense, indexed by tile id; entries of tiles
 // not listed are stale and never read).  Within a key, particles that came

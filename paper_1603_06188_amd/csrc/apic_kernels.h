@@ -31,7 +31,7 @@ void launch_bin_records(const GridDims &d, const BinLists &nxt, const TileTables
                         int64_t max_records, hipStream_t st);
 
 // Prefix tables (records and particle bases per bucket) of a finished layout.
-void launch_bin_finalize(const BinLists &nxt, hipStream_t st);
+void launch_bin_finalize(const BinLists &nxt, int64_t max_records, hipStream_t st);
 template <typename T>
 void launch_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n, int k, int blocks,
                                hipStream_t st);

@@ -17,6 +17,8 @@ static inline int blocks_for(int64_t work, int threads, int cap) {
 __global__ void k_bin_reset(BinLists nxt) {
     for (int t = (int)threadIdx.x; t < kBuckets; t += (int)blockDim.x) {
         nxt.rec_count[t] = 0u;
+        nxt.nfull[t] = 0u;
+        nxt.nsparse[t] = 0u;
         nxt.tot[t] = 0u;
     }
     if (threadIdx.x < kCtrCount) nxt.ctr[threadIdx.x] = 0u;
@@ -97,8 +99,11 @@ __device__ __forceinline__ void records_body(const BinLists &nxt, const TileTabl
             tab.maxc[t] = mx;
             tab.tcount[t] = total;
             tab.off[t] = atomicAdd(nxt.tot + b, total);
-            nxt.slot[t] = r;
-            nxt.rec_tile[r] = t;
+            // rank among the bucket's tiles of its class (high bit: fewer
+            // than kFullTile particles); the finalize pass makes it the
+            // tile's record number
+            nxt.slot[t] = total >= kFullTile ? atomicAdd(nxt.nfull + b, 1u)
+                                             : (0x80000000u | atomicAdd(nxt.nsparse + b, 1u));
         }
         if (mx <= (uint32_t)kMaxLevels) {
             // level jj holds the jj-th particle of every key with more than jj
@@ -177,31 +182,63 @@ void launch_copy_back_batch(const SceneDesc<T> *descs, const int32_t *start, int
     hipLaunchKernelGGL((k_copy_back_batch<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, st, descs, start, n, k);
 }
 
-// --- prefix tables of a finished layout (one block) ----------------------------------
-__device__ __forceinline__ void finalize_body(const BinLists &nxt) {
-    __shared__ uint32_t tmp[kBuckets + 8];
-    const uint32_t nrec = block_bucket_prefix(nxt.rec_count, tmp, tmp + kBuckets);
-    for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) nxt.rpre[i] = tmp[i];
+// --- prefix tables and record numbers of a finished layout --------------------------
+// Every block forms the bucket prefixes in LDS (block 0 also stores them).
+// Record numbers: the tiles of at least kFullTile particles first, in bucket
+// order and then by their rank in the bucket, then the others the same way,
+// so that every tile walk takes the short tiles last.
+
+// Last bucket whose exclusive prefix is <= i (pre[kBuckets] = total > i).
+__device__ __forceinline__ uint32_t bucket_search(const uint32_t *pre, uint32_t i) {
+    uint32_t lo = 0, hi = kBuckets;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void finalize_body(const BinLists &nxt, uint32_t blk, uint32_t nblk) {
+    __shared__ uint32_t rpre[kBuckets + 1], fpre[kBuckets + 1], bpre[kBuckets + 1], part[12];
+    const uint32_t nrec = block_bucket_prefix(nxt.rec_count, rpre, part);
+    const uint32_t nfull = block_bucket_prefix(nxt.nfull, fpre, part + 4);
+    if (threadIdx.x == 0) rpre[kBuckets] = nrec;
+    if (blk == 0) {
+        const uint32_t live = block_bucket_prefix(nxt.tot, bpre, part + 8);
+        for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) {
+            nxt.rpre[i] = rpre[i];
+            nxt.bpre[i] = bpre[i];
+        }
+        if (threadIdx.x == 0) {
+            nxt.rpre[kBuckets] = nrec;
+            nxt.bpre[kBuckets] = live;
+        }
+    }
     __syncthreads();
-    const uint32_t live = block_bucket_prefix(nxt.tot, tmp, tmp + kBuckets + 4);
-    for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) nxt.bpre[i] = tmp[i];
-    if (threadIdx.x == 0) {
-        nxt.rpre[kBuckets] = nrec;
-        nxt.bpre[kBuckets] = live;
+    for (uint32_t i = blk * blockDim.x + threadIdx.x; i < nrec; i += nblk * blockDim.x) {
+        const uint32_t b = bucket_search(rpre, i);
+        const uint32_t t = nxt.rec_list[(int64_t)b * nxt.rcap + (i - rpre[b])];
+        const uint32_t v = nxt.slot[t];
+        const uint32_t rec = (v & 0x80000000u) ? nfull + (rpre[b] - fpre[b]) + (v & 0x7FFFFFFFu) : fpre[b] + v;
+        nxt.slot[t] = rec;
+        nxt.rec_tile[rec] = t;
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt) { finalize_body(nxt); }
+__global__ __launch_bounds__(256) void k_bin_finalize(BinLists nxt) { finalize_body(nxt, blockIdx.x, gridDim.x); }
 
-void launch_bin_finalize(const BinLists &nxt, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, st, nxt);
+void launch_bin_finalize(const BinLists &nxt, int64_t max_records, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_finalize, dim3(blocks_for(max_records, 256, 128)), dim3(256), 0, st, nxt);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_bin_finalize_batch(const SceneDesc<T> *descs, const int32_t *start, int n,
                                                             int k) {
     const BatchStep<T> b = batch_step<T>(descs, start, n, k, blockIdx.x);
-    finalize_body(b.nxt);
+    finalize_body(b.nxt, b.blk, b.nblk);
 }
 
 template <typename T>

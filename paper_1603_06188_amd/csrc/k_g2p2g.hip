@@ -241,6 +241,8 @@ __device__ __forceinline__ void p2g_movers_body(const Parts<T> &P, const BinList
         for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) {
             g.vmax[i] = 0u;
             cur.rec_count[i] = 0u;
+            cur.nfull[i] = 0u;
+            cur.nsparse[i] = 0u;
             cur.tot[i] = 0u;
         }
         if (threadIdx.x < kCtrCount) cur.ctr[threadIdx.x] = 0u;

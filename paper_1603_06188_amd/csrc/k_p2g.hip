@@ -41,6 +41,8 @@ __device__ __forceinline__ void p2g_body(const Parts<T> &P, const BinLists &cur,
         for (int i = (int)threadIdx.x; i < kBuckets; i += (int)blockDim.x) {
             g.vmax[i] = 0u;
             nxt.rec_count[i] = 0u;
+            nxt.nfull[i] = 0u;
+            nxt.nsparse[i] = 0u;
             nxt.tot[i] = 0u;
         }
         if (threadIdx.x < kCtrCount) nxt.ctr[threadIdx.x] = 0u;
