@@ -501,6 +501,14 @@ __device__ __forceinline__ bool is_finite(T x) {
 }
 
 template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
+template <typename T>
 __device__ __forceinline__ T log_t(T x);
 template <>
 __device__ __forceinline__ float log_t<float>(float x) { return logf(x); }

@@ -78,7 +78,10 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
                                                  const StepParams<T> &prm_in, uint32_t blk, uint32_t nblk) {
     const StepParams<T> prm = with_step_dt(prm_in);
     using Gm = Geo<DIM, DEG>;
-    constexpr int TE = Gm::TE, RE = Gm::RE, RN = Gm::RN, NC = Gm::NC, NCOR = 1 << DIM;
+    constexpr int TE = Gm::TE, RN = Gm::RN, NC = Gm::NC, NCOR = 1 << DIM;
+    // slab values in flight per group: at most 32 registers
+    constexpr int NP = NC * (COMP ? 2 : 1), REGS = NP * (int)(sizeof(T) / 4);
+    constexpr int GE = REGS * NCOR <= 32 ? NCOR : (REGS * NCOR / 2 <= 32 ? NCOR / 2 : NCOR / 4);
     const int lane = lane_id();
     const int64_t G = g.d.G;
     __shared__ uint32_t wave_bits[4];
@@ -149,39 +152,49 @@ __device__ __forceinline__ void grid_update_body(const BinLists &cur, const Slab
             }
             // sum of the covering slabs, e in increasing order, each slab's
             // momentum moved to this node tile's reference (the difference of
-            // two references is exact)
+            // two references is exact).  The slabs are fetched in groups of
+            // GE, every load of a group issued before the first is used (a
+            // lane without a slab of that e reads the first slab and drops it)
             T hi[NC], lo[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) hi[q] = lo[q] = T(0);
 #pragma unroll
-            for (int e = 0; e < NCOR; ++e) {
-                const uint32_t srec = __shfl(rec, c * NCOR + e, 64);
-                T du[DIM];
+            for (int e0 = 0; e0 < NCOR; e0 += GE) {
+                T val[GE][NP];
+                bool use[GE];
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) du[a] = __shfl(ur[a], c * NCOR + e, 64) - own[a];
-                if (!((lst >> e) & 1u)) continue;
-                int loc[3] = {0, 0, 0};
-                bool ok = valid;
+                for (int j = 0; j < GE; ++j) {
+                    const int e = e0 + j;
+                    const uint32_t srec = __shfl(rec, c * NCOR + e, 64);
+                    // block e of the slab (one contiguous run per plane): the
+                    // nodes within DEG of the tile's low faces along e's axes
+                    bool ok = valid && ((lst >> e) & 1u);
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    loc[a] = lc[a] + ((e >> a) & 1) * TE;
-                    ok = ok && loc[a] < RE;
+                    for (int a = 0; a < DIM; ++a) ok = ok && lc[a] < SlabMap<DIM, DEG>::edge(e, a);
+                    use[j] = ok;
+                    const T *sp = slabs.v + (ok ? (int64_t)srec * slabs.stride + SlabMap<DIM, DEG>::in_block(e, lc) : 0);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) val[j][q] = sp[q * RN];
                 }
-                if (!ok) continue;
-                // block e of the slab: one contiguous run per plane
-                const int idx = SlabMap<DIM, DEG>::in_block(e, lc);
-                const T *sp = slabs.v + (int64_t)srec * slabs.stride;
-                const T ms = sp[idx], ms_lo = COMP ? sp[NC * RN + idx] : T(0);
 #pragma unroll
-                for (int q = 0; q < NC; ++q) {
-                    const T u = q == 0 ? T(0) : du[q - 1];
-                    const T x = sp[q * RN + idx] + ms * u;
-                    if constexpr (COMP) {
-                        const T sum = hi[q] + x;
-                        lo[q] += two_sum_err(hi[q], x, sum) + (sp[(NC + q) * RN + idx] + ms_lo * u);
-                        hi[q] = sum;
-                    } else {
-                        hi[q] += x;
+                for (int j = 0; j < GE; ++j) {
+                    const int e = e0 + j;
+                    T du[DIM];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) du[a] = __shfl(ur[a], c * NCOR + e, 64) - own[a];
+                    if (!use[j]) continue;
+                    const T ms = val[j][0], ms_lo = COMP ? val[j][NC] : T(0);
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) {
+                        const T u = q == 0 ? T(0) : du[q - 1];
+                        const T x = val[j][q] + ms * u;
+                        if constexpr (COMP) {
+                            const T sum = hi[q] + x;
+                            lo[q] += two_sum_err(hi[q], x, sum) + (val[j][NC + q] + ms_lo * u);
+                            hi[q] = sum;
+                        } else {
+                            hi[q] += x;
+                        }
                     }
                 }
             }

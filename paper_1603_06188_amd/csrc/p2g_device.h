@@ -52,19 +52,25 @@ __device__ __forceinline__ bool p2g_prepare(const P2GRaw<T, DIM> &r, const int *
     int ci[3] = {0, 0, 0};
     T off[DIM], v[DIM], B[DIM * DIM], F[DIM * DIM];
     const T m = r.m;
-    bool finite = is_finite(m);
+    // x * 0 is NaN exactly when x is infinite or NaN, and +-0 otherwise, so
+    // the sum of all of them is zero exactly when every value is finite (one
+    // multiply-add per value instead of a class test and a mask merge)
+    T z = m * T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         v[a] = r.v[a];
-        finite = finite && is_finite(r.off[a]) && is_finite(v[a]);
+        z = fma_t(r.off[a], T(0), z);
+        z = fma_t(v[a], T(0), z);
     }
     particle_cells<T, DIM, ABS>(r.cell, r.off, inv_dx, ci, off);
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) {
         B[k] = r.B[k];
         F[k] = r.F[k];
-        finite = finite && is_finite(B[k]) && is_finite(F[k]);
+        z = fma_t(B[k], T(0), z);
+        z = fma_t(F[k], T(0), z);
     }
+    const bool finite = z == T(0);
     if (!finite) {
         atomicOr(flags, FLAG_NONFINITE);
         return false;
@@ -381,20 +387,25 @@ __device__ __forceinline__ void p2g_pass3(const Parts<T> &P, const int *key, int
     P2GRaw<T, 3> raw;
     if (n_act > 0) p2g_load<T, 3, ABS>(P, (uint32_t)particle_at(start, kstart, 0, mask, 0, maxc, lane), raw);
     if constexpr (DERIVE) reference_of_level0<T, 3>(raw.v, n_act > 0, uref);
-    for (uint32_t j = 0; j < j_end; ++j) {
+    // level j from cur while level j + 1 loads into nxt; two levels per trip
+    // with the buffers swapped, so no registers are copied between levels
+    P2GRaw<T, 3> raw_b;
+    auto level_step = [&](const P2GRaw<T, 3> &cur, P2GRaw<T, 3> &nxt, uint32_t j) {
         const uint32_t level_n = level + (uint32_t)popc64(mask);
         const uint64_t mask_n = ballot(cnt > j + 1);
-        P2GRaw<T, 3> raw_n;
         if (n_act > j + 1)
-            p2g_load<T, 3, ABS>(P, (uint32_t)particle_at(start, kstart, level_n, mask_n, j + 1, maxc, lane), raw_n);
+            p2g_load<T, 3, ABS>(P, (uint32_t)particle_at(start, kstart, level_n, mask_n, j + 1, maxc, lane), nxt);
         if (n_act > j) {
             P2GParticle<T, 3, DEG> pp;
-            if (p2g_prepare<T, 3, DEG, ABS>(raw, key, prm, inv_dx, flags, uref, pp))
+            if (p2g_prepare<T, 3, DEG, ABS>(cur, key, prm, inv_dx, flags, uref, pp))
                 p2g_accumulate3<T, DEG, C0, CZ>(pp, acc_m, acc_v);
         }
-        raw = raw_n;
         level = level_n;
         mask = mask_n;
+    };
+    for (uint32_t j = 0; j < j_end; j += 2) {
+        level_step(raw, raw_b, j);
+        if (j + 1 < j_end) level_step(raw_b, raw, j + 1);
     }
     slab_flush3<T, DEG, COMP, C0, CZ>(lcoord, acc_m, acc_v, lds);
 }
