@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_place(int64_t n, const uint32
 // tile, their prefix sums (the scan kernels above), then the placement.
 template <int DIM>
 __global__ __launch_bounds__(kMidBlock) void k_mid_tile_flags(MidGrid g, const uint32_t *start, uint32_t *kf,
-                                                              uint32_t *nf) {
+                                                              uint32_t *nf, uint32_t *hf) {
     const int64_t t = gtid();
     if (t >= g.tiles) return;
     int tc[3];
@@ -462,12 +462,19 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_tile_flags(MidGrid g, const u
         const int64_t ut = tile_index<DIM>(g, u);
         nact = nact || start[ut * 64 + 64] > start[ut * 64];
     }
-    kf[t] = start[t * 64 + 64] > start[t * 64] ? 1u : 0u;
+    const uint32_t np = start[t * 64 + 64] - start[t * 64];
+    kf[t] = np > 0u ? 1u : 0u;
+    hf[t] = np >= kFullTile ? 1u : 0u;
     nf[t] = nact ? 1u : 0u;
 }
 
+// Key tiles of at least kFullTile particles take the first places of the
+// list (in tile order), the others follow (in tile order), so that the tile
+// passes, one block per listed key tile in list order, end with the short
+// tiles.
 __global__ __launch_bounds__(kMidBlock) void k_mid_tile_place(int64_t tiles, const uint32_t *kf, const uint32_t *nf,
-                                                              const uint32_t *ks, const uint32_t *ns, MidTiles tl,
+                                                              const uint32_t *hf, const uint32_t *ks,
+                                                              const uint32_t *ns, const uint32_t *hs, MidTiles tl,
                                                               int32_t *counts) {
     const int64_t t = gtid();
     if (t == 0) {
@@ -475,8 +482,9 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_tile_place(int64_t tiles, con
         counts[1] = (int32_t)ns[tiles];
     }
     if (t >= tiles) return;
-    tl.slot[t] = kf[t] ? (int32_t)ks[t] : -1;
-    if (kf[t]) tl.klist[ks[t]] = (int32_t)t;
+    const uint32_t pos = hf[t] ? hs[t] : hs[tiles] + (ks[t] - hs[t]);
+    tl.slot[t] = kf[t] ? (int32_t)pos : -1;
+    if (kf[t]) tl.klist[pos] = (int32_t)t;
     if (nf[t]) tl.nlist[ns[t]] = (int32_t)t;
 }
 
@@ -486,50 +494,133 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_tile_place(int64_t tiles, con
 // term of Sec. 3.2 with D = dx^2 / k I).  A key's particles are first put in
 // ascending index order, so the copy and every sum after it are the same on
 // every run.
+// A lane's walk over the levels of its key in a key tile: position of level
+// r (consecutive positions per level, in lane order) and the level count.
+struct LevelWalk {
+    int64_t pos0;
+    uint32_t maxc;
+    uint64_t below;
+};
+
+__device__ __forceinline__ LevelWalk level_walk(const uint32_t *start, int64_t t, uint32_t cnt) {
+    const int lane = threadIdx.x & 63;
+    LevelWalk w;
+    w.maxc = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t other = __shfl_xor(w.maxc, o, 64);
+        w.maxc = other > w.maxc ? other : w.maxc;
+    }
+    w.pos0 = start[t * 64];
+    w.below = (1ull << lane) - 1ull;
+    return w;
+}
+
+// What the sort copy moves of one particle.
+template <int DIM>
+struct SortRow {
+    uint32_t cell, id;
+    double m, off[DIM], v[DIM], F[DIM * DIM], B[DIM * DIM];
+};
+
+template <int DIM>
+__device__ __forceinline__ void sort_row_load(const Parts<double> &P, int64_t q, bool with_id, SortRow<DIM> &w) {
+    w.cell = P.cell[q];
+    w.id = with_id ? P.id[q] : 0u;
+    w.m = P.m[q];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        w.off[a] = P.off[a * P.s + q];
+        w.v[a] = P.v[a * P.s + q];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) {
+        w.F[k] = P.F[k * P.s + q];
+        w.B[k] = P.B[k * P.s + q];
+    }
+}
+
+// Level-major copies of what the solve reads (cell, offset, F, m) and the
+// transfer-to-grid terms mv = m v and Q = m (k / dx) B, so that node i
+// receives w (mv + Q r) with r = (x_i - x_p) / dx (the B D^{-1} (x_i - x_p)
+// term of Sec. 3.2 with D = dx^2 / k I).  A key's particles are first put in
+// ascending index order, so the copy and every sum after it are the same on
+// every run: up to kSortLds of them in the lane's own LDS column (all loads
+// in flight together, insertion sort in LDS), more with a Shell sort of the
+// segment in place.  The copy loads level r + 1 before it stores level r.
+constexpr uint32_t kSortLds = 32;
+
 template <int DIM, int DEG>
 __global__ __launch_bounds__(64) void k_mid_sort_state(Parts<double> P, MidSorted S, MidTiles tl) {
+    __shared__ uint32_t col[kSortLds * 64];
+    const int lane = threadIdx.x;
     const int64_t t = tl.klist[blockIdx.x];
-    const int64_t key = t * 64 + lane_key<DIM, DEG>(threadIdx.x);
+    const int64_t key = t * 64 + lane_key<DIM, DEG>(lane);
     const uint32_t k0 = S.start[key], cnt = S.start[key + 1] - k0;
     uint32_t *seg = S.perm + k0;
-    // ascending particle index within the key: a Shell sort of the lane's own
-    // segment (gaps 701, 301, 132, 57, 23, 10, 4, 1, then 2.25x above), so a
-    // key that gathers many particles costs about cnt^1.3, not cnt^2
-    uint32_t gap = 1;
-    while (gap < cnt / 3) gap = gap < 701 ? (gap < 4 ? 4 : gap < 10 ? 10 : gap < 23 ? 23 : gap < 57 ? 57 :
-                                             gap < 132 ? 132 : gap < 301 ? 301 : 701)
-                                          : gap * 9 / 4;
-    for (;; gap = gap > 701 ? max(gap * 4 / 9, 701u) : (gap == 701 ? 301 : gap == 301 ? 132 : gap == 132 ? 57 :
-                                                gap == 57 ? 23 : gap == 23 ? 10 : gap == 10 ? 4 : 1)) {
-        for (uint32_t i = gap; i < cnt; ++i) {
-            const uint32_t v = seg[i];
+    const bool in_lds = cnt <= kSortLds;
+    if (in_lds) {
+#pragma unroll 8
+        for (uint32_t i = 0; i < cnt; ++i) col[i * 64 + lane] = seg[i];
+        for (uint32_t i = 1; i < cnt; ++i) {
+            const uint32_t v = col[i * 64 + lane];
             uint32_t j = i;
-            while (j >= gap && seg[j - gap] > v) {
-                seg[j] = seg[j - gap];
-                j -= gap;
+            while (j > 0 && col[(j - 1) * 64 + lane] > v) {
+                col[j * 64 + lane] = col[(j - 1) * 64 + lane];
+                --j;
             }
-            seg[j] = v;
+            col[j * 64 + lane] = v;
         }
-        if (gap == 1) break;
+    } else {
+        // Shell sort (gaps 701, 301, 132, 57, 23, 10, 4, 1, then 2.25x
+        // above): about cnt^1.3 steps, not cnt^2
+        uint32_t gap = 1;
+        while (gap < cnt / 3) gap = gap < 701 ? (gap < 4 ? 4 : gap < 10 ? 10 : gap < 23 ? 23 : gap < 57 ? 57 :
+                                                 gap < 132 ? 132 : gap < 301 ? 301 : 701)
+                                              : gap * 9 / 4;
+        for (;; gap = gap > 701 ? max(gap * 4 / 9, 701u) : (gap == 701 ? 301 : gap == 301 ? 132 : gap == 132 ? 57 :
+                                                    gap == 57 ? 23 : gap == 23 ? 10 : gap == 10 ? 4 : 1)) {
+            for (uint32_t i = gap; i < cnt; ++i) {
+                const uint32_t v = seg[i];
+                uint32_t j = i;
+                while (j >= gap && seg[j - gap] > v) {
+                    seg[j] = seg[j - gap];
+                    j -= gap;
+                }
+                seg[j] = v;
+            }
+            if (gap == 1) break;
+        }
     }
+    auto index_of = [&](uint32_t r) -> int64_t { return in_lds ? col[r * 64 + lane] : seg[r]; };
     const double kD = inv_D_factor<double, DEG>() / S.dx;
-    for_levels<DIM, DEG>(S.start, t, [&](int64_t pos, uint32_t r, uint32_t) {
-        const int64_t q = seg[r];
-        S.cell[pos] = P.cell[q];
-        if (S.id) S.id[pos] = P.id[q];
-        const double m = P.m[q];
-        S.m[pos] = m;
+    const bool with_id = S.id != nullptr;
+    LevelWalk lw = level_walk(S.start, t, cnt);
+    SortRow<DIM> cur, nxt;
+    if (cnt > 0) sort_row_load<DIM>(P, index_of(0), with_id, cur);
+    for (uint32_t r = 0; r < lw.maxc; ++r) {
+        const bool act = r < cnt;
+        const uint64_t bal = ballot(act);
+        if (r + 1 < cnt) sort_row_load<DIM>(P, index_of(r + 1), with_id, nxt);
+        if (act) {
+            const int64_t pos = lw.pos0 + __popcll(bal & lw.below);
+            S.cell[pos] = cur.cell;
+            if (with_id) S.id[pos] = cur.id;
+            S.m[pos] = cur.m;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            S.off[a * S.n + pos] = P.off[a * P.s + q];
-            S.mv[a * S.n + pos] = m * P.v[a * P.s + q];
-        }
+            for (int a = 0; a < DIM; ++a) {
+                S.off[a * S.n + pos] = cur.off[a];
+                S.mv[a * S.n + pos] = cur.m * cur.v[a];
+            }
 #pragma unroll
-        for (int k = 0; k < DIM * DIM; ++k) {
-            S.F[k * S.n + pos] = P.F[k * P.s + q];
-            S.M[k * S.n + pos] = m * kD * P.B[k * P.s + q];
+            for (int k = 0; k < DIM * DIM; ++k) {
+                S.F[k * S.n + pos] = cur.F[k];
+                S.M[k * S.n + pos] = cur.m * kD * cur.B[k];
+            }
         }
-    });
+        lw.pos0 += __popcll(bal);
+        cur = nxt;
+    }
 }
 
 // Full copies of the particles that take no part (positions after every
@@ -1072,6 +1163,24 @@ __global__ __launch_bounds__(kMidBlock) void k_mid_finish(MidGrid g, MidTiles tl
 // caller's planes at the particle's sorted position, so the particles leave
 // the step in the solve's order (the next step's sort reads them nearly in
 // place).
+// What the transfer to particles reads of one particle of the sorted copy.
+template <int DIM>
+struct MidRow {
+    uint32_t cell, id;
+    double m, off[DIM], F[DIM * DIM];
+};
+
+template <int DIM>
+__device__ __forceinline__ void mid_row_load(const MidSorted &S, int64_t p, bool with_id, MidRow<DIM> &w) {
+    w.cell = S.cell[p];
+    w.id = with_id ? S.id[p] : 0u;
+    w.m = S.m[p];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) w.off[a] = S.off[a * S.n + p];
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) w.F[k] = S.F[k * S.n + p];
+}
+
 template <int DIM, int DEG>
 __global__ __launch_bounds__(64) void k_mid_g2p(Parts<double> P, MidSorted S, MidGrid g, MidTiles tl,
                                                 const double *gvt, const double *gu) {
@@ -1096,9 +1205,27 @@ __global__ __launch_bounds__(64) void k_mid_g2p(Parts<double> P, MidSorted S, Mi
     }
     __syncthreads();
     const double s = 1.0 / g.dx;
-    for_levels<DIM, DEG>(S.start, t, [&](int64_t p, uint32_t, uint32_t) {
+    // level r + 1 of the sorted copy loads while level r is computed and stored
+    const bool with_id = P.id != nullptr && S.id != nullptr;
+    const int64_t key = t * 64 + lane_key<DIM, DEG>(lane);
+    const uint32_t cnt = S.start[key + 1] - S.start[key];
+    LevelWalk lw = level_walk(S.start, t, cnt);
+    MidRow<DIM> cur, nxt;
+    const uint64_t bal0 = ballot(cnt > 0);
+    if (cnt > 0) mid_row_load<DIM>(S, lw.pos0 + __popcll(bal0 & lw.below), with_id, cur);
+    for (uint32_t lr = 0; lr < lw.maxc; ++lr) {
+        const bool act = lr < cnt;
+        const uint64_t bal = ballot(act);
+        const uint64_t bal_n = ballot(lr + 1 < cnt);
+        const int64_t p = lw.pos0 + __popcll(bal & lw.below);
+        lw.pos0 += __popcll(bal);
+        if (lr + 1 < cnt) mid_row_load<DIM>(S, lw.pos0 + __popcll(bal_n & lw.below), with_id, nxt);
+        if (!act) continue;
         Axis<double, DEG> ax[DIM];
-        sorted_axes<DIM, DEG>(S, p, ax);
+        int ci[3];
+        unpack_cell<DIM>(cur.cell, ci);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) axis_weights<double, DEG>(ci[a], cur.off[a], ax[a]);
         const int rb[3] = {ax[0].base - org[0], ax[1].base - org[1], DIM == 3 ? ax[DIM - 1].base - org[2] : 0};
         auto region = [&](int i, int j, int k) {
             return DIM == 3 ? (rb[0] + i) + RE * ((rb[1] + j) + RE * (rb[2] + k)) : (rb[0] + i) + RE * (rb[1] + j);
@@ -1130,33 +1257,30 @@ __global__ __launch_bounds__(64) void k_mid_g2p(Parts<double> P, MidSorted S, Mi
                     G[a * DIM + b] += un[a] * gw[b];
                 }
         });
-        double F[D2], Fn[D2];
-#pragma unroll
-        for (int k = 0; k < D2; ++k) F[k] = S.F[k * S.n + p];
+        double Fn[D2];
 #pragma unroll
         for (int k = 0; k < D2; ++k) G[k] *= s;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) G[a * DIM + a] += 1.0;
-        mat_mul<DIM>(G, F, Fn);
-        int ci[3];
-        unpack_cell<DIM>(S.cell[p], ci);
+        mat_mul<DIM>(G, cur.F, Fn);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            double o = S.off[a * S.n + p] + U[a] * s;
+            double o = cur.off[a] + U[a] * s;
             const double c = floor(o);
             ci[a] += (int)c;
             P.off[a * P.s + p] = o - c;
             P.v[a * P.s + p] = v[a];
         }
         P.cell[p] = pack_cell<DIM>(ci);
-        P.m[p] = S.m[p];
-        if (P.id) P.id[p] = S.id[p];
+        P.m[p] = cur.m;
+        if (with_id) P.id[p] = cur.id;
 #pragma unroll
         for (int k = 0; k < D2; ++k) {
             P.B[k * P.s + p] = B[k];
             P.F[k * P.s + p] = Fn[k];
         }
-    });
+        cur = nxt;
+    }
 }
 
 // The particles that took no part, back after all others, unchanged (staged
@@ -1239,17 +1363,18 @@ void launch_mid_sort(const Parts<double> &P, const MidGrid &g, const MidSorted &
     k_mid_scan3<<<blocks_for(nbk), kMidBlock, 0, st>>>(start, nbk, bsum);
     if (P.n > 0) k_mid_place<<<blocks_for(P.n), kMidBlock, 0, st>>>(P.n, key, S.start, cursor, S.perm);
     // count and cursor are free again: tile flags and their prefix sums
-    uint32_t *kf = count, *nf = count + g.tiles, *ks = cursor, *ns = cursor + g.tiles + 1;
+    uint32_t *kf = count, *nf = count + g.tiles, *hf = count + 2 * g.tiles;
+    uint32_t *ks = cursor, *ns = cursor + g.tiles + 1, *hs = cursor + 2 * (g.tiles + 1);
     const int64_t tb = mid_scan_blocks(g.tiles);
-    k_mid_tile_flags<DIM><<<blocks_for(g.tiles), kMidBlock, 0, st>>>(g, S.start, kf, nf);
-    for (int q = 0; q < 2; ++q) {
-        const uint32_t *f = q == 0 ? kf : nf;
-        uint32_t *sc = q == 0 ? ks : ns;
+    k_mid_tile_flags<DIM><<<blocks_for(g.tiles), kMidBlock, 0, st>>>(g, S.start, kf, nf, hf);
+    for (int q = 0; q < 3; ++q) {
+        const uint32_t *f = q == 0 ? kf : (q == 1 ? nf : hf);
+        uint32_t *sc = q == 0 ? ks : (q == 1 ? ns : hs);
         k_mid_scan1<<<(unsigned)tb, kMidBlock, 0, st>>>(f, g.tiles, sc, bsum);
         k_mid_scan2<<<1, kMidBlock, 0, st>>>(bsum, tb, sc, g.tiles);
         k_mid_scan3<<<blocks_for(g.tiles), kMidBlock, 0, st>>>(sc, g.tiles, bsum);
     }
-    k_mid_tile_place<<<blocks_for(g.tiles), kMidBlock, 0, st>>>(g.tiles, kf, nf, ks, ns, tl, counts);
+    k_mid_tile_place<<<blocks_for(g.tiles), kMidBlock, 0, st>>>(g.tiles, kf, nf, hf, ks, ns, hs, tl, counts);
 }
 
 template <int DIM, int DEG>
