@@ -34,13 +34,6 @@ __device__ __forceinline__ int axis_w_fixed(int cell, T off, T *w) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T fma_t(T a, T b, T c);
-template <>
-__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <>
-__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
 // New velocity v = sum_i w_i vt_i with a fixed operation sequence, shared
 // by both passes: first the x-axis sums Tx_k(a) = sum_{c,b} (wy(b) wz(c))
 // (vt_k(a,b,c) - c_k), nodes in (c, b) order, then
