@@ -254,13 +254,14 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         const uint32_t t = tile_range(walk, r, cur, ctab, start, total);
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
+        // the first chunk is in flight while the grid velocities are staged
+        G2PRaw<T, DIM> raw;
+        if ((uint32_t)lane < total) g2p_load<T, DIM, ABS>(src, start + (uint32_t)lane, raw);
         stage_velocities<T, DIM>(t, g, reg);
         // stayers of a key follow its movers in the new layout
         rankc[lane] = ntab.kmov[t * 64 + (uint32_t)lane];
         const uint32_t tbase = bases[bucket_of(t)];
         wave_lds_sync();
-        G2PRaw<T, DIM> raw;
-        if ((uint32_t)lane < total) g2p_load<T, DIM, ABS>(src, start + (uint32_t)lane, raw);
         for (uint32_t c0 = 0; c0 < total; c0 += 64) {
             const uint32_t i = c0 + (uint32_t)lane;
             // the next chunk is in flight while this one is computed
