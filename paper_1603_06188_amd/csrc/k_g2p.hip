@@ -254,21 +254,25 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         const uint32_t t = tile_range(walk, r, cur, ctab, start, total);
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
-        // the first chunk is in flight while the grid velocities are staged
+        // chunks of 64 start on 32-particle boundaries of the planes (128 B
+        // in binary32): each chunk reads whole cache lines, so no line is
+        // fetched again by the next chunk after the write stream evicted it.
+        // The first chunk is in flight while the grid velocities are staged.
+        const uint32_t head = start & 31u, span = total + head, first = start - head;
         G2PRaw<T, DIM> raw;
-        if ((uint32_t)lane < total) g2p_load<T, DIM, ABS>(src, start + (uint32_t)lane, raw);
+        if ((uint32_t)lane >= head && (uint32_t)lane < span) g2p_load<T, DIM, ABS>(src, first + (uint32_t)lane, raw);
         stage_velocities<T, DIM>(t, g, reg);
         // stayers of a key follow its movers in the new layout
         rankc[lane] = ntab.kmov[t * 64 + (uint32_t)lane];
         const uint32_t tbase = bases[bucket_of(t)];
         wave_lds_sync();
-        for (uint32_t c0 = 0; c0 < total; c0 += 64) {
-            const uint32_t i = c0 + (uint32_t)lane;
+        for (uint32_t c0 = 0; c0 < span; c0 += 64) {
+            const uint32_t e = c0 + (uint32_t)lane;
             // the next chunk is in flight while this one is computed
             G2PRaw<T, DIM> raw_n;
-            if (i + 64 < total) g2p_load<T, DIM, ABS>(src, start + i + 64, raw_n);
-            if (i < total) {
-                const uint32_t p = start + i;
+            if (e + 64 < span) g2p_load<T, DIM, ABS>(src, first + e + 64, raw_n);
+            if (e >= head && e < span) {
+                const uint32_t p = first + e;
                 int cn[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
                 T on[DIM], vn[DIM], Bs[DIM * DIM], Fn[DIM * DIM], xs[DIM];
                 g2p_update<T, DIM, DEG, ABS>(raw, reg, origin, g, dt_inv_dx, gs, lk, cn, on, vn, Bs, Fn, prm.transfer,
