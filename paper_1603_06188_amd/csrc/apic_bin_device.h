@@ -89,13 +89,16 @@ __device__ __forceinline__ uint32_t bin_destination(uint32_t key, uint32_t rank,
     return start + tab.kprefix[(int64_t)t * 64 + l] + rank;
 }
 
+// Appends tile t to its bucket's list of `nxt`.
+__device__ __forceinline__ void append_tile(uint32_t t, const BinLists &nxt) {
+    const uint32_t b = bucket_of(t);
+    const uint32_t j = atomicAdd(nxt.rec_count + b, 1u);
+    nxt.rec_list[(int64_t)b * nxt.rcap + j] = t;
+}
+
 // Lists tile t in `nxt` unless already listed in this generation.
 __device__ __forceinline__ void list_tile(uint32_t t, const BinLists &nxt) {
-    if (nxt.tile_gen[t] != nxt.gen && atomicExch(nxt.tile_gen + t, nxt.gen) != nxt.gen) {
-        const uint32_t b = bucket_of(t);
-        const uint32_t j = atomicAdd(nxt.rec_count + b, 1u);
-        nxt.rec_list[(int64_t)b * nxt.rcap + j] = t;
-    }
+    if (nxt.tile_gen[t] != nxt.gen && atomicExch(nxt.tile_gen + t, nxt.gen) != nxt.gen) append_tile(t, nxt);
 }
 
 // Index of the jj-th particle of a lane's key within a listed tile: level-

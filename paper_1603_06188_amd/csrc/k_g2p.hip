@@ -112,6 +112,12 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         tile_origin<DIM>(t, g.d.TN, origin);
         bool staged = false;  // grid velocities around the tile, on first use
         stay[lane] = 0u;
+        // the tile is claimed in the new layout now (its particles nearly all
+        // stay) and appended at the end, so the claim's round trip overlaps
+        // the tile's loads; a tile all of whose particles leave is listed
+        // empty, which every later pass walks as a tile without particles
+        uint32_t claim = nxt.gen;
+        if (lane == 0 && total > 0u) claim = atomicExch(nxt.tile_gen + t, nxt.gen);
         wave_lds_sync();
         uint32_t queued = 0;
         // groups of kKeyChunks chunks of 64: every load of a group is in
@@ -163,7 +169,7 @@ __device__ __forceinline__ void keys_body(const Parts<T> &P, const BinLists &cur
         wave_lds_sync();
         const uint32_t s = stay[lane];
         sc.scount[t * 64 + (uint32_t)lane] = s;
-        if (ballot(s > 0u) != 0ull && lane == 0) list_tile(t, nxt);
+        if (lane == 0 && claim != nxt.gen) append_tile(t, nxt);
         wave_lds_sync();
     }
 }
