@@ -160,12 +160,21 @@ __device__ __forceinline__ uint32_t bin_take_slot(uint32_t key, bool active, uin
                                                   const BinLists &nxt, const BinScratch &sc) {
     const bool live = active && key != kDeadKey;
     const uint32_t t = key >> 6;
+    // the rank and list atomics are issued before the tile listing, whose
+    // probe and claim depend on each other, so their round trips overlap
+    uint32_t rank = 0u;
+    if (active) {
+        if (key == kDeadKey) {
+            rank = atomicAdd(nxt.ctr + kCtrDead, 1u);
+        } else {
+            sc.pord[p] = ord;
+            const uint32_t nx = atomicExch(sc.head + key, p + 1u);
+            rank = atomicAdd(sc.key_count + key, 1u);
+            sc.next[p] = nx;
+        }
+    }
     if (first_lane_of_value(t, live)) list_tile(t, nxt);
-    if (!active) return 0u;
-    if (key == kDeadKey) return atomicAdd(nxt.ctr + kCtrDead, 1u);
-    sc.pord[p] = ord;
-    sc.next[p] = atomicExch(sc.head + key, p + 1u);
-    return atomicAdd(sc.key_count + key, 1u);
+    return rank;
 }
 
 // Final ranks of the n movers on a key's list (head: first old position +
