@@ -253,7 +253,7 @@ template void launch_bin_finalize_batch<double>(const SceneDesc<double> *, const
 template <int DIM>
 void launch_bin_records(const GridDims &d, const BinLists &nxt, const TileTables &tab, const BinScratch &sc,
                         int64_t max_records, hipStream_t st) {
-    hipLaunchKernelGGL((k_bin_records<DIM>), dim3(blocks_for(max_records, 4, 1024)), dim3(256), 0, st, nxt, tab, sc,
+    hipLaunchKernelGGL((k_bin_records<DIM>), dim3(blocks_for(max_records, 4, 2048)), dim3(256), 0, st, nxt, tab, sc,
                        d);
 }
 
