@@ -1031,7 +1031,8 @@ apic_status run_batch(apic_scene *scenes, int32_t n, int32_t n_steps, void *bws,
         const int pb = plan.per_block;
         const int share[BK_COUNT] = {share_blocks(np, pb, 4096), share_blocks(np, pb, 8192), share_blocks(np, pb, 2048),
                                      share_blocks(np, pb, 1024), share_blocks(np, pb, 4096), share_blocks(np, 1024, 4096),
-                                     1};
+                                     // finalize: one block per ~65k particles (a few hundred records)
+                                     share_blocks(np, 65536, 128)};
         for (int k = 0; k < BK_COUNT; ++k) {
             starts[(size_t)k * (n + 1) + i] = total[k];
             total[k] += share[k];

@@ -136,7 +136,12 @@ __global__ __launch_bounds__(256) void k_bin_records_batch(const SceneDesc<T> *d
     batch_items<QUEUE>(q, [&](uint32_t it) {
         const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
         const SceneDesc<T> &d = *b.d;
-        records_body<DIM>(b.nxt, d.tab[b.sp.nxt], d.sc, d.g.d, b.blk, b.nblk);
+        // the scene's structs as values: read through the table they would be
+        // read again after every store the compiler cannot prove apart
+        const TileTables tab = d.tab[b.sp.nxt];
+        const BinScratch sc = d.sc;
+        const GridDims dims = d.g.d;
+        records_body<DIM>(b.nxt, tab, sc, dims, b.blk, b.nblk);
     });
 }
 

@@ -195,8 +195,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_wa
     batch_items<QUEUE>(q, [&](uint32_t it) {
         const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
         const SceneDesc<T> &d = *b.d;
-        keys_body<T, DIM, DEG, false>(d.bufs[b.sp.src], b.cur, d.tab[b.sp.cur], d.g, d.prm, b.nxt, d.sc, b.blk,
-                                      b.nblk);
+        // the scene's structs as values: read through the table they would be
+        // read again after every store the compiler cannot prove apart
+        const Parts<T> P = d.bufs[b.sp.src];
+        const TileTables ctab = d.tab[b.sp.cur];
+        const GridState<T> g = d.g;
+        const StepParams<T> prm = d.prm;
+        const BinScratch sc = d.sc;
+        keys_body<T, DIM, DEG, false>(P, b.cur, ctab, g, prm, b.nxt, sc, b.blk, b.nblk);
     });
 }
 
@@ -353,8 +359,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_wav
         const SceneDesc<T> &d = *b.d;
         Parts<T> src = d.bufs[b.sp.src], dst = d.bufs[b.sp.src ^ 1];
         if (!src.id || !dst.id) src.id = dst.id = nullptr;
-        g2p_body<T, DIM, DEG, ADAPT>(src, dst, b.cur, d.tab[b.sp.cur], b.nxt, d.tab[b.sp.nxt], d.sc, d.g, d.prm,
-                                     b.blk, b.nblk);
+        // the scene's structs as values: read through the table they would be
+        // read again after every store the compiler cannot prove apart
+        const TileTables ctab = d.tab[b.sp.cur], ntab = d.tab[b.sp.nxt];
+        const BinScratch sc = d.sc;
+        const GridState<T> g = d.g;
+        const StepParams<T> prm = d.prm;
+        g2p_body<T, DIM, DEG, ADAPT>(src, dst, b.cur, ctab, b.nxt, ntab, sc, g, prm, b.blk, b.nblk);
     });
 }
 

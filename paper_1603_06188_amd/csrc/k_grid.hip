@@ -244,7 +244,12 @@ __global__ __launch_bounds__(256) void k_grid_update_batch(const SceneDesc<T> *d
     batch_items<QUEUE>(q, [&](uint32_t it) {
         const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
         const SceneDesc<T> &d = *b.d;
-        grid_update_body<T, DIM, DEG, COMP>(b.cur, d.slabs, d.g, d.prm, b.blk, b.nblk);
+        // the scene's structs as values: read through the table they would be
+        // read again after every store the compiler cannot prove apart
+        const Slabs<T> slabs = d.slabs;
+        const GridState<T> g = d.g;
+        const StepParams<T> prm = d.prm;
+        grid_update_body<T, DIM, DEG, COMP>(b.cur, slabs, g, prm, b.blk, b.nblk);
     });
 }
 

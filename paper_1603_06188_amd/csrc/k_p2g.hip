@@ -129,8 +129,14 @@ __global__ __launch_bounds__(256) void k_p2g_batch(const SceneDesc<T> *descs, co
     batch_items<QUEUE>(q, [&](uint32_t it) {
         const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
         const SceneDesc<T> &d = *b.d;
-        p2g_body<T, DIM, DEG, COMP>(d.bufs[b.sp.src], b.cur, b.nxt, d.tab[b.sp.cur], d.slabs, d.g, d.prm, b.blk,
-                                    b.nblk);
+        // the scene's structs as values: read through the table they would be
+        // read again after every store the compiler cannot prove apart
+        const Parts<T> P = d.bufs[b.sp.src];
+        const TileTables tab = d.tab[b.sp.cur];
+        const Slabs<T> slabs = d.slabs;
+        const GridState<T> g = d.g;
+        const StepParams<T> prm = d.prm;
+        p2g_body<T, DIM, DEG, COMP>(P, b.cur, b.nxt, tab, slabs, g, prm, b.blk, b.nblk);
     });
 }
 
