@@ -101,6 +101,20 @@ def test_host_validation_without_gpu():
     g.cells[1] = 2000
     with pytest.raises(b.ApicError):
         b.apic_workspace_bytes(g, 10)
+    # the packed cell index holds 10 bits per axis in 3D, 16 in 2D: 1024 and
+    # 65535 cells are the largest grids, one cell more is refused
+    g.cells[1] = 1024
+    assert b.apic_workspace_bytes(g, 10) > 0
+    g.cells[1] = 1025
+    with pytest.raises(b.ApicError):
+        b.apic_workspace_bytes(g, 10)
+    g2 = b.ApicGridDesc()
+    g2.dim, g2.degree, g2.precision, g2.options = 2, 2, b.APIC_F64, 0
+    g2.cells[0], g2.cells[1], g2.dx = 65535, 8, 1.0 / 8
+    assert b.apic_workspace_bytes(g2, 10) > 0
+    g2.cells[0] = 65536
+    with pytest.raises(b.ApicError):
+        b.apic_workspace_bytes(g2, 10)
     g.cells[1] = 128
     with pytest.raises(b.ApicError):
         b.apic_workspace_bytes(g, -1)
