@@ -39,6 +39,9 @@
  *
  * Particles: structure of arrays.  A "plane" is one scalar field for all n
  * particles; consecutive planes of one field are `stride` elements apart.
+ * Any stride >= n works; a multiple of 64 keeps every plane on the first
+ * plane's 256-byte alignment, so that the transfers' aligned runs of 64
+ * particles cover whole cache lines in every plane.
  * Position = packed cell index + offset inside the cell in cell units:
  *   3D: cell = cx | cy << 10 | cz << 20   (cells per axis <= 1024)
  *   2D: cell = cx | cy << 16              (cells per axis <= 65535)

@@ -345,11 +345,20 @@ def grid_desc(scene, precision=None, compensated=False, fused=False, adaptive=Fa
     return g
 
 
+def plane_capacity(n: int) -> int:
+    """Plane stride, in particles, of a DeviceScene for n particles: n rounded
+    up to a whole number of 64-particle blocks, so that every plane starts on
+    a 256-byte boundary (the transfers move aligned runs of 64 particles per
+    plane and cover whole cache lines only when all planes share the first
+    plane's alignment)."""
+    return (max(int(n), 1) + 63) // 64 * 64
+
+
 def scene_footprint_bytes(scene, precision=None, compensated=False, with_id=True, capacity=None) -> int:
     """Device bytes a DeviceScene of `scene` holds: its particle planes, cell
     (and id) arrays and its workspace."""
     precision = precision or scene.precision
-    cap = max(int(capacity or scene.n), 1)
+    cap = plane_capacity(capacity or scene.n)
     d = scene.dim
     elem = 4 if precision == "fp32" else 8
     planes = (2 * d + 2 * d * d + 1) * cap * elem
@@ -371,7 +380,7 @@ class DeviceScene:
         self.precision = precision or scene.precision
         self.dtype = torch.float32 if self.precision == "fp32" else torch.float64
         self.n = scene.n
-        self.capacity = max(int(capacity or self.n), 1)
+        self.capacity = plane_capacity(capacity or self.n)
         d = self.dim
         self.nplanes = 2 * d + 2 * d * d + 1
         cap = self.capacity

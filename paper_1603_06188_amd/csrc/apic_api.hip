@@ -35,6 +35,11 @@ apic_status fail(apic_status code, const char *fmt, ...) {
 }
 
 constexpr size_t kAlign = 256;
+// Shadow planes are a whole number of 64-particle blocks apart, so that every
+// plane starts on a 256-byte boundary like the first: the transfers read and
+// write runs of 64 particles aligned to the planes and cover whole cache
+// lines only when every plane shares that alignment.
+constexpr int64_t kPlaneAlign = 64;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int slab_nodes(int dim, int degree) {
@@ -58,6 +63,7 @@ struct Layout {
     size_t elem;
     bool comp;
     int64_t cap;    // particle capacity
+    int64_t sst;    // plane stride of the shadow state: cap rounded up to kPlaneAlign
     int64_t rc;     // record (slab) capacity: min(tiles, cap)
     int64_t rcap;   // list capacity per bucket: ceil(tiles / kBuckets)
     int64_t slab_stride;
@@ -93,6 +99,7 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.elem = g->precision == APIC_F64 ? 8 : 4;
     L.comp = (g->options & APIC_OPT_COMPENSATED) != 0;
     L.cap = cap < 1 ? 1 : cap;
+    L.sst = (L.cap + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
     L.rc = L.d.tiles < L.cap ? L.d.tiles : L.cap;
     L.rcap = (L.d.tiles + kBuckets - 1) / kBuckets;
     const size_t TT = (size_t)L.d.tiles, G = (size_t)L.d.G, dim = (size_t)g->dim, e = L.elem;
@@ -148,7 +155,7 @@ Layout make_layout(const apic_grid_desc *g, int64_t cap) {
     L.o_pord = take(cp * 8);
     L.o_sh_cell = take(cp * 4);
     L.o_sh_id = take(cp * 4);
-    L.o_sh_f = take((2 * dim + 2 * dim * dim + 1) * cp * e);
+    L.o_sh_f = take((2 * dim + 2 * dim * dim + 1) * (size_t)L.sst * e);
     L.total = o;
     return L;
 }
@@ -405,7 +412,7 @@ View<T> make_view(const apic_scene *s, int64_t cap, const SceneState &ss) {
     v.user.id = s->p.id;
     v.user.n = s->p.n;
     v.user.s = s->p.stride;
-    const int64_t dim = L.d.dim, cp = L.cap;
+    const int64_t dim = L.d.dim, cp = L.sst;
     v.shadow.cell = (uint32_t *)(w + L.o_sh_cell);
     v.shadow.id = s->p.id ? (int32_t *)(w + L.o_sh_id) : nullptr;
     T *f = (T *)(w + L.o_sh_f);

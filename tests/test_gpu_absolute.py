@@ -94,11 +94,14 @@ def test_absolute_positions_conversions():
     b = _b()
     s = _rounded(scenes.random_particles(500, dim=3, cells=16, degree=3, seed=5, precision="fp32"))
     ds = b.DeviceScene(s, absolute=True)
-    x = torch.tensor(np.ascontiguousarray(s.x.T), dtype=torch.float64, device="cuda")
+    # dim planes of the scene's plane stride (its capacity, whole 64-particle blocks)
+    assert ds.capacity >= s.n and ds.capacity % 64 == 0
+    x = torch.zeros((3, ds.capacity), dtype=torch.float64, device="cuda")
+    x[:, :s.n] = torch.tensor(np.ascontiguousarray(s.x.T), dtype=torch.float64)
     back = torch.empty_like(x)
     b.apic_positions_to_absolute(ds.s, back.data_ptr())
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(back.cpu().numpy().T, s.x)
+    np.testing.assert_array_equal(back[:, :s.n].cpu().numpy().T, s.x)
     b.apic_positions_from_absolute(ds.s, x.data_ptr())
     b.apic_sort(ds.s)
     np.testing.assert_array_equal(ds.state()["x"], s.x)
