@@ -266,11 +266,15 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         const uint32_t t = tile_range(walk, r, cur, ctab, start, total);
         int origin[3] = {0, 0, 0};
         tile_origin<DIM>(t, g.d.TN, origin);
-        // chunks of 64 start on 32-particle boundaries of the planes (128 B
-        // in binary32): each chunk reads whole cache lines, so no line is
-        // fetched again by the next chunk after the write stream evicted it.
-        // The first chunk is in flight while the grid velocities are staged.
-        const uint32_t head = start & 31u, span = total + head, first = start - head;
+        // chunks of 64 start on 32-particle boundaries (128 B in binary32)
+        // of the tile's place in the new layout: the particles keep their
+        // order there up to the few that change key, so each chunk writes
+        // whole cache lines (the writes move twice the bytes of the reads,
+        // which now start mid-line), and the next step's transfer to grid
+        // reads lines written whole.  The first chunk is in flight while the
+        // grid velocities are staged.
+        const uint32_t head = (nxt.bpre[bucket_of(t)] + ntab.off[t]) & 31u, span = total + head,
+                       first = start - head;
         G2PRaw<T, DIM> raw;
         if ((uint32_t)lane >= head && (uint32_t)lane < span) g2p_load<T, DIM, ABS>(src, first + (uint32_t)lane, raw);
         stage_velocities<T, DIM>(t, g, reg);
