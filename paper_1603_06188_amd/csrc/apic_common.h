@@ -85,11 +85,14 @@ enum : int { kCtrDead = 0, kCtrCount = 4 };
 constexpr uint32_t kFullTile = 4 * 64;
 
 // Per-tile tables of one layout (dense, indexed by tile id; entries of tiles
-// not listed are stale and never read).  Within a key, particles that came
-// from other keys (movers) take ranks [0, kmov) in the order of their
-// positions in the layout they came from, and particles that stayed take
-// ranks [kmov, kcount) in their old order: a layout is a function of the
-// one before it, whatever order the device's atomics ran in.
+// not listed are stale and never read).  Within a key, the particles that
+// stayed keep their old order and the particles that came from other keys
+// (movers) are ranked among themselves in the order of their positions in the
+// layout they came from; the G2P places the stayers first (ranks [0, kcount -
+// kmov)) so that they keep their levels, the fused G2P -> P2G pass the movers
+// first (ranks [0, kmov), the levels its mover pass walks).  Either way a
+// layout is a function of the one before it, whatever order the device's
+// atomics ran in.
 struct TileTables {
     uint32_t *kcount;      // [tiles * 64] particles per key
     uint32_t *kmov;        // [tiles * 64] of which movers

@@ -11,7 +11,8 @@
 // that changes key ("mover", rare) takes a rank in its new key by a counter.
 // Pass 2 (k_g2p) stages the grid velocities around the tile in LDS, computes
 // the whole update and writes each particle at its place in the new layout
-// (movers first within a key, then stayers in their old order).  Both passes
+// (within a key the stayers first, in their old order, then the movers
+// that entered it).  Both passes
 // get the new position through the same fixed operation sequence (no
 // contraction freedom), so they agree bit for bit on every key.
 #include "apic_kernels.h"
@@ -278,8 +279,9 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
         G2PRaw<T, DIM> raw;
         if ((uint32_t)lane >= head && (uint32_t)lane < span) g2p_load<T, DIM, ABS>(src, first + (uint32_t)lane, raw);
         stage_velocities<T, DIM>(t, g, reg);
-        // stayers of a key follow its movers in the new layout
-        rankc[lane] = ntab.kmov[t * 64 + (uint32_t)lane];
+        // a key's stayers keep their levels in the new layout: they take the
+        // first ranks, the movers entering the key the ranks after them
+        rankc[lane] = 0u;
         const uint32_t tbase = bases[bucket_of(t)];
         wave_lds_sync();
         for (uint32_t c0 = 0; c0 < span; c0 += 64) {
@@ -314,7 +316,7 @@ __device__ __forceinline__ void g2p_body(const Parts<T> &src, const Parts<T> &ds
                     base = tbase;
                 } else {
                     dkey = sc.pkey[p];
-                    drank = sc.prank[p];
+                    drank = sc.prank[p] + (dkey == kDeadKey ? 0u : ntab.kcount[dkey] - ntab.kmov[dkey]);
                     base = bucket_base_of(dkey, bases);
                 }
                 const uint32_t q = bin_destination(dkey, drank, ntab, base, live_nxt);

@@ -77,7 +77,8 @@ __device__ __forceinline__ void g2p2g_body(const Parts<T> &src, const Parts<T> &
         if (producer) {
             // --- wavefront 0: G2P, write, hand the stayers over ---------------------
             stage_velocities<T, 3>(t, g, L.vt);
-            // stayers of a key follow its movers, in their old order
+            // stayers of a key follow its movers, in their old order (the
+            // mover pass after this one walks the lowest levels)
             uint32_t srank = ntab.kmov[t * 64 + (uint32_t)lane];
             const uint32_t tbase = bases[bucket_of(t)];
             wave_lds_sync();
