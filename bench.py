@@ -390,8 +390,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the explicit APIC step of one scene is not "
-              "sharded across GPUs); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU (the explicit APIC step of one scene is not sharded across "
+              "GPUs); run with --gpus 1", file=sys.stderr)
         return 2
 
     _ensure_built()
@@ -402,6 +402,14 @@ def main(argv=None):
     from paper_1603_06188_amd import scenes
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a plain 256 MiB device copy (known bytes) that scales the traffic counters
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batch":
         res = batched(args.scenes, args.steps if args.steps != 100 else 20)
         print(json.dumps({
@@ -428,13 +436,6 @@ def main(argv=None):
                                    "dt=1e-4", "particles": main_mode["particles"]},
             "modes": res}), flush=True)
         return 0
-    if args.calibrate_copy and args.workload == "midpoint":
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     if args.workload == "midpoint":
         nsteps = args.steps if args.steps != 100 else 3
         res = midpoint(nsteps, args.cells)
@@ -451,13 +452,6 @@ def main(argv=None):
             "cpu_baseline": None if args.no_cpu_baseline else midpoint_cpu_baseline(),
             "modes": res}), flush=True)
         return 0
-    if args.calibrate_copy:
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     scene = scenes.cube3d(cells=args.cells)
     compensated = not args.plain
     ds = b.DeviceScene(scene, compensated=compensated, with_id=False, fused=args.fused)
