@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_wa
 }
 
 template <typename T, int DIM, int DEG, bool QUEUE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_min_waves<T, DIM, DEG>()))) void k_bin_keys_moved_batch(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUEUE ? 1 : keys_min_waves<T, DIM, DEG>()))) void k_bin_keys_moved_batch(
     const SceneDesc<T> *descs, const int32_t *start, int n, int k, BatchQueue q) {
     batch_items<QUEUE>(q, [&](uint32_t it) {
         const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADAPT ? 1 :
 }
 
 template <typename T, int DIM, int DEG, bool ADAPT, bool QUEUE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g2p_min_waves<T, DIM, DEG>()))) void k_g2p_batch(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUEUE ? 1 : g2p_min_waves<T, DIM, DEG>()))) void k_g2p_batch(
     const SceneDesc<T> *descs, const int32_t *start, int n, int k, BatchQueue q) {
     batch_items<QUEUE>(q, [&](uint32_t it) {
         const BatchStep<T> b = batch_step<T>(descs, start, n, k, it);
