@@ -11,10 +11,10 @@
 // that changes key ("mover", rare) takes a rank in its new key by a counter.
 // Pass 2 (k_g2p) stages the grid velocities around the tile in LDS, computes
 // the whole update and writes each particle at its place in the new layout
-// (within a key the stayers first, in their old order, then the movers
-// that entered it).  Both passes
-// get the new position through the same fixed operation sequence (no
-// contraction freedom), so they agree bit for bit on every key.
+// (within a key the stayers first, in their old order, then the movers that
+// entered it).  Both passes get the new position through the same fixed
+// operation sequence (no contraction freedom), so they agree bit for bit on
+// every key.
 #include "apic_kernels.h"
 #include "g2p_device.h"
 
@@ -231,8 +231,9 @@ void launch_bin_keys_moved(const Parts<T> &P, const BinLists &cur, const TileTab
 
 // --- pass 2: the transfer, written to the new layout ------------------------------------
 // One wavefront per listed tile walks the tile's particles in chunks of 64
-// (every lane busy).  A stayer's rank in its key continues from the key's
-// mover count (LDS counter); a mover takes the key and rank of pass 1.
+// (every lane busy).  A stayer's rank in its key comes from an LDS counter
+// from 0; a mover takes the key of pass 1 and its rank there after the key's
+// stayers.
 // ADAPT: the step's dt comes from the device and the CFL bound of the
 // written state is folded into g.cfl (adaptive steps); a separate
 // instantiation, so that fixed steps carry none of it.
