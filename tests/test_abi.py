@@ -246,3 +246,18 @@ def test_batch_plans_without_gpu():
             b.apic_batch_set_plan(bad)
     b.apic_batch_set_plan(n - 1)
     b.apic_batch_set_plan(-1)
+
+
+def test_plane_capacity_is_whole_blocks():
+    """DeviceScene planes are a whole number of 64-particle blocks apart (every
+    plane on the first plane's 256-byte alignment), never fewer than n, and
+    the footprint used for admission counts that stride."""
+    from paper_1603_06188_amd import binding as b, scenes
+    for n, want in ((0, 64), (1, 64), (63, 64), (64, 64), (65, 128), (2_097_152, 2_097_152), (147_920, 147_968)):
+        assert b.plane_capacity(n) == want
+    s = scenes.body3d(3, n_target=3000)
+    assert s.n % 64 != 0
+    cap = b.plane_capacity(s.n)
+    fp = b.scene_footprint_bytes(s, compensated=True, with_id=False)
+    ws = b.apic_workspace_bytes(b.grid_desc(s, compensated=True), cap)
+    assert fp == (2 * 3 + 2 * 9 + 1) * cap * 4 + cap * 4 + ws + 256
